@@ -1,0 +1,417 @@
+/*
+ * Log(Graph) CPU oracle -- TEST INFRASTRUCTURE ONLY.
+ *
+ * A plain, slow, deliberately obvious implementation of what the packed
+ * graph path computes, used to check the GPU library.  Only the test suite,
+ * the smoke check and the benchmark's CPU-baseline leg may load it; the
+ * product path never calls into it.  It shares no code, header or table
+ * with the GPU library.
+ *
+ * Conventions (the paper leaves these open; each reading is stated where it
+ * is used):
+ *   - vertex IDs are 0-based unsigned 32-bit integers;
+ *   - bl(x) is the bit length of x, bl(0) = 0;
+ *   - a packed bit stream stores its bit b as bit (b mod 64) of little-endian
+ *     64-bit word floor(b / 64); a value's bit k goes to stream bit start + k
+ *     (this is the byte/bit addressing of the edge-access listing in the
+ *     "Accessing An Edge" subsection, read with an x86 bit-field extract);
+ *     unused bits are zero and every stream carries one extra zero word.
+ *
+ * Every read and write of a packed stream below goes one bit at a time, on
+ * purpose unlike any word-level implementation.
+ *
+ * Parity status: every function here is pinned by the CPU test suite
+ * (closed forms, brute force, textbook library routines, hand-computed
+ * fixtures); none is "parity unpinned".
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_API __attribute__((visibility("default")))
+
+/* ------------------------------------------------------------------ */
+/* bit helpers                                                          */
+/* ------------------------------------------------------------------ */
+
+static unsigned bitlen(uint64_t x) {
+    unsigned b = 0;
+    while (x) { b++; x >>= 1; }
+    return b;
+}
+
+ORC_API unsigned orc_bitlen(uint64_t x) { return bitlen(x); }
+
+static void put_bit(uint64_t *words, uint64_t pos) {
+    words[pos / 64] |= (uint64_t)1 << (pos % 64);
+}
+
+static int get_bit(const uint64_t *words, uint64_t pos) {
+    return (int)((words[pos / 64] >> (pos % 64)) & 1u);
+}
+
+/* write `width` low bits of value at stream bit `start`, one bit at a time */
+static void put_bits(uint64_t *words, uint64_t start, uint64_t value, unsigned width) {
+    for (unsigned k = 0; k < width; k++)
+        if ((value >> k) & 1u) put_bit(words, start + k);
+}
+
+static uint64_t get_bits(const uint64_t *words, uint64_t start, unsigned width) {
+    uint64_t v = 0;
+    for (unsigned k = 0; k < width; k++)
+        if (get_bit(words, start + k)) v |= (uint64_t)1 << k;
+    return v;
+}
+
+/* number of 64-bit words of a stream of `bits` bits, plus the zero pad word */
+ORC_API uint64_t orc_stream_words(uint64_t bits) { return (bits + 63) / 64 + 1; }
+
+ORC_API uint64_t orc_get_bits(const uint64_t *words, uint64_t start, unsigned width) {
+    return get_bits(words, start, width);
+}
+
+/* ------------------------------------------------------------------ */
+/* vertex ID widths -- section "Logarithmization of Vertex IDs"          */
+/* ------------------------------------------------------------------ */
+
+/* Global approach: ceil(log2 n) bits per ID.  Reading: for n = 1 the
+ * formula gives 0, so the width is max(1, bl(n - 1)), which equals
+ * ceil(log2 n) for every n >= 2. */
+ORC_API unsigned orc_global_width(uint64_t n) {
+    unsigned s = n ? bitlen(n - 1) : 0;
+    return s ? s : 1;
+}
+
+/* Local approach: the list of v is stored with enough bits for its largest
+ * ID.  Reading: ceil(log2 maxN_v) undercounts when maxN_v is a power of two
+ * and gives 0 for maxN_v in {0, 1}; the width is max(1, bl(maxN_v)) for a
+ * non-empty list and 0 for an empty one.  The maximum is found by scanning,
+ * not by assuming the list is sorted. */
+ORC_API void orc_local_widths(uint64_t n, const uint64_t *off, const uint32_t *col, uint8_t *w) {
+    for (uint64_t v = 0; v < n; v++) {
+        if (off[v + 1] == off[v]) { w[v] = 0; continue; }
+        uint32_t mx = 0;
+        for (uint64_t i = off[v]; i < off[v + 1]; i++)
+            if (col[i] > mx) mx = col[i];
+        unsigned b = bitlen(mx);
+        w[v] = (uint8_t)(b ? b : 1);
+    }
+}
+
+/* bits of the per-vertex width field: enough to write the global width */
+ORC_API unsigned orc_width_field_bits(uint64_t n) { return bitlen(orc_global_width(n)); }
+
+/* ------------------------------------------------------------------ */
+/* packed adjacency -- "Vertex IDs: The Global/Local Approach" and the   */
+/* edge-access listing of "Accessing An Edge"                            */
+/* ------------------------------------------------------------------ */
+
+/* Bit length of every neighbor list laid end to end: |A| = 2m*s (global)
+ * or sum_v d_v * w_v (local).  w == NULL selects the global width s. */
+ORC_API uint64_t orc_adjacency_bits(uint64_t n, const uint64_t *off, const uint8_t *w, unsigned s) {
+    uint64_t U = 0;
+    for (uint64_t v = 0; v < n; v++)
+        U += (off[v + 1] - off[v]) * (uint64_t)(w ? w[v] : s);
+    return U;
+}
+
+/* Bit start P_v of every list (v = 0..n): the running total of the list
+ * bit lengths before v. */
+ORC_API void orc_bit_starts(uint64_t n, const uint64_t *off, const uint8_t *w, unsigned s, uint64_t *P) {
+    uint64_t acc = 0;
+    for (uint64_t v = 0; v < n; v++) {
+        P[v] = acc;
+        acc += (off[v + 1] - off[v]) * (uint64_t)(w ? w[v] : s);
+    }
+    P[n] = acc;
+}
+
+/* Element i of the list of v occupies stream bits [P_v + i*w_v, + w_v).
+ * `words` must hold orc_stream_words(U) zeroed words. */
+ORC_API void orc_pack_adjacency(uint64_t n, const uint64_t *off, const uint32_t *col,
+                                const uint8_t *w, unsigned s, uint64_t *words) {
+    uint64_t pos = 0;
+    for (uint64_t v = 0; v < n; v++) {
+        unsigned wv = w ? w[v] : s;
+        for (uint64_t i = off[v]; i < off[v + 1]; i++) {
+            put_bits(words, pos, col[i], wv);
+            pos += wv;
+        }
+    }
+}
+
+/* Words [k0, k1) of the same stream, computed without building the rest:
+ * every element is visited in order and only its bits that fall inside
+ * [64*k0, 64*k1) are written.  `out` holds k1 - k0 zeroed words. */
+ORC_API void orc_pack_adjacency_words(uint64_t n, const uint64_t *off, const uint32_t *col,
+                                      const uint8_t *w, unsigned s, uint64_t k0, uint64_t k1,
+                                      uint64_t *out) {
+    uint64_t lo = 64 * k0, hi = 64 * k1, pos = 0;
+    for (uint64_t v = 0; v < n && pos < hi; v++) {
+        unsigned wv = w ? w[v] : s;
+        uint64_t d = off[v + 1] - off[v];
+        if (pos + d * wv <= lo) { pos += d * wv; continue; }
+        for (uint64_t i = off[v]; i < off[v + 1]; i++) {
+            for (unsigned k = 0; k < wv; k++) {
+                uint64_t b = pos + k;
+                if (b >= lo && b < hi && ((col[i] >> k) & 1u)) put_bit(out, b - lo);
+            }
+            pos += wv;
+        }
+    }
+}
+
+/* Element i of a list whose first element starts at stream bit `start`. */
+ORC_API void orc_decode_list(const uint64_t *words, uint64_t start, uint64_t d, unsigned w, uint32_t *out) {
+    for (uint64_t i = 0; i < d; i++)
+        out[i] = (uint32_t)get_bits(words, start + i * (uint64_t)w, w);
+}
+
+/* Fixed-width packing of a value sequence: value j at bits [j*width, +width).
+ * Used for the packed offsets ("Logarithmization of Single Offsets"), the
+ * Elias-Fano low bits and the per-vertex width table. */
+ORC_API void orc_pack_fixed(const uint64_t *vals, uint64_t count, unsigned width, uint64_t *words) {
+    for (uint64_t j = 0; j < count; j++)
+        put_bits(words, j * (uint64_t)width, vals[j], width);
+}
+
+/* ------------------------------------------------------------------ */
+/* bit vector queries -- subsection "Bit Vectors"                        */
+/* ------------------------------------------------------------------ */
+
+/* Reading of the conventions: rank1(i) counts the ones in positions [0, i)
+ * (exclusive).  The paper's inclusive rank_S(x) equals rank1(x + 1).
+ * select1(k) is the position of the k-th one, counting k from 0.  Both
+ * are linear scans. */
+ORC_API uint64_t orc_rank1(const uint64_t *words, uint64_t i) {
+    uint64_t r = 0;
+    for (uint64_t p = 0; p < i; p++) r += (uint64_t)get_bit(words, p);
+    return r;
+}
+
+/* returns the position, or `nbits` when the vector has at most k ones */
+ORC_API uint64_t orc_select1(const uint64_t *words, uint64_t nbits, uint64_t k) {
+    uint64_t seen = 0;
+    for (uint64_t p = 0; p < nbits; p++) {
+        if (get_bit(words, p)) {
+            if (seen == k) return p;
+            seen++;
+        }
+    }
+    return nbits;
+}
+
+/* ------------------------------------------------------------------ */
+/* Elias-Fano offsets -- sections "Logarithmizing Offsets" and           */
+/* "Succinct Bit Vectors in Log(Graph)" (sparse bit vector bvSD)        */
+/* ------------------------------------------------------------------ */
+
+/* The offsets x_0 <= x_1 <= ... <= x_n (universe u = x_n) are kept as an
+ * Elias-Fano sequence.  Reading (the paper sets one bit per list start,
+ * which cannot mark two starts at the same place; the non-decreasing
+ * sequence formulation allows repeats): the low l bits of every x_v are
+ * stored verbatim, and the high part sets bit (x_v >> l) + v of the upper
+ * bit vector H, which therefore holds exactly n + 1 ones.
+ * l = floor(log2(u / (n + 1))) when u >= n + 1, else 0. */
+ORC_API unsigned orc_ef_low_bits(uint64_t count, uint64_t universe) {
+    if (universe < count || count == 0) return 0;
+    return bitlen(universe / count) - 1;
+}
+
+ORC_API uint64_t orc_ef_upper_bits(uint64_t count, uint64_t universe, unsigned l) {
+    return (universe >> l) + count;
+}
+
+/* Directory over H, checkable bit-exactly because every entry is a plain
+ * rank or select value:
+ *   rank_sb[b] = rank1(512 * b) for b = 0 .. ceil(|H| / 512)  (one extra
+ *                entry at the end, which equals the number of ones);
+ *   sel[j]     = select1(64 * j) for j = 0 .. ceil((n + 1) / 64) - 1.     */
+ORC_API uint64_t orc_ef_rank_entries(uint64_t hbits) { return (hbits + 511) / 512 + 1; }
+ORC_API uint64_t orc_ef_select_entries(uint64_t count) { return (count + 63) / 64; }
+
+ORC_API void orc_ef_build(const uint64_t *x, uint64_t count, uint64_t universe,
+                          uint64_t *L, uint64_t *H, uint32_t *rank_sb, uint32_t *sel) {
+    unsigned l = orc_ef_low_bits(count, universe);
+    uint64_t hbits = orc_ef_upper_bits(count, universe, l);
+    for (uint64_t v = 0; v < count; v++) {
+        uint64_t low = l ? (x[v] & (((uint64_t)1 << l) - 1)) : 0;
+        put_bits(L, v * (uint64_t)l, low, l);
+        put_bit(H, (x[v] >> l) + v);
+    }
+    /* one running count over H gives both directory tables */
+    uint64_t nr = orc_ef_rank_entries(hbits), ns = orc_ef_select_entries(count);
+    uint64_t ones = 0;
+    for (uint64_t p = 0; p <= hbits; p++) {
+        if (p % 512 == 0 && p / 512 < nr) rank_sb[p / 512] = (uint32_t)ones;
+        if (p == hbits) break;
+        if (get_bit(H, p)) {
+            if (ones % 64 == 0 && ones / 64 < ns) sel[ones / 64] = (uint32_t)p;
+            ones++;
+        }
+    }
+    rank_sb[nr - 1] = (uint32_t)ones; /* the extra last entry: all ones */
+}
+
+/* x_v recovered from L and H: ((select1(v) - v) << l) | L[v] */
+ORC_API uint64_t orc_ef_get(const uint64_t *L, const uint64_t *H, uint64_t hbits, unsigned l, uint64_t v) {
+    uint64_t pos = orc_select1(H, hbits, v);
+    return ((pos - v) << l) | get_bits(L, v * (uint64_t)l, l);
+}
+
+/* ------------------------------------------------------------------ */
+/* degree-minimizing relabeling -- "Incorporating Degree-Minimizing"   */
+/* ------------------------------------------------------------------ */
+
+/* Higher degree gets a lower label.  Reading of the unstated tie-break:
+ * equal degrees keep their original order.  perm[new] = old and
+ * inv[old] = new.  A plain insertion-free approach: qsort on (-d, id). */
+static const uint64_t *g_sort_off;
+
+static int cmp_dm(const void *a, const void *b) {
+    uint32_t x = *(const uint32_t *)a, y = *(const uint32_t *)b;
+    uint64_t dx = g_sort_off[x + 1] - g_sort_off[x];
+    uint64_t dy = g_sort_off[y + 1] - g_sort_off[y];
+    if (dx != dy) return dx > dy ? -1 : 1;
+    return x < y ? -1 : (x > y ? 1 : 0);
+}
+
+static int cmp_u32(const void *a, const void *b) {
+    uint32_t x = *(const uint32_t *)a, y = *(const uint32_t *)b;
+    return x < y ? -1 : (x > y ? 1 : 0);
+}
+
+ORC_API void orc_dm_permutation(uint64_t n, const uint64_t *off, uint32_t *perm, uint32_t *inv) {
+    for (uint64_t v = 0; v < n; v++) perm[v] = (uint32_t)v;
+    g_sort_off = off;
+    qsort(perm, n, sizeof(uint32_t), cmp_dm);
+    for (uint64_t x = 0; x < n; x++) inv[perm[x]] = (uint32_t)x;
+}
+
+/* The relabeled adjacency array: row x is the list of perm[x] with every
+ * neighbor renamed through inv and re-sorted ascending (lists are kept
+ * sorted, subsection "Adjacency Array Data Structures"). */
+ORC_API void orc_relabel(uint64_t n, const uint64_t *off, const uint32_t *col,
+                         const uint32_t *perm, const uint32_t *inv,
+                         uint64_t *off2, uint32_t *col2) {
+    off2[0] = 0;
+    for (uint64_t x = 0; x < n; x++) {
+        uint32_t v = perm[x];
+        uint64_t d = off[v + 1] - off[v];
+        off2[x + 1] = off2[x] + d;
+        for (uint64_t i = 0; i < d; i++) col2[off2[x] + i] = inv[col[off[v] + i]];
+        qsort(col2 + off2[x], d, sizeof(uint32_t), cmp_u32);
+    }
+}
+
+/* One row of the relabeled adjacency array (row x = list of perm[x]). */
+ORC_API void orc_relabel_row(const uint64_t *off, const uint32_t *col, const uint32_t *perm,
+                             const uint32_t *inv, uint32_t x, uint32_t *out) {
+    uint32_t v = perm[x];
+    uint64_t d = off[v + 1] - off[v];
+    for (uint64_t i = 0; i < d; i++) out[i] = inv[col[off[v] + i]];
+    qsort(out, d, sizeof(uint32_t), cmp_u32);
+}
+
+/* ------------------------------------------------------------------ */
+/* BFS -- section "Considered Algorithms"                               */
+/* ------------------------------------------------------------------ */
+
+/* Textbook FIFO breadth-first search.  depth[v] = hop distance from the
+ * root, -1 when unreachable.  Reading of the (non-unique) BFS tree: the
+ * parent of a reached v != root is its neighbor of depth depth[v] - 1 whose
+ * stored label is smallest; parent[root] = root; parent of an unreached
+ * vertex is -1.  `label` gives the stored label of every vertex (NULL: the
+ * vertex's own ID); depths do not depend on labels.  With max_depth >= 0
+ * every vertex deeper than max_depth is reported as -1 / -1 (k-hop). */
+ORC_API int orc_bfs_labels(uint64_t n, const uint64_t *off, const uint32_t *col, uint32_t root,
+                           int32_t max_depth, const uint32_t *label, int32_t *depth, int32_t *parent) {
+    if (root >= n) return -1;
+    uint32_t *queue = (uint32_t *)malloc(sizeof(uint32_t) * (n ? n : 1));
+    if (!queue) return -2;
+    for (uint64_t v = 0; v < n; v++) depth[v] = -1;
+    uint64_t head = 0, tail = 0;
+    depth[root] = 0;
+    queue[tail++] = root;
+    while (head < tail) {
+        uint32_t v = queue[head++];
+        for (uint64_t i = off[v]; i < off[v + 1]; i++) {
+            uint32_t u = col[i];
+            if (depth[u] < 0) {
+                depth[u] = depth[v] + 1;
+                queue[tail++] = u;
+            }
+        }
+    }
+    free(queue);
+    for (uint64_t v = 0; v < n; v++) {
+        parent[v] = -1;
+        if (depth[v] < 0) continue;
+        if (v == root) { parent[v] = (int32_t)root; continue; }
+        uint32_t best = UINT32_MAX, best_label = UINT32_MAX;
+        for (uint64_t i = off[v]; i < off[v + 1]; i++) {
+            uint32_t u = col[i];
+            uint32_t lu = label ? label[u] : u;
+            if (depth[u] == depth[v] - 1 && lu < best_label) { best_label = lu; best = u; }
+        }
+        parent[v] = (int32_t)best;
+    }
+    if (max_depth >= 0)
+        for (uint64_t v = 0; v < n; v++)
+            if (depth[v] > max_depth) { depth[v] = -1; parent[v] = -1; }
+    return 0;
+}
+
+ORC_API int orc_bfs(uint64_t n, const uint64_t *off, const uint32_t *col, uint32_t root,
+                    int32_t max_depth, int32_t *depth, int32_t *parent) {
+    return orc_bfs_labels(n, off, col, root, max_depth, NULL, depth, parent);
+}
+
+/* BFS when the graph is stored under the degree-minimizing relabeling:
+ * the smallest-label rule applies to the new labels; results stay in
+ * original IDs. */
+ORC_API int orc_bfs_relabeled(uint64_t n, const uint64_t *off, const uint32_t *col, uint32_t root,
+                              int32_t max_depth, int32_t *depth, int32_t *parent) {
+    if (root >= n) return -1;
+    uint32_t *perm = (uint32_t *)malloc(sizeof(uint32_t) * (n ? n : 1));
+    uint32_t *inv = (uint32_t *)malloc(sizeof(uint32_t) * (n ? n : 1));
+    int rc = -2;
+    if (perm && inv) {
+        orc_dm_permutation(n, off, perm, inv);
+        rc = orc_bfs_labels(n, off, col, root, max_depth, inv, depth, parent);
+    }
+    free(perm); free(inv);
+    return rc;
+}
+
+/* ------------------------------------------------------------------ */
+/* PageRank -- section "Considered Algorithms" (pull variant)           */
+/* ------------------------------------------------------------------ */
+
+/* FP64 power iteration on the undirected graph.  Readings of what the
+ * paper leaves unstated: PR_0 = 1/n; the rank of vertices without edges
+ * (dangling mass D_t) is spread uniformly; exactly `iters` iterations:
+ *   PR_{t+1}(v) = (1 - a)/n + a * ( sum_{u in N_v} PR_t(u)/d_u + D_t/n ). */
+ORC_API int orc_pagerank(uint64_t n, const uint64_t *off, const uint32_t *col,
+                         double alpha, uint32_t iters, double *pr) {
+    if (n == 0) return 0;
+    double *next = (double *)malloc(sizeof(double) * n);
+    if (!next) return -2;
+    for (uint64_t v = 0; v < n; v++) pr[v] = 1.0 / (double)n;
+    for (uint32_t t = 0; t < iters; t++) {
+        double dangling = 0.0;
+        for (uint64_t u = 0; u < n; u++)
+            if (off[u + 1] == off[u]) dangling += pr[u];
+        for (uint64_t v = 0; v < n; v++) {
+            double sum = 0.0;
+            for (uint64_t i = off[v]; i < off[v + 1]; i++) {
+                uint32_t u = col[i];
+                sum += pr[u] / (double)(off[u + 1] - off[u]);
+            }
+            next[v] = (1.0 - alpha) / (double)n + alpha * (sum + dangling / (double)n);
+        }
+        memcpy(pr, next, sizeof(double) * n);
+    }
+    free(next);
+    return 0;
+}

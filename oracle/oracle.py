@@ -1,0 +1,307 @@
+"""numpy wrappers over the C oracle (test infrastructure only)."""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+u64p = np.ctypeslib.ndpointer(np.uint64, flags="C_CONTIGUOUS")
+u32p = np.ctypeslib.ndpointer(np.uint32, flags="C_CONTIGUOUS")
+i32p = np.ctypeslib.ndpointer(np.int32, flags="C_CONTIGUOUS")
+u8p = np.ctypeslib.ndpointer(np.uint8, flags="C_CONTIGUOUS")
+f64p = np.ctypeslib.ndpointer(np.float64, flags="C_CONTIGUOUS")
+
+
+class _NullableU8:
+    """ctypes argument type accepting a uint8 array or None."""
+
+    @classmethod
+    def from_param(cls, obj):
+        if obj is None:
+            return None
+        return u8p.from_param(obj)
+
+
+class _NullableU32:
+    @classmethod
+    def from_param(cls, obj):
+        if obj is None:
+            return None
+        return u32p.from_param(obj)
+
+
+def lib():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH) or (
+        os.path.getmtime(_LIB_PATH) < os.path.getmtime(os.path.join(_HERE, "lg_oracle.c"))
+    ):
+        from . import build as _b
+        _b.build()
+    L = C.CDLL(_LIB_PATH)
+    sig = {
+        "orc_bitlen": (C.c_uint, [C.c_uint64]),
+        "orc_stream_words": (C.c_uint64, [C.c_uint64]),
+        "orc_get_bits": (C.c_uint64, [u64p, C.c_uint64, C.c_uint]),
+        "orc_global_width": (C.c_uint, [C.c_uint64]),
+        "orc_local_widths": (None, [C.c_uint64, u64p, u32p, u8p]),
+        "orc_width_field_bits": (C.c_uint, [C.c_uint64]),
+        "orc_adjacency_bits": (C.c_uint64, [C.c_uint64, u64p, _NullableU8, C.c_uint]),
+        "orc_bit_starts": (None, [C.c_uint64, u64p, _NullableU8, C.c_uint, u64p]),
+        "orc_pack_adjacency": (None, [C.c_uint64, u64p, u32p, _NullableU8, C.c_uint, u64p]),
+        "orc_pack_adjacency_words": (None, [C.c_uint64, u64p, u32p, _NullableU8, C.c_uint,
+                                            C.c_uint64, C.c_uint64, u64p]),
+        "orc_decode_list": (None, [u64p, C.c_uint64, C.c_uint64, C.c_uint, u32p]),
+        "orc_pack_fixed": (None, [u64p, C.c_uint64, C.c_uint, u64p]),
+        "orc_rank1": (C.c_uint64, [u64p, C.c_uint64]),
+        "orc_select1": (C.c_uint64, [u64p, C.c_uint64, C.c_uint64]),
+        "orc_ef_low_bits": (C.c_uint, [C.c_uint64, C.c_uint64]),
+        "orc_ef_upper_bits": (C.c_uint64, [C.c_uint64, C.c_uint64, C.c_uint]),
+        "orc_ef_rank_entries": (C.c_uint64, [C.c_uint64]),
+        "orc_ef_select_entries": (C.c_uint64, [C.c_uint64]),
+        "orc_ef_build": (None, [u64p, C.c_uint64, C.c_uint64, u64p, u64p, u32p, u32p]),
+        "orc_ef_get": (C.c_uint64, [u64p, u64p, C.c_uint64, C.c_uint, C.c_uint64]),
+        "orc_dm_permutation": (None, [C.c_uint64, u64p, u32p, u32p]),
+        "orc_relabel": (None, [C.c_uint64, u64p, u32p, u32p, u32p, u64p, u32p]),
+        "orc_relabel_row": (None, [u64p, u32p, u32p, u32p, C.c_uint32, u32p]),
+        "orc_bfs_labels": (C.c_int, [C.c_uint64, u64p, u32p, C.c_uint32, C.c_int32, _NullableU32,
+                                     i32p, i32p]),
+        "orc_bfs": (C.c_int, [C.c_uint64, u64p, u32p, C.c_uint32, C.c_int32, i32p, i32p]),
+        "orc_bfs_relabeled": (C.c_int, [C.c_uint64, u64p, u32p, C.c_uint32, C.c_int32, i32p, i32p]),
+        "orc_pagerank": (C.c_int, [C.c_uint64, u64p, u32p, C.c_double, C.c_uint32, f64p]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def _csr(off, col):
+    off = np.ascontiguousarray(off, dtype=np.uint64)
+    col = np.ascontiguousarray(col, dtype=np.uint32)
+    n = off.size - 1
+    return n, off, col
+
+
+# -- widths -------------------------------------------------------------
+
+def bitlen(x: int) -> int:
+    return int(lib().orc_bitlen(int(x)))
+
+
+def global_width(n: int) -> int:
+    return int(lib().orc_global_width(int(n)))
+
+
+def width_field_bits(n: int) -> int:
+    return int(lib().orc_width_field_bits(int(n)))
+
+
+def local_widths(off, col) -> np.ndarray:
+    n, off, col = _csr(off, col)
+    w = np.zeros(n, dtype=np.uint8)
+    lib().orc_local_widths(n, off, col, w)
+    return w
+
+
+# -- packing ----------------------------------------------------------
+
+def stream_words(bits: int) -> int:
+    return int(lib().orc_stream_words(int(bits)))
+
+
+def adjacency_bits(off, widths=None, s: int = 0) -> int:
+    off = np.ascontiguousarray(off, dtype=np.uint64)
+    return int(lib().orc_adjacency_bits(off.size - 1, off, widths, s))
+
+
+def bit_starts(off, widths=None, s: int = 0) -> np.ndarray:
+    off = np.ascontiguousarray(off, dtype=np.uint64)
+    P = np.zeros(off.size, dtype=np.uint64)
+    lib().orc_bit_starts(off.size - 1, off, widths, s, P)
+    return P
+
+
+def pack_adjacency(off, col, widths=None, s: int = 0) -> np.ndarray:
+    n, off, col = _csr(off, col)
+    U = adjacency_bits(off, widths, s)
+    words = np.zeros(stream_words(U), dtype=np.uint64)
+    lib().orc_pack_adjacency(n, off, col, widths, s, words)
+    return words
+
+
+def pack_adjacency_words(off, col, k0: int, k1: int, widths=None, s: int = 0) -> np.ndarray:
+    n, off, col = _csr(off, col)
+    out = np.zeros(max(k1 - k0, 1), dtype=np.uint64)
+    lib().orc_pack_adjacency_words(n, off, col, widths, s, k0, k1, out)
+    return out[: k1 - k0]
+
+
+def decode_list(words, start: int, d: int, w: int) -> np.ndarray:
+    words = np.ascontiguousarray(words, dtype=np.uint64)
+    out = np.zeros(max(d, 1), dtype=np.uint32)
+    lib().orc_decode_list(words, start, d, w, out)
+    return out[:d]
+
+
+def get_bits(words, start: int, width: int) -> int:
+    words = np.ascontiguousarray(words, dtype=np.uint64)
+    return int(lib().orc_get_bits(words, start, width))
+
+
+def pack_fixed(vals, width: int) -> np.ndarray:
+    vals = np.ascontiguousarray(vals, dtype=np.uint64)
+    words = np.zeros(stream_words(vals.size * width), dtype=np.uint64)
+    lib().orc_pack_fixed(vals, vals.size, width, words)
+    return words
+
+
+# -- bit vectors ------------------------------------------------------
+
+def rank1(words, i: int) -> int:
+    return int(lib().orc_rank1(np.ascontiguousarray(words, dtype=np.uint64), i))
+
+
+def select1(words, nbits: int, k: int) -> int:
+    return int(lib().orc_select1(np.ascontiguousarray(words, dtype=np.uint64), nbits, k))
+
+
+class EF:
+    """Elias-Fano offsets as the oracle builds them."""
+
+    def __init__(self, x, universe: int):
+        x = np.ascontiguousarray(x, dtype=np.uint64)
+        L = lib()
+        self.count = x.size
+        self.universe = int(universe)
+        self.l = int(L.orc_ef_low_bits(self.count, self.universe))
+        self.hbits = int(L.orc_ef_upper_bits(self.count, self.universe, self.l))
+        self.low = np.zeros(stream_words(self.count * self.l), dtype=np.uint64)
+        self.high = np.zeros(stream_words(self.hbits), dtype=np.uint64)
+        self.rank_sb = np.zeros(int(L.orc_ef_rank_entries(self.hbits)), dtype=np.uint32)
+        self.sel = np.zeros(max(int(L.orc_ef_select_entries(self.count)), 1), dtype=np.uint32)
+        L.orc_ef_build(x, self.count, self.universe, self.low, self.high, self.rank_sb, self.sel)
+        self.sel = self.sel[: int(L.orc_ef_select_entries(self.count))]
+
+    def get(self, v: int) -> int:
+        return int(lib().orc_ef_get(self.low, self.high, self.hbits, self.l, v))
+
+
+# -- relabeling -------------------------------------------------------
+
+def dm_permutation(off):
+    off = np.ascontiguousarray(off, dtype=np.uint64)
+    n = off.size - 1
+    perm = np.zeros(max(n, 1), dtype=np.uint32)
+    inv = np.zeros(max(n, 1), dtype=np.uint32)
+    lib().orc_dm_permutation(n, off, perm, inv)
+    return perm[:n], inv[:n]
+
+
+def relabel(off, col, perm, inv):
+    n, off, col = _csr(off, col)
+    off2 = np.zeros(n + 1, dtype=np.uint64)
+    col2 = np.zeros(max(col.size, 1), dtype=np.uint32)
+    lib().orc_relabel(n, off, col, np.ascontiguousarray(perm, np.uint32),
+                      np.ascontiguousarray(inv, np.uint32), off2, col2)
+    return off2, col2[: col.size]
+
+
+def relabel_row(off, col, perm, inv, x: int) -> np.ndarray:
+    n, off, col = _csr(off, col)
+    v = int(perm[x])
+    d = int(off[v + 1] - off[v])
+    out = np.zeros(max(d, 1), dtype=np.uint32)
+    lib().orc_relabel_row(off, col, np.ascontiguousarray(perm, np.uint32),
+                          np.ascontiguousarray(inv, np.uint32), x, out)
+    return out[:d]
+
+
+# -- algorithms -------------------------------------------------------
+
+def bfs(off, col, root: int, max_depth: int = -1, relabeled: bool = False, labels=None):
+    n, off, col = _csr(off, col)
+    depth = np.zeros(max(n, 1), dtype=np.int32)
+    parent = np.zeros(max(n, 1), dtype=np.int32)
+    if relabeled:
+        rc = lib().orc_bfs_relabeled(n, off, col, root, max_depth, depth, parent)
+    elif labels is not None:
+        rc = lib().orc_bfs_labels(n, off, col, root, max_depth,
+                                  np.ascontiguousarray(labels, np.uint32), depth, parent)
+    else:
+        rc = lib().orc_bfs(n, off, col, root, max_depth, depth, parent)
+    if rc != 0:
+        raise ValueError(f"oracle bfs failed ({rc})")
+    return depth[:n], parent[:n]
+
+
+def pagerank(off, col, alpha: float = 0.85, iters: int = 20) -> np.ndarray:
+    n, off, col = _csr(off, col)
+    pr = np.zeros(max(n, 1), dtype=np.float64)
+    rc = lib().orc_pagerank(n, off, col, alpha, iters, pr)
+    if rc != 0:
+        raise ValueError("oracle pagerank failed")
+    return pr[:n]
+
+
+# -- the whole encoding as the oracle defines it --------------------
+
+class Encoding:
+    """Every array of the packed representation, built by the oracle.
+
+    id_mode: "global" (every ID at s bits) or "local" (list v at w_v bits,
+    with a width table at F bits per vertex).  offset_mode: "packed"
+    (fixed-width offsets) or "ef" (Elias-Fano with rank/select directory).
+    The offset values are element offsets O[v] in global mode (bit start =
+    s * O[v]) and bit starts P_v in local mode.  relabel: apply the
+    degree-minimizing permutation first."""
+
+    def __init__(self, off, col, id_mode="global", offset_mode="packed", relabel=False):
+        n, off, col = _csr(off, col)
+        self.n = n
+        self.m = col.size
+        if relabel:
+            self.perm, self.inv = dm_permutation(off)
+            off, col = globals()["relabel"](off, col, self.perm, self.inv)
+        else:
+            self.perm = self.inv = None
+        self.off, self.col = off, col
+        self.s = global_width(n)
+        if id_mode == "global":
+            self.widths = None
+            self.U = adjacency_bits(off, None, self.s)
+            self.A = pack_adjacency(off, col, None, self.s)
+            vals = off
+            universe = self.m
+        else:
+            self.widths = local_widths(off, col)
+            self.F = width_field_bits(n)
+            self.W = pack_fixed(self.widths.astype(np.uint64), self.F)
+            self.U = adjacency_bits(off, self.widths, 0)
+            self.A = pack_adjacency(off, col, self.widths, 0)
+            vals = bit_starts(off, self.widths, 0)
+            universe = self.U
+        self.P = bit_starts(off, self.widths, self.s if self.widths is None else 0)
+        self.offset_values = vals
+        self.universe = universe
+        if offset_mode == "packed":
+            self.wO = bitlen(universe)
+            self.O = pack_fixed(vals, self.wO)
+            self.ef = None
+        else:
+            self.ef = EF(vals, universe)
+
+    def neighbors(self, x: int) -> np.ndarray:
+        """Stored list of stored label x, decoded bit by bit."""
+        w = self.s if self.widths is None else int(self.widths[x])
+        d = int(self.off[x + 1] - self.off[x])
+        return decode_list(self.A, int(self.P[x]), d, w)
