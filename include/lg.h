@@ -1,0 +1,236 @@
+/*
+ * lg.h -- C ABI of the MI355X Log(Graph) packed-graph library (liblg.so).
+ *
+ * Log(Graph) (Besta et al., "Log(Graph): A Near-Optimal High-Performance
+ * Graph Representation") stores an undirected graph as an adjacency array
+ * whose neighbor IDs are bit-packed ("logarithmized") and whose offsets are
+ * either bit-packed or held in a succinct bit vector.  This library builds
+ * that representation on the GPU and runs BFS and PageRank directly on it,
+ * decoding inside the traversal kernels.
+ *
+ * Conventions shared by every call:
+ *   - Vertex IDs are 0-based uint32.  The input graph is undirected: both
+ *     directions of every edge are stored, no self-loops, no duplicates,
+ *     each neighbor list strictly increasing (the paper's adjacency array,
+ *     section "Adjacency Array Data Structures", keeps every list sorted).
+ *   - "dev" pointers are device pointers on the current HIP device; "host"
+ *     pointers are ordinary host memory.  The caller owns every buffer it
+ *     passes; the library keeps no reference to it after the call returns.
+ *   - A packed bit stream stores its bit b as bit (b mod 64) of little-endian
+ *     64-bit word b/64; a value's bit k is stream bit start + k; unused bits
+ *     are zero and every stream ends with one extra zero word (the layout of
+ *     the edge-access listing in subsection "Accessing An Edge").
+ *   - Calls return an lg_status and never throw.  On failure nothing is left
+ *     allocated, output handles are left NULL and lg_last_error() describes
+ *     the failure.  Device faults surface as LG_ERR_DEVICE.
+ *   - Every call except lg_encode (and lg_decode_neighbors, which reads one
+ *     total back) is asynchronous on `stream`; results are valid once the
+ *     stream has been synchronized.  Calls on one graph must not overlap in
+ *     time on different streams: they share the graph's device workspace.
+ */
+#ifndef LG_H
+#define LG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lg_graph lg_graph; /* opaque; owned by the library */
+
+typedef enum lg_status {
+    LG_OK = 0,
+    LG_ERR_INVALID = 1,     /* argument or input graph violates the contract   */
+    LG_ERR_OOM = 2,         /* device allocation failed                          */
+    LG_ERR_DEVICE = 3,      /* a HIP call or kernel failed                       */
+    LG_ERR_UNSUPPORTED = 4, /* valid request outside what this build handles     */
+    LG_ERR_CAPACITY = 5     /* caller-provided output buffer too small           */
+} lg_status;
+
+/* lg_encode_opts.layout */
+#define LG_LAYOUT_PACKED 0u /* the logarithmized representation                  */
+#define LG_LAYOUT_PLAIN 1u  /* plain CSR baseline: uint32 IDs, uint32 offsets
+                               (uint64 when M >= 2^32), same labeling rules     */
+/* lg_encode_opts.id_mode -- section "Logarithmization of Vertex IDs" */
+#define LG_IDS_GLOBAL 0u /* every ID at s = ceil(log2 n) bits (max(1, bl(n-1)))   */
+#define LG_IDS_LOCAL 1u  /* list of v at w_v = max(1, bl(max N_v)) bits, 0 when
+                            empty; w_v kept in a table of F = bl(s) bits/vertex  */
+/* lg_encode_opts.offset_mode -- sections "Logarithmization of Single Offsets"
+ * and "Logarithmizing Offsets" */
+#define LG_OFFS_PACKED 0u   /* offsets packed at bl(universe) bits each          */
+#define LG_OFFS_SUCCINCT 1u /* Elias-Fano sequence (sparse bit vector bvSD) with
+                               a rank/select directory                           */
+/* lg_encode_opts.relabel -- section "Incorporating Degree-Minimizing (DM)" */
+#define LG_RELABEL_NONE 0u
+#define LG_RELABEL_DEGREE 1u /* new label = rank by (degree desc, ID asc)         */
+
+typedef struct lg_encode_opts {
+    uint32_t layout;      /* LG_LAYOUT_*                                          */
+    uint32_t id_mode;     /* LG_IDS_* (packed layout only)                        */
+    uint32_t offset_mode; /* LG_OFFS_* (packed layout only)                       */
+    uint32_t relabel;     /* LG_RELABEL_*                                         */
+    uint32_t flags;       /* reserved, must be 0                                  */
+    uint32_t reserved[3]; /* must be 0                                            */
+} lg_encode_opts;
+
+/*
+ * lg_encode -- build a graph representation from an adjacency array.
+ *
+ * Follows the construction of the library listing in section
+ * "High-Performance Library" (relabel the vertices with the permuter, map
+ * the relabeled lists to bits with the transformer, then build and condense
+ * the offset structure), with the widths of "Logarithmization of Vertex
+ * IDs", the offsets of "Logarithmization of Single Offsets" or the sparse
+ * succinct bit vector of "Succinct Bit Vectors in Log(Graph)".
+ *
+ *   n            number of vertices, 1 <= n < 2^31
+ *   m            number of stored directed entries M (twice the undirected
+ *                edge count), m < 2^36
+ *   row_offsets  dev, uint64[n+1]; row_offsets[0] = 0, row_offsets[n] = m
+ *   col          dev, uint32[m]; the neighbor lists, back to back
+ *   opts         host; NULL means packed layout, global IDs, packed offsets,
+ *                no relabeling
+ *   stream       HIP stream for all work
+ *   out          host; receives the new handle
+ *
+ * The input is validated on the device: offsets non-decreasing, every ID
+ * < n, no self-loop, lists strictly increasing, and the graph symmetric.  A
+ * violation returns LG_ERR_INVALID.  Synchronous: it reads the total bit
+ * length back to size the packed arrays.  The input buffers are not kept.
+ */
+lg_status lg_encode(uint32_t n, uint64_t m, const uint64_t *row_offsets, const uint32_t *col,
+                    const lg_encode_opts *opts, hipStream_t stream, lg_graph **out);
+
+/* lg_decode_neighbors flags */
+#define LG_DECODE_SORTED 0u  /* original IDs, every list ascending (default)        */
+#define LG_DECODE_ORIGINAL 1u /* original IDs, in stored order                      */
+#define LG_DECODE_RAW 2u     /* `vertices` and results are stored labels, stored
+                                order (what the traversal kernels see)            */
+
+/*
+ * lg_decode_neighbors -- N_v for a batch of vertices (getNeighbors of the
+ * library listing in section "High-Performance Library"; per element the
+ * N_{i,v} extraction of subsection "Accessing An Edge", the degree
+ * d_v = O[v+1] - O[v] of subsection "Accessing a Degree").
+ *
+ *   vertices  dev, uint32[k]: original IDs (stored labels with LG_DECODE_RAW),
+ *             each < n
+ *   k         number of vertices (0 allowed)
+ *   out_off   dev, uint64[k+1]: exclusive prefix of the list lengths; always
+ *             written, also when LG_ERR_CAPACITY is returned
+ *   out_ids   dev, uint32[cap] or NULL: list i at out_ids[out_off[i] ..
+ *             out_off[i+1])
+ *   cap       capacity of out_ids in elements
+ * Returns LG_ERR_CAPACITY when out_ids is NULL or too small for the total.
+ * Reads the total back (one stream synchronization).
+ */
+lg_status lg_decode_neighbors(const lg_graph *g, const uint32_t *vertices, uint32_t k,
+                              uint64_t *out_off, uint32_t *out_ids, uint64_t cap,
+                              uint32_t flags, hipStream_t stream);
+
+/* lg_bfs flags */
+#define LG_BFS_DIRECTION_OPT 0u /* top-down/bottom-up switching (default)          */
+#define LG_BFS_TOP_DOWN 1u      /* top-down steps only                              */
+#define LG_BFS_BOTTOM_UP 2u     /* bottom-up steps after the first level            */
+
+/*
+ * lg_bfs -- breadth-first search from each root (the direction-optimizing
+ * BFS of section "Considered Algorithms"), decoding the packed lists inside
+ * the frontier kernels.
+ *
+ *   roots      host, uint32[r]: original IDs, each < n
+ *   r          number of roots
+ *   depth      dev, int32[r*n]: row i = hop distance from roots[i], -1 when
+ *              unreachable (or deeper than max_depth)
+ *   parent     dev, int32[r*n] or NULL: row i = BFS tree in original IDs;
+ *              parent of a reached v != root is its neighbor one level up
+ *              with the smallest stored label, parent[root] = root, -1 for
+ *              unreached vertices
+ *   max_depth  -1 for a full traversal; k >= 0 stops after depth k (k-hop)
+ * Results are independent of the flags and of the direction switching.
+ */
+lg_status lg_bfs(const lg_graph *g, const uint32_t *roots, uint32_t r, int32_t *depth,
+                 int32_t *parent, int32_t max_depth, uint32_t flags, hipStream_t stream);
+
+/*
+ * lg_pagerank -- pull PageRank without atomics (section "Considered
+ * Algorithms"), FP32 storage:
+ *   PR_0 = 1/n;  PR_{t+1}(v) = (1-a)/n + a (sum_{u in N_v} PR_t(u)/d_u + D_t/n)
+ * where D_t is the rank held by vertices without edges, spread uniformly.
+ *
+ *   damping  a, in [0, 1]
+ *   iters    number of iterations (exactly; no convergence test)
+ *   scores   dev, float[n], indexed by original ID
+ */
+lg_status lg_pagerank(const lg_graph *g, float damping, uint32_t iters, float *scores,
+                      hipStream_t stream);
+
+/* Release a graph and its device memory.  NULL is accepted. */
+void lg_free(lg_graph *g);
+
+/* Sizes and parameters of a built representation. */
+typedef struct lg_graph_info {
+    uint64_t n;            /* vertices                                           */
+    uint64_t m;            /* stored directed entries M                          */
+    uint32_t layout, id_mode, offset_mode, relabel;
+    uint32_t s;            /* global ID width                                    */
+    uint32_t F;            /* width-table field bits (local mode), else 0        */
+    uint32_t w_offset;     /* packed offset width (packed offsets), else 0       */
+    uint32_t ef_l;         /* Elias-Fano low bits (succinct offsets), else 0     */
+    uint64_t universe;     /* largest offset value: M (global) or U (local)      */
+    uint64_t adj_bits;     /* U: bits of the packed lists                        */
+    uint64_t ef_high_bits; /* |H| in bits (succinct offsets)                     */
+    uint64_t bytes_adj;    /* bytes of the neighbor data (packed words / uint32) */
+    uint64_t bytes_offsets;/* bytes of the offset structure incl. directory      */
+    uint64_t bytes_widths; /* bytes of the width table                           */
+    uint64_t bytes_perm;   /* bytes of the two permutation arrays                */
+    uint64_t device_bytes; /* all device memory held by the handle now           */
+    uint32_t max_degree;
+    uint32_t isolated;     /* vertices without edges                             */
+} lg_graph_info;
+
+lg_status lg_info(const lg_graph *g, lg_graph_info *out);
+
+/* lg_export `which` */
+#define LG_EXPORT_ADJ 0u       /* packed words (uint64) or plain IDs (uint32)     */
+#define LG_EXPORT_OFFSETS 1u   /* packed offset words (uint64) or plain offsets   */
+#define LG_EXPORT_WIDTHS 2u    /* width-table words (uint64)                      */
+#define LG_EXPORT_EF_LOW 3u    /* Elias-Fano low-bit words (uint64)               */
+#define LG_EXPORT_EF_HIGH 4u   /* upper bit vector H words (uint64)               */
+#define LG_EXPORT_EF_RANK 5u   /* uint32 rank1(512 b), b = 0 .. ceil(|H|/512)     */
+#define LG_EXPORT_EF_SELECT 6u /* uint32 select1(64 j), j < ceil((n+1)/64)        */
+#define LG_EXPORT_PERM 7u      /* uint32 perm[new] = original                     */
+#define LG_EXPORT_INV 8u       /* uint32 inv[original] = new                      */
+
+/*
+ * Copy one raw array of the representation to host memory (synchronous).
+ * `bytes` must equal lg_export_bytes(g, which); an array the handle does
+ * not hold returns LG_ERR_INVALID.
+ */
+lg_status lg_export(const lg_graph *g, uint32_t which, void *host_dst, uint64_t bytes);
+uint64_t lg_export_bytes(const lg_graph *g, uint32_t which);
+
+/* Thread-local description of the last failure on this thread. */
+const char *lg_last_error(void);
+
+/*
+ * Kernel timing: while enabled, every kernel launch is bracketed by two HIP
+ * events on the stream it is launched on.  lg_prof_query sums the elapsed
+ * times of all completed launches of the kernel named `kernel` since the
+ * last reset (waiting for them).  lg_prof_names writes the known kernel
+ * names, newline separated, into buf.
+ */
+lg_status lg_prof_enable(int on);
+lg_status lg_prof_reset(void);
+lg_status lg_prof_query(const char *kernel, uint64_t *launches, double *total_ms);
+lg_status lg_prof_names(char *buf, uint64_t bytes);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LG_H */

@@ -1,0 +1,425 @@
+// lg_bfs: direction-optimizing breadth-first search over the packed (or
+// plain) adjacency array, decoding neighbor lists inside the frontier
+// kernels (BFS of section "Considered Algorithms"; the edge extraction of
+// subsection "Accessing An Edge").
+//
+// Top-down level d:
+//   prepare  per frontier vertex: (first bit, degree, width) from the offset
+//            structure; exclusive scan of the degrees
+//   expand   every block takes a fixed tile of frontier edges, stages the
+//            frontier entries the tile touches in LDS, and each lane decodes
+//            one edge (u), skips u if visited before this level, claims
+//            depth[u] with a CAS, records the smallest-label parent with
+//            atomicMin, and winners are appended to the next queue with one
+//            atomic per wave (ballot + mbcnt)
+// Bottom-up level d:
+//   each wave owns 64 consecutive vertices (one visited word); an unvisited
+//   vertex decodes its list in ascending order and stops at the first
+//   neighbor in the frontier bitmap, which is its smallest-label parent
+// The switch between the two follows the edge-count heuristic of
+// direction-optimizing BFS; it changes the running time only.
+#include <algorithm>
+
+#include "lg_device.hpp"
+
+namespace lg {
+
+struct BfsWork {
+    uint32_t n = 0;
+    DevBuf qa, qb;              // frontier queues (stored labels)
+    DevBuf fstart, fdeg, fw;    // per frontier entry: first bit/element, degree, width
+    DevBuf fscan;               // exclusive scan of fdeg
+    DevBuf visited, curr, next; // bitmaps, one bit per vertex
+    DevBuf counters;            // [0] queue tail, [1] awakened count
+    DevBuf depth_i, parent_i;   // label-space results when relabeled
+    DevBuf scan_tmp;
+    uint64_t *host = nullptr;   // pinned readback slots
+};
+
+uint64_t bfs_bytes(const lg_graph *g) {
+    if (!g->bfs) return 0;
+    const BfsWork *w = g->bfs;
+    return w->qa.bytes + w->qb.bytes + w->fstart.bytes + w->fdeg.bytes + w->fw.bytes + w->fscan.bytes +
+           w->visited.bytes + w->curr.bytes + w->next.bytes + w->counters.bytes + w->depth_i.bytes +
+           w->parent_i.bytes + w->scan_tmp.bytes;
+}
+
+lg_status bfs_free(lg_graph *g) {
+    if (g->bfs) {
+        if (g->bfs->host) (void)hipHostFree(g->bfs->host);
+        delete g->bfs;
+        g->bfs = nullptr;
+    }
+    return LG_OK;
+}
+
+static lg_status bfs_workspace(lg_graph *g, bool need_parent) {
+    if (!g->bfs) {
+        g->bfs = new (std::nothrow) BfsWork();
+        if (!g->bfs) { set_error("lg_bfs: host allocation failed"); return LG_ERR_OOM; }
+        if (hipHostMalloc((void **)&g->bfs->host, 8 * sizeof(uint64_t)) != hipSuccess) {
+            g->bfs->host = nullptr;
+            bfs_free(g);
+            set_error("lg_bfs: pinned host allocation failed");
+            return LG_ERR_OOM;
+        }
+    }
+    BfsWork &w = *g->bfs;
+    const uint64_t n = g->n;
+    const uint64_t words = (n + 63) / 64;
+    w.n = g->n;
+    LG_TRY(w.qa.ensure(n * 4));
+    LG_TRY(w.qb.ensure(n * 4));
+    LG_TRY(w.fstart.ensure(n * 8));
+    LG_TRY(w.fdeg.ensure(n * 4));
+    LG_TRY(w.fw.ensure(n * 4));
+    LG_TRY(w.fscan.ensure((n + 1) * 8));
+    LG_TRY(w.visited.ensure(words * 8));
+    LG_TRY(w.curr.ensure(words * 8));
+    LG_TRY(w.next.ensure(words * 8));
+    LG_TRY(w.counters.ensure(8 * 8));
+    if (g->relabel == LG_RELABEL_DEGREE) {
+        LG_TRY(w.depth_i.ensure(n * 4));
+        if (need_parent) LG_TRY(w.parent_i.ensure(n * 4));
+    }
+    return LG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// kernels
+// ---------------------------------------------------------------------------
+
+__global__ void bfs_init_kernel(uint32_t n, int32_t *__restrict__ depth, uint32_t *__restrict__ parent,
+                                uint64_t *__restrict__ visited, uint32_t root, uint32_t *__restrict__ queue,
+                                uint64_t *__restrict__ counters) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    const uint64_t words = ((uint64_t)n + 63) / 64;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        depth[i] = i == root ? 0 : -1;
+        if (parent) parent[i] = i == root ? root : 0xFFFFFFFFu;
+        if (i < words) visited[i] = (i == (root >> 6)) ? (1ull << (root & 63)) : 0ull;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        queue[0] = root;
+        counters[0] = 0;
+        counters[1] = 0;
+    }
+}
+
+template <class Acc>
+__global__ void td_prepare_kernel(Acc acc, const uint32_t *__restrict__ queue, uint32_t qsize,
+                                  uint64_t *__restrict__ fstart, uint32_t *__restrict__ fdeg,
+                                  uint32_t *__restrict__ fw) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < qsize; i += stride) {
+        const VInfo vi = acc.info(queue[i]);
+        fstart[i] = vi.start;
+        fdeg[i] = vi.deg;
+        fw[i] = vi.w;
+    }
+}
+
+constexpr int kTdThreads = 256;
+constexpr int kTdEdgesPerThread = 4;
+constexpr uint32_t kTdTile = kTdThreads * kTdEdgesPerThread;
+
+// largest i in [lo, hi] with a[i] <= x (a non-decreasing, a[lo] <= x)
+template <class T>
+__device__ __forceinline__ uint32_t last_le(const T *a, uint32_t lo, uint32_t hi, uint64_t x) {
+    while (lo < hi) {
+        const uint32_t mid = lo + ((hi - lo + 1) >> 1);
+        if ((uint64_t)a[mid] <= x) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+template <class Acc, bool kParent>
+__global__ __launch_bounds__(kTdThreads) void td_expand_kernel(
+    Acc acc, const uint32_t *__restrict__ queue, uint32_t qsize, const uint64_t *__restrict__ fstart,
+    const uint32_t *__restrict__ fw, const uint64_t *__restrict__ fscan, uint64_t edges,
+    const uint64_t *__restrict__ visited, int32_t *__restrict__ depth, uint32_t *__restrict__ parent,
+    int32_t next_depth, uint32_t *__restrict__ queue_out, unsigned long long *__restrict__ tail) {
+    __shared__ uint64_t s_scan[kTdTile + 1];
+    __shared__ uint64_t s_start[kTdTile];
+    __shared__ uint32_t s_w[kTdTile];
+    __shared__ uint32_t s_v[kTdTile];
+    __shared__ uint32_t s_range[2];
+    const uint32_t lane = lane_id();
+    for (uint64_t t = blockIdx.x; t * kTdTile < edges; t += gridDim.x) {
+        const uint64_t e0 = t * kTdTile;
+        const uint64_t e1 = e0 + kTdTile < edges ? e0 + kTdTile : edges;
+        if (threadIdx.x == 0) s_range[0] = last_le(fscan, 0, qsize - 1, e0);
+        if (threadIdx.x == 1) s_range[1] = last_le(fscan, 0, qsize - 1, e1 - 1);
+        __syncthreads();
+        const uint32_t i0 = s_range[0];
+        const uint32_t span = s_range[1] - i0 + 1;
+        const bool staged = span <= kTdTile;
+        if (staged) {
+            for (uint32_t j = threadIdx.x; j < span; j += kTdThreads) {
+                s_scan[j] = fscan[i0 + j];
+                s_start[j] = fstart[i0 + j];
+                s_w[j] = fw[i0 + j];
+                s_v[j] = queue[i0 + j];
+            }
+        }
+        __syncthreads();
+        for (uint64_t e = e0 + threadIdx.x; e < e1; e += kTdThreads) {
+            uint64_t base_e, start;
+            uint32_t w, v;
+            if (staged) {
+                const uint32_t j = last_le(s_scan, 0, span - 1, e);
+                base_e = s_scan[j]; start = s_start[j]; w = s_w[j]; v = s_v[j];
+            } else {
+                const uint32_t j = last_le(fscan, i0, s_range[1], e);
+                base_e = fscan[j]; start = fstart[j]; w = fw[j]; v = queue[j];
+            }
+            const uint32_t u = acc.get(start + (e - base_e) * Acc::step(w), Acc::mask(w));
+            bool win = false;
+            if (!((visited[u >> 6] >> (u & 63)) & 1ull)) {
+                const int32_t old = atomicCAS(&depth[u], -1, next_depth);
+                if (kParent && (old == -1 || old == next_depth)) atomicMin(&parent[u], v);
+                win = old == -1;
+            }
+            const uint64_t m = __ballot(win);
+            if (m) {
+                const uint32_t leader = (uint32_t)__ffsll((long long)m) - 1;
+                unsigned long long base = 0;
+                if (lane == leader) base = atomicAdd(tail, (unsigned long long)__popcll(m));
+                base = __shfl(base, leader, kWave);
+                if (win) queue_out[base + popc_below(m)] = u;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void mark_queue_kernel(const uint32_t *__restrict__ queue, const unsigned long long *__restrict__ qsize_dev,
+                                  unsigned long long *__restrict__ bits) {
+    const uint64_t q = *qsize_dev;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < q; i += stride) {
+        const uint32_t u = queue[i];
+        atomicOr(&bits[u >> 6], 1ull << (u & 63));
+    }
+}
+
+template <class Acc, bool kParent>
+__global__ void bu_step_kernel(Acc acc, uint32_t n, const uint64_t *__restrict__ curr,
+                               uint64_t *__restrict__ visited, uint64_t *__restrict__ next,
+                               int32_t *__restrict__ depth, uint32_t *__restrict__ parent, int32_t next_depth,
+                               unsigned long long *__restrict__ awake) {
+    const uint32_t lane = lane_id();
+    const uint64_t words = ((uint64_t)n + 63) / 64;
+    const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) / kWave;
+    for (uint64_t q = wave; q < words; q += nwaves) {
+        const uint64_t vis = visited[q];
+        const uint64_t v = q * 64 + lane;
+        bool found = false;
+        uint32_t par = 0;
+        if (v < n && !((vis >> lane) & 1ull)) {
+            const VInfo vi = acc.info((uint32_t)v);
+            uint64_t pos = vi.start;
+            const uint32_t st = Acc::step(vi.w), mk = Acc::mask(vi.w);
+            for (uint32_t i = 0; i < vi.deg; ++i, pos += st) {
+                const uint32_t u = acc.get(pos, mk);
+                if ((curr[u >> 6] >> (u & 63)) & 1ull) { found = true; par = u; break; }
+            }
+        }
+        const uint64_t fm = __ballot(found);
+        if (found) {
+            depth[v] = next_depth;
+            if (kParent) parent[v] = par;
+        }
+        if (lane == 0) {
+            next[q] = fm;
+            if (fm) {
+                visited[q] = vis | fm;
+                atomicAdd(awake, (unsigned long long)__popcll(fm));
+            }
+        }
+    }
+}
+
+// frontier bitmap -> queue
+__global__ void bitmap_to_queue_kernel(uint64_t words, const uint64_t *__restrict__ bits,
+                                       uint32_t *__restrict__ queue, unsigned long long *__restrict__ tail) {
+    const uint32_t lane = lane_id();
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t base = (uint64_t)blockIdx.x * blockDim.x; base < words; base += stride) {
+        const uint64_t q = base + threadIdx.x;
+        uint64_t b = q < words ? bits[q] : 0ull;
+        const uint32_t c = (uint32_t)__popcll(b);
+        const uint32_t incl = wave_incl_scan(c);
+        const uint32_t total = __shfl(incl, kWave - 1, kWave);
+        unsigned long long off = 0;
+        if (lane == 0 && total) off = atomicAdd(tail, (unsigned long long)total);
+        off = __shfl(off, 0, kWave) + (incl - c);
+        while (b) {
+            const uint32_t bit = (uint32_t)__ffsll((long long)b) - 1;
+            queue[off++] = (uint32_t)(q * 64 + bit);
+            b &= b - 1;
+        }
+    }
+}
+
+// results in original IDs: depth_out[o] = depth[inv[o]], parent through perm
+__global__ void bfs_unpermute_kernel(uint32_t n, const uint32_t *__restrict__ inv, const uint32_t *__restrict__ perm,
+                                     const int32_t *__restrict__ depth_i, const uint32_t *__restrict__ parent_i,
+                                     int32_t *__restrict__ depth, int32_t *__restrict__ parent) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t o = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; o < n; o += stride) {
+        const uint32_t x = inv[o];
+        depth[o] = depth_i[x];
+        if (parent) {
+            const uint32_t p = parent_i[x];
+            parent[o] = p == 0xFFFFFFFFu ? -1 : (int32_t)perm[p];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// host driver
+// ---------------------------------------------------------------------------
+
+struct BfsParams {
+    double alpha = 15.0;  // top-down -> bottom-up when frontier edges > unexplored / alpha
+    double beta = 18.0;   // bottom-up -> top-down when the frontier shrinks below n / beta
+};
+
+template <class Acc>
+static lg_status bfs_one(lg_graph *g, Acc acc, uint32_t root_label, int32_t *depth, uint32_t *parent,
+                         int32_t max_depth, uint32_t flags, hipStream_t s) {
+    BfsWork &w = *g->bfs;
+    const uint32_t n = g->n;
+    const uint64_t words = ((uint64_t)n + 63) / 64;
+    const BfsParams prm;
+    uint32_t *qin = w.qa.as<uint32_t>(), *qout = w.qb.as<uint32_t>();
+    uint64_t *visited = w.visited.as<uint64_t>(), *curr = w.curr.as<uint64_t>(), *next = w.next.as<uint64_t>();
+    unsigned long long *ctr = w.counters.as<unsigned long long>();
+    const uint32_t gsz = grid_for(n, 256, 1u << 16);
+
+    LG_LAUNCH(bfs_init_kernel, gsz, 256, 0, s, n, depth, parent, visited, root_label, qin, (uint64_t *)ctr);
+    LG_CHECK_LAUNCH();
+
+    uint64_t qsize = 1;
+    uint64_t edges_to_check = g->m;
+    uint64_t awake = 0;
+    int32_t level = 0;
+    bool topdown = true;
+    for (;;) {
+        if (max_depth >= 0 && level >= max_depth) break;
+        if (topdown) {
+            if (qsize == 0) break;
+            LG_LAUNCH(td_prepare_kernel<Acc>, grid_for(qsize, 256, 1u << 16), 256, 0, s, acc, qin, (uint32_t)qsize,
+                      w.fstart.as<uint64_t>(), w.fdeg.as<uint32_t>(), w.fw.as<uint32_t>());
+            LG_CHECK_LAUNCH();
+            LG_TRY(exclusive_scan_u32(w.fdeg.as<uint32_t>(), w.fscan.as<uint64_t>(), qsize, w.scan_tmp, s));
+            LG_CHECK_HIP(hipMemcpyAsync(w.host, w.fscan.as<uint64_t>() + qsize, 8, hipMemcpyDeviceToHost, s));
+            LG_CHECK_HIP(hipStreamSynchronize(s));
+            const uint64_t fedges = w.host[0];
+            const bool go_bu = (flags == LG_BFS_BOTTOM_UP && level >= 1) ||
+                               (flags == LG_BFS_DIRECTION_OPT && (double)fedges > (double)edges_to_check / prm.alpha);
+            if (go_bu) {
+                LG_TRY(fill_u64(curr, 0, words, s));
+                LG_TRY(fill_u64((uint64_t *)ctr, qsize, 1, s));
+                LG_LAUNCH(mark_queue_kernel, grid_for(qsize, 256, 1u << 16), 256, 0, s, qin, ctr,
+                          (unsigned long long *)curr);
+                LG_CHECK_LAUNCH();
+                awake = qsize;
+                topdown = false;
+                continue;
+            }
+            edges_to_check = edges_to_check > fedges ? edges_to_check - fedges : 0;
+            LG_TRY(fill_u64((uint64_t *)ctr, 0, 1, s));
+            if (fedges) {
+                const uint32_t tiles = grid_for(fedges, kTdTile, 1u << 20);
+                if (parent)
+                    LG_LAUNCH((td_expand_kernel<Acc, true>), tiles, kTdThreads, 0, s, acc, qin, (uint32_t)qsize,
+                              w.fstart.as<uint64_t>(), w.fw.as<uint32_t>(), w.fscan.as<uint64_t>(), fedges, visited,
+                              depth, parent, level + 1, qout, ctr);
+                else
+                    LG_LAUNCH((td_expand_kernel<Acc, false>), tiles, kTdThreads, 0, s, acc, qin, (uint32_t)qsize,
+                              w.fstart.as<uint64_t>(), w.fw.as<uint32_t>(), w.fscan.as<uint64_t>(), fedges, visited,
+                              depth, parent, level + 1, qout, ctr);
+                LG_CHECK_LAUNCH();
+            }
+            LG_CHECK_HIP(hipMemcpyAsync(w.host, ctr, 8, hipMemcpyDeviceToHost, s));
+            LG_CHECK_HIP(hipStreamSynchronize(s));
+            qsize = w.host[0];
+            if (qsize) {
+                LG_LAUNCH(mark_queue_kernel, grid_for(qsize, 256, 1u << 16), 256, 0, s, qout, ctr,
+                          (unsigned long long *)visited);
+                LG_CHECK_LAUNCH();
+            }
+            std::swap(qin, qout);
+            ++level;
+        } else {
+            LG_TRY(fill_u64((uint64_t *)ctr + 1, 0, 1, s));
+            const uint32_t grid = grid_for(words * kWave, 256, 1u << 16);
+            if (parent)
+                LG_LAUNCH((bu_step_kernel<Acc, true>), grid, 256, 0, s, acc, n, curr, visited, next, depth, parent,
+                          level + 1, ctr + 1);
+            else
+                LG_LAUNCH((bu_step_kernel<Acc, false>), grid, 256, 0, s, acc, n, curr, visited, next, depth, parent,
+                          level + 1, ctr + 1);
+            LG_CHECK_LAUNCH();
+            LG_CHECK_HIP(hipMemcpyAsync(w.host, ctr + 1, 8, hipMemcpyDeviceToHost, s));
+            LG_CHECK_HIP(hipStreamSynchronize(s));
+            const uint64_t now = w.host[0];
+            std::swap(curr, next);
+            ++level;
+            if (now == 0) break;
+            const bool back = flags == LG_BFS_DIRECTION_OPT && now < awake && (double)now <= (double)n / prm.beta;
+            awake = now;
+            if (back) {
+                LG_TRY(fill_u64((uint64_t *)ctr, 0, 1, s));
+                LG_LAUNCH(bitmap_to_queue_kernel, grid_for(words, 256, 1u << 16), 256, 0, s, words, curr, qin, ctr);
+                LG_CHECK_LAUNCH();
+                qsize = now;
+                topdown = true;
+            }
+        }
+    }
+    return LG_OK;
+}
+
+}  // namespace lg
+
+extern "C" lg_status lg_bfs(const lg_graph *gc, const uint32_t *roots, uint32_t r, int32_t *depth, int32_t *parent,
+                            int32_t max_depth, uint32_t flags, hipStream_t stream) {
+    using namespace lg;
+    lg_graph *g = const_cast<lg_graph *>(gc);
+    if (!g || (r && (!roots || !depth))) { set_error("lg_bfs: NULL argument"); return LG_ERR_INVALID; }
+    if (flags > LG_BFS_BOTTOM_UP) { set_error("lg_bfs: unknown flags"); return LG_ERR_INVALID; }
+    for (uint32_t i = 0; i < r; ++i)
+        if (roots[i] >= g->n) { set_error("lg_bfs: root %u out of range", roots[i]); return LG_ERR_INVALID; }
+    if (r == 0) return LG_OK;
+    LG_TRY(bfs_workspace(g, parent != nullptr));
+    const bool rel = g->relabel == LG_RELABEL_DEGREE;
+    uint32_t *inv_host = nullptr;
+    (void)inv_host;
+    return dispatch_acc(g, [&](auto acc) -> lg_status {
+        for (uint32_t i = 0; i < r; ++i) {
+            int32_t *d_out = depth + (uint64_t)i * g->n;
+            int32_t *p_out = parent ? parent + (uint64_t)i * g->n : nullptr;
+            uint32_t root_label = roots[i];
+            if (rel) {
+                LG_CHECK_HIP(hipMemcpyAsync(g->bfs->host + 2, g->inv.as<uint32_t>() + roots[i], 4,
+                                            hipMemcpyDeviceToHost, stream));
+                LG_CHECK_HIP(hipStreamSynchronize(stream));
+                root_label = *reinterpret_cast<uint32_t *>(g->bfs->host + 2);
+                LG_TRY(bfs_one(g, acc, root_label, g->bfs->depth_i.as<int32_t>(),
+                               p_out ? g->bfs->parent_i.as<uint32_t>() : nullptr, max_depth, flags, stream));
+                LG_LAUNCH(bfs_unpermute_kernel, grid_for(g->n, 256, 1u << 16), 256, 0, stream, g->n,
+                          g->inv.as<uint32_t>(), g->perm.as<uint32_t>(), g->bfs->depth_i.as<int32_t>(),
+                          p_out ? g->bfs->parent_i.as<uint32_t>() : nullptr, d_out, p_out);
+                LG_CHECK_LAUNCH();
+            } else {
+                LG_TRY(bfs_one(g, acc, root_label, d_out, reinterpret_cast<uint32_t *>(p_out), max_depth, flags,
+                               stream));
+            }
+        }
+        return LG_OK;
+    });
+}

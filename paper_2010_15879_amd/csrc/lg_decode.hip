@@ -1,0 +1,124 @@
+// lg_decode_neighbors: N_v for a batch of vertices (getNeighbors of the
+// library listing in section "High-Performance Library"): the offset lookup,
+// d_v = O[v+1] - O[v] (subsection "Accessing a Degree") and the element
+// extraction of subsection "Accessing An Edge", one wave per requested
+// vertex so that consecutive lanes decode consecutive elements.
+#include "lg_device.hpp"
+
+namespace lg {
+
+__global__ void dec_map_kernel(uint32_t n, const uint32_t *__restrict__ vin, uint32_t k,
+                               const uint32_t *__restrict__ inv, uint32_t *__restrict__ labels,
+                               uint32_t *__restrict__ bad) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < k; i += stride) {
+        const uint32_t v = vin[i];
+        if (v >= n) { atomicOr(bad, 1u); labels[i] = 0; continue; }
+        labels[i] = inv ? inv[v] : v;
+    }
+}
+
+template <class Acc>
+__global__ void dec_degree_kernel(Acc acc, const uint32_t *__restrict__ labels, uint32_t k,
+                                  uint32_t *__restrict__ deg) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < k; i += stride)
+        deg[i] = acc.info(labels[i]).deg;
+}
+
+// kSorted: emit ((i << 32) | original ID) keys for the segmented sort
+template <class Acc, bool kSorted>
+__global__ void dec_lists_kernel(Acc acc, const uint32_t *__restrict__ labels, uint32_t k,
+                                 const uint64_t *__restrict__ out_off, const uint32_t *__restrict__ perm,
+                                 uint32_t *__restrict__ out_ids, uint64_t *__restrict__ keys) {
+    const uint32_t lane = lane_id();
+    const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) / kWave;
+    for (uint64_t i = wave; i < k; i += nwaves) {
+        const VInfo vi = acc.info(labels[i]);
+        const uint64_t o = out_off[i];
+        const uint32_t st = Acc::step(vi.w), mk = Acc::mask(vi.w);
+        for (uint64_t j = lane; j < vi.deg; j += kWave) {
+            uint32_t u = acc.get(vi.start + j * st, mk);
+            if (perm) u = perm[u];
+            if (kSorted) keys[o + j] = (i << 32) | u;
+            else out_ids[o + j] = u;
+        }
+    }
+}
+
+__global__ void dec_unkey_kernel(uint64_t total, const uint64_t *__restrict__ keys, uint32_t *__restrict__ out) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; j < total; j += stride)
+        out[j] = (uint32_t)keys[j];
+}
+
+}  // namespace lg
+
+extern "C" lg_status lg_decode_neighbors(const lg_graph *gc, const uint32_t *vertices, uint32_t k,
+                                         uint64_t *out_off, uint32_t *out_ids, uint64_t cap, uint32_t flags,
+                                         hipStream_t stream) {
+    using namespace lg;
+    lg_graph *g = const_cast<lg_graph *>(gc);
+    if (!g || !out_off || (k && !vertices)) { set_error("lg_decode_neighbors: NULL argument"); return LG_ERR_INVALID; }
+    if (flags > LG_DECODE_RAW) { set_error("lg_decode_neighbors: unknown flags"); return LG_ERR_INVALID; }
+    if (k == 0) return fill_u64(out_off, 0, 1, stream);
+    const bool rel = g->relabel == LG_RELABEL_DEGREE;
+    const uint32_t *inv = (rel && flags != LG_DECODE_RAW) ? g->inv.as<uint32_t>() : nullptr;
+    const uint32_t *perm = (rel && flags != LG_DECODE_RAW) ? g->perm.as<uint32_t>() : nullptr;
+    const bool sorted = rel && flags == LG_DECODE_SORTED;
+
+    // scratch: labels (k) | degrees (k) | flag | scan tmp (separate buffer)
+    DevBuf scan_tmp;
+    const uint64_t head = ((uint64_t)k * 8 + 8 + 7) & ~7ull;
+    LG_TRY(g->dec_tmp.ensure(head));
+    uint32_t *labels = g->dec_tmp.as<uint32_t>();
+    uint32_t *deg = labels + k;
+    uint32_t *bad = deg + k;
+    LG_TRY(fill_u32(bad, 0, 1, stream));
+    LG_LAUNCH(dec_map_kernel, grid_for(k, 256, 1u << 16), 256, 0, stream, g->n, vertices, k, inv, labels, bad);
+    LG_CHECK_LAUNCH();
+    uint32_t host_bad = 0;
+    LG_CHECK_HIP(hipMemcpyAsync(&host_bad, bad, 4, hipMemcpyDeviceToHost, stream));
+    LG_CHECK_HIP(hipStreamSynchronize(stream));
+    if (host_bad) { set_error("lg_decode_neighbors: vertex id >= n"); return LG_ERR_INVALID; }
+
+    return dispatch_acc(g, [&](auto acc) -> lg_status {
+        using Acc = decltype(acc);
+        LG_LAUNCH(dec_degree_kernel<Acc>, grid_for(k, 256, 1u << 16), 256, 0, stream, acc, labels, k, deg);
+        LG_CHECK_LAUNCH();
+        LG_TRY(exclusive_scan_u32(deg, out_off, k, scan_tmp, stream));
+        uint64_t total = 0;
+        LG_CHECK_HIP(hipMemcpyAsync(&total, out_off + k, 8, hipMemcpyDeviceToHost, stream));
+        LG_CHECK_HIP(hipStreamSynchronize(stream));
+        if (!out_ids || total > cap) {
+            set_error("lg_decode_neighbors: %llu ids do not fit in capacity %llu", (unsigned long long)total,
+                      (unsigned long long)cap);
+            return LG_ERR_CAPACITY;
+        }
+        if (total == 0) return LG_OK;
+        const uint32_t grid = grid_for((uint64_t)k * kWave, 256, 1u << 16);
+        if (!sorted) {
+            LG_LAUNCH((dec_lists_kernel<Acc, false>), grid, 256, 0, stream, acc, labels, k, (const uint64_t *)out_off,
+                      perm, out_ids, (uint64_t *)nullptr);
+            LG_CHECK_LAUNCH();
+            LG_CHECK_HIP(hipStreamSynchronize(stream));
+            return LG_OK;
+        }
+        DevBuf keys, keys2, vals, vals2, sort_tmp;
+        LG_TRY(keys.alloc(total * 8));
+        LG_TRY(keys2.alloc(total * 8));
+        LG_TRY(vals.alloc(total * 4));
+        LG_TRY(vals2.alloc(total * 4));
+        LG_LAUNCH((dec_lists_kernel<Acc, true>), grid, 256, 0, stream, acc, labels, k, (const uint64_t *)out_off, perm,
+                  out_ids, keys.as<uint64_t>());
+        LG_CHECK_LAUNCH();
+        const uint32_t bits = 32 + bitlen_u64(k - 1);
+        LG_TRY(radix_sort_pairs64(keys.as<uint64_t>(), vals.as<uint32_t>(), keys2.as<uint64_t>(), vals2.as<uint32_t>(),
+                                  total, bits, sort_tmp, stream));
+        LG_LAUNCH(dec_unkey_kernel, grid_for(total, 256, 1u << 16), 256, 0, stream, total, keys.as<uint64_t>(), out_ids);
+        LG_CHECK_LAUNCH();
+        LG_CHECK_HIP(hipStreamSynchronize(stream));
+        return LG_OK;
+    });
+}

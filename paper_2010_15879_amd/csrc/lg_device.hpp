@@ -1,0 +1,235 @@
+// Device-side building blocks of liblg: bit-field extraction from packed
+// streams, Elias-Fano select, per-vertex accessors for every layout, and
+// wave64 primitives for gfx950.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "lg_internal.hpp"
+
+namespace lg {
+
+constexpr int kWave = 64;
+
+// ---------------------------------------------------------------------------
+// wave64 primitives
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ uint32_t lane_id() {
+    return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+}
+
+// number of set bits of `mask` at lanes below this one
+__device__ __forceinline__ uint32_t popc_below(uint64_t mask) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                     __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+template <class T>
+__device__ __forceinline__ T wave_incl_scan(T x) {
+    const uint32_t lane = lane_id();
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        T y = __shfl_up(x, d, kWave);
+        if (lane >= (uint32_t)d) x += y;
+    }
+    return x;
+}
+
+template <class T>
+__device__ __forceinline__ T wave_sum(T x) {
+#pragma unroll
+    for (int d = kWave / 2; d > 0; d >>= 1) x += __shfl_xor(x, d, kWave);
+    return x;
+}
+
+// ---------------------------------------------------------------------------
+// bit-field extraction
+// ---------------------------------------------------------------------------
+
+// A packed list element of width <= 32: the two 32-bit words holding stream
+// bits [bit, bit + 32) are joined with one funnel shift (v_alignbit_b32) and
+// masked.  The zero pad word at the end of every stream keeps A32[k + 1] in
+// bounds.
+__device__ __forceinline__ uint32_t extract32(const uint32_t *__restrict__ A32, uint64_t bit,
+                                              uint32_t mask) {
+    const uint64_t k = bit >> 5;
+    const uint32_t lo = A32[k];
+    const uint32_t hi = A32[k + 1];
+    return __builtin_amdgcn_alignbit(hi, lo, (uint32_t)bit & 31u) & mask;
+}
+
+__device__ __forceinline__ uint32_t width_mask(uint32_t w) {
+    return w >= 32 ? 0xFFFFFFFFu : ((1u << w) - 1u);
+}
+
+// A fixed-width field of up to 64 bits from a stream of 64-bit words.
+__device__ __forceinline__ uint64_t extract64(const uint64_t *__restrict__ S, uint64_t bit, uint32_t w) {
+    if (w == 0) return 0;
+    const uint64_t k = bit >> 6;
+    const uint32_t sh = (uint32_t)bit & 63u;
+    uint64_t v = S[k] >> sh;
+    if (sh + w > 64) v |= S[k + 1] << (64 - sh);
+    return w >= 64 ? v : (v & ((1ull << w) - 1ull));
+}
+
+// ---------------------------------------------------------------------------
+// Elias-Fano select over the upper bit vector H
+// ---------------------------------------------------------------------------
+
+// Position of the r-th set bit (0-based) of x; x must hold more than r ones.
+__device__ __forceinline__ uint32_t select_in_word(uint64_t x, uint32_t r) {
+    uint32_t pos = 0;
+    uint32_t w = (uint32_t)x;
+    uint32_t c = __popc(w);
+    if (r >= c) { r -= c; pos = 32; w = (uint32_t)(x >> 32); }
+    c = __popc(w & 0xFFFFu);
+    if (r >= c) { r -= c; pos += 16; w >>= 16; }
+    c = __popc(w & 0xFFu);
+    if (r >= c) { r -= c; pos += 8; w >>= 8; }
+    c = __popc(w & 0xFu);
+    if (r >= c) { r -= c; pos += 4; w >>= 4; }
+    c = __popc(w & 0x3u);
+    if (r >= c) { r -= c; pos += 2; w >>= 2; }
+    c = w & 1u;
+    if (r >= c) pos += 1;
+    return pos;
+}
+
+// select1(k): the sample table gives the position of one number 64*floor(k/64);
+// the rank directory is searched between that superblock and the next
+// sample's, then at most eight words are scanned with popcount.
+__device__ __forceinline__ uint64_t ef_select1(const EFView &e, uint32_t k) {
+    const uint32_t j = k >> 6;
+    const uint32_t p = e.sel[j];
+    if ((k & 63u) == 0) return p;
+    uint32_t lo = p >> 9;
+    uint32_t hi = (j + 1 < e.n_sel) ? (e.sel[j + 1] >> 9) : (e.n_sb - 1);
+    while (lo < hi) {  // largest superblock b with rank_sb[b] <= k
+        const uint32_t mid = (lo + hi + 1) >> 1;
+        if (e.rank_sb[mid] <= k) lo = mid; else hi = mid - 1;
+    }
+    uint32_t r = e.rank_sb[lo];
+    uint64_t wi = (uint64_t)lo * 8;
+    for (;;) {
+        const uint64_t x = e.H[wi];
+        const uint32_t c = (uint32_t)__popcll(x);
+        if (r + c > k) return wi * 64 + select_in_word(x, k - r);
+        r += c;
+        ++wi;
+    }
+}
+
+__device__ __forceinline__ uint64_t ef_get(const EFView &e, uint32_t v) {
+    const uint64_t pos = ef_select1(e, v);
+    const uint64_t low = e.l ? extract64(e.L, (uint64_t)v * e.l, e.l) : 0ull;
+    return ((pos - v) << e.l) | low;
+}
+
+// exact quotient of a multiple of w (1 <= w <= 32) by w, below 2^51
+static __device__ __constant__ double c_inv_width[33] = {
+    0.0, 1.0, 1.0 / 2, 1.0 / 3, 1.0 / 4, 1.0 / 5, 1.0 / 6, 1.0 / 7, 1.0 / 8, 1.0 / 9, 1.0 / 10,
+    1.0 / 11, 1.0 / 12, 1.0 / 13, 1.0 / 14, 1.0 / 15, 1.0 / 16, 1.0 / 17, 1.0 / 18, 1.0 / 19,
+    1.0 / 20, 1.0 / 21, 1.0 / 22, 1.0 / 23, 1.0 / 24, 1.0 / 25, 1.0 / 26, 1.0 / 27, 1.0 / 28,
+    1.0 / 29, 1.0 / 30, 1.0 / 31, 1.0 / 32};
+
+__device__ __forceinline__ uint32_t exact_div_width(uint64_t x, uint32_t w) {
+    return (uint32_t)((double)x * c_inv_width[w] + 0.5);
+}
+
+// ---------------------------------------------------------------------------
+// per-vertex accessors
+// ---------------------------------------------------------------------------
+
+// start: first bit of the list (packed) or first element index (plain);
+// deg: list length; w: element width (packed) or 32 (plain).
+struct VInfo {
+    uint64_t start;
+    uint32_t deg;
+    uint32_t w;
+};
+
+enum : int { kIdsGlobal = 0, kIdsLocal = 1 };
+enum : int { kOffsPacked = 0, kOffsEF = 1 };
+
+template <int IDM, int OFM>
+struct PackedAcc {
+    PackedView pv;
+    static constexpr bool kPacked = true;
+
+    __device__ __forceinline__ uint64_t offset_value(uint32_t v) const {
+        if constexpr (OFM == kOffsPacked) return extract64(pv.po.O, (uint64_t)v * pv.po.w, pv.po.w);
+        else return ef_get(pv.ef, v);
+    }
+    __device__ __forceinline__ uint32_t width(uint32_t v) const {
+        if constexpr (IDM == kIdsGlobal) return pv.s;
+        else return (uint32_t)extract64(pv.W, (uint64_t)v * pv.F, pv.F);
+    }
+    // info from the two offset values bracketing the list of v
+    __device__ __forceinline__ VInfo make(uint32_t v, uint64_t o0, uint64_t o1) const {
+        VInfo r;
+        if constexpr (IDM == kIdsGlobal) {
+            r.start = o0 * pv.s;
+            r.deg = (uint32_t)(o1 - o0);
+            r.w = pv.s;
+        } else {
+            r.w = width(v);
+            r.start = o0;
+            r.deg = r.w ? exact_div_width(o1 - o0, r.w) : 0u;
+        }
+        return r;
+    }
+    __device__ __forceinline__ VInfo info(uint32_t v) const {
+        return make(v, offset_value(v), offset_value(v + 1));
+    }
+    // element at position `pos` (a bit position)
+    __device__ __forceinline__ uint32_t get(uint64_t pos, uint32_t mask) const {
+        return extract32(pv.A32, pos, mask);
+    }
+    __device__ __forceinline__ static uint32_t step(uint32_t w) { return w; }
+    __device__ __forceinline__ static uint32_t mask(uint32_t w) { return width_mask(w); }
+};
+
+template <bool OFF64>
+struct PlainAcc {
+    PlainView pv;
+    static constexpr bool kPacked = false;
+
+    __device__ __forceinline__ uint64_t offset_value(uint32_t v) const {
+        if constexpr (OFF64) return static_cast<const uint64_t *>(pv.off)[v];
+        else return static_cast<const uint32_t *>(pv.off)[v];
+    }
+    __device__ __forceinline__ VInfo make(uint32_t, uint64_t o0, uint64_t o1) const {
+        VInfo r;
+        r.start = o0;
+        r.deg = (uint32_t)(o1 - o0);
+        r.w = 32;
+        return r;
+    }
+    __device__ __forceinline__ VInfo info(uint32_t v) const {
+        return make(v, offset_value(v), offset_value(v + 1));
+    }
+    __device__ __forceinline__ uint32_t get(uint64_t pos, uint32_t) const { return pv.col[pos]; }
+    __device__ __forceinline__ static uint32_t step(uint32_t) { return 1; }
+    __device__ __forceinline__ static uint32_t mask(uint32_t) { return 0xFFFFFFFFu; }
+};
+
+// Call `fn(acc)` with the accessor matching the graph's layout.
+template <class Fn>
+lg_status dispatch_acc(const lg_graph *g, Fn &&fn) {
+    if (g->layout == LG_LAYOUT_PLAIN) {
+        if (g->poff64) return fn(PlainAcc<true>{g->plain_view()});
+        return fn(PlainAcc<false>{g->plain_view()});
+    }
+    const PackedView pv = g->packed_view();
+    if (g->id_mode == LG_IDS_GLOBAL) {
+        if (g->offset_mode == LG_OFFS_PACKED) return fn(PackedAcc<kIdsGlobal, kOffsPacked>{pv});
+        return fn(PackedAcc<kIdsGlobal, kOffsEF>{pv});
+    }
+    if (g->offset_mode == LG_OFFS_PACKED) return fn(PackedAcc<kIdsLocal, kOffsPacked>{pv});
+    return fn(PackedAcc<kIdsLocal, kOffsEF>{pv});
+}
+
+}  // namespace lg

@@ -1,0 +1,525 @@
+// lg_encode: build the logarithmized representation on the GPU.
+//
+// Steps (each a kernel or a short sequence of kernels on the caller's
+// stream):
+//   validate      canonical undirected adjacency array (sorted lists, IDs < n,
+//                 no self-loops, symmetric)
+//   relabel       degree-minimizing permutation (section "Incorporating
+//                 Degree-Minimizing (DM)"): stable radix sort of vertices by
+//                 degree, then the relabeled lists via one stable radix sort of
+//                 (new target, new source) pairs by target
+//   widths        global s or local w_v ("Logarithmization of Vertex IDs")
+//   scan          bit starts P_v = exclusive prefix of d_v * w_v
+//   pack          each thread assembles one 64-bit output word from the
+//                 elements overlapping it (no atomics, deterministic)
+//   offsets       packed offsets ("Logarithmization of Single Offsets") or an
+//                 Elias-Fano sequence with a rank/select directory ("Succinct
+//                 Bit Vectors in Log(Graph)")
+#include <cstring>
+
+#include "lg_device.hpp"
+
+namespace lg {
+
+enum : uint32_t {
+    kBadOffsets = 1u,
+    kBadId = 2u,
+    kSelfLoop = 4u,
+    kUnsorted = 8u,
+    kAsymmetric = 16u,
+};
+
+// ---------------------------------------------------------------------------
+// validation and degree statistics
+// ---------------------------------------------------------------------------
+
+// One wave per vertex; lanes walk the list.  The symmetric check looks every
+// entry (v, u) up in N_u by binary search.
+__global__ void validate_kernel(uint32_t n, uint64_t m, const uint64_t *__restrict__ off,
+                                const uint32_t *__restrict__ col, uint32_t *__restrict__ status) {
+    const uint32_t lane = lane_id();
+    const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) / kWave;
+    uint32_t flags = 0;
+    for (uint64_t v = wave; v < n; v += nwaves) {
+        const uint64_t o0 = off[v], o1 = off[v + 1];
+        if (o1 < o0 || o1 > m || (v == 0 && o0 != 0) || (v + 1 == n && o1 != m)) {
+            flags |= kBadOffsets;
+            continue;
+        }
+        for (uint64_t i = o0 + lane; i < o1; i += kWave) {
+            const uint32_t u = col[i];
+            if (u >= n) { flags |= kBadId; continue; }
+            if (u == v) flags |= kSelfLoop;
+            if (i > o0 && col[i - 1] >= u) flags |= kUnsorted;
+            uint64_t lo = off[u], hi = off[u + 1];
+            if (hi > m) hi = m;
+            bool found = false;
+            while (lo < hi) {
+                const uint64_t mid = (lo + hi) >> 1;
+                const uint32_t x = col[mid];
+                if (x == (uint32_t)v) { found = true; break; }
+                if (x < (uint32_t)v) lo = mid + 1; else hi = mid;
+            }
+            if (!found) flags |= kAsymmetric;
+        }
+    }
+    if (flags) atomicOr(status, flags);
+}
+
+// deg[v] (uint32), plus the maximum degree and the number of isolated vertices
+__global__ void degree_kernel(uint32_t n, const uint64_t *__restrict__ off, uint32_t *__restrict__ deg,
+                              uint32_t *__restrict__ stats) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    uint32_t mx = 0, iso = 0;
+    for (uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) {
+        const uint32_t d = (uint32_t)(off[v + 1] - off[v]);
+        deg[v] = d;
+        mx = d > mx ? d : mx;
+        iso += d == 0;
+    }
+#pragma unroll
+    for (int k = kWave / 2; k > 0; k >>= 1) {
+        const uint32_t o = __shfl_xor(mx, k, kWave);
+        mx = o > mx ? o : mx;
+    }
+    iso = wave_sum(iso);
+    if (lane_id() == 0) {
+        atomicMax(&stats[0], mx);
+        if (iso) atomicAdd(&stats[1], iso);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// degree-minimizing relabeling
+// ---------------------------------------------------------------------------
+
+// sort key: (n - 1) - d_v, so an ascending stable sort orders by degree
+// descending and keeps equal degrees in ID order
+__global__ void dm_keys_kernel(uint32_t n, const uint32_t *__restrict__ deg, uint32_t *__restrict__ keys,
+                               uint32_t *__restrict__ vals) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) {
+        keys[v] = (n - 1) - deg[v];
+        vals[v] = (uint32_t)v;
+    }
+}
+
+__global__ void dm_inverse_kernel(uint32_t n, const uint32_t *__restrict__ perm, const uint32_t *__restrict__ deg,
+                                  uint32_t *__restrict__ inv, uint32_t *__restrict__ deg_new) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t x = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n; x += stride) {
+        const uint32_t v = perm[x];
+        inv[v] = (uint32_t)x;
+        deg_new[x] = deg[v];
+    }
+}
+
+// Row x of the relabeled array receives the list of perm[x], renamed; it is
+// emitted as (target, source) pairs.  Sorting the pairs stably by target
+// lists, for every target y in increasing order, the sources x adjacent to
+// y in increasing order; by symmetry that sequence is the sorted relabeled
+// adjacency array itself, so the sorted sources are the new lists.
+__global__ void dm_gather_kernel(uint32_t n, const uint32_t *__restrict__ perm, const uint32_t *__restrict__ inv,
+                                 const uint64_t *__restrict__ off, const uint32_t *__restrict__ col,
+                                 const uint64_t *__restrict__ off_new, uint32_t *__restrict__ key,
+                                 uint32_t *__restrict__ val) {
+    const uint32_t lane = lane_id();
+    const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) / kWave;
+    for (uint64_t x = wave; x < n; x += nwaves) {
+        const uint32_t v = perm[x];
+        const uint64_t o0 = off[v], d = off[v + 1] - o0, dst = off_new[x];
+        for (uint64_t i = lane; i < d; i += kWave) {
+            key[dst + i] = inv[col[o0 + i]];
+            val[dst + i] = (uint32_t)x;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// widths and bit lengths
+// ---------------------------------------------------------------------------
+
+// w_v = max(1, bl(max N_v)) for a non-empty list (its last element, lists
+// being sorted), 0 otherwise; len[v] = d_v * w_v.
+__global__ void local_width_kernel(uint32_t n, const uint64_t *__restrict__ off, const uint32_t *__restrict__ col,
+                                   uint8_t *__restrict__ w, uint64_t *__restrict__ len) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) {
+        const uint64_t o0 = off[v], o1 = off[v + 1];
+        uint32_t wv = 0;
+        if (o1 > o0) {
+            const uint32_t mx = col[o1 - 1];
+            wv = mx ? 32u - (uint32_t)__clz(mx) : 1u;
+        }
+        w[v] = (uint8_t)wv;
+        len[v] = (o1 - o0) * wv;
+    }
+}
+
+// floor(x / d) for x < 2^53 and a small d, via a double reciprocal and an
+// exact correction
+__device__ __forceinline__ uint64_t div_small(uint64_t x, uint64_t d, double inv_d) {
+    uint64_t q = (uint64_t)((double)x * inv_d);
+    while (q * d > x) --q;
+    while ((q + 1) * d <= x) ++q;
+    return q;
+}
+
+// ---------------------------------------------------------------------------
+// packing: one thread per output word
+// ---------------------------------------------------------------------------
+
+struct SrcU32 {
+    const uint32_t *p;
+    __device__ __forceinline__ uint64_t operator()(uint64_t j) const { return p[j]; }
+};
+struct SrcU8 {
+    const uint8_t *p;
+    __device__ __forceinline__ uint64_t operator()(uint64_t j) const { return p[j]; }
+};
+struct SrcU64Mask {
+    const uint64_t *p;
+    uint64_t mask;
+    __device__ __forceinline__ uint64_t operator()(uint64_t j) const { return p[j] & mask; }
+};
+
+// Value j of a sequence of `count` values occupies bits [j*w, j*w + w).
+// Word k gathers the values overlapping bits [64k, 64k + 64).
+template <class Src>
+__global__ void pack_fixed_kernel(Src src, uint64_t count, uint32_t w, double inv_w, uint64_t words,
+                                  uint64_t *__restrict__ out) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    const uint64_t total_bits = count * w;
+    for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < words; k += stride) {
+        const uint64_t b0 = k * 64;
+        uint64_t word = 0;
+        if (w && b0 < total_bits) {
+            for (uint64_t j = div_small(b0, w, inv_w); j < count; ++j) {
+                const uint64_t b = j * w;
+                if (b >= b0 + 64) break;
+                const uint64_t x = src(j);
+                word |= (b >= b0) ? (x << (b - b0)) : (x >> (b0 - b));
+            }
+        }
+        out[k] = word;
+    }
+}
+
+// Local widths: the list of v starts at bit P_v.  A block of 256 threads
+// packs 256 consecutive words; the vertex owning each word's first bit is
+// found by a binary search of P bounded by the block's own vertex range.
+__device__ __forceinline__ uint32_t vertex_of_bit(const uint64_t *__restrict__ P, uint32_t lo, uint32_t hi,
+                                                  uint64_t b) {
+    // largest v in [lo, hi] with P[v] <= b
+    while (lo < hi) {
+        const uint32_t mid = lo + ((hi - lo + 1) >> 1);
+        if (P[mid] <= b) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+__global__ void pack_local_kernel(uint32_t n, const uint64_t *__restrict__ off, const uint32_t *__restrict__ col,
+                                  const uint8_t *__restrict__ w, const uint64_t *__restrict__ P, uint64_t U,
+                                  uint64_t words, uint64_t *__restrict__ out) {
+    __shared__ uint32_t s_range[2];
+    const uint64_t k0 = (uint64_t)blockIdx.x * blockDim.x;
+    if (threadIdx.x < 2) {
+        const uint64_t b = threadIdx.x == 0 ? k0 * 64 : (k0 + blockDim.x) * 64 - 1;
+        s_range[threadIdx.x] = b < U ? vertex_of_bit(P, 0, n - 1, b) : n - 1;
+    }
+    __syncthreads();
+    const uint64_t k = k0 + threadIdx.x;
+    if (k >= words) return;
+    const uint64_t b0 = k * 64;
+    uint64_t word = 0;
+    if (b0 < U) {
+        uint32_t v = vertex_of_bit(P, s_range[0], s_range[1], b0);
+        uint32_t wv = w[v];
+        uint64_t pv = P[v];
+        uint64_t i = div_small(b0 - pv, wv, 1.0 / (double)wv);
+        uint64_t pos = pv + i * wv;
+        uint64_t d = off[v + 1] - off[v];
+        const uint64_t end = b0 + 64 < U ? b0 + 64 : U;
+        while (pos < end) {
+            while (i >= d) {  // next vertex with a non-empty list
+                ++v;
+                wv = w[v];
+                d = off[v + 1] - off[v];
+                i = 0;
+            }
+            const uint64_t x = col[off[v] + i];
+            word |= (pos >= b0) ? (x << (pos - b0)) : (x >> (b0 - pos));
+            pos += wv;
+            ++i;
+        }
+    }
+    out[k] = word;
+}
+
+// ---------------------------------------------------------------------------
+// Elias-Fano upper bits and directory
+// ---------------------------------------------------------------------------
+
+__global__ void ef_high_kernel(uint64_t count, const uint64_t *__restrict__ x, uint32_t l,
+                               unsigned long long *__restrict__ H) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; v < count; v += stride) {
+        const uint64_t y = (x[v] >> l) + v;
+        atomicOr(&H[y >> 6], 1ull << (y & 63));
+    }
+}
+
+__global__ void ef_superblock_count_kernel(uint64_t nsb, uint64_t hwords, const uint64_t *__restrict__ H,
+                                           uint32_t *__restrict__ cnt) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; b < nsb; b += stride) {
+        uint32_t c = 0;
+        for (uint64_t k = 8 * b; k < 8 * b + 8 && k < hwords; ++k) c += (uint32_t)__popcll(H[k]);
+        cnt[b] = c;
+    }
+}
+
+__global__ void u64_to_u32_kernel(uint64_t count, const uint64_t *__restrict__ in, uint32_t *__restrict__ out) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride)
+        out[i] = (uint32_t)in[i];
+}
+
+__global__ void ef_select_kernel(uint64_t nsel, const uint64_t *__restrict__ x, uint32_t l,
+                                 uint32_t *__restrict__ sel) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; j < nsel; j += stride)
+        sel[j] = (uint32_t)((x[64 * j] >> l) + 64 * j);
+}
+
+__global__ void offsets_to_u32_kernel(uint64_t count, const uint64_t *__restrict__ in, uint32_t *__restrict__ out) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride)
+        out[i] = (uint32_t)in[i];
+}
+
+// ---------------------------------------------------------------------------
+// host orchestration
+// ---------------------------------------------------------------------------
+
+static inline uint32_t grid1(uint64_t count) { return grid_for(count, 256, 1u << 20); }
+
+template <class Src>
+static lg_status pack_fixed(Src src, uint64_t count, uint32_t w, DevBuf &dst, uint64_t &words, hipStream_t s) {
+    words = (count * w + 63) / 64 + 1;
+    LG_TRY(dst.alloc(words * 8));
+    LG_LAUNCH(pack_fixed_kernel<Src>, grid1(words), 256, 0, s, src, count, w, w ? 1.0 / (double)w : 0.0, words,
+              dst.as<uint64_t>());
+    LG_CHECK_LAUNCH();
+    return LG_OK;
+}
+
+// offsets structure over the values x[0..n] (element offsets or bit starts)
+static lg_status build_offsets(lg_graph *g, const uint64_t *x, uint64_t universe, DevBuf &tmp, hipStream_t s) {
+    const uint64_t count = (uint64_t)g->n + 1;
+    g->universe = universe;
+    if (g->offset_mode == LG_OFFS_PACKED) {
+        g->wO = bitlen_u64(universe);  // 0 when every offset is 0 (no edges)
+        return pack_fixed(SrcU64Mask{x, ~0ull}, count, g->wO, g->O, g->O_words, s);
+    }
+    // Elias-Fano: l = floor(log2(universe / count)) when universe >= count
+    const uint32_t l = universe >= count ? bitlen_u64(universe / count) - 1 : 0;
+    g->ef_l = l;
+    g->hbits = (universe >> l) + count;
+    if (g->hbits >= (1ull << 32)) {
+        set_error("succinct offsets: upper bit vector of %llu bits exceeds 2^32", (unsigned long long)g->hbits);
+        return LG_ERR_UNSUPPORTED;
+    }
+    const uint64_t lowmask = l ? ((1ull << l) - 1) : 0ull;
+    LG_TRY(pack_fixed(SrcU64Mask{x, lowmask}, count, l, g->L, g->L_words, s));
+    g->H_words = (g->hbits + 63) / 64 + 1;
+    LG_TRY(g->H.alloc(g->H_words * 8));
+    LG_TRY(fill_u64(g->H.as<uint64_t>(), 0, g->H_words, s));
+    LG_LAUNCH(ef_high_kernel, grid1(count), 256, 0, s, count, x, l, g->H.as<unsigned long long>());
+    LG_CHECK_LAUNCH();
+    const uint64_t nsb = (g->hbits + 511) / 512;
+    g->n_rank = nsb + 1;
+    DevBuf cnt, scanned;
+    LG_TRY(cnt.alloc(nsb * 4));
+    LG_TRY(scanned.alloc((nsb + 1) * 8));
+    LG_LAUNCH(ef_superblock_count_kernel, grid1(nsb), 256, 0, s, nsb, g->H_words, g->H.as<uint64_t>(),
+              cnt.as<uint32_t>());
+    LG_CHECK_LAUNCH();
+    LG_TRY(exclusive_scan_u32(cnt.as<uint32_t>(), scanned.as<uint64_t>(), nsb, tmp, s));
+    LG_TRY(g->rank_sb.alloc(g->n_rank * 4));
+    LG_LAUNCH(u64_to_u32_kernel, grid1(g->n_rank), 256, 0, s, g->n_rank, scanned.as<uint64_t>(),
+              g->rank_sb.as<uint32_t>());
+    LG_CHECK_LAUNCH();
+    g->n_sel = (count + 63) / 64;
+    LG_TRY(g->sel.alloc(g->n_sel * 4));
+    LG_LAUNCH(ef_select_kernel, grid1(g->n_sel), 256, 0, s, g->n_sel, x, l, g->sel.as<uint32_t>());
+    LG_CHECK_LAUNCH();
+    // the kernels above read cnt/scanned before this function returns and
+    // frees them: wait for the stream
+    LG_CHECK_HIP(hipStreamSynchronize(s));
+    return LG_OK;
+}
+
+static lg_status encode_impl(uint32_t n, uint64_t m, const uint64_t *row_offsets, const uint32_t *col,
+                             const lg_encode_opts &o, hipStream_t s, lg_graph *g) {
+    DevBuf tmp, status, deg, stats;
+    LG_CHECK_HIP(hipGetDevice(&g->device));
+
+    // -- validation ------------------------------------------------------
+    LG_TRY(status.alloc(4));
+    LG_TRY(stats.alloc(8));
+    LG_TRY(fill_u32(status.as<uint32_t>(), 0, 1, s));
+    LG_TRY(fill_u32(stats.as<uint32_t>(), 0, 2, s));
+    LG_LAUNCH(validate_kernel, grid_for((uint64_t)n * kWave, 256, 1u << 16), 256, 0, s, n, m, row_offsets, col,
+              status.as<uint32_t>());
+    LG_CHECK_LAUNCH();
+    uint32_t bad = 0;
+    LG_CHECK_HIP(hipMemcpyAsync(&bad, status.p, 4, hipMemcpyDeviceToHost, s));
+    LG_CHECK_HIP(hipStreamSynchronize(s));
+    if (bad) {
+        set_error("invalid input graph:%s%s%s%s%s", (bad & kBadOffsets) ? " bad-offsets" : "",
+                  (bad & kBadId) ? " id>=n" : "", (bad & kSelfLoop) ? " self-loop" : "",
+                  (bad & kUnsorted) ? " unsorted-or-duplicate" : "", (bad & kAsymmetric) ? " not-symmetric" : "");
+        return LG_ERR_INVALID;
+    }
+    LG_TRY(deg.alloc((uint64_t)n * 4));
+    LG_LAUNCH(degree_kernel, grid1(n), 256, 0, s, n, row_offsets, deg.as<uint32_t>(), stats.as<uint32_t>());
+    LG_CHECK_LAUNCH();
+    uint32_t st[2];
+    LG_CHECK_HIP(hipMemcpyAsync(st, stats.p, 8, hipMemcpyDeviceToHost, s));
+    LG_CHECK_HIP(hipStreamSynchronize(s));
+    g->max_degree = st[0];
+    g->isolated = st[1];
+
+    // -- relabeling --------------------------------------------------------
+    const uint64_t *cur_off = row_offsets;
+    const uint32_t *cur_col = col;
+    DevBuf off_new, col_new;
+    const uint32_t idbits = bitlen_u64(n - 1);
+    if (o.relabel == LG_RELABEL_DEGREE) {
+        DevBuf k1, k2, v2, deg_new;
+        LG_TRY(k1.alloc((uint64_t)n * 4));
+        LG_TRY(k2.alloc((uint64_t)n * 4));
+        LG_TRY(v2.alloc((uint64_t)n * 4));
+        LG_TRY(g->perm.alloc((uint64_t)n * 4));
+        LG_TRY(g->inv.alloc((uint64_t)n * 4));
+        LG_TRY(deg_new.alloc((uint64_t)n * 4));
+        LG_LAUNCH(dm_keys_kernel, grid1(n), 256, 0, s, n, deg.as<uint32_t>(), k1.as<uint32_t>(),
+                  g->perm.as<uint32_t>());
+        LG_CHECK_LAUNCH();
+        LG_TRY(radix_sort_pairs(k1.as<uint32_t>(), g->perm.as<uint32_t>(), k2.as<uint32_t>(), v2.as<uint32_t>(), n,
+                                idbits, tmp, s));
+        LG_LAUNCH(dm_inverse_kernel, grid1(n), 256, 0, s, n, g->perm.as<uint32_t>(), deg.as<uint32_t>(),
+                  g->inv.as<uint32_t>(), deg_new.as<uint32_t>());
+        LG_CHECK_LAUNCH();
+        LG_TRY(off_new.alloc(((uint64_t)n + 1) * 8));
+        LG_TRY(exclusive_scan_u32(deg_new.as<uint32_t>(), off_new.as<uint64_t>(), n, tmp, s));
+        if (m) {
+            DevBuf key, key2, val2;
+            LG_TRY(key.alloc(m * 4));
+            LG_TRY(col_new.alloc(m * 4));
+            LG_TRY(key2.alloc(m * 4));
+            LG_TRY(val2.alloc(m * 4));
+            LG_LAUNCH(dm_gather_kernel, grid_for((uint64_t)n * kWave, 256, 1u << 16), 256, 0, s, n,
+                      g->perm.as<uint32_t>(), g->inv.as<uint32_t>(), row_offsets, col, off_new.as<uint64_t>(),
+                      key.as<uint32_t>(), col_new.as<uint32_t>());
+            LG_CHECK_LAUNCH();
+            LG_TRY(radix_sort_pairs(key.as<uint32_t>(), col_new.as<uint32_t>(), key2.as<uint32_t>(),
+                                    val2.as<uint32_t>(), m, idbits, tmp, s));
+            LG_CHECK_HIP(hipStreamSynchronize(s));
+        }
+        LG_CHECK_HIP(hipStreamSynchronize(s));
+        cur_off = off_new.as<uint64_t>();
+        cur_col = col_new.as<uint32_t>();
+    }
+
+    // -- plain CSR baseline ----------------------------------------------
+    if (o.layout == LG_LAYOUT_PLAIN) {
+        g->poff64 = m >= (1ull << 32);
+        if (g->poff64) {
+            LG_TRY(g->poff.alloc(((uint64_t)n + 1) * 8));
+            LG_CHECK_HIP(hipMemcpyAsync(g->poff.p, cur_off, ((uint64_t)n + 1) * 8, hipMemcpyDeviceToDevice, s));
+        } else {
+            LG_TRY(g->poff.alloc(((uint64_t)n + 1) * 4));
+            LG_LAUNCH(offsets_to_u32_kernel, grid1(n + 1ull), 256, 0, s, (uint64_t)n + 1, cur_off,
+                      g->poff.as<uint32_t>());
+            LG_CHECK_LAUNCH();
+        }
+        if (col_new.p) {
+            g->pcol = std::move(col_new);
+        } else {
+            LG_TRY(g->pcol.alloc((m ? m : 1) * 4));
+            if (m) LG_CHECK_HIP(hipMemcpyAsync(g->pcol.p, cur_col, m * 4, hipMemcpyDeviceToDevice, s));
+        }
+        LG_CHECK_HIP(hipStreamSynchronize(s));
+        return LG_OK;
+    }
+
+    // -- packed representation ---------------------------------------------
+    g->s = idbits ? idbits : 1;
+    if (o.id_mode == LG_IDS_GLOBAL) {
+        g->U = m * g->s;
+        LG_TRY(pack_fixed(SrcU32{cur_col}, m, g->s, g->A, g->A_words, s));
+        LG_TRY(build_offsets(g, cur_off, m, tmp, s));
+    } else {
+        g->F = bitlen_u64(g->s);
+        DevBuf w8, len, P;
+        LG_TRY(w8.alloc((uint64_t)n));
+        LG_TRY(len.alloc((uint64_t)n * 8));
+        LG_TRY(P.alloc(((uint64_t)n + 1) * 8));
+        LG_LAUNCH(local_width_kernel, grid1(n), 256, 0, s, n, cur_off, cur_col, w8.as<uint8_t>(),
+                  len.as<uint64_t>());
+        LG_CHECK_LAUNCH();
+        LG_TRY(exclusive_scan_u64(len.as<uint64_t>(), P.as<uint64_t>(), n, tmp, s));
+        LG_CHECK_HIP(hipMemcpyAsync(&g->U, P.as<uint64_t>() + n, 8, hipMemcpyDeviceToHost, s));
+        LG_CHECK_HIP(hipStreamSynchronize(s));
+        LG_TRY(pack_fixed(SrcU8{w8.as<uint8_t>()}, n, g->F, g->W, g->W_words, s));
+        g->A_words = (g->U + 63) / 64 + 1;
+        LG_TRY(g->A.alloc(g->A_words * 8));
+        LG_LAUNCH(pack_local_kernel, grid_for(g->A_words, 256, 1ull << 31), 256, 0, s, n, cur_off, cur_col,
+                  w8.as<uint8_t>(), P.as<uint64_t>(), g->U, g->A_words, g->A.as<uint64_t>());
+        LG_CHECK_LAUNCH();
+        LG_TRY(build_offsets(g, P.as<uint64_t>(), g->U, tmp, s));
+        LG_CHECK_HIP(hipStreamSynchronize(s));
+    }
+    LG_CHECK_HIP(hipStreamSynchronize(s));
+    return LG_OK;
+}
+
+}  // namespace lg
+
+extern "C" lg_status lg_encode(uint32_t n, uint64_t m, const uint64_t *row_offsets, const uint32_t *col,
+                               const lg_encode_opts *opts, hipStream_t stream, lg_graph **out) {
+    using namespace lg;
+    if (!out) { set_error("lg_encode: out is NULL"); return LG_ERR_INVALID; }
+    *out = nullptr;
+    lg_encode_opts o;
+    std::memset(&o, 0, sizeof(o));
+    if (opts) o = *opts;
+    if (n == 0 || n >= (1u << 31)) { set_error("lg_encode: n must be in [1, 2^31)"); return LG_ERR_INVALID; }
+    if (m >= (1ull << 36)) { set_error("lg_encode: m must be below 2^36"); return LG_ERR_UNSUPPORTED; }
+    if (!row_offsets || (m && !col)) { set_error("lg_encode: NULL input array"); return LG_ERR_INVALID; }
+    if (o.layout > LG_LAYOUT_PLAIN || o.id_mode > LG_IDS_LOCAL || o.offset_mode > LG_OFFS_SUCCINCT ||
+        o.relabel > LG_RELABEL_DEGREE || o.flags || o.reserved[0] || o.reserved[1] || o.reserved[2]) {
+        set_error("lg_encode: unknown option value");
+        return LG_ERR_INVALID;
+    }
+    lg_graph *g = new (std::nothrow) lg_graph();
+    if (!g) { set_error("lg_encode: host allocation failed"); return LG_ERR_OOM; }
+    g->n = n;
+    g->m = m;
+    g->layout = o.layout;
+    g->id_mode = o.layout == LG_LAYOUT_PACKED ? o.id_mode : 0;
+    g->offset_mode = o.layout == LG_LAYOUT_PACKED ? o.offset_mode : 0;
+    g->relabel = o.relabel;
+    const lg_status st = encode_impl(n, m, row_offsets, col, o, stream, g);
+    if (st != LG_OK) {
+        (void)hipStreamSynchronize(stream);
+        lg_free(g);
+        return st;
+    }
+    *out = g;
+    return LG_OK;
+}

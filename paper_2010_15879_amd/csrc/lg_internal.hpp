@@ -1,0 +1,201 @@
+// Internal declarations of liblg: the graph handle, device views of it,
+// error plumbing, kernel-launch timing and shared utility launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "lg.h"
+
+namespace lg {
+
+// ---------------------------------------------------------------------------
+// error plumbing
+// ---------------------------------------------------------------------------
+
+void set_error(const char *fmt, ...);
+
+#define LG_CHECK_HIP(expr)                                                              \
+    do {                                                                                \
+        hipError_t e_ = (expr);                                                         \
+        if (e_ != hipSuccess) {                                                         \
+            ::lg::set_error("%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_),      \
+                            __FILE__, __LINE__);                                        \
+            return e_ == hipErrorOutOfMemory ? LG_ERR_OOM : LG_ERR_DEVICE;              \
+        }                                                                               \
+    } while (0)
+
+#define LG_TRY(expr)                                                                    \
+    do {                                                                                \
+        lg_status s_ = (expr);                                                          \
+        if (s_ != LG_OK) return s_;                                                     \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// device memory owned by the library
+// ---------------------------------------------------------------------------
+
+// A device buffer with RAII release; on failure the status says OOM.
+struct DevBuf {
+    void *p = nullptr;
+    uint64_t bytes = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    DevBuf(DevBuf &&o) noexcept : p(o.p), bytes(o.bytes) { o.p = nullptr; o.bytes = 0; }
+    DevBuf &operator=(DevBuf &&o) noexcept {
+        if (this != &o) { release(); p = o.p; bytes = o.bytes; o.p = nullptr; o.bytes = 0; }
+        return *this;
+    }
+    ~DevBuf() { release(); }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    lg_status alloc(uint64_t nbytes);          // release + allocate
+    lg_status ensure(uint64_t nbytes);         // grow only
+    template <class T> T *as() const { return static_cast<T *>(p); }
+};
+
+// ---------------------------------------------------------------------------
+// device views (passed to kernels by value)
+// ---------------------------------------------------------------------------
+
+// Elias-Fano offsets: x_v = ((select1(H, v) - v) << l) | L[v].
+struct EFView {
+    const uint64_t *L;        // low bits, l per value
+    const uint64_t *H;        // upper bit vector
+    const uint32_t *rank_sb;  // rank1(512 b)
+    const uint32_t *sel;      // select1(64 j)
+    uint32_t l;
+    uint32_t n_sel;           // entries of sel
+    uint32_t n_sb;            // superblocks = entries of rank_sb - 1
+};
+
+// Packed offsets: value v at bits [v*w, v*w + w).
+struct POffView {
+    const uint64_t *O;
+    uint32_t w;
+};
+
+struct PackedView {
+    const uint32_t *A32;      // packed lists viewed as 32-bit words
+    const uint64_t *W;        // width table (local mode)
+    uint32_t s;               // global width
+    uint32_t F;               // width field bits
+    POffView po;
+    EFView ef;
+};
+
+struct PlainView {
+    const void *off;          // uint32 or uint64 offsets
+    const uint32_t *col;
+};
+
+// ---------------------------------------------------------------------------
+// the graph handle
+// ---------------------------------------------------------------------------
+
+struct BfsWork;
+struct PrWork;
+
+}  // namespace lg
+
+struct lg_graph {
+    uint32_t n = 0;
+    uint64_t m = 0;
+    uint32_t layout = 0, id_mode = 0, offset_mode = 0, relabel = 0;
+    int device = 0;
+    uint32_t max_degree = 0, isolated = 0;
+
+    // packed layout
+    uint32_t s = 0, F = 0, wO = 0, ef_l = 0;
+    uint64_t U = 0, universe = 0, hbits = 0;
+    lg::DevBuf A, O, W, L, H, rank_sb, sel;
+    uint64_t A_words = 0, O_words = 0, W_words = 0, L_words = 0, H_words = 0, n_rank = 0, n_sel = 0;
+
+    // plain layout
+    lg::DevBuf poff, pcol;
+    bool poff64 = false;
+
+    // relabeling: perm[new] = old, inv[old] = new
+    lg::DevBuf perm, inv;
+
+    // lazily allocated workspaces
+    lg::BfsWork *bfs = nullptr;
+    lg::PrWork *pr = nullptr;
+    lg::DevBuf dec_tmp;        // lg_decode_neighbors scratch
+
+    lg::PackedView packed_view() const;
+    lg::PlainView plain_view() const;
+    uint64_t device_bytes() const;
+};
+
+namespace lg {
+
+// ---------------------------------------------------------------------------
+// kernel timing (lg_prof_*)
+// ---------------------------------------------------------------------------
+
+bool prof_on();
+struct ProfMark {
+    hipEvent_t a = nullptr, b = nullptr;
+    const char *name = nullptr;
+    hipStream_t stream = nullptr;
+};
+ProfMark prof_begin(const char *name, hipStream_t stream);
+void prof_end(ProfMark &m);
+
+// Launch a kernel with timing when profiling is on.
+#define LG_LAUNCH(kernel, grid, block, shmem, stream, ...)                              \
+    do {                                                                                \
+        ::lg::ProfMark pm_;                                                             \
+        if (::lg::prof_on()) pm_ = ::lg::prof_begin(#kernel, stream);                   \
+        hipLaunchKernelGGL(kernel, dim3(grid), dim3(block), shmem, stream, __VA_ARGS__); \
+        if (pm_.a) ::lg::prof_end(pm_);                                                 \
+    } while (0)
+
+#define LG_CHECK_LAUNCH() LG_CHECK_HIP(hipGetLastError())
+
+// ---------------------------------------------------------------------------
+// utility launchers (lg_util.hip)
+// ---------------------------------------------------------------------------
+
+lg_status fill_u32(uint32_t *p, uint32_t value, uint64_t count, hipStream_t s);
+lg_status fill_u64(uint64_t *p, uint64_t value, uint64_t count, hipStream_t s);
+
+// Exclusive prefix sum: out[0..count] with out[count] = total.  `tmp` is
+// grown as needed.
+lg_status exclusive_scan_u32(const uint32_t *in, uint64_t *out, uint64_t count, DevBuf &tmp,
+                             hipStream_t s);
+lg_status exclusive_scan_u64(const uint64_t *in, uint64_t *out, uint64_t count, DevBuf &tmp,
+                             hipStream_t s);
+
+// Stable LSD radix sort of (key, value) pairs on key bits [0, bits).
+// Results end in keys/vals (the buffers are ping-ponged with the alt ones).
+lg_status radix_sort_pairs(uint32_t *keys, uint32_t *vals, uint32_t *keys_alt, uint32_t *vals_alt,
+                           uint64_t count, uint32_t bits, DevBuf &tmp, hipStream_t s);
+
+// Stable radix sort of (key, value) pairs whose keys are 64-bit: bits [0, bits).
+lg_status radix_sort_pairs64(uint64_t *keys, uint32_t *vals, uint64_t *keys_alt, uint32_t *vals_alt,
+                             uint64_t count, uint32_t bits, DevBuf &tmp, hipStream_t s);
+
+// Grid size helper: blocks needed for `count` items at `per_block`, capped.
+inline uint32_t grid_for(uint64_t count, uint64_t per_block, uint64_t cap = 1u << 30) {
+    uint64_t g = (count + per_block - 1) / per_block;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (uint32_t)g;
+}
+
+inline uint32_t bitlen_u64(uint64_t x) { return x ? 64u - (uint32_t)__builtin_clzll(x) : 0u; }
+
+lg_status bfs_free(lg_graph *g);
+lg_status pr_free(lg_graph *g);
+
+}  // namespace lg

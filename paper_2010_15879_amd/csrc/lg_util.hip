@@ -1,0 +1,267 @@
+// Device utilities of liblg: fills, exclusive prefix sums and a stable LSD
+// radix sort of key/value pairs (used by the degree relabeling and the
+// sorted neighbor decode).
+#include "lg_device.hpp"
+
+namespace lg {
+
+// ---------------------------------------------------------------------------
+// fill
+// ---------------------------------------------------------------------------
+
+template <class T>
+__global__ void fill_kernel(T *__restrict__ p, T value, uint64_t count) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) p[i] = value;
+}
+
+lg_status fill_u32(uint32_t *p, uint32_t value, uint64_t count, hipStream_t s) {
+    if (!count) return LG_OK;
+    LG_LAUNCH(fill_kernel<uint32_t>, grid_for(count, 256 * 8, 1u << 16), 256, 0, s, p, value, count);
+    LG_CHECK_LAUNCH();
+    return LG_OK;
+}
+
+lg_status fill_u64(uint64_t *p, uint64_t value, uint64_t count, hipStream_t s) {
+    if (!count) return LG_OK;
+    LG_LAUNCH(fill_kernel<uint64_t>, grid_for(count, 256 * 8, 1u << 16), 256, 0, s, p, value, count);
+    LG_CHECK_LAUNCH();
+    return LG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// exclusive scan: reduce tiles -> scan tile sums (recursively) -> scan tiles
+// ---------------------------------------------------------------------------
+
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 8;
+constexpr uint64_t kScanTile = (uint64_t)kScanThreads * kScanItems;
+
+// block-wide exclusive scan of one value per thread; returns the block total
+__device__ __forceinline__ uint64_t block_excl_scan(uint64_t x, uint64_t &excl) {
+    __shared__ uint64_t wave_tot[kScanThreads / kWave];
+    const uint32_t lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+    const uint64_t incl = wave_incl_scan(x);
+    if (lane == kWave - 1) wave_tot[wv] = incl;
+    __syncthreads();
+    uint64_t base = 0, total = 0;
+#pragma unroll
+    for (int w = 0; w < kScanThreads / kWave; ++w) {
+        if (w < (int)wv) base += wave_tot[w];
+        total += wave_tot[w];
+    }
+    __syncthreads();
+    excl = base + incl - x;
+    return total;
+}
+
+template <class T>
+__global__ void scan_reduce_kernel(const T *__restrict__ in, uint64_t count, uint64_t *__restrict__ sums) {
+    const uint64_t t0 = (uint64_t)blockIdx.x * kScanTile;
+    uint64_t acc = 0;
+#pragma unroll
+    for (int r = 0; r < kScanItems; ++r) {
+        const uint64_t i = t0 + (uint64_t)r * kScanThreads + threadIdx.x;
+        if (i < count) acc += (uint64_t)in[i];
+    }
+    uint64_t excl;
+    const uint64_t total = block_excl_scan(acc, excl);
+    if (threadIdx.x == 0) sums[blockIdx.x] = total;
+}
+
+// Each thread scans kScanItems consecutive inputs; offsets[b] is the
+// exclusive prefix of the tile (NULL: 0).  The block owning the last item
+// also writes out[count].
+template <class T>
+__global__ void scan_tile_kernel(const T *__restrict__ in, uint64_t count, const uint64_t *__restrict__ offsets,
+                                 uint64_t *__restrict__ out) {
+    const uint64_t t0 = (uint64_t)blockIdx.x * kScanTile;
+    const uint64_t i0 = t0 + (uint64_t)threadIdx.x * kScanItems;
+    uint64_t v[kScanItems];
+    uint64_t acc = 0;
+#pragma unroll
+    for (int r = 0; r < kScanItems; ++r) {
+        v[r] = (i0 + r < count) ? (uint64_t)in[i0 + r] : 0ull;
+        acc += v[r];
+    }
+    uint64_t excl;
+    const uint64_t total = block_excl_scan(acc, excl);
+    const uint64_t base = (offsets ? offsets[blockIdx.x] : 0ull);
+    uint64_t run = base + excl;
+#pragma unroll
+    for (int r = 0; r < kScanItems; ++r) {
+        if (i0 + r < count) out[i0 + r] = run;
+        run += v[r];
+    }
+    if (t0 + kScanTile >= count && threadIdx.x == 0) out[count] = base + total;
+}
+
+template <class T>
+static lg_status scan_level(const T *in, uint64_t *out, uint64_t count, uint64_t *tmp, hipStream_t s) {
+    if (count <= kScanTile) {
+        LG_LAUNCH((scan_tile_kernel<T>), 1, kScanThreads, 0, s, in, count, (const uint64_t *)nullptr, out);
+        LG_CHECK_LAUNCH();
+        return LG_OK;
+    }
+    const uint64_t nb = (count + kScanTile - 1) / kScanTile;
+    uint64_t *sums = tmp;
+    uint64_t *sums_scan = tmp + nb;
+    LG_LAUNCH((scan_reduce_kernel<T>), (uint32_t)nb, kScanThreads, 0, s, in, count, sums);
+    LG_CHECK_LAUNCH();
+    LG_TRY(scan_level<uint64_t>(sums, sums_scan, nb, tmp + 2 * nb + 1, s));
+    LG_LAUNCH((scan_tile_kernel<T>), (uint32_t)nb, kScanThreads, 0, s, in, count,
+              (const uint64_t *)sums_scan, out);
+    LG_CHECK_LAUNCH();
+    return LG_OK;
+}
+
+static uint64_t scan_tmp_words(uint64_t count) {
+    uint64_t words = 0;
+    while (count > kScanTile) {
+        const uint64_t nb = (count + kScanTile - 1) / kScanTile;
+        words += 2 * nb + 1;
+        count = nb;
+    }
+    return words + 1;
+}
+
+lg_status exclusive_scan_u32(const uint32_t *in, uint64_t *out, uint64_t count, DevBuf &tmp, hipStream_t s) {
+    if (count == 0) return fill_u64(out, 0, 1, s);
+    LG_TRY(tmp.ensure(scan_tmp_words(count) * sizeof(uint64_t)));
+    return scan_level<uint32_t>(in, out, count, tmp.as<uint64_t>(), s);
+}
+
+lg_status exclusive_scan_u64(const uint64_t *in, uint64_t *out, uint64_t count, DevBuf &tmp, hipStream_t s) {
+    if (count == 0) return fill_u64(out, 0, 1, s);
+    LG_TRY(tmp.ensure(scan_tmp_words(count) * sizeof(uint64_t)));
+    return scan_level<uint64_t>(in, out, count, tmp.as<uint64_t>(), s);
+}
+
+// ---------------------------------------------------------------------------
+// stable LSD radix sort of (key, value) pairs, 8-bit digits
+// ---------------------------------------------------------------------------
+
+constexpr int kSortThreads = 256;
+constexpr int kSortRounds = 16;
+constexpr uint64_t kSortTile = (uint64_t)kSortThreads * kSortRounds;
+constexpr int kSortWaves = kSortThreads / kWave;
+
+template <class K>
+__global__ void radix_hist_kernel(const K *__restrict__ keys, uint64_t count, uint32_t shift, uint32_t ntiles,
+                                  uint32_t *__restrict__ counts) {
+    __shared__ uint32_t hist[256];
+    hist[threadIdx.x] = 0;
+    __syncthreads();
+    const uint64_t t0 = (uint64_t)blockIdx.x * kSortTile;
+#pragma unroll 4
+    for (int r = 0; r < kSortRounds; ++r) {
+        const uint64_t i = t0 + (uint64_t)r * kSortThreads + threadIdx.x;
+        if (i < count) atomicAdd(&hist[(uint32_t)(keys[i] >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    counts[(uint64_t)threadIdx.x * ntiles + blockIdx.x] = hist[threadIdx.x];
+}
+
+// Items of a tile are taken in rounds of 256 consecutive keys; within a
+// round, lanes with equal digits are found with eight ballots, so every key
+// gets its rank among equal digits in input order (stability).
+template <class K>
+__global__ void radix_scatter_kernel(const K *__restrict__ keys, const uint32_t *__restrict__ vals, uint64_t count,
+                                     uint32_t shift, uint32_t ntiles, const uint64_t *__restrict__ offsets,
+                                     K *__restrict__ keys_out, uint32_t *__restrict__ vals_out) {
+    __shared__ uint64_t base[256];
+    __shared__ uint32_t wave_cnt[kSortWaves][256];
+    const uint32_t lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+    base[threadIdx.x] = offsets[(uint64_t)threadIdx.x * ntiles + blockIdx.x];
+    const uint64_t t0 = (uint64_t)blockIdx.x * kSortTile;
+    for (int r = 0; r < kSortRounds; ++r) {
+        const uint64_t i = t0 + (uint64_t)r * kSortThreads + threadIdx.x;
+        const bool valid = i < count;
+        K key = 0;
+        uint32_t val = 0;
+        if (valid) { key = keys[i]; val = vals[i]; }
+        const uint32_t digit = (uint32_t)(key >> shift) & 255u;
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const uint64_t m = __ballot((digit >> b) & 1u);
+            peers &= ((digit >> b) & 1u) ? m : ~m;
+        }
+#pragma unroll
+        for (int w = 0; w < kSortWaves; ++w) wave_cnt[w][threadIdx.x] = 0;
+        __syncthreads();
+        const uint32_t rank = popc_below(peers);
+        if (valid && rank == 0) wave_cnt[wv][digit] = (uint32_t)__popcll(peers);
+        __syncthreads();
+        {   // per digit: exclusive prefix over waves, then advance the base
+            const uint32_t d = threadIdx.x;
+            uint64_t run = base[d];
+#pragma unroll
+            for (int w = 0; w < kSortWaves; ++w) {
+                const uint32_t c = wave_cnt[w][d];
+                wave_cnt[w][d] = (uint32_t)(run - base[d]);
+                run += c;
+            }
+            __syncthreads();
+            if (valid) {
+                const uint64_t dst = base[digit] + wave_cnt[wv][digit] + rank;
+                keys_out[dst] = key;
+                vals_out[dst] = val;
+            }
+            __syncthreads();
+            base[d] = run;
+        }
+        __syncthreads();
+        (void)lane;
+    }
+}
+
+template <class K>
+static lg_status radix_sort_impl(K *keys, uint32_t *vals, K *keys_alt, uint32_t *vals_alt, uint64_t count,
+                                 uint32_t bits, DevBuf &tmp, hipStream_t s) {
+    if (count <= 1 || bits == 0) return LG_OK;
+    const uint64_t ntiles = (count + kSortTile - 1) / kSortTile;
+    if (ntiles * 256 >= (1ull << 32)) {
+        set_error("radix sort: %llu items is too many", (unsigned long long)count);
+        return LG_ERR_UNSUPPORTED;
+    }
+    const uint64_t ncount = ntiles * 256;
+    const uint64_t scan_words = scan_tmp_words(ncount);
+    // layout of tmp: counts (u32, ncount) | offsets (u64, ncount + 1) | scan scratch
+    const uint64_t bytes = ((ncount * 4 + 7) & ~7ull) + (ncount + 1) * 8 + scan_words * 8;
+    LG_TRY(tmp.ensure(bytes));
+    uint32_t *counts = tmp.as<uint32_t>();
+    uint64_t *offs = reinterpret_cast<uint64_t *>(tmp.as<char>() + ((ncount * 4 + 7) & ~7ull));
+    uint64_t *scratch = offs + ncount + 1;
+    K *src_k = keys, *dst_k = keys_alt;
+    uint32_t *src_v = vals, *dst_v = vals_alt;
+    int passes = 0;
+    for (uint32_t shift = 0; shift < bits; shift += 8, ++passes) {
+        LG_LAUNCH(radix_hist_kernel<K>, (uint32_t)ntiles, kSortThreads, 0, s, src_k, count, shift,
+                  (uint32_t)ntiles, counts);
+        LG_CHECK_LAUNCH();
+        LG_TRY(scan_level<uint32_t>(counts, offs, ncount, scratch, s));
+        LG_LAUNCH(radix_scatter_kernel<K>, (uint32_t)ntiles, kSortThreads, 0, s, src_k, src_v, count, shift,
+                  (uint32_t)ntiles, (const uint64_t *)offs, dst_k, dst_v);
+        LG_CHECK_LAUNCH();
+        K *tk = src_k; src_k = dst_k; dst_k = tk;
+        uint32_t *tv = src_v; src_v = dst_v; dst_v = tv;
+    }
+    if (passes & 1) {
+        LG_CHECK_HIP(hipMemcpyAsync(keys, keys_alt, count * sizeof(K), hipMemcpyDeviceToDevice, s));
+        LG_CHECK_HIP(hipMemcpyAsync(vals, vals_alt, count * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
+    }
+    return LG_OK;
+}
+
+lg_status radix_sort_pairs(uint32_t *keys, uint32_t *vals, uint32_t *keys_alt, uint32_t *vals_alt, uint64_t count,
+                           uint32_t bits, DevBuf &tmp, hipStream_t s) {
+    return radix_sort_impl<uint32_t>(keys, vals, keys_alt, vals_alt, count, bits, tmp, s);
+}
+
+lg_status radix_sort_pairs64(uint64_t *keys, uint32_t *vals, uint64_t *keys_alt, uint32_t *vals_alt, uint64_t count,
+                             uint32_t bits, DevBuf &tmp, hipStream_t s) {
+    return radix_sort_impl<uint64_t>(keys, vals, keys_alt, vals_alt, count, bits, tmp, s);
+}
+
+}  // namespace lg

@@ -1,0 +1,235 @@
+"""Python binding of liblg (include/lg.h): argument marshalling only.
+
+Every step of encoding, decoding, BFS and PageRank runs in the HIP kernels of
+liblg.so; PyTorch provides device memory and the current HIP stream.  If the
+library is not built this module raises on import of the library -- there is
+no fallback path.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblg.so")
+
+# -- constants of include/lg.h --------------------------------------------
+LG_OK, LG_ERR_INVALID, LG_ERR_OOM, LG_ERR_DEVICE, LG_ERR_UNSUPPORTED, LG_ERR_CAPACITY = range(6)
+STATUS_NAMES = {0: "LG_OK", 1: "LG_ERR_INVALID", 2: "LG_ERR_OOM", 3: "LG_ERR_DEVICE",
+                4: "LG_ERR_UNSUPPORTED", 5: "LG_ERR_CAPACITY"}
+LAYOUTS = {"packed": 0, "plain": 1}
+ID_MODES = {"global": 0, "local": 1}
+OFFSET_MODES = {"packed": 0, "succinct": 1, "ef": 1}
+DECODE_FLAGS = {"sorted": 0, "original": 1, "raw": 2}
+BFS_FLAGS = {"do": 0, "direction-opt": 0, "top-down": 1, "td": 1, "bottom-up": 2, "bu": 2}
+EXPORTS = {"adj": 0, "offsets": 1, "widths": 2, "ef_low": 3, "ef_high": 4, "ef_rank": 5,
+           "ef_select": 6, "perm": 7, "inv": 8}
+_EXPORT_DTYPE = {"ef_rank": np.uint32, "ef_select": np.uint32, "perm": np.uint32, "inv": np.uint32}
+
+
+class LGError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class EncodeOpts(C.Structure):
+    _fields_ = [("layout", C.c_uint32), ("id_mode", C.c_uint32), ("offset_mode", C.c_uint32),
+                ("relabel", C.c_uint32), ("flags", C.c_uint32), ("reserved", C.c_uint32 * 3)]
+
+
+class GraphInfo(C.Structure):
+    _fields_ = [("n", C.c_uint64), ("m", C.c_uint64), ("layout", C.c_uint32), ("id_mode", C.c_uint32),
+                ("offset_mode", C.c_uint32), ("relabel", C.c_uint32), ("s", C.c_uint32), ("F", C.c_uint32),
+                ("w_offset", C.c_uint32), ("ef_l", C.c_uint32), ("universe", C.c_uint64),
+                ("adj_bits", C.c_uint64), ("ef_high_bits", C.c_uint64), ("bytes_adj", C.c_uint64),
+                ("bytes_offsets", C.c_uint64), ("bytes_widths", C.c_uint64), ("bytes_perm", C.c_uint64),
+                ("device_bytes", C.c_uint64), ("max_degree", C.c_uint32), ("isolated", C.c_uint32)]
+
+
+_lib = None
+
+FUNCTIONS = {
+    "lg_encode": (C.c_int, [C.c_uint32, C.c_uint64, C.c_void_p, C.c_void_p, C.POINTER(EncodeOpts), C.c_void_p,
+                            C.POINTER(C.c_void_p)]),
+    "lg_decode_neighbors": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint32, C.c_void_p, C.c_void_p, C.c_uint64,
+                                      C.c_uint32, C.c_void_p]),
+    "lg_bfs": (C.c_int, [C.c_void_p, C.POINTER(C.c_uint32), C.c_uint32, C.c_void_p, C.c_void_p, C.c_int32,
+                         C.c_uint32, C.c_void_p]),
+    "lg_pagerank": (C.c_int, [C.c_void_p, C.c_float, C.c_uint32, C.c_void_p, C.c_void_p]),
+    "lg_free": (None, [C.c_void_p]),
+    "lg_info": (C.c_int, [C.c_void_p, C.POINTER(GraphInfo)]),
+    "lg_export": (C.c_int, [C.c_void_p, C.c_uint32, C.c_void_p, C.c_uint64]),
+    "lg_export_bytes": (C.c_uint64, [C.c_void_p, C.c_uint32]),
+    "lg_last_error": (C.c_char_p, []),
+    "lg_prof_enable": (C.c_int, [C.c_int]),
+    "lg_prof_reset": (C.c_int, []),
+    "lg_prof_query": (C.c_int, [C.c_char_p, C.POINTER(C.c_uint64), C.POINTER(C.c_double)]),
+    "lg_prof_names": (C.c_int, [C.c_char_p, C.c_uint64]),
+}
+
+
+def lib() -> C.CDLL:
+    """Load liblg.so; raise if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() or "
+                          f"python paper_2010_15879_amd/build.py")
+    L = C.CDLL(LIB_PATH)
+    for name, (res, args) in FUNCTIONS.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def _check(status: int):
+    if status != LG_OK:
+        msg = lib().lg_last_error()
+        raise LGError(status, msg.decode() if msg else "")
+
+
+def _stream(stream=None) -> int:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return int(stream.cuda_stream)
+
+
+def _dev_ptr(t: Optional[torch.Tensor], dtype, what: str) -> Optional[int]:
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError(f"{what} must be a device tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{what} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{what} must be contiguous")
+    return t.data_ptr()
+
+
+class Graph:
+    """A representation built by lg_encode; owns the device arrays."""
+
+    def __init__(self, handle: int, n: int, m: int):
+        self._h = C.c_void_p(handle)
+        self.n = n
+        self.m = m
+
+    @property
+    def handle(self) -> C.c_void_p:
+        if not self._h:
+            raise ValueError("graph already freed")
+        return self._h
+
+    def free(self):
+        if self._h:
+            lib().lg_free(self._h)
+            self._h = C.c_void_p(None)
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    def info(self) -> dict:
+        out = GraphInfo()
+        _check(lib().lg_info(self.handle, C.byref(out)))
+        return {k: getattr(out, k) for k, _ in GraphInfo._fields_}
+
+    def export(self, which: str) -> np.ndarray:
+        code = EXPORTS[which]
+        nbytes = int(lib().lg_export_bytes(self.handle, code))
+        inf = self.info()
+        if which == "adj" and inf["layout"] == LAYOUTS["plain"]:
+            dtype = np.uint32
+        elif which == "offsets" and inf["layout"] == LAYOUTS["plain"]:
+            dtype = np.uint64 if inf["m"] >= (1 << 32) else np.uint32
+        else:
+            dtype = _EXPORT_DTYPE.get(which, np.uint64)
+        buf = np.zeros(nbytes // np.dtype(dtype).itemsize, dtype=dtype)
+        _check(lib().lg_export(self.handle, code, buf.ctypes.data_as(C.c_void_p), nbytes))
+        return buf
+
+
+def encode(row_offsets: torch.Tensor, col: torch.Tensor, n: Optional[int] = None, *, layout="packed",
+           ids="global", offsets="packed", relabel=False, stream=None) -> Graph:
+    """lg_encode over a device CSR (row_offsets int64[n+1], col int32[M])."""
+    n = row_offsets.numel() - 1 if n is None else n
+    m = col.numel()
+    opts = EncodeOpts(LAYOUTS[layout], ID_MODES[ids], OFFSET_MODES[offsets], 1 if relabel else 0, 0)
+    out = C.c_void_p()
+    _check(lib().lg_encode(n, m, _dev_ptr(row_offsets, torch.int64, "row_offsets"),
+                           _dev_ptr(col, torch.int32, "col") if m else None, C.byref(opts), _stream(stream),
+                           C.byref(out)))
+    return Graph(out.value, n, m)
+
+
+def decode_neighbors(g: Graph, vertices: torch.Tensor, flags="sorted", cap: Optional[int] = None, stream=None):
+    """Returns (offsets int64[k+1], ids int32[total]) on the device."""
+    k = vertices.numel()
+    dev = vertices.device
+    off = torch.empty(k + 1, dtype=torch.int64, device=dev)
+    vptr = _dev_ptr(vertices, torch.int32, "vertices") if k else None
+    s = _stream(stream)
+    if cap is None:
+        st = lib().lg_decode_neighbors(g.handle, vptr, k, off.data_ptr(), None, 0, DECODE_FLAGS[flags], s)
+        if st not in (LG_OK, LG_ERR_CAPACITY):
+            _check(st)
+        cap = int(off[-1].item())
+    ids = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+    _check(lib().lg_decode_neighbors(g.handle, vptr, k, off.data_ptr(), ids.data_ptr(), cap, DECODE_FLAGS[flags], s))
+    return off, ids[: int(off[-1].item())]
+
+
+def bfs(g: Graph, roots: Sequence[int], *, parent=True, max_depth=-1, mode="do", depth_out=None,
+        parent_out=None, stream=None):
+    """Returns (depth int32[r, n], parent int32[r, n] or None)."""
+    r = len(roots)
+    dev = torch.device("cuda", torch.cuda.current_device())
+    depth = depth_out if depth_out is not None else torch.empty((r, g.n), dtype=torch.int32, device=dev)
+    par = parent_out if parent_out is not None else (
+        torch.empty((r, g.n), dtype=torch.int32, device=dev) if parent else None)
+    arr = (C.c_uint32 * max(r, 1))(*[int(x) for x in roots])
+    _check(lib().lg_bfs(g.handle, arr, r, _dev_ptr(depth, torch.int32, "depth"),
+                        _dev_ptr(par, torch.int32, "parent"), max_depth, BFS_FLAGS[mode], _stream(stream)))
+    return depth, par
+
+
+def pagerank(g: Graph, damping: float = 0.85, iters: int = 20, out=None, stream=None) -> torch.Tensor:
+    dev = torch.device("cuda", torch.cuda.current_device())
+    scores = out if out is not None else torch.empty(g.n, dtype=torch.float32, device=dev)
+    _check(lib().lg_pagerank(g.handle, float(damping), int(iters), _dev_ptr(scores, torch.float32, "scores"),
+                             _stream(stream)))
+    return scores
+
+
+# -- kernel timing ------------------------------------------------------
+
+def prof_enable(on: bool = True):
+    _check(lib().lg_prof_enable(1 if on else 0))
+
+
+def prof_reset():
+    _check(lib().lg_prof_reset())
+
+
+def prof_query(kernel: str):
+    launches = C.c_uint64()
+    ms = C.c_double()
+    _check(lib().lg_prof_query(kernel.encode(), C.byref(launches), C.byref(ms)))
+    return int(launches.value), float(ms.value)
+
+
+def prof_names() -> list:
+    buf = C.create_string_buffer(1 << 16)
+    lib().lg_prof_names(buf, len(buf))
+    return [x for x in buf.value.decode().split("\n") if x]
