@@ -1,0 +1,268 @@
+#!/usr/bin/env python3
+"""Benchmark of the Log(Graph) packed-graph hot path on one MI355X.
+
+One step = encode the graph (validate, degree relabel, local widths, scan,
+pack, Elias-Fano offsets), BFS from 64 roots (direction-optimizing, depths
+and parents) and 20 PageRank iterations, all on the packed representation.
+Workload: Kronecker (R-MAT a=.57 b=.19 c=.19) scale 24, edge factor 16,
+seed 1, symmetrized, self-loops and duplicates removed.
+
+Throughput is counted in undirected traversed edges (Graph500 convention):
+BFS from root r counts half the degree sum of the vertices it reaches; one
+PageRank iteration counts every undirected edge once.  value = those edges
+per second over the whole step, inputs resident in HBM.
+
+The same step is also run on the plain uint32 CSR (same labeling) for the
+packed/plain comparison, and the CPU oracle is timed on a bounded sample.
+Prints one JSON line.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+WORKLOADS = {
+    # name: (generator, scale, encoding)
+    "kronecker-s24-dm-local-ef": ("kronecker", 24, dict(ids="local", offsets="succinct", relabel=True)),
+    "kronecker-s16-global-packed": ("kronecker", 16, dict(ids="global", offsets="packed", relabel=False)),
+    "er-s26-global-packed": ("er", 26, dict(ids="global", offsets="packed", relabel=False)),
+    "kronecker-s20-dm-local-ef": ("kronecker", 20, dict(ids="local", offsets="succinct", relabel=True)),
+}
+DEFAULT_WORKLOAD = "kronecker-s24-dm-local-ef"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=3)
+    p.add_argument("--warmup", type=int, default=1)
+    p.add_argument("--workload", default=DEFAULT_WORKLOAD, choices=sorted(WORKLOADS))
+    p.add_argument("--roots", type=int, default=64)
+    p.add_argument("--pr-iters", type=int, default=20)
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--no-plain", action="store_true")
+    p.add_argument("--kernels", action="store_true", help="print the per-kernel time breakdown to stderr")
+    return p.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only: --gpus {args.gpus} is not supported by this build "
+              f"(the path runs on a single MI355X; sharding is described in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2010_15879_amd import graphgen as gg
+    from paper_2010_15879_amd import lg
+
+    lg.lib()  # fail loudly without the HIP library
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda", 0)
+    gen, scale, enc = WORKLOADS[args.workload]
+
+    t0 = time.time()
+    g = (gg.kronecker if gen == "kronecker" else gg.erdos_renyi)(scale, 16, seed=1, device=dev)
+    torch.cuda.synchronize()
+    roots = gg.pick_roots(g, args.roots, seed=1)
+    deg = g.degrees()
+    log(f"[bench] graph {args.workload}: n={g.n} M={g.m} isolated={int((deg == 0).sum())} "
+        f"maxdeg={int(deg.max())} gen {time.time() - t0:.1f}s")
+
+    stream = torch.cuda.current_stream()
+    n, M = g.n, g.m
+    degf = deg.to(torch.float64)
+
+    def run_step(layout, opts, prof=False):
+        """One step; returns (handle, timings dict).  Times come from HIP events
+        on the stream the library launches on."""
+        ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
+        e0, e1 = ev(), ev()
+        e0.record(stream)
+        h = lg.encode(g.row_offsets, g.col, n, layout=layout, **opts)
+        e1.record(stream)
+        bfs_ev = []
+        depth = torch.empty((1, n), dtype=torch.int32, device=dev)
+        parent = torch.empty((1, n), dtype=torch.int32, device=dev)
+        depths = []
+        for r in roots:
+            a, b = ev(), ev()
+            a.record(stream)
+            lg.bfs(h, [r], depth_out=depth, parent_out=parent)
+            b.record(stream)
+            bfs_ev.append((a, b))
+            depths.append((depth[0] >= 0))
+        p0, p1 = ev(), ev()
+        p0.record(stream)
+        pr = lg.pagerank(h, 0.85, args.pr_iters)
+        p1.record(stream)
+        torch.cuda.synchronize()
+        t = dict(encode=e0.elapsed_time(e1), bfs=[a.elapsed_time(b) for a, b in bfs_ev], pr=p0.elapsed_time(p1))
+        return h, t, depths, pr
+
+    # -- parity before timing: one root's BFS and the PageRank sum ----------
+    import oracle as orc  # the CPU oracle: test infrastructure, timed below as the CPU baseline
+
+    off_h = g.row_offsets.cpu().numpy()
+    col_h = g.col.cpu().numpy()
+
+    h, t, reached, pr = run_step("packed", enc)
+    d_gpu, p_gpu = lg.bfs(h, [roots[0]])
+    torch.cuda.synchronize()
+    tc = time.time()
+    d_o, p_o = orc.bfs(off_h, col_h, roots[0], relabeled=enc["relabel"])
+    t_orc_bfs = time.time() - tc
+    parity = bool(np.array_equal(d_gpu[0].cpu().numpy(), d_o) and np.array_equal(p_gpu[0].cpu().numpy(), p_o))
+    pr_sum = float(pr.double().sum())
+    parity = parity and abs(pr_sum - 1.0) <= 1e-5
+    log(f"[bench] parity root {roots[0]}: {'ok' if parity else 'FAILED'}; oracle BFS {t_orc_bfs:.1f}s; "
+        f"PR sum {pr_sum:.8f}")
+    if not parity:
+        print(json.dumps({"error": "parity check failed before timing"}))
+        sys.exit(1)
+
+    # Graph500 edge counts per root (undirected edges in the reached component)
+    edges_root = [float(degf[m].sum()) / 2.0 for m in reached]
+    pr_edges = args.pr_iters * (M / 2.0)
+    step_edges = sum(edges_root) + pr_edges
+    info = h.info()
+    h.free()
+
+    # -- timed steps: packed ------------------------------------------------
+    for _ in range(args.warmup):
+        h, _, _, _ = run_step("packed", enc)
+        h.free()
+    lg.prof_reset()
+    lg.prof_enable(True)
+    torch.cuda.synchronize()
+    t_begin = time.perf_counter()
+    timings = []
+    for _ in range(args.steps):
+        h, tt, _, _ = run_step("packed", enc)
+        timings.append(tt)
+        h.free()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_begin
+    lg.prof_enable(False)
+    kernel_ms = {}
+    for name in lg.prof_names():
+        base = name.lstrip("(").split("<")[0].rstrip(")")
+        kernel_ms.setdefault(base, [0, 0.0])
+    for base in kernel_ms:
+        c, ms = lg.prof_query(base)
+        kernel_ms[base] = [c, ms]
+    step_ms_gpu = [tt["encode"] + sum(tt["bfs"]) + tt["pr"] for tt in timings]
+    ms_per_step = wall * 1000.0 / args.steps
+    value = step_edges / (ms_per_step / 1000.0) / 1e9
+
+    bfs_ms = np.array([np.mean([tt["bfs"][i] for tt in timings]) for i in range(len(roots))])
+    bfs_teps = np.array(edges_root) / (bfs_ms / 1000.0)
+    bfs_gteps_hmean = float(len(bfs_teps) / np.sum(1.0 / bfs_teps)) / 1e9
+    pr_ms = float(np.mean([tt["pr"] for tt in timings]))
+    encode_ms = float(np.mean([tt["encode"] for tt in timings]))
+
+    if args.kernels:
+        tot = sum(v[1] for v in kernel_ms.values())
+        for k, (c, ms) in sorted(kernel_ms.items(), key=lambda kv: -kv[1][1]):
+            log(f"[kernel] {k:32s} launches={c:7d} total={ms:10.3f} ms ({100 * ms / max(tot, 1e-9):5.1f}%) "
+                f"avg={ms / max(c, 1) * 1000:9.2f} us")
+
+    # -- roofline of the PageRank pull kernel (algorithmic bytes per launch) --
+    # per launch: packed lists (U bits) + offset structure + width table
+    #             + one 4-byte contribution gathered per stored edge
+    #             + one 4-byte contribution written per vertex
+    struct_bytes = info["adj_bits"] / 8.0 + info["bytes_offsets"] + info["bytes_widths"]
+    pr_launch_bytes = struct_bytes + 4.0 * M + 4.0 * n
+    c_pull, ms_pull = kernel_ms.get("pr_pull_kernel", [0, 0.0])
+    pull_avg_ms = ms_pull / max(c_pull, 1)
+    pull_gbs = pr_launch_bytes / (pull_avg_ms / 1000.0) / 1e9 if c_pull else 0.0
+    dominant = max(kernel_ms.items(), key=lambda kv: kv[1][1])[0] if kernel_ms else None
+
+    # -- plain uint32 CSR on the same labeling ----------------------------------
+    plain = None
+    if not args.no_plain:
+        hp, _, _, _ = run_step("plain", dict(relabel=enc["relabel"]))
+        hp.free()
+        pt = []
+        tp0 = time.perf_counter()
+        for _ in range(args.steps):
+            hp, tt, _, _ = run_step("plain", dict(relabel=enc["relabel"]))
+            pt.append(tt)
+            hp.free()
+        torch.cuda.synchronize()
+        pwall = (time.perf_counter() - tp0) * 1000.0 / args.steps
+        pbfs_ms = np.array([np.mean([tt["bfs"][i] for tt in pt]) for i in range(len(roots))])
+        pteps = np.array(edges_root) / (pbfs_ms / 1000.0)
+        ppr_ms = float(np.mean([tt["pr"] for tt in pt]))
+        plain = dict(value=step_edges / (pwall / 1000.0) / 1e9, ms_per_step=pwall,
+                     bfs_gteps_hmean=float(len(pteps) / np.sum(1.0 / pteps)) / 1e9,
+                     pr_ms=ppr_ms, encode_ms=float(np.mean([tt["encode"] for tt in pt])))
+
+    # -- CPU baseline: the oracle on a bounded sample -----------------------
+    cpu = None
+    if not args.no_cpu_baseline:
+        # sample: the oracle's BFS from the parity root (already timed above) and
+        # one PageRank iteration over the whole graph
+        tc = time.time()
+        orc.pagerank(off_h, col_h, 0.85, 1)
+        t_orc_pr = time.time() - tc
+        cpu_edges = edges_root[0] + M / 2.0
+        cpu = {"value": cpu_edges / (t_orc_bfs + t_orc_pr) / 1e9, "unit": "GTEPS", "cores": 1, "kind": "oracle",
+               "sample": f"oracle BFS from 1 root ({t_orc_bfs:.1f}s, incl. degree relabel for parents) + "
+                         f"1 PageRank iteration ({t_orc_pr:.1f}s) on the same graph, single thread"}
+
+    out = {
+        "metric": "GTEPS & HBM GB/s, Log(Graph)-packed vs plain CSR on GPU; p99 query latency",
+        "value": round(value, 4),
+        "unit": "GTEPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32/f32",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "n": n, "stored_edges": M, "roots": len(roots),
+                   "pagerank_iters": args.pr_iters, "encoding": enc, "seed": 1, "edge_factor": 16},
+        "roofline": {"bound": "hbm", "kernel": "pr_pull_kernel", "achieved": round(pull_gbs, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(pull_gbs / HBM_PEAK_GBS, 4),
+                     "traffic": None, "bytes_per_launch": pr_launch_bytes, "avg_launch_ms": pull_avg_ms,
+                     "dominant_kernel": dominant},
+        "cpu_baseline": cpu,
+        "detail": {
+            "bfs_gteps_hmean": round(bfs_gteps_hmean, 3), "bfs_ms_mean": float(bfs_ms.mean()),
+            "pr_ms": pr_ms, "pr_gteps_directed": round(args.pr_iters * M / (pr_ms / 1000.0) / 1e9, 3),
+            "encode_ms": encode_ms, "encode_gedges_s": round(M / (encode_ms / 1000.0) / 1e9, 3),
+            "gpu_event_ms_per_step": float(np.mean(step_ms_gpu)),
+            "bytes": {k: info[k] for k in ("bytes_adj", "bytes_offsets", "bytes_widths", "bytes_perm")},
+            "plain_csr": plain,
+            "packed_over_plain": None if plain is None else {
+                "step": round(value / plain["value"], 4),
+                "bfs": round(bfs_gteps_hmean / plain["bfs_gteps_hmean"], 4),
+                "pr": round(plain["pr_ms"] / pr_ms, 4)},
+            "kernels_ms": {k: round(v[1] / args.steps, 3) for k, v in kernel_ms.items()},
+        },
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

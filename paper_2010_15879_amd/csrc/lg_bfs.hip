@@ -119,6 +119,7 @@ __global__ void td_prepare_kernel(Acc acc, const uint32_t *__restrict__ queue, u
     }
 }
 
+constexpr uint32_t kStrideBlocks = 4096;  // grid of the grid-stride sweep kernels
 constexpr int kTdThreads = 256;
 constexpr int kTdEdgesPerThread = 4;
 constexpr uint32_t kTdTile = kTdThreads * kTdEdgesPerThread;
@@ -144,6 +145,8 @@ __global__ __launch_bounds__(kTdThreads) void td_expand_kernel(
     __shared__ uint32_t s_w[kTdTile];
     __shared__ uint32_t s_v[kTdTile];
     __shared__ uint32_t s_range[2];
+    __shared__ uint32_t s_wsum[kTdThreads / kWave];
+    __shared__ unsigned long long s_base;
     const uint32_t lane = lane_id();
     for (uint64_t t = blockIdx.x; t * kTdTile < edges; t += gridDim.x) {
         const uint64_t e0 = t * kTdTile;
@@ -163,7 +166,14 @@ __global__ __launch_bounds__(kTdThreads) void td_expand_kernel(
             }
         }
         __syncthreads();
-        for (uint64_t e = e0 + threadIdx.x; e < e1; e += kTdThreads) {
+        // every thread decodes its (up to) kTdEdgesPerThread edges, keeps the
+        // vertices it claimed, and the block reserves queue space once
+        uint32_t won[kTdEdgesPerThread];
+        uint32_t nwon = 0;
+#pragma unroll
+        for (int r = 0; r < kTdEdgesPerThread; ++r) {
+            const uint64_t e = e0 + (uint64_t)r * kTdThreads + threadIdx.x;
+            if (e >= e1) continue;
             uint64_t base_e, start;
             uint32_t w, v;
             if (staged) {
@@ -174,21 +184,24 @@ __global__ __launch_bounds__(kTdThreads) void td_expand_kernel(
                 base_e = fscan[j]; start = fstart[j]; w = fw[j]; v = queue[j];
             }
             const uint32_t u = acc.get(start + (e - base_e) * Acc::step(w), Acc::mask(w));
-            bool win = false;
             if (!((visited[u >> 6] >> (u & 63)) & 1ull)) {
                 const int32_t old = atomicCAS(&depth[u], -1, next_depth);
                 if (kParent && (old == -1 || old == next_depth)) atomicMin(&parent[u], v);
-                win = old == -1;
-            }
-            const uint64_t m = __ballot(win);
-            if (m) {
-                const uint32_t leader = (uint32_t)__ffsll((long long)m) - 1;
-                unsigned long long base = 0;
-                if (lane == leader) base = atomicAdd(tail, (unsigned long long)__popcll(m));
-                base = __shfl(base, leader, kWave);
-                if (win) queue_out[base + popc_below(m)] = u;
+                if (old == -1) won[nwon++] = u;
             }
         }
+        // block exclusive scan of the claim counts, one atomic per tile
+        const uint32_t incl = wave_incl_scan(nwon);
+        if (lane == kWave - 1) s_wsum[threadIdx.x / kWave] = incl;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint32_t tot = 0;
+            for (int w = 0; w < kTdThreads / kWave; ++w) { const uint32_t c = s_wsum[w]; s_wsum[w] = tot; tot += c; }
+            s_base = tot ? atomicAdd(tail, (unsigned long long)tot) : 0ull;
+        }
+        __syncthreads();
+        unsigned long long pos = s_base + s_wsum[threadIdx.x / kWave] + (incl - nwon);
+        for (uint32_t i = 0; i < nwon; ++i) queue_out[pos + i] = won[i];
         __syncthreads();
     }
 }
@@ -203,8 +216,12 @@ __global__ void mark_queue_kernel(const uint32_t *__restrict__ queue, const unsi
     }
 }
 
+// Light vertices (degree <= threshold): lane per vertex, the list decoded in
+// ascending order four elements at a time, stopping at the first frontier
+// neighbor.  Heavy vertices are skipped here (bu_heavy_kernel ran first and
+// already set their bits in next/visited).
 template <class Acc, bool kParent>
-__global__ void bu_step_kernel(Acc acc, uint32_t n, const uint64_t *__restrict__ curr,
+__global__ void bu_step_kernel(Acc acc, uint32_t n, uint32_t threshold, const uint64_t *__restrict__ curr,
                                uint64_t *__restrict__ visited, uint64_t *__restrict__ next,
                                int32_t *__restrict__ depth, uint32_t *__restrict__ parent, int32_t next_depth,
                                unsigned long long *__restrict__ awake) {
@@ -212,18 +229,27 @@ __global__ void bu_step_kernel(Acc acc, uint32_t n, const uint64_t *__restrict__
     const uint64_t words = ((uint64_t)n + 63) / 64;
     const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
     const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) / kWave;
+    unsigned long long woke = 0;
     for (uint64_t q = wave; q < words; q += nwaves) {
         const uint64_t vis = visited[q];
+        if (vis == ~0ull) continue;
+        const VInfo vi = wave_info(acc, q * 64, n);
         const uint64_t v = q * 64 + lane;
         bool found = false;
         uint32_t par = 0;
-        if (v < n && !((vis >> lane) & 1ull)) {
-            const VInfo vi = acc.info((uint32_t)v);
-            uint64_t pos = vi.start;
+        if (v < n && !((vis >> lane) & 1ull) && vi.deg <= threshold) {
             const uint32_t st = Acc::step(vi.w), mk = Acc::mask(vi.w);
-            for (uint32_t i = 0; i < vi.deg; ++i, pos += st) {
-                const uint32_t u = acc.get(pos, mk);
-                if ((curr[u >> 6] >> (u & 63)) & 1ull) { found = true; par = u; break; }
+            for (uint32_t i = 0; i < vi.deg && !found; i += 4) {
+                uint32_t u[4];
+                bool f[4];
+#pragma unroll
+                for (int b = 0; b < 4; ++b) u[b] = i + b < vi.deg ? acc.get(vi.start + (uint64_t)(i + b) * st, mk) : 0u;
+#pragma unroll
+                for (int b = 0; b < 4; ++b) f[b] = i + b < vi.deg && ((curr[u[b] >> 6] >> (u[b] & 63)) & 1ull);
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    if (f[b] && !found) { found = true; par = u[b]; }
+                }
             }
         }
         const uint64_t fm = __ballot(found);
@@ -231,14 +257,77 @@ __global__ void bu_step_kernel(Acc acc, uint32_t n, const uint64_t *__restrict__
             depth[v] = next_depth;
             if (kParent) parent[v] = par;
         }
-        if (lane == 0) {
-            next[q] = fm;
-            if (fm) {
-                visited[q] = vis | fm;
-                atomicAdd(awake, (unsigned long long)__popcll(fm));
+        if (lane == 0 && fm) {
+            next[q] |= fm;
+            visited[q] |= fm;
+            woke += (unsigned long long)__popcll(fm);
+        }
+    }
+    woke = block_sum_u64(woke);
+    if (threadIdx.x == 0 && woke) atomicAdd(awake, woke);
+}
+
+// Heavy vertices: one wave per segment of kHeavySeg edges, 64 neighbors per
+// probe.  Lists ascend, so a segment's first frontier neighbor is its
+// smallest, and the smallest over all segments of v is v's parent
+// (atomicMin).  "Not visited before this level" is read from depth (-1 or
+// the level being built), never from the visited bitmap, which this kernel
+// updates.  A segment whose first label exceeds the best parent already
+// found skips its scan.
+template <class Acc, bool kParent>
+__global__ void bu_heavy_kernel(Acc acc, const uint32_t *__restrict__ heavy, uint64_t n_seg,
+                                const uint32_t *__restrict__ seg_map, const uint64_t *__restrict__ seg_off,
+                                const uint64_t *__restrict__ hstart, const uint32_t *__restrict__ hdeg,
+                                const uint32_t *__restrict__ hw, const uint64_t *__restrict__ curr,
+                                unsigned long long *__restrict__ visited, unsigned long long *__restrict__ next,
+                                int32_t *__restrict__ depth, uint32_t *__restrict__ parent, int32_t next_depth,
+                                unsigned long long *__restrict__ awake) {
+    const uint32_t lane = lane_id();
+    const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) / kWave;
+    unsigned long long woke = 0;
+    for (uint64_t k = wave; k < n_seg; k += nwaves) {
+        const uint32_t h = seg_map[k];
+        const uint32_t v = heavy[h];
+        const int32_t dv = depth[v];
+        if (dv != -1 && dv != next_depth) continue;        // reached at an earlier level
+        if (!kParent && dv == next_depth) continue;        // any frontier neighbor will do
+        const uint32_t w = hw[h];
+        const uint32_t st = Acc::step(w), mk = Acc::mask(w);
+        const uint64_t start = hstart[h];
+        const uint64_t e0 = (k - seg_off[h]) * kHeavySeg;
+        const uint64_t d = hdeg[h];
+        const uint64_t e1 = e0 + kHeavySeg < d ? e0 + kHeavySeg : d;
+        if (kParent && dv == next_depth) {
+            const uint32_t first = acc.get(start + e0 * st, mk);
+            if (parent[v] < first) continue;
+        }
+        for (uint64_t base = e0; base < e1; base += kWave) {
+            const uint64_t i = base + lane;
+            uint32_t u = 0;
+            bool hit = false;
+            if (i < e1) {
+                u = acc.get(start + i * st, mk);
+                hit = (curr[u >> 6] >> (u & 63)) & 1ull;
+            }
+            const uint64_t m = __ballot(hit);
+            if (m) {
+                const uint32_t first = (uint32_t)__ffsll((long long)m) - 1;
+                const uint32_t par = __shfl(u, first, kWave);
+                if (lane == 0) {
+                    if (kParent) atomicMin(&parent[v], par);
+                    if (atomicCAS(&depth[v], -1, next_depth) == -1) {
+                        atomicOr(&next[v >> 6], 1ull << (v & 63));
+                        atomicOr(&visited[v >> 6], 1ull << (v & 63));
+                        ++woke;
+                    }
+                }
+                break;
             }
         }
     }
+    woke = block_sum_u64(woke);
+    if (threadIdx.x == 0 && woke) atomicAdd(awake, woke);
 }
 
 // frontier bitmap -> queue
@@ -356,13 +445,31 @@ static lg_status bfs_one(lg_graph *g, Acc acc, uint32_t root_label, int32_t *dep
             ++level;
         } else {
             LG_TRY(fill_u64((uint64_t *)ctr + 1, 0, 1, s));
-            const uint32_t grid = grid_for(words * kWave, 256, 1u << 16);
+            LG_TRY(fill_u64(next, 0, words, s));
+            if (g->n_seg) {
+                const uint32_t hg = grid_for(g->n_seg * kWave, 256, kStrideBlocks);
+                const uint32_t *hv = g->heavy.as<uint32_t>();
+                const uint32_t *sm = g->seg_map.as<uint32_t>();
+                const uint64_t *so = g->seg_off.as<uint64_t>();
+                const uint64_t *hs = g->hstart.as<uint64_t>();
+                const uint32_t *hd = g->hdeg.as<uint32_t>(), *hwd = g->hw.as<uint32_t>();
+                if (parent)
+                    LG_LAUNCH((bu_heavy_kernel<Acc, true>), hg, 256, 0, s, acc, hv, g->n_seg, sm, so, hs, hd, hwd,
+                              curr, (unsigned long long *)visited, (unsigned long long *)next, depth, parent,
+                              level + 1, ctr + 1);
+                else
+                    LG_LAUNCH((bu_heavy_kernel<Acc, false>), hg, 256, 0, s, acc, hv, g->n_seg, sm, so, hs, hd, hwd,
+                              curr, (unsigned long long *)visited, (unsigned long long *)next, depth, parent,
+                              level + 1, ctr + 1);
+                LG_CHECK_LAUNCH();
+            }
+            const uint32_t grid = grid_for(words * kWave, 256, kStrideBlocks);
             if (parent)
-                LG_LAUNCH((bu_step_kernel<Acc, true>), grid, 256, 0, s, acc, n, curr, visited, next, depth, parent,
-                          level + 1, ctr + 1);
+                LG_LAUNCH((bu_step_kernel<Acc, true>), grid, 256, 0, s, acc, n, g->heavy_threshold, curr, visited,
+                          next, depth, parent, level + 1, ctr + 1);
             else
-                LG_LAUNCH((bu_step_kernel<Acc, false>), grid, 256, 0, s, acc, n, curr, visited, next, depth, parent,
-                          level + 1, ctr + 1);
+                LG_LAUNCH((bu_step_kernel<Acc, false>), grid, 256, 0, s, acc, n, g->heavy_threshold, curr, visited,
+                          next, depth, parent, level + 1, ctr + 1);
             LG_CHECK_LAUNCH();
             LG_CHECK_HIP(hipMemcpyAsync(w.host, ctr + 1, 8, hipMemcpyDeviceToHost, s));
             LG_CHECK_HIP(hipStreamSynchronize(s));
@@ -396,6 +503,7 @@ extern "C" lg_status lg_bfs(const lg_graph *gc, const uint32_t *roots, uint32_t 
         if (roots[i] >= g->n) { set_error("lg_bfs: root %u out of range", roots[i]); return LG_ERR_INVALID; }
     if (r == 0) return LG_OK;
     LG_TRY(bfs_workspace(g, parent != nullptr));
+    LG_TRY(ensure_heavy_segments(g, stream));
     const bool rel = g->relabel == LG_RELABEL_DEGREE;
     uint32_t *inv_host = nullptr;
     (void)inv_host;

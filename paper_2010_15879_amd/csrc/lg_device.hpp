@@ -216,6 +216,47 @@ struct PlainAcc {
     __device__ __forceinline__ static uint32_t mask(uint32_t) { return 0xFFFFFFFFu; }
 };
 
+// VInfo of vertex v0 + lane for the 64 lanes of a wave: every lane decodes
+// one offset value and takes the next one from its neighbor lane, so a sweep
+// over consecutive vertices decodes each offset once.  Lanes past n get an
+// empty list.
+template <class Acc>
+__device__ __forceinline__ VInfo wave_info(const Acc &acc, uint64_t v0, uint32_t n) {
+    const uint32_t lane = lane_id();
+    const uint64_t v = v0 + lane;
+    const uint64_t o0 = acc.offset_value((uint32_t)(v < n ? v : n));
+    const uint64_t end = acc.offset_value((uint32_t)(v0 + kWave < n ? v0 + kWave : n));
+    uint64_t o1 = __shfl_down(o0, 1, kWave);
+    if (lane == kWave - 1) o1 = end;
+    if (v >= n) return VInfo{0, 0, 0};
+    return acc.make((uint32_t)v, o0, o1);
+}
+
+// Sum of one value per thread over a block of up to 1024 threads (result
+// valid in thread 0).  Every thread of the block must call it.
+__device__ __forceinline__ unsigned long long block_sum_u64(unsigned long long x) {
+    __shared__ unsigned long long s_part[16];
+    x = wave_sum(x);
+    const uint32_t wv = threadIdx.x / kWave;
+    if (lane_id() == 0) s_part[wv] = x;
+    __syncthreads();
+    unsigned long long t = 0;
+    if (threadIdx.x == 0)
+        for (uint32_t w = 0; w < (blockDim.x + kWave - 1) / kWave; ++w) t += s_part[w];
+    __syncthreads();
+    return t;
+}
+
+// index of v in the ascending heavy list (v must be in it)
+__device__ __forceinline__ uint32_t heavy_index(const uint32_t *__restrict__ heavy, uint32_t n_heavy, uint32_t v) {
+    uint32_t lo = 0, hi = n_heavy - 1;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (heavy[mid] < v) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
 // Call `fn(acc)` with the accessor matching the graph's layout.
 template <class Fn>
 lg_status dispatch_acc(const lg_graph *g, Fn &&fn) {

@@ -84,7 +84,12 @@ __global__ void degree_kernel(uint32_t n, const uint64_t *__restrict__ off, uint
         mx = o > mx ? o : mx;
     }
     iso = wave_sum(iso);
-    if (lane_id() == 0) {
+    __shared__ uint32_t s_mx[4], s_iso[4];  // blockDim = 256: four waves
+    const uint32_t wv = threadIdx.x / kWave;
+    if (lane_id() == 0) { s_mx[wv] = mx; s_iso[wv] = iso; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < 4; ++w) { mx = s_mx[w] > mx ? s_mx[w] : mx; iso += s_iso[w]; }
         atomicMax(&stats[0], mx);
         if (iso) atomicAdd(&stats[1], iso);
     }
@@ -301,6 +306,24 @@ __global__ void offsets_to_u32_kernel(uint64_t count, const uint64_t *__restrict
 }
 
 // ---------------------------------------------------------------------------
+// heavy vertices: degree above the threshold, listed in ascending order
+// ---------------------------------------------------------------------------
+
+__global__ void heavy_flag_kernel(uint32_t n, const uint64_t *__restrict__ off, uint32_t threshold,
+                                  uint32_t *__restrict__ flag) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride)
+        flag[v] = (off[v + 1] - off[v]) > threshold ? 1u : 0u;
+}
+
+__global__ void heavy_scatter_kernel(uint32_t n, const uint32_t *__restrict__ flag, const uint64_t *__restrict__ pos,
+                                     uint32_t *__restrict__ heavy) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride)
+        if (flag[v]) heavy[pos[v]] = (uint32_t)v;
+}
+
+// ---------------------------------------------------------------------------
 // host orchestration
 // ---------------------------------------------------------------------------
 
@@ -385,7 +408,7 @@ static lg_status encode_impl(uint32_t n, uint64_t m, const uint64_t *row_offsets
         return LG_ERR_INVALID;
     }
     LG_TRY(deg.alloc((uint64_t)n * 4));
-    LG_LAUNCH(degree_kernel, grid1(n), 256, 0, s, n, row_offsets, deg.as<uint32_t>(), stats.as<uint32_t>());
+    LG_LAUNCH(degree_kernel, grid_for(n, 256, 4096), 256, 0, s, n, row_offsets, deg.as<uint32_t>(), stats.as<uint32_t>());
     LG_CHECK_LAUNCH();
     uint32_t st[2];
     LG_CHECK_HIP(hipMemcpyAsync(st, stats.p, 8, hipMemcpyDeviceToHost, s));
@@ -433,6 +456,25 @@ static lg_status encode_impl(uint32_t n, uint64_t m, const uint64_t *row_offsets
         LG_CHECK_HIP(hipStreamSynchronize(s));
         cur_off = off_new.as<uint64_t>();
         cur_col = col_new.as<uint32_t>();
+    }
+
+    // -- heavy vertex list (shared by the traversal kernels) -------------
+    {
+        DevBuf flag, pos;
+        LG_TRY(flag.alloc((uint64_t)n * 4));
+        LG_TRY(pos.alloc(((uint64_t)n + 1) * 8));
+        LG_LAUNCH(heavy_flag_kernel, grid1(n), 256, 0, s, n, cur_off, g->heavy_threshold, flag.as<uint32_t>());
+        LG_CHECK_LAUNCH();
+        LG_TRY(exclusive_scan_u32(flag.as<uint32_t>(), pos.as<uint64_t>(), n, tmp, s));
+        uint64_t nh = 0;
+        LG_CHECK_HIP(hipMemcpyAsync(&nh, pos.as<uint64_t>() + n, 8, hipMemcpyDeviceToHost, s));
+        LG_CHECK_HIP(hipStreamSynchronize(s));
+        g->n_heavy = (uint32_t)nh;
+        LG_TRY(g->heavy.alloc((nh ? nh : 1) * 4));
+        LG_LAUNCH(heavy_scatter_kernel, grid1(n), 256, 0, s, n, flag.as<uint32_t>(), pos.as<uint64_t>(),
+                  g->heavy.as<uint32_t>());
+        LG_CHECK_LAUNCH();
+        LG_CHECK_HIP(hipStreamSynchronize(s));
     }
 
     // -- plain CSR baseline ----------------------------------------------

@@ -126,6 +126,18 @@ struct lg_graph {
     // relabeling: perm[new] = old, inv[old] = new
     lg::DevBuf perm, inv;
 
+    // vertices whose degree exceeds heavy_threshold, ascending: the traversal
+    // kernels give each of them a wave (bottom-up BFS) or several waves
+    // (PageRank) instead of one lane
+    lg::DevBuf heavy;
+    uint32_t n_heavy = 0;
+    uint32_t heavy_threshold = 64;
+    // per heavy vertex: first bit/element, degree, width; its list cut into
+    // segments of kHeavySeg edges: seg_off[h] .. seg_off[h+1], seg_map[k] = h
+    lg::DevBuf hstart, hdeg, hw, seg_off, seg_map;
+    uint64_t n_seg = 0;
+    bool segs_built = false;
+
     // lazily allocated workspaces
     lg::BfsWork *bfs = nullptr;
     lg::PrWork *pr = nullptr;
@@ -194,6 +206,11 @@ inline uint32_t grid_for(uint64_t count, uint64_t per_block, uint64_t cap = 1u <
 }
 
 inline uint32_t bitlen_u64(uint64_t x) { return x ? 64u - (uint32_t)__builtin_clzll(x) : 0u; }
+
+constexpr uint32_t kHeavySeg = 1024;  // edges per heavy-vertex segment
+
+// Build the heavy-vertex segment table of g (once); defined in lg_heavy.hip.
+lg_status ensure_heavy_segments(lg_graph *g, hipStream_t s);
 
 lg_status bfs_free(lg_graph *g);
 lg_status pr_free(lg_graph *g);

@@ -1,31 +1,45 @@
 // lg_pagerank: pull PageRank without atomics on global memory (PR of
 // section "Considered Algorithms"), FP32 storage, decoding every list inside
-// the pull kernel.
+// the pull kernels.
 //
 //   PR_0 = 1/n
 //   PR_{t+1}(v) = (1-a)/n + a (sum_{u in N_v} PR_t(u)/d_u + D_t/n)
 //
-// Each iteration is one kernel.  It reads contrib_t[u] = PR_t(u)/d_u and
-// writes contrib_{t+1}[v]; the final iteration also writes the scores.  All
-// vertices without edges hold the same value, b_t = (1-a)/n + a D_t/n, so the
-// dangling mass follows D_{t+1} = z b_t (z = number of such vertices) and is
-// passed to the kernel as a scalar instead of being reduced over the graph.
+// An iteration reads contrib_t[u] = PR_t(u)/d_u and writes contrib_{t+1};
+// the final one also writes the scores.  All vertices without edges hold the
+// same value b_t = (1-a)/n + a D_t/n, so the dangling mass follows
+// D_{t+1} = z b_t (z = number of such vertices) and is passed to the kernels
+// as a scalar instead of being reduced over the graph.
 //
-// Work split: a wave owns 64 consecutive vertices.  It scans their degrees,
-// then its lanes walk the chunk's edges 64 at a time (consecutive lanes read
-// consecutive packed elements, so the stream is coalesced).  A lane keeps a
-// running sum while its edges belong to one vertex and adds it to that
-// vertex's LDS accumulator when the owner changes; the accumulation order is
-// fixed by the data, so results are reproducible run to run.
+// Work split (bounded work per wave, whatever the degree distribution):
+//   heavy vertices (degree > threshold) are cut into segments of kSeg edges;
+//     one wave sums one segment (pr_heavy_kernel)
+//   light vertices are taken 64 consecutive vertices per wave; the wave's
+//     lanes walk the chunk's (at most 64 * threshold) edges 64 at a time, so
+//     consecutive lanes decode consecutive packed elements (coalesced), and a
+//     lane's running sum is flushed to its vertex's LDS accumulator when the
+//     owner changes (pr_pull_kernel, which also finalizes every vertex and
+//     adds a heavy vertex's segment sums in segment order)
+// All summation orders are fixed by the data: results repeat bit for bit.
 #include "lg_device.hpp"
 
 namespace lg {
 
+constexpr uint32_t kSeg = kHeavySeg; // edges per heavy segment
+constexpr int kPrThreads = 256;
+constexpr int kPrWaves = kPrThreads / kWave;
+constexpr int kBatch = 4;            // independent edges in flight per lane
+
 struct PrWork {
-    DevBuf ca, cb;  // contrib ping-pong
+    DevBuf ca, cb;                   // contrib ping-pong
+    DevBuf seg_sum;                  // one partial sum per heavy segment
 };
 
-uint64_t pr_bytes(const lg_graph *g) { return g->pr ? g->pr->ca.bytes + g->pr->cb.bytes : 0; }
+uint64_t pr_bytes(const lg_graph *g) {
+    if (!g->pr) return 0;
+    const PrWork *w = g->pr;
+    return w->ca.bytes + w->cb.bytes + w->seg_sum.bytes;
+}
 
 lg_status pr_free(lg_graph *g) {
     delete g->pr;
@@ -33,24 +47,59 @@ lg_status pr_free(lg_graph *g) {
     return LG_OK;
 }
 
-constexpr int kPrThreads = 256;
-constexpr int kPrWaves = kPrThreads / kWave;
-
 template <class Acc>
 __global__ void pr_init_kernel(Acc acc, uint32_t n, double inv_n, float *__restrict__ contrib) {
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) {
-        const uint32_t d = acc.info((uint32_t)v).deg;
-        contrib[v] = d ? (float)(inv_n / (double)d) : 0.0f;
+    for (uint64_t v0 = (uint64_t)blockIdx.x * blockDim.x; v0 < n; v0 += stride) {
+        const uint64_t w0 = v0 + (threadIdx.x & ~(uint64_t)(kWave - 1));
+        const VInfo vi = wave_info(acc, w0, n);
+        const uint64_t v = w0 + lane_id();
+        if (v < n) contrib[v] = vi.deg ? (float)(inv_n / (double)vi.deg) : 0.0f;
+    }
+}
+
+// one wave per segment of a heavy vertex
+template <class Acc>
+__global__ __launch_bounds__(kPrThreads) void pr_heavy_kernel(
+    Acc acc, uint64_t n_seg, const uint32_t *__restrict__ seg_map, const uint64_t *__restrict__ seg_off,
+    const uint64_t *__restrict__ hstart, const uint32_t *__restrict__ hdeg, const uint32_t *__restrict__ hw,
+    const float *__restrict__ cin, float *__restrict__ seg_sum) {
+    const uint32_t lane = lane_id();
+    const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) / kWave;
+    for (uint64_t k = wave; k < n_seg; k += nwaves) {
+        const uint32_t h = seg_map[k];
+        const uint64_t e0 = (k - seg_off[h]) * kSeg;
+        const uint64_t d = hdeg[h];
+        const uint64_t e1 = e0 + kSeg < d ? e0 + kSeg : d;
+        const uint32_t w = hw[h];
+        const uint64_t start = hstart[h];
+        const uint32_t st = Acc::step(w), mk = Acc::mask(w);
+        float sum = 0.0f;
+        for (uint64_t e = e0 + lane; e < e1; e += kWave * kBatch) {
+            uint32_t u[kBatch];
+#pragma unroll
+            for (int b = 0; b < kBatch; ++b) {
+                const uint64_t eb = e + (uint64_t)b * kWave;
+                u[b] = eb < e1 ? acc.get(start + eb * st, mk) : 0xFFFFFFFFu;
+            }
+            float x[kBatch];
+#pragma unroll
+            for (int b = 0; b < kBatch; ++b) x[b] = u[b] != 0xFFFFFFFFu ? cin[u[b]] : 0.0f;
+#pragma unroll
+            for (int b = 0; b < kBatch; ++b) sum += x[b];
+        }
+        sum = wave_sum(sum);
+        if (lane == 0) seg_sum[k] = sum;
     }
 }
 
 template <class Acc>
-__global__ __launch_bounds__(kPrThreads) void pr_pull_kernel(Acc acc, uint32_t n, const float *__restrict__ cin,
-                                                             float *__restrict__ cout, float base, float alpha,
-                                                             float *__restrict__ scores,
-                                                             const uint32_t *__restrict__ perm) {
-    __shared__ uint64_t s_excl[kPrWaves][kWave + 1];
+__global__ __launch_bounds__(kPrThreads) void pr_pull_kernel(
+    Acc acc, uint32_t n, uint32_t threshold, const float *__restrict__ cin, float *__restrict__ cout, float base,
+    float alpha, const uint32_t *__restrict__ heavy, uint32_t n_heavy, const uint64_t *__restrict__ seg_off,
+    const float *__restrict__ seg_sum, float *__restrict__ scores, const uint32_t *__restrict__ perm) {
+    __shared__ uint32_t s_excl[kPrWaves][kWave + 1];
     __shared__ uint64_t s_start[kPrWaves][kWave];
     __shared__ uint32_t s_w[kPrWaves][kWave];
     __shared__ float s_acc[kPrWaves][kWave];
@@ -58,47 +107,61 @@ __global__ __launch_bounds__(kPrThreads) void pr_pull_kernel(Acc acc, uint32_t n
     const uint32_t wv = threadIdx.x / kWave;
     const uint64_t nchunks = ((uint64_t)n + kPrThreads - 1) / kPrThreads;
     for (uint64_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
-        const uint64_t v = c * kPrThreads + threadIdx.x;
-        VInfo vi{0, 0, 0};
-        if (v < n) vi = acc.info((uint32_t)v);
-        const uint64_t d = vi.deg;
-        const uint64_t incl = wave_incl_scan(d);
-        const uint64_t total = __shfl(incl, kWave - 1, kWave);
+        const uint64_t w0 = c * kPrThreads + (uint64_t)wv * kWave;
+        const uint64_t v = w0 + lane;
+        const VInfo vi = wave_info(acc, w0, n);
+        const bool is_heavy = vi.deg > threshold;
+        const uint32_t d = is_heavy ? 0u : vi.deg;  // heavy lists are summed by segments
+        const uint32_t incl = wave_incl_scan(d);
+        const uint32_t total = __shfl(incl, kWave - 1, kWave);
         s_excl[wv][lane] = incl - d;
         if (lane == kWave - 1) s_excl[wv][kWave] = total;
         s_start[wv][lane] = vi.start;
         s_w[wv][lane] = vi.w;
         s_acc[wv][lane] = 0.0f;
         __syncthreads();
-        if (total) {
-            uint32_t j = 0;
-            uint64_t nb = 0;  // first edge index past owner j
-            uint64_t pos = 0, adv = 0;
-            uint32_t mk = 0;
-            float part = 0.0f;
-            uint32_t owner = 0xFFFFFFFFu;
-            for (uint64_t e = lane; e < total; e += kWave) {
-                if (e >= nb || owner == 0xFFFFFFFFu) {
-                    while (s_excl[wv][j + 1] <= e) ++j;
-                    if (owner != 0xFFFFFFFFu) atomicAdd(&s_acc[wv][owner], part);
-                    owner = j;
-                    part = 0.0f;
-                    nb = s_excl[wv][j + 1];
+        uint32_t j = 0, owner = 0xFFFFFFFFu;
+        float part = 0.0f;
+        for (uint32_t e = lane; e < total; e += kWave * kBatch) {
+            uint32_t u[kBatch], own[kBatch];
+#pragma unroll
+            for (int b = 0; b < kBatch; ++b) {
+                const uint32_t eb = e + (uint32_t)b * kWave;
+                own[b] = 0xFFFFFFFFu;
+                u[b] = 0;
+                if (eb < total) {
+                    while (s_excl[wv][j + 1] <= eb) ++j;
                     const uint32_t w = s_w[wv][j];
-                    pos = s_start[wv][j] + (e - s_excl[wv][j]) * Acc::step(w);
-                    adv = (uint64_t)kWave * Acc::step(w);
-                    mk = Acc::mask(w);
+                    u[b] = acc.get(s_start[wv][j] + (uint64_t)(eb - s_excl[wv][j]) * Acc::step(w), Acc::mask(w));
+                    own[b] = j;
                 }
-                const uint32_t u = acc.get(pos, mk);
-                part += cin[u];
-                pos += adv;
             }
-            if (owner != 0xFFFFFFFFu) atomicAdd(&s_acc[wv][owner], part);
+            float x[kBatch];
+#pragma unroll
+            for (int b = 0; b < kBatch; ++b) x[b] = own[b] != 0xFFFFFFFFu ? cin[u[b]] : 0.0f;
+#pragma unroll
+            for (int b = 0; b < kBatch; ++b) {
+                if (own[b] == 0xFFFFFFFFu) continue;
+                if (own[b] != owner) {
+                    if (owner != 0xFFFFFFFFu) atomicAdd(&s_acc[wv][owner], part);
+                    owner = own[b];
+                    part = 0.0f;
+                }
+                part += x[b];
+            }
         }
+        if (owner != 0xFFFFFFFFu) atomicAdd(&s_acc[wv][owner], part);
         __syncthreads();
         if (v < n) {
-            const float pr = base + alpha * s_acc[wv][lane];
-            cout[v] = d ? pr / (float)d : 0.0f;
+            float sum = s_acc[wv][lane];
+            if (is_heavy) {
+                const uint32_t h = heavy_index(heavy, n_heavy, (uint32_t)v);
+                double hs = 0.0;
+                for (uint64_t k = seg_off[h]; k < seg_off[h + 1]; ++k) hs += seg_sum[k];
+                sum = (float)hs;
+            }
+            const float pr = base + alpha * sum;
+            cout[v] = vi.deg ? pr / (float)vi.deg : 0.0f;
             if (scores) scores[perm ? perm[v] : v] = pr;
         }
         __syncthreads();
@@ -131,21 +194,33 @@ extern "C" lg_status lg_pagerank(const lg_graph *gc, float damping, uint32_t ite
     }
     LG_TRY(g->pr->ca.ensure((uint64_t)n * 4));
     LG_TRY(g->pr->cb.ensure((uint64_t)n * 4));
+    LG_TRY(ensure_heavy_segments(g, stream));
+    LG_TRY(g->pr->seg_sum.ensure((g->n_seg ? g->n_seg : 1) * 4));
     const uint32_t *perm = g->relabel == LG_RELABEL_DEGREE ? g->perm.as<uint32_t>() : nullptr;
     const double a = damping;
     const double z = g->isolated;
     return dispatch_acc(g, [&](auto acc) -> lg_status {
         using Acc = decltype(acc);
-        float *cin = g->pr->ca.as<float>(), *cout = g->pr->cb.as<float>();
+        PrWork &w = *g->pr;
+        float *cin = w.ca.as<float>(), *cout = w.cb.as<float>();
         LG_LAUNCH(pr_init_kernel<Acc>, grid_for(n, 256, 1u << 16), 256, 0, stream, acc, n, 1.0 / nd, cin);
         LG_CHECK_LAUNCH();
         double D = z / nd;  // D_0: rank on vertices without edges
         const uint32_t grid = grid_for(n, kPrThreads, 1u << 20);
+        const uint32_t hgrid = grid_for(g->n_seg * kWave, 256, 1u << 20);
         for (uint32_t t = 0; t < iters; ++t) {
             const double b = (1.0 - a) / nd + a * D / nd;
             const bool last = t + 1 == iters;
-            LG_LAUNCH(pr_pull_kernel<Acc>, grid, kPrThreads, 0, stream, acc, n, (const float *)cin, cout, (float)b,
-                      (float)a, last ? scores : (float *)nullptr, last ? perm : (const uint32_t *)nullptr);
+            if (g->n_seg) {
+                LG_LAUNCH(pr_heavy_kernel<Acc>, hgrid, 256, 0, stream, acc, g->n_seg, (const uint32_t *)g->seg_map.p,
+                          (const uint64_t *)g->seg_off.p, (const uint64_t *)g->hstart.p, (const uint32_t *)g->hdeg.p,
+                          (const uint32_t *)g->hw.p, (const float *)cin, w.seg_sum.as<float>());
+                LG_CHECK_LAUNCH();
+            }
+            LG_LAUNCH(pr_pull_kernel<Acc>, grid, kPrThreads, 0, stream, acc, n, g->heavy_threshold, (const float *)cin,
+                      cout, (float)b, (float)a, (const uint32_t *)g->heavy.p, g->n_heavy,
+                      (const uint64_t *)g->seg_off.p, (const float *)w.seg_sum.p, last ? scores : (float *)nullptr,
+                      last ? perm : (const uint32_t *)nullptr);
             LG_CHECK_LAUNCH();
             D = z * b;
             float *tmp = cin; cin = cout; cout = tmp;

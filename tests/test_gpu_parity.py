@@ -42,6 +42,11 @@ def _tiny_graphs():
     G["clique12"] = gg.csr_from_edges(12, [(i, j) for i in range(12) for j in range(i + 1, 12)])
     G["only0"] = gg.csr_from_edges(5, [(0, 4), (1, 2)])
     G["hubtail"] = gg.csr_from_edges(70, [(69, i) for i in range(69)] + [(3, 4)])
+    # degrees 64 and 65 straddle the heavy-vertex threshold of the traversal kernels
+    G["deg64_65"] = gg.csr_from_edges(200, [(0, i) for i in range(2, 66)] + [(1, i) for i in range(100, 165)]
+                                      + [(2, 100)])
+    # a hub whose list spans several PageRank segments (1024 edges each)
+    G["bigstar"] = gg.csr_from_edges(3001, [(0, i) for i in range(1, 3001)] + [(5, 6), (6, 7)])
     for n in [63, 64, 65, 127, 129]:
         G[f"rand{n}"] = gg.random_graph(n, 0.07, seed=n)
     G["kron12"] = gg.kronecker(12, 16, seed=1)
@@ -115,7 +120,8 @@ def test_encoding_bit_exact(lgmod, name, e):
 
 
 @pytest.mark.parametrize("e", ENCODINGS, ids=enc_id)
-@pytest.mark.parametrize("name", ["star33", "hubtail", "rand65", "kron12", "er12", "single", "isolated7"])
+@pytest.mark.parametrize("name", ["star33", "hubtail", "rand65", "kron12", "er12", "single", "isolated7",
+                                  "bigstar"])
 def test_decode_neighbors(lgmod, name, e):
     g = GRAPHS[name]
     print(f"[decode] {name} {e}", flush=True)
@@ -145,7 +151,7 @@ def test_decode_neighbors(lgmod, name, e):
 @pytest.mark.parametrize("mode", ["do", "td", "bu"])
 @pytest.mark.parametrize("e", ENCODINGS, ids=enc_id)
 @pytest.mark.parametrize("name", ["path9", "star33", "clique12", "only0", "hubtail", "rand64", "rand129",
-                                  "kron12", "er12", "kron10ef4", "single", "edge"])
+                                  "kron12", "er12", "kron10ef4", "single", "edge", "deg64_65", "bigstar"])
 def test_bfs_bit_exact(lgmod, name, e, mode):
     g = GRAPHS[name]
     off, col = g.numpy()
@@ -195,7 +201,7 @@ def test_bfs_without_parents(lgmod):
 
 @pytest.mark.parametrize("e", ENCODINGS, ids=enc_id)
 @pytest.mark.parametrize("name", ["star33", "clique12", "isolated7", "single", "hubtail", "rand127", "kron12",
-                                  "er12"])
+                                  "er12", "deg64_65", "bigstar"])
 def test_pagerank_l1(lgmod, name, e):
     g = GRAPHS[name]
     off, col = g.numpy()
