@@ -200,6 +200,9 @@ def main():
         hp, _, _, _ = run_step("plain", dict(relabel=enc["relabel"]))
         hp.free()
         pt = []
+        if args.kernels:
+            lg.prof_reset()
+            lg.prof_enable(True)
         tp0 = time.perf_counter()
         for _ in range(args.steps):
             hp, tt, _, _ = run_step("plain", dict(relabel=enc["relabel"]))
@@ -207,6 +210,15 @@ def main():
             hp.free()
         torch.cuda.synchronize()
         pwall = (time.perf_counter() - tp0) * 1000.0 / args.steps
+        if args.kernels:
+            lg.prof_enable(False)
+            rows = []
+            for name in lg.prof_names():
+                base = name.lstrip("(").split("<")[0].rstrip(")")
+                if base not in [r[0] for r in rows]:
+                    rows.append((base, *lg.prof_query(base)))
+            for k, c, ms in sorted(rows, key=lambda r: -r[2])[:12]:
+                log(f"[plain-kernel] {k:32s} launches={c:7d} total={ms:10.3f} ms avg={ms / max(c, 1) * 1000:9.2f} us")
         pbfs_ms = np.array([np.mean([tt["bfs"][i] for tt in pt]) for i in range(len(roots))])
         pteps = np.array(edges_root) / (pbfs_ms / 1000.0)
         ppr_ms = float(np.mean([tt["pr"] for tt in pt]))

@@ -30,7 +30,9 @@ struct BfsWork {
     DevBuf fstart, fdeg, fw;    // per frontier entry: first bit/element, degree, width
     DevBuf fscan;               // exclusive scan of fdeg
     DevBuf visited, curr, next; // bitmaps, one bit per vertex
-    DevBuf counters;            // [0] queue tail, [1] awakened count
+    DevBuf counters;            // [0] queue tail, [1] awakened count, [2] pending count
+    DevBuf pv, pstart, pdeg, pw; // bottom-up: heavy vertices left for the segment pass
+    DevBuf pseg_cnt, pseg_off;
     DevBuf depth_i, parent_i;   // label-space results when relabeled
     DevBuf scan_tmp;
     uint64_t *host = nullptr;   // pinned readback slots
@@ -41,7 +43,8 @@ uint64_t bfs_bytes(const lg_graph *g) {
     const BfsWork *w = g->bfs;
     return w->qa.bytes + w->qb.bytes + w->fstart.bytes + w->fdeg.bytes + w->fw.bytes + w->fscan.bytes +
            w->visited.bytes + w->curr.bytes + w->next.bytes + w->counters.bytes + w->depth_i.bytes +
-           w->parent_i.bytes + w->scan_tmp.bytes;
+           w->parent_i.bytes + w->scan_tmp.bytes + w->pv.bytes + w->pstart.bytes + w->pdeg.bytes + w->pw.bytes +
+           w->pseg_cnt.bytes + w->pseg_off.bytes;
 }
 
 lg_status bfs_free(lg_graph *g) {
@@ -78,6 +81,13 @@ static lg_status bfs_workspace(lg_graph *g, bool need_parent) {
     LG_TRY(w.curr.ensure(words * 8));
     LG_TRY(w.next.ensure(words * 8));
     LG_TRY(w.counters.ensure(8 * 8));
+    const uint64_t nh = g->n_heavy ? g->n_heavy : 1;
+    LG_TRY(w.pv.ensure(nh * 4));
+    LG_TRY(w.pstart.ensure(nh * 8));
+    LG_TRY(w.pdeg.ensure(nh * 4));
+    LG_TRY(w.pw.ensure(nh * 4));
+    LG_TRY(w.pseg_cnt.ensure(nh * 4));
+    LG_TRY(w.pseg_off.ensure((nh + 1) * 8));
     if (g->relabel == LG_RELABEL_DEGREE) {
         LG_TRY(w.depth_i.ensure(n * 4));
         if (need_parent) LG_TRY(w.parent_i.ensure(n * 4));
@@ -216,15 +226,18 @@ __global__ void mark_queue_kernel(const uint32_t *__restrict__ queue, const unsi
     }
 }
 
-// Light vertices (degree <= threshold): lane per vertex, the list decoded in
-// ascending order four elements at a time, stopping at the first frontier
-// neighbor.  Heavy vertices are skipped here (bu_heavy_kernel ran first and
-// already set their bits in next/visited).
+// Sweep over all vertices, a lane per vertex: an unvisited vertex decodes
+// the first min(d_v, threshold) entries of its list (its smallest labels),
+// four at a time, and stops at the first frontier neighbor -- its parent.
+// A vertex with more entries and no hit among them is appended to the
+// pending list for the segment pass.
 template <class Acc, bool kParent>
 __global__ void bu_step_kernel(Acc acc, uint32_t n, uint32_t threshold, const uint64_t *__restrict__ curr,
                                uint64_t *__restrict__ visited, uint64_t *__restrict__ next,
                                int32_t *__restrict__ depth, uint32_t *__restrict__ parent, int32_t next_depth,
-                               unsigned long long *__restrict__ awake) {
+                               unsigned long long *__restrict__ counters, uint32_t *__restrict__ pv,
+                               uint64_t *__restrict__ pstart, uint32_t *__restrict__ pdeg,
+                               uint32_t *__restrict__ pw) {
     const uint32_t lane = lane_id();
     const uint64_t words = ((uint64_t)n + 63) / 64;
     const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
@@ -235,22 +248,24 @@ __global__ void bu_step_kernel(Acc acc, uint32_t n, uint32_t threshold, const ui
         if (vis == ~0ull) continue;
         const VInfo vi = wave_info(acc, q * 64, n);
         const uint64_t v = q * 64 + lane;
-        bool found = false;
+        bool found = false, pending = false;
         uint32_t par = 0;
-        if (v < n && !((vis >> lane) & 1ull) && vi.deg <= threshold) {
+        if (v < n && !((vis >> lane) & 1ull) && vi.deg) {
             const uint32_t st = Acc::step(vi.w), mk = Acc::mask(vi.w);
-            for (uint32_t i = 0; i < vi.deg && !found; i += 4) {
+            const uint32_t lim = vi.deg < threshold ? vi.deg : threshold;
+            for (uint32_t i = 0; i < lim && !found; i += 4) {
                 uint32_t u[4];
                 bool f[4];
 #pragma unroll
-                for (int b = 0; b < 4; ++b) u[b] = i + b < vi.deg ? acc.get(vi.start + (uint64_t)(i + b) * st, mk) : 0u;
+                for (int b = 0; b < 4; ++b) u[b] = i + b < lim ? acc.get(vi.start + (uint64_t)(i + b) * st, mk) : 0u;
 #pragma unroll
-                for (int b = 0; b < 4; ++b) f[b] = i + b < vi.deg && ((curr[u[b] >> 6] >> (u[b] & 63)) & 1ull);
+                for (int b = 0; b < 4; ++b) f[b] = i + b < lim && ((curr[u[b] >> 6] >> (u[b] & 63)) & 1ull);
 #pragma unroll
                 for (int b = 0; b < 4; ++b) {
                     if (f[b] && !found) { found = true; par = u[b]; }
                 }
             }
+            pending = !found && vi.deg > threshold;
         }
         const uint64_t fm = __ballot(found);
         if (found) {
@@ -262,45 +277,66 @@ __global__ void bu_step_kernel(Acc acc, uint32_t n, uint32_t threshold, const ui
             visited[q] |= fm;
             woke += (unsigned long long)__popcll(fm);
         }
+        const uint64_t pm = __ballot(pending);
+        if (pm) {
+            unsigned long long base = 0;
+            if (lane == 0) base = atomicAdd(&counters[2], (unsigned long long)__popcll(pm));
+            base = __shfl(base, 0, kWave) + popc_below(pm);
+            if (pending) {
+                pv[base] = (uint32_t)v;
+                pstart[base] = vi.start;
+                pdeg[base] = vi.deg;
+                pw[base] = vi.w;
+            }
+        }
     }
     woke = block_sum_u64(woke);
-    if (threadIdx.x == 0 && woke) atomicAdd(awake, woke);
+    if (threadIdx.x == 0 && woke) atomicAdd(&counters[1], woke);
 }
 
-// Heavy vertices: one wave per segment of kHeavySeg edges, 64 neighbors per
-// probe.  Lists ascend, so a segment's first frontier neighbor is its
-// smallest, and the smallest over all segments of v is v's parent
-// (atomicMin).  "Not visited before this level" is read from depth (-1 or
-// the level being built), never from the visited bitmap, which this kernel
-// updates.  A segment whose first label exceeds the best parent already
-// found skips its scan.
+__global__ void bu_pending_count_kernel(const unsigned long long *__restrict__ counters, uint32_t threshold,
+                                        const uint32_t *__restrict__ pdeg, uint32_t *__restrict__ cnt) {
+    const uint64_t np = counters[2];
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < np; i += stride)
+        cnt[i] = (pdeg[i] - threshold + kHeavySeg - 1) / kHeavySeg;
+}
+
+// Segment pass over the pending heavy vertices' entries [threshold, d):
+// one wave per segment of kHeavySeg entries, 64 per probe.  Lists ascend,
+// so a segment's first frontier neighbor is its smallest and the smallest
+// over the segments is the parent (atomicMin); a segment whose first label
+// already exceeds the best parent found skips its scan.
 template <class Acc, bool kParent>
-__global__ void bu_heavy_kernel(Acc acc, const uint32_t *__restrict__ heavy, uint64_t n_seg,
-                                const uint32_t *__restrict__ seg_map, const uint64_t *__restrict__ seg_off,
-                                const uint64_t *__restrict__ hstart, const uint32_t *__restrict__ hdeg,
-                                const uint32_t *__restrict__ hw, const uint64_t *__restrict__ curr,
-                                unsigned long long *__restrict__ visited, unsigned long long *__restrict__ next,
-                                int32_t *__restrict__ depth, uint32_t *__restrict__ parent, int32_t next_depth,
-                                unsigned long long *__restrict__ awake) {
+__global__ void bu_pending_kernel(Acc acc, uint32_t threshold, uint64_t np, const uint64_t *__restrict__ pseg_off,
+                                  const uint32_t *__restrict__ pv, const uint64_t *__restrict__ pstart,
+                                  const uint32_t *__restrict__ pdeg, const uint32_t *__restrict__ pw,
+                                  const uint64_t *__restrict__ curr, unsigned long long *__restrict__ visited,
+                                  unsigned long long *__restrict__ next, int32_t *__restrict__ depth,
+                                  uint32_t *__restrict__ parent, int32_t next_depth,
+                                  unsigned long long *__restrict__ counters) {
     const uint32_t lane = lane_id();
+    const uint64_t nseg = pseg_off[np];
     const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
     const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) / kWave;
     unsigned long long woke = 0;
-    for (uint64_t k = wave; k < n_seg; k += nwaves) {
-        const uint32_t h = seg_map[k];
-        const uint32_t v = heavy[h];
-        const int32_t dv = depth[v];
-        if (dv != -1 && dv != next_depth) continue;        // reached at an earlier level
-        if (!kParent && dv == next_depth) continue;        // any frontier neighbor will do
-        const uint32_t w = hw[h];
+    for (uint64_t k = wave; k < nseg; k += nwaves) {
+        uint32_t lo = 0, hi = (uint32_t)np - 1;  // pending vertex owning segment k
+        while (lo < hi) {
+            const uint32_t mid = lo + ((hi - lo + 1) >> 1);
+            if (pseg_off[mid] <= k) lo = mid; else hi = mid - 1;
+        }
+        const uint32_t v = pv[lo];
+        const uint32_t w = pw[lo];
         const uint32_t st = Acc::step(w), mk = Acc::mask(w);
-        const uint64_t start = hstart[h];
-        const uint64_t e0 = (k - seg_off[h]) * kHeavySeg;
-        const uint64_t d = hdeg[h];
+        const uint64_t start = pstart[lo];
+        const uint64_t d = pdeg[lo];
+        const uint64_t e0 = threshold + (k - pseg_off[lo]) * kHeavySeg;
         const uint64_t e1 = e0 + kHeavySeg < d ? e0 + kHeavySeg : d;
-        if (kParent && dv == next_depth) {
-            const uint32_t first = acc.get(start + e0 * st, mk);
-            if (parent[v] < first) continue;
+        if (kParent) {
+            if (parent[v] < acc.get(start + e0 * st, mk)) continue;
+        } else if (depth[v] == next_depth) {
+            continue;
         }
         for (uint64_t base = e0; base < e1; base += kWave) {
             const uint64_t i = base + lane;
@@ -327,7 +363,7 @@ __global__ void bu_heavy_kernel(Acc acc, const uint32_t *__restrict__ heavy, uin
         }
     }
     woke = block_sum_u64(woke);
-    if (threadIdx.x == 0 && woke) atomicAdd(awake, woke);
+    if (threadIdx.x == 0 && woke) atomicAdd(&counters[1], woke);
 }
 
 // frontier bitmap -> queue
@@ -444,35 +480,40 @@ static lg_status bfs_one(lg_graph *g, Acc acc, uint32_t root_label, int32_t *dep
             std::swap(qin, qout);
             ++level;
         } else {
-            LG_TRY(fill_u64((uint64_t *)ctr + 1, 0, 1, s));
+            LG_TRY(fill_u64((uint64_t *)ctr + 1, 0, 2, s));
             LG_TRY(fill_u64(next, 0, words, s));
-            if (g->n_seg) {
-                const uint32_t hg = grid_for(g->n_seg * kWave, 256, kStrideBlocks);
-                const uint32_t *hv = g->heavy.as<uint32_t>();
-                const uint32_t *sm = g->seg_map.as<uint32_t>();
-                const uint64_t *so = g->seg_off.as<uint64_t>();
-                const uint64_t *hs = g->hstart.as<uint64_t>();
-                const uint32_t *hd = g->hdeg.as<uint32_t>(), *hwd = g->hw.as<uint32_t>();
-                if (parent)
-                    LG_LAUNCH((bu_heavy_kernel<Acc, true>), hg, 256, 0, s, acc, hv, g->n_seg, sm, so, hs, hd, hwd,
-                              curr, (unsigned long long *)visited, (unsigned long long *)next, depth, parent,
-                              level + 1, ctr + 1);
-                else
-                    LG_LAUNCH((bu_heavy_kernel<Acc, false>), hg, 256, 0, s, acc, hv, g->n_seg, sm, so, hs, hd, hwd,
-                              curr, (unsigned long long *)visited, (unsigned long long *)next, depth, parent,
-                              level + 1, ctr + 1);
-                LG_CHECK_LAUNCH();
-            }
             const uint32_t grid = grid_for(words * kWave, 256, kStrideBlocks);
             if (parent)
                 LG_LAUNCH((bu_step_kernel<Acc, true>), grid, 256, 0, s, acc, n, g->heavy_threshold, curr, visited,
-                          next, depth, parent, level + 1, ctr + 1);
+                          next, depth, parent, level + 1, ctr, w.pv.as<uint32_t>(), w.pstart.as<uint64_t>(),
+                          w.pdeg.as<uint32_t>(), w.pw.as<uint32_t>());
             else
                 LG_LAUNCH((bu_step_kernel<Acc, false>), grid, 256, 0, s, acc, n, g->heavy_threshold, curr, visited,
-                          next, depth, parent, level + 1, ctr + 1);
+                          next, depth, parent, level + 1, ctr, w.pv.as<uint32_t>(), w.pstart.as<uint64_t>(),
+                          w.pdeg.as<uint32_t>(), w.pw.as<uint32_t>());
             LG_CHECK_LAUNCH();
-            LG_CHECK_HIP(hipMemcpyAsync(w.host, ctr + 1, 8, hipMemcpyDeviceToHost, s));
+            LG_CHECK_HIP(hipMemcpyAsync(w.host, ctr + 1, 16, hipMemcpyDeviceToHost, s));
             LG_CHECK_HIP(hipStreamSynchronize(s));
+            const uint64_t np = w.host[1];
+            if (np) {
+                LG_LAUNCH(bu_pending_count_kernel, grid_for(np, 256, 1u << 16), 256, 0, s, ctr, g->heavy_threshold,
+                          w.pdeg.as<uint32_t>(), w.pseg_cnt.as<uint32_t>());
+                LG_CHECK_LAUNCH();
+                LG_TRY(exclusive_scan_u32(w.pseg_cnt.as<uint32_t>(), w.pseg_off.as<uint64_t>(), np, w.scan_tmp, s));
+                if (parent)
+                    LG_LAUNCH((bu_pending_kernel<Acc, true>), kStrideBlocks, 256, 0, s, acc, g->heavy_threshold, np,
+                              w.pseg_off.as<uint64_t>(), w.pv.as<uint32_t>(), w.pstart.as<uint64_t>(),
+                              w.pdeg.as<uint32_t>(), w.pw.as<uint32_t>(), curr, (unsigned long long *)visited,
+                              (unsigned long long *)next, depth, parent, level + 1, ctr);
+                else
+                    LG_LAUNCH((bu_pending_kernel<Acc, false>), kStrideBlocks, 256, 0, s, acc, g->heavy_threshold, np,
+                              w.pseg_off.as<uint64_t>(), w.pv.as<uint32_t>(), w.pstart.as<uint64_t>(),
+                              w.pdeg.as<uint32_t>(), w.pw.as<uint32_t>(), curr, (unsigned long long *)visited,
+                              (unsigned long long *)next, depth, parent, level + 1, ctr);
+                LG_CHECK_LAUNCH();
+                LG_CHECK_HIP(hipMemcpyAsync(w.host, ctr + 1, 8, hipMemcpyDeviceToHost, s));
+                LG_CHECK_HIP(hipStreamSynchronize(s));
+            }
             const uint64_t now = w.host[0];
             std::swap(curr, next);
             ++level;
@@ -503,7 +544,6 @@ extern "C" lg_status lg_bfs(const lg_graph *gc, const uint32_t *roots, uint32_t 
         if (roots[i] >= g->n) { set_error("lg_bfs: root %u out of range", roots[i]); return LG_ERR_INVALID; }
     if (r == 0) return LG_OK;
     LG_TRY(bfs_workspace(g, parent != nullptr));
-    LG_TRY(ensure_heavy_segments(g, stream));
     const bool rel = g->relabel == LG_RELABEL_DEGREE;
     uint32_t *inv_host = nullptr;
     (void)inv_host;

@@ -122,6 +122,15 @@ __device__ __forceinline__ uint64_t ef_select1(const EFView &e, uint32_t k) {
     }
 }
 
+// position of the first set bit of H after position p (one must exist)
+__device__ __forceinline__ uint64_t ef_next_one(const EFView &e, uint64_t p) {
+    uint64_t wi = p >> 6;
+    const uint32_t sh = (uint32_t)(p & 63);
+    uint64_t x = sh == 63 ? 0ull : (e.H[wi] & (~0ull << (sh + 1)));
+    while (!x) x = e.H[++wi];
+    return wi * 64 + (uint64_t)(__ffsll((long long)x) - 1);
+}
+
 __device__ __forceinline__ uint64_t ef_get(const EFView &e, uint32_t v) {
     const uint64_t pos = ef_select1(e, v);
     const uint64_t low = e.l ? extract64(e.L, (uint64_t)v * e.l, e.l) : 0ull;
@@ -158,6 +167,7 @@ template <int IDM, int OFM>
 struct PackedAcc {
     PackedView pv;
     static constexpr bool kPacked = true;
+    static constexpr bool kEF = OFM == kOffsEF;
 
     __device__ __forceinline__ uint64_t offset_value(uint32_t v) const {
         if constexpr (OFM == kOffsPacked) return extract64(pv.po.O, (uint64_t)v * pv.po.w, pv.po.w);
@@ -182,7 +192,17 @@ struct PackedAcc {
         return r;
     }
     __device__ __forceinline__ VInfo info(uint32_t v) const {
-        return make(v, offset_value(v), offset_value(v + 1));
+        if constexpr (OFM == kOffsPacked) {
+            return make(v, offset_value(v), offset_value(v + 1));
+        } else {
+            // x_{v+1}'s upper bit is the next one of H after x_v's
+            const EFView &e = pv.ef;
+            const uint64_t p0 = ef_select1(e, v);
+            const uint64_t p1 = ef_next_one(e, p0);
+            const uint64_t lo0 = e.l ? extract64(e.L, (uint64_t)v * e.l, e.l) : 0ull;
+            const uint64_t lo1 = e.l ? extract64(e.L, (uint64_t)(v + 1) * e.l, e.l) : 0ull;
+            return make(v, ((p0 - v) << e.l) | lo0, ((p1 - v - 1) << e.l) | lo1);
+        }
     }
     // element at position `pos` (a bit position)
     __device__ __forceinline__ uint32_t get(uint64_t pos, uint32_t mask) const {
@@ -196,6 +216,7 @@ template <bool OFF64>
 struct PlainAcc {
     PlainView pv;
     static constexpr bool kPacked = false;
+    static constexpr bool kEF = false;
 
     __device__ __forceinline__ uint64_t offset_value(uint32_t v) const {
         if constexpr (OFF64) return static_cast<const uint64_t *>(pv.off)[v];
@@ -216,16 +237,78 @@ struct PlainAcc {
     __device__ __forceinline__ static uint32_t mask(uint32_t) { return 0xFFFFFFFFu; }
 };
 
-// VInfo of vertex v0 + lane for the 64 lanes of a wave: every lane decodes
-// one offset value and takes the next one from its neighbor lane, so a sweep
-// over consecutive vertices decodes each offset once.  Lanes past n get an
-// empty list.
+// Upper-bit positions of ones number v0 + lane and v0 + 64 (broadcast) for a
+// 64-aligned v0: sel[v0/64] is select1(v0) and sel[v0/64 + 1] is select1(v0 +
+// 64), so the 65 ones lie in the H words between those two positions.  When
+// they span at most 64 words, lane i loads word i, a wave prefix of the
+// popcounts tells every lane which word holds its one, and an in-word select
+// finishes; otherwise each lane runs a full select.
+__device__ __forceinline__ void ef_wave_select(const EFView &e, uint64_t v0, uint32_t count, uint64_t &pos,
+                                               uint64_t &pos_end) {
+    const uint32_t lane = lane_id();
+    const uint32_t q = (uint32_t)(v0 >> 6);
+    const uint64_t p0 = e.sel[q];
+    // one number v0 + 64 exists iff v0 + 64 < count
+    const bool have_end = v0 + kWave < count;
+    const uint64_t p1 = have_end ? e.sel[q + 1] : 0;
+    const uint64_t w0 = p0 >> 6;
+    const uint64_t w1 = have_end ? (p1 >> 6) : w0 + kWave;  // unknown end: let the fallback decide
+    if (have_end && w1 - w0 < (uint64_t)kWave) {
+        const uint32_t nw = (uint32_t)(w1 - w0 + 1);
+        uint64_t x = lane < nw ? e.H[w0 + lane] : 0ull;
+        if (lane == 0) x &= ~0ull << (p0 & 63);
+        const uint32_t c = (uint32_t)__popcll(x);
+        const uint32_t incl = wave_incl_scan(c);
+        // lane t wants one number t of the window (t = 0..63): the word i with
+        // excl(i) <= t < incl(i), i.e. the count of words whose inclusive
+        // prefix is <= t.  Fixed power-of-two steps keep every shuffle
+        // wave-uniform; the window holds at least 65 ones, so lo < nw.
+        uint32_t lo = 0;
+#pragma unroll
+        for (uint32_t step = kWave / 2; step > 0; step >>= 1) {
+            const uint32_t probe = lo + step - 1;  // at most 62
+            const uint32_t val = __shfl(incl, probe, kWave);
+            if (probe < nw && val <= lane) lo += step;
+        }
+        const uint64_t xi = __shfl(x, lo, kWave);
+        const uint32_t ei = __shfl(incl, lo, kWave) - __shfl(c, lo, kWave);
+        pos = (w0 + lo) * 64 + select_in_word(xi, lane - ei);
+        pos_end = p1;
+        return;
+    }
+    const uint64_t v = v0 + lane;
+    pos = v < count ? ef_select1(e, (uint32_t)v) : 0;
+    pos_end = (v0 + kWave < count) ? ef_select1(e, (uint32_t)(v0 + kWave)) : 0;
+}
+
+// VInfo of vertex v0 + lane for the 64 lanes of a wave (v0 a multiple of
+// 64): every lane decodes one offset value and takes the next one from its
+// neighbor lane, so a sweep over consecutive vertices decodes each offset
+// once.  Lanes past n get an empty list.
 template <class Acc>
 __device__ __forceinline__ VInfo wave_info(const Acc &acc, uint64_t v0, uint32_t n) {
     const uint32_t lane = lane_id();
     const uint64_t v = v0 + lane;
-    const uint64_t o0 = acc.offset_value((uint32_t)(v < n ? v : n));
-    const uint64_t end = acc.offset_value((uint32_t)(v0 + kWave < n ? v0 + kWave : n));
+    if (v0 >= n) return VInfo{0, 0, 0};  // wave-uniform: a block past the last vertex
+    uint64_t o0, end;
+    if constexpr (Acc::kPacked && Acc::kEF) {
+        const EFView &e = acc.pv.ef;
+        uint64_t pos, pos_end;
+        ef_wave_select(e, v0, n + 1, pos, pos_end);
+        const uint64_t vv = v < n ? v : n;
+        const uint64_t ve = v0 + kWave < n ? v0 + kWave : n;
+        if (v > n) pos = 0;
+        o0 = v <= n ? (((pos - vv) << e.l) | (e.l ? extract64(e.L, vv * e.l, e.l) : 0ull)) : 0ull;
+        // the end value: one number ve; when ve = n it is one number n itself
+        if (v0 + kWave <= n) {
+            end = ((pos_end - ve) << e.l) | (e.l ? extract64(e.L, ve * e.l, e.l) : 0ull);
+        } else {
+            end = __shfl(o0, (uint32_t)(n - v0), kWave);
+        }
+    } else {
+        o0 = acc.offset_value((uint32_t)(v < n ? v : n));
+        end = acc.offset_value((uint32_t)(v0 + kWave < n ? v0 + kWave : n));
+    }
     uint64_t o1 = __shfl_down(o0, 1, kWave);
     if (lane == kWave - 1) o1 = end;
     if (v >= n) return VInfo{0, 0, 0};

@@ -33,8 +33,7 @@ enum : uint32_t {
 // validation and degree statistics
 // ---------------------------------------------------------------------------
 
-// One wave per vertex; lanes walk the list.  The symmetric check looks every
-// entry (v, u) up in N_u by binary search.
+// One wave per vertex; lanes walk the list.
 __global__ void validate_kernel(uint32_t n, uint64_t m, const uint64_t *__restrict__ off,
                                 const uint32_t *__restrict__ col, uint32_t *__restrict__ status) {
     const uint32_t lane = lane_id();
@@ -52,19 +51,41 @@ __global__ void validate_kernel(uint32_t n, uint64_t m, const uint64_t *__restri
             if (u >= n) { flags |= kBadId; continue; }
             if (u == v) flags |= kSelfLoop;
             if (i > o0 && col[i - 1] >= u) flags |= kUnsorted;
-            uint64_t lo = off[u], hi = off[u + 1];
-            if (hi > m) hi = m;
-            bool found = false;
-            while (lo < hi) {
-                const uint64_t mid = (lo + hi) >> 1;
-                const uint32_t x = col[mid];
-                if (x == (uint32_t)v) { found = true; break; }
-                if (x < (uint32_t)v) lo = mid + 1; else hi = mid;
-            }
-            if (!found) flags |= kAsymmetric;
         }
     }
     if (flags) atomicOr(status, flags);
+}
+
+// Symmetry, exactly: the entries (v, u) emitted in row order and sorted
+// stably by u list the transpose in adjacency-array order; the graph is
+// symmetric iff that is the input itself, entry for entry.
+__global__ void sym_emit_kernel(uint32_t n, const uint64_t *__restrict__ off, const uint32_t *__restrict__ col,
+                                uint32_t *__restrict__ key, uint32_t *__restrict__ val) {
+    const uint32_t lane = lane_id();
+    const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) / kWave;
+    for (uint64_t v = wave; v < n; v += nwaves) {
+        const uint64_t o0 = off[v], o1 = off[v + 1];
+        for (uint64_t i = o0 + lane; i < o1; i += kWave) {
+            key[i] = col[i];
+            val[i] = (uint32_t)v;
+        }
+    }
+}
+
+__global__ void sym_check_kernel(uint32_t n, const uint64_t *__restrict__ off, const uint32_t *__restrict__ col,
+                                 const uint32_t *__restrict__ key, const uint32_t *__restrict__ val,
+                                 uint32_t *__restrict__ status) {
+    const uint32_t lane = lane_id();
+    const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) / kWave;
+    bool bad = false;
+    for (uint64_t v = wave; v < n; v += nwaves) {
+        const uint64_t o0 = off[v], o1 = off[v + 1];
+        for (uint64_t i = o0 + lane; i < o1; i += kWave)
+            bad |= key[i] != (uint32_t)v || val[i] != col[i];
+    }
+    if (__ballot(bad) && lane == 0) atomicOr(status, kAsymmetric);
 }
 
 // deg[v] (uint32), plus the maximum degree and the number of isolated vertices
@@ -401,6 +422,23 @@ static lg_status encode_impl(uint32_t n, uint64_t m, const uint64_t *row_offsets
     uint32_t bad = 0;
     LG_CHECK_HIP(hipMemcpyAsync(&bad, status.p, 4, hipMemcpyDeviceToHost, s));
     LG_CHECK_HIP(hipStreamSynchronize(s));
+    if (!bad && m) {
+        DevBuf key, val, key2, val2;
+        LG_TRY(key.alloc(m * 4));
+        LG_TRY(val.alloc(m * 4));
+        LG_TRY(key2.alloc(m * 4));
+        LG_TRY(val2.alloc(m * 4));
+        const uint32_t wgrid = grid_for((uint64_t)n * kWave, 256, 1u << 16);
+        LG_LAUNCH(sym_emit_kernel, wgrid, 256, 0, s, n, row_offsets, col, key.as<uint32_t>(), val.as<uint32_t>());
+        LG_CHECK_LAUNCH();
+        LG_TRY(radix_sort_pairs(key.as<uint32_t>(), val.as<uint32_t>(), key2.as<uint32_t>(), val2.as<uint32_t>(), m,
+                                bitlen_u64(n - 1), tmp, s));
+        LG_LAUNCH(sym_check_kernel, wgrid, 256, 0, s, n, row_offsets, col, key.as<uint32_t>(), val.as<uint32_t>(),
+                  status.as<uint32_t>());
+        LG_CHECK_LAUNCH();
+        LG_CHECK_HIP(hipMemcpyAsync(&bad, status.p, 4, hipMemcpyDeviceToHost, s));
+        LG_CHECK_HIP(hipStreamSynchronize(s));
+    }
     if (bad) {
         set_error("invalid input graph:%s%s%s%s%s", (bad & kBadOffsets) ? " bad-offsets" : "",
                   (bad & kBadId) ? " id>=n" : "", (bad & kSelfLoop) ? " self-loop" : "",

@@ -164,18 +164,36 @@ __global__ void radix_hist_kernel(const K *__restrict__ keys, uint64_t count, ui
 
 // Items of a tile are taken in rounds of 256 consecutive keys; within a
 // round, lanes with equal digits are found with eight ballots, so every key
-// gets its rank among equal digits in input order (stability).
+// gets its rank among equal digits in input order (stability).  Keys are
+// first placed in LDS in digit order, then written out so that consecutive
+// threads store consecutive addresses of one digit's run.
 template <class K>
-__global__ void radix_scatter_kernel(const K *__restrict__ keys, const uint32_t *__restrict__ vals, uint64_t count,
-                                     uint32_t shift, uint32_t ntiles, const uint64_t *__restrict__ offsets,
-                                     K *__restrict__ keys_out, uint32_t *__restrict__ vals_out) {
-    __shared__ uint64_t base[256];
+__global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
+    const K *__restrict__ keys, const uint32_t *__restrict__ vals, uint64_t count, uint32_t shift, uint32_t ntiles,
+    const uint32_t *__restrict__ counts, const uint64_t *__restrict__ offsets, K *__restrict__ keys_out,
+    uint32_t *__restrict__ vals_out) {
+    __shared__ K s_key[kSortTile];
+    __shared__ uint32_t s_val[kSortTile];
+    __shared__ uint32_t s_start[256];
+    __shared__ uint32_t s_run[256];
+    __shared__ uint64_t s_gbase[256];
+    __shared__ uint32_t s_wtot[kSortWaves];
     __shared__ uint32_t wave_cnt[kSortWaves][256];
-    const uint32_t lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
-    base[threadIdx.x] = offsets[(uint64_t)threadIdx.x * ntiles + blockIdx.x];
+    const uint32_t lane = lane_id(), wv = threadIdx.x / kWave;
+    const uint32_t tid = threadIdx.x;
+    // tile-local start of every digit: exclusive scan of this tile's histogram
+    const uint32_t c = counts[(uint64_t)tid * ntiles + blockIdx.x];
+    const uint32_t incl = wave_incl_scan(c);
+    if (lane == kWave - 1) s_wtot[wv] = incl;
+    __syncthreads();
+    uint32_t before = 0;
+    for (uint32_t w = 0; w < wv; ++w) before += s_wtot[w];
+    s_start[tid] = before + incl - c;
+    s_run[tid] = 0;
+    s_gbase[tid] = offsets[(uint64_t)tid * ntiles + blockIdx.x] - (before + incl - c);
     const uint64_t t0 = (uint64_t)blockIdx.x * kSortTile;
     for (int r = 0; r < kSortRounds; ++r) {
-        const uint64_t i = t0 + (uint64_t)r * kSortThreads + threadIdx.x;
+        const uint64_t i = t0 + (uint64_t)r * kSortThreads + tid;
         const bool valid = i < count;
         K key = 0;
         uint32_t val = 0;
@@ -188,31 +206,35 @@ __global__ void radix_scatter_kernel(const K *__restrict__ keys, const uint32_t 
             peers &= ((digit >> b) & 1u) ? m : ~m;
         }
 #pragma unroll
-        for (int w = 0; w < kSortWaves; ++w) wave_cnt[w][threadIdx.x] = 0;
+        for (int w = 0; w < kSortWaves; ++w) wave_cnt[w][tid] = 0;
         __syncthreads();
         const uint32_t rank = popc_below(peers);
         if (valid && rank == 0) wave_cnt[wv][digit] = (uint32_t)__popcll(peers);
         __syncthreads();
-        {   // per digit: exclusive prefix over waves, then advance the base
-            const uint32_t d = threadIdx.x;
-            uint64_t run = base[d];
+        {   // per digit: running count + exclusive prefix over the waves
+            uint32_t run = s_run[tid];
 #pragma unroll
             for (int w = 0; w < kSortWaves; ++w) {
-                const uint32_t c = wave_cnt[w][d];
-                wave_cnt[w][d] = (uint32_t)(run - base[d]);
-                run += c;
+                const uint32_t cw = wave_cnt[w][tid];
+                wave_cnt[w][tid] = run;
+                run += cw;
             }
-            __syncthreads();
-            if (valid) {
-                const uint64_t dst = base[digit] + wave_cnt[wv][digit] + rank;
-                keys_out[dst] = key;
-                vals_out[dst] = val;
-            }
-            __syncthreads();
-            base[d] = run;
+            s_run[tid] = run;
         }
         __syncthreads();
-        (void)lane;
+        if (valid) {
+            const uint32_t idx = s_start[digit] + wave_cnt[wv][digit] + rank;
+            s_key[idx] = key;
+            s_val[idx] = val;
+        }
+        __syncthreads();
+    }
+    const uint64_t tile_n = count - t0 < kSortTile ? count - t0 : kSortTile;
+    for (uint32_t idx = tid; idx < tile_n; idx += kSortThreads) {
+        const K key = s_key[idx];
+        const uint64_t dst = s_gbase[(uint32_t)(key >> shift) & 255u] + idx;
+        keys_out[dst] = key;
+        vals_out[dst] = s_val[idx];
     }
 }
 
@@ -242,7 +264,7 @@ static lg_status radix_sort_impl(K *keys, uint32_t *vals, K *keys_alt, uint32_t 
         LG_CHECK_LAUNCH();
         LG_TRY(scan_level<uint32_t>(counts, offs, ncount, scratch, s));
         LG_LAUNCH(radix_scatter_kernel<K>, (uint32_t)ntiles, kSortThreads, 0, s, src_k, src_v, count, shift,
-                  (uint32_t)ntiles, (const uint64_t *)offs, dst_k, dst_v);
+                  (uint32_t)ntiles, (const uint32_t *)counts, (const uint64_t *)offs, dst_k, dst_v);
         LG_CHECK_LAUNCH();
         K *tk = src_k; src_k = dst_k; dst_k = tk;
         uint32_t *tv = src_v; src_v = dst_v; dst_v = tv;

@@ -47,6 +47,9 @@ def _tiny_graphs():
                                       + [(2, 100)])
     # a hub whose list spans several PageRank segments (1024 edges each)
     G["bigstar"] = gg.csr_from_edges(3001, [(0, i) for i in range(1, 3001)] + [(5, 6), (6, 7)])
+    # a hub so large that its gap in the Elias-Fano upper bits spans more than
+    # 64 words (the per-lane select fallback of the sweep kernels)
+    G["megastar"] = gg.csr_from_edges(20001, [(0, i) for i in range(1, 20001)] + [(7, 8), (8, 9)])
     for n in [63, 64, 65, 127, 129]:
         G[f"rand{n}"] = gg.random_graph(n, 0.07, seed=n)
     G["kron12"] = gg.kronecker(12, 16, seed=1)
@@ -151,7 +154,8 @@ def test_decode_neighbors(lgmod, name, e):
 @pytest.mark.parametrize("mode", ["do", "td", "bu"])
 @pytest.mark.parametrize("e", ENCODINGS, ids=enc_id)
 @pytest.mark.parametrize("name", ["path9", "star33", "clique12", "only0", "hubtail", "rand64", "rand129",
-                                  "kron12", "er12", "kron10ef4", "single", "edge", "deg64_65", "bigstar"])
+                                  "kron12", "er12", "kron10ef4", "single", "edge", "deg64_65", "bigstar",
+                                  "megastar"])
 def test_bfs_bit_exact(lgmod, name, e, mode):
     g = GRAPHS[name]
     off, col = g.numpy()
@@ -201,7 +205,7 @@ def test_bfs_without_parents(lgmod):
 
 @pytest.mark.parametrize("e", ENCODINGS, ids=enc_id)
 @pytest.mark.parametrize("name", ["star33", "clique12", "isolated7", "single", "hubtail", "rand127", "kron12",
-                                  "er12", "deg64_65", "bigstar"])
+                                  "er12", "deg64_65", "bigstar", "megastar"])
 def test_pagerank_l1(lgmod, name, e):
     g = GRAPHS[name]
     off, col = g.numpy()
