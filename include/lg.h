@@ -191,6 +191,13 @@ typedef struct lg_graph_info {
     uint64_t device_bytes; /* all device memory held by the handle now           */
     uint32_t max_degree;
     uint32_t isolated;     /* vertices without edges                             */
+    uint32_t heavy_threshold; /* degree above which a vertex is "heavy": the
+                                 traversal kernels split its list into segments */
+    uint32_t n_heavy;      /* heavy vertices                                     */
+    uint64_t n_segments;   /* segments of the heavy lists (0 until first use)    */
+    uint64_t heavy_edges;  /* entries of the heavy lists (0 until first use)     */
+    uint64_t heavy_bits;   /* bits of the heavy lists (element bits; 32/entry on
+                              the plain layout; 0 until first use)               */
 } lg_graph_info;
 
 lg_status lg_info(const lg_graph *g, lg_graph_info *out);

@@ -171,6 +171,11 @@ extern "C" lg_status lg_info(const lg_graph *g, lg_graph_info *out) {
     out->F = g->F;
     out->max_degree = g->max_degree;
     out->isolated = g->isolated;
+    out->heavy_threshold = g->heavy_threshold;
+    out->n_heavy = g->n_heavy;
+    out->n_segments = g->n_seg;
+    out->heavy_edges = g->heavy_edges;
+    out->heavy_bits = g->heavy_bits;
     if (g->layout == LG_LAYOUT_PLAIN) {
         out->bytes_adj = g->m * 4;
         out->bytes_offsets = ((uint64_t)g->n + 1) * (g->poff64 ? 8 : 4);

@@ -294,16 +294,18 @@ __global__ void bu_step_kernel(Acc acc, uint32_t n, uint32_t threshold, const ui
     if (threadIdx.x == 0 && woke) atomicAdd(&counters[1], woke);
 }
 
+constexpr uint32_t kPendingSeg = 1024;  // entries per segment of the pending pass
+
 __global__ void bu_pending_count_kernel(const unsigned long long *__restrict__ counters, uint32_t threshold,
                                         const uint32_t *__restrict__ pdeg, uint32_t *__restrict__ cnt) {
     const uint64_t np = counters[2];
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < np; i += stride)
-        cnt[i] = (pdeg[i] - threshold + kHeavySeg - 1) / kHeavySeg;
+        cnt[i] = (pdeg[i] - threshold + kPendingSeg - 1) / kPendingSeg;
 }
 
 // Segment pass over the pending heavy vertices' entries [threshold, d):
-// one wave per segment of kHeavySeg entries, 64 per probe.  Lists ascend,
+// one wave per segment of kPendingSeg entries, 64 per probe.  Lists ascend,
 // so a segment's first frontier neighbor is its smallest and the smallest
 // over the segments is the parent (atomicMin); a segment whose first label
 // already exceeds the best parent found skips its scan.
@@ -331,8 +333,8 @@ __global__ void bu_pending_kernel(Acc acc, uint32_t threshold, uint64_t np, cons
         const uint32_t st = Acc::step(w), mk = Acc::mask(w);
         const uint64_t start = pstart[lo];
         const uint64_t d = pdeg[lo];
-        const uint64_t e0 = threshold + (k - pseg_off[lo]) * kHeavySeg;
-        const uint64_t e1 = e0 + kHeavySeg < d ? e0 + kHeavySeg : d;
+        const uint64_t e0 = threshold + (k - pseg_off[lo]) * kPendingSeg;
+        const uint64_t e1 = e0 + kPendingSeg < d ? e0 + kPendingSeg : d;
         if (kParent) {
             if (parent[v] < acc.get(start + e0 * st, mk)) continue;
         } else if (depth[v] == next_depth) {

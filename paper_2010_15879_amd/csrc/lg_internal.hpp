@@ -133,9 +133,11 @@ struct lg_graph {
     uint32_t n_heavy = 0;
     uint32_t heavy_threshold = 64;
     // per heavy vertex: first bit/element, degree, width; its list cut into
-    // segments of kHeavySeg edges: seg_off[h] .. seg_off[h+1], seg_map[k] = h
+    // segments of seg_size edges: seg_off[h] .. seg_off[h+1], seg_map[k] = h
     lg::DevBuf hstart, hdeg, hw, seg_off, seg_map;
     uint64_t n_seg = 0;
+    uint32_t seg_size = 1024;  // a power of two >= 1024 keeping every vertex below 65536 segments
+    uint64_t heavy_edges = 0, heavy_bits = 0;  // entries and bits (packed) of the heavy lists
     bool segs_built = false;
 
     // lazily allocated workspaces
@@ -206,8 +208,6 @@ inline uint32_t grid_for(uint64_t count, uint64_t per_block, uint64_t cap = 1u <
 }
 
 inline uint32_t bitlen_u64(uint64_t x) { return x ? 64u - (uint32_t)__builtin_clzll(x) : 0u; }
-
-constexpr uint32_t kHeavySeg = 1024;  // edges per heavy-vertex segment
 
 // Build the heavy-vertex segment table of g (once); defined in lg_heavy.hip.
 lg_status ensure_heavy_segments(lg_graph *g, hipStream_t s);

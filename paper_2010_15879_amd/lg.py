@@ -49,7 +49,9 @@ class GraphInfo(C.Structure):
                 ("w_offset", C.c_uint32), ("ef_l", C.c_uint32), ("universe", C.c_uint64),
                 ("adj_bits", C.c_uint64), ("ef_high_bits", C.c_uint64), ("bytes_adj", C.c_uint64),
                 ("bytes_offsets", C.c_uint64), ("bytes_widths", C.c_uint64), ("bytes_perm", C.c_uint64),
-                ("device_bytes", C.c_uint64), ("max_degree", C.c_uint32), ("isolated", C.c_uint32)]
+                ("device_bytes", C.c_uint64), ("max_degree", C.c_uint32), ("isolated", C.c_uint32),
+                ("heavy_threshold", C.c_uint32), ("n_heavy", C.c_uint32), ("n_segments", C.c_uint64),
+                ("heavy_edges", C.c_uint64), ("heavy_bits", C.c_uint64)]
 
 
 _lib = None
