@@ -169,6 +169,48 @@ lg_status lg_bfs(const lg_graph *g, const uint32_t *roots, uint32_t r, int32_t *
 lg_status lg_pagerank(const lg_graph *g, float damping, uint32_t iters, float *scores,
                       hipStream_t stream);
 
+/*
+ * Batched BFS: many queries over many graphs in one persistent launch.
+ *
+ * Each query is a BFS (same rule and results as lg_bfs) from `root` on
+ * graphs[graph]; its depths (and parents) are written to depth[out_offset ..
+ * out_offset + n_graph) (and parent[...]).  A plan validates the jobs,
+ * optionally times candidate launch settings on the batch itself
+ * (LG_BATCH_AUTOTUNE: work chunk and wave-per-vertex degree threshold) and
+ * captures "reset + persistent launch" in a HIP graph; lg_bfs_batch_run
+ * replays it.  All graphs of a plan must share layout and encoding and must
+ * not be relabeled.  The plan keeps the graph handles and the output
+ * pointers: they must outlive it.  Creating a plan runs the batch at least
+ * once (synchronously).
+ */
+typedef struct lg_bfs_job {
+    uint32_t graph;      /* index into `graphs`                                   */
+    uint32_t root;       /* vertex ID < n of that graph                           */
+    uint64_t out_offset; /* element offset of this query's rows in depth/parent   */
+} lg_bfs_job;
+
+#define LG_BATCH_AUTOTUNE 1u
+
+typedef struct lg_batch_plan lg_batch_plan;
+
+typedef struct lg_batch_info {
+    uint32_t num_jobs;
+    uint32_t workgroups;     /* persistent workers                              */
+    uint32_t threads;        /* threads per worker                              */
+    uint32_t chunk;          /* frontier vertices staged per pass               */
+    uint32_t wave_threshold; /* degree from which a whole wave expands a vertex */
+    uint32_t candidates;     /* settings timed by the autotuner (1 = none)      */
+    double tuned_ms;         /* time of the chosen setting on the batch         */
+    uint64_t scratch_bytes;  /* per-worker frontier queues                      */
+} lg_batch_info;
+
+lg_status lg_bfs_batch_plan(const lg_graph *const *graphs, uint32_t num_graphs, const lg_bfs_job *jobs,
+                            uint32_t num_jobs, int32_t *depth /*dev*/, int32_t *parent /*dev or NULL*/,
+                            int32_t max_depth, uint32_t flags, hipStream_t stream, lg_batch_plan **out);
+lg_status lg_bfs_batch_run(lg_batch_plan *plan, hipStream_t stream);
+lg_status lg_bfs_batch_info(const lg_batch_plan *plan, lg_batch_info *out);
+void lg_bfs_batch_free(lg_batch_plan *plan); /* NULL-safe */
+
 /* Release a graph and its device memory.  NULL is accepted. */
 void lg_free(lg_graph *g);
 

@@ -54,6 +54,16 @@ class GraphInfo(C.Structure):
                 ("heavy_edges", C.c_uint64), ("heavy_bits", C.c_uint64)]
 
 
+class BfsJob(C.Structure):
+    _fields_ = [("graph", C.c_uint32), ("root", C.c_uint32), ("out_offset", C.c_uint64)]
+
+
+class BatchInfo(C.Structure):
+    _fields_ = [("num_jobs", C.c_uint32), ("workgroups", C.c_uint32), ("threads", C.c_uint32),
+                ("chunk", C.c_uint32), ("wave_threshold", C.c_uint32), ("candidates", C.c_uint32),
+                ("tuned_ms", C.c_double), ("scratch_bytes", C.c_uint64)]
+
+
 _lib = None
 
 FUNCTIONS = {
@@ -73,6 +83,11 @@ FUNCTIONS = {
     "lg_prof_reset": (C.c_int, []),
     "lg_prof_query": (C.c_int, [C.c_char_p, C.POINTER(C.c_uint64), C.POINTER(C.c_double)]),
     "lg_prof_names": (C.c_int, [C.c_char_p, C.c_uint64]),
+    "lg_bfs_batch_plan": (C.c_int, [C.POINTER(C.c_void_p), C.c_uint32, C.POINTER(BfsJob), C.c_uint32, C.c_void_p,
+                                    C.c_void_p, C.c_int32, C.c_uint32, C.c_void_p, C.POINTER(C.c_void_p)]),
+    "lg_bfs_batch_run": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "lg_bfs_batch_info": (C.c_int, [C.c_void_p, C.POINTER(BatchInfo)]),
+    "lg_bfs_batch_free": (None, [C.c_void_p]),
 }
 
 
@@ -235,3 +250,57 @@ def prof_names() -> list:
     buf = C.create_string_buffer(1 << 16)
     lib().lg_prof_names(buf, len(buf))
     return [x for x in buf.value.decode().split("\n") if x]
+
+
+# -- batched BFS -----------------------------------------------------------
+
+class BatchPlan:
+    """A captured persistent launch running many BFS queries (lg_bfs_batch_*).
+
+    jobs: list of (graph index, root).  Results: depth[i] / parent[i] are the
+    rows of query i (views into flat device buffers)."""
+
+    def __init__(self, graphs, jobs, *, parent=True, max_depth=-1, autotune=True, stream=None):
+        dev = torch.device("cuda", torch.cuda.current_device())
+        self.graphs = list(graphs)
+        self.jobs = list(jobs)
+        # a bad graph index is left for the library to reject (LG_ERR_INVALID)
+        sizes = [self.graphs[g].n if 0 <= g < len(self.graphs) else 0 for g, _ in self.jobs]
+        offs = [0]
+        for s_ in sizes:
+            offs.append(offs[-1] + s_)
+        self.offsets = offs
+        self.depth_flat = torch.empty(max(offs[-1], 1), dtype=torch.int32, device=dev)
+        self.parent_flat = torch.empty(max(offs[-1], 1), dtype=torch.int32, device=dev) if parent else None
+        arr_g = (C.c_void_p * len(self.graphs))(*[g.handle.value for g in self.graphs])
+        arr_j = (BfsJob * max(len(self.jobs), 1))(*[BfsJob(g, r, offs[i]) for i, (g, r) in enumerate(self.jobs)])
+        out = C.c_void_p()
+        _check(lib().lg_bfs_batch_plan(arr_g, len(self.graphs), arr_j, len(self.jobs), self.depth_flat.data_ptr(),
+                                       self.parent_flat.data_ptr() if parent else None, max_depth,
+                                       1 if autotune else 0, _stream(stream), C.byref(out)))
+        self._p = out
+
+    def run(self, stream=None):
+        _check(lib().lg_bfs_batch_run(self._p, _stream(stream)))
+
+    def info(self) -> dict:
+        out = BatchInfo()
+        _check(lib().lg_bfs_batch_info(self._p, C.byref(out)))
+        return {k: getattr(out, k) for k, _ in BatchInfo._fields_}
+
+    def depth(self, i):
+        return self.depth_flat[self.offsets[i]:self.offsets[i + 1]]
+
+    def parent(self, i):
+        return self.parent_flat[self.offsets[i]:self.offsets[i + 1]]
+
+    def free(self):
+        if self._p:
+            lib().lg_bfs_batch_free(self._p)
+            self._p = C.c_void_p(None)
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass

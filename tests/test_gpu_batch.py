@@ -1,0 +1,121 @@
+"""GPU parity of the batched BFS (one persistent, graph-captured launch for
+many queries over many graphs): every query's depths and parents are
+bit-exact against the oracle, on every replay of the captured graph."""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as orc
+from paper_2010_15879_amd import graphgen as gg
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lgmod():
+    from paper_2010_15879_amd import lg
+    lg.lib()
+    return lg
+
+
+def small_graphs(count, smin, smax, seed0):
+    rng = np.random.default_rng(seed0)
+    out = []
+    for i in range(count):
+        scale = int(rng.integers(smin, smax + 1))
+        out.append(gg.kronecker(scale, 16, seed=seed0 + i))
+    return out
+
+
+def make_jobs(graphs, per_graph):
+    jobs = []
+    for gi, g in enumerate(graphs):
+        roots = gg.pick_roots(g, per_graph, seed=gi + 7)
+        jobs += [(gi, r) for r in roots]
+    jobs.append((0, 0))  # vertex 0 may be isolated: still a valid query
+    return jobs
+
+
+def check_plan(plan, graphs, jobs, max_depth=-1):
+    torch.cuda.synchronize()
+    cache = {}
+    for i, (gi, r) in enumerate(jobs):
+        if gi not in cache:
+            cache[gi] = graphs[gi].numpy()
+        off, col = cache[gi]
+        d0, p0 = orc.bfs(off, col, r, max_depth=max_depth)
+        np.testing.assert_array_equal(plan.depth(i).cpu().numpy(), d0, err_msg=f"job {i} depth")
+        if plan.parent_flat is not None:
+            np.testing.assert_array_equal(plan.parent(i).cpu().numpy(), p0, err_msg=f"job {i} parent")
+
+
+@pytest.mark.parametrize("enc", [dict(layout="packed", ids="global", offsets="packed"),
+                                 dict(layout="packed", ids="local", offsets="succinct"),
+                                 dict(layout="plain")], ids=["global-packed", "local-ef", "plain"])
+def test_batch_matches_oracle_every_replay(lgmod, enc):
+    graphs = small_graphs(24, 6, 12, seed0=1000)
+    print(f"[batch] {enc} graphs={len(graphs)}", flush=True)
+    hs = [lgmod.encode(g.row_offsets.cuda(), g.col.cuda(), g.n, **enc) for g in graphs]
+    jobs = make_jobs(graphs, 6)
+    plan = lgmod.BatchPlan(hs, jobs, autotune=True)
+    info = plan.info()
+    assert info["candidates"] > 1 and info["workgroups"] >= 1
+    check_plan(plan, graphs, jobs)
+    for rep in range(3):
+        plan.depth_flat.fill_(-7)          # eager work between replays
+        plan.parent_flat.fill_(-7)
+        torch.cuda.synchronize()
+        plan.run()
+        check_plan(plan, graphs, jobs)
+    plan.free()
+    for h in hs:
+        h.free()
+
+
+def test_batch_k_hop_and_no_parents(lgmod):
+    graphs = small_graphs(8, 8, 11, seed0=2000)
+    hs = [lgmod.encode(g.row_offsets.cuda(), g.col.cuda(), g.n) for g in graphs]
+    jobs = make_jobs(graphs, 4)
+    plan = lgmod.BatchPlan(hs, jobs, parent=False, max_depth=2, autotune=False)
+    check_plan(plan, graphs, jobs, max_depth=2)
+    plan.run()
+    check_plan(plan, graphs, jobs, max_depth=2)
+    plan.free()
+    for h in hs:
+        h.free()
+
+
+def test_batch_equals_single_queries(lgmod):
+    graphs = small_graphs(6, 9, 12, seed0=3000)
+    hs = [lgmod.encode(g.row_offsets.cuda(), g.col.cuda(), g.n) for g in graphs]
+    jobs = make_jobs(graphs, 5)
+    plan = lgmod.BatchPlan(hs, jobs)
+    for i, (gi, r) in enumerate(jobs):
+        d, p = lgmod.bfs(hs[gi], [r])
+        assert torch.equal(d[0], plan.depth(i)) and torch.equal(p[0], plan.parent(i))
+    plan.free()
+    for h in hs:
+        h.free()
+
+
+def test_batch_rejects_bad_plans(lgmod):
+    from paper_2010_15879_amd.lg import LGError, LG_ERR_INVALID, LG_ERR_UNSUPPORTED
+    g = gg.kronecker(8, 8, seed=5)
+    a = lgmod.encode(g.row_offsets.cuda(), g.col.cuda(), g.n)
+    b = lgmod.encode(g.row_offsets.cuda(), g.col.cuda(), g.n, layout="plain")
+    c = lgmod.encode(g.row_offsets.cuda(), g.col.cuda(), g.n, relabel=True)
+    with pytest.raises(LGError) as e:
+        lgmod.BatchPlan([a, b], [(0, 1)])
+    assert e.value.status == LG_ERR_UNSUPPORTED
+    with pytest.raises(LGError) as e:
+        lgmod.BatchPlan([c], [(0, 1)])
+    assert e.value.status == LG_ERR_UNSUPPORTED
+    with pytest.raises(LGError) as e:
+        lgmod.BatchPlan([a], [(0, g.n)])
+    assert e.value.status == LG_ERR_INVALID
+    with pytest.raises(LGError) as e:
+        lgmod.BatchPlan([a], [(1, 0)])
+    assert e.value.status == LG_ERR_INVALID
+    for h in (a, b, c):
+        h.free()
