@@ -98,6 +98,24 @@ ORC_API void orc_local_widths(uint64_t n, const uint64_t *off, const uint32_t *c
     }
 }
 
+/* Local widths of the relabeled graph, read off the original lists: row x
+ * is the list of perm[x] renamed through inv, so its largest entry is the
+ * largest inv[u] over that list.  deg2[x] receives the row length. */
+ORC_API void orc_relabeled_local_widths(uint64_t n, const uint64_t *off, const uint32_t *col,
+                                        const uint32_t *perm, const uint32_t *inv, uint8_t *w,
+                                        uint64_t *deg2) {
+    for (uint64_t x = 0; x < n; x++) {
+        uint32_t v = perm[x];
+        deg2[x] = off[v + 1] - off[v];
+        if (deg2[x] == 0) { w[x] = 0; continue; }
+        uint32_t mx = 0;
+        for (uint64_t i = off[v]; i < off[v + 1]; i++)
+            if (inv[col[i]] > mx) mx = inv[col[i]];
+        unsigned b = bitlen(mx);
+        w[x] = (uint8_t)(b ? b : 1);
+    }
+}
+
 /* bits of the per-vertex width field: enough to write the global width */
 ORC_API unsigned orc_width_field_bits(uint64_t n) { return bitlen(orc_global_width(n)); }
 

@@ -53,6 +53,7 @@ def lib():
         "orc_global_width": (C.c_uint, [C.c_uint64]),
         "orc_local_widths": (None, [C.c_uint64, u64p, u32p, u8p]),
         "orc_width_field_bits": (C.c_uint, [C.c_uint64]),
+        "orc_relabeled_local_widths": (None, [C.c_uint64, u64p, u32p, u32p, u32p, u8p, u64p]),
         "orc_adjacency_bits": (C.c_uint64, [C.c_uint64, u64p, _NullableU8, C.c_uint]),
         "orc_bit_starts": (None, [C.c_uint64, u64p, _NullableU8, C.c_uint, u64p]),
         "orc_pack_adjacency": (None, [C.c_uint64, u64p, u32p, _NullableU8, C.c_uint, u64p]),
@@ -104,6 +105,16 @@ def global_width(n: int) -> int:
 
 def width_field_bits(n: int) -> int:
     return int(lib().orc_width_field_bits(int(n)))
+
+
+def relabeled_local_widths(off, col, perm, inv):
+    """(widths, row lengths) of the relabeled graph, from the original lists."""
+    n, off, col = _csr(off, col)
+    w = np.zeros(max(n, 1), dtype=np.uint8)
+    d = np.zeros(max(n, 1), dtype=np.uint64)
+    lib().orc_relabeled_local_widths(n, off, col, np.ascontiguousarray(perm, np.uint32),
+                                     np.ascontiguousarray(inv, np.uint32), w, d)
+    return w[:n], d[:n]
 
 
 def local_widths(off, col) -> np.ndarray:

@@ -194,14 +194,26 @@ def canonical_csr(n: int, src: torch.Tensor, dst: torch.Tensor) -> CSR:
     d = dst[keep]
     key = torch.cat([s * n + d, d * n + s])
     del s, d, keep
-    key = torch.unique(key, sorted=True)
-    row = torch.div(key, n, rounding_mode="floor")
-    col = (key - row * n).to(torch.int32)
-    deg = torch.bincount(row, minlength=n)
-    del key, row
-    offs = torch.zeros(n + 1, dtype=torch.int64, device=col.device)
-    offs[1:] = torch.cumsum(deg, 0)
-    return CSR(n, offs, col)
+    # sort in source ranges of at most 2^30 keys each (large graphs), so that no
+    # single sort exceeds 32-bit indexing; the concatenation is globally sorted
+    parts = max(1, -(-key.numel() // (1 << 30)))
+    if parts == 1:
+        key = torch.unique(key, sorted=True)
+    else:
+        bounds = [(n * i) // parts for i in range(parts + 1)]
+        chunks = []
+        for lo, hi in zip(bounds[:-1], bounds[1:]):
+            sel = key[(key >= lo * n) & (key < hi * n)]
+            chunks.append(torch.unique(sel, sorted=True))
+            del sel
+        del key
+        key = torch.cat(chunks)
+        del chunks
+    # row v starts at the first key >= v * n
+    offs = torch.searchsorted(key, torch.arange(n + 1, dtype=torch.int64, device=key.device) * n)
+    col = torch.remainder(key, n).to(torch.int32)
+    del key
+    return CSR(n, offs.to(torch.int64), col)
 
 
 def csr_from_edges(n: int, edges, device="cpu") -> CSR:

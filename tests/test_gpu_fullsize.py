@@ -1,0 +1,132 @@
+"""Parity at full size, in the launch configuration the benchmark times.
+
+Kronecker scale 24 (DM relabel, local widths, Elias-Fano offsets) and
+Erdos-Renyi scale 26 (global widths, packed offsets, and the plain uint32
+CSR).  The oracle computes whole arrays where that is cheap (permutation,
+widths, bit starts, Elias-Fano arrays, packed offsets, one BFS tree, early
+PageRank iterations) and sampled rows of the packed lists, bit by bit."""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as orc
+from paper_2010_15879_amd import graphgen as gg
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lgmod():
+    from paper_2010_15879_amd import lg
+    lg.lib()
+    return lg
+
+
+def host_csr(g):
+    """Host copies in the oracle's element types (no per-call conversions)."""
+    off, col = g.numpy()
+    return off.astype(np.uint64), col.view(np.uint32)
+
+
+def check_sampled_rows(A, P, W, F, s, rows, expect_row):
+    """Every bit of the sampled rows of the packed stream, read bit by bit."""
+    for x in rows:
+        want = expect_row(x)
+        w = orc.get_bits(W, x * F, F) if W is not None else s
+        got = orc.decode_list(A, int(P[x]), want.size, w)
+        np.testing.assert_array_equal(got, want, err_msg=f"row {x}")
+
+
+def test_kronecker24_local_ef_relabeled(lgmod):
+    print("[fullsize] kronecker s24: generate", flush=True)
+    g = gg.kronecker(24, 16, seed=1, device="cuda")
+    off, col = host_csr(g)
+    n = g.n
+    print("[fullsize] kronecker s24: encode", flush=True)
+    h = lgmod.encode(g.row_offsets, g.col, n, ids="local", offsets="succinct", relabel=True)
+    info = h.info()
+    # permutation: the whole array
+    perm, inv = orc.dm_permutation(off)
+    np.testing.assert_array_equal(h.export("perm"), perm)
+    np.testing.assert_array_equal(h.export("inv"), inv)
+    # widths, bit starts, width table and the Elias-Fano arrays: whole arrays
+    w, d2 = orc.relabeled_local_widths(off, col, perm, inv)
+    off2 = np.zeros(n + 1, dtype=np.uint64)
+    off2[1:] = np.cumsum(d2)
+    P = orc.bit_starts(off2, w, 0)
+    assert info["adj_bits"] == int(P[-1])
+    F = orc.width_field_bits(n)
+    W = h.export("widths")
+    np.testing.assert_array_equal(W, orc.pack_fixed(w.astype(np.uint64), F))
+    ef = orc.EF(P, int(P[-1]))
+    np.testing.assert_array_equal(h.export("ef_low"), ef.low)
+    np.testing.assert_array_equal(h.export("ef_high"), ef.high)
+    np.testing.assert_array_equal(h.export("ef_rank"), ef.rank_sb)
+    np.testing.assert_array_equal(h.export("ef_select"), ef.sel)
+    # the packed lists: sampled rows (hubs, middle, last non-empty), every bit
+    A = h.export("adj")
+    assert A.size == (int(P[-1]) + 63) // 64 + 1 and int(A[-1]) == 0
+    rng = np.random.default_rng(11)
+    nonempty = int(np.count_nonzero(d2))
+    rows = sorted(set([0, 1, 2, 63, 64, 65, nonempty - 1] + rng.integers(0, nonempty, 300).tolist()))
+    check_sampled_rows(A, P, W, F, 0, rows, lambda x: orc.relabel_row(off, col, perm, inv, x))
+    del A
+    # BFS: one whole tree, bit-exact (depths and smallest-label parents)
+    root = gg.pick_roots(g, 1, seed=1)[0]
+    depth, parent = lgmod.bfs(h, [root])
+    d0, p0 = orc.bfs(off, col, root, relabeled=True)
+    np.testing.assert_array_equal(depth[0].cpu().numpy(), d0)
+    np.testing.assert_array_equal(parent[0].cpu().numpy(), p0)
+    # PageRank: whole vectors for the first iterations, and the 20-iteration sum
+    for iters in [1, 2]:
+        pr = lgmod.pagerank(h, 0.85, iters).cpu().numpy().astype(np.float64)
+        pr64 = orc.pagerank(off, col, 0.85, iters)
+        assert np.abs(pr - pr64).sum() <= 1e-5, iters
+    pr20 = lgmod.pagerank(h, 0.85, 20).double()
+    assert abs(float(pr20.sum()) - 1.0) <= 1e-5
+    h.free()
+
+
+def test_erdos_renyi26_packed_and_plain(lgmod):
+    print("[fullsize] ER s26: generate", flush=True)
+    g = gg.erdos_renyi(26, 16, seed=1, device="cuda")
+    n, M = g.n, g.m
+    assert M < (1 << 31) and orc.global_width(n) == 26
+    print(f"[fullsize] ER s26: n={n} M={M}; encode packed", flush=True)
+    h = lgmod.encode(g.row_offsets, g.col, n)
+    info = h.info()
+    assert info["s"] == 26 and info["adj_bits"] == 26 * M
+    assert info["w_offset"] == orc.bitlen(M)
+    off, col = host_csr(g)
+    # packed offsets: the whole array
+    np.testing.assert_array_equal(h.export("offsets"), orc.pack_fixed(off, orc.bitlen(M)))
+    A = h.export("adj")
+    assert A.size == (26 * M + 63) // 64 + 1 and int(A[-1]) == 0
+    rng = np.random.default_rng(3)
+    rows = sorted(set([0, n - 1] + rng.integers(0, n, 300).tolist()))
+    P = orc.bit_starts(off, None, 26)
+    check_sampled_rows(A, P, None, 0, 26, rows, lambda v: col[int(off[v]):int(off[v + 1])])
+    del A
+    root = gg.pick_roots(g, 1, seed=1)[0]
+    print("[fullsize] ER s26: BFS", flush=True)
+    depth, parent = lgmod.bfs(h, [root])
+    d_gpu, p_gpu = depth[0].cpu().numpy(), parent[0].cpu().numpy()
+    del depth, parent
+    print("[fullsize] ER s26: oracle BFS", flush=True)
+    d0, p0 = orc.bfs(off, col, root)
+    np.testing.assert_array_equal(d_gpu, d0)
+    np.testing.assert_array_equal(p_gpu, p0)
+    print("[fullsize] ER s26: PageRank", flush=True)
+    pr = lgmod.pagerank(h, 0.85, 1).cpu().numpy().astype(np.float64)
+    pr64 = orc.pagerank(off, col, 0.85, 1)
+    assert np.abs(pr - pr64).sum() <= 1e-5
+    h.free()
+    print("[fullsize] ER s26: plain CSR", flush=True)
+    hp = lgmod.encode(g.row_offsets, g.col, n, layout="plain")
+    depth, parent = lgmod.bfs(hp, [root])
+    np.testing.assert_array_equal(depth[0].cpu().numpy(), d0)
+    np.testing.assert_array_equal(parent[0].cpu().numpy(), p0)
+    prp = lgmod.pagerank(hp, 0.85, 1).cpu().numpy().astype(np.float64)
+    assert np.abs(prp - pr64).sum() <= 1e-5
+    hp.free()

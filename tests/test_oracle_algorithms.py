@@ -281,3 +281,13 @@ def test_pagerank_alpha_one_random_walk():
     assert not nx.is_bipartite(nx.from_scipy_sparse_array(A))
     pr = orc.pagerank(off, col, 1.0, 2000)
     np.testing.assert_allclose(pr, np.diff(off.astype(np.int64)) / col.size, rtol=0, atol=1e-12)
+
+
+def test_relabeled_widths_match_relabeled_csr():
+    g = gg.kronecker(10, 8, seed=21)
+    off, col = g.numpy()
+    perm, inv = orc.dm_permutation(off)
+    off2, col2 = orc.relabel(off, col, perm, inv)
+    w, d = orc.relabeled_local_widths(off, col, perm, inv)
+    np.testing.assert_array_equal(w, orc.local_widths(off2, col2))
+    np.testing.assert_array_equal(d, np.diff(off2.astype(np.uint64)))
