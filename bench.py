@@ -78,6 +78,12 @@ def parse():
     p.add_argument("--batch", action="store_true",
                    help="batching configuration: 256 R-MAT graphs (scales 10..18), 16 roots each, one "
                         "persistent graph-captured launch vs one launch per query (own JSON line)")
+    p.add_argument("--serve", action="store_true",
+                   help="serving configuration: 8 resident graphs (Kronecker and uniform-random scales "
+                        "20/22/24/26), Poisson arrivals of 60%% neighbor / 30%% 2-hop / 10%% BFS queries under a "
+                        "200 GB budget; saturated queries/s and p50/p99 latency per offered load (own JSON line)")
+    p.add_argument("--serve-scales", default="20,22,24,26")
+    p.add_argument("--serve-seconds", type=float, default=6.0, help="arrival window per offered load")
     p.add_argument("--pr-only", action="store_true",
                    help="counter-run mode: one 1 GiB device copy (calibration) then one PageRank call; no timing")
     return p.parse_args()
@@ -101,6 +107,8 @@ def main():
     dev = torch.device("cuda", 0)
     if args.batch:
         return batch_main(args, np, torch, gg, lg, dev)
+    if args.serve:
+        return serve_main(args, np, torch, gg, lg, dev)
     gen, scale, enc = WORKLOADS[args.workload]
 
     t0 = time.time()
@@ -380,6 +388,117 @@ def batch_main(args, np, torch, gg, lg, dev):
                       "autotune": info}}
     print(json.dumps(out), flush=True)
     plan.free()
+    for h in hs:
+        h.free()
+
+
+def serve_main(args, np, torch, gg, lg, dev):
+    """8 resident graphs: Kronecker and uniform-random at each scale of
+    --serve-scales (edge factor 16, seed 1), global widths + packed offsets.
+    Queries: graph uniform, vertex uniform over the graph's non-isolated
+    vertices, kind 60% neighbor fetch / 30% 2-hop / 10% full BFS.  First the
+    saturated throughput (a closed batch submitted at once), then Poisson
+    arrivals at 0.25/0.5/0.75/0.9 of it; latency runs from the scheduled
+    arrival to the result on the host."""
+    import threading
+    scales = [int(x) for x in args.serve_scales.split(",")]
+    t0 = time.time()
+    hs, cands, names = [], [], []
+    for gen in ["kronecker", "er"]:
+        for sc in scales:
+            g = (gg.kronecker if gen == "kronecker" else gg.erdos_renyi)(sc, 16, seed=1, device=dev)
+            hs.append(lg.encode(g.row_offsets, g.col, g.n))
+            cands.append(torch.nonzero(g.degrees() > 0).flatten().cpu().numpy())
+            names.append(f"{gen}-s{sc}")
+            log(f"[serve] {names[-1]}: n={g.n} M={g.m} packed {hs[-1].info()['device_bytes'] / 1e9:.2f} GB "
+                f"({time.time() - t0:.0f}s)")
+            del g
+            torch.cuda.empty_cache()
+    torch.cuda.synchronize()
+    budget = 200 * 10**9
+    srv = lg.Server(hs, budget_bytes=budget, workers=8, max_batch=64)
+    kinds = ["neighbors", "khop", "bfs"]
+
+    def draw(count, seed):
+        rng = np.random.default_rng(seed)
+        gi = rng.integers(len(hs), size=count)
+        r = rng.random(count)
+        kind = np.where(r < 0.6, 0, np.where(r < 0.9, 1, 2))
+        vs = [int(cands[g][rng.integers(cands[g].size)]) for g in gi]
+        return [(kinds[k], int(g), v) for k, g, v in zip(kind, gi, vs)]
+
+    def closed(qs):
+        t = time.perf_counter()
+        tickets = [srv.submit(k, g, v, k=2) for k, g, v in qs]
+        res = [srv.wait(x, arrays=False) for x in tickets]
+        return time.perf_counter() - t, res
+
+    # warm every worker's buffers on every graph and kind
+    warm = [(k, g, int(cands[g][0])) for g in range(len(hs)) for k in kinds for _ in range(2)]
+    closed(warm)
+    wall, res = closed(draw(4000, seed=1))
+    assert all(r["status"] == 0 for r in res), "a query failed"
+    sat_qps = len(res) / wall
+    log(f"[serve] saturated: {len(res)} queries in {wall:.2f}s = {sat_qps:.1f} q/s")
+
+    loads = {}
+    for li, f in enumerate([0.25, 0.5, 0.75, 0.9]):
+        lam = f * sat_qps
+        count = max(200, int(lam * args.serve_seconds))
+        qs = draw(count, seed=100 + li)
+        rng = np.random.default_rng(200 + li)
+        arrivals = np.cumsum(rng.exponential(1.0 / lam, size=count))
+        tickets, lag = [None] * count, [0.0] * count
+        out = [None] * count
+        submitted = threading.Semaphore(0)
+
+        def collect():
+            for i in range(count):
+                submitted.acquire()
+                out[i] = srv.wait(tickets[i], arrays=False)
+
+        th = threading.Thread(target=collect)
+        th.start()
+        start = time.perf_counter()
+        for i, (k, g, v) in enumerate(qs):
+            due = start + arrivals[i]
+            while True:
+                d = due - time.perf_counter()
+                if d <= 0:
+                    break
+                time.sleep(min(d, 0.002) if d > 0.0005 else 0)
+            lag[i] = (time.perf_counter() - due) * 1e3
+            tickets[i] = srv.submit(k, g, v, k=2)
+            submitted.release()
+        th.join()
+        end = max(lag[i] / 1e3 + arrivals[i] + out[i]["latency_ms"] / 1e3 for i in range(count))
+        lat = np.array([lag[i] + out[i]["latency_ms"] for i in range(count)])
+        assert all(r["status"] == 0 for r in out), "a query failed"
+        per_kind = {}
+        for kname in kinds:
+            sel = np.array([q[0] == kname for q in qs])
+            if sel.any():
+                per_kind[kname] = {"p50_ms": round(float(np.percentile(lat[sel], 50)), 3),
+                                   "p99_ms": round(float(np.percentile(lat[sel], 99)), 3), "count": int(sel.sum())}
+        loads[str(f)] = {"offered_qps": round(lam, 1), "achieved_qps": round(float(count / end), 1), "queries": count,
+                         "p50_ms": round(float(np.percentile(lat, 50)), 3),
+                         "p99_ms": round(float(np.percentile(lat, 99)), 3),
+                         "mean_batch": round(float(np.mean([r["batch"] for r in out])), 2),
+                         "submit_lag_p99_ms": round(float(np.percentile(lag, 99)), 3), "per_kind": per_kind}
+        log(f"[serve] load {f}: {loads[str(f)]}")
+    st = srv.stats()
+    srv.free()
+    assert st["peak_bytes"] <= budget and st["overruns"] == 0
+    out = {"metric": "GTEPS & HBM GB/s, Log(Graph)-packed vs plain CSR on GPU; p99 query latency",
+           "value": round(sat_qps, 2), "unit": "queries/s", "n_gpus": 1, "steps": 1, "warmup": 1,
+           "ms_per_step": round(1000.0 / sat_qps, 3), "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+           "config": {"workload": "serve-8graphs-kron-er-s" + "-".join(map(str, scales)), "graphs": names,
+                      "mix": {"neighbors": 0.6, "khop2": 0.3, "bfs": 0.1}, "budget_bytes": budget,
+                      "workers": st["workers"], "encoding": {"ids": "global", "offsets": "packed"}},
+           "detail": {"loads": loads, "resident_bytes": st["resident_bytes"], "peak_bytes": st["peak_bytes"],
+                      "batches": st["batches"], "completed": st["completed"]}}
+    print(json.dumps(out), flush=True)
     for h in hs:
         h.free()
 

@@ -211,6 +211,90 @@ lg_status lg_bfs_batch_run(lg_batch_plan *plan, hipStream_t stream);
 lg_status lg_bfs_batch_info(const lg_batch_plan *plan, lg_batch_info *out);
 void lg_bfs_batch_free(lg_batch_plan *plan); /* NULL-safe */
 
+/*
+ * Query server over resident graphs.
+ *
+ * Queries are submitted from any host thread and served by `workers` worker
+ * threads, each with its own HIP stream and device workspaces, so that
+ * queries overlap on the device.  Admission is first-come first-served and
+ * bounded by `budget_bytes` of device memory: the resident graphs plus every
+ * worker's buffers never exceed it.  Before a query runs, its worker grows
+ * its buffers to the most the query can use, so this holds at every instant;
+ * a query that cannot fit even alone completes with status LG_ERR_CAPACITY.
+ * The resident part is each graph's device memory when the server is created
+ * (lg_graph_info.device_bytes); the graphs must stay unchanged (no lg_bfs,
+ * lg_pagerank or lg_decode_neighbors on them, which grow their own
+ * workspaces) and alive until lg_server_free.  Neighbor fetches queued on the
+ * same graph are served together in one decode launch (up to max_batch).
+ * Results are exactly those of the same query run alone.  Latencies are
+ * measured from submission to completion on the host's steady clock.
+ */
+typedef struct lg_server lg_server;
+
+typedef struct lg_server_opts {
+    uint64_t budget_bytes; /* 0: unlimited                                     */
+    uint32_t workers;      /* 0: 8                                              */
+    uint32_t max_batch;    /* neighbor fetches per decode launch; 0: 64         */
+    uint32_t reserved[4];  /* must be 0                                         */
+} lg_server_opts;
+
+#define LG_QUERY_NEIGHBORS 0u /* sorted N_v, original IDs                      */
+#define LG_QUERY_KHOP 1u      /* sorted {u : 1 <= depth(u) <= k} from `vertex`   */
+#define LG_QUERY_BFS 2u       /* full BFS from `vertex`                          */
+#define LG_QUERY_KEEP_ARRAYS 1u /* BFS: return depth and parent arrays too       */
+
+typedef struct lg_query {
+    uint32_t kind;   /* LG_QUERY_*                                              */
+    uint32_t graph;  /* index into the server's graphs                          */
+    uint32_t vertex; /* original ID < n                                         */
+    int32_t k;       /* hops for LG_QUERY_KHOP                                  */
+    uint32_t flags;  /* LG_QUERY_KEEP_ARRAYS                                    */
+    uint32_t reserved;
+} lg_query;
+
+typedef struct lg_query_result {
+    int32_t status;        /* LG_OK, or why the query failed                     */
+    uint32_t kind;
+    uint64_t count;        /* ids returned (neighbors, k-hop) or vertices reached (BFS) */
+    const uint32_t *ids;   /* host, `count` entries; valid until lg_server_release */
+    const int32_t *depth;  /* host, n entries (BFS with LG_QUERY_KEEP_ARRAYS)     */
+    const int32_t *parent; /* host, n entries (BFS with LG_QUERY_KEEP_ARRAYS)     */
+    uint64_t n;
+    int32_t max_depth;     /* BFS: largest depth reached                          */
+    uint32_t batch;        /* queries served by the same launch                   */
+    uint64_t digest;       /* BFS: order-independent digest of (depth, parent)    */
+    double queue_ms;       /* submission to start                                 */
+    double service_ms;     /* start to completion                                 */
+    double latency_ms;     /* submission to completion                            */
+} lg_query_result;
+
+typedef struct lg_server_stats {
+    uint64_t submitted, completed, rejected, queued, running;
+    uint64_t budget_bytes, resident_bytes, in_use_bytes, peak_bytes;
+    uint32_t workers;
+    uint32_t overruns;     /* times a worker held more than was admitted (0)      */
+    uint64_t batches;      /* launches (batches) started                          */
+} lg_server_stats;
+
+lg_status lg_server_create(const lg_graph *const *graphs, uint32_t num_graphs, const lg_server_opts *opts,
+                           lg_server **out);
+lg_status lg_server_submit(lg_server *server, const lg_query *query, uint64_t *ticket);
+lg_status lg_server_wait(lg_server *server, uint64_t ticket, lg_query_result *out);   /* blocks   */
+lg_status lg_server_result(lg_server *server, uint64_t ticket, lg_query_result *out); /* no wait  */
+lg_status lg_server_poll(lg_server *server, uint64_t *tickets, uint32_t cap, uint32_t *count);
+lg_status lg_server_release(lg_server *server, uint64_t ticket);
+lg_status lg_server_get_stats(lg_server *server, lg_server_stats *out);
+void lg_server_free(lg_server *server); /* waits for every submitted query; NULL-safe */
+
+/* Host-only model of the server's admission rule (no device work): FIFO
+ * queries with arrival times (ascending), bytes of the buffers each needs and
+ * fixed service times, on `workers` workers that each keep one grow-only
+ * buffer.  Writes start/finish times,
+ * per-query status (LG_OK or LG_ERR_CAPACITY) and the peak accounted bytes. */
+lg_status lg_admission_simulate(const double *arrival, const uint64_t *need, const double *service, uint32_t count,
+                                uint64_t budget, uint64_t resident, uint32_t workers, double *start, double *finish,
+                                int32_t *status, uint64_t *peak);
+
 /* Release a graph and its device memory.  NULL is accepted. */
 void lg_free(lg_graph *g);
 

@@ -141,7 +141,7 @@ lg::PlainView lg_graph::plain_view() const {
 uint64_t lg_graph::device_bytes() const {
     uint64_t b = A.bytes + O.bytes + W.bytes + L.bytes + H.bytes + rank_sb.bytes + sel.bytes + poff.bytes +
                  pcol.bytes + perm.bytes + inv.bytes + heavy.bytes + hstart.bytes + hdeg.bytes + hw.bytes +
-                 seg_off.bytes + seg_map.bytes + dec_tmp.bytes;
+                 seg_off.bytes + seg_map.bytes + (dec ? dec->bytes() : 0);
     return b;
 }
 
@@ -155,6 +155,7 @@ extern "C" void lg_free(lg_graph *g) {
     (void)hipDeviceSynchronize();
     lg::bfs_free(g);
     lg::pr_free(g);
+    delete g->dec;
     delete g;
 }
 

@@ -24,53 +24,33 @@
 
 namespace lg {
 
-struct BfsWork {
-    uint32_t n = 0;
-    DevBuf qa, qb;              // frontier queues (stored labels)
-    DevBuf fstart, fdeg, fw;    // per frontier entry: first bit/element, degree, width
-    DevBuf fscan;               // exclusive scan of fdeg
-    DevBuf visited, curr, next; // bitmaps, one bit per vertex
-    DevBuf counters;            // [0] queue tail, [1] awakened count, [2] pending count
-    DevBuf pv, pstart, pdeg, pw; // bottom-up: heavy vertices left for the segment pass
-    DevBuf pseg_cnt, pseg_off;
-    DevBuf depth_i, parent_i;   // label-space results when relabeled
-    DevBuf scan_tmp;
-    uint64_t *host = nullptr;   // pinned readback slots
-};
-
-uint64_t bfs_bytes(const lg_graph *g) {
-    if (!g->bfs) return 0;
-    const BfsWork *w = g->bfs;
-    return w->qa.bytes + w->qb.bytes + w->fstart.bytes + w->fdeg.bytes + w->fw.bytes + w->fscan.bytes +
-           w->visited.bytes + w->curr.bytes + w->next.bytes + w->counters.bytes + w->depth_i.bytes +
-           w->parent_i.bytes + w->scan_tmp.bytes + w->pv.bytes + w->pstart.bytes + w->pdeg.bytes + w->pw.bytes +
-           w->pseg_cnt.bytes + w->pseg_off.bytes;
+uint64_t BfsWork::bytes() const {
+    return qa.bytes + qb.bytes + fstart.bytes + fdeg.bytes + fw.bytes + fscan.bytes + visited.bytes + curr.bytes +
+           next.bytes + counters.bytes + depth_i.bytes + parent_i.bytes + scan_tmp.bytes + pv.bytes + pstart.bytes +
+           pdeg.bytes + pw.bytes + pseg_cnt.bytes + pseg_off.bytes;
 }
 
+BfsWork::~BfsWork() {
+    if (host) (void)hipHostFree(host);
+}
+
+uint64_t bfs_bytes(const lg_graph *g) { return g->bfs ? g->bfs->bytes() : 0; }
+
 lg_status bfs_free(lg_graph *g) {
-    if (g->bfs) {
-        if (g->bfs->host) (void)hipHostFree(g->bfs->host);
-        delete g->bfs;
-        g->bfs = nullptr;
-    }
+    delete g->bfs;
+    g->bfs = nullptr;
     return LG_OK;
 }
 
-static lg_status bfs_workspace(lg_graph *g, bool need_parent) {
-    if (!g->bfs) {
-        g->bfs = new (std::nothrow) BfsWork();
-        if (!g->bfs) { set_error("lg_bfs: host allocation failed"); return LG_ERR_OOM; }
-        if (hipHostMalloc((void **)&g->bfs->host, 8 * sizeof(uint64_t)) != hipSuccess) {
-            g->bfs->host = nullptr;
-            bfs_free(g);
+lg_status bfs_workspace_ensure(BfsWork &w, uint64_t n, uint64_t n_heavy, bool relabel, bool need_parent) {
+    if (!w.host) {
+        if (hipHostMalloc((void **)&w.host, 8 * sizeof(uint64_t)) != hipSuccess) {
+            w.host = nullptr;
             set_error("lg_bfs: pinned host allocation failed");
             return LG_ERR_OOM;
         }
     }
-    BfsWork &w = *g->bfs;
-    const uint64_t n = g->n;
     const uint64_t words = (n + 63) / 64;
-    w.n = g->n;
     LG_TRY(w.qa.ensure(n * 4));
     LG_TRY(w.qb.ensure(n * 4));
     LG_TRY(w.fstart.ensure(n * 8));
@@ -81,14 +61,14 @@ static lg_status bfs_workspace(lg_graph *g, bool need_parent) {
     LG_TRY(w.curr.ensure(words * 8));
     LG_TRY(w.next.ensure(words * 8));
     LG_TRY(w.counters.ensure(8 * 8));
-    const uint64_t nh = g->n_heavy ? g->n_heavy : 1;
+    const uint64_t nh = n_heavy ? n_heavy : 1;
     LG_TRY(w.pv.ensure(nh * 4));
     LG_TRY(w.pstart.ensure(nh * 8));
     LG_TRY(w.pdeg.ensure(nh * 4));
     LG_TRY(w.pw.ensure(nh * 4));
     LG_TRY(w.pseg_cnt.ensure(nh * 4));
     LG_TRY(w.pseg_off.ensure((nh + 1) * 8));
-    if (g->relabel == LG_RELABEL_DEGREE) {
+    if (relabel) {
         LG_TRY(w.depth_i.ensure(n * 4));
         if (need_parent) LG_TRY(w.parent_i.ensure(n * 4));
     }
@@ -415,9 +395,8 @@ struct BfsParams {
 };
 
 template <class Acc>
-static lg_status bfs_one(lg_graph *g, Acc acc, uint32_t root_label, int32_t *depth, uint32_t *parent,
+static lg_status bfs_one(lg_graph *g, BfsWork &w, Acc acc, uint32_t root_label, int32_t *depth, uint32_t *parent,
                          int32_t max_depth, uint32_t flags, hipStream_t s) {
-    BfsWork &w = *g->bfs;
     const uint32_t n = g->n;
     const uint64_t words = ((uint64_t)n + 63) / 64;
     const BfsParams prm;
@@ -534,6 +513,36 @@ static lg_status bfs_one(lg_graph *g, Acc acc, uint32_t root_label, int32_t *dep
     return LG_OK;
 }
 
+lg_status bfs_run(lg_graph *g, BfsWork &w, const uint32_t *roots, uint32_t r, int32_t *depth, int32_t *parent,
+                  int32_t max_depth, uint32_t flags, hipStream_t stream) {
+    if (r == 0) return LG_OK;
+    LG_TRY(bfs_workspace_ensure(w, g->n, g->n_heavy, g->relabel == LG_RELABEL_DEGREE, parent != nullptr));
+    const bool rel = g->relabel == LG_RELABEL_DEGREE;
+    return dispatch_acc(g, [&](auto acc) -> lg_status {
+        for (uint32_t i = 0; i < r; ++i) {
+            int32_t *d_out = depth + (uint64_t)i * g->n;
+            int32_t *p_out = parent ? parent + (uint64_t)i * g->n : nullptr;
+            uint32_t root_label = roots[i];
+            if (rel) {
+                LG_CHECK_HIP(hipMemcpyAsync(w.host + 2, g->inv.as<uint32_t>() + roots[i], 4, hipMemcpyDeviceToHost,
+                                            stream));
+                LG_CHECK_HIP(hipStreamSynchronize(stream));
+                root_label = *reinterpret_cast<uint32_t *>(w.host + 2);
+                LG_TRY(bfs_one(g, w, acc, root_label, w.depth_i.as<int32_t>(),
+                               p_out ? w.parent_i.as<uint32_t>() : nullptr, max_depth, flags, stream));
+                LG_LAUNCH(bfs_unpermute_kernel, grid_for(g->n, 256, 1u << 16), 256, 0, stream, g->n,
+                          g->inv.as<uint32_t>(), g->perm.as<uint32_t>(), w.depth_i.as<int32_t>(),
+                          p_out ? w.parent_i.as<uint32_t>() : nullptr, d_out, p_out);
+                LG_CHECK_LAUNCH();
+            } else {
+                LG_TRY(bfs_one(g, w, acc, root_label, d_out, reinterpret_cast<uint32_t *>(p_out), max_depth, flags,
+                               stream));
+            }
+        }
+        return LG_OK;
+    });
+}
+
 }  // namespace lg
 
 extern "C" lg_status lg_bfs(const lg_graph *gc, const uint32_t *roots, uint32_t r, int32_t *depth, int32_t *parent,
@@ -545,31 +554,9 @@ extern "C" lg_status lg_bfs(const lg_graph *gc, const uint32_t *roots, uint32_t 
     for (uint32_t i = 0; i < r; ++i)
         if (roots[i] >= g->n) { set_error("lg_bfs: root %u out of range", roots[i]); return LG_ERR_INVALID; }
     if (r == 0) return LG_OK;
-    LG_TRY(bfs_workspace(g, parent != nullptr));
-    const bool rel = g->relabel == LG_RELABEL_DEGREE;
-    uint32_t *inv_host = nullptr;
-    (void)inv_host;
-    return dispatch_acc(g, [&](auto acc) -> lg_status {
-        for (uint32_t i = 0; i < r; ++i) {
-            int32_t *d_out = depth + (uint64_t)i * g->n;
-            int32_t *p_out = parent ? parent + (uint64_t)i * g->n : nullptr;
-            uint32_t root_label = roots[i];
-            if (rel) {
-                LG_CHECK_HIP(hipMemcpyAsync(g->bfs->host + 2, g->inv.as<uint32_t>() + roots[i], 4,
-                                            hipMemcpyDeviceToHost, stream));
-                LG_CHECK_HIP(hipStreamSynchronize(stream));
-                root_label = *reinterpret_cast<uint32_t *>(g->bfs->host + 2);
-                LG_TRY(bfs_one(g, acc, root_label, g->bfs->depth_i.as<int32_t>(),
-                               p_out ? g->bfs->parent_i.as<uint32_t>() : nullptr, max_depth, flags, stream));
-                LG_LAUNCH(bfs_unpermute_kernel, grid_for(g->n, 256, 1u << 16), 256, 0, stream, g->n,
-                          g->inv.as<uint32_t>(), g->perm.as<uint32_t>(), g->bfs->depth_i.as<int32_t>(),
-                          p_out ? g->bfs->parent_i.as<uint32_t>() : nullptr, d_out, p_out);
-                LG_CHECK_LAUNCH();
-            } else {
-                LG_TRY(bfs_one(g, acc, root_label, d_out, reinterpret_cast<uint32_t *>(p_out), max_depth, flags,
-                               stream));
-            }
-        }
-        return LG_OK;
-    });
+    if (!g->bfs) {
+        g->bfs = new (std::nothrow) BfsWork();
+        if (!g->bfs) { set_error("lg_bfs: host allocation failed"); return LG_ERR_OOM; }
+    }
+    return bfs_run(g, *g->bfs, roots, r, depth, parent, max_depth, flags, stream);
 }

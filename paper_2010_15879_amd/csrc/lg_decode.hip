@@ -53,44 +53,52 @@ __global__ void dec_unkey_kernel(uint64_t total, const uint64_t *__restrict__ ke
         out[j] = (uint32_t)keys[j];
 }
 
-}  // namespace lg
+DecodeWork::~DecodeWork() {
+    if (host) (void)hipHostFree(host);
+}
 
-extern "C" lg_status lg_decode_neighbors(const lg_graph *gc, const uint32_t *vertices, uint32_t k,
-                                         uint64_t *out_off, uint32_t *out_ids, uint64_t cap, uint32_t flags,
-                                         hipStream_t stream) {
-    using namespace lg;
-    lg_graph *g = const_cast<lg_graph *>(gc);
-    if (!g || !out_off || (k && !vertices)) { set_error("lg_decode_neighbors: NULL argument"); return LG_ERR_INVALID; }
-    if (flags > LG_DECODE_RAW) { set_error("lg_decode_neighbors: unknown flags"); return LG_ERR_INVALID; }
+uint64_t DecodeWork::bytes() const {
+    return head.bytes + scan_tmp.bytes + keys.bytes + keys2.bytes + vals.bytes + vals2.bytes + sort_tmp.bytes;
+}
+
+lg_status decode_run(lg_graph *g, DecodeWork &w, const uint32_t *vertices, uint32_t k, uint64_t *out_off,
+                     uint32_t *out_ids, uint64_t cap, uint32_t flags, hipStream_t stream, uint64_t *total_out) {
+    if (total_out) *total_out = 0;
     if (k == 0) return fill_u64(out_off, 0, 1, stream);
+    if (!w.host) {
+        if (hipHostMalloc((void **)&w.host, 4 * sizeof(uint64_t)) != hipSuccess) {
+            w.host = nullptr;
+            set_error("lg_decode_neighbors: pinned host allocation failed");
+            return LG_ERR_OOM;
+        }
+    }
     const bool rel = g->relabel == LG_RELABEL_DEGREE;
     const uint32_t *inv = (rel && flags != LG_DECODE_RAW) ? g->inv.as<uint32_t>() : nullptr;
     const uint32_t *perm = (rel && flags != LG_DECODE_RAW) ? g->perm.as<uint32_t>() : nullptr;
     const bool sorted = rel && flags == LG_DECODE_SORTED;
 
-    // scratch: labels (k) | degrees (k) | flag | scan tmp (separate buffer)
-    DevBuf scan_tmp;
-    const uint64_t head = ((uint64_t)k * 8 + 8 + 7) & ~7ull;
-    LG_TRY(g->dec_tmp.ensure(head));
-    uint32_t *labels = g->dec_tmp.as<uint32_t>();
+    // head: labels (k) | degrees (k) | flag
+    LG_TRY(w.head.ensure(((uint64_t)k * 8 + 8 + 7) & ~7ull));
+    uint32_t *labels = w.head.as<uint32_t>();
     uint32_t *deg = labels + k;
     uint32_t *bad = deg + k;
     LG_TRY(fill_u32(bad, 0, 1, stream));
     LG_LAUNCH(dec_map_kernel, grid_for(k, 256, 1u << 16), 256, 0, stream, g->n, vertices, k, inv, labels, bad);
     LG_CHECK_LAUNCH();
-    uint32_t host_bad = 0;
-    LG_CHECK_HIP(hipMemcpyAsync(&host_bad, bad, 4, hipMemcpyDeviceToHost, stream));
-    LG_CHECK_HIP(hipStreamSynchronize(stream));
-    if (host_bad) { set_error("lg_decode_neighbors: vertex id >= n"); return LG_ERR_INVALID; }
-
     return dispatch_acc(g, [&](auto acc) -> lg_status {
         using Acc = decltype(acc);
         LG_LAUNCH(dec_degree_kernel<Acc>, grid_for(k, 256, 1u << 16), 256, 0, stream, acc, labels, k, deg);
         LG_CHECK_LAUNCH();
-        LG_TRY(exclusive_scan_u32(deg, out_off, k, scan_tmp, stream));
-        uint64_t total = 0;
-        LG_CHECK_HIP(hipMemcpyAsync(&total, out_off + k, 8, hipMemcpyDeviceToHost, stream));
+        LG_TRY(exclusive_scan_u32(deg, out_off, k, w.scan_tmp, stream));
+        LG_CHECK_HIP(hipMemcpyAsync(w.host, out_off + k, 8, hipMemcpyDeviceToHost, stream));
+        LG_CHECK_HIP(hipMemcpyAsync(w.host + 1, bad, 4, hipMemcpyDeviceToHost, stream));
         LG_CHECK_HIP(hipStreamSynchronize(stream));
+        if (*reinterpret_cast<uint32_t *>(w.host + 1)) {
+            set_error("lg_decode_neighbors: vertex id >= n");
+            return LG_ERR_INVALID;
+        }
+        const uint64_t total = w.host[0];
+        if (total_out) *total_out = total;
         if (!out_ids || total > cap) {
             set_error("lg_decode_neighbors: %llu ids do not fit in capacity %llu", (unsigned long long)total,
                       (unsigned long long)cap);
@@ -102,23 +110,39 @@ extern "C" lg_status lg_decode_neighbors(const lg_graph *gc, const uint32_t *ver
             LG_LAUNCH((dec_lists_kernel<Acc, false>), grid, 256, 0, stream, acc, labels, k, (const uint64_t *)out_off,
                       perm, out_ids, (uint64_t *)nullptr);
             LG_CHECK_LAUNCH();
-            LG_CHECK_HIP(hipStreamSynchronize(stream));
             return LG_OK;
         }
-        DevBuf keys, keys2, vals, vals2, sort_tmp;
-        LG_TRY(keys.alloc(total * 8));
-        LG_TRY(keys2.alloc(total * 8));
-        LG_TRY(vals.alloc(total * 4));
-        LG_TRY(vals2.alloc(total * 4));
+        LG_TRY(w.keys.ensure(total * 8));
+        LG_TRY(w.keys2.ensure(total * 8));
+        LG_TRY(w.vals.ensure(total * 4));
+        LG_TRY(w.vals2.ensure(total * 4));
         LG_LAUNCH((dec_lists_kernel<Acc, true>), grid, 256, 0, stream, acc, labels, k, (const uint64_t *)out_off, perm,
-                  out_ids, keys.as<uint64_t>());
+                  out_ids, w.keys.as<uint64_t>());
         LG_CHECK_LAUNCH();
         const uint32_t bits = 32 + bitlen_u64(k - 1);
-        LG_TRY(radix_sort_pairs64(keys.as<uint64_t>(), vals.as<uint32_t>(), keys2.as<uint64_t>(), vals2.as<uint32_t>(),
-                                  total, bits, sort_tmp, stream));
-        LG_LAUNCH(dec_unkey_kernel, grid_for(total, 256, 1u << 16), 256, 0, stream, total, keys.as<uint64_t>(), out_ids);
+        LG_TRY(radix_sort_pairs64(w.keys.as<uint64_t>(), w.vals.as<uint32_t>(), w.keys2.as<uint64_t>(),
+                                  w.vals2.as<uint32_t>(), total, bits, w.sort_tmp, stream));
+        LG_LAUNCH(dec_unkey_kernel, grid_for(total, 256, 1u << 16), 256, 0, stream, total, w.keys.as<uint64_t>(),
+                  out_ids);
         LG_CHECK_LAUNCH();
-        LG_CHECK_HIP(hipStreamSynchronize(stream));
         return LG_OK;
     });
+}
+
+}  // namespace lg
+
+extern "C" lg_status lg_decode_neighbors(const lg_graph *gc, const uint32_t *vertices, uint32_t k,
+                                         uint64_t *out_off, uint32_t *out_ids, uint64_t cap, uint32_t flags,
+                                         hipStream_t stream) {
+    using namespace lg;
+    lg_graph *g = const_cast<lg_graph *>(gc);
+    if (!g || !out_off || (k && !vertices)) { set_error("lg_decode_neighbors: NULL argument"); return LG_ERR_INVALID; }
+    if (flags > LG_DECODE_RAW) { set_error("lg_decode_neighbors: unknown flags"); return LG_ERR_INVALID; }
+    if (!g->dec) {
+        g->dec = new (std::nothrow) DecodeWork();
+        if (!g->dec) { set_error("lg_decode_neighbors: host allocation failed"); return LG_ERR_OOM; }
+    }
+    const lg_status st = decode_run(g, *g->dec, vertices, k, out_off, out_ids, cap, flags, stream, nullptr);
+    if (st == LG_OK) LG_CHECK_HIP(hipStreamSynchronize(stream));
+    return st;
 }

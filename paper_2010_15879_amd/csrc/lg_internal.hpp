@@ -101,8 +101,38 @@ struct PlainView {
 // the graph handle
 // ---------------------------------------------------------------------------
 
-struct BfsWork;
 struct PrWork;
+
+// Device workspace of one BFS at a time (grow-only buffers).
+struct BfsWork {
+    DevBuf qa, qb;               // frontier queues (stored labels)
+    DevBuf fstart, fdeg, fw;     // per frontier entry: first bit/element, degree, width
+    DevBuf fscan;                // exclusive scan of fdeg
+    DevBuf visited, curr, next;  // bitmaps, one bit per vertex
+    DevBuf counters;             // [0] queue tail, [1] awakened count, [2] pending count
+    DevBuf pv, pstart, pdeg, pw; // bottom-up: heavy vertices left for the segment pass
+    DevBuf pseg_cnt, pseg_off;
+    DevBuf depth_i, parent_i;    // label-space results when relabeled
+    DevBuf scan_tmp;
+    uint64_t *host = nullptr;    // pinned readback slots
+    BfsWork() = default;
+    BfsWork(const BfsWork &) = delete;
+    BfsWork &operator=(const BfsWork &) = delete;
+    ~BfsWork();
+    uint64_t bytes() const;
+};
+
+// Device workspace of one neighbor decode at a time (grow-only buffers).
+struct DecodeWork {
+    DevBuf head;                 // labels, degrees, flag
+    DevBuf scan_tmp, keys, keys2, vals, vals2, sort_tmp;
+    uint64_t *host = nullptr;    // pinned readback slots
+    DecodeWork() = default;
+    DecodeWork(const DecodeWork &) = delete;
+    DecodeWork &operator=(const DecodeWork &) = delete;
+    ~DecodeWork();
+    uint64_t bytes() const;
+};
 
 }  // namespace lg
 
@@ -140,10 +170,11 @@ struct lg_graph {
     uint64_t heavy_edges = 0, heavy_bits = 0;  // entries and bits (packed) of the heavy lists
     bool segs_built = false;
 
-    // lazily allocated workspaces
+    // lazily allocated workspaces of the plain calls (lg_bfs, lg_pagerank,
+    // lg_decode_neighbors); the server brings its own per worker
     lg::BfsWork *bfs = nullptr;
     lg::PrWork *pr = nullptr;
-    lg::DevBuf dec_tmp;        // lg_decode_neighbors scratch
+    lg::DecodeWork *dec = nullptr;
 
     lg::PackedView packed_view() const;
     lg::PlainView plain_view() const;
@@ -190,6 +221,11 @@ lg_status exclusive_scan_u32(const uint32_t *in, uint64_t *out, uint64_t count, 
 lg_status exclusive_scan_u64(const uint64_t *in, uint64_t *out, uint64_t count, DevBuf &tmp,
                              hipStream_t s);
 
+// Scratch bytes the scans and sorts below grow `tmp` to for `count` items
+// (non-decreasing in count).
+uint64_t scan_tmp_bytes(uint64_t count);
+uint64_t radix_sort_tmp_bytes(uint64_t count);
+
 // Stable LSD radix sort of (key, value) pairs on key bits [0, bits).
 // Results end in keys/vals (the buffers are ping-ponged with the alt ones).
 lg_status radix_sort_pairs(uint32_t *keys, uint32_t *vals, uint32_t *keys_alt, uint32_t *vals_alt,
@@ -213,6 +249,13 @@ inline uint32_t bitlen_u64(uint64_t x) { return x ? 64u - (uint32_t)__builtin_cl
 lg_status ensure_heavy_segments(lg_graph *g, hipStream_t s);
 
 lg_status bfs_free(lg_graph *g);
+lg_status bfs_workspace_ensure(BfsWork &w, uint64_t n, uint64_t n_heavy, bool relabel, bool need_parent);
+// BFS from host roots on an explicit workspace (lg_bfs without argument checks)
+lg_status bfs_run(lg_graph *g, BfsWork &w, const uint32_t *roots, uint32_t r, int32_t *depth, int32_t *parent,
+                  int32_t max_depth, uint32_t flags, hipStream_t stream);
+// lg_decode_neighbors on an explicit workspace
+lg_status decode_run(lg_graph *g, DecodeWork &w, const uint32_t *vertices, uint32_t k, uint64_t *out_off,
+                     uint32_t *out_ids, uint64_t cap, uint32_t flags, hipStream_t stream, uint64_t *total);
 lg_status pr_free(lg_graph *g);
 
 }  // namespace lg

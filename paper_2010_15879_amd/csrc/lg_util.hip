@@ -125,6 +125,8 @@ static uint64_t scan_tmp_words(uint64_t count) {
     return words + 1;
 }
 
+uint64_t scan_tmp_bytes(uint64_t count) { return count ? scan_tmp_words(count) * sizeof(uint64_t) : 0; }
+
 lg_status exclusive_scan_u32(const uint32_t *in, uint64_t *out, uint64_t count, DevBuf &tmp, hipStream_t s) {
     if (count == 0) return fill_u64(out, 0, 1, s);
     LG_TRY(tmp.ensure(scan_tmp_words(count) * sizeof(uint64_t)));
@@ -238,6 +240,12 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
     }
 }
 
+uint64_t radix_sort_tmp_bytes(uint64_t count) {
+    if (count <= 1) return 0;
+    const uint64_t ncount = (count + kSortTile - 1) / kSortTile * 256;
+    return ((ncount * 4 + 7) & ~7ull) + (ncount + 1) * 8 + scan_tmp_words(ncount) * 8;
+}
+
 template <class K>
 static lg_status radix_sort_impl(K *keys, uint32_t *vals, K *keys_alt, uint32_t *vals_alt, uint64_t count,
                                  uint32_t bits, DevBuf &tmp, hipStream_t s) {
@@ -248,10 +256,8 @@ static lg_status radix_sort_impl(K *keys, uint32_t *vals, K *keys_alt, uint32_t 
         return LG_ERR_UNSUPPORTED;
     }
     const uint64_t ncount = ntiles * 256;
-    const uint64_t scan_words = scan_tmp_words(ncount);
     // layout of tmp: counts (u32, ncount) | offsets (u64, ncount + 1) | scan scratch
-    const uint64_t bytes = ((ncount * 4 + 7) & ~7ull) + (ncount + 1) * 8 + scan_words * 8;
-    LG_TRY(tmp.ensure(bytes));
+    LG_TRY(tmp.ensure(radix_sort_tmp_bytes(count)));
     uint32_t *counts = tmp.as<uint32_t>();
     uint64_t *offs = reinterpret_cast<uint64_t *>(tmp.as<char>() + ((ncount * 4 + 7) & ~7ull));
     uint64_t *scratch = offs + ncount + 1;

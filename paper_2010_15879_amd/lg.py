@@ -64,6 +64,32 @@ class BatchInfo(C.Structure):
                 ("tuned_ms", C.c_double), ("scratch_bytes", C.c_uint64)]
 
 
+class ServerOpts(C.Structure):
+    _fields_ = [("budget_bytes", C.c_uint64), ("workers", C.c_uint32), ("max_batch", C.c_uint32),
+                ("reserved", C.c_uint32 * 4)]
+
+
+class Query(C.Structure):
+    _fields_ = [("kind", C.c_uint32), ("graph", C.c_uint32), ("vertex", C.c_uint32), ("k", C.c_int32),
+                ("flags", C.c_uint32), ("reserved", C.c_uint32)]
+
+
+class QueryResult(C.Structure):
+    _fields_ = [("status", C.c_int32), ("kind", C.c_uint32), ("count", C.c_uint64),
+                ("ids", C.POINTER(C.c_uint32)), ("depth", C.POINTER(C.c_int32)), ("parent", C.POINTER(C.c_int32)),
+                ("n", C.c_uint64), ("max_depth", C.c_int32), ("batch", C.c_uint32), ("digest", C.c_uint64),
+                ("queue_ms", C.c_double), ("service_ms", C.c_double), ("latency_ms", C.c_double)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [("submitted", C.c_uint64), ("completed", C.c_uint64), ("rejected", C.c_uint64),
+                ("queued", C.c_uint64), ("running", C.c_uint64), ("budget_bytes", C.c_uint64),
+                ("resident_bytes", C.c_uint64), ("in_use_bytes", C.c_uint64), ("peak_bytes", C.c_uint64),
+                ("workers", C.c_uint32), ("overruns", C.c_uint32), ("batches", C.c_uint64)]
+
+
+QUERY_KINDS = {"neighbors": 0, "khop": 1, "bfs": 2}
+
 _lib = None
 
 FUNCTIONS = {
@@ -88,6 +114,17 @@ FUNCTIONS = {
     "lg_bfs_batch_run": (C.c_int, [C.c_void_p, C.c_void_p]),
     "lg_bfs_batch_info": (C.c_int, [C.c_void_p, C.POINTER(BatchInfo)]),
     "lg_bfs_batch_free": (None, [C.c_void_p]),
+    "lg_server_create": (C.c_int, [C.POINTER(C.c_void_p), C.c_uint32, C.POINTER(ServerOpts), C.POINTER(C.c_void_p)]),
+    "lg_server_submit": (C.c_int, [C.c_void_p, C.POINTER(Query), C.POINTER(C.c_uint64)]),
+    "lg_server_wait": (C.c_int, [C.c_void_p, C.c_uint64, C.POINTER(QueryResult)]),
+    "lg_server_result": (C.c_int, [C.c_void_p, C.c_uint64, C.POINTER(QueryResult)]),
+    "lg_server_poll": (C.c_int, [C.c_void_p, C.POINTER(C.c_uint64), C.c_uint32, C.POINTER(C.c_uint32)]),
+    "lg_server_release": (C.c_int, [C.c_void_p, C.c_uint64]),
+    "lg_server_get_stats": (C.c_int, [C.c_void_p, C.POINTER(ServerStats)]),
+    "lg_server_free": (None, [C.c_void_p]),
+    "lg_admission_simulate": (C.c_int, [C.POINTER(C.c_double), C.POINTER(C.c_uint64), C.POINTER(C.c_double),
+                                        C.c_uint32, C.c_uint64, C.c_uint64, C.c_uint32, C.POINTER(C.c_double),
+                                        C.POINTER(C.c_double), C.POINTER(C.c_int32), C.POINTER(C.c_uint64)]),
 }
 
 
@@ -304,3 +341,90 @@ class BatchPlan:
             self.free()
         except Exception:
             pass
+
+
+# -- query server -----------------------------------------------------------
+
+class Server:
+    """lg_server_*: queries over resident graphs, served by worker threads with
+    their own streams, admitted under a device-memory budget."""
+
+    def __init__(self, graphs, budget_bytes=0, workers=8, max_batch=64):
+        self.graphs = list(graphs)
+        arr = (C.c_void_p * len(self.graphs))(*[g.handle.value for g in self.graphs])
+        opts = ServerOpts(int(budget_bytes), int(workers), int(max_batch))
+        out = C.c_void_p()
+        _check(lib().lg_server_create(arr, len(self.graphs), C.byref(opts), C.byref(out)))
+        self._s = out
+
+    def submit(self, kind, graph, vertex, k=0, keep_arrays=False) -> int:
+        q = Query(QUERY_KINDS[kind], graph, vertex, k, 1 if keep_arrays else 0, 0)
+        t = C.c_uint64()
+        _check(lib().lg_server_submit(self._s, C.byref(q), C.byref(t)))
+        return int(t.value)
+
+    @staticmethod
+    def _unpack(r: QueryResult, arrays=True) -> dict:
+        out = {k: getattr(r, k) for k, _ in QueryResult._fields_ if k not in ("ids", "depth", "parent")}
+        if not arrays:
+            return out
+        out["ids"] = np.ctypeslib.as_array(r.ids, shape=(r.count,)).copy() if r.ids else np.zeros(0, np.uint32)
+        if r.depth:
+            out["depth"] = np.ctypeslib.as_array(r.depth, shape=(r.n,)).copy()
+            out["parent"] = np.ctypeslib.as_array(r.parent, shape=(r.n,)).copy()
+        return out
+
+    def wait(self, ticket: int, release=True, arrays=True) -> dict:
+        """Block until the query completes; arrays=False skips copying the
+        returned IDs / BFS arrays into numpy."""
+        r = QueryResult()
+        _check(lib().lg_server_wait(self._s, ticket, C.byref(r)))
+        out = self._unpack(r, arrays)
+        if release:
+            lib().lg_server_release(self._s, ticket)
+        return out
+
+    def poll(self, cap=4096) -> list:
+        arr = (C.c_uint64 * cap)()
+        cnt = C.c_uint32()
+        _check(lib().lg_server_poll(self._s, arr, cap, C.byref(cnt)))
+        return [int(arr[i]) for i in range(cnt.value)]
+
+    def result(self, ticket: int, release=True) -> dict:
+        r = QueryResult()
+        _check(lib().lg_server_result(self._s, ticket, C.byref(r)))
+        out = self._unpack(r)
+        if release:
+            lib().lg_server_release(self._s, ticket)
+        return out
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        _check(lib().lg_server_get_stats(self._s, C.byref(st)))
+        return {k: getattr(st, k) for k, _ in ServerStats._fields_}
+
+    def free(self):
+        if self._s:
+            lib().lg_server_free(self._s)
+            self._s = C.c_void_p(None)
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def admission_simulate(arrival, need, service, budget, resident, workers):
+    """Host-only model of the server's admission (lg_admission_simulate)."""
+    n = len(arrival)
+    a = (C.c_double * max(n, 1))(*arrival)
+    nd = (C.c_uint64 * max(n, 1))(*[int(x) for x in need])
+    sv = (C.c_double * max(n, 1))(*service)
+    st = (C.c_double * max(n, 1))()
+    fi = (C.c_double * max(n, 1))()
+    ss = (C.c_int32 * max(n, 1))()
+    pk = C.c_uint64()
+    _check(lib().lg_admission_simulate(a, nd, sv, n, int(budget), int(resident), int(workers), st, fi, ss,
+                                       C.byref(pk)))
+    return list(st)[:n], list(fi)[:n], list(ss)[:n], int(pk.value)
