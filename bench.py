@@ -124,11 +124,13 @@ def main():
     degf = deg.to(torch.float64)
 
     if args.pr_only:
-        # A plain copy of known size calibrates the HBM byte counters, then one
-        # PageRank call runs the iteration kernel args.pr_iters times.
+        # A kernel of known traffic calibrates the HBM byte counters (an
+        # elementwise kernel that reads 1 GiB and writes 1 GiB; a tensor copy
+        # would run on a DMA engine, not as a kernel), then one PageRank call
+        # runs the iteration kernel args.pr_iters times.
         src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
-        dst.copy_(src)
+        torch.add(src, 1.0, out=dst)
         torch.cuda.synchronize()
         del src, dst
         h = lg.encode(g.row_offsets, g.col, n, layout="packed", **enc)

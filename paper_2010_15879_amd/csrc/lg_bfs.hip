@@ -79,15 +79,17 @@ lg_status bfs_workspace_ensure(BfsWork &w, uint64_t n, uint64_t n_heavy, bool re
 // kernels
 // ---------------------------------------------------------------------------
 
+// visited starts as the root plus every vertex without edges (never reached,
+// never a neighbor), so bottom-up sweeps skip words of such vertices
 __global__ void bfs_init_kernel(uint32_t n, int32_t *__restrict__ depth, uint32_t *__restrict__ parent,
-                                uint64_t *__restrict__ visited, uint32_t root, uint32_t *__restrict__ queue,
-                                uint64_t *__restrict__ counters) {
+                                const uint64_t *__restrict__ iso, uint64_t *__restrict__ visited, uint32_t root,
+                                uint32_t *__restrict__ queue, uint64_t *__restrict__ counters) {
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     const uint64_t words = ((uint64_t)n + 63) / 64;
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
         depth[i] = i == root ? 0 : -1;
         if (parent) parent[i] = i == root ? root : 0xFFFFFFFFu;
-        if (i < words) visited[i] = (i == (root >> 6)) ? (1ull << (root & 63)) : 0ull;
+        if (i < words) visited[i] = iso[i] | ((i == (root >> 6)) ? (1ull << (root & 63)) : 0ull);
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         queue[0] = root;
@@ -405,7 +407,8 @@ static lg_status bfs_one(lg_graph *g, BfsWork &w, Acc acc, uint32_t root_label, 
     unsigned long long *ctr = w.counters.as<unsigned long long>();
     const uint32_t gsz = grid_for(n, 256, 1u << 16);
 
-    LG_LAUNCH(bfs_init_kernel, gsz, 256, 0, s, n, depth, parent, visited, root_label, qin, (uint64_t *)ctr);
+    LG_LAUNCH(bfs_init_kernel, gsz, 256, 0, s, n, depth, parent, g->iso.as<uint64_t>(), visited, root_label, qin,
+              (uint64_t *)ctr);
     LG_CHECK_LAUNCH();
 
     uint64_t qsize = 1;

@@ -337,6 +337,20 @@ __global__ void heavy_flag_kernel(uint32_t n, const uint64_t *__restrict__ off, 
         flag[v] = (off[v + 1] - off[v]) > threshold ? 1u : 0u;
 }
 
+// bit v of word v/64: vertex v has no edges, or v >= n (padding)
+__global__ void isolated_bitmap_kernel(uint32_t n, const uint64_t *__restrict__ off, uint64_t *__restrict__ iso) {
+    const uint64_t words = ((uint64_t)n + 63) / 64;
+    const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) / kWave;
+    const uint32_t lane = lane_id();
+    for (uint64_t q = wave; q < words; q += nwaves) {
+        const uint64_t v = q * 64 + lane;
+        const bool empty = v >= n || off[v + 1] == off[v];
+        const uint64_t m = __ballot(empty);
+        if (lane == 0) iso[q] = m;
+    }
+}
+
 __global__ void heavy_scatter_kernel(uint32_t n, const uint32_t *__restrict__ flag, const uint64_t *__restrict__ pos,
                                      uint32_t *__restrict__ heavy) {
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
@@ -511,6 +525,11 @@ static lg_status encode_impl(uint32_t n, uint64_t m, const uint64_t *row_offsets
         LG_TRY(g->heavy.alloc((nh ? nh : 1) * 4));
         LG_LAUNCH(heavy_scatter_kernel, grid1(n), 256, 0, s, n, flag.as<uint32_t>(), pos.as<uint64_t>(),
                   g->heavy.as<uint32_t>());
+        LG_CHECK_LAUNCH();
+        const uint64_t words = ((uint64_t)n + 63) / 64;
+        LG_TRY(g->iso.alloc(words * 8));
+        LG_LAUNCH(isolated_bitmap_kernel, grid_for(words * kWave, 256, 1u << 16), 256, 0, s, n, cur_off,
+                  g->iso.as<uint64_t>());
         LG_CHECK_LAUNCH();
         LG_CHECK_HIP(hipStreamSynchronize(s));
     }

@@ -1,8 +1,14 @@
-// Heavy-vertex segment table shared by the bottom-up BFS step and the
-// PageRank pull: every vertex of degree above the threshold gets its
-// (first bit, degree, width) cached and its list cut into segments of
-// seg_size edges, so that one wave handles one segment and no wave walks a
-// hub's whole list alone.
+// PageRank work tables (built once per graph, at the first lg_pagerank):
+//   * every heavy vertex (degree above the traversal threshold) gets its
+//     (first bit, degree, width) cached;
+//   * lists longer than pr_split are cut into segments of seg_size edges,
+//     one wave per segment, so that no wave walks a hub's list alone;
+//   * all other vertices are grouped into units: consecutive vertices of one
+//     64-aligned block whose first edges fall into the same window of
+//     pr_unit_edges edges of that block.  A unit then holds at most 64
+//     vertices and at most pr_unit_edges + pr_split edges, and a wave takes
+//     one unit at a time, so waves get comparable work whatever the degree
+//     distribution, without giving a wave to a list of a hundred edges.
 #include "lg_device.hpp"
 
 namespace lg {
@@ -10,14 +16,15 @@ namespace lg {
 template <class Acc>
 __global__ void heavy_info_kernel(Acc acc, const uint32_t *__restrict__ heavy, uint32_t n_heavy,
                                   uint64_t *__restrict__ hstart, uint32_t *__restrict__ hdeg,
-                                  uint32_t *__restrict__ hw, uint32_t seg_size, uint32_t *__restrict__ segcnt) {
+                                  uint32_t *__restrict__ hw, uint32_t split, uint32_t seg_size,
+                                  uint32_t *__restrict__ segcnt) {
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t h = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; h < n_heavy; h += stride) {
         const VInfo vi = acc.info(heavy[h]);
         hstart[h] = vi.start;
         hdeg[h] = vi.deg;
         hw[h] = vi.w;
-        segcnt[h] = (vi.deg + seg_size - 1) / seg_size;
+        segcnt[h] = vi.deg > split ? (vi.deg + seg_size - 1) / seg_size : 0u;
     }
 }
 
@@ -44,24 +51,55 @@ __global__ void heavy_seg_map_kernel(uint32_t n_heavy, const uint64_t *__restric
         for (uint64_t k = seg_off[h]; k < seg_off[h + 1]; ++k) seg_map[k] = (uint32_t)h;
 }
 
+// Unit starts of block q (vertices 64q .. 64q+63): the block's first vertex,
+// and every vertex whose first unit edge lies in a later window of `budget`
+// edges than its predecessor's.  Pass 1 counts them, pass 2 writes them.
+template <class Acc, bool kWrite>
+__global__ void pr_units_kernel(Acc acc, uint32_t n, uint32_t split, uint32_t budget,
+                                uint32_t *__restrict__ cnt, const uint64_t *__restrict__ off,
+                                uint32_t *__restrict__ units) {
+    const uint64_t words = ((uint64_t)n + 63) / 64;
+    const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) / kWave;
+    const uint32_t lane = lane_id();
+    for (uint64_t q = wave; q < words; q += nwaves) {
+        const VInfo vi = wave_info(acc, q * 64, n);
+        const uint64_t v = q * 64 + lane;
+        const uint32_t d = (v < n && vi.deg <= split) ? vi.deg : 0u;
+        const uint32_t excl = wave_incl_scan(d) - d;
+        const uint32_t prev = __shfl_up(excl, 1, kWave);
+        const bool start = v < n && (lane == 0 || excl / budget != prev / budget);
+        const uint64_t m = __ballot(start);
+        if (!kWrite) {
+            if (lane == 0) cnt[q] = (uint32_t)__popcll(m);
+        } else if (start) {
+            units[off[q] + popc_below(m)] = (uint32_t)v;
+        }
+    }
+}
+
 lg_status ensure_heavy_segments(lg_graph *g, hipStream_t s) {
     if (g->segs_built) return LG_OK;
     const uint32_t nh = g->n_heavy;
-    g->seg_size = 1024;
+    const uint32_t n = g->n;
+    g->seg_size = 4096;
     while (((uint64_t)g->max_degree + g->seg_size - 1) / g->seg_size > 65535) g->seg_size *= 2;
+    g->pr_split = 4096;
+    g->pr_unit_edges = 8192;
     LG_TRY(g->hstart.alloc((uint64_t)(nh ? nh : 1) * 8));
     LG_TRY(g->hdeg.alloc((uint64_t)(nh ? nh : 1) * 4));
     LG_TRY(g->hw.alloc((uint64_t)(nh ? nh : 1) * 4));
     LG_TRY(g->seg_off.alloc(((uint64_t)nh + 1) * 8));
     g->n_seg = 0;
+    DevBuf tmp;
     if (nh) {
-        DevBuf segcnt, tmp;
+        DevBuf segcnt;
         LG_TRY(segcnt.alloc((uint64_t)nh * 4));
         LG_TRY(dispatch_acc(g, [&](auto acc) -> lg_status {
             using Acc = decltype(acc);
             LG_LAUNCH(heavy_info_kernel<Acc>, grid_for(nh, 256, 1u << 16), 256, 0, s, acc, g->heavy.as<uint32_t>(),
-                      nh, g->hstart.as<uint64_t>(), g->hdeg.as<uint32_t>(), g->hw.as<uint32_t>(), g->seg_size,
-                      segcnt.as<uint32_t>());
+                      nh, g->hstart.as<uint64_t>(), g->hdeg.as<uint32_t>(), g->hw.as<uint32_t>(), g->pr_split,
+                      g->seg_size, segcnt.as<uint32_t>());
             LG_CHECK_LAUNCH();
             return LG_OK;
         }));
@@ -83,11 +121,33 @@ lg_status ensure_heavy_segments(lg_graph *g, hipStream_t s) {
         LG_TRY(fill_u64(g->seg_off.as<uint64_t>(), 0, 1, s));
     }
     LG_TRY(g->seg_map.alloc((g->n_seg ? g->n_seg : 1) * 4));
-    if (nh) {
+    LG_TRY(g->seg_part.alloc((g->n_seg ? g->n_seg : 1) * 4));
+    if (g->n_seg) {
         LG_LAUNCH(heavy_seg_map_kernel, grid_for(nh, 256, 1u << 16), 256, 0, s, nh, g->seg_off.as<uint64_t>(),
                   g->seg_map.as<uint32_t>());
         LG_CHECK_LAUNCH();
     }
+    // units
+    const uint64_t words = ((uint64_t)n + 63) / 64;
+    DevBuf cnt, uoff;
+    LG_TRY(cnt.alloc(words * 4));
+    LG_TRY(uoff.alloc((words + 1) * 8));
+    const uint32_t ugrid = grid_for(words * kWave, 256, 1u << 16);
+    LG_TRY(dispatch_acc(g, [&](auto acc) -> lg_status {
+        using Acc = decltype(acc);
+        LG_LAUNCH((pr_units_kernel<Acc, false>), ugrid, 256, 0, s, acc, n, g->pr_split, g->pr_unit_edges,
+                  cnt.as<uint32_t>(), (const uint64_t *)nullptr, (uint32_t *)nullptr);
+        LG_CHECK_LAUNCH();
+        LG_TRY(exclusive_scan_u32(cnt.as<uint32_t>(), uoff.as<uint64_t>(), words, tmp, s));
+        LG_CHECK_HIP(hipMemcpyAsync(&g->n_units, uoff.as<uint64_t>() + words, 8, hipMemcpyDeviceToHost, s));
+        LG_CHECK_HIP(hipStreamSynchronize(s));
+        LG_TRY(g->units.alloc((g->n_units + 1) * 4));
+        LG_LAUNCH((pr_units_kernel<Acc, true>), ugrid, 256, 0, s, acc, n, g->pr_split, g->pr_unit_edges,
+                  (uint32_t *)nullptr, (const uint64_t *)uoff.as<uint64_t>(), g->units.as<uint32_t>());
+        LG_CHECK_LAUNCH();
+        return LG_OK;
+    }));
+    LG_TRY(fill_u32(g->units.as<uint32_t>() + g->n_units, n, 1, s));  // sentinel
     LG_CHECK_HIP(hipStreamSynchronize(s));
     g->segs_built = true;
     return LG_OK;

@@ -161,12 +161,23 @@ struct lg_graph {
     // (PageRank) instead of one lane
     lg::DevBuf heavy;
     uint32_t n_heavy = 0;
+    // one bit per vertex (label space), set for vertices without edges and
+    // for the padding past n: BFS starts with them marked visited, so sweeps
+    // skip words that hold only such vertices
+    lg::DevBuf iso;
     uint32_t heavy_threshold = 64;
-    // per heavy vertex: first bit/element, degree, width; its list cut into
-    // segments of seg_size edges: seg_off[h] .. seg_off[h+1], seg_map[k] = h
-    lg::DevBuf hstart, hdeg, hw, seg_off, seg_map;
-    uint64_t n_seg = 0;
-    uint32_t seg_size = 1024;  // a power of two >= 1024 keeping every vertex below 65536 segments
+    // PageRank work tables, built at the first lg_pagerank.  Per heavy
+    // vertex: first bit/element, degree, width.  Vertices of degree above
+    // pr_split have their lists cut into segments of seg_size edges
+    // (seg_off[h] .. seg_off[h+1], seg_map[k] = h; seg_part[k] holds the
+    // segment's sum in the current iteration).  The other vertices are taken
+    // in units of consecutive vertices inside one 64-aligned block, at most
+    // about pr_unit_edges edges each: unit k = [units[k], units[k+1]).
+    lg::DevBuf hstart, hdeg, hw, seg_off, seg_map, seg_part, units;
+    uint64_t n_seg = 0, n_units = 0;
+    uint32_t seg_size = 4096;       // a power of two keeping every vertex below 2^16 segments
+    uint32_t pr_split = 4096;       // degree above which PageRank segments a list
+    uint32_t pr_unit_edges = 8192;  // edge budget of a unit (plus at most one list of <= pr_split)
     uint64_t heavy_edges = 0, heavy_bits = 0;  // entries and bits (packed) of the heavy lists
     bool segs_built = false;
 
@@ -245,7 +256,7 @@ inline uint32_t grid_for(uint64_t count, uint64_t per_block, uint64_t cap = 1u <
 
 inline uint32_t bitlen_u64(uint64_t x) { return x ? 64u - (uint32_t)__builtin_clzll(x) : 0u; }
 
-// Build the heavy-vertex segment table of g (once); defined in lg_heavy.hip.
+// Build the PageRank work tables of g (once); defined in lg_heavy.hip.
 lg_status ensure_heavy_segments(lg_graph *g, hipStream_t s);
 
 lg_status bfs_free(lg_graph *g);

@@ -11,34 +11,41 @@
 // D_{t+1} = z b_t (z = number of such vertices) and is passed to the kernels
 // as a scalar instead of being reduced over the graph.
 //
-// Work split (bounded work per wave, whatever the degree distribution), in
-// one kernel per iteration (pr_iter_kernel):
-//   heavy vertices (degree > threshold) are cut into segments of seg_size edges;
-//     one wave sums one segment and adds it, in fixed point, to its vertex's
-//     64-bit accumulator; the last segment to arrive finalizes the vertex
-//   light vertices are taken 64 consecutive vertices per wave; the wave's
-//     lanes walk the chunk's (at most 64 * threshold) edges 64 at a time, so
-//     consecutive lanes decode consecutive packed elements (coalesced), and a
-//     lane's running sum is flushed to its vertex's LDS accumulator when the
-//     owner changes
-// All summation orders are fixed by the data: results repeat bit for bit.
+// Work split, bounded work per wave whatever the degree distribution (the
+// tables are built once per graph, see lg_heavy.hip):
+//   lists longer than pr_split are cut into segments of seg_size edges; one
+//     wave sums one segment and stores the sum in that segment's slot
+//   all other vertices come in units (consecutive vertices of one 64-aligned
+//     block, about pr_unit_edges edges in total); the wave's lanes walk the
+//     unit's edges 64 at a time, so consecutive lanes decode consecutive
+//     packed elements (coalesced), and a lane's running sum is flushed to its
+//     vertex's LDS accumulator when the owner changes; the wave then
+//     finalizes the unit's vertices
+//   a second, small kernel adds up every segmented vertex's slots, in
+//     segment order, and finalizes it
+// Each workgroup first copies the contributions of the smallest labels into
+// LDS.  Waves then take segments, then units, by static interleaving and
+// never wait for each other; every sum is taken in an order fixed by the
+// data, so results repeat bit for bit.
+#include <algorithm>
+
 #include "lg_device.hpp"
 
 namespace lg {
 
-constexpr int kPrThreads = 256;
+constexpr int kPrThreads = 512;
 constexpr int kPrWaves = kPrThreads / kWave;
-constexpr int kBatch = 4;            // independent edges in flight per lane
+constexpr int kBatch = 4;           // independent edges in flight per lane
+constexpr uint32_t kPrHot = 16384;  // contributions each workgroup keeps in LDS (64 KiB)
 
 struct PrWork {
-    DevBuf ca, cb;                   // contrib ping-pong
-    DevBuf acc;                      // per heavy vertex: arrivals | fixed-point sum
+    DevBuf ca, cb;  // contrib ping-pong
 };
 
 uint64_t pr_bytes(const lg_graph *g) {
     if (!g->pr) return 0;
     const PrWork *w = g->pr;
-    return w->ca.bytes + w->cb.bytes + w->acc.bytes;
+    return w->ca.bytes + w->cb.bytes;
 }
 
 lg_status pr_free(lg_graph *g) {
@@ -47,95 +54,97 @@ lg_status pr_free(lg_graph *g) {
     return LG_OK;
 }
 
+// contrib_0 = PR_0 / d in both ping-pong buffers (zero for vertices without
+// edges, which the iterations then leave alone when a whole word of them)
 template <class Acc>
-__global__ void pr_init_kernel(Acc acc, uint32_t n, double inv_n, float *__restrict__ contrib) {
+__global__ void pr_init_kernel(Acc acc, uint32_t n, double inv_n, float *__restrict__ contrib,
+                               float *__restrict__ contrib2) {
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t v0 = (uint64_t)blockIdx.x * blockDim.x; v0 < n; v0 += stride) {
         const uint64_t w0 = v0 + (threadIdx.x & ~(uint64_t)(kWave - 1));
         const VInfo vi = wave_info(acc, w0, n);
         const uint64_t v = w0 + lane_id();
-        if (v < n) contrib[v] = vi.deg ? (float)(inv_n / (double)vi.deg) : 0.0f;
+        if (v < n) {
+            const float c = vi.deg ? (float)(inv_n / (double)vi.deg) : 0.0f;
+            contrib[v] = c;
+            contrib2[v] = c;
+        }
     }
 }
 
-// One launch per iteration, two kinds of blocks running side by side:
-//   blocks [0, heavy_blocks): a wave per heavy segment sums its contributions
-//     and adds them to its vertex's accumulator; the arrival that completes a
-//     vertex finalizes it
-//   the other blocks: 64 consecutive vertices per wave, lanes walk the
-//     light lists edge-parallel, flushing running sums to LDS accumulators
-//     when the owner changes, then finalize every light vertex
+// Lanes of one wave exchange data through its own LDS rows: keep the
+// compiler from moving LDS accesses across this point (a wave's LDS
+// operations complete in order).
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// One launch per iteration: every wave of the grid takes segments
+// (grid-stride), then units (grid-stride).
 template <class Acc>
 __global__ __launch_bounds__(kPrThreads) void pr_iter_kernel(
-    Acc acc, uint32_t n, uint32_t threshold, const float *__restrict__ cin, float *__restrict__ cout, float base,
-    float alpha, uint32_t heavy_blocks, uint32_t seg_size, const uint32_t *__restrict__ heavy, uint64_t n_seg,
-    const uint32_t *__restrict__ seg_map, const uint64_t *__restrict__ seg_off, const uint64_t *__restrict__ hstart,
-    const uint32_t *__restrict__ hdeg, const uint32_t *__restrict__ hw, unsigned long long *__restrict__ hsum,
-    float *__restrict__ scores, const uint32_t *__restrict__ perm) {
+    Acc acc, uint32_t n, uint32_t split, const float *__restrict__ cin, float *__restrict__ cout, float base,
+    float alpha, uint32_t seg_size, uint64_t n_seg, const uint32_t *__restrict__ seg_map,
+    const uint64_t *__restrict__ seg_off, const uint64_t *__restrict__ hstart, const uint32_t *__restrict__ hdeg,
+    const uint32_t *__restrict__ hw, float *__restrict__ seg_part, uint64_t n_units,
+    const uint32_t *__restrict__ units, const uint64_t *__restrict__ iso, float *__restrict__ scores,
+    const uint32_t *__restrict__ perm) {
+    __shared__ float s_hot[kPrHot];
     __shared__ uint32_t s_excl[kPrWaves][kWave + 1];
     __shared__ uint64_t s_start[kPrWaves][kWave];
     __shared__ uint32_t s_w[kPrWaves][kWave];
     __shared__ float s_acc[kPrWaves][kWave];
     const uint32_t lane = lane_id();
     const uint32_t wv = threadIdx.x / kWave;
-    if (blockIdx.x < heavy_blocks) {
-        const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
-        const uint64_t nwaves = (uint64_t)heavy_blocks * (kPrThreads / kWave);
-        for (uint64_t k = wave; k < n_seg; k += nwaves) {
-            const uint32_t h = seg_map[k];
-            const uint64_t s0 = seg_off[h], s1 = seg_off[h + 1];
-            const uint64_t e0 = (k - s0) * seg_size;
-            const uint64_t d = hdeg[h];
-            const uint64_t e1 = e0 + seg_size < d ? e0 + seg_size : d;
-            const uint32_t w = hw[h];
-            const uint64_t start = hstart[h];
-            const uint32_t st = Acc::step(w), mk = Acc::mask(w);
-            float sum = 0.0f;
-            for (uint64_t e = e0 + lane; e < e1; e += kWave * kBatch) {
-                uint32_t u[kBatch];
+    // A divergent 4-byte gather from global memory costs a whole cache-line
+    // fill of the vector L1; from LDS it costs a bank access.  The smallest
+    // labels are the highest-degree vertices after the degree-descending
+    // relabel (the sources of about a quarter of all gathers at Kronecker
+    // scale 24), so their contributions are read from an LDS copy.
+    const uint32_t hot = kPrHot < n ? kPrHot : n;
+    for (uint32_t i = threadIdx.x; i < hot; i += kPrThreads) s_hot[i] = cin[i];
+    __syncthreads();
+    auto gather = [&](uint32_t u) -> float { return u < hot ? s_hot[u] : cin[u]; };
+    const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const uint64_t nwaves = (uint64_t)gridDim.x * kPrWaves;
+    for (uint64_t k = wave; k < n_seg; k += nwaves) {
+        const uint32_t h = seg_map[k];
+        const uint64_t e0 = (k - seg_off[h]) * seg_size;
+        const uint64_t d = hdeg[h];
+        const uint64_t e1 = e0 + seg_size < d ? e0 + seg_size : d;
+        const uint32_t w = hw[h];
+        const uint64_t start = hstart[h];
+        const uint32_t st = Acc::step(w), mk = Acc::mask(w);
+        float sum = 0.0f;
+        for (uint64_t e = e0 + lane; e < e1; e += kWave * kBatch) {
+            uint32_t u[kBatch];
 #pragma unroll
-                for (int b = 0; b < kBatch; ++b) {
-                    const uint64_t eb = e + (uint64_t)b * kWave;
-                    u[b] = eb < e1 ? acc.get(start + eb * st, mk) : 0xFFFFFFFFu;
-                }
-                float x[kBatch];
-#pragma unroll
-                for (int b = 0; b < kBatch; ++b) x[b] = u[b] != 0xFFFFFFFFu ? cin[u[b]] : 0.0f;
-#pragma unroll
-                for (int b = 0; b < kBatch; ++b) sum += x[b];
+            for (int b = 0; b < kBatch; ++b) {
+                const uint64_t eb = e + (uint64_t)b * kWave;
+                u[b] = eb < e1 ? acc.get(start + eb * st, mk) : 0xFFFFFFFFu;
             }
-            sum = wave_sum(sum);
-            if (lane == 0) {
-                // One integer atomic carries both the segment's sum, as a
-                // fixed-point value with 2^-46 resolution in the low 48 bits
-                // (a vertex's total is at most 1), and an arrival count in the
-                // high 16 bits (at most 65535 segments per vertex).  Integer
-                // addition does not depend on arrival order, and the last
-                // arrival reads the total from the atomic's own result: no
-                // fence, no cross-XCD data reads.
-                const uint64_t fixed = (uint64_t)__double2ll_rn((double)sum * 0x1p46);
-                const unsigned long long add = (1ull << 48) | fixed;
-                const unsigned long long now = atomicAdd(&hsum[h], add) + add;
-                if ((now >> 48) == s1 - s0) {
-                    const double hs = (double)(now & ((1ull << 48) - 1)) * 0x1p-46;
-                    const uint32_t v = heavy[h];
-                    const float pr = base + alpha * (float)hs;
-                    cout[v] = pr / (float)d;
-                    if (scores) scores[perm ? perm[v] : v] = pr;
-                    hsum[h] = 0ull;  // ready for the next launch
-                }
-            }
+            float x[kBatch];
+#pragma unroll
+            for (int b = 0; b < kBatch; ++b) x[b] = u[b] != 0xFFFFFFFFu ? gather(u[b]) : 0.0f;
+#pragma unroll
+            for (int b = 0; b < kBatch; ++b) sum += x[b];
         }
-        return;
+        sum = wave_sum(sum);
+        if (lane == 0) seg_part[k] = sum;
     }
-    const uint64_t nchunks = ((uint64_t)n + kPrThreads - 1) / kPrThreads;
-    const uint32_t lblocks = gridDim.x - heavy_blocks;
-    for (uint64_t c = blockIdx.x - heavy_blocks; c < nchunks; c += lblocks) {
-        const uint64_t w0 = c * kPrThreads + (uint64_t)wv * kWave;
+    for (uint64_t k = wave; k < n_units; k += nwaves) {
+        const uint32_t vb = units[k], ve = units[k + 1];
+        const uint64_t w0 = vb & ~(uint64_t)(kWave - 1);
         const uint64_t v = w0 + lane;
-        const VInfo vi = wave_info(acc, w0, n);
-        const bool is_heavy = vi.deg > threshold;
-        const uint32_t d = is_heavy ? 0u : vi.deg;  // heavy lists are summed by segments
+        const bool mine = v >= vb && v < ve;
+        // a block of vertices without edges: contrib stays 0, only scores change
+        const bool all_iso = iso[w0 / kWave] == ~0ull;
+        if (all_iso && !scores) continue;
+        const VInfo vi = all_iso ? VInfo{0, 0, 0} : wave_info(acc, w0, n);
+        const bool segmented = vi.deg > split;
+        const uint32_t d = (mine && !segmented) ? vi.deg : 0u;
         const uint32_t incl = wave_incl_scan(d);
         const uint32_t total = __shfl(incl, kWave - 1, kWave);
         s_excl[wv][lane] = incl - d;
@@ -143,7 +152,7 @@ __global__ __launch_bounds__(kPrThreads) void pr_iter_kernel(
         s_start[wv][lane] = vi.start;
         s_w[wv][lane] = vi.w;
         s_acc[wv][lane] = 0.0f;
-        __syncthreads();
+        wave_lds_sync();
         uint32_t j = 0, owner = 0xFFFFFFFFu;
         float part = 0.0f;
         for (uint32_t e = lane; e < total; e += kWave * kBatch) {
@@ -162,7 +171,7 @@ __global__ __launch_bounds__(kPrThreads) void pr_iter_kernel(
             }
             float x[kBatch];
 #pragma unroll
-            for (int b = 0; b < kBatch; ++b) x[b] = own[b] != 0xFFFFFFFFu ? cin[u[b]] : 0.0f;
+            for (int b = 0; b < kBatch; ++b) x[b] = own[b] != 0xFFFFFFFFu ? gather(u[b]) : 0.0f;
 #pragma unroll
             for (int b = 0; b < kBatch; ++b) {
                 if (own[b] == 0xFFFFFFFFu) continue;
@@ -175,13 +184,32 @@ __global__ __launch_bounds__(kPrThreads) void pr_iter_kernel(
             }
         }
         if (owner != 0xFFFFFFFFu) atomicAdd(&s_acc[wv][owner], part);
-        __syncthreads();
-        if (v < n && !is_heavy) {
+        wave_lds_sync();
+        if (mine && !segmented) {
             const float pr = base + alpha * s_acc[wv][lane];
-            cout[v] = vi.deg ? pr / (float)vi.deg : 0.0f;
+            if (!all_iso) cout[v] = vi.deg ? pr / (float)vi.deg : 0.0f;
             if (scores) scores[perm ? perm[v] : v] = pr;
         }
-        __syncthreads();
+        wave_lds_sync();
+    }
+}
+
+// Segmented vertices: the sum of their segments' slots, in segment order.
+__global__ void pr_segmented_kernel(uint32_t n_heavy, const uint32_t *__restrict__ heavy,
+                                    const uint64_t *__restrict__ seg_off, const uint32_t *__restrict__ hdeg,
+                                    const float *__restrict__ seg_part, float base, float alpha,
+                                    float *__restrict__ cout, float *__restrict__ scores,
+                                    const uint32_t *__restrict__ perm) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t h = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; h < n_heavy; h += stride) {
+        const uint64_t s0 = seg_off[h], s1 = seg_off[h + 1];
+        if (s0 == s1) continue;
+        float sum = 0.0f;
+        for (uint64_t k = s0; k < s1; ++k) sum += seg_part[k];
+        const uint32_t v = heavy[h];
+        const float pr = base + alpha * sum;
+        cout[v] = pr / (float)hdeg[h];
+        if (scores) scores[perm ? perm[v] : v] = pr;
     }
 }
 
@@ -212,8 +240,6 @@ extern "C" lg_status lg_pagerank(const lg_graph *gc, float damping, uint32_t ite
     LG_TRY(g->pr->ca.ensure((uint64_t)n * 4));
     LG_TRY(g->pr->cb.ensure((uint64_t)n * 4));
     LG_TRY(ensure_heavy_segments(g, stream));
-    LG_TRY(g->pr->acc.ensure((uint64_t)(g->n_heavy ? g->n_heavy : 1) * 8));
-    LG_TRY(fill_u64(g->pr->acc.as<uint64_t>(), 0, g->n_heavy ? g->n_heavy : 1, stream));
     const uint32_t *perm = g->relabel == LG_RELABEL_DEGREE ? g->perm.as<uint32_t>() : nullptr;
     const double a = damping;
     const double z = g->isolated;
@@ -221,23 +247,34 @@ extern "C" lg_status lg_pagerank(const lg_graph *gc, float damping, uint32_t ite
         using Acc = decltype(acc);
         PrWork &w = *g->pr;
         float *cin = w.ca.as<float>(), *cout = w.cb.as<float>();
-        LG_LAUNCH(pr_init_kernel<Acc>, grid_for(n, 256, 1u << 16), 256, 0, stream, acc, n, 1.0 / nd, cin);
+        LG_LAUNCH(pr_init_kernel<Acc>, grid_for(n, 256, 1u << 16), 256, 0, stream, acc, n, 1.0 / nd, cin, cout);
         LG_CHECK_LAUNCH();
         double D = z / nd;  // D_0: rank on vertices without edges
-        // heavy blocks: enough waves for the segments, capped; light blocks: one
-        // per 256-vertex chunk, capped (both loops are grid-stride)
-        const uint32_t heavy_blocks = g->n_seg ? grid_for(g->n_seg, kPrThreads / kWave, 8192) : 0;
-        const uint32_t light_blocks = grid_for(n, kPrThreads, 8192);
+        // persistent grid: as many workgroups as fit on the device at once,
+        // fewer when there is little work
+        int cus = 0, per_cu = 0;
+        LG_CHECK_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, g->device));
+        LG_CHECK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, pr_iter_kernel<Acc>, kPrThreads, 0));
+        const uint64_t want = (g->n_units + g->n_seg + kPrWaves - 1) / kPrWaves;
+        const uint32_t blocks =
+            (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((uint64_t)std::max(cus, 1) * std::max(per_cu, 1), want));
         for (uint32_t t = 0; t < iters; ++t) {
             const double b = (1.0 - a) / nd + a * D / nd;
             const bool last = t + 1 == iters;
-            LG_LAUNCH(pr_iter_kernel<Acc>, heavy_blocks + light_blocks, kPrThreads, 0, stream, acc, n,
-                      g->heavy_threshold, (const float *)cin, cout, (float)b, (float)a, heavy_blocks, g->seg_size,
-                      (const uint32_t *)g->heavy.p, g->n_seg, (const uint32_t *)g->seg_map.p,
+            float *sc = last ? scores : (float *)nullptr;
+            const uint32_t *pm = last ? perm : (const uint32_t *)nullptr;
+            LG_LAUNCH(pr_iter_kernel<Acc>, blocks, kPrThreads, 0, stream, acc, n, g->pr_split, (const float *)cin,
+                      cout, (float)b, (float)a, g->seg_size, g->n_seg, (const uint32_t *)g->seg_map.p,
                       (const uint64_t *)g->seg_off.p, (const uint64_t *)g->hstart.p, (const uint32_t *)g->hdeg.p,
-                      (const uint32_t *)g->hw.p, w.acc.as<unsigned long long>(),
-                      last ? scores : (float *)nullptr, last ? perm : (const uint32_t *)nullptr);
+                      (const uint32_t *)g->hw.p, g->seg_part.as<float>(), g->n_units, (const uint32_t *)g->units.p,
+                      g->iso.as<uint64_t>(), sc, pm);
             LG_CHECK_LAUNCH();
+            if (g->n_seg) {
+                LG_LAUNCH(pr_segmented_kernel, grid_for(g->n_heavy, 256, 4096), 256, 0, stream, g->n_heavy,
+                          (const uint32_t *)g->heavy.p, (const uint64_t *)g->seg_off.p, (const uint32_t *)g->hdeg.p,
+                          (const float *)g->seg_part.p, (float)b, (float)a, cout, sc, pm);
+                LG_CHECK_LAUNCH();
+            }
             D = z * b;
             float *tmp = cin; cin = cout; cout = tmp;
         }
