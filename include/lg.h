@@ -152,6 +152,11 @@ lg_status lg_decode_neighbors(const lg_graph *g, const uint32_t *vertices, uint3
  *              unreached vertices
  *   max_depth  -1 for a full traversal; k >= 0 stops after depth k (k-hop)
  * Results are independent of the flags and of the direction switching.
+ * With r > 1 the roots run a few at a time, each on its own internal stream
+ * with its own workspace; work queued on `stream` before the call completes
+ * first, and work queued on `stream` after it waits for every root.  The
+ * call returns once every root has been enqueued; each row equals the result
+ * of a call with that root alone.  Calls on the same graph must not overlap.
  */
 lg_status lg_bfs(const lg_graph *g, const uint32_t *roots, uint32_t r, int32_t *depth,
                  int32_t *parent, int32_t max_depth, uint32_t flags, hipStream_t stream);

@@ -19,6 +19,10 @@
 // The switch between the two follows the edge-count heuristic of
 // direction-optimizing BFS; it changes the running time only.
 #include <algorithm>
+#include <atomic>
+#include <string>
+#include <thread>
+#include <vector>
 
 #include "lg_device.hpp"
 
@@ -34,11 +38,33 @@ BfsWork::~BfsWork() {
     if (host) (void)hipHostFree(host);
 }
 
-uint64_t bfs_bytes(const lg_graph *g) { return g->bfs ? g->bfs->bytes() : 0; }
+BfsPool::~BfsPool() {
+    for (BfsLane *l : lanes) {
+        if (l->stream) {
+            (void)hipStreamSynchronize(l->stream);
+            (void)hipStreamDestroy(l->stream);
+        }
+        if (l->done) (void)hipEventDestroy(l->done);
+        delete l;
+    }
+    if (start) (void)hipEventDestroy(start);
+}
+
+uint64_t BfsPool::bytes() const {
+    uint64_t b = 0;
+    for (const BfsLane *l : lanes) b += l->work.bytes();
+    return b;
+}
+
+uint64_t bfs_bytes(const lg_graph *g) {
+    return (g->bfs ? g->bfs->bytes() : 0) + (g->bfs_pool ? g->bfs_pool->bytes() : 0);
+}
 
 lg_status bfs_free(lg_graph *g) {
     delete g->bfs;
     g->bfs = nullptr;
+    delete g->bfs_pool;
+    g->bfs_pool = nullptr;
     return LG_OK;
 }
 
@@ -81,11 +107,15 @@ lg_status bfs_workspace_ensure(BfsWork &w, uint64_t n, uint64_t n_heavy, bool re
 
 // visited starts as the root plus every vertex without edges (never reached,
 // never a neighbor), so bottom-up sweeps skip words of such vertices
+// The root arrives as its original ID and is mapped to its label here (inv,
+// when relabeled), so that no host round trip is needed.
 __global__ void bfs_init_kernel(uint32_t n, int32_t *__restrict__ depth, uint32_t *__restrict__ parent,
-                                const uint64_t *__restrict__ iso, uint64_t *__restrict__ visited, uint32_t root,
-                                uint32_t *__restrict__ queue, uint64_t *__restrict__ counters) {
+                                const uint64_t *__restrict__ iso, uint64_t *__restrict__ visited, uint32_t root_id,
+                                const uint32_t *__restrict__ inv, uint32_t *__restrict__ queue,
+                                uint64_t *__restrict__ counters) {
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     const uint64_t words = ((uint64_t)n + 63) / 64;
+    const uint32_t root = inv ? inv[root_id] : root_id;
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
         depth[i] = i == root ? 0 : -1;
         if (parent) parent[i] = i == root ? root : 0xFFFFFFFFu;
@@ -397,8 +427,8 @@ struct BfsParams {
 };
 
 template <class Acc>
-static lg_status bfs_one(lg_graph *g, BfsWork &w, Acc acc, uint32_t root_label, int32_t *depth, uint32_t *parent,
-                         int32_t max_depth, uint32_t flags, hipStream_t s) {
+static lg_status bfs_one(lg_graph *g, BfsWork &w, Acc acc, uint32_t root_id, const uint32_t *inv, int32_t *depth,
+                         uint32_t *parent, int32_t max_depth, uint32_t flags, hipStream_t s) {
     const uint32_t n = g->n;
     const uint64_t words = ((uint64_t)n + 63) / 64;
     const BfsParams prm;
@@ -407,7 +437,7 @@ static lg_status bfs_one(lg_graph *g, BfsWork &w, Acc acc, uint32_t root_label, 
     unsigned long long *ctr = w.counters.as<unsigned long long>();
     const uint32_t gsz = grid_for(n, 256, 1u << 16);
 
-    LG_LAUNCH(bfs_init_kernel, gsz, 256, 0, s, n, depth, parent, g->iso.as<uint64_t>(), visited, root_label, qin,
+    LG_LAUNCH(bfs_init_kernel, gsz, 256, 0, s, n, depth, parent, g->iso.as<uint64_t>(), visited, root_id, inv, qin,
               (uint64_t *)ctr);
     LG_CHECK_LAUNCH();
 
@@ -521,29 +551,82 @@ lg_status bfs_run(lg_graph *g, BfsWork &w, const uint32_t *roots, uint32_t r, in
     if (r == 0) return LG_OK;
     LG_TRY(bfs_workspace_ensure(w, g->n, g->n_heavy, g->relabel == LG_RELABEL_DEGREE, parent != nullptr));
     const bool rel = g->relabel == LG_RELABEL_DEGREE;
+    const uint32_t *inv = rel ? g->inv.as<uint32_t>() : nullptr;
     return dispatch_acc(g, [&](auto acc) -> lg_status {
         for (uint32_t i = 0; i < r; ++i) {
             int32_t *d_out = depth + (uint64_t)i * g->n;
             int32_t *p_out = parent ? parent + (uint64_t)i * g->n : nullptr;
-            uint32_t root_label = roots[i];
             if (rel) {
-                LG_CHECK_HIP(hipMemcpyAsync(w.host + 2, g->inv.as<uint32_t>() + roots[i], 4, hipMemcpyDeviceToHost,
-                                            stream));
-                LG_CHECK_HIP(hipStreamSynchronize(stream));
-                root_label = *reinterpret_cast<uint32_t *>(w.host + 2);
-                LG_TRY(bfs_one(g, w, acc, root_label, w.depth_i.as<int32_t>(),
+                LG_TRY(bfs_one(g, w, acc, roots[i], inv, w.depth_i.as<int32_t>(),
                                p_out ? w.parent_i.as<uint32_t>() : nullptr, max_depth, flags, stream));
                 LG_LAUNCH(bfs_unpermute_kernel, grid_for(g->n, 256, 1u << 16), 256, 0, stream, g->n,
                           g->inv.as<uint32_t>(), g->perm.as<uint32_t>(), w.depth_i.as<int32_t>(),
                           p_out ? w.parent_i.as<uint32_t>() : nullptr, d_out, p_out);
                 LG_CHECK_LAUNCH();
             } else {
-                LG_TRY(bfs_one(g, w, acc, root_label, d_out, reinterpret_cast<uint32_t *>(p_out), max_depth, flags,
+                LG_TRY(bfs_one(g, w, acc, roots[i], inv, d_out, reinterpret_cast<uint32_t *>(p_out), max_depth, flags,
                                stream));
             }
         }
         return LG_OK;
     });
+}
+
+constexpr uint32_t kBfsLanes = 4;
+
+static lg_status pool_ensure(lg_graph *g, uint32_t lanes) {
+    if (!g->bfs_pool) {
+        g->bfs_pool = new (std::nothrow) BfsPool();
+        if (!g->bfs_pool) { set_error("lg_bfs: host allocation failed"); return LG_ERR_OOM; }
+        LG_CHECK_HIP(hipEventCreateWithFlags(&g->bfs_pool->start, hipEventDisableTiming));
+    }
+    BfsPool &p = *g->bfs_pool;
+    while (p.lanes.size() < lanes) {
+        BfsLane *l = new (std::nothrow) BfsLane();
+        if (!l) { set_error("lg_bfs: host allocation failed"); return LG_ERR_OOM; }
+        p.lanes.push_back(l);
+        LG_CHECK_HIP(hipStreamCreateWithFlags(&l->stream, hipStreamNonBlocking));
+        LG_CHECK_HIP(hipEventCreateWithFlags(&l->done, hipEventDisableTiming));
+    }
+    return LG_OK;
+}
+
+// Several roots: lanes take the next root from a shared counter until none
+// is left.  Work on `stream` before the call is complete before any lane
+// starts, and `stream` waits for every lane before work queued after the
+// call runs.  Every root's result is that of a run alone.
+static lg_status bfs_run_lanes(lg_graph *g, const uint32_t *roots, uint32_t r, int32_t *depth, int32_t *parent,
+                               int32_t max_depth, uint32_t flags, hipStream_t stream) {
+    const uint32_t L = std::min<uint32_t>(r, kBfsLanes);
+    LG_TRY(pool_ensure(g, L));
+    BfsPool &p = *g->bfs_pool;
+    LG_CHECK_HIP(hipEventRecord(p.start, stream));
+    for (uint32_t i = 0; i < L; ++i) LG_CHECK_HIP(hipStreamWaitEvent(p.lanes[i]->stream, p.start, 0));
+    std::atomic<uint32_t> next{0};
+    std::vector<lg_status> st(L, LG_OK);
+    std::vector<std::string> err(L);
+    std::vector<std::thread> th;
+    const uint64_t n = g->n;
+    for (uint32_t i = 0; i < L; ++i) {
+        th.emplace_back([&, i] {
+            (void)hipSetDevice(g->device);
+            BfsLane &ln = *p.lanes[i];
+            for (uint32_t k = next++; k < r && st[i] == LG_OK; k = next++) {
+                st[i] = bfs_run(g, ln.work, roots + k, 1, depth + (uint64_t)k * n,
+                                parent ? parent + (uint64_t)k * n : nullptr, max_depth, flags, ln.stream);
+                if (st[i] != LG_OK) err[i] = lg_last_error();
+            }
+            (void)hipEventRecord(ln.done, ln.stream);
+        });
+    }
+    for (auto &t : th) t.join();
+    for (uint32_t i = 0; i < L; ++i) LG_CHECK_HIP(hipStreamWaitEvent(stream, p.lanes[i]->done, 0));
+    for (uint32_t i = 0; i < L; ++i)
+        if (st[i] != LG_OK) {
+            set_error("%s", err[i].c_str());
+            return st[i];
+        }
+    return LG_OK;
 }
 
 }  // namespace lg
@@ -557,6 +640,7 @@ extern "C" lg_status lg_bfs(const lg_graph *gc, const uint32_t *roots, uint32_t 
     for (uint32_t i = 0; i < r; ++i)
         if (roots[i] >= g->n) { set_error("lg_bfs: root %u out of range", roots[i]); return LG_ERR_INVALID; }
     if (r == 0) return LG_OK;
+    if (r > 1) return bfs_run_lanes(g, roots, r, depth, parent, max_depth, flags, stream);
     if (!g->bfs) {
         g->bfs = new (std::nothrow) BfsWork();
         if (!g->bfs) { set_error("lg_bfs: host allocation failed"); return LG_ERR_OOM; }

@@ -122,6 +122,21 @@ struct BfsWork {
     uint64_t bytes() const;
 };
 
+// Roots of one lg_bfs call run on a few lanes at once: each lane has its own
+// stream (default priority), workspace and host thread, so that one root's
+// host round trips between levels are covered by another root's kernels.
+struct BfsLane {
+    hipStream_t stream = nullptr;
+    hipEvent_t done = nullptr;
+    BfsWork work;
+};
+struct BfsPool {
+    std::vector<BfsLane *> lanes;
+    hipEvent_t start = nullptr;
+    ~BfsPool();
+    uint64_t bytes() const;
+};
+
 // Device workspace of one neighbor decode at a time (grow-only buffers).
 struct DecodeWork {
     DevBuf head;                 // labels, degrees, flag
@@ -184,6 +199,7 @@ struct lg_graph {
     // lazily allocated workspaces of the plain calls (lg_bfs, lg_pagerank,
     // lg_decode_neighbors); the server brings its own per worker
     lg::BfsWork *bfs = nullptr;
+    lg::BfsPool *bfs_pool = nullptr;
     lg::PrWork *pr = nullptr;
     lg::DecodeWork *dec = nullptr;
 

@@ -252,6 +252,9 @@ def bfs(g: Graph, roots: Sequence[int], *, parent=True, max_depth=-1, mode="do",
     depth = depth_out if depth_out is not None else torch.empty((r, g.n), dtype=torch.int32, device=dev)
     par = parent_out if parent_out is not None else (
         torch.empty((r, g.n), dtype=torch.int32, device=dev) if parent else None)
+    for t, what in [(depth, "depth"), (par, "parent")]:
+        if t is not None and t.numel() < r * g.n:
+            raise ValueError(f"{what} must hold {r} x {g.n} entries, got {t.numel()}")
     arr = (C.c_uint32 * max(r, 1))(*[int(x) for x in roots])
     _check(lib().lg_bfs(g.handle, arr, r, _dev_ptr(depth, torch.int32, "depth"),
                         _dev_ptr(par, torch.int32, "parent"), max_depth, BFS_FLAGS[mode], _stream(stream)))
@@ -261,6 +264,8 @@ def bfs(g: Graph, roots: Sequence[int], *, parent=True, max_depth=-1, mode="do",
 def pagerank(g: Graph, damping: float = 0.85, iters: int = 20, out=None, stream=None) -> torch.Tensor:
     dev = torch.device("cuda", torch.cuda.current_device())
     scores = out if out is not None else torch.empty(g.n, dtype=torch.float32, device=dev)
+    if scores.numel() < g.n:
+        raise ValueError(f"out must hold {g.n} entries, got {scores.numel()}")
     _check(lib().lg_pagerank(g.handle, float(damping), int(iters), _dev_ptr(scores, torch.float32, "scores"),
                              _stream(stream)))
     return scores
