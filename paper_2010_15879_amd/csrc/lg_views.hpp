@@ -1,0 +1,40 @@
+// Device views of a packed or plain graph: plain structs of pointers and
+// sizes, passed to kernels by value.
+#pragma once
+
+#include <cstdint>
+
+namespace lg {
+
+// Elias-Fano offsets: x_v = ((select1(H, v) - v) << l) | L[v].
+struct EFView {
+    const uint64_t *L;        // low bits, l per value
+    const uint64_t *H;        // upper bit vector
+    const uint32_t *rank_sb;  // rank1(512 b)
+    const uint32_t *sel;      // select1(64 j)
+    uint32_t l;
+    uint32_t n_sel;           // entries of sel
+    uint32_t n_sb;            // superblocks = entries of rank_sb - 1
+};
+
+// Packed offsets: value v at bits [v*w, v*w + w).
+struct POffView {
+    const uint64_t *O;
+    uint32_t w;
+};
+
+struct PackedView {
+    const uint32_t *A32;      // packed lists viewed as 32-bit words
+    const uint64_t *W;        // width table (local mode)
+    uint32_t s;               // global width
+    uint32_t F;               // width field bits
+    POffView po;
+    EFView ef;
+};
+
+struct PlainView {
+    const void *off;          // uint32 or uint64 offsets
+    const uint32_t *col;
+};
+
+}  // namespace lg
