@@ -38,6 +38,12 @@ __device__ __forceinline__ T wave_incl_scan(T x) {
     return x;
 }
 
+__device__ __forceinline__ uint32_t wave_or(uint32_t x) {
+#pragma unroll
+    for (int d = kWave / 2; d > 0; d >>= 1) x |= __shfl_xor(x, d, kWave);
+    return x;
+}
+
 template <class T>
 __device__ __forceinline__ T wave_sum(T x) {
 #pragma unroll

@@ -16,6 +16,7 @@
 //                 Elias-Fano sequence with a rank/select directory ("Succinct
 //                 Bit Vectors in Log(Graph)")
 #include <cstring>
+#include <utility>
 
 #include "lg_device.hpp"
 
@@ -33,59 +34,152 @@ enum : uint32_t {
 // validation and degree statistics
 // ---------------------------------------------------------------------------
 
-// One wave per vertex; lanes walk the list.
-__global__ void validate_kernel(uint32_t n, uint64_t m, const uint64_t *__restrict__ off,
-                                const uint32_t *__restrict__ col, uint32_t *__restrict__ status) {
+// Offsets: non-decreasing, off[0] = 0, off[n] = m (one thread per vertex).
+__global__ void validate_offsets_kernel(uint32_t n, uint64_t m, const uint64_t *__restrict__ off,
+                                        uint32_t *__restrict__ status) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    bool bad = false;
+    for (uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) {
+        const uint64_t o0 = off[v], o1 = off[v + 1];
+        bad |= o1 < o0 || o1 > m || (v == 0 && o0 != 0) || (v + 1 == n && o1 != m);
+    }
+    if (__ballot(bad) && lane_id() == 0) atomicOr(status, kBadOffsets);
+}
+
+// ---------------------------------------------------------------------------
+// edge walks over 64-row blocks
+// ---------------------------------------------------------------------------
+//
+// The lists of rows 64q .. 64q+63 are one contiguous range of entries.  It is
+// cut into pieces of at most kWalkChunk entries; a piece is one work item, so
+// that a hub's list is shared by many waves and a block of short lists is one
+// wave's work.  Item k belongs to block map[k] and is its piece k - coff[q].
+
+constexpr uint64_t kWalkChunk = 8192;
+
+__global__ void walk_count_kernel(uint32_t n, const uint64_t *__restrict__ off, uint32_t *__restrict__ cnt) {
+    const uint64_t blocks = ((uint64_t)n + 63) / 64;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; q < blocks; q += stride) {
+        const uint64_t e0 = off[q * 64], e1 = off[q * 64 + 64 <= n ? q * 64 + 64 : n];
+        const uint64_t pieces = (e1 - e0 + kWalkChunk - 1) / kWalkChunk;
+        cnt[q] = (uint32_t)(pieces ? pieces : 1);
+    }
+}
+
+__global__ void walk_map_kernel(uint64_t blocks, const uint64_t *__restrict__ coff, uint32_t *__restrict__ map) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; q < blocks; q += stride)
+        for (uint64_t k = coff[q]; k < coff[q + 1]; ++k) map[k] = (uint32_t)q;
+}
+
+// Lanes of one wave exchange data through its own LDS rows: keep the
+// compiler from moving LDS accesses across this point.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Work item k of a walk over the rows of `off`: s_rs gets the block's 65 row
+// starts; f(e, j, valid) is called by every lane for entries e = base + lane
+// in steps of 64 (valid = e lies in the piece), j = the row of e within the
+// block.  Every lane makes the same calls (shuffles inside f are safe).
+template <class F>
+__device__ __forceinline__ void walk_item(uint32_t n, const uint64_t *__restrict__ off,
+                                          const uint32_t *__restrict__ map, const uint64_t *__restrict__ coff,
+                                          uint64_t k, uint64_t *s_rs, F &&f) {
     const uint32_t lane = lane_id();
+    const uint64_t q = map[k];
+    const uint64_t v0 = q * 64;
+    const uint64_t o = off[v0 + lane <= n ? v0 + lane : n];
+    const uint64_t E1 = off[v0 + 64 <= n ? v0 + 64 : n];
+    s_rs[lane] = o;
+    if (lane == 0) s_rs[64] = E1;
+    wave_lds_sync();
+    const uint64_t eb = __shfl(o, 0, kWave) + (k - coff[q]) * kWalkChunk;
+    const uint64_t ee = eb + kWalkChunk < E1 ? eb + kWalkChunk : E1;
+    if (eb < ee) {
+        // row of eb: the largest j with s_rs[j] <= eb (empty rows share starts)
+        uint32_t j = 0;
+#pragma unroll
+        for (uint32_t step = 32; step > 0; step >>= 1)
+            if (s_rs[j + step] <= eb) j += step;
+        for (uint64_t base = eb; base < ee; base += kWave) {
+            const uint64_t e = base + lane;
+            const bool valid = e < ee;
+            if (valid)
+                while (s_rs[j + 1] <= e) ++j;
+            f(e, j, valid);
+        }
+    }
+    wave_lds_sync();
+}
+
+// IDs < n, no self-loop, strictly increasing lists.
+__global__ void validate_edges_kernel(uint32_t n, const uint64_t *__restrict__ off, const uint32_t *__restrict__ col,
+                                      uint64_t items, const uint32_t *__restrict__ map,
+                                      const uint64_t *__restrict__ coff, uint32_t *__restrict__ status) {
+    __shared__ uint64_t s_rs[4][kWave + 1];
+    const uint32_t wv = threadIdx.x / kWave;
     const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
     const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) / kWave;
     uint32_t flags = 0;
-    for (uint64_t v = wave; v < n; v += nwaves) {
-        const uint64_t o0 = off[v], o1 = off[v + 1];
-        if (o1 < o0 || o1 > m || (v == 0 && o0 != 0) || (v + 1 == n && o1 != m)) {
-            flags |= kBadOffsets;
-            continue;
-        }
-        for (uint64_t i = o0 + lane; i < o1; i += kWave) {
-            const uint32_t u = col[i];
-            if (u >= n) { flags |= kBadId; continue; }
-            if (u == v) flags |= kSelfLoop;
-            if (i > o0 && col[i - 1] >= u) flags |= kUnsorted;
-        }
+    for (uint64_t k = wave; k < items; k += nwaves) {
+        const uint64_t v0 = (uint64_t)map[k] * 64;
+        walk_item(n, off, map, coff, k, s_rs[wv], [&](uint64_t e, uint32_t j, bool valid) {
+            const uint32_t u = valid ? col[e] : 0u;
+            uint32_t prev = __shfl_up(u, 1, kWave);
+            if (!valid) return;
+            if (lane_id() == 0 && e > 0) prev = col[e - 1];
+            if (u >= n) flags |= kBadId;
+            if (u == v0 + j) flags |= kSelfLoop;
+            if (e > s_rs[wv][j] && prev >= u) flags |= kUnsorted;
+        });
     }
-    if (flags) atomicOr(status, flags);
+    if (__ballot(flags != 0)) {
+        flags = wave_or(flags);
+        if (lane_id() == 0) atomicOr(status, flags);
+    }
 }
 
 // Symmetry, exactly: the entries (v, u) emitted in row order and sorted
 // stably by u list the transpose in adjacency-array order; the graph is
 // symmetric iff that is the input itself, entry for entry.
 __global__ void sym_emit_kernel(uint32_t n, const uint64_t *__restrict__ off, const uint32_t *__restrict__ col,
+                                uint64_t items, const uint32_t *__restrict__ map, const uint64_t *__restrict__ coff,
                                 uint32_t *__restrict__ key, uint32_t *__restrict__ val) {
-    const uint32_t lane = lane_id();
+    __shared__ uint64_t s_rs[4][kWave + 1];
+    const uint32_t wv = threadIdx.x / kWave;
     const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
     const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) / kWave;
-    for (uint64_t v = wave; v < n; v += nwaves) {
-        const uint64_t o0 = off[v], o1 = off[v + 1];
-        for (uint64_t i = o0 + lane; i < o1; i += kWave) {
-            key[i] = col[i];
-            val[i] = (uint32_t)v;
-        }
+    for (uint64_t k = wave; k < items; k += nwaves) {
+        const uint32_t v0 = map[k] * 64u;
+        walk_item(n, off, map, coff, k, s_rs[wv], [&](uint64_t e, uint32_t j, bool valid) {
+            if (!valid) return;
+            key[e] = col[e];
+            val[e] = v0 + j;
+        });
     }
 }
 
 __global__ void sym_check_kernel(uint32_t n, const uint64_t *__restrict__ off, const uint32_t *__restrict__ col,
+                                 uint64_t items, const uint32_t *__restrict__ map, const uint64_t *__restrict__ coff,
                                  const uint32_t *__restrict__ key, const uint32_t *__restrict__ val,
                                  uint32_t *__restrict__ status) {
-    const uint32_t lane = lane_id();
+    __shared__ uint64_t s_rs[4][kWave + 1];
+    const uint32_t wv = threadIdx.x / kWave;
     const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
     const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) / kWave;
     bool bad = false;
-    for (uint64_t v = wave; v < n; v += nwaves) {
-        const uint64_t o0 = off[v], o1 = off[v + 1];
-        for (uint64_t i = o0 + lane; i < o1; i += kWave)
-            bad |= key[i] != (uint32_t)v || val[i] != col[i];
+    for (uint64_t k = wave; k < items; k += nwaves) {
+        const uint32_t v0 = map[k] * 64u;
+        walk_item(n, off, map, coff, k, s_rs[wv], [&](uint64_t e, uint32_t j, bool valid) {
+            if (!valid) return;
+            bad |= key[e] != v0 + j || val[e] != col[e];
+        });
     }
-    if (__ballot(bad) && lane == 0) atomicOr(status, kAsymmetric);
+    if (__ballot(bad) && lane_id() == 0) atomicOr(status, kAsymmetric);
 }
 
 // deg[v] (uint32), plus the maximum degree and the number of isolated vertices
@@ -141,25 +235,53 @@ __global__ void dm_inverse_kernel(uint32_t n, const uint32_t *__restrict__ perm,
     }
 }
 
-// Row x of the relabeled array receives the list of perm[x], renamed; it is
-// emitted as (target, source) pairs.  Sorting the pairs stably by target
-// lists, for every target y in increasing order, the sources x adjacent to
-// y in increasing order; by symmetry that sequence is the sorted relabeled
-// adjacency array itself, so the sorted sources are the new lists.
-__global__ void dm_gather_kernel(uint32_t n, const uint32_t *__restrict__ perm, const uint32_t *__restrict__ inv,
-                                 const uint64_t *__restrict__ off, const uint32_t *__restrict__ col,
-                                 const uint64_t *__restrict__ off_new, uint32_t *__restrict__ key,
-                                 uint32_t *__restrict__ val) {
+// The relabeled lists without a gather per entry.  Rows are taken in new
+// order x, and every entry w of the list of perm[x] is emitted as the pair
+// (w, x): original target, new source.  A stable sort by w groups, for each
+// original vertex w, the new labels x of the vertices whose lists hold w, in
+// increasing order; by symmetry that group is the relabeled list of w, which
+// becomes row inv[w] (one lookup per row, not per entry).
+__global__ void dm_emit_kernel(uint32_t n, const uint32_t *__restrict__ perm, const uint64_t *__restrict__ off,
+                               const uint32_t *__restrict__ col, const uint64_t *__restrict__ off_new, uint64_t items,
+                               const uint32_t *__restrict__ map, const uint64_t *__restrict__ coff,
+                               uint32_t *__restrict__ key, uint32_t *__restrict__ val) {
+    __shared__ uint64_t s_rs[4][kWave + 1];
+    __shared__ uint64_t s_src[4][kWave];
+    const uint32_t wv = threadIdx.x / kWave;
     const uint32_t lane = lane_id();
     const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
     const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) / kWave;
-    for (uint64_t x = wave; x < n; x += nwaves) {
-        const uint32_t v = perm[x];
-        const uint64_t o0 = off[v], d = off[v + 1] - o0, dst = off_new[x];
-        for (uint64_t i = lane; i < d; i += kWave) {
-            key[dst + i] = inv[col[o0 + i]];
-            val[dst + i] = (uint32_t)x;
-        }
+    for (uint64_t k = wave; k < items; k += nwaves) {
+        // new rows x = 64q + lane take the list of perm[x]: its first entry in col
+        const uint32_t x0 = map[k] * 64u;
+        s_src[wv][lane] = x0 + lane < n ? off[perm[x0 + lane]] : 0ull;
+        walk_item(n, off_new, map, coff, k, s_rs[wv], [&](uint64_t e, uint32_t j, bool valid) {
+            if (!valid) return;
+            key[e] = col[s_src[wv][j] + (e - s_rs[wv][j])];
+            val[e] = x0 + j;
+        });
+    }
+}
+
+// After the sort, the group of original vertex w sits at [off[w], off[w+1])
+// (its degree is unchanged); new row y = inv[w], i.e. w = perm[y], copies it.
+__global__ void dm_place_kernel(uint32_t n, const uint32_t *__restrict__ perm, const uint64_t *__restrict__ off,
+                                const uint32_t *__restrict__ grouped, const uint64_t *__restrict__ off_new,
+                                uint64_t items, const uint32_t *__restrict__ map, const uint64_t *__restrict__ coff,
+                                uint32_t *__restrict__ col_new) {
+    __shared__ uint64_t s_rs[4][kWave + 1];
+    __shared__ uint64_t s_src[4][kWave];
+    const uint32_t wv = threadIdx.x / kWave;
+    const uint32_t lane = lane_id();
+    const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) / kWave;
+    for (uint64_t k = wave; k < items; k += nwaves) {
+        const uint32_t y0 = map[k] * 64u;
+        s_src[wv][lane] = y0 + lane < n ? off[perm[y0 + lane]] : 0ull;
+        walk_item(n, off_new, map, coff, k, s_rs[wv], [&](uint64_t e, uint32_t j, bool valid) {
+            if (!valid) return;
+            col_new[e] = grouped[s_src[wv][j] + (e - s_rs[wv][j])];
+        });
     }
 }
 
@@ -420,6 +542,30 @@ static lg_status build_offsets(lg_graph *g, const uint64_t *x, uint64_t universe
     return LG_OK;
 }
 
+// Work items of an edge walk over the rows of `off` (see walk_item).
+struct WalkTable {
+    DevBuf cnt, coff, map;
+    uint64_t items = 0;
+    uint32_t grid = 1;
+};
+
+static lg_status walk_table(uint32_t n, const uint64_t *off, WalkTable &t, DevBuf &tmp, hipStream_t s) {
+    const uint64_t blocks = ((uint64_t)n + 63) / 64;
+    LG_TRY(t.cnt.ensure(blocks * 4));
+    LG_TRY(t.coff.ensure((blocks + 1) * 8));
+    LG_LAUNCH(walk_count_kernel, grid_for(blocks, 256, 1u << 16), 256, 0, s, n, off, t.cnt.as<uint32_t>());
+    LG_CHECK_LAUNCH();
+    LG_TRY(exclusive_scan_u32(t.cnt.as<uint32_t>(), t.coff.as<uint64_t>(), blocks, tmp, s));
+    LG_CHECK_HIP(hipMemcpyAsync(&t.items, t.coff.as<uint64_t>() + blocks, 8, hipMemcpyDeviceToHost, s));
+    LG_CHECK_HIP(hipStreamSynchronize(s));
+    LG_TRY(t.map.ensure(t.items * 4));
+    LG_LAUNCH(walk_map_kernel, grid_for(blocks, 256, 1u << 16), 256, 0, s, blocks, t.coff.as<uint64_t>(),
+              t.map.as<uint32_t>());
+    LG_CHECK_LAUNCH();
+    t.grid = grid_for(t.items * kWave, 256, 16384);
+    return LG_OK;
+}
+
 static lg_status encode_impl(uint32_t n, uint64_t m, const uint64_t *row_offsets, const uint32_t *col,
                              const lg_encode_opts &o, hipStream_t s, lg_graph *g) {
     DevBuf tmp, status, deg, stats;
@@ -430,24 +576,35 @@ static lg_status encode_impl(uint32_t n, uint64_t m, const uint64_t *row_offsets
     LG_TRY(stats.alloc(8));
     LG_TRY(fill_u32(status.as<uint32_t>(), 0, 1, s));
     LG_TRY(fill_u32(stats.as<uint32_t>(), 0, 2, s));
-    LG_LAUNCH(validate_kernel, grid_for((uint64_t)n * kWave, 256, 1u << 16), 256, 0, s, n, m, row_offsets, col,
+    LG_LAUNCH(validate_offsets_kernel, grid_for(n, 256, 1u << 16), 256, 0, s, n, m, row_offsets,
               status.as<uint32_t>());
     LG_CHECK_LAUNCH();
     uint32_t bad = 0;
     LG_CHECK_HIP(hipMemcpyAsync(&bad, status.p, 4, hipMemcpyDeviceToHost, s));
     LG_CHECK_HIP(hipStreamSynchronize(s));
+    WalkTable walk;
+    if (!bad) {  // the offsets are sound: walk the lists
+        LG_TRY(walk_table(n, row_offsets, walk, tmp, s));
+        LG_LAUNCH(validate_edges_kernel, walk.grid, 256, 0, s, n, row_offsets, col, walk.items,
+                  walk.map.as<uint32_t>(), walk.coff.as<uint64_t>(), status.as<uint32_t>());
+        LG_CHECK_LAUNCH();
+        LG_CHECK_HIP(hipMemcpyAsync(&bad, status.p, 4, hipMemcpyDeviceToHost, s));
+        LG_CHECK_HIP(hipStreamSynchronize(s));
+    }
     if (!bad && m) {
         DevBuf key, val, key2, val2;
         LG_TRY(key.alloc(m * 4));
         LG_TRY(val.alloc(m * 4));
         LG_TRY(key2.alloc(m * 4));
         LG_TRY(val2.alloc(m * 4));
-        const uint32_t wgrid = grid_for((uint64_t)n * kWave, 256, 1u << 16);
-        LG_LAUNCH(sym_emit_kernel, wgrid, 256, 0, s, n, row_offsets, col, key.as<uint32_t>(), val.as<uint32_t>());
+        LG_LAUNCH(sym_emit_kernel, walk.grid, 256, 0, s, n, row_offsets, col, walk.items, walk.map.as<uint32_t>(),
+                  walk.coff.as<uint64_t>(), key.as<uint32_t>(), val.as<uint32_t>());
         LG_CHECK_LAUNCH();
+        int alt = 0;
         LG_TRY(radix_sort_pairs(key.as<uint32_t>(), val.as<uint32_t>(), key2.as<uint32_t>(), val2.as<uint32_t>(), m,
-                                bitlen_u64(n - 1), tmp, s));
-        LG_LAUNCH(sym_check_kernel, wgrid, 256, 0, s, n, row_offsets, col, key.as<uint32_t>(), val.as<uint32_t>(),
+                                bitlen_u64(n - 1), tmp, s, &alt));
+        LG_LAUNCH(sym_check_kernel, walk.grid, 256, 0, s, n, row_offsets, col, walk.items, walk.map.as<uint32_t>(),
+                  walk.coff.as<uint64_t>(), (alt ? key2 : key).as<uint32_t>(), (alt ? val2 : val).as<uint32_t>(),
                   status.as<uint32_t>());
         LG_CHECK_LAUNCH();
         LG_CHECK_HIP(hipMemcpyAsync(&bad, status.p, 4, hipMemcpyDeviceToHost, s));
@@ -497,12 +654,24 @@ static lg_status encode_impl(uint32_t n, uint64_t m, const uint64_t *row_offsets
             LG_TRY(col_new.alloc(m * 4));
             LG_TRY(key2.alloc(m * 4));
             LG_TRY(val2.alloc(m * 4));
-            LG_LAUNCH(dm_gather_kernel, grid_for((uint64_t)n * kWave, 256, 1u << 16), 256, 0, s, n,
-                      g->perm.as<uint32_t>(), g->inv.as<uint32_t>(), row_offsets, col, off_new.as<uint64_t>(),
+            WalkTable wnew;
+            LG_TRY(walk_table(n, off_new.as<uint64_t>(), wnew, tmp, s));
+            // key: original target; col_new (as values): new source row
+            LG_LAUNCH(dm_emit_kernel, wnew.grid, 256, 0, s, n, g->perm.as<uint32_t>(), row_offsets, col,
+                      off_new.as<uint64_t>(), wnew.items, wnew.map.as<uint32_t>(), wnew.coff.as<uint64_t>(),
                       key.as<uint32_t>(), col_new.as<uint32_t>());
             LG_CHECK_LAUNCH();
+            int alt = 0;
             LG_TRY(radix_sort_pairs(key.as<uint32_t>(), col_new.as<uint32_t>(), key2.as<uint32_t>(),
-                                    val2.as<uint32_t>(), m, idbits, tmp, s));
+                                    val2.as<uint32_t>(), m, idbits, tmp, s, &alt));
+            // the grouped values now sit in col_new (or val2); place them by new row into the other buffer
+            DevBuf &grouped = alt ? val2 : col_new;
+            DevBuf &placed = alt ? col_new : key2;
+            LG_LAUNCH(dm_place_kernel, wnew.grid, 256, 0, s, n, g->perm.as<uint32_t>(), row_offsets,
+                      grouped.as<uint32_t>(), off_new.as<uint64_t>(), wnew.items, wnew.map.as<uint32_t>(),
+                      wnew.coff.as<uint64_t>(), placed.as<uint32_t>());
+            LG_CHECK_LAUNCH();
+            if (!alt) std::swap(col_new, key2);  // col_new holds the relabeled lists
             LG_CHECK_HIP(hipStreamSynchronize(s));
         }
         LG_CHECK_HIP(hipStreamSynchronize(s));

@@ -224,14 +224,16 @@ lg_status exclusive_scan_u64(const uint64_t *in, uint64_t *out, uint64_t count, 
 uint64_t scan_tmp_bytes(uint64_t count);
 uint64_t radix_sort_tmp_bytes(uint64_t count);
 
-// Stable LSD radix sort of (key, value) pairs on key bits [0, bits).
-// Results end in keys/vals (the buffers are ping-ponged with the alt ones).
+// Stable LSD radix sort of (key, value) pairs on key bits [0, bits).  The
+// buffers are ping-ponged with the alt ones; results end in keys/vals, or,
+// when in_alt is not NULL, wherever the last pass wrote them (*in_alt = 1:
+// in keys_alt/vals_alt), which saves a copy after an odd number of passes.
 lg_status radix_sort_pairs(uint32_t *keys, uint32_t *vals, uint32_t *keys_alt, uint32_t *vals_alt,
-                           uint64_t count, uint32_t bits, DevBuf &tmp, hipStream_t s);
+                           uint64_t count, uint32_t bits, DevBuf &tmp, hipStream_t s, int *in_alt = nullptr);
 
 // Stable radix sort of (key, value) pairs whose keys are 64-bit: bits [0, bits).
 lg_status radix_sort_pairs64(uint64_t *keys, uint32_t *vals, uint64_t *keys_alt, uint32_t *vals_alt,
-                             uint64_t count, uint32_t bits, DevBuf &tmp, hipStream_t s);
+                             uint64_t count, uint32_t bits, DevBuf &tmp, hipStream_t s, int *in_alt = nullptr);
 
 // Grid size helper: blocks needed for `count` items at `per_block`, capped.
 inline uint32_t grid_for(uint64_t count, uint64_t per_block, uint64_t cap = 1u << 30) {

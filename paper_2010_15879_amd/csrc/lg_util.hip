@@ -248,7 +248,8 @@ uint64_t radix_sort_tmp_bytes(uint64_t count) {
 
 template <class K>
 static lg_status radix_sort_impl(K *keys, uint32_t *vals, K *keys_alt, uint32_t *vals_alt, uint64_t count,
-                                 uint32_t bits, DevBuf &tmp, hipStream_t s) {
+                                 uint32_t bits, DevBuf &tmp, hipStream_t s, int *in_alt) {
+    if (in_alt) *in_alt = 0;
     if (count <= 1 || bits == 0) return LG_OK;
     const uint64_t ntiles = (count + kSortTile - 1) / kSortTile;
     if (ntiles * 256 >= (1ull << 32)) {
@@ -276,6 +277,10 @@ static lg_status radix_sort_impl(K *keys, uint32_t *vals, K *keys_alt, uint32_t 
         uint32_t *tv = src_v; src_v = dst_v; dst_v = tv;
     }
     if (passes & 1) {
+        if (in_alt) {
+            *in_alt = 1;
+            return LG_OK;
+        }
         LG_CHECK_HIP(hipMemcpyAsync(keys, keys_alt, count * sizeof(K), hipMemcpyDeviceToDevice, s));
         LG_CHECK_HIP(hipMemcpyAsync(vals, vals_alt, count * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
     }
@@ -283,13 +288,13 @@ static lg_status radix_sort_impl(K *keys, uint32_t *vals, K *keys_alt, uint32_t 
 }
 
 lg_status radix_sort_pairs(uint32_t *keys, uint32_t *vals, uint32_t *keys_alt, uint32_t *vals_alt, uint64_t count,
-                           uint32_t bits, DevBuf &tmp, hipStream_t s) {
-    return radix_sort_impl<uint32_t>(keys, vals, keys_alt, vals_alt, count, bits, tmp, s);
+                           uint32_t bits, DevBuf &tmp, hipStream_t s, int *in_alt) {
+    return radix_sort_impl<uint32_t>(keys, vals, keys_alt, vals_alt, count, bits, tmp, s, in_alt);
 }
 
 lg_status radix_sort_pairs64(uint64_t *keys, uint32_t *vals, uint64_t *keys_alt, uint32_t *vals_alt, uint64_t count,
-                             uint32_t bits, DevBuf &tmp, hipStream_t s) {
-    return radix_sort_impl<uint64_t>(keys, vals, keys_alt, vals_alt, count, bits, tmp, s);
+                             uint32_t bits, DevBuf &tmp, hipStream_t s, int *in_alt) {
+    return radix_sort_impl<uint64_t>(keys, vals, keys_alt, vals_alt, count, bits, tmp, s, in_alt);
 }
 
 }  // namespace lg
