@@ -403,17 +403,16 @@ __global__ void bitmap_to_queue_kernel(uint64_t words, const uint64_t *__restric
 }
 
 // results in original IDs: depth_out[o] = depth[inv[o]], parent through perm
+// (unreached vertices, among them every edgeless one, need no parent lookup)
 __global__ void bfs_unpermute_kernel(uint32_t n, const uint32_t *__restrict__ inv, const uint32_t *__restrict__ perm,
                                      const int32_t *__restrict__ depth_i, const uint32_t *__restrict__ parent_i,
                                      int32_t *__restrict__ depth, int32_t *__restrict__ parent) {
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t o = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; o < n; o += stride) {
         const uint32_t x = inv[o];
-        depth[o] = depth_i[x];
-        if (parent) {
-            const uint32_t p = parent_i[x];
-            parent[o] = p == 0xFFFFFFFFu ? -1 : (int32_t)perm[p];
-        }
+        const int32_t d = depth_i[x];
+        depth[o] = d;
+        if (parent) parent[o] = d < 0 ? -1 : (int32_t)perm[parent_i[x]];
     }
 }
 

@@ -143,7 +143,7 @@ lg_status exclusive_scan_u64(const uint64_t *in, uint64_t *out, uint64_t count, 
 // stable LSD radix sort of (key, value) pairs, 8-bit digits
 // ---------------------------------------------------------------------------
 
-constexpr int kSortThreads = 256;
+constexpr int kSortThreads = 512;
 constexpr int kSortRounds = 16;
 constexpr uint64_t kSortTile = (uint64_t)kSortThreads * kSortRounds;
 constexpr int kSortWaves = kSortThreads / kWave;
@@ -152,7 +152,7 @@ template <class K>
 __global__ void radix_hist_kernel(const K *__restrict__ keys, uint64_t count, uint32_t shift, uint32_t ntiles,
                                   uint32_t *__restrict__ counts) {
     __shared__ uint32_t hist[256];
-    hist[threadIdx.x] = 0;
+    if (threadIdx.x < 256) hist[threadIdx.x] = 0;
     __syncthreads();
     const uint64_t t0 = (uint64_t)blockIdx.x * kSortTile;
 #pragma unroll 4
@@ -161,76 +161,98 @@ __global__ void radix_hist_kernel(const K *__restrict__ keys, uint64_t count, ui
         if (i < count) atomicAdd(&hist[(uint32_t)(keys[i] >> shift) & 255u], 1u);
     }
     __syncthreads();
-    counts[(uint64_t)threadIdx.x * ntiles + blockIdx.x] = hist[threadIdx.x];
+    if (threadIdx.x < 256) counts[(uint64_t)threadIdx.x * ntiles + blockIdx.x] = hist[threadIdx.x];
 }
 
-// Items of a tile are taken in rounds of 256 consecutive keys; within a
-// round, lanes with equal digits are found with eight ballots, so every key
-// gets its rank among equal digits in input order (stability).  Keys are
-// first placed in LDS in digit order, then written out so that consecutive
-// threads store consecutive addresses of one digit's run.
+// A tile is eight contiguous sub-tiles of 1,024 keys, one per wave.  A wave
+// ranks its keys 64 at a time: lanes with equal digits are found with eight
+// ballots, and a wave-private LDS counter per digit carries the running count
+// from one group of 64 to the next, so every key gets its rank among equal
+// digits of its sub-tile in input order without waiting for the other waves.
+// One prefix over the waves' counts then gives every key its place in the
+// tile (stability), keys are placed in LDS in digit order, and written out so
+// that consecutive threads store consecutive addresses of one digit's run.
 template <class K>
 __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
     const K *__restrict__ keys, const uint32_t *__restrict__ vals, uint64_t count, uint32_t shift, uint32_t ntiles,
     const uint32_t *__restrict__ counts, const uint64_t *__restrict__ offsets, K *__restrict__ keys_out,
     uint32_t *__restrict__ vals_out) {
+    constexpr int kPer = kSortRounds;  // keys per lane (sub-tile = kWave * kPer keys)
     __shared__ K s_key[kSortTile];
     __shared__ uint32_t s_val[kSortTile];
     __shared__ uint32_t s_start[256];
-    __shared__ uint32_t s_run[256];
     __shared__ uint64_t s_gbase[256];
     __shared__ uint32_t s_wtot[kSortWaves];
     __shared__ uint32_t wave_cnt[kSortWaves][256];
     const uint32_t lane = lane_id(), wv = threadIdx.x / kWave;
     const uint32_t tid = threadIdx.x;
-    // tile-local start of every digit: exclusive scan of this tile's histogram
-    const uint32_t c = counts[(uint64_t)tid * ntiles + blockIdx.x];
+    // tile-local start of every digit (threads 0..255, one digit each):
+    // exclusive scan of this tile's histogram
+    const uint32_t c = tid < 256 ? counts[(uint64_t)tid * ntiles + blockIdx.x] : 0u;
     const uint32_t incl = wave_incl_scan(c);
     if (lane == kWave - 1) s_wtot[wv] = incl;
+    for (uint32_t i = tid; i < kSortWaves * 256; i += kSortThreads) (&wave_cnt[0][0])[i] = 0;
     __syncthreads();
-    uint32_t before = 0;
-    for (uint32_t w = 0; w < wv; ++w) before += s_wtot[w];
-    s_start[tid] = before + incl - c;
-    s_run[tid] = 0;
-    s_gbase[tid] = offsets[(uint64_t)tid * ntiles + blockIdx.x] - (before + incl - c);
-    const uint64_t t0 = (uint64_t)blockIdx.x * kSortTile;
-    for (int r = 0; r < kSortRounds; ++r) {
-        const uint64_t i = t0 + (uint64_t)r * kSortThreads + tid;
-        const bool valid = i < count;
-        K key = 0;
-        uint32_t val = 0;
-        if (valid) { key = keys[i]; val = vals[i]; }
-        const uint32_t digit = (uint32_t)(key >> shift) & 255u;
+    if (tid < 256) {
+        uint32_t before = 0;
+        for (uint32_t w = 0; w < wv; ++w) before += s_wtot[w];
+        s_start[tid] = before + incl - c;
+        s_gbase[tid] = offsets[(uint64_t)tid * ntiles + blockIdx.x] - (before + incl - c);
+    }
+    // this wave's sub-tile, all loads in flight before the first use
+    const uint64_t w0 = (uint64_t)blockIdx.x * kSortTile + (uint64_t)wv * kWave * kPer;
+    K kr[kPer];
+    uint32_t vr[kPer];
+#pragma unroll
+    for (int r = 0; r < kPer; ++r) {
+        const uint64_t i = w0 + (uint64_t)r * kWave + lane;
+        kr[r] = i < count ? keys[i] : (K)0;
+        vr[r] = i < count ? vals[i] : 0u;
+    }
+    uint32_t rank[kPer];
+#pragma unroll
+    for (int r = 0; r < kPer; ++r) {
+        const bool valid = w0 + (uint64_t)r * kWave + lane < count;
+        const uint32_t digit = (uint32_t)(kr[r] >> shift) & 255u;
         uint64_t peers = __ballot(valid);
 #pragma unroll
         for (int b = 0; b < 8; ++b) {
             const uint64_t m = __ballot((digit >> b) & 1u);
             peers &= ((digit >> b) & 1u) ? m : ~m;
         }
-#pragma unroll
-        for (int w = 0; w < kSortWaves; ++w) wave_cnt[w][tid] = 0;
-        __syncthreads();
-        const uint32_t rank = popc_below(peers);
-        if (valid && rank == 0) wave_cnt[wv][digit] = (uint32_t)__popcll(peers);
-        __syncthreads();
-        {   // per digit: running count + exclusive prefix over the waves
-            uint32_t run = s_run[tid];
-#pragma unroll
-            for (int w = 0; w < kSortWaves; ++w) {
-                const uint32_t cw = wave_cnt[w][tid];
-                wave_cnt[w][tid] = run;
-                run += cw;
-            }
-            s_run[tid] = run;
-        }
-        __syncthreads();
-        if (valid) {
-            const uint32_t idx = s_start[digit] + wave_cnt[wv][digit] + rank;
-            s_key[idx] = key;
-            s_val[idx] = val;
-        }
-        __syncthreads();
+        const uint32_t below = popc_below(peers);
+        const uint32_t run = valid ? wave_cnt[wv][digit] : 0u;
+        rank[r] = run + below;
+        // the group's first lane advances the digit's running count; the wave
+        // reads every count of this group before any lane writes
+        __builtin_amdgcn_wave_barrier();
+        if (valid && below == 0) wave_cnt[wv][digit] = run + (uint32_t)__popcll(peers);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
+    __syncthreads();
+    if (tid < 256) {  // per digit: exclusive prefix of the waves' counts
+        uint32_t run = 0;
+#pragma unroll
+        for (int w = 0; w < kSortWaves; ++w) {
+            const uint32_t cw = wave_cnt[w][tid];
+            wave_cnt[w][tid] = run;
+            run += cw;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kPer; ++r) {
+        if (w0 + (uint64_t)r * kWave + lane < count) {
+            const uint32_t digit = (uint32_t)(kr[r] >> shift) & 255u;
+            const uint32_t idx = s_start[digit] + wave_cnt[wv][digit] + rank[r];
+            s_key[idx] = kr[r];
+            s_val[idx] = vr[r];
+        }
+    }
+    __syncthreads();
+    const uint64_t t0 = (uint64_t)blockIdx.x * kSortTile;
     const uint64_t tile_n = count - t0 < kSortTile ? count - t0 : kSortTile;
     for (uint32_t idx = tid; idx < tile_n; idx += kSortThreads) {
         const K key = s_key[idx];
