@@ -439,6 +439,8 @@ def serve_main(args, np, torch, gg, lg, dev):
             del g
             torch.cuda.empty_cache()
     torch.cuda.synchronize()
+    lg.trim()  # the encoder's cached temporaries are not part of the served state
+    torch.cuda.empty_cache()
     budget = 200 * 10**9
     srv = lg.Server(hs, budget_bytes=budget, workers=8, max_batch=64)
     kinds = ["neighbors", "khop", "bfs"]

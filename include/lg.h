@@ -355,6 +355,14 @@ uint64_t lg_export_bytes(const lg_graph *g, uint32_t which);
 /* Thread-local description of the last failure on this thread. */
 const char *lg_last_error(void);
 
+/* lg_encode keeps its temporary device buffers (sort keys, scans, tables;
+ * about four times the input neighbor array) in a per-process cache for the next
+ * encode on the same device and stream, instead of freeing them, so that
+ * repeated encodes neither allocate nor synchronize the device to free.  The
+ * cache holds at most 64 GiB; lg_trim frees it.  Call it when no library call
+ * is running. */
+void lg_trim(void);
+
 /*
  * Kernel timing: while enabled, every kernel launch is bracketed by two HIP
  * events on the stream it is launched on.  lg_prof_query sums the elapsed

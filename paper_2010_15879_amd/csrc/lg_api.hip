@@ -20,6 +20,89 @@ void set_error(const char *fmt, ...) {
     va_end(ap);
 }
 
+// ---------------------------------------------------------------------------
+// scratch pool: released scratch buffers stay allocated for the next request
+// on the same device and stream (work on one stream runs in order, so a
+// buffer taken again there is only touched after the earlier work)
+// ---------------------------------------------------------------------------
+
+namespace {
+struct Cached {
+    int device;
+    hipStream_t stream;
+    uint64_t bytes;
+    void *p;
+};
+struct Pool {
+    std::mutex mu;
+    std::vector<Cached> list;
+    uint64_t total = 0;
+};
+Pool &pool() {
+    static Pool *p = new Pool();  // never destroyed: buffers may outlive static teardown
+    return *p;
+}
+constexpr uint64_t kPoolCap = 64ull << 30;  // bytes the pool keeps at most
+}  // namespace
+
+void DevBuf::release() {
+    if (p) {
+        if (pooled) {
+            int dev = 0;
+            (void)hipGetDevice(&dev);
+            Pool &pl = pool();
+            std::lock_guard<std::mutex> g(pl.mu);
+            while (pl.total + bytes > kPoolCap && !pl.list.empty()) {
+                (void)hipFree(pl.list.front().p);
+                pl.total -= pl.list.front().bytes;
+                pl.list.erase(pl.list.begin());
+            }
+            if (bytes <= kPoolCap) {
+                pl.list.push_back(Cached{dev, pool_stream, bytes, p});
+                pl.total += bytes;
+            } else {
+                (void)hipFree(p);
+            }
+        } else {
+            (void)hipFree(p);
+        }
+    }
+    p = nullptr;
+    bytes = 0;
+    pooled = false;
+}
+
+lg_status DevBuf::scratch(uint64_t nbytes, hipStream_t s) {
+    release();
+    if (nbytes == 0) nbytes = 8;
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    {
+        Pool &pl = pool();
+        std::lock_guard<std::mutex> g(pl.mu);
+        size_t best = pl.list.size();
+        for (size_t i = 0; i < pl.list.size(); ++i) {
+            const Cached &c = pl.list[i];
+            if (c.device == dev && c.stream == s && c.bytes >= nbytes && c.bytes <= nbytes + nbytes / 4 + (2u << 20) &&
+                (best == pl.list.size() || c.bytes < pl.list[best].bytes))
+                best = i;
+        }
+        if (best < pl.list.size()) {
+            p = pl.list[best].p;
+            bytes = pl.list[best].bytes;
+            pl.total -= bytes;
+            pl.list.erase(pl.list.begin() + (long)best);
+            pool_stream = s;
+            pooled = true;
+            return LG_OK;
+        }
+    }
+    LG_TRY(alloc(nbytes));
+    pool_stream = s;
+    pooled = true;
+    return LG_OK;
+}
+
 lg_status DevBuf::alloc(uint64_t nbytes) {
     release();
     if (nbytes == 0) nbytes = 8;
@@ -36,6 +119,7 @@ lg_status DevBuf::alloc(uint64_t nbytes) {
 
 lg_status DevBuf::ensure(uint64_t nbytes) {
     if (p && bytes >= nbytes) return LG_OK;
+    if (pooled) return scratch(nbytes, pool_stream);
     return alloc(nbytes);
 }
 
@@ -263,6 +347,14 @@ extern "C" lg_status lg_export(const lg_graph *g, uint32_t which, void *host_dst
 }
 
 extern "C" const char *lg_last_error(void) { return lg::t_err; }
+
+extern "C" void lg_trim(void) {
+    lg::Pool &pl = lg::pool();
+    std::lock_guard<std::mutex> g(pl.mu);
+    for (const lg::Cached &c : pl.list) (void)hipFree(c.p);
+    pl.list.clear();
+    pl.total = 0;
+}
 
 extern "C" lg_status lg_prof_enable(int on) {
     auto &st = lg::prof();

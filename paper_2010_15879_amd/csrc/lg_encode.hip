@@ -522,8 +522,8 @@ static lg_status build_offsets(lg_graph *g, const uint64_t *x, uint64_t universe
     const uint64_t nsb = (g->hbits + 511) / 512;
     g->n_rank = nsb + 1;
     DevBuf cnt, scanned;
-    LG_TRY(cnt.alloc(nsb * 4));
-    LG_TRY(scanned.alloc((nsb + 1) * 8));
+    LG_TRY(cnt.scratch(nsb * 4, s));
+    LG_TRY(scanned.scratch((nsb + 1) * 8, s));
     LG_LAUNCH(ef_superblock_count_kernel, grid1(nsb), 256, 0, s, nsb, g->H_words, g->H.as<uint64_t>(),
               cnt.as<uint32_t>());
     LG_CHECK_LAUNCH();
@@ -551,14 +551,14 @@ struct WalkTable {
 
 static lg_status walk_table(uint32_t n, const uint64_t *off, WalkTable &t, DevBuf &tmp, hipStream_t s) {
     const uint64_t blocks = ((uint64_t)n + 63) / 64;
-    LG_TRY(t.cnt.ensure(blocks * 4));
-    LG_TRY(t.coff.ensure((blocks + 1) * 8));
+    LG_TRY(t.cnt.scratch(blocks * 4, s));
+    LG_TRY(t.coff.scratch((blocks + 1) * 8, s));
     LG_LAUNCH(walk_count_kernel, grid_for(blocks, 256, 1u << 16), 256, 0, s, n, off, t.cnt.as<uint32_t>());
     LG_CHECK_LAUNCH();
     LG_TRY(exclusive_scan_u32(t.cnt.as<uint32_t>(), t.coff.as<uint64_t>(), blocks, tmp, s));
     LG_CHECK_HIP(hipMemcpyAsync(&t.items, t.coff.as<uint64_t>() + blocks, 8, hipMemcpyDeviceToHost, s));
     LG_CHECK_HIP(hipStreamSynchronize(s));
-    LG_TRY(t.map.ensure(t.items * 4));
+    LG_TRY(t.map.scratch(t.items * 4, s));
     LG_LAUNCH(walk_map_kernel, grid_for(blocks, 256, 1u << 16), 256, 0, s, blocks, t.coff.as<uint64_t>(),
               t.map.as<uint32_t>());
     LG_CHECK_LAUNCH();
@@ -572,8 +572,9 @@ static lg_status encode_impl(uint32_t n, uint64_t m, const uint64_t *row_offsets
     LG_CHECK_HIP(hipGetDevice(&g->device));
 
     // -- validation ------------------------------------------------------
-    LG_TRY(status.alloc(4));
-    LG_TRY(stats.alloc(8));
+    LG_TRY(tmp.scratch(8, s));
+    LG_TRY(status.scratch(4, s));
+    LG_TRY(stats.scratch(8, s));
     LG_TRY(fill_u32(status.as<uint32_t>(), 0, 1, s));
     LG_TRY(fill_u32(stats.as<uint32_t>(), 0, 2, s));
     LG_LAUNCH(validate_offsets_kernel, grid_for(n, 256, 1u << 16), 256, 0, s, n, m, row_offsets,
@@ -593,10 +594,10 @@ static lg_status encode_impl(uint32_t n, uint64_t m, const uint64_t *row_offsets
     }
     if (!bad && m) {
         DevBuf key, val, key2, val2;
-        LG_TRY(key.alloc(m * 4));
-        LG_TRY(val.alloc(m * 4));
-        LG_TRY(key2.alloc(m * 4));
-        LG_TRY(val2.alloc(m * 4));
+        LG_TRY(key.scratch(m * 4, s));
+        LG_TRY(val.scratch(m * 4, s));
+        LG_TRY(key2.scratch(m * 4, s));
+        LG_TRY(val2.scratch(m * 4, s));
         LG_LAUNCH(sym_emit_kernel, walk.grid, 256, 0, s, n, row_offsets, col, walk.items, walk.map.as<uint32_t>(),
                   walk.coff.as<uint64_t>(), key.as<uint32_t>(), val.as<uint32_t>());
         LG_CHECK_LAUNCH();
@@ -616,7 +617,7 @@ static lg_status encode_impl(uint32_t n, uint64_t m, const uint64_t *row_offsets
                   (bad & kUnsorted) ? " unsorted-or-duplicate" : "", (bad & kAsymmetric) ? " not-symmetric" : "");
         return LG_ERR_INVALID;
     }
-    LG_TRY(deg.alloc((uint64_t)n * 4));
+    LG_TRY(deg.scratch((uint64_t)n * 4, s));
     LG_LAUNCH(degree_kernel, grid_for(n, 256, 4096), 256, 0, s, n, row_offsets, deg.as<uint32_t>(), stats.as<uint32_t>());
     LG_CHECK_LAUNCH();
     uint32_t st[2];
@@ -632,12 +633,12 @@ static lg_status encode_impl(uint32_t n, uint64_t m, const uint64_t *row_offsets
     const uint32_t idbits = bitlen_u64(n - 1);
     if (o.relabel == LG_RELABEL_DEGREE) {
         DevBuf k1, k2, v2, deg_new;
-        LG_TRY(k1.alloc((uint64_t)n * 4));
-        LG_TRY(k2.alloc((uint64_t)n * 4));
-        LG_TRY(v2.alloc((uint64_t)n * 4));
+        LG_TRY(k1.scratch((uint64_t)n * 4, s));
+        LG_TRY(k2.scratch((uint64_t)n * 4, s));
+        LG_TRY(v2.scratch((uint64_t)n * 4, s));
         LG_TRY(g->perm.alloc((uint64_t)n * 4));
         LG_TRY(g->inv.alloc((uint64_t)n * 4));
-        LG_TRY(deg_new.alloc((uint64_t)n * 4));
+        LG_TRY(deg_new.scratch((uint64_t)n * 4, s));
         LG_LAUNCH(dm_keys_kernel, grid1(n), 256, 0, s, n, deg.as<uint32_t>(), k1.as<uint32_t>(),
                   g->perm.as<uint32_t>());
         LG_CHECK_LAUNCH();
@@ -646,14 +647,14 @@ static lg_status encode_impl(uint32_t n, uint64_t m, const uint64_t *row_offsets
         LG_LAUNCH(dm_inverse_kernel, grid1(n), 256, 0, s, n, g->perm.as<uint32_t>(), deg.as<uint32_t>(),
                   g->inv.as<uint32_t>(), deg_new.as<uint32_t>());
         LG_CHECK_LAUNCH();
-        LG_TRY(off_new.alloc(((uint64_t)n + 1) * 8));
+        LG_TRY(off_new.scratch(((uint64_t)n + 1) * 8, s));
         LG_TRY(exclusive_scan_u32(deg_new.as<uint32_t>(), off_new.as<uint64_t>(), n, tmp, s));
         if (m) {
             DevBuf key, key2, val2;
-            LG_TRY(key.alloc(m * 4));
-            LG_TRY(col_new.alloc(m * 4));
-            LG_TRY(key2.alloc(m * 4));
-            LG_TRY(val2.alloc(m * 4));
+            LG_TRY(key.scratch(m * 4, s));
+            LG_TRY(col_new.scratch(m * 4, s));
+            LG_TRY(key2.scratch(m * 4, s));
+            LG_TRY(val2.scratch(m * 4, s));
             WalkTable wnew;
             LG_TRY(walk_table(n, off_new.as<uint64_t>(), wnew, tmp, s));
             // key: original target; col_new (as values): new source row
@@ -682,8 +683,8 @@ static lg_status encode_impl(uint32_t n, uint64_t m, const uint64_t *row_offsets
     // -- heavy vertex list (shared by the traversal kernels) -------------
     {
         DevBuf flag, pos;
-        LG_TRY(flag.alloc((uint64_t)n * 4));
-        LG_TRY(pos.alloc(((uint64_t)n + 1) * 8));
+        LG_TRY(flag.scratch((uint64_t)n * 4, s));
+        LG_TRY(pos.scratch(((uint64_t)n + 1) * 8, s));
         LG_LAUNCH(heavy_flag_kernel, grid1(n), 256, 0, s, n, cur_off, g->heavy_threshold, flag.as<uint32_t>());
         LG_CHECK_LAUNCH();
         LG_TRY(exclusive_scan_u32(flag.as<uint32_t>(), pos.as<uint64_t>(), n, tmp, s));
@@ -734,9 +735,9 @@ static lg_status encode_impl(uint32_t n, uint64_t m, const uint64_t *row_offsets
     } else {
         g->F = bitlen_u64(g->s);
         DevBuf w8, len, P;
-        LG_TRY(w8.alloc((uint64_t)n));
-        LG_TRY(len.alloc((uint64_t)n * 8));
-        LG_TRY(P.alloc(((uint64_t)n + 1) * 8));
+        LG_TRY(w8.scratch((uint64_t)n, s));
+        LG_TRY(len.scratch((uint64_t)n * 8, s));
+        LG_TRY(P.scratch(((uint64_t)n + 1) * 8, s));
         LG_LAUNCH(local_width_kernel, grid1(n), 256, 0, s, n, cur_off, cur_col, w8.as<uint8_t>(),
                   len.as<uint64_t>());
         LG_CHECK_LAUNCH();

@@ -43,22 +43,32 @@ void set_error(const char *fmt, ...);
 struct DevBuf {
     void *p = nullptr;
     uint64_t bytes = 0;
+    hipStream_t pool_stream = nullptr;  // scratch from the pool: returns there on release
+    bool pooled = false;
     DevBuf() = default;
     DevBuf(const DevBuf &) = delete;
     DevBuf &operator=(const DevBuf &) = delete;
-    DevBuf(DevBuf &&o) noexcept : p(o.p), bytes(o.bytes) { o.p = nullptr; o.bytes = 0; }
+    DevBuf(DevBuf &&o) noexcept : p(o.p), bytes(o.bytes), pool_stream(o.pool_stream), pooled(o.pooled) {
+        o.p = nullptr;
+        o.bytes = 0;
+        o.pooled = false;
+    }
     DevBuf &operator=(DevBuf &&o) noexcept {
-        if (this != &o) { release(); p = o.p; bytes = o.bytes; o.p = nullptr; o.bytes = 0; }
+        if (this != &o) {
+            release();
+            p = o.p; bytes = o.bytes; pool_stream = o.pool_stream; pooled = o.pooled;
+            o.p = nullptr; o.bytes = 0; o.pooled = false;
+        }
         return *this;
     }
     ~DevBuf() { release(); }
-    void release() {
-        if (p) (void)hipFree(p);
-        p = nullptr;
-        bytes = 0;
-    }
+    void release();
     lg_status alloc(uint64_t nbytes);          // release + allocate
     lg_status ensure(uint64_t nbytes);         // grow only
+    // release + take a buffer of at least nbytes that is only ever used on
+    // stream s, from the scratch pool when one fits (no allocation, no
+    // device-wide synchronization when it is released again)
+    lg_status scratch(uint64_t nbytes, hipStream_t s);
     template <class T> T *as() const { return static_cast<T *>(p); }
 };
 

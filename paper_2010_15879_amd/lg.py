@@ -105,6 +105,7 @@ FUNCTIONS = {
     "lg_export": (C.c_int, [C.c_void_p, C.c_uint32, C.c_void_p, C.c_uint64]),
     "lg_export_bytes": (C.c_uint64, [C.c_void_p, C.c_uint32]),
     "lg_last_error": (C.c_char_p, []),
+    "lg_trim": (None, []),
     "lg_prof_enable": (C.c_int, [C.c_int]),
     "lg_prof_reset": (C.c_int, []),
     "lg_prof_query": (C.c_int, [C.c_char_p, C.POINTER(C.c_uint64), C.POINTER(C.c_double)]),
@@ -433,3 +434,8 @@ def admission_simulate(arrival, need, service, budget, resident, workers):
     _check(lib().lg_admission_simulate(a, nd, sv, n, int(budget), int(resident), int(workers), st, fi, ss,
                                        C.byref(pk)))
     return list(st)[:n], list(fi)[:n], list(ss)[:n], int(pk.value)
+
+
+def trim():
+    """Free the device buffers lg_encode keeps for reuse (lg_trim)."""
+    lib().lg_trim()
