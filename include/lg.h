@@ -156,7 +156,9 @@ lg_status lg_decode_neighbors(const lg_graph *g, const uint32_t *vertices, uint3
  * with its own workspace; work queued on `stream` before the call completes
  * first, and work queued on `stream` after it waits for every root.  The
  * call returns once every root has been enqueued; each row equals the result
- * of a call with that root alone.  Calls on the same graph must not overlap.
+ * of a call with that root alone.  Those streams and workspaces belong to the
+ * device, not to the graph: they grow to the largest graph searched and stay
+ * until lg_trim; multi-root calls on one device run one after the other.
  */
 lg_status lg_bfs(const lg_graph *g, const uint32_t *roots, uint32_t r, int32_t *depth,
                  int32_t *parent, int32_t max_depth, uint32_t flags, hipStream_t stream);
@@ -359,8 +361,8 @@ const char *lg_last_error(void);
  * about four times the input neighbor array) in a per-process cache for the next
  * encode on the same device and stream, instead of freeing them, so that
  * repeated encodes neither allocate nor synchronize the device to free.  The
- * cache holds at most 64 GiB; lg_trim frees it.  Call it when no library call
- * is running. */
+ * cache holds at most 64 GiB.  lg_trim frees it, and the per-device workspaces
+ * of multi-root lg_bfs calls.  Call it when no library call is running. */
 void lg_trim(void);
 
 /*

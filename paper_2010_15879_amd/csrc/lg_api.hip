@@ -349,6 +349,7 @@ extern "C" lg_status lg_export(const lg_graph *g, uint32_t which, void *host_dst
 extern "C" const char *lg_last_error(void) { return lg::t_err; }
 
 extern "C" void lg_trim(void) {
+    lg::bfs_pools_trim();
     lg::Pool &pl = lg::pool();
     std::lock_guard<std::mutex> g(pl.mu);
     for (const lg::Cached &c : pl.list) (void)hipFree(c.p);

@@ -20,6 +20,8 @@
 // direction-optimizing BFS; it changes the running time only.
 #include <algorithm>
 #include <atomic>
+#include <map>
+#include <mutex>
 #include <string>
 #include <thread>
 #include <vector>
@@ -56,15 +58,11 @@ uint64_t BfsPool::bytes() const {
     return b;
 }
 
-uint64_t bfs_bytes(const lg_graph *g) {
-    return (g->bfs ? g->bfs->bytes() : 0) + (g->bfs_pool ? g->bfs_pool->bytes() : 0);
-}
+uint64_t bfs_bytes(const lg_graph *g) { return g->bfs ? g->bfs->bytes() : 0; }
 
 lg_status bfs_free(lg_graph *g) {
     delete g->bfs;
     g->bfs = nullptr;
-    delete g->bfs_pool;
-    g->bfs_pool = nullptr;
     return LG_OK;
 }
 
@@ -573,13 +571,42 @@ lg_status bfs_run(lg_graph *g, BfsWork &w, const uint32_t *roots, uint32_t r, in
 
 constexpr uint32_t kBfsLanes = 4;
 
-static lg_status pool_ensure(lg_graph *g, uint32_t lanes) {
-    if (!g->bfs_pool) {
-        g->bfs_pool = new (std::nothrow) BfsPool();
-        if (!g->bfs_pool) { set_error("lg_bfs: host allocation failed"); return LG_ERR_OOM; }
-        LG_CHECK_HIP(hipEventCreateWithFlags(&g->bfs_pool->start, hipEventDisableTiming));
+// One set of lanes per device, shared by all graphs (workspaces grow to the
+// largest graph and stay until lg_trim); a multi-root call holds it for its
+// duration, so such calls on one device run one after the other.
+namespace {
+struct DevicePools {
+    std::mutex mu;
+    std::map<int, BfsPool *> pools;
+    std::map<int, std::mutex *> locks;
+};
+DevicePools &device_pools() {
+    static DevicePools *d = new DevicePools();  // never destroyed (streams may outlive static teardown)
+    return *d;
+}
+}  // namespace
+
+void bfs_pools_trim() {
+    DevicePools &d = device_pools();
+    std::lock_guard<std::mutex> g(d.mu);
+    for (auto &kv : d.pools) {
+        std::lock_guard<std::mutex> l(*d.locks[kv.first]);
+        int prev = 0;
+        (void)hipGetDevice(&prev);
+        (void)hipSetDevice(kv.first);
+        delete kv.second;
+        (void)hipSetDevice(prev);
     }
-    BfsPool &p = *g->bfs_pool;
+    d.pools.clear();
+}
+
+static lg_status pool_ensure(BfsPool *&pp, uint32_t lanes) {
+    if (!pp) {
+        pp = new (std::nothrow) BfsPool();
+        if (!pp) { set_error("lg_bfs: host allocation failed"); return LG_ERR_OOM; }
+        LG_CHECK_HIP(hipEventCreateWithFlags(&pp->start, hipEventDisableTiming));
+    }
+    BfsPool &p = *pp;
     while (p.lanes.size() < lanes) {
         BfsLane *l = new (std::nothrow) BfsLane();
         if (!l) { set_error("lg_bfs: host allocation failed"); return LG_ERR_OOM; }
@@ -597,8 +624,18 @@ static lg_status pool_ensure(lg_graph *g, uint32_t lanes) {
 static lg_status bfs_run_lanes(lg_graph *g, const uint32_t *roots, uint32_t r, int32_t *depth, int32_t *parent,
                                int32_t max_depth, uint32_t flags, hipStream_t stream) {
     const uint32_t L = std::min<uint32_t>(r, kBfsLanes);
-    LG_TRY(pool_ensure(g, L));
-    BfsPool &p = *g->bfs_pool;
+    DevicePools &dp = device_pools();
+    std::mutex *dev_lock;
+    BfsPool **slot;
+    {
+        std::lock_guard<std::mutex> gl(dp.mu);
+        if (!dp.locks.count(g->device)) dp.locks[g->device] = new std::mutex();
+        dev_lock = dp.locks[g->device];
+        slot = &dp.pools[g->device];
+    }
+    std::lock_guard<std::mutex> hold(*dev_lock);
+    LG_TRY(pool_ensure(*slot, L));
+    BfsPool &p = **slot;
     LG_CHECK_HIP(hipEventRecord(p.start, stream));
     for (uint32_t i = 0; i < L; ++i) LG_CHECK_HIP(hipStreamWaitEvent(p.lanes[i]->stream, p.start, 0));
     std::atomic<uint32_t> next{0};

@@ -106,6 +106,7 @@ struct BfsWork {
 // Roots of one lg_bfs call run on a few lanes at once: each lane has its own
 // stream (default priority), workspace and host thread, so that one root's
 // host round trips between levels are covered by another root's kernels.
+// One set of lanes per device (lg_bfs.hip), freed by lg_trim.
 struct BfsLane {
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr;
@@ -180,7 +181,6 @@ struct lg_graph {
     // lazily allocated workspaces of the plain calls (lg_bfs, lg_pagerank,
     // lg_decode_neighbors); the server brings its own per worker
     lg::BfsWork *bfs = nullptr;
-    lg::BfsPool *bfs_pool = nullptr;
     lg::PrWork *pr = nullptr;
     lg::DecodeWork *dec = nullptr;
 
@@ -259,6 +259,7 @@ inline uint32_t bitlen_u64(uint64_t x) { return x ? 64u - (uint32_t)__builtin_cl
 lg_status ensure_heavy_segments(lg_graph *g, hipStream_t s);
 
 lg_status bfs_free(lg_graph *g);
+void bfs_pools_trim();
 lg_status bfs_workspace_ensure(BfsWork &w, uint64_t n, uint64_t n_heavy, bool relabel, bool need_parent);
 // BFS from host roots on an explicit workspace (lg_bfs without argument checks)
 lg_status bfs_run(lg_graph *g, BfsWork &w, const uint32_t *roots, uint32_t r, int32_t *depth, int32_t *parent,
