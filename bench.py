@@ -268,7 +268,12 @@ def main():
     c_pull, ms_pull = kernel_ms.get("pr_iter_kernel", [0, 0.0])
     pull_avg_ms = ms_pull / max(c_pull, 1)
     pull_gbs = pr_launch_bytes / (pull_avg_ms / 1000.0) / 1e9 if c_pull else 0.0
-    dominant = max(kernel_ms.items(), key=lambda kv: kv[1][1])[0] if kernel_ms else None
+    # The roofline goes with the kernel that holds the largest share of wall
+    # time.  PageRank launches run one after another; the BFS kernels run on
+    # eight concurrent lanes, so their summed launch times overlap and bound
+    # nothing: the whole BFS phase (bfs_all_ms) is an upper bound on any one of
+    # them, as the encode phase is for every encoder kernel.
+    largest_summed = max(kernel_ms.items(), key=lambda kv: kv[1][1])[0] if kernel_ms else None
 
     # -- plain uint32 CSR on the same labeling ----------------------------------
     plain = None
@@ -317,6 +322,8 @@ def main():
                "sample": f"oracle BFS from 1 root ({t_orc_bfs:.1f}s, incl. degree relabel for parents) + "
                          f"1 PageRank iteration ({t_orc_pr:.1f}s) on the same graph, single thread"}
 
+    pr_kernel_ms_step = ms_pull / args.steps
+    dominant = "pr_iter_kernel" if pr_kernel_ms_step >= max(bfs_all_ms, encode_ms) else largest_summed
     out = {
         "metric": "GTEPS & HBM GB/s, Log(Graph)-packed vs plain CSR on GPU; p99 query latency",
         "value": round(value, 4),
@@ -336,7 +343,10 @@ def main():
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(pull_gbs / HBM_PEAK_GBS, 4),
                      "traffic": measured_traffic("pr_iter_kernel", args.workload),
                      "bytes_per_launch": pr_launch_bytes, "avg_launch_ms": pull_avg_ms,
-                     "dominant_kernel": dominant},
+                     "dominant_kernel": dominant,
+                     "dominant_by": "wall-time share: pr_iter_kernel time per step vs the BFS and encode phases' "
+                                    "wall times, which bound every kernel inside them",
+                     "largest_summed_kernel": largest_summed},
         "cpu_baseline": cpu,
         "detail": {
             "bfs_all_roots_ms": bfs_all_ms, "bfs_gteps_all_roots": round(bfs_gteps_all, 3),

@@ -569,7 +569,7 @@ lg_status bfs_run(lg_graph *g, BfsWork &w, const uint32_t *roots, uint32_t r, in
     });
 }
 
-constexpr uint32_t kBfsLanes = 4;
+constexpr uint32_t kBfsLanes = 8;
 
 // One set of lanes per device, shared by all graphs (workspaces grow to the
 // largest graph and stay until lg_trim); a multi-root call holds it for its
