@@ -357,12 +357,14 @@ uint64_t lg_export_bytes(const lg_graph *g, uint32_t which);
 /* Thread-local description of the last failure on this thread. */
 const char *lg_last_error(void);
 
-/* lg_encode keeps its temporary device buffers (sort keys, scans, tables;
- * about four times the input neighbor array) in a per-process cache for the next
- * encode on the same device and stream, instead of freeing them, so that
- * repeated encodes neither allocate nor synchronize the device to free.  The
- * cache holds at most 64 GiB.  lg_trim frees it, and the per-device workspaces
- * of multi-root lg_bfs calls.  Call it when no library call is running. */
+/* Device buffers of lg_encode (its temporaries: sort keys, scans, tables;
+ * about four times the input neighbor array) and of a graph (its arrays and
+ * PageRank tables, when lg_free releases them) go to a per-process cache for
+ * the next request on the same device and stream, instead of being freed, so
+ * that repeated encodes neither allocate nor synchronize the device to free.
+ * The cache holds at most 64 GiB.  lg_trim frees it, and the per-device
+ * workspaces of multi-root lg_bfs calls.  Call it when no library call is
+ * running. */
 void lg_trim(void);
 
 /*

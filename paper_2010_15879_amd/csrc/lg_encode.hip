@@ -489,7 +489,7 @@ static inline uint32_t grid1(uint64_t count) { return grid_for(count, 256, 1u <<
 template <class Src>
 static lg_status pack_fixed(Src src, uint64_t count, uint32_t w, DevBuf &dst, uint64_t &words, hipStream_t s) {
     words = (count * w + 63) / 64 + 1;
-    LG_TRY(dst.alloc(words * 8));
+    LG_TRY(dst.scratch(words * 8, s));
     LG_LAUNCH(pack_fixed_kernel<Src>, grid1(words), 256, 0, s, src, count, w, w ? 1.0 / (double)w : 0.0, words,
               dst.as<uint64_t>());
     LG_CHECK_LAUNCH();
@@ -515,7 +515,7 @@ static lg_status build_offsets(lg_graph *g, const uint64_t *x, uint64_t universe
     const uint64_t lowmask = l ? ((1ull << l) - 1) : 0ull;
     LG_TRY(pack_fixed(SrcU64Mask{x, lowmask}, count, l, g->L, g->L_words, s));
     g->H_words = (g->hbits + 63) / 64 + 1;
-    LG_TRY(g->H.alloc(g->H_words * 8));
+    LG_TRY(g->H.scratch(g->H_words * 8, s));
     LG_TRY(fill_u64(g->H.as<uint64_t>(), 0, g->H_words, s));
     LG_LAUNCH(ef_high_kernel, grid1(count), 256, 0, s, count, x, l, g->H.as<unsigned long long>());
     LG_CHECK_LAUNCH();
@@ -528,12 +528,12 @@ static lg_status build_offsets(lg_graph *g, const uint64_t *x, uint64_t universe
               cnt.as<uint32_t>());
     LG_CHECK_LAUNCH();
     LG_TRY(exclusive_scan_u32(cnt.as<uint32_t>(), scanned.as<uint64_t>(), nsb, tmp, s));
-    LG_TRY(g->rank_sb.alloc(g->n_rank * 4));
+    LG_TRY(g->rank_sb.scratch(g->n_rank * 4, s));
     LG_LAUNCH(u64_to_u32_kernel, grid1(g->n_rank), 256, 0, s, g->n_rank, scanned.as<uint64_t>(),
               g->rank_sb.as<uint32_t>());
     LG_CHECK_LAUNCH();
     g->n_sel = (count + 63) / 64;
-    LG_TRY(g->sel.alloc(g->n_sel * 4));
+    LG_TRY(g->sel.scratch(g->n_sel * 4, s));
     LG_LAUNCH(ef_select_kernel, grid1(g->n_sel), 256, 0, s, g->n_sel, x, l, g->sel.as<uint32_t>());
     LG_CHECK_LAUNCH();
     // the kernels above read cnt/scanned before this function returns and
@@ -636,8 +636,8 @@ static lg_status encode_impl(uint32_t n, uint64_t m, const uint64_t *row_offsets
         LG_TRY(k1.scratch((uint64_t)n * 4, s));
         LG_TRY(k2.scratch((uint64_t)n * 4, s));
         LG_TRY(v2.scratch((uint64_t)n * 4, s));
-        LG_TRY(g->perm.alloc((uint64_t)n * 4));
-        LG_TRY(g->inv.alloc((uint64_t)n * 4));
+        LG_TRY(g->perm.scratch((uint64_t)n * 4, s));
+        LG_TRY(g->inv.scratch((uint64_t)n * 4, s));
         LG_TRY(deg_new.scratch((uint64_t)n * 4, s));
         LG_LAUNCH(dm_keys_kernel, grid1(n), 256, 0, s, n, deg.as<uint32_t>(), k1.as<uint32_t>(),
                   g->perm.as<uint32_t>());
@@ -692,12 +692,12 @@ static lg_status encode_impl(uint32_t n, uint64_t m, const uint64_t *row_offsets
         LG_CHECK_HIP(hipMemcpyAsync(&nh, pos.as<uint64_t>() + n, 8, hipMemcpyDeviceToHost, s));
         LG_CHECK_HIP(hipStreamSynchronize(s));
         g->n_heavy = (uint32_t)nh;
-        LG_TRY(g->heavy.alloc((nh ? nh : 1) * 4));
+        LG_TRY(g->heavy.scratch((nh ? nh : 1) * 4, s));
         LG_LAUNCH(heavy_scatter_kernel, grid1(n), 256, 0, s, n, flag.as<uint32_t>(), pos.as<uint64_t>(),
                   g->heavy.as<uint32_t>());
         LG_CHECK_LAUNCH();
         const uint64_t words = ((uint64_t)n + 63) / 64;
-        LG_TRY(g->iso.alloc(words * 8));
+        LG_TRY(g->iso.scratch(words * 8, s));
         LG_LAUNCH(isolated_bitmap_kernel, grid_for(words * kWave, 256, 1u << 16), 256, 0, s, n, cur_off,
                   g->iso.as<uint64_t>());
         LG_CHECK_LAUNCH();
@@ -708,10 +708,10 @@ static lg_status encode_impl(uint32_t n, uint64_t m, const uint64_t *row_offsets
     if (o.layout == LG_LAYOUT_PLAIN) {
         g->poff64 = m >= (1ull << 32);
         if (g->poff64) {
-            LG_TRY(g->poff.alloc(((uint64_t)n + 1) * 8));
+            LG_TRY(g->poff.scratch(((uint64_t)n + 1) * 8, s));
             LG_CHECK_HIP(hipMemcpyAsync(g->poff.p, cur_off, ((uint64_t)n + 1) * 8, hipMemcpyDeviceToDevice, s));
         } else {
-            LG_TRY(g->poff.alloc(((uint64_t)n + 1) * 4));
+            LG_TRY(g->poff.scratch(((uint64_t)n + 1) * 4, s));
             LG_LAUNCH(offsets_to_u32_kernel, grid1(n + 1ull), 256, 0, s, (uint64_t)n + 1, cur_off,
                       g->poff.as<uint32_t>());
             LG_CHECK_LAUNCH();
@@ -719,7 +719,7 @@ static lg_status encode_impl(uint32_t n, uint64_t m, const uint64_t *row_offsets
         if (col_new.p) {
             g->pcol = std::move(col_new);
         } else {
-            LG_TRY(g->pcol.alloc((m ? m : 1) * 4));
+            LG_TRY(g->pcol.scratch((m ? m : 1) * 4, s));
             if (m) LG_CHECK_HIP(hipMemcpyAsync(g->pcol.p, cur_col, m * 4, hipMemcpyDeviceToDevice, s));
         }
         LG_CHECK_HIP(hipStreamSynchronize(s));
@@ -746,7 +746,7 @@ static lg_status encode_impl(uint32_t n, uint64_t m, const uint64_t *row_offsets
         LG_CHECK_HIP(hipStreamSynchronize(s));
         LG_TRY(pack_fixed(SrcU8{w8.as<uint8_t>()}, n, g->F, g->W, g->W_words, s));
         g->A_words = (g->U + 63) / 64 + 1;
-        LG_TRY(g->A.alloc(g->A_words * 8));
+        LG_TRY(g->A.scratch(g->A_words * 8, s));
         LG_LAUNCH(pack_local_kernel, grid_for(g->A_words, 256, 1ull << 31), 256, 0, s, n, cur_off, cur_col,
                   w8.as<uint8_t>(), P.as<uint64_t>(), g->U, g->A_words, g->A.as<uint64_t>());
         LG_CHECK_LAUNCH();

@@ -86,15 +86,16 @@ lg_status ensure_heavy_segments(lg_graph *g, hipStream_t s) {
     while (((uint64_t)g->max_degree + g->seg_size - 1) / g->seg_size > 65535) g->seg_size *= 2;
     g->pr_split = 4096;
     g->pr_unit_edges = 8192;
-    LG_TRY(g->hstart.alloc((uint64_t)(nh ? nh : 1) * 8));
-    LG_TRY(g->hdeg.alloc((uint64_t)(nh ? nh : 1) * 4));
-    LG_TRY(g->hw.alloc((uint64_t)(nh ? nh : 1) * 4));
-    LG_TRY(g->seg_off.alloc(((uint64_t)nh + 1) * 8));
+    LG_TRY(g->hstart.scratch((uint64_t)(nh ? nh : 1) * 8, s));
+    LG_TRY(g->hdeg.scratch((uint64_t)(nh ? nh : 1) * 4, s));
+    LG_TRY(g->hw.scratch((uint64_t)(nh ? nh : 1) * 4, s));
+    LG_TRY(g->seg_off.scratch(((uint64_t)nh + 1) * 8, s));
     g->n_seg = 0;
     DevBuf tmp;
+    LG_TRY(tmp.scratch(8, s));
     if (nh) {
         DevBuf segcnt;
-        LG_TRY(segcnt.alloc((uint64_t)nh * 4));
+        LG_TRY(segcnt.scratch((uint64_t)nh * 4, s));
         LG_TRY(dispatch_acc(g, [&](auto acc) -> lg_status {
             using Acc = decltype(acc);
             LG_LAUNCH(heavy_info_kernel<Acc>, grid_for(nh, 256, 1u << 16), 256, 0, s, acc, g->heavy.as<uint32_t>(),
@@ -105,7 +106,7 @@ lg_status ensure_heavy_segments(lg_graph *g, hipStream_t s) {
         }));
         LG_TRY(exclusive_scan_u32(segcnt.as<uint32_t>(), g->seg_off.as<uint64_t>(), nh, tmp, s));
         DevBuf sums;
-        LG_TRY(sums.alloc(16));
+        LG_TRY(sums.scratch(16, s));
         LG_TRY(fill_u64(sums.as<uint64_t>(), 0, 2, s));
         LG_LAUNCH(heavy_sum_kernel, grid_for(nh, 256, 1024), 256, 0, s, nh, g->hdeg.as<uint32_t>(),
                   g->hw.as<uint32_t>(), sums.as<unsigned long long>());
@@ -120,8 +121,8 @@ lg_status ensure_heavy_segments(lg_graph *g, hipStream_t s) {
     } else {
         LG_TRY(fill_u64(g->seg_off.as<uint64_t>(), 0, 1, s));
     }
-    LG_TRY(g->seg_map.alloc((g->n_seg ? g->n_seg : 1) * 4));
-    LG_TRY(g->seg_part.alloc((g->n_seg ? g->n_seg : 1) * 4));
+    LG_TRY(g->seg_map.scratch((g->n_seg ? g->n_seg : 1) * 4, s));
+    LG_TRY(g->seg_part.scratch((g->n_seg ? g->n_seg : 1) * 4, s));
     if (g->n_seg) {
         LG_LAUNCH(heavy_seg_map_kernel, grid_for(nh, 256, 1u << 16), 256, 0, s, nh, g->seg_off.as<uint64_t>(),
                   g->seg_map.as<uint32_t>());
@@ -130,8 +131,8 @@ lg_status ensure_heavy_segments(lg_graph *g, hipStream_t s) {
     // units
     const uint64_t words = ((uint64_t)n + 63) / 64;
     DevBuf cnt, uoff;
-    LG_TRY(cnt.alloc(words * 4));
-    LG_TRY(uoff.alloc((words + 1) * 8));
+    LG_TRY(cnt.scratch(words * 4, s));
+    LG_TRY(uoff.scratch((words + 1) * 8, s));
     const uint32_t ugrid = grid_for(words * kWave, 256, 1u << 16);
     LG_TRY(dispatch_acc(g, [&](auto acc) -> lg_status {
         using Acc = decltype(acc);
@@ -141,7 +142,7 @@ lg_status ensure_heavy_segments(lg_graph *g, hipStream_t s) {
         LG_TRY(exclusive_scan_u32(cnt.as<uint32_t>(), uoff.as<uint64_t>(), words, tmp, s));
         LG_CHECK_HIP(hipMemcpyAsync(&g->n_units, uoff.as<uint64_t>() + words, 8, hipMemcpyDeviceToHost, s));
         LG_CHECK_HIP(hipStreamSynchronize(s));
-        LG_TRY(g->units.alloc((g->n_units + 1) * 4));
+        LG_TRY(g->units.scratch((g->n_units + 1) * 4, s));
         LG_LAUNCH((pr_units_kernel<Acc, true>), ugrid, 256, 0, s, acc, n, g->pr_split, g->pr_unit_edges,
                   (uint32_t *)nullptr, (const uint64_t *)uoff.as<uint64_t>(), g->units.as<uint32_t>());
         LG_CHECK_LAUNCH();

@@ -237,8 +237,8 @@ extern "C" lg_status lg_pagerank(const lg_graph *gc, float damping, uint32_t ite
         g->pr = new (std::nothrow) PrWork();
         if (!g->pr) { set_error("lg_pagerank: host allocation failed"); return LG_ERR_OOM; }
     }
-    LG_TRY(g->pr->ca.ensure((uint64_t)n * 4));
-    LG_TRY(g->pr->cb.ensure((uint64_t)n * 4));
+    if (g->pr->ca.bytes < (uint64_t)n * 4) LG_TRY(g->pr->ca.scratch((uint64_t)n * 4, stream));
+    if (g->pr->cb.bytes < (uint64_t)n * 4) LG_TRY(g->pr->cb.scratch((uint64_t)n * 4, stream));
     LG_TRY(ensure_heavy_segments(g, stream));
     const uint32_t *perm = g->relabel == LG_RELABEL_DEGREE ? g->perm.as<uint32_t>() : nullptr;
     const double a = damping;
