@@ -103,10 +103,32 @@ lg_status DevBuf::scratch(uint64_t nbytes, hipStream_t s) {
     return LG_OK;
 }
 
+// Free every cached scratch buffer of the current device (out of memory).
+static void pool_drop_device() {
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    Pool &pl = pool();
+    std::lock_guard<std::mutex> g(pl.mu);
+    for (size_t i = 0; i < pl.list.size();) {
+        if (pl.list[i].device == dev) {
+            (void)hipFree(pl.list[i].p);
+            pl.total -= pl.list[i].bytes;
+            pl.list.erase(pl.list.begin() + (long)i);
+        } else {
+            ++i;
+        }
+    }
+}
+
 lg_status DevBuf::alloc(uint64_t nbytes) {
     release();
     if (nbytes == 0) nbytes = 8;
     hipError_t e = hipMalloc(&p, nbytes);
+    if (e != hipSuccess) {  // the scratch cache may hold the memory: give it back, try once more
+        (void)hipGetLastError();
+        pool_drop_device();
+        e = hipMalloc(&p, nbytes);
+    }
     if (e != hipSuccess) {
         p = nullptr;
         (void)hipGetLastError();

@@ -255,8 +255,12 @@ __global__ void bu_step_kernel(Acc acc, uint32_t n, uint32_t threshold, const ui
     unsigned long long woke = 0;
     for (uint64_t q = wave; q < words; q += nwaves) {
         const uint64_t vis = visited[q];
+        // the offset decode's select samples do not depend on the visited
+        // word: issue their loads together with it
+        EFSamples smp{0, 0};
+        if constexpr (Acc::kPacked && Acc::kEF) smp = ef_samples(acc.pv.ef, q * 64, n + 1);
         if (vis == ~0ull) continue;
-        const VInfo vi = wave_info(acc, q * 64, n);
+        const VInfo vi = wave_info(acc, q * 64, n, &smp);
         const uint64_t v = q * 64 + lane;
         bool found = false, pending = false;
         uint32_t par = 0;

@@ -197,6 +197,21 @@ struct PackedAcc {
         }
         return r;
     }
+    // make() with the width already loaded (ignored in global mode)
+    __device__ __forceinline__ VInfo make_w(uint32_t v, uint64_t o0, uint64_t o1, uint32_t w) const {
+        VInfo r;
+        if constexpr (IDM == kIdsGlobal) {
+            (void)w;
+            r.start = o0 * pv.s;
+            r.deg = (uint32_t)(o1 - o0);
+            r.w = pv.s;
+        } else {
+            r.w = w;
+            r.start = o0;
+            r.deg = r.w ? exact_div_width(o1 - o0, r.w) : 0u;
+        }
+        return r;
+    }
     __device__ __forceinline__ VInfo info(uint32_t v) const {
         if constexpr (OFM == kOffsPacked) {
             return make(v, offset_value(v), offset_value(v + 1));
@@ -249,14 +264,24 @@ struct PlainAcc {
 // they span at most 64 words, lane i loads word i, a wave prefix of the
 // popcounts tells every lane which word holds its one, and an in-word select
 // finishes; otherwise each lane runs a full select.
-__device__ __forceinline__ void ef_wave_select(const EFView &e, uint64_t v0, uint32_t count, uint64_t &pos,
-                                               uint64_t &pos_end) {
-    const uint32_t lane = lane_id();
+// The two samples sel[v0/64] and sel[v0/64 + 1] (0 when v0 + 64 >= count),
+// loaded ahead by callers that can issue them early.
+struct EFSamples {
+    uint64_t p0, p1;
+};
+
+__device__ __forceinline__ EFSamples ef_samples(const EFView &e, uint64_t v0, uint32_t count) {
     const uint32_t q = (uint32_t)(v0 >> 6);
-    const uint64_t p0 = e.sel[q];
+    return EFSamples{e.sel[q], v0 + kWave < count ? e.sel[q + 1] : 0ull};
+}
+
+__device__ __forceinline__ void ef_wave_select(const EFView &e, uint64_t v0, uint32_t count, EFSamples smp,
+                                               uint64_t &pos, uint64_t &pos_end) {
+    const uint32_t lane = lane_id();
+    const uint64_t p0 = smp.p0;
     // one number v0 + 64 exists iff v0 + 64 < count
     const bool have_end = v0 + kWave < count;
-    const uint64_t p1 = have_end ? e.sel[q + 1] : 0;
+    const uint64_t p1 = smp.p1;
     const uint64_t w0 = p0 >> 6;
     const uint64_t w1 = have_end ? (p1 >> 6) : w0 + kWave;  // unknown end: let the fallback decide
     if (have_end && w1 - w0 < (uint64_t)kWave) {
@@ -290,35 +315,45 @@ __device__ __forceinline__ void ef_wave_select(const EFView &e, uint64_t v0, uin
 // VInfo of vertex v0 + lane for the 64 lanes of a wave (v0 a multiple of
 // 64): every lane decodes one offset value and takes the next one from its
 // neighbor lane, so a sweep over consecutive vertices decodes each offset
-// once.  Lanes past n get an empty list.
+// once.  Lanes past n get an empty list.  With Elias-Fano offsets the low
+// bits and widths do not depend on the select, so they are loaded first and
+// overlap it; `smp` carries select samples a caller loaded ahead.
 template <class Acc>
-__device__ __forceinline__ VInfo wave_info(const Acc &acc, uint64_t v0, uint32_t n) {
+__device__ __forceinline__ VInfo wave_info(const Acc &acc, uint64_t v0, uint32_t n, const EFSamples *smp = nullptr) {
     const uint32_t lane = lane_id();
     const uint64_t v = v0 + lane;
     if (v0 >= n) return VInfo{0, 0, 0};  // wave-uniform: a block past the last vertex
     uint64_t o0, end;
     if constexpr (Acc::kPacked && Acc::kEF) {
         const EFView &e = acc.pv.ef;
-        uint64_t pos, pos_end;
-        ef_wave_select(e, v0, n + 1, pos, pos_end);
         const uint64_t vv = v < n ? v : n;
         const uint64_t ve = v0 + kWave < n ? v0 + kWave : n;
+        const uint64_t lo0 = e.l ? extract64(e.L, vv * e.l, e.l) : 0ull;
+        const uint64_t lo_end = (e.l && v0 + kWave <= n) ? extract64(e.L, ve * e.l, e.l) : 0ull;
+        const uint32_t wv = v < n ? acc.width((uint32_t)v) : 0u;
+        uint64_t pos, pos_end;
+        ef_wave_select(e, v0, n + 1, smp ? *smp : ef_samples(e, v0, n + 1), pos, pos_end);
         if (v > n) pos = 0;
-        o0 = v <= n ? (((pos - vv) << e.l) | (e.l ? extract64(e.L, vv * e.l, e.l) : 0ull)) : 0ull;
+        o0 = v <= n ? (((pos - vv) << e.l) | lo0) : 0ull;
         // the end value: one number ve; when ve = n it is one number n itself
         if (v0 + kWave <= n) {
-            end = ((pos_end - ve) << e.l) | (e.l ? extract64(e.L, ve * e.l, e.l) : 0ull);
+            end = ((pos_end - ve) << e.l) | lo_end;
         } else {
             end = __shfl(o0, (uint32_t)(n - v0), kWave);
         }
+        uint64_t o1 = __shfl_down(o0, 1, kWave);
+        if (lane == kWave - 1) o1 = end;
+        if (v >= n) return VInfo{0, 0, 0};
+        return acc.make_w((uint32_t)v, o0, o1, wv);
     } else {
+        (void)smp;
         o0 = acc.offset_value((uint32_t)(v < n ? v : n));
         end = acc.offset_value((uint32_t)(v0 + kWave < n ? v0 + kWave : n));
+        uint64_t o1 = __shfl_down(o0, 1, kWave);
+        if (lane == kWave - 1) o1 = end;
+        if (v >= n) return VInfo{0, 0, 0};
+        return acc.make((uint32_t)v, o0, o1);
     }
-    uint64_t o1 = __shfl_down(o0, 1, kWave);
-    if (lane == kWave - 1) o1 = end;
-    if (v >= n) return VInfo{0, 0, 0};
-    return acc.make((uint32_t)v, o0, o1);
 }
 
 // Sum of one value per thread over a block of up to 1024 threads (result

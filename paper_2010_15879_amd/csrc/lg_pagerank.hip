@@ -141,8 +141,10 @@ __global__ __launch_bounds__(kPrThreads) void pr_iter_kernel(
         const bool mine = v >= vb && v < ve;
         // a block of vertices without edges: contrib stays 0, only scores change
         const bool all_iso = iso[w0 / kWave] == ~0ull;
+        EFSamples smp{0, 0};
+        if constexpr (Acc::kPacked && Acc::kEF) smp = ef_samples(acc.pv.ef, w0, n + 1);
         if (all_iso && !scores) continue;
-        const VInfo vi = all_iso ? VInfo{0, 0, 0} : wave_info(acc, w0, n);
+        const VInfo vi = all_iso ? VInfo{0, 0, 0} : wave_info(acc, w0, n, &smp);
         const bool segmented = vi.deg > split;
         const uint32_t d = (mine && !segmented) ? vi.deg : 0u;
         const uint32_t incl = wave_incl_scan(d);
