@@ -226,6 +226,49 @@ __global__ __launch_bounds__(kTdThreads) void td_expand_kernel(
     }
 }
 
+// A small top-down level in one launch: a wave per frontier vertex decodes
+// its list and claims neighbors by the same rule as td_expand_kernel (skip
+// vertices visited before this level, CAS the depth, smallest parent label
+// among the claimants of the level).  Used for the small frontiers at the end
+// of a search, where the prepare / scan / expand launches and their host
+// round trips would cost more than the work.
+template <class Acc, bool kParent>
+__global__ void td_small_kernel(Acc acc, const uint32_t *__restrict__ queue, uint32_t qsize,
+                                const uint64_t *__restrict__ visited, int32_t *__restrict__ depth,
+                                uint32_t *__restrict__ parent, int32_t next_depth, uint32_t *__restrict__ queue_out,
+                                unsigned long long *__restrict__ tail) {
+    const uint32_t lane = lane_id();
+    const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) / kWave;
+    for (uint64_t i = wave; i < qsize; i += nwaves) {
+        const uint32_t v = queue[i];
+        const VInfo vi = acc.info(v);
+        const uint32_t st = Acc::step(vi.w), mk = Acc::mask(vi.w);
+        for (uint64_t e0 = 0; e0 < vi.deg; e0 += kWave) {
+            const uint64_t e = e0 + lane;
+            bool won = false;
+            uint32_t u = 0;
+            if (e < vi.deg) {
+                u = acc.get(vi.start + e * st, mk);
+                if (!((visited[u >> 6] >> (u & 63)) & 1ull)) {
+                    const int32_t old = atomicCAS(&depth[u], -1, next_depth);
+                    if (kParent && (old == -1 || old == next_depth)) atomicMin(&parent[u], v);
+                    won = old == -1;
+                }
+            }
+            const uint64_t m = __ballot(won);
+            if (m) {
+                unsigned long long base = 0;
+                if (lane == 0) base = atomicAdd(tail, (unsigned long long)__popcll(m));
+                base = __shfl(base, 0, kWave) + popc_below(m);
+                if (won) queue_out[base] = u;
+            }
+        }
+    }
+}
+
+constexpr uint32_t kSmallFrontier = 16384;  // frontier size up to which late levels take td_small_kernel
+
 __global__ void mark_queue_kernel(const uint32_t *__restrict__ queue, const unsigned long long *__restrict__ qsize_dev,
                                   unsigned long long *__restrict__ bits) {
     const uint64_t q = *qsize_dev;
@@ -451,8 +494,31 @@ static lg_status bfs_one(lg_graph *g, BfsWork &w, Acc acc, uint32_t root_id, con
     uint64_t awake = 0;
     int32_t level = 0;
     bool topdown = true;
+    bool bu_done = false;  // a bottom-up phase is over: the frontier only shrinks from here
     for (;;) {
         if (max_depth >= 0 && level >= max_depth) break;
+        if (topdown && qsize && bu_done && qsize <= kSmallFrontier) {
+            LG_TRY(fill_u64((uint64_t *)ctr, 0, 1, s));
+            const uint32_t grid = grid_for(qsize * kWave, 256, kStrideBlocks);
+            if (parent)
+                LG_LAUNCH((td_small_kernel<Acc, true>), grid, 256, 0, s, acc, qin, (uint32_t)qsize, visited, depth,
+                          parent, level + 1, qout, ctr);
+            else
+                LG_LAUNCH((td_small_kernel<Acc, false>), grid, 256, 0, s, acc, qin, (uint32_t)qsize, visited, depth,
+                          parent, level + 1, qout, ctr);
+            LG_CHECK_LAUNCH();
+            LG_CHECK_HIP(hipMemcpyAsync(w.host, ctr, 8, hipMemcpyDeviceToHost, s));
+            LG_CHECK_HIP(hipStreamSynchronize(s));
+            qsize = w.host[0];
+            if (qsize) {
+                LG_LAUNCH(mark_queue_kernel, grid_for(qsize, 256, 1u << 16), 256, 0, s, qout, ctr,
+                          (unsigned long long *)visited);
+                LG_CHECK_LAUNCH();
+            }
+            std::swap(qin, qout);
+            ++level;
+            continue;
+        }
         if (topdown) {
             if (qsize == 0) break;
             LG_LAUNCH(td_prepare_kernel<Acc>, grid_for(qsize, 256, 1u << 16), 256, 0, s, acc, qin, (uint32_t)qsize,
@@ -540,6 +606,7 @@ static lg_status bfs_one(lg_graph *g, BfsWork &w, Acc acc, uint32_t root_id, con
             const bool back = flags == LG_BFS_DIRECTION_OPT && now < awake && (double)now <= (double)n / prm.beta;
             awake = now;
             if (back) {
+                bu_done = true;
                 LG_TRY(fill_u64((uint64_t *)ctr, 0, 1, s));
                 LG_LAUNCH(bitmap_to_queue_kernel, grid_for(words, 256, 1u << 16), 256, 0, s, words, curr, qin, ctr);
                 LG_CHECK_LAUNCH();
