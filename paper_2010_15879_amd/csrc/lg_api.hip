@@ -153,6 +153,7 @@ namespace {
 struct ProfState {
     std::mutex mu;
     bool on = false;
+    char filter[128] = "";  // time only launches whose kernel name contains this (empty: all)
     std::vector<ProfMark> pending;
     std::vector<hipEvent_t> pool;
     std::map<std::string, std::pair<uint64_t, double>> done;
@@ -194,6 +195,7 @@ bool prof_on() { return prof().on; }
 
 ProfMark prof_begin(const char *name, hipStream_t stream) {
     ProfState &st = prof();
+    if (st.filter[0] && !std::strstr(name, st.filter)) return ProfMark{};
     std::lock_guard<std::mutex> g(st.mu);
     ProfMark m;
     if (st.pending.size() > 4096) drain(st, false);
@@ -383,6 +385,15 @@ extern "C" lg_status lg_prof_enable(int on) {
     auto &st = lg::prof();
     std::lock_guard<std::mutex> g(st.mu);
     st.on = on != 0;
+    return LG_OK;
+}
+
+extern "C" lg_status lg_prof_filter(const char *substr) {
+    auto &st = lg::prof();
+    std::lock_guard<std::mutex> g(st.mu);
+    if (!substr) substr = "";
+    if (std::strlen(substr) >= sizeof(st.filter)) { lg::set_error("lg_prof_filter: name too long"); return LG_ERR_INVALID; }
+    std::strcpy(st.filter, substr);
     return LG_OK;
 }
 

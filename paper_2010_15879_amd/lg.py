@@ -107,6 +107,7 @@ FUNCTIONS = {
     "lg_last_error": (C.c_char_p, []),
     "lg_trim": (None, []),
     "lg_prof_enable": (C.c_int, [C.c_int]),
+    "lg_prof_filter": (C.c_int, [C.c_char_p]),
     "lg_prof_reset": (C.c_int, []),
     "lg_prof_query": (C.c_int, [C.c_char_p, C.POINTER(C.c_uint64), C.POINTER(C.c_double)]),
     "lg_prof_names": (C.c_int, [C.c_char_p, C.c_uint64]),
@@ -276,6 +277,10 @@ def pagerank(g: Graph, damping: float = 0.85, iters: int = 20, out=None, stream=
 
 def prof_enable(on: bool = True):
     _check(lib().lg_prof_enable(1 if on else 0))
+
+
+def prof_filter(substr: str = ""):
+    _check(lib().lg_prof_filter(substr.encode()))
 
 
 def prof_reset():
