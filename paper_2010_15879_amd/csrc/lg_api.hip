@@ -236,6 +236,7 @@ lg::PackedView lg_graph::packed_view() const {
     v.ef.l = ef_l;
     v.ef.n_sel = (uint32_t)n_sel;
     v.ef.n_sb = n_rank ? (uint32_t)(n_rank - 1) : 0;
+    v.ef.n_hw = (uint32_t)H_words;
     return v;
 }
 

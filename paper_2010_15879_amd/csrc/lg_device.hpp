@@ -106,7 +106,9 @@ __device__ __forceinline__ uint32_t select_in_word(uint64_t x, uint32_t r) {
 
 // select1(k): the sample table gives the position of one number 64*floor(k/64);
 // the rank directory is searched between that superblock and the next
-// sample's, then at most eight words are scanned with popcount.
+// sample's, then at most eight words are scanned with popcount.  The
+// directory matters where H is sparse (between the offsets of long lists
+// lie thousands of zero words).
 __device__ __forceinline__ uint64_t ef_select1(const EFView &e, uint32_t k) {
     const uint32_t j = k >> 6;
     const uint32_t p = e.sel[j];
@@ -126,6 +128,31 @@ __device__ __forceinline__ uint64_t ef_select1(const EFView &e, uint32_t k) {
         r += c;
         ++wi;
     }
+}
+
+// The same select for random vertices (top-down frontiers, tables): one
+// number k is the (k mod 64)-th one after the sample's position p; the four
+// words from p are loaded at once and searched in registers, which settles
+// dense stretches of H in one round trip after the sample; a longer gap goes
+// through the rank directory.
+__device__ __forceinline__ uint64_t ef_select1_wide(const EFView &e, uint32_t k) {
+    const uint64_t p = e.sel[k >> 6];
+    uint32_t need = k & 63u;
+    if (need == 0) return p;
+    --need;  // index among the ones after p
+    const uint64_t w0 = p >> 6;
+    const uint32_t sh = (uint32_t)(p & 63u);
+    uint64_t x[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) x[t] = w0 + t < e.n_hw ? e.H[w0 + t] : 0ull;
+    x[0] = sh == 63 ? 0ull : (x[0] & (~0ull << (sh + 1)));
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const uint32_t c = (uint32_t)__popcll(x[t]);
+        if (need < c) return (w0 + t) * 64 + select_in_word(x[t], need);
+        need -= c;
+    }
+    return ef_select1(e, k);
 }
 
 // position of the first set bit of H after position p (one must exist)
@@ -218,7 +245,7 @@ struct PackedAcc {
         } else {
             // x_{v+1}'s upper bit is the next one of H after x_v's
             const EFView &e = pv.ef;
-            const uint64_t p0 = ef_select1(e, v);
+            const uint64_t p0 = ef_select1_wide(e, v);
             const uint64_t p1 = ef_next_one(e, p0);
             const uint64_t lo0 = e.l ? extract64(e.L, (uint64_t)v * e.l, e.l) : 0ull;
             const uint64_t lo1 = e.l ? extract64(e.L, (uint64_t)(v + 1) * e.l, e.l) : 0ull;

@@ -15,6 +15,7 @@ struct EFView {
     uint32_t l;
     uint32_t n_sel;           // entries of sel
     uint32_t n_sb;            // superblocks = entries of rank_sb - 1
+    uint32_t n_hw;            // words of H
 };
 
 // Packed offsets: value v at bits [v*w, v*w + w).
