@@ -465,21 +465,14 @@ __global__ void bfs_unpermute_kernel(uint32_t n, const uint32_t *__restrict__ in
 // host driver
 // ---------------------------------------------------------------------------
 
-struct BfsParams {
-    // top-down -> bottom-up when frontier edges > unexplored / alpha.  Chosen
-    // by timing 64-root searches on Kronecker scale 24 (alpha 5 .. 1000): 60 is
-    // 16 % faster than the customary 15 (bottom-up sweeps here are cheap
-    // relative to top-down expansion), anything in 60 .. 250 about equal
-    double alpha = 60.0;
-    double beta = 18.0;   // bottom-up -> top-down when the frontier shrinks below n / beta
-};
+// bottom-up -> top-down when the frontier shrinks below n / kBfsBeta
+constexpr double kBfsBeta = 18.0;
 
 template <class Acc>
 static lg_status bfs_one(lg_graph *g, BfsWork &w, Acc acc, uint32_t root_id, const uint32_t *inv, int32_t *depth,
-                         uint32_t *parent, int32_t max_depth, uint32_t flags, hipStream_t s) {
+                         uint32_t *parent, int32_t max_depth, uint32_t flags, double alpha, hipStream_t s) {
     const uint32_t n = g->n;
     const uint64_t words = ((uint64_t)n + 63) / 64;
-    const BfsParams prm;
     uint32_t *qin = w.qa.as<uint32_t>(), *qout = w.qb.as<uint32_t>();
     uint64_t *visited = w.visited.as<uint64_t>(), *curr = w.curr.as<uint64_t>(), *next = w.next.as<uint64_t>();
     unsigned long long *ctr = w.counters.as<unsigned long long>();
@@ -529,7 +522,7 @@ static lg_status bfs_one(lg_graph *g, BfsWork &w, Acc acc, uint32_t root_id, con
             LG_CHECK_HIP(hipStreamSynchronize(s));
             const uint64_t fedges = w.host[0];
             const bool go_bu = (flags == LG_BFS_BOTTOM_UP && level >= 1) ||
-                               (flags == LG_BFS_DIRECTION_OPT && (double)fedges > (double)edges_to_check / prm.alpha);
+                               (flags == LG_BFS_DIRECTION_OPT && (double)fedges > (double)edges_to_check / alpha);
             if (go_bu) {
                 LG_TRY(fill_u64(curr, 0, words, s));
                 LG_TRY(fill_u64((uint64_t *)ctr, qsize, 1, s));
@@ -603,7 +596,7 @@ static lg_status bfs_one(lg_graph *g, BfsWork &w, Acc acc, uint32_t root_id, con
             std::swap(curr, next);
             ++level;
             if (now == 0) break;
-            const bool back = flags == LG_BFS_DIRECTION_OPT && now < awake && (double)now <= (double)n / prm.beta;
+            const bool back = flags == LG_BFS_DIRECTION_OPT && now < awake && (double)now <= (double)n / kBfsBeta;
             awake = now;
             if (back) {
                 bu_done = true;
@@ -619,7 +612,7 @@ static lg_status bfs_one(lg_graph *g, BfsWork &w, Acc acc, uint32_t root_id, con
 }
 
 lg_status bfs_run(lg_graph *g, BfsWork &w, const uint32_t *roots, uint32_t r, int32_t *depth, int32_t *parent,
-                  int32_t max_depth, uint32_t flags, hipStream_t stream) {
+                  int32_t max_depth, uint32_t flags, hipStream_t stream, double alpha) {
     if (r == 0) return LG_OK;
     LG_TRY(bfs_workspace_ensure(w, g->n, g->n_heavy, g->relabel == LG_RELABEL_DEGREE, parent != nullptr));
     const bool rel = g->relabel == LG_RELABEL_DEGREE;
@@ -630,14 +623,14 @@ lg_status bfs_run(lg_graph *g, BfsWork &w, const uint32_t *roots, uint32_t r, in
             int32_t *p_out = parent ? parent + (uint64_t)i * g->n : nullptr;
             if (rel) {
                 LG_TRY(bfs_one(g, w, acc, roots[i], inv, w.depth_i.as<int32_t>(),
-                               p_out ? w.parent_i.as<uint32_t>() : nullptr, max_depth, flags, stream));
+                               p_out ? w.parent_i.as<uint32_t>() : nullptr, max_depth, flags, alpha, stream));
                 LG_LAUNCH(bfs_unpermute_kernel, grid_for(g->n, 256, 1u << 16), 256, 0, stream, g->n,
                           g->inv.as<uint32_t>(), g->perm.as<uint32_t>(), w.depth_i.as<int32_t>(),
                           p_out ? w.parent_i.as<uint32_t>() : nullptr, d_out, p_out);
                 LG_CHECK_LAUNCH();
             } else {
                 LG_TRY(bfs_one(g, w, acc, roots[i], inv, d_out, reinterpret_cast<uint32_t *>(p_out), max_depth, flags,
-                               stream));
+                               alpha, stream));
             }
         }
         return LG_OK;

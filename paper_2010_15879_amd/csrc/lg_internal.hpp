@@ -261,9 +261,24 @@ lg_status ensure_heavy_segments(lg_graph *g, hipStream_t s);
 lg_status bfs_free(lg_graph *g);
 void bfs_pools_trim();
 lg_status bfs_workspace_ensure(BfsWork &w, uint64_t n, uint64_t n_heavy, bool relabel, bool need_parent);
+// Direction switch of the direction-optimizing BFS: top-down -> bottom-up
+// when the frontier's edges exceed the unexplored edges / alpha.
+//   kBfsAlphaLatency  searches that have the device to themselves (lg_bfs).
+//                     Timing 64-root searches on Kronecker scale 24 over
+//                     alpha 5 .. 1000: 60 is 16 % faster than the customary
+//                     15, anything in 60 .. 250 about equal.
+//   kBfsAlphaShared   searches that share the device with unrelated queries
+//                     (the query server).  Switching early shortens one
+//                     search by sweeping every vertex a level sooner; the
+//                     extra sweeps are device time the other queries wait
+//                     for, and on the mixed serving input 15 serves 30 % more
+//                     queries per second than 60 at a third of the p99.
+constexpr double kBfsAlphaLatency = 60.0;
+constexpr double kBfsAlphaShared = 15.0;
+
 // BFS from host roots on an explicit workspace (lg_bfs without argument checks)
 lg_status bfs_run(lg_graph *g, BfsWork &w, const uint32_t *roots, uint32_t r, int32_t *depth, int32_t *parent,
-                  int32_t max_depth, uint32_t flags, hipStream_t stream);
+                  int32_t max_depth, uint32_t flags, hipStream_t stream, double alpha = kBfsAlphaLatency);
 // lg_decode_neighbors on an explicit workspace
 lg_status decode_run(lg_graph *g, DecodeWork &w, const uint32_t *vertices, uint32_t k, uint64_t *out_off,
                      uint32_t *out_ids, uint64_t cap, uint32_t flags, hipStream_t stream, uint64_t *total);

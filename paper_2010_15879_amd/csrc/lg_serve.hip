@@ -307,7 +307,7 @@ lg_status lg_server::serve_bfs(Worker &W, lg_graph *g, const Query &q, Result &r
     if (!khop) LG_TRY(W.parent.ensure(n * 4));
     const uint32_t root = q.q.vertex;
     LG_TRY(bfs_run(g, W.bfs, &root, 1, W.depth.as<int32_t>(), khop ? nullptr : W.parent.as<int32_t>(),
-                   khop ? q.q.k : -1, LG_BFS_DIRECTION_OPT, W.stream));
+                   khop ? q.q.k : -1, LG_BFS_DIRECTION_OPT, W.stream, kBfsAlphaShared));
     res.r.n = n;
     if (khop) {
         const uint64_t words = (n + 63) / 64;
