@@ -252,6 +252,56 @@ def test_invalid_inputs_rejected(lgmod):
     h.free()
 
 
+def _rewired(g):
+    """g with two entries retargeted so that every in-degree equals the
+    out-degree but the graph is not symmetric: a->b, c->d become a->d, c->b
+    (b->a and d->c stay)."""
+    off, col = g.numpy()
+    off = off.astype(np.int64)
+    rows = [list(col[off[v]:off[v + 1]]) for v in range(g.n)]
+    rng = np.random.default_rng(11)
+    while True:
+        a, c = (int(x) for x in rng.integers(g.n, size=2))
+        if a == c or not rows[a] or not rows[c]:
+            continue
+        b, d = int(rows[a][rng.integers(len(rows[a]))]), int(rows[c][rng.integers(len(rows[c]))])
+        if len({a, b, c, d}) < 4 or d in rows[a] or b in rows[c]:
+            continue
+        break
+    rows[a] = sorted(set(rows[a]) - {b} | {d})
+    rows[c] = sorted(set(rows[c]) - {d} | {b})
+    noff = np.zeros(g.n + 1, np.int64)
+    noff[1:] = np.cumsum([len(r) for r in rows])
+    return noff, np.concatenate([np.array(r, np.int32) for r in rows])
+
+
+@pytest.mark.parametrize("layout", ["packed", "plain"])
+def test_invalid_inputs_rejected_relabel(lgmod, layout):
+    """Invalid graphs are rejected with the degree relabeling too, including
+    graphs whose in-degrees equal their out-degrees but that are not
+    symmetric (a directed 3-cycle, two retargeted entries)."""
+    from paper_2010_15879_amd.lg import LGError, LG_ERR_INVALID
+    cases = {
+        "unsorted": (np.array([0, 2, 3, 4], np.int64), np.array([2, 1, 0, 0], np.int32)),
+        "asymmetric": (np.array([0, 1, 1, 1], np.int64), np.array([1], np.int32)),
+        "cycle3": (np.array([0, 1, 2, 3], np.int64), np.array([1, 2, 0], np.int32)),
+        "self_loop": (np.array([0, 1, 1], np.int64), np.array([0], np.int32)),
+        "rewired_kron10": _rewired(gg.kronecker(10, 8, seed=4)),
+        "rewired_er9": _rewired(gg.erdos_renyi(9, 6, seed=2)),
+    }
+    for name, (off, col) in cases.items():
+        print(f"[invalid relabel {layout}] {name}", flush=True)
+        with pytest.raises(LGError) as ei:
+            lgmod.encode(torch.from_numpy(off).cuda(), torch.from_numpy(col).cuda(), off.size - 1,
+                         layout=layout, relabel=True)
+        assert ei.value.status == LG_ERR_INVALID, name
+        assert "not-symmetric" in str(ei.value) or name in ("unsorted", "self_loop"), name
+    # the same graphs before rewiring are accepted
+    for g in [gg.kronecker(10, 8, seed=4), gg.erdos_renyi(9, 6, seed=2)]:
+        h = encode(lgmod, g, dict(layout=layout, relabel=True) if layout == "plain" else ENCODINGS[3])
+        h.free()
+
+
 def test_decode_capacity_error(lgmod):
     from paper_2010_15879_amd.lg import LGError, LG_ERR_CAPACITY
     g = GRAPHS["star33"]
