@@ -82,13 +82,16 @@ __device__ __forceinline__ void wave_lds_sync() {
 }
 
 // Work item k of a walk over the rows of `off`: s_rs gets the block's 65 row
-// starts; f(e, j, valid) is called by every lane for entries e = base + lane
-// in steps of 64 (valid = e lies in the piece), j = the row of e within the
-// block.  Every lane makes the same calls (shuffles inside f are safe).
-template <class F>
+// starts.  Entries e = base + lane are taken in steps of 64, with j the row
+// of e within the block and valid = e lies in the piece.  Four steps at a
+// time, every lane calls x = load(e, j, valid) for each step, then
+// use(e, j, valid, x) for each step.  load reads in bounds whatever valid is
+// and does not branch on it, so the four steps' loads are in flight
+// together; every lane makes the same calls (shuffles inside use are safe).
+template <class Load, class Use>
 __device__ __forceinline__ void walk_item(uint32_t n, const uint64_t *__restrict__ off,
                                           const uint32_t *__restrict__ map, const uint64_t *__restrict__ coff,
-                                          uint64_t k, uint64_t *s_rs, F &&f) {
+                                          uint64_t k, uint64_t *s_rs, Load &&load, Use &&use) {
     const uint32_t lane = lane_id();
     const uint64_t q = map[k];
     const uint64_t v0 = q * 64;
@@ -105,12 +108,24 @@ __device__ __forceinline__ void walk_item(uint32_t n, const uint64_t *__restrict
 #pragma unroll
         for (uint32_t step = 32; step > 0; step >>= 1)
             if (s_rs[j + step] <= eb) j += step;
-        for (uint64_t base = eb; base < ee; base += kWave) {
-            const uint64_t e = base + lane;
-            const bool valid = e < ee;
-            if (valid)
-                while (s_rs[j + 1] <= e) ++j;
-            f(e, j, valid);
+        constexpr int kSteps = 4;
+        for (uint64_t base = eb; base < ee; base += kSteps * kWave) {
+            uint64_t e[kSteps];
+            uint32_t row[kSteps];
+            bool valid[kSteps];
+#pragma unroll
+            for (int r = 0; r < kSteps; ++r) {  // rows from LDS only
+                e[r] = base + (uint64_t)r * kWave + lane;
+                valid[r] = e[r] < ee;
+                if (valid[r])
+                    while (s_rs[j + 1] <= e[r]) ++j;
+                row[r] = j;
+            }
+            decltype(load(e[0], row[0], valid[0])) x[kSteps];
+#pragma unroll
+            for (int r = 0; r < kSteps; ++r) x[r] = load(e[r], row[r], valid[r]);
+#pragma unroll
+            for (int r = 0; r < kSteps; ++r) use(e[r], row[r], valid[r], x[r]);
         }
     }
     wave_lds_sync();
@@ -127,11 +142,18 @@ __global__ void validate_edges_kernel(uint32_t n, const uint64_t *__restrict__ o
     uint32_t flags = 0;
     for (uint64_t k = wave; k < items; k += nwaves) {
         const uint64_t v0 = (uint64_t)map[k] * 64;
-        walk_item(n, off, map, coff, k, s_rs[wv], [&](uint64_t e, uint32_t j, bool valid) {
-            const uint32_t u = valid ? col[e] : 0u;
+        // the entry and, for lane 0, the one before it (other lanes get theirs
+        // from the lane below)
+        auto load = [&](uint64_t e, uint32_t, bool valid) {
+            const uint64_t i = valid ? e : 0;
+            const uint64_t ip = lane_id() == 0 && valid && e > 0 ? e - 1 : i;
+            return make_uint2(col[i], col[ip]);
+        };
+        walk_item(n, off, map, coff, k, s_rs[wv], load, [&](uint64_t e, uint32_t j, bool valid, uint2 x) {
+            const uint32_t u = x.x;
             uint32_t prev = __shfl_up(u, 1, kWave);
             if (!valid) return;
-            if (lane_id() == 0 && e > 0) prev = col[e - 1];
+            if (lane_id() == 0) prev = x.y;
             if (u >= n) flags |= kBadId;
             if (u == v0 + j) flags |= kSelfLoop;
             if (e > s_rs[wv][j] && prev >= u) flags |= kUnsorted;
@@ -155,11 +177,13 @@ __global__ void sym_emit_kernel(uint32_t n, const uint64_t *__restrict__ off, co
     const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) / kWave;
     for (uint64_t k = wave; k < items; k += nwaves) {
         const uint32_t v0 = map[k] * 64u;
-        walk_item(n, off, map, coff, k, s_rs[wv], [&](uint64_t e, uint32_t j, bool valid) {
-            if (!valid) return;
-            key[e] = col[e];
-            val[e] = v0 + j;
-        });
+        walk_item(
+            n, off, map, coff, k, s_rs[wv], [&](uint64_t e, uint32_t, bool valid) { return col[valid ? e : 0]; },
+            [&](uint64_t e, uint32_t j, bool valid, uint32_t u) {
+                if (!valid) return;
+                key[e] = u;
+                val[e] = v0 + j;
+            });
     }
 }
 
@@ -174,9 +198,13 @@ __global__ void sym_check_kernel(uint32_t n, const uint64_t *__restrict__ off, c
     bool bad = false;
     for (uint64_t k = wave; k < items; k += nwaves) {
         const uint32_t v0 = map[k] * 64u;
-        walk_item(n, off, map, coff, k, s_rs[wv], [&](uint64_t e, uint32_t j, bool valid) {
+        auto load = [&](uint64_t e, uint32_t, bool valid) {
+            const uint64_t i = valid ? e : 0;
+            return make_uint3(key[i], val[i], col[i]);
+        };
+        walk_item(n, off, map, coff, k, s_rs[wv], load, [&](uint64_t, uint32_t j, bool valid, uint3 x) {
             if (!valid) return;
-            bad |= key[e] != v0 + j || val[e] != col[e];
+            bad |= x.x != v0 + j || x.y != x.z;
         });
     }
     if (__ballot(bad) && lane_id() == 0) atomicOr(status, kAsymmetric);
@@ -255,9 +283,12 @@ __global__ void dm_emit_kernel(uint32_t n, const uint32_t *__restrict__ perm, co
         // new rows x = 64q + lane take the list of perm[x]: its first entry in col
         const uint32_t x0 = map[k] * 64u;
         s_src[wv][lane] = x0 + lane < n ? off[perm[x0 + lane]] : 0ull;
-        walk_item(n, off_new, map, coff, k, s_rs[wv], [&](uint64_t e, uint32_t j, bool valid) {
+        auto load = [&](uint64_t e, uint32_t j, bool valid) {
+            return col[valid ? s_src[wv][j] + (e - s_rs[wv][j]) : 0];
+        };
+        walk_item(n, off_new, map, coff, k, s_rs[wv], load, [&](uint64_t e, uint32_t j, bool valid, uint32_t w) {
             if (!valid) return;
-            key[e] = col[s_src[wv][j] + (e - s_rs[wv][j])];
+            key[e] = w;
             val[e] = x0 + j;
         });
     }
@@ -278,9 +309,11 @@ __global__ void dm_place_kernel(uint32_t n, const uint32_t *__restrict__ perm, c
     for (uint64_t k = wave; k < items; k += nwaves) {
         const uint32_t y0 = map[k] * 64u;
         s_src[wv][lane] = y0 + lane < n ? off[perm[y0 + lane]] : 0ull;
-        walk_item(n, off_new, map, coff, k, s_rs[wv], [&](uint64_t e, uint32_t j, bool valid) {
-            if (!valid) return;
-            col_new[e] = grouped[s_src[wv][j] + (e - s_rs[wv][j])];
+        auto load = [&](uint64_t e, uint32_t j, bool valid) {
+            return grouped[valid ? s_src[wv][j] + (e - s_rs[wv][j]) : 0];
+        };
+        walk_item(n, off_new, map, coff, k, s_rs[wv], load, [&](uint64_t e, uint32_t, bool valid, uint32_t x) {
+            if (valid) col_new[e] = x;
         });
     }
 }
@@ -355,55 +388,103 @@ __global__ void pack_fixed_kernel(Src src, uint64_t count, uint32_t w, double in
     }
 }
 
-// Local widths: the list of v starts at bit P_v.  A block of 256 threads
-// packs 256 consecutive words; the vertex owning each word's first bit is
-// found by a binary search of P bounded by the block's own vertex range.
-__device__ __forceinline__ uint32_t vertex_of_bit(const uint64_t *__restrict__ P, uint32_t lo, uint32_t hi,
-                                                  uint64_t b) {
-    // largest v in [lo, hi] with P[v] <= b
-    while (lo < hi) {
-        const uint32_t mid = lo + ((hi - lo + 1) >> 1);
-        if (P[mid] <= b) lo = mid; else hi = mid - 1;
-    }
-    return lo;
-}
+// Local widths: entry i of list v occupies stream bits [P_v + i w_v, + w_v).
+// Walked like the validation passes: a wave takes a piece of consecutive
+// entries, 64 per step (four steps' loads issued together).  The lanes of a
+// step cover adjacent bit ranges; their parts are ORed into words in the
+// wave's LDS, every word completed inside the piece is stored once, and the
+// word a step leaves open is carried into the next step.  The first word of
+// a piece and the word left open at its end may hold bits of the
+// neighbouring pieces: those two are ORed into the (zeroed) stream
+// atomically.
+constexpr int kPackBuf = 34;  // words one step can touch: 64 x 32 bits, misaligned, plus the carry
 
-__global__ void pack_local_kernel(uint32_t n, const uint64_t *__restrict__ off, const uint32_t *__restrict__ col,
-                                  const uint8_t *__restrict__ w, const uint64_t *__restrict__ P, uint64_t U,
-                                  uint64_t words, uint64_t *__restrict__ out) {
-    __shared__ uint32_t s_range[2];
-    const uint64_t k0 = (uint64_t)blockIdx.x * blockDim.x;
-    if (threadIdx.x < 2) {
-        const uint64_t b = threadIdx.x == 0 ? k0 * 64 : (k0 + blockDim.x) * 64 - 1;
-        s_range[threadIdx.x] = b < U ? vertex_of_bit(P, 0, n - 1, b) : n - 1;
-    }
-    __syncthreads();
-    const uint64_t k = k0 + threadIdx.x;
-    if (k >= words) return;
-    const uint64_t b0 = k * 64;
-    uint64_t word = 0;
-    if (b0 < U) {
-        uint32_t v = vertex_of_bit(P, s_range[0], s_range[1], b0);
-        uint32_t wv = w[v];
-        uint64_t pv = P[v];
-        uint64_t i = div_small(b0 - pv, wv, 1.0 / (double)wv);
-        uint64_t pos = pv + i * wv;
-        uint64_t d = off[v + 1] - off[v];
-        const uint64_t end = b0 + 64 < U ? b0 + 64 : U;
-        while (pos < end) {
-            while (i >= d) {  // next vertex with a non-empty list
-                ++v;
-                wv = w[v];
-                d = off[v + 1] - off[v];
-                i = 0;
+__global__ void pack_walk_kernel(uint32_t n, const uint64_t *__restrict__ off, const uint32_t *__restrict__ col,
+                                 const uint8_t *__restrict__ wid, const uint64_t *__restrict__ P, uint64_t items,
+                                 const uint32_t *__restrict__ map, const uint64_t *__restrict__ coff,
+                                 unsigned long long *__restrict__ out) {
+    __shared__ uint64_t s_rs[4][kWave + 1];
+    __shared__ uint64_t s_p[4][kWave];
+    __shared__ uint32_t s_w[4][kWave];
+    __shared__ unsigned long long s_buf[4][kPackBuf];
+    const uint32_t wv = threadIdx.x / kWave;
+    const uint32_t lane = lane_id();
+    const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) / kWave;
+    for (uint64_t k = wave; k < items; k += nwaves) {
+        const uint64_t q = map[k];
+        const uint64_t v0 = q * 64;
+        const uint64_t o = off[v0 + lane <= n ? v0 + lane : n];
+        const uint64_t E1 = off[v0 + 64 <= n ? v0 + 64 : n];
+        s_rs[wv][lane] = o;
+        if (lane == 0) s_rs[wv][64] = E1;
+        s_p[wv][lane] = v0 + lane < n ? P[v0 + lane] : 0ull;
+        s_w[wv][lane] = v0 + lane < n ? wid[v0 + lane] : 0u;
+        wave_lds_sync();
+        const uint64_t eb = __shfl(o, 0, kWave) + (k - coff[q]) * kWalkChunk;
+        const uint64_t ee = eb + kWalkChunk < E1 ? eb + kWalkChunk : E1;
+        if (eb < ee) {
+            uint32_t j = 0;
+#pragma unroll
+            for (uint32_t step = 32; step > 0; step >>= 1)
+                if (s_rs[wv][j + step] <= eb) j += step;
+            const uint64_t first_word = (s_p[wv][j] + (eb - s_rs[wv][j]) * s_w[wv][j]) >> 6;
+            bool open = false;  // a word of the previous step is still being filled
+            unsigned long long carry = 0;
+            uint64_t carry_word = 0;
+            constexpr int kSteps = 4;
+            for (uint64_t base = eb; base < ee; base += kSteps * kWave) {
+                uint64_t e[kSteps];
+                uint32_t row[kSteps];
+                bool valid[kSteps];
+                uint32_t x[kSteps];
+#pragma unroll
+                for (int r = 0; r < kSteps; ++r) {
+                    e[r] = base + (uint64_t)r * kWave + lane;
+                    valid[r] = e[r] < ee;
+                    if (valid[r])
+                        while (s_rs[wv][j + 1] <= e[r]) ++j;
+                    row[r] = j;
+                }
+#pragma unroll
+                for (int r = 0; r < kSteps; ++r) x[r] = col[valid[r] ? e[r] : 0];
+#pragma unroll
+                for (int r = 0; r < kSteps; ++r) {
+                    const uint64_t sb = base + (uint64_t)r * kWave;
+                    if (sb >= ee) break;  // same for every lane
+                    const uint32_t ww = valid[r] ? s_w[wv][row[r]] : 0u;
+                    const uint64_t b = valid[r] ? s_p[wv][row[r]] + (e[r] - s_rs[wv][row[r]]) * ww : 0ull;
+                    const uint32_t last = (uint32_t)(ee - sb < kWave ? ee - sb : kWave) - 1;
+                    const uint64_t b_first = __shfl(b, 0, kWave);
+                    const uint64_t b_end = __shfl(b + ww, last, kWave);
+                    const uint64_t kw0 = b_first >> 6;
+                    const uint32_t nw = (uint32_t)(((b_end - 1) >> 6) - kw0) + 1;
+                    // an open word of the previous step is this step's first word
+                    if (lane < kPackBuf) s_buf[wv][lane] = (lane == 0 && open) ? carry : 0ull;
+                    wave_lds_sync();
+                    if (valid[r]) {
+                        const uint32_t sh = (uint32_t)(b & 63);
+                        const uint32_t idx = (uint32_t)((b >> 6) - kw0);
+                        atomicOr(&s_buf[wv][idx], (unsigned long long)x[r] << sh);
+                        if (sh + ww > 64) atomicOr(&s_buf[wv][idx + 1], (unsigned long long)x[r] >> (64 - sh));
+                    }
+                    wave_lds_sync();
+                    open = (b_end & 63) != 0;
+                    const uint32_t done = open ? nw - 1 : nw;
+                    if (lane < done) {
+                        const uint64_t word = kw0 + lane;
+                        if (word == first_word) atomicOr(&out[word], s_buf[wv][lane]);
+                        else out[word] = s_buf[wv][lane];
+                    }
+                    carry = s_buf[wv][nw - 1];
+                    carry_word = kw0 + nw - 1;
+                    wave_lds_sync();
+                }
             }
-            const uint64_t x = col[off[v] + i];
-            word |= (pos >= b0) ? (x << (pos - b0)) : (x >> (b0 - pos));
-            pos += wv;
-            ++i;
+            if (open && lane == 0) atomicOr(&out[carry_word], carry);
         }
+        wave_lds_sync();
     }
-    out[k] = word;
 }
 
 // ---------------------------------------------------------------------------
@@ -747,8 +828,11 @@ static lg_status encode_impl(uint32_t n, uint64_t m, const uint64_t *row_offsets
         LG_TRY(pack_fixed(SrcU8{w8.as<uint8_t>()}, n, g->F, g->W, g->W_words, s));
         g->A_words = (g->U + 63) / 64 + 1;
         LG_TRY(g->A.scratch(g->A_words * 8, s));
-        LG_LAUNCH(pack_local_kernel, grid_for(g->A_words, 256, 1ull << 31), 256, 0, s, n, cur_off, cur_col,
-                  w8.as<uint8_t>(), P.as<uint64_t>(), g->U, g->A_words, g->A.as<uint64_t>());
+        LG_TRY(fill_u64(g->A.as<uint64_t>(), 0, g->A_words, s));
+        WalkTable wp;
+        LG_TRY(walk_table(n, cur_off, wp, tmp, s));
+        LG_LAUNCH(pack_walk_kernel, wp.grid, 256, 0, s, n, cur_off, cur_col, w8.as<uint8_t>(), P.as<uint64_t>(),
+                  wp.items, wp.map.as<uint32_t>(), wp.coff.as<uint64_t>(), g->A.as<unsigned long long>());
         LG_CHECK_LAUNCH();
         LG_TRY(build_offsets(g, P.as<uint64_t>(), g->U, tmp, s));
         LG_CHECK_HIP(hipStreamSynchronize(s));
