@@ -121,8 +121,7 @@ __global__ void bfs_init_kernel(uint32_t n, int32_t *__restrict__ depth, uint32_
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         queue[0] = root;
-        counters[0] = 0;
-        counters[1] = 0;
+        for (int i = 0; i < 5; ++i) counters[i] = 0;  // queue count and both bottom-up pairs
     }
 }
 
@@ -269,9 +268,11 @@ __global__ void td_small_kernel(Acc acc, const uint32_t *__restrict__ queue, uin
 
 constexpr uint32_t kSmallFrontier = 16384;  // frontier size up to which late levels take td_small_kernel
 
-__global__ void mark_queue_kernel(const uint32_t *__restrict__ queue, const unsigned long long *__restrict__ qsize_dev,
-                                  unsigned long long *__restrict__ bits) {
-    const uint64_t q = *qsize_dev;
+// Marks the q queued vertices in a bitmap.  The queue counter was read by
+// the host already: the kernel clears it for the next level's appends.
+__global__ void mark_queue_kernel(const uint32_t *__restrict__ queue, uint64_t q, unsigned long long *__restrict__ bits,
+                                  unsigned long long *__restrict__ counter) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) *counter = 0;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < q; i += stride) {
         const uint32_t u = queue[i];
@@ -288,10 +289,15 @@ template <class Acc, bool kParent>
 __global__ void bu_step_kernel(Acc acc, uint32_t n, uint32_t threshold, const uint64_t *__restrict__ curr,
                                uint64_t *__restrict__ visited, uint64_t *__restrict__ next,
                                int32_t *__restrict__ depth, uint32_t *__restrict__ parent, int32_t next_depth,
-                               unsigned long long *__restrict__ counters, uint32_t *__restrict__ pv,
-                               uint64_t *__restrict__ pstart, uint32_t *__restrict__ pdeg,
+                               unsigned long long *__restrict__ counters, unsigned long long *__restrict__ next_counters,
+                               uint32_t *__restrict__ pv, uint64_t *__restrict__ pstart, uint32_t *__restrict__ pdeg,
                                uint32_t *__restrict__ pw) {
     const uint32_t lane = lane_id();
+    // the next bottom-up level counts into the other pair: clear it here
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        next_counters[1] = 0;
+        next_counters[2] = 0;
+    }
     const uint64_t words = ((uint64_t)n + 63) / 64;
     const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
     const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) / kWave;
@@ -302,7 +308,10 @@ __global__ void bu_step_kernel(Acc acc, uint32_t n, uint32_t threshold, const ui
         // word: issue their loads together with it
         EFSamples smp{0, 0};
         if constexpr (Acc::kPacked && Acc::kEF) smp = ef_samples(acc.pv.ef, q * 64, n + 1);
-        if (vis == ~0ull) continue;
+        if (vis == ~0ull) {  // every word of next is written: no clearing launch
+            if (lane == 0) next[q] = 0;
+            continue;
+        }
         const VInfo vi = wave_info(acc, q * 64, n, &smp);
         const uint64_t v = q * 64 + lane;
         bool found = false, pending = false;
@@ -329,8 +338,8 @@ __global__ void bu_step_kernel(Acc acc, uint32_t n, uint32_t threshold, const ui
             depth[v] = next_depth;
             if (kParent) parent[v] = par;
         }
+        if (lane == 0) next[q] = fm;
         if (lane == 0 && fm) {
-            next[q] |= fm;
             visited[q] |= fm;
             woke += (unsigned long long)__popcll(fm);
         }
@@ -488,10 +497,14 @@ static lg_status bfs_one(lg_graph *g, BfsWork &w, Acc acc, uint32_t root_id, con
     int32_t level = 0;
     bool topdown = true;
     bool bu_done = false;  // a bottom-up phase is over: the frontier only shrinks from here
+    uint32_t bu_pair = 0;  // counter pair of the next bottom-up level
     for (;;) {
         if (max_depth >= 0 && level >= max_depth) break;
+        // ctr[0], the queue counter, is zero at every level's start: bfs_init
+        // clears it, and every level that appends clears it again when it
+        // marks its queue (the queue built after a bottom-up phase counts
+        // into ctr[5] instead)
         if (topdown && qsize && bu_done && qsize <= kSmallFrontier) {
-            LG_TRY(fill_u64((uint64_t *)ctr, 0, 1, s));
             const uint32_t grid = grid_for(qsize * kWave, 256, kStrideBlocks);
             if (parent)
                 LG_LAUNCH((td_small_kernel<Acc, true>), grid, 256, 0, s, acc, qin, (uint32_t)qsize, visited, depth,
@@ -504,8 +517,8 @@ static lg_status bfs_one(lg_graph *g, BfsWork &w, Acc acc, uint32_t root_id, con
             LG_CHECK_HIP(hipStreamSynchronize(s));
             qsize = w.host[0];
             if (qsize) {
-                LG_LAUNCH(mark_queue_kernel, grid_for(qsize, 256, 1u << 16), 256, 0, s, qout, ctr,
-                          (unsigned long long *)visited);
+                LG_LAUNCH(mark_queue_kernel, grid_for(qsize, 256, 1u << 16), 256, 0, s, qout, qsize,
+                          (unsigned long long *)visited, ctr);
                 LG_CHECK_LAUNCH();
             }
             std::swap(qin, qout);
@@ -525,16 +538,14 @@ static lg_status bfs_one(lg_graph *g, BfsWork &w, Acc acc, uint32_t root_id, con
                                (flags == LG_BFS_DIRECTION_OPT && (double)fedges > (double)edges_to_check / alpha);
             if (go_bu) {
                 LG_TRY(fill_u64(curr, 0, words, s));
-                LG_TRY(fill_u64((uint64_t *)ctr, qsize, 1, s));
-                LG_LAUNCH(mark_queue_kernel, grid_for(qsize, 256, 1u << 16), 256, 0, s, qin, ctr,
-                          (unsigned long long *)curr);
+                LG_LAUNCH(mark_queue_kernel, grid_for(qsize, 256, 1u << 16), 256, 0, s, qin, qsize,
+                          (unsigned long long *)curr, ctr);
                 LG_CHECK_LAUNCH();
                 awake = qsize;
                 topdown = false;
                 continue;
             }
             edges_to_check = edges_to_check > fedges ? edges_to_check - fedges : 0;
-            LG_TRY(fill_u64((uint64_t *)ctr, 0, 1, s));
             if (fedges) {
                 const uint32_t tiles = grid_for(fedges, kTdTile, 1u << 20);
                 if (parent)
@@ -551,30 +562,34 @@ static lg_status bfs_one(lg_graph *g, BfsWork &w, Acc acc, uint32_t root_id, con
             LG_CHECK_HIP(hipStreamSynchronize(s));
             qsize = w.host[0];
             if (qsize) {
-                LG_LAUNCH(mark_queue_kernel, grid_for(qsize, 256, 1u << 16), 256, 0, s, qout, ctr,
-                          (unsigned long long *)visited);
+                LG_LAUNCH(mark_queue_kernel, grid_for(qsize, 256, 1u << 16), 256, 0, s, qout, qsize,
+                          (unsigned long long *)visited, ctr);
                 LG_CHECK_LAUNCH();
             }
             std::swap(qin, qout);
             ++level;
         } else {
-            LG_TRY(fill_u64((uint64_t *)ctr + 1, 0, 2, s));
-            LG_TRY(fill_u64(next, 0, words, s));
+            // bottom-up levels alternate between two counter pairs (woken,
+            // pending) at ctr[1..2] and ctr[3..4]; each level's sweep clears
+            // the pair of the next one (bfs_init clears both)
+            unsigned long long *bc = ctr + 2 * bu_pair;
+            unsigned long long *bc_next = ctr + 2 * (bu_pair ^ 1u);
+            bu_pair ^= 1u;
             const uint32_t grid = grid_for(words * kWave, 256, kStrideBlocks);
             if (parent)
                 LG_LAUNCH((bu_step_kernel<Acc, true>), grid, 256, 0, s, acc, n, g->heavy_threshold, curr, visited,
-                          next, depth, parent, level + 1, ctr, w.pv.as<uint32_t>(), w.pstart.as<uint64_t>(),
+                          next, depth, parent, level + 1, bc, bc_next, w.pv.as<uint32_t>(), w.pstart.as<uint64_t>(),
                           w.pdeg.as<uint32_t>(), w.pw.as<uint32_t>());
             else
                 LG_LAUNCH((bu_step_kernel<Acc, false>), grid, 256, 0, s, acc, n, g->heavy_threshold, curr, visited,
-                          next, depth, parent, level + 1, ctr, w.pv.as<uint32_t>(), w.pstart.as<uint64_t>(),
+                          next, depth, parent, level + 1, bc, bc_next, w.pv.as<uint32_t>(), w.pstart.as<uint64_t>(),
                           w.pdeg.as<uint32_t>(), w.pw.as<uint32_t>());
             LG_CHECK_LAUNCH();
-            LG_CHECK_HIP(hipMemcpyAsync(w.host, ctr + 1, 16, hipMemcpyDeviceToHost, s));
+            LG_CHECK_HIP(hipMemcpyAsync(w.host, bc + 1, 16, hipMemcpyDeviceToHost, s));
             LG_CHECK_HIP(hipStreamSynchronize(s));
             const uint64_t np = w.host[1];
             if (np) {
-                LG_LAUNCH(bu_pending_count_kernel, grid_for(np, 256, 1u << 16), 256, 0, s, ctr, g->heavy_threshold,
+                LG_LAUNCH(bu_pending_count_kernel, grid_for(np, 256, 1u << 16), 256, 0, s, bc, g->heavy_threshold,
                           w.pdeg.as<uint32_t>(), w.pseg_cnt.as<uint32_t>());
                 LG_CHECK_LAUNCH();
                 LG_TRY(exclusive_scan_u32(w.pseg_cnt.as<uint32_t>(), w.pseg_off.as<uint64_t>(), np, w.scan_tmp, s));
@@ -582,14 +597,14 @@ static lg_status bfs_one(lg_graph *g, BfsWork &w, Acc acc, uint32_t root_id, con
                     LG_LAUNCH((bu_pending_kernel<Acc, true>), kStrideBlocks, 256, 0, s, acc, g->heavy_threshold, np,
                               w.pseg_off.as<uint64_t>(), w.pv.as<uint32_t>(), w.pstart.as<uint64_t>(),
                               w.pdeg.as<uint32_t>(), w.pw.as<uint32_t>(), curr, (unsigned long long *)visited,
-                              (unsigned long long *)next, depth, parent, level + 1, ctr);
+                              (unsigned long long *)next, depth, parent, level + 1, bc);
                 else
                     LG_LAUNCH((bu_pending_kernel<Acc, false>), kStrideBlocks, 256, 0, s, acc, g->heavy_threshold, np,
                               w.pseg_off.as<uint64_t>(), w.pv.as<uint32_t>(), w.pstart.as<uint64_t>(),
                               w.pdeg.as<uint32_t>(), w.pw.as<uint32_t>(), curr, (unsigned long long *)visited,
-                              (unsigned long long *)next, depth, parent, level + 1, ctr);
+                              (unsigned long long *)next, depth, parent, level + 1, bc);
                 LG_CHECK_LAUNCH();
-                LG_CHECK_HIP(hipMemcpyAsync(w.host, ctr + 1, 8, hipMemcpyDeviceToHost, s));
+                LG_CHECK_HIP(hipMemcpyAsync(w.host, bc + 1, 8, hipMemcpyDeviceToHost, s));
                 LG_CHECK_HIP(hipStreamSynchronize(s));
             }
             const uint64_t now = w.host[0];
@@ -600,8 +615,9 @@ static lg_status bfs_one(lg_graph *g, BfsWork &w, Acc acc, uint32_t root_id, con
             awake = now;
             if (back) {
                 bu_done = true;
-                LG_TRY(fill_u64((uint64_t *)ctr, 0, 1, s));
-                LG_LAUNCH(bitmap_to_queue_kernel, grid_for(words, 256, 1u << 16), 256, 0, s, words, curr, qin, ctr);
+                LG_TRY(fill_u64((uint64_t *)ctr + 5, 0, 1, s));
+                LG_LAUNCH(bitmap_to_queue_kernel, grid_for(words, 256, 1u << 16), 256, 0, s, words, curr, qin,
+                          ctr + 5);
                 LG_CHECK_LAUNCH();
                 qsize = now;
                 topdown = true;

@@ -491,12 +491,28 @@ __global__ void pack_walk_kernel(uint32_t n, const uint64_t *__restrict__ off, c
 // Elias-Fano upper bits and directory
 // ---------------------------------------------------------------------------
 
+// Bit (x_v >> l) + v of H for every v.  The positions increase with v, so
+// the lanes of a wave that set bits of one word are adjacent: a segmented OR
+// across the lanes gathers each word's bits, and the word's first lane ORs
+// them in (a few atomics per wave instead of one per vertex).
 __global__ void ef_high_kernel(uint64_t count, const uint64_t *__restrict__ x, uint32_t l,
                                unsigned long long *__restrict__ H) {
+    const uint32_t lane = lane_id();
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; v < count; v += stride) {
-        const uint64_t y = (x[v] >> l) + v;
-        atomicOr(&H[y >> 6], 1ull << (y & 63));
+    for (uint64_t base = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x - lane; base < count; base += stride) {
+        const uint64_t v = base + lane;
+        const bool valid = v < count;
+        const uint64_t y = valid ? (x[v] >> l) + v : 0ull;
+        const uint64_t word = valid ? y >> 6 : ~0ull;
+        unsigned long long bits = valid ? 1ull << (y & 63) : 0ull;
+#pragma unroll
+        for (int d = 1; d < kWave; d <<= 1) {
+            const unsigned long long ob = __shfl_down(bits, d, kWave);
+            const uint64_t ow = __shfl_down(word, d, kWave);
+            if (lane + d < kWave && ow == word) bits |= ob;
+        }
+        const uint64_t prev = __shfl_up(word, 1, kWave);
+        if (valid && (lane == 0 || prev != word)) atomicOr(&H[word], bits);
     }
 }
 
