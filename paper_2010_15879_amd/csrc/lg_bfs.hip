@@ -320,12 +320,18 @@ __global__ void bu_step_kernel(Acc acc, uint32_t n, uint32_t threshold, const ui
             const uint32_t st = Acc::step(vi.w), mk = Acc::mask(vi.w);
             const uint32_t lim = vi.deg < threshold ? vi.deg : threshold;
             for (uint32_t i = 0; i < lim && !found; i += 4) {
+                // four list loads, then four frontier-bitmap loads, with no
+                // branch between them (entries past the limit re-read the
+                // first one, which exists: d_v >= 1)
                 uint32_t u[4];
+                uint64_t cw[4];
                 bool f[4];
 #pragma unroll
-                for (int b = 0; b < 4; ++b) u[b] = i + b < lim ? acc.get(vi.start + (uint64_t)(i + b) * st, mk) : 0u;
+                for (int b = 0; b < 4; ++b) u[b] = acc.get(vi.start + (uint64_t)(i + b < lim ? i + b : 0u) * st, mk);
 #pragma unroll
-                for (int b = 0; b < 4; ++b) f[b] = i + b < lim && ((curr[u[b] >> 6] >> (u[b] & 63)) & 1ull);
+                for (int b = 0; b < 4; ++b) cw[b] = curr[u[b] >> 6];
+#pragma unroll
+                for (int b = 0; b < 4; ++b) f[b] = i + b < lim && ((cw[b] >> (u[b] & 63)) & 1ull);
 #pragma unroll
                 for (int b = 0; b < 4; ++b) {
                     if (f[b] && !found) { found = true; par = u[b]; }
