@@ -125,6 +125,24 @@ __global__ void bfs_init_kernel(uint32_t n, int32_t *__restrict__ depth, uint32_
     }
 }
 
+// Degrees of a fixed sample of a large frontier: kDirSample vertices at
+// evenly spaced queue positions, a partial sum per block.  Decoding every
+// frontier vertex's offsets only to learn that the search turns bottom-up
+// is the costliest step of that level with Elias-Fano offsets.
+constexpr uint32_t kDirSampleBlocks = 8;
+constexpr uint32_t kDirSampleThreads = 512;
+constexpr uint32_t kDirSample = kDirSampleBlocks * kDirSampleThreads;
+static_assert(kDirSampleBlocks <= 8, "the partial sums are read back into the 8-word host staging area");
+
+template <class Acc>
+__global__ __launch_bounds__(kDirSampleThreads) void td_sample_kernel(Acc acc, const uint32_t *__restrict__ queue,
+                                                                      uint64_t qsize, uint64_t *__restrict__ part) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const unsigned long long d = acc.info(queue[i * qsize / kDirSample]).deg;
+    const unsigned long long t = block_sum_u64(d);
+    if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
 template <class Acc>
 __global__ void td_prepare_kernel(Acc acc, const uint32_t *__restrict__ queue, uint32_t qsize,
                                   uint64_t *__restrict__ fstart, uint32_t *__restrict__ fdeg,
@@ -533,6 +551,29 @@ static lg_status bfs_one(lg_graph *g, BfsWork &w, Acc acc, uint32_t root_id, con
         }
         if (topdown) {
             if (qsize == 0) break;
+            if (flags == LG_BFS_DIRECTION_OPT && qsize > 2 * (uint64_t)kDirSample) {
+                // a large frontier: when a sample's degrees put its edges at
+                // twice the switch point or more, turn bottom-up without
+                // decoding the whole frontier (the direction changes the
+                // time, never the result)
+                LG_LAUNCH(td_sample_kernel<Acc>, kDirSampleBlocks, kDirSampleThreads, 0, s, acc, qin, qsize,
+                          w.fscan.as<uint64_t>());
+                LG_CHECK_LAUNCH();
+                LG_CHECK_HIP(hipMemcpyAsync(w.host, w.fscan.p, kDirSampleBlocks * 8, hipMemcpyDeviceToHost, s));
+                LG_CHECK_HIP(hipStreamSynchronize(s));
+                uint64_t sampled = 0;
+                for (uint32_t b = 0; b < kDirSampleBlocks; ++b) sampled += w.host[b];
+                const double est = (double)sampled * ((double)qsize / (double)kDirSample);
+                if (est > 2.0 * (double)edges_to_check / alpha) {
+                    LG_TRY(fill_u64(curr, 0, words, s));
+                    LG_LAUNCH(mark_queue_kernel, grid_for(qsize, 256, 1u << 16), 256, 0, s, qin, qsize,
+                              (unsigned long long *)curr, ctr);
+                    LG_CHECK_LAUNCH();
+                    awake = qsize;
+                    topdown = false;
+                    continue;
+                }
+            }
             LG_LAUNCH(td_prepare_kernel<Acc>, grid_for(qsize, 256, 1u << 16), 256, 0, s, acc, qin, (uint32_t)qsize,
                       w.fstart.as<uint64_t>(), w.fdeg.as<uint32_t>(), w.fw.as<uint32_t>());
             LG_CHECK_LAUNCH();
