@@ -50,6 +50,10 @@ def _tiny_graphs():
     # a hub so large that its gap in the Elias-Fano upper bits spans more than
     # 64 words (the per-lane select fallback of the sweep kernels)
     G["megastar"] = gg.csr_from_edges(20001, [(0, i) for i in range(1, 20001)] + [(7, 8), (8, 9)])
+    # the hub is row 1, not row 0: the 8,192-entry pieces of its 64-row block
+    # start in the middle of a 64-bit word, so neighbouring pieces share the
+    # packed words at their boundaries
+    G["offhub"] = gg.csr_from_edges(20002, [(0, 2)] + [(1, i) for i in range(2, 20002)])
     for n in [63, 64, 65, 127, 129]:
         G[f"rand{n}"] = gg.random_graph(n, 0.07, seed=n)
     G["kron12"] = gg.kronecker(12, 16, seed=1)
