@@ -94,8 +94,8 @@ def parse():
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only: --gpus {args.gpus} is not supported by this build "
-              f"(the path runs on a single MI355X; sharding is described in DESIGN.md)", file=sys.stderr)
+        print(f"bench.py measures one GPU only: --gpus {args.gpus} is not supported "
+              f"(the path runs on a single MI355X and has no multi-GPU sharding)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
