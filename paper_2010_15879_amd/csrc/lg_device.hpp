@@ -38,37 +38,6 @@ __device__ __forceinline__ T wave_incl_scan(T x) {
     return x;
 }
 
-// Data-parallel-primitive (DPP) lane moves of the GFX9 family: a VALU
-// operand modifier, no LDS instruction (a shuffle is a ds_bpermute).  A lane
-// whose source is out of range gets 0.
-constexpr int kDppRowShr1 = 0x111;    // lane i takes lane i - k of its 16-lane row (0x110 + k)
-constexpr int kDppWaveShl1 = 0x130;   // lane i takes lane i + 1 of the wave
-constexpr int kDppRowBcast15 = 0x142; // a row takes lane 15 of the row before
-constexpr int kDppRowBcast31 = 0x143; // rows 2 and 3 take lane 31
-
-// Inclusive prefix sum over the 64 lanes of 32-bit values: a scan inside
-// each 16-lane row (shifts by 1, 2, 4, 8), then row 0's total into rows 1
-// and 3 (row mask 1010b) and rows 0-1's total into rows 2 and 3 (1100b).
-// Every lane must be active.
-template <>
-__device__ __forceinline__ uint32_t wave_incl_scan<uint32_t>(uint32_t x) {
-    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, kDppRowShr1, 0xf, 0xf, false);
-    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, kDppRowShr1 + 1, 0xf, 0xf, false);
-    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, kDppRowShr1 + 3, 0xf, 0xf, false);
-    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, kDppRowShr1 + 7, 0xf, 0xf, false);
-    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, kDppRowBcast15, 0xa, 0xf, false);
-    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, kDppRowBcast31, 0xc, 0xf, false);
-    return x;
-}
-
-// x of lane i + 1 (0 for lane 63), 64 bits.  Every lane must be active.
-__device__ __forceinline__ uint64_t wave_next_lane(uint64_t x) {
-    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)x, kDppWaveShl1, 0xf, 0xf, false);
-    const uint32_t hi =
-        (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(x >> 32), kDppWaveShl1, 0xf, 0xf, false);
-    return ((uint64_t)hi << 32) | lo;
-}
-
 __device__ __forceinline__ uint32_t wave_or(uint32_t x) {
 #pragma unroll
     for (int d = kWave / 2; d > 0; d >>= 1) x |= __shfl_xor(x, d, kWave);
@@ -399,7 +368,7 @@ __device__ __forceinline__ VInfo wave_info(const Acc &acc, uint64_t v0, uint32_t
         } else {
             end = __shfl(o0, (uint32_t)(n - v0), kWave);
         }
-        uint64_t o1 = wave_next_lane(o0);
+        uint64_t o1 = __shfl_down(o0, 1, kWave);
         if (lane == kWave - 1) o1 = end;
         if (v >= n) return VInfo{0, 0, 0};
         return acc.make_w((uint32_t)v, o0, o1, wv);
@@ -407,7 +376,7 @@ __device__ __forceinline__ VInfo wave_info(const Acc &acc, uint64_t v0, uint32_t
         (void)smp;
         o0 = acc.offset_value((uint32_t)(v < n ? v : n));
         end = acc.offset_value((uint32_t)(v0 + kWave < n ? v0 + kWave : n));
-        uint64_t o1 = wave_next_lane(o0);
+        uint64_t o1 = __shfl_down(o0, 1, kWave);
         if (lane == kWave - 1) o1 = end;
         if (v >= n) return VInfo{0, 0, 0};
         return acc.make((uint32_t)v, o0, o1);
