@@ -306,6 +306,55 @@ ORC_API void orc_dm_permutation(uint64_t n, const uint64_t *off, uint32_t *perm,
     for (uint64_t x = 0; x < n; x++) inv[perm[x]] = (uint32_t)x;
 }
 
+/* The greedy relabeling heuristic of subsection "Adding Integer Linear
+ * Programming" (its listing of a greedy heuristic for vertex relabeling):
+ * visit the vertices in increasing order of degree; each visited vertex
+ * hands the next unused label to every neighbor, in list order, that has no
+ * label yet; vertices that never received one (no edges) take the remaining
+ * labels in ID order.  Readings of the printed listing: the vertex IDs are
+ * ordered by their degrees (ties by ID; the listing sorts the two arrays
+ * independently), the loops start at vertex 0 and labels start at 0 (the
+ * listing starts both at 1), and the leftover loop labels vertex i.
+ * perm[x] = vertex with new label x, inv[v] = new label of v. */
+ORC_API void orc_greedy_permutation(uint64_t n, const uint64_t *off, const uint32_t *col, uint32_t *perm,
+                                    uint32_t *inv) {
+    if (n == 0) return;
+    uint64_t maxd = 0;
+    for (uint64_t v = 0; v < n; v++) {
+        const uint64_t d = off[v + 1] - off[v];
+        if (d > maxd) maxd = d;
+    }
+    /* IDs ordered by degree ascending, stable (counting sort by degree) */
+    uint64_t *start = (uint64_t *)calloc(maxd + 2, sizeof(uint64_t));
+    uint32_t *order = (uint32_t *)malloc(n * sizeof(uint32_t));
+    unsigned char *visit = (unsigned char *)calloc(n, 1);
+    for (uint64_t v = 0; v < n; v++) start[off[v + 1] - off[v] + 1]++;
+    for (uint64_t d = 1; d <= maxd + 1; d++) start[d] += start[d - 1];
+    for (uint64_t v = 0; v < n; v++) order[start[off[v + 1] - off[v]]++] = (uint32_t)v;
+    uint32_t nl = 0;
+    for (uint64_t i = 0; i < n; i++) {
+        const uint32_t v = order[i];
+        for (uint64_t e = off[v]; e < off[v + 1]; e++) {
+            const uint32_t id = col[e];
+            if (!visit[id]) {
+                inv[id] = nl;
+                perm[nl] = id;
+                nl++;
+                visit[id] = 1;
+            }
+        }
+    }
+    for (uint64_t i = 0; i < n; i++)
+        if (!visit[i]) {
+            inv[i] = nl;
+            perm[nl] = (uint32_t)i;
+            nl++;
+        }
+    free(start);
+    free(order);
+    free(visit);
+}
+
 /* The relabeled adjacency array: row x is the list of perm[x] with every
  * neighbor renamed through inv and re-sorted ascending (lists are kept
  * sorted, subsection "Adjacency Array Data Structures"). */

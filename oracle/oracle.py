@@ -71,6 +71,7 @@ def lib():
         "orc_ef_get": (C.c_uint64, [u64p, u64p, C.c_uint64, C.c_uint, C.c_uint64]),
         "orc_dm_permutation": (None, [C.c_uint64, u64p, u32p, u32p]),
         "orc_relabel": (None, [C.c_uint64, u64p, u32p, u32p, u32p, u64p, u32p]),
+        "orc_greedy_permutation": (None, [C.c_uint64, u64p, u32p, u32p, u32p]),
         "orc_relabel_row": (None, [u64p, u32p, u32p, u32p, C.c_uint32, u32p]),
         "orc_bfs_labels": (C.c_int, [C.c_uint64, u64p, u32p, C.c_uint32, C.c_int32, _NullableU32,
                                      i32p, i32p]),
@@ -218,6 +219,17 @@ def dm_permutation(off):
     return perm[:n], inv[:n]
 
 
+def greedy_permutation(off, col):
+    """(perm, inv) of the greedy relabeling heuristic (subsection "Adding
+    Integer Linear Programming"): vertices by increasing degree hand labels to
+    their unlabeled neighbors in list order; edgeless vertices last, by ID."""
+    n, off, col = _csr(off, col)
+    perm = np.zeros(max(n, 1), dtype=np.uint32)
+    inv = np.zeros(max(n, 1), dtype=np.uint32)
+    lib().orc_greedy_permutation(n, off, col, perm, inv)
+    return perm[:n], inv[:n]
+
+
 def relabel(off, col, perm, inv):
     n, off, col = _csr(off, col)
     off2 = np.zeros(n + 1, dtype=np.uint64)
@@ -273,15 +285,19 @@ class Encoding:
     with a width table at F bits per vertex).  offset_mode: "packed"
     (fixed-width offsets) or "ef" (Elias-Fano with rank/select directory).
     The offset values are element offsets O[v] in global mode (bit start =
-    s * O[v]) and bit starts P_v in local mode.  relabel: apply the
-    degree-minimizing permutation first."""
+    s * O[v]) and bit starts P_v in local mode.  relabel: False, True or
+    "degree" (the degree-minimizing permutation), or "greedy" (the greedy
+    heuristic), applied first."""
 
     def __init__(self, off, col, id_mode="global", offset_mode="packed", relabel=False):
         n, off, col = _csr(off, col)
         self.n = n
         self.m = col.size
         if relabel:
-            self.perm, self.inv = dm_permutation(off)
+            if relabel == "greedy":
+                self.perm, self.inv = greedy_permutation(off, col)
+            else:
+                self.perm, self.inv = dm_permutation(off)
             off, col = globals()["relabel"](off, col, self.perm, self.inv)
         else:
             self.perm = self.inv = None
