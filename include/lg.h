@@ -67,6 +67,11 @@ typedef enum lg_status {
 /* lg_encode_opts.relabel -- section "Incorporating Degree-Minimizing (DM)" */
 #define LG_RELABEL_NONE 0u
 #define LG_RELABEL_DEGREE 1u /* new label = rank by (degree desc, ID asc)         */
+/* subsection "Adding Integer Linear Programming", its greedy heuristic:
+ * vertices taken by increasing degree (ties by ID) give the next label to
+ * each neighbor, in list order, that has none yet; edgeless vertices take
+ * the last labels in ID order */
+#define LG_RELABEL_GREEDY 2u
 
 typedef struct lg_encode_opts {
     uint32_t layout;      /* LG_LAYOUT_*                                          */

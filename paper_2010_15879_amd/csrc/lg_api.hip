@@ -339,7 +339,7 @@ static bool export_src(const lg_graph *g, uint32_t which, const void **p, uint64
             return true;
         case LG_EXPORT_PERM:
         case LG_EXPORT_INV:
-            if (g->relabel != LG_RELABEL_DEGREE) return false;
+            if (g->relabel == LG_RELABEL_NONE) return false;
             *p = which == LG_EXPORT_PERM ? g->perm.p : g->inv.p;
             *bytes = (uint64_t)g->n * 4;
             return true;

@@ -677,8 +677,8 @@ static lg_status bfs_one(lg_graph *g, BfsWork &w, Acc acc, uint32_t root_id, con
 lg_status bfs_run(lg_graph *g, BfsWork &w, const uint32_t *roots, uint32_t r, int32_t *depth, int32_t *parent,
                   int32_t max_depth, uint32_t flags, hipStream_t stream, double alpha) {
     if (r == 0) return LG_OK;
-    LG_TRY(bfs_workspace_ensure(w, g->n, g->n_heavy, g->relabel == LG_RELABEL_DEGREE, parent != nullptr));
-    const bool rel = g->relabel == LG_RELABEL_DEGREE;
+    LG_TRY(bfs_workspace_ensure(w, g->n, g->n_heavy, g->relabel != LG_RELABEL_NONE, parent != nullptr));
+    const bool rel = g->relabel != LG_RELABEL_NONE;
     const uint32_t *inv = rel ? g->inv.as<uint32_t>() : nullptr;
     return dispatch_acc(g, [&](auto acc) -> lg_status {
         for (uint32_t i = 0; i < r; ++i) {

@@ -72,7 +72,7 @@ lg_status decode_run(lg_graph *g, DecodeWork &w, const uint32_t *vertices, uint3
             return LG_ERR_OOM;
         }
     }
-    const bool rel = g->relabel == LG_RELABEL_DEGREE;
+    const bool rel = g->relabel != LG_RELABEL_NONE;
     const uint32_t *inv = (rel && flags != LG_DECODE_RAW) ? g->inv.as<uint32_t>() : nullptr;
     const uint32_t *perm = (rel && flags != LG_DECODE_RAW) ? g->perm.as<uint32_t>() : nullptr;
     const bool sorted = rel && flags == LG_DECODE_SORTED;

@@ -6,12 +6,14 @@
 //                 no self-loops, symmetric)
 //   relabel       degree-minimizing permutation (section "Incorporating
 //                 Degree-Minimizing (DM)"): stable radix sort of vertices by
-//                 degree, then the relabeled lists via one stable radix sort of
-//                 (new target, new source) pairs by target
+//                 degree; or the greedy heuristic of subsection "Adding
+//                 Integer Linear Programming"; then the relabeled lists via
+//                 one stable radix sort of (original target, new source)
+//                 pairs by target
 //   widths        global s or local w_v ("Logarithmization of Vertex IDs")
 //   scan          bit starts P_v = exclusive prefix of d_v * w_v
-//   pack          each thread assembles one 64-bit output word from the
-//                 elements overlapping it (no atomics, deterministic)
+//   pack          fixed widths: each thread assembles one 64-bit output word;
+//                 local widths: a walk over the lists, words gathered in LDS
 //   offsets       packed offsets ("Logarithmization of Single Offsets") or an
 //                 Elias-Fano sequence with a rank/select directory ("Succinct
 //                 Bit Vectors in Log(Graph)")
@@ -315,6 +317,83 @@ __global__ void dm_place_kernel(uint32_t n, const uint32_t *__restrict__ perm, c
         walk_item(n, off_new, map, coff, k, s_rs[wv], load, [&](uint64_t e, uint32_t, bool valid, uint32_t x) {
             if (valid) col_new[e] = x;
         });
+    }
+}
+
+// Greedy relabeling (subsection "Adding Integer Linear Programming", its
+// listing of a greedy heuristic): vertices taken by increasing degree (ties
+// by ID) hand the next label to each neighbor, in list order, that has none
+// yet; edgeless vertices take the last labels in ID order.  The label order
+// of a vertex x is that of its first hand-out: the smallest rank r(u) of a
+// neighbor u in the processing order, then x's position in the list of u.
+// So the sequential loop becomes: ranks by a sort on degree; per x the
+// minimum rank over its own list (lists are symmetric); x's position in that
+// neighbor's list by binary search; a stable sort of the vertices by
+// (rank, position).
+
+// sort key d_v (an ascending stable sort orders by degree, ties by ID)
+__global__ void greedy_order_keys_kernel(uint32_t n, const uint32_t *__restrict__ deg, uint32_t *__restrict__ keys,
+                                         uint32_t *__restrict__ vals) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) {
+        keys[v] = deg[v];
+        vals[v] = (uint32_t)v;
+    }
+}
+
+// rank[order[r]] = r
+__global__ void greedy_rank_kernel(uint32_t n, const uint32_t *__restrict__ order, uint32_t *__restrict__ rank) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += stride) rank[order[r]] = (uint32_t)r;
+}
+
+// rmin[x] = min over u in N_x of rank[u] (rmin starts at ~0): a walk over
+// the lists, a per-row minimum in LDS, one global atomic per row and piece
+__global__ void greedy_min_kernel(uint32_t n, const uint64_t *__restrict__ off, const uint32_t *__restrict__ col,
+                                  const uint32_t *__restrict__ rank, uint64_t items, const uint32_t *__restrict__ map,
+                                  const uint64_t *__restrict__ coff, uint32_t *__restrict__ rmin) {
+    __shared__ uint64_t s_rs[4][kWave + 1];
+    __shared__ uint32_t s_min[4][kWave];
+    const uint32_t wv = threadIdx.x / kWave;
+    const uint32_t lane = lane_id();
+    const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) / kWave;
+    for (uint64_t k = wave; k < items; k += nwaves) {
+        const uint64_t v0 = (uint64_t)map[k] * 64;
+        s_min[wv][lane] = 0xFFFFFFFFu;
+        walk_item(
+            n, off, map, coff, k, s_rs[wv], [&](uint64_t e, uint32_t, bool valid) { return col[valid ? e : 0]; },
+            [&](uint64_t, uint32_t j, bool valid, uint32_t u) {
+                if (valid) atomicMin(&s_min[wv][j], rank[u]);
+            });
+        // walk_item ends with a wave LDS sync: every lane's minimum is in
+        if (v0 + lane < n && s_min[wv][lane] != 0xFFFFFFFFu) atomicMin(&rmin[v0 + lane], s_min[wv][lane]);
+        wave_lds_sync();
+    }
+}
+
+// key[x] = rmin[x] << jbits | (position of x in the list of order[rmin[x]]),
+// n << jbits for a vertex without edges; val[x] = x.  The lists are
+// symmetric and strictly increasing, so x is found.
+__global__ void greedy_key_kernel(uint32_t n, const uint64_t *__restrict__ off, const uint32_t *__restrict__ col,
+                                  const uint32_t *__restrict__ order, const uint32_t *__restrict__ rmin,
+                                  uint32_t jbits, uint64_t *__restrict__ key, uint32_t *__restrict__ val) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t x = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n; x += stride) {
+        const uint32_t r = rmin[x];
+        uint64_t k = (uint64_t)n << jbits;
+        if (r != 0xFFFFFFFFu) {
+            const uint32_t u = order[r];
+            uint64_t lo = off[u], hi = off[u + 1];
+            const uint64_t base = lo;
+            while (lo < hi) {
+                const uint64_t mid = lo + ((hi - lo) >> 1);
+                if (col[mid] < (uint32_t)x) lo = mid + 1; else hi = mid;
+            }
+            k = ((uint64_t)r << jbits) | (lo - base);
+        }
+        key[x] = k;
+        val[x] = (uint32_t)x;
     }
 }
 
@@ -663,6 +742,46 @@ static lg_status walk_table(uint32_t n, const uint64_t *off, WalkTable &t, DevBu
     return LG_OK;
 }
 
+// perm (new label -> vertex) of the greedy relabeling; `walk` walks the
+// input lists, `deg` holds the degrees
+static lg_status greedy_permutation(uint32_t n, const uint64_t *off, const uint32_t *col, const DevBuf &deg,
+                                    uint32_t max_degree, const WalkTable &walk, uint32_t *perm, DevBuf &tmp,
+                                    hipStream_t s) {
+    DevBuf k1, v1, k2, v2, rank, rmin, key, key2, val2;
+    // processing order: degree ascending, ties by ID (stable sort)
+    LG_TRY(k1.scratch((uint64_t)n * 4, s));
+    LG_TRY(v1.scratch((uint64_t)n * 4, s));
+    LG_TRY(k2.scratch((uint64_t)n * 4, s));
+    LG_TRY(v2.scratch((uint64_t)n * 4, s));
+    LG_LAUNCH(greedy_order_keys_kernel, grid1(n), 256, 0, s, n, deg.as<uint32_t>(), k1.as<uint32_t>(),
+              v1.as<uint32_t>());
+    LG_CHECK_LAUNCH();
+    int alt = 0;
+    LG_TRY(radix_sort_pairs(k1.as<uint32_t>(), v1.as<uint32_t>(), k2.as<uint32_t>(), v2.as<uint32_t>(), n,
+                            std::max<uint32_t>(bitlen_u64(max_degree), 1u), tmp, s, &alt));
+    const uint32_t *order = (alt ? v2 : v1).as<uint32_t>();
+    LG_TRY(rank.scratch((uint64_t)n * 4, s));
+    LG_LAUNCH(greedy_rank_kernel, grid1(n), 256, 0, s, n, order, rank.as<uint32_t>());
+    LG_CHECK_LAUNCH();
+    LG_TRY(rmin.scratch((uint64_t)n * 4, s));
+    LG_TRY(fill_u32(rmin.as<uint32_t>(), 0xFFFFFFFFu, n, s));
+    LG_LAUNCH(greedy_min_kernel, walk.grid, 256, 0, s, n, off, col, rank.as<uint32_t>(), walk.items,
+              walk.map.as<uint32_t>(), walk.coff.as<uint64_t>(), rmin.as<uint32_t>());
+    LG_CHECK_LAUNCH();
+    // keys: rank below n (bitlen(n) bits) over a position below max_degree
+    const uint32_t jbits = std::max<uint32_t>(bitlen_u64(max_degree ? max_degree - 1 : 0), 1u);
+    LG_TRY(key.scratch((uint64_t)n * 8, s));
+    LG_TRY(key2.scratch((uint64_t)n * 8, s));
+    LG_TRY(val2.scratch((uint64_t)n * 4, s));
+    LG_LAUNCH(greedy_key_kernel, grid1(n), 256, 0, s, n, off, col, order, rmin.as<uint32_t>(), jbits,
+              key.as<uint64_t>(), perm);
+    LG_CHECK_LAUNCH();
+    LG_TRY(radix_sort_pairs64(key.as<uint64_t>(), perm, key2.as<uint64_t>(), val2.as<uint32_t>(), n,
+                              bitlen_u64(n) + jbits, tmp, s));
+    LG_CHECK_HIP(hipStreamSynchronize(s));
+    return LG_OK;
+}
+
 static lg_status encode_impl(uint32_t n, uint64_t m, const uint64_t *row_offsets, const uint32_t *col,
                              const lg_encode_opts &o, hipStream_t s, lg_graph *g) {
     DevBuf tmp, status, deg, stats;
@@ -728,19 +847,25 @@ static lg_status encode_impl(uint32_t n, uint64_t m, const uint64_t *row_offsets
     const uint32_t *cur_col = col;
     DevBuf off_new, col_new;
     const uint32_t idbits = bitlen_u64(n - 1);
-    if (o.relabel == LG_RELABEL_DEGREE) {
-        DevBuf k1, k2, v2, deg_new;
-        LG_TRY(k1.scratch((uint64_t)n * 4, s));
-        LG_TRY(k2.scratch((uint64_t)n * 4, s));
-        LG_TRY(v2.scratch((uint64_t)n * 4, s));
+    if (o.relabel != LG_RELABEL_NONE) {
+        DevBuf deg_new;
         LG_TRY(g->perm.scratch((uint64_t)n * 4, s));
         LG_TRY(g->inv.scratch((uint64_t)n * 4, s));
         LG_TRY(deg_new.scratch((uint64_t)n * 4, s));
-        LG_LAUNCH(dm_keys_kernel, grid1(n), 256, 0, s, n, deg.as<uint32_t>(), k1.as<uint32_t>(),
-                  g->perm.as<uint32_t>());
-        LG_CHECK_LAUNCH();
-        LG_TRY(radix_sort_pairs(k1.as<uint32_t>(), g->perm.as<uint32_t>(), k2.as<uint32_t>(), v2.as<uint32_t>(), n,
-                                idbits, tmp, s));
+        if (o.relabel == LG_RELABEL_DEGREE) {
+            DevBuf k1, k2, v2;
+            LG_TRY(k1.scratch((uint64_t)n * 4, s));
+            LG_TRY(k2.scratch((uint64_t)n * 4, s));
+            LG_TRY(v2.scratch((uint64_t)n * 4, s));
+            LG_LAUNCH(dm_keys_kernel, grid1(n), 256, 0, s, n, deg.as<uint32_t>(), k1.as<uint32_t>(),
+                      g->perm.as<uint32_t>());
+            LG_CHECK_LAUNCH();
+            LG_TRY(radix_sort_pairs(k1.as<uint32_t>(), g->perm.as<uint32_t>(), k2.as<uint32_t>(),
+                                    v2.as<uint32_t>(), n, idbits, tmp, s));
+        } else {
+            LG_TRY(greedy_permutation(n, row_offsets, col, deg, g->max_degree, walk, g->perm.as<uint32_t>(), tmp,
+                                      s));
+        }
         LG_LAUNCH(dm_inverse_kernel, grid1(n), 256, 0, s, n, g->perm.as<uint32_t>(), deg.as<uint32_t>(),
                   g->inv.as<uint32_t>(), deg_new.as<uint32_t>());
         LG_CHECK_LAUNCH();
@@ -871,7 +996,7 @@ extern "C" lg_status lg_encode(uint32_t n, uint64_t m, const uint64_t *row_offse
     if (m >= (1ull << 36)) { set_error("lg_encode: m must be below 2^36"); return LG_ERR_UNSUPPORTED; }
     if (!row_offsets || (m && !col)) { set_error("lg_encode: NULL input array"); return LG_ERR_INVALID; }
     if (o.layout > LG_LAYOUT_PLAIN || o.id_mode > LG_IDS_LOCAL || o.offset_mode > LG_OFFS_SUCCINCT ||
-        o.relabel > LG_RELABEL_DEGREE || o.flags || o.reserved[0] || o.reserved[1] || o.reserved[2]) {
+        o.relabel > LG_RELABEL_GREEDY || o.flags || o.reserved[0] || o.reserved[1] || o.reserved[2]) {
         set_error("lg_encode: unknown option value");
         return LG_ERR_INVALID;
     }

@@ -242,7 +242,7 @@ extern "C" lg_status lg_pagerank(const lg_graph *gc, float damping, uint32_t ite
     if (g->pr->ca.bytes < (uint64_t)n * 4) LG_TRY(g->pr->ca.scratch((uint64_t)n * 4, stream));
     if (g->pr->cb.bytes < (uint64_t)n * 4) LG_TRY(g->pr->cb.scratch((uint64_t)n * 4, stream));
     LG_TRY(ensure_heavy_segments(g, stream));
-    const uint32_t *perm = g->relabel == LG_RELABEL_DEGREE ? g->perm.as<uint32_t>() : nullptr;
+    const uint32_t *perm = g->relabel != LG_RELABEL_NONE ? g->perm.as<uint32_t>() : nullptr;
     const double a = damping;
     const double z = g->isolated;
     return dispatch_acc(g, [&](auto acc) -> lg_status {

@@ -217,7 +217,7 @@ void lg_server::plan(Worker &W, const lg_query &q, uint32_t batch, std::vector<R
     using namespace lg;
     const lg_graph *g = graphs[q.graph];
     const uint64_t n = g->n;
-    const bool rel = g->relabel == LG_RELABEL_DEGREE;
+    const bool rel = g->relabel != LG_RELABEL_NONE;
     out.clear();
     if (q.kind == LG_QUERY_NEIGHBORS) {
         const uint64_t k = batch;

@@ -218,10 +218,20 @@ class Graph:
 
 def encode(row_offsets: torch.Tensor, col: torch.Tensor, n: Optional[int] = None, *, layout="packed",
            ids="global", offsets="packed", relabel=False, stream=None) -> Graph:
-    """lg_encode over a device CSR (row_offsets int64[n+1], col int32[M])."""
+    """lg_encode over a device CSR (row_offsets int64[n+1], col int32[M]).
+    relabel: False, True or "degree" (degree-minimizing), or "greedy" (the
+    greedy heuristic)."""
     n = row_offsets.numel() - 1 if n is None else n
     m = col.numel()
-    opts = EncodeOpts(LAYOUTS[layout], ID_MODES[ids], OFFSET_MODES[offsets], 1 if relabel else 0, 0)
+    if relabel is True or relabel == "degree":
+        rl = 1
+    elif relabel == "greedy":
+        rl = 2
+    elif relabel is False or relabel is None:
+        rl = 0
+    else:
+        raise ValueError(f"relabel must be False, True, 'degree' or 'greedy', not {relabel!r}")
+    opts = EncodeOpts(LAYOUTS[layout], ID_MODES[ids], OFFSET_MODES[offsets], rl, 0)
     out = C.c_void_p()
     _check(lib().lg_encode(n, m, _dev_ptr(row_offsets, torch.int64, "row_offsets"),
                            _dev_ptr(col, torch.int32, "col") if m else None, C.byref(opts), _stream(stream),

@@ -25,7 +25,21 @@ ENCODINGS = [
     dict(layout="packed", ids="local", offsets="succinct", relabel=False),
     dict(layout="plain", relabel=False),
     dict(layout="plain", relabel=True),
+    dict(layout="packed", ids="local", offsets="succinct", relabel="greedy"),
+    dict(layout="plain", relabel="greedy"),
 ]
+
+
+def oracle_perm(off, col, relabel):
+    """(perm, inv) of the oracle for the encoding's relabeling."""
+    return orc.greedy_permutation(off, col) if relabel == "greedy" else orc.dm_permutation(off)
+
+
+def oracle_bfs(off, col, root, relabel, max_depth=-1):
+    """Depths and parents (smallest stored label among the candidates)."""
+    if relabel == "greedy":
+        return orc.bfs(off, col, root, max_depth=max_depth, labels=oracle_perm(off, col, relabel)[1])
+    return orc.bfs(off, col, root, max_depth=max_depth, relabeled=bool(relabel))
 
 
 def enc_id(e):
@@ -95,7 +109,7 @@ def test_encoding_bit_exact(lgmod, name, e):
     off, col = g.numpy()
     if e["layout"] == "plain":
         if e["relabel"]:
-            perm, inv = orc.dm_permutation(off)
+            perm, inv = oracle_perm(off, col, e["relabel"])
             off, col = orc.relabel(off, col, perm, inv)
             np.testing.assert_array_equal(h.export("perm"), perm)
             np.testing.assert_array_equal(h.export("inv"), inv)
@@ -143,7 +157,7 @@ def test_decode_neighbors(lgmod, name, e):
         np.testing.assert_array_equal(o_ids[o_off[i]:o_off[i + 1]], col[off[v]:off[v + 1]])
     # stored order / stored labels
     if e["relabel"]:
-        perm, inv = orc.dm_permutation(off)
+        perm, inv = oracle_perm(off, col, e["relabel"])
         r_off, r_ids = lgmod.decode_neighbors(h, vt, "raw")
         r_off, r_ids = r_off.cpu().numpy(), r_ids.cpu().numpy()
         for i, x in enumerate(vs):
@@ -171,7 +185,7 @@ def test_bfs_bit_exact(lgmod, name, e, mode):
     depth, parent = lgmod.bfs(h, roots, mode=mode)
     depth, parent = depth.cpu().numpy(), parent.cpu().numpy()
     for i, r in enumerate(roots):
-        d0, p0 = orc.bfs(off, col, r, relabeled=e["relabel"])
+        d0, p0 = oracle_bfs(off, col, r, e["relabel"])
         np.testing.assert_array_equal(depth[i], d0)
         np.testing.assert_array_equal(parent[i], p0)
     h.free()
@@ -187,7 +201,7 @@ def test_bfs_k_hop(lgmod, e, k):
     h = encode(lgmod, g, e)
     depth, parent = lgmod.bfs(h, roots, max_depth=k)
     for i, r in enumerate(roots):
-        d0, p0 = orc.bfs(off, col, r, max_depth=k, relabeled=e["relabel"])
+        d0, p0 = oracle_bfs(off, col, r, e["relabel"], max_depth=k)
         np.testing.assert_array_equal(depth[i].cpu().numpy(), d0)
         np.testing.assert_array_equal(parent[i].cpu().numpy(), p0)
     h.free()
@@ -317,7 +331,7 @@ def test_decode_capacity_error(lgmod):
     h.free()
 
 
-@pytest.mark.parametrize("e", [ENCODINGS[0], ENCODINGS[3], ENCODINGS[6], ENCODINGS[7]], ids=enc_id)
+@pytest.mark.parametrize("e", [ENCODINGS[0], ENCODINGS[3], ENCODINGS[6], ENCODINGS[7], ENCODINGS[8]], ids=enc_id)
 def test_kronecker16_config(lgmod, e):
     """Kronecker scale 16, edge factor 16, seed 1: 64 roots, 20 PR iterations."""
     g = gg.kronecker(16, 16, seed=1)
@@ -331,7 +345,7 @@ def test_kronecker16_config(lgmod, e):
     depth, parent = lgmod.bfs(h, roots)
     depth, parent = depth.cpu().numpy(), parent.cpu().numpy()
     for i, r in enumerate(roots[:16]):
-        d0, p0 = orc.bfs(off, col, r, relabeled=e["relabel"])
+        d0, p0 = oracle_bfs(off, col, r, e["relabel"])
         np.testing.assert_array_equal(depth[i], d0)
         np.testing.assert_array_equal(parent[i], p0)
     pr = lgmod.pagerank(h, 0.85, 20).cpu().numpy().astype(np.float64)
