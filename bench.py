@@ -86,6 +86,14 @@ def parse():
                         "200 GB budget; saturated queries/s and p50/p99 latency per offered load (own JSON line)")
     p.add_argument("--serve-scales", default="20,22,24,26")
     p.add_argument("--serve-seconds", type=float, default=6.0, help="arrival window per offered load")
+    p.add_argument("--relabel-compare", action="store_true",
+                   help="the workload's graph under no relabeling, the degree-minimizing relabeling and the greedy "
+                        "heuristic (local widths, Elias-Fano offsets): |A|, encode, BFS and PageRank times "
+                        "(own JSON line)")
+    p.add_argument("--offset-fetch", action="store_true",
+                   help="random fetch of 1,000 vertices per worker (256 workers, one call) under 32-bit plain "
+                        "offsets, packed offsets and Elias-Fano offsets: degrees only and whole lists "
+                        "(own JSON line)")
     p.add_argument("--pr-only", action="store_true",
                    help="counter-run mode: one 1 GiB device copy (calibration) then one PageRank call; no timing")
     return p.parse_args()
@@ -124,6 +132,10 @@ def main():
     stream = torch.cuda.current_stream()
     n, M = g.n, g.m
     degf = deg.to(torch.float64)
+    if args.relabel_compare:
+        return relabel_main(args, np, torch, lg, g, roots)
+    if args.offset_fetch:
+        return offset_fetch_main(args, np, torch, lg, g)
 
     if args.pr_only:
         # A kernel of known traffic calibrates the HBM byte counters (an
@@ -381,6 +393,97 @@ def main():
         },
     }
     print(json.dumps(out), flush=True)
+
+
+def _time_ms(torch, fn, reps=3):
+    """Median of `reps` timed calls after one untimed call, HIP events on the
+    current stream."""
+    fn()
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        fn()
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    return sorted(ts)[len(ts) // 2]
+
+
+def relabel_main(args, np, torch, lg, g, roots):
+    """The workload's graph under each relabeling, local widths and
+    Elias-Fano offsets: bytes of the packed lists |A|, of the offsets and of
+    the width table; encode time; BFS from the roots (one call) and 20
+    PageRank iterations.  The same graph and roots for every relabeling."""
+    n = g.n
+    depth = torch.empty((len(roots), n), dtype=torch.int32, device=g.col.device)
+    parent = torch.empty_like(depth)
+    res = {}
+    for rl, name in [(False, "none"), (True, "degree"), ("greedy", "greedy")]:
+        enc = lambda: lg.encode(g.row_offsets, g.col, n, ids="local", offsets="succinct", relabel=rl)  # noqa: E731
+        hs = []
+        enc_ms = _time_ms(torch, lambda: hs.append(enc()))
+        for h in hs[:-1]:
+            h.free()
+        h = hs[-1]
+        info = h.info()
+        bfs_ms = _time_ms(torch, lambda: lg.bfs(h, roots, depth_out=depth, parent_out=parent))
+        pr = lg.pagerank(h, 0.85, 20)
+        pr_ms = _time_ms(torch, lambda: lg.pagerank(h, 0.85, 20, out=pr))
+        res[name] = {"adj_bytes": info["adj_bits"] / 8.0, "offsets_bytes": info["bytes_offsets"],
+                     "widths_bytes": info["bytes_widths"], "encode_ms": round(enc_ms, 3),
+                     "bfs_all_roots_ms": round(bfs_ms, 3), "pagerank_20_ms": round(pr_ms, 3)}
+        log(f"[relabel] {name}: {res[name]}")
+        h.free()
+    base = res["none"]["adj_bytes"]
+    for name in res:
+        res[name]["adj_vs_none"] = round(res[name]["adj_bytes"] / base, 4)
+    print(json.dumps({"mode": "relabel-compare", "workload": args.workload, "n": n, "stored_edges": g.m,
+                      "roots": len(roots), "encoding": {"ids": "local", "offsets": "succinct"},
+                      "data": "synthetic", "results": res}), flush=True)
+
+
+def offset_fetch_main(args, np, torch, lg, g):
+    """Random fetch under each offset structure (the random-offset-fetch test
+    of the offset-structure comparison: 1,000 random vertices per worker;
+    here 256 workers, one per compute unit, in one call), no relabeling,
+    local widths: degrees only (one offset pair per vertex: the structure's
+    random access) and whole lists."""
+    import ctypes as C
+    n = g.n
+    k = 1000 * 256
+    rng = np.random.default_rng(7)
+    vt = torch.from_numpy(rng.integers(0, n, size=k).astype(np.int32)).to(g.col.device)
+    off = torch.empty(k + 1, dtype=torch.int64, device=g.col.device)
+    s = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    res = {}
+    for name, kw in [("ptr32", dict(layout="plain")), ("bvPL", dict(ids="local", offsets="packed")),
+                     ("bvSD", dict(ids="local", offsets="succinct"))]:
+        h = lg.encode(g.row_offsets, g.col, n, **kw)
+        info = h.info()
+
+        def degrees_only():
+            # no output array: only the offsets are fetched (the call reports
+            # the capacity it would need)
+            lg.lib().lg_decode_neighbors(h.handle, C.c_void_p(vt.data_ptr()), k, C.c_void_p(off.data_ptr()), None, 0,
+                                         2, s)
+        deg_ms = _time_ms(torch, degrees_only, reps=5)
+        total = int(off[-1].item())
+        ids = torch.empty(max(total, 1), dtype=torch.int32, device=g.col.device)
+
+        def lists():
+            st = lg.lib().lg_decode_neighbors(h.handle, C.c_void_p(vt.data_ptr()), k, C.c_void_p(off.data_ptr()),
+                                              C.c_void_p(ids.data_ptr()), total, 2, s)
+            assert st == 0, lg.lib().lg_last_error()
+        lists_ms = _time_ms(torch, lists, reps=5)
+        res[name] = {"offsets_bytes": info["bytes_offsets"], "degrees_only_ms": round(deg_ms, 4),
+                     "ns_per_offset_fetch": round(deg_ms * 1e6 / k, 3), "lists_ms": round(lists_ms, 4),
+                     "entries": total, "gentries_per_s": round(total / (lists_ms * 1e-3) / 1e9, 3)}
+        log(f"[offsets] {name}: {res[name]}")
+        h.free()
+    print(json.dumps({"mode": "offset-fetch", "workload": args.workload, "n": n, "stored_edges": g.m,
+                      "vertices_per_call": k, "data": "synthetic", "results": res}), flush=True)
 
 
 def batch_main(args, np, torch, gg, lg, dev):
