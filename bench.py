@@ -92,7 +92,8 @@ def parse():
                         "(own JSON line)")
     p.add_argument("--offset-fetch", action="store_true",
                    help="random fetch of 1,000 vertices per worker (256 workers, one call) under 32-bit plain "
-                        "offsets, packed offsets and Elias-Fano offsets: degrees only and whole lists "
+                        "offsets (ptr32), offsets at bl(universe) bits (ptrW) and Elias-Fano offsets (bvSD): "
+                        "degrees only and whole lists "
                         "(own JSON line)")
     p.add_argument("--pr-only", action="store_true",
                    help="counter-run mode: one 1 GiB device copy (calibration) then one PageRank call; no timing")
@@ -458,7 +459,9 @@ def offset_fetch_main(args, np, torch, lg, g):
     off = torch.empty(k + 1, dtype=torch.int64, device=g.col.device)
     s = C.c_void_p(torch.cuda.current_stream().cuda_stream)
     res = {}
-    for name, kw in [("ptr32", dict(layout="plain")), ("bvPL", dict(ids="local", offsets="packed")),
+    # ptr32: plain 32-bit element offsets; ptrW: offsets at bl(universe) bits
+    # (logarithmized single offsets); bvSD: the Elias-Fano sparse bit vector
+    for name, kw in [("ptr32", dict(layout="plain")), ("ptrW", dict(ids="local", offsets="packed")),
                      ("bvSD", dict(ids="local", offsets="succinct"))]:
         h = lg.encode(g.row_offsets, g.col, n, **kw)
         info = h.info()
