@@ -130,3 +130,32 @@ def test_erdos_renyi26_packed_and_plain(lgmod):
     prp = lgmod.pagerank(hp, 0.85, 1).cpu().numpy().astype(np.float64)
     assert np.abs(prp - pr64).sum() <= 1e-5
     hp.free()
+
+
+def test_kronecker24_greedy_relabel(lgmod):
+    """The greedy relabeling at the benchmark's size: the whole permutation
+    against the oracle's literal loop, the widths and bit starts it implies,
+    and sampled rows of the packed lists."""
+    print("[fullsize] kronecker s24 greedy: generate", flush=True)
+    g = gg.kronecker(24, 16, seed=1, device="cuda")
+    off, col = host_csr(g)
+    n = g.n
+    print("[fullsize] kronecker s24 greedy: encode", flush=True)
+    h = lgmod.encode(g.row_offsets, g.col, n, ids="local", offsets="succinct", relabel="greedy")
+    info = h.info()
+    perm, inv = orc.greedy_permutation(off, col)
+    np.testing.assert_array_equal(h.export("perm"), perm)
+    np.testing.assert_array_equal(h.export("inv"), inv)
+    w, d2 = orc.relabeled_local_widths(off, col, perm, inv)
+    off2 = np.zeros(n + 1, dtype=np.uint64)
+    off2[1:] = np.cumsum(d2)
+    P = orc.bit_starts(off2, w, 0)
+    assert info["adj_bits"] == int(P[-1])
+    F = orc.width_field_bits(n)
+    W = h.export("widths")
+    np.testing.assert_array_equal(W, orc.pack_fixed(w.astype(np.uint64), F))
+    A = h.export("adj")
+    rng = np.random.default_rng(3)
+    rows = np.concatenate([np.arange(8), rng.integers(0, n, size=64)])
+    check_sampled_rows(A, P, W, F, 0, rows, lambda x: orc.relabel_row(off, col, perm, inv, int(x)))
+    h.free()
