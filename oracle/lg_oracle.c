@@ -179,6 +179,65 @@ ORC_API void orc_pack_adjacency_words(uint64_t n, const uint64_t *off, const uin
     }
 }
 
+/* Fixed-size gap encoding, local approach (subsection "Adding Fixed-Size Gap
+ * Encoding"): the differences between consecutive neighbors of A_v, all at
+ * the width of the largest difference in A_v.  Readings: the first element
+ * is stored as is, at the local width w_v of "The Local Approach"
+ * (max(1, bl(max N_v))); the gap width is g_v = bl(largest difference)
+ * (>= 1, the lists being strictly increasing) for d_v >= 2 and 0 for
+ * shorter lists; the list of v then takes w_v + (d_v - 1) g_v bits (0 when
+ * d_v = 0). */
+ORC_API void orc_gap_widths(uint64_t n, const uint64_t *off, const uint32_t *col, uint8_t *g) {
+    for (uint64_t v = 0; v < n; v++) {
+        uint32_t mx = 0;
+        for (uint64_t i = off[v] + 1; i < off[v + 1]; i++)
+            if (col[i] - col[i - 1] > mx) mx = col[i] - col[i - 1];
+        g[v] = (uint8_t)bitlen(mx);
+    }
+}
+
+ORC_API void orc_gap_bit_starts(uint64_t n, const uint64_t *off, const uint8_t *w, const uint8_t *g, uint64_t *P) {
+    uint64_t acc = 0;
+    for (uint64_t v = 0; v < n; v++) {
+        P[v] = acc;
+        const uint64_t d = off[v + 1] - off[v];
+        if (d) acc += w[v] + (d - 1) * (uint64_t)g[v];
+    }
+    P[n] = acc;
+}
+
+/* The gap stream: per list the first element at w_v bits, then each
+ * difference at g_v bits, LSB-first.  `words` holds orc_stream_words(U)
+ * zeroed words. */
+ORC_API void orc_pack_gap(uint64_t n, const uint64_t *off, const uint32_t *col, const uint8_t *w,
+                          const uint8_t *g, uint64_t *words) {
+    uint64_t pos = 0;
+    for (uint64_t v = 0; v < n; v++) {
+        for (uint64_t i = off[v]; i < off[v + 1]; i++) {
+            if (i == off[v]) {
+                put_bits(words, pos, col[i], w[v]);
+                pos += w[v];
+            } else {
+                put_bits(words, pos, col[i] - col[i - 1], g[v]);
+                pos += g[v];
+            }
+        }
+    }
+}
+
+/* A gap-encoded list of d elements starting at stream bit `start`: the
+ * first element, then running sums of the differences. */
+ORC_API void orc_decode_gap_list(const uint64_t *words, uint64_t start, uint64_t d, unsigned w, unsigned g,
+                                 uint32_t *out) {
+    if (d == 0) return;
+    uint32_t x = (uint32_t)orc_get_bits(words, start, w);
+    out[0] = x;
+    for (uint64_t i = 1; i < d; i++) {
+        x += (uint32_t)orc_get_bits(words, start + w + (i - 1) * g, g);
+        out[i] = x;
+    }
+}
+
 /* Element i of a list whose first element starts at stream bit `start`. */
 ORC_API void orc_decode_list(const uint64_t *words, uint64_t start, uint64_t d, unsigned w, uint32_t *out) {
     for (uint64_t i = 0; i < d; i++)

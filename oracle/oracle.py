@@ -72,6 +72,10 @@ def lib():
         "orc_dm_permutation": (None, [C.c_uint64, u64p, u32p, u32p]),
         "orc_relabel": (None, [C.c_uint64, u64p, u32p, u32p, u32p, u64p, u32p]),
         "orc_greedy_permutation": (None, [C.c_uint64, u64p, u32p, u32p, u32p]),
+        "orc_gap_widths": (None, [C.c_uint64, u64p, u32p, u8p]),
+        "orc_gap_bit_starts": (None, [C.c_uint64, u64p, u8p, u8p, u64p]),
+        "orc_pack_gap": (None, [C.c_uint64, u64p, u32p, u8p, u8p, u64p]),
+        "orc_decode_gap_list": (None, [u64p, C.c_uint64, C.c_uint64, C.c_uint, C.c_uint, u32p]),
         "orc_relabel_row": (None, [u64p, u32p, u32p, u32p, C.c_uint32, u32p]),
         "orc_bfs_labels": (C.c_int, [C.c_uint64, u64p, u32p, C.c_uint32, C.c_int32, _NullableU32,
                                      i32p, i32p]),
@@ -156,6 +160,38 @@ def pack_adjacency_words(off, col, k0: int, k1: int, widths=None, s: int = 0) ->
     out = np.zeros(max(k1 - k0, 1), dtype=np.uint64)
     lib().orc_pack_adjacency_words(n, off, col, widths, s, k0, k1, out)
     return out[: k1 - k0]
+
+
+def gap_widths(off, col) -> np.ndarray:
+    """g_v = bl(largest difference of consecutive neighbors) (0 when d_v < 2):
+    subsection "Adding Fixed-Size Gap Encoding", local approach."""
+    n, off, col = _csr(off, col)
+    g = np.zeros(max(n, 1), dtype=np.uint8)
+    lib().orc_gap_widths(n, off, col, g)
+    return g[:n]
+
+
+def gap_bit_starts(off, w, g) -> np.ndarray:
+    off = np.ascontiguousarray(off, dtype=np.uint64)
+    P = np.zeros(off.size, dtype=np.uint64)
+    lib().orc_gap_bit_starts(off.size - 1, off, np.ascontiguousarray(w, np.uint8),
+                             np.ascontiguousarray(g, np.uint8), P)
+    return P
+
+
+def pack_gap(off, col, w, g) -> np.ndarray:
+    n, off, col = _csr(off, col)
+    U = int(gap_bit_starts(off, w, g)[-1])
+    words = np.zeros(stream_words(U), dtype=np.uint64)
+    lib().orc_pack_gap(n, off, col, np.ascontiguousarray(w, np.uint8), np.ascontiguousarray(g, np.uint8), words)
+    return words
+
+
+def decode_gap_list(words, start: int, d: int, w: int, g: int) -> np.ndarray:
+    words = np.ascontiguousarray(words, dtype=np.uint64)
+    out = np.zeros(max(d, 1), dtype=np.uint32)
+    lib().orc_decode_gap_list(words, start, d, w, g, out)
+    return out[:d]
 
 
 def decode_list(words, start: int, d: int, w: int) -> np.ndarray:
@@ -281,8 +317,9 @@ def pagerank(off, col, alpha: float = 0.85, iters: int = 20) -> np.ndarray:
 class Encoding:
     """Every array of the packed representation, built by the oracle.
 
-    id_mode: "global" (every ID at s bits) or "local" (list v at w_v bits,
-    with a width table at F bits per vertex).  offset_mode: "packed"
+    id_mode: "global" (every ID at s bits), "local" (list v at w_v bits,
+    with a width table at F bits per vertex) or "local-gap" (first element at
+    w_v bits, the differences at g_v bits, both tables at F bits).  offset_mode: "packed"
     (fixed-width offsets) or "ef" (Elias-Fano with rank/select directory).
     The offset values are element offsets O[v] in global mode (bit start =
     s * O[v]) and bit starts P_v in local mode.  relabel: False, True or
@@ -303,12 +340,24 @@ class Encoding:
             self.perm = self.inv = None
         self.off, self.col = off, col
         self.s = global_width(n)
+        self.gwidths = None
         if id_mode == "global":
             self.widths = None
             self.U = adjacency_bits(off, None, self.s)
             self.A = pack_adjacency(off, col, None, self.s)
             vals = off
             universe = self.m
+        elif id_mode == "local-gap":
+            self.widths = local_widths(off, col)
+            self.gwidths = gap_widths(off, col)
+            self.F = width_field_bits(n)
+            self.W = pack_fixed(self.widths.astype(np.uint64), self.F)
+            self.G = pack_fixed(self.gwidths.astype(np.uint64), self.F)
+            P = gap_bit_starts(off, self.widths, self.gwidths)
+            self.U = int(P[-1])
+            self.A = pack_gap(off, col, self.widths, self.gwidths)
+            vals = P
+            universe = self.U
         else:
             self.widths = local_widths(off, col)
             self.F = width_field_bits(n)
@@ -317,7 +366,10 @@ class Encoding:
             self.A = pack_adjacency(off, col, self.widths, 0)
             vals = bit_starts(off, self.widths, 0)
             universe = self.U
-        self.P = bit_starts(off, self.widths, self.s if self.widths is None else 0)
+        if self.gwidths is None:
+            self.P = bit_starts(off, self.widths, self.s if self.widths is None else 0)
+        else:
+            self.P = vals
         self.offset_values = vals
         self.universe = universe
         if offset_mode == "packed":
@@ -331,4 +383,6 @@ class Encoding:
         """Stored list of stored label x, decoded bit by bit."""
         w = self.s if self.widths is None else int(self.widths[x])
         d = int(self.off[x + 1] - self.off[x])
+        if self.gwidths is not None:
+            return decode_gap_list(self.A, int(self.P[x]), d, w, int(self.gwidths[x]))
         return decode_list(self.A, int(self.P[x]), d, w)
