@@ -59,6 +59,14 @@ typedef enum lg_status {
 #define LG_IDS_GLOBAL 0u /* every ID at s = ceil(log2 n) bits (max(1, bl(n-1)))   */
 #define LG_IDS_LOCAL 1u  /* list of v at w_v = max(1, bl(max N_v)) bits, 0 when
                             empty; w_v kept in a table of F = bl(s) bits/vertex  */
+/* subsection "Adding Fixed-Size Gap Encoding", local approach: the first
+ * element of the list of v at w_v bits (as LG_IDS_LOCAL), every difference
+ * of consecutive neighbors at g_v = bl(largest difference) bits (0 when
+ * d_v < 2), kept in a second table of F bits/vertex; the list takes
+ * w_v + (d_v - 1) g_v bits.  Such graphs are read by lg_decode_neighbors
+ * (a prefix sum per list); lg_bfs, lg_pagerank, batch plans and servers
+ * return LG_ERR_UNSUPPORTED for them. */
+#define LG_IDS_LOCAL_GAP 2u
 /* lg_encode_opts.offset_mode -- sections "Logarithmization of Single Offsets"
  * and "Logarithmizing Offsets" */
 #define LG_OFFS_PACKED 0u   /* offsets packed at bl(universe) bits each          */
@@ -324,7 +332,7 @@ typedef struct lg_graph_info {
     uint64_t ef_high_bits; /* |H| in bits (succinct offsets)                     */
     uint64_t bytes_adj;    /* bytes of the neighbor data (packed words / uint32) */
     uint64_t bytes_offsets;/* bytes of the offset structure incl. directory      */
-    uint64_t bytes_widths; /* bytes of the width table                           */
+    uint64_t bytes_widths; /* bytes of the width table(s) (both in gap mode)     */
     uint64_t bytes_perm;   /* bytes of the two permutation arrays                */
     uint64_t device_bytes; /* all device memory held by the handle now           */
     uint32_t max_degree;
@@ -350,6 +358,7 @@ lg_status lg_info(const lg_graph *g, lg_graph_info *out);
 #define LG_EXPORT_EF_SELECT 6u /* uint32 select1(64 j), j < ceil((n+1)/64)        */
 #define LG_EXPORT_PERM 7u      /* uint32 perm[new] = original                     */
 #define LG_EXPORT_INV 8u       /* uint32 inv[original] = new                      */
+#define LG_EXPORT_GAP_WIDTHS 9u /* gap-width-table words (uint64), gap mode       */
 
 /*
  * Copy one raw array of the representation to host memory (synchronous).

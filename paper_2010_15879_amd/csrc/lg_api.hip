@@ -225,6 +225,7 @@ lg::PackedView lg_graph::packed_view() const {
     lg::PackedView v;
     v.A32 = A.as<uint32_t>();
     v.W = W.as<uint64_t>();
+    v.G = G.as<uint64_t>();
     v.s = s;
     v.F = F;
     v.po.O = O.as<uint64_t>();
@@ -248,7 +249,7 @@ lg::PlainView lg_graph::plain_view() const {
 }
 
 uint64_t lg_graph::device_bytes() const {
-    uint64_t b = A.bytes + O.bytes + W.bytes + L.bytes + H.bytes + rank_sb.bytes + sel.bytes + poff.bytes +
+    uint64_t b = A.bytes + O.bytes + W.bytes + G.bytes + L.bytes + H.bytes + rank_sb.bytes + sel.bytes + poff.bytes +
                  pcol.bytes + perm.bytes + inv.bytes + heavy.bytes + iso.bytes + hstart.bytes + hdeg.bytes + hw.bytes +
                  seg_off.bytes + seg_map.bytes + seg_part.bytes + units.bytes + (dec ? dec->bytes() : 0);
     return b;
@@ -299,7 +300,7 @@ extern "C" lg_status lg_info(const lg_graph *g, lg_graph_info *out) {
         out->bytes_offsets = g->offset_mode == LG_OFFS_PACKED
                                  ? g->O_words * 8
                                  : g->L_words * 8 + g->H_words * 8 + g->n_rank * 4 + g->n_sel * 4;
-        out->bytes_widths = g->W_words * 8;
+        out->bytes_widths = (g->W_words + g->G_words) * 8;
     }
     out->bytes_perm = g->perm.bytes + g->inv.bytes;
     out->device_bytes = g->device_bytes() + lg::bfs_bytes(g) + lg::pr_bytes(g);
@@ -324,8 +325,12 @@ static bool export_src(const lg_graph *g, uint32_t which, const void **p, uint64
             }
             return true;
         case LG_EXPORT_WIDTHS:
-            if (!packed || g->id_mode != LG_IDS_LOCAL) return false;
+            if (!packed || g->id_mode == LG_IDS_GLOBAL) return false;
             *p = g->W.p; *bytes = g->W_words * 8;
+            return true;
+        case LG_EXPORT_GAP_WIDTHS:
+            if (!packed || g->id_mode != LG_IDS_LOCAL_GAP) return false;
+            *p = g->G.p; *bytes = g->G_words * 8;
             return true;
         case LG_EXPORT_EF_LOW:
         case LG_EXPORT_EF_HIGH:

@@ -26,23 +26,58 @@ __global__ void dec_degree_kernel(Acc acc, const uint32_t *__restrict__ labels, 
         deg[i] = acc.info(labels[i]).deg;
 }
 
+template <class Acc>
+struct IsGapAcc {
+    static constexpr bool value = false;
+};
+template <int OFM>
+struct IsGapAcc<GapAcc<OFM>> {
+    static constexpr bool value = true;
+};
+
 // kSorted: emit ((i << 32) | original ID) keys for the segmented sort
 template <class Acc, bool kSorted>
-__global__ void dec_lists_kernel(Acc acc, const uint32_t *__restrict__ labels, uint32_t k,
+__global__ void dec_lists_kernel(Acc acc, uint32_t n, const uint32_t *__restrict__ labels, uint32_t k,
                                  const uint64_t *__restrict__ out_off, const uint32_t *__restrict__ perm,
                                  uint32_t *__restrict__ out_ids, uint64_t *__restrict__ keys) {
     const uint32_t lane = lane_id();
     const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
     const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) / kWave;
-    for (uint64_t i = wave; i < k; i += nwaves) {
-        const VInfo vi = acc.info(labels[i]);
-        const uint64_t o = out_off[i];
-        const uint32_t st = Acc::step(vi.w), mk = Acc::mask(vi.w);
-        for (uint64_t j = lane; j < vi.deg; j += kWave) {
-            uint32_t u = acc.get(vi.start + j * st, mk);
-            if (perm) u = perm[u];
-            if (kSorted) keys[o + j] = (i << 32) | u;
-            else out_ids[o + j] = u;
+    if constexpr (IsGapAcc<Acc>::value) {
+        // gap lists: element j is the first element plus the differences
+        // 1..j; 64 at a time, a wave prefix sum plus the running total of the
+        // steps before (lanes past the end read the first element and drop it)
+        for (uint64_t i = wave; i < k; i += nwaves) {
+            const GapInfo gi = acc.info(labels[i]);
+            const uint64_t o = out_off[i];
+            uint32_t carry = 0;
+            for (uint64_t j0 = 0; j0 < gi.deg; j0 += kWave) {
+                const uint64_t j = j0 + lane;
+                const bool valid = j < gi.deg;
+                const uint64_t jj = valid ? j : 0;
+                const uint32_t x = acc.get(Acc::entry_bit(gi, jj), jj ? gi.g : gi.w);
+                const uint32_t val = wave_incl_scan(valid ? x : 0u) + carry;
+                carry = __shfl(val, kWave - 1, kWave);
+                if (valid) {
+                    // a stored label is < n; the clamp keeps the lookup in
+                    // bounds whatever the stream holds
+                    const uint32_t u = perm ? perm[val < n ? val : n - 1] : val;
+                    if (kSorted) keys[o + j] = (i << 32) | u;
+                    else out_ids[o + j] = u;
+                }
+            }
+        }
+    } else {
+        for (uint64_t i = wave; i < k; i += nwaves) {
+            const VInfo vi = acc.info(labels[i]);
+            const uint64_t o = out_off[i];
+            const uint32_t st = Acc::step(vi.w), mk = Acc::mask(vi.w);
+            for (uint64_t j = lane; j < vi.deg; j += kWave) {
+                uint32_t u = acc.get(vi.start + j * st, mk);
+                if (perm) u = perm[u];
+                if (kSorted) keys[o + j] = (i << 32) | u;
+                else out_ids[o + j] = u;
+            }
         }
     }
 }
@@ -59,6 +94,17 @@ DecodeWork::~DecodeWork() {
 
 uint64_t DecodeWork::bytes() const {
     return head.bytes + scan_tmp.bytes + keys.bytes + keys2.bytes + vals.bytes + vals2.bytes + sort_tmp.bytes;
+}
+
+// dispatch_acc plus the gap accessors, which only this in-order decode takes
+template <class Fn>
+static lg_status decode_dispatch(const lg_graph *g, Fn &&fn) {
+    if (g->layout == LG_LAYOUT_PACKED && g->id_mode == LG_IDS_LOCAL_GAP) {
+        const PackedView pv = g->packed_view();
+        if (g->offset_mode == LG_OFFS_PACKED) return fn(GapAcc<kOffsPacked>{PackedAcc<kIdsLocal, kOffsPacked>{pv}});
+        return fn(GapAcc<kOffsEF>{PackedAcc<kIdsLocal, kOffsEF>{pv}});
+    }
+    return dispatch_acc(g, fn);
 }
 
 lg_status decode_run(lg_graph *g, DecodeWork &w, const uint32_t *vertices, uint32_t k, uint64_t *out_off,
@@ -85,7 +131,7 @@ lg_status decode_run(lg_graph *g, DecodeWork &w, const uint32_t *vertices, uint3
     LG_TRY(fill_u32(bad, 0, 1, stream));
     LG_LAUNCH(dec_map_kernel, grid_for(k, 256, 1u << 16), 256, 0, stream, g->n, vertices, k, inv, labels, bad);
     LG_CHECK_LAUNCH();
-    return dispatch_acc(g, [&](auto acc) -> lg_status {
+    return decode_dispatch(g, [&](auto acc) -> lg_status {
         using Acc = decltype(acc);
         LG_LAUNCH(dec_degree_kernel<Acc>, grid_for(k, 256, 1u << 16), 256, 0, stream, acc, labels, k, deg);
         LG_CHECK_LAUNCH();
@@ -107,8 +153,8 @@ lg_status decode_run(lg_graph *g, DecodeWork &w, const uint32_t *vertices, uint3
         if (total == 0) return LG_OK;
         const uint32_t grid = grid_for((uint64_t)k * kWave, 256, 1u << 16);
         if (!sorted) {
-            LG_LAUNCH((dec_lists_kernel<Acc, false>), grid, 256, 0, stream, acc, labels, k, (const uint64_t *)out_off,
-                      perm, out_ids, (uint64_t *)nullptr);
+            LG_LAUNCH((dec_lists_kernel<Acc, false>), grid, 256, 0, stream, acc, g->n, labels, k,
+                      (const uint64_t *)out_off, perm, out_ids, (uint64_t *)nullptr);
             LG_CHECK_LAUNCH();
             return LG_OK;
         }
@@ -116,8 +162,8 @@ lg_status decode_run(lg_graph *g, DecodeWork &w, const uint32_t *vertices, uint3
         LG_TRY(w.keys2.ensure(total * 8));
         LG_TRY(w.vals.ensure(total * 4));
         LG_TRY(w.vals2.ensure(total * 4));
-        LG_LAUNCH((dec_lists_kernel<Acc, true>), grid, 256, 0, stream, acc, labels, k, (const uint64_t *)out_off, perm,
-                  out_ids, w.keys.as<uint64_t>());
+        LG_LAUNCH((dec_lists_kernel<Acc, true>), grid, 256, 0, stream, acc, g->n, labels, k,
+                  (const uint64_t *)out_off, perm, out_ids, w.keys.as<uint64_t>());
         LG_CHECK_LAUNCH();
         const uint32_t bits = 32 + bitlen_u64(k - 1);
         LG_TRY(radix_sort_pairs64(w.keys.as<uint64_t>(), w.vals.as<uint32_t>(), w.keys2.as<uint64_t>(),

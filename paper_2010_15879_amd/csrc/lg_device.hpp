@@ -239,9 +239,11 @@ struct PackedAcc {
         }
         return r;
     }
-    __device__ __forceinline__ VInfo info(uint32_t v) const {
+    // the two offset values bracketing the list of v
+    __device__ __forceinline__ void offsets(uint32_t v, uint64_t &o0, uint64_t &o1) const {
         if constexpr (OFM == kOffsPacked) {
-            return make(v, offset_value(v), offset_value(v + 1));
+            o0 = offset_value(v);
+            o1 = offset_value(v + 1);
         } else {
             // x_{v+1}'s upper bit is the next one of H after x_v's
             const EFView &e = pv.ef;
@@ -249,8 +251,14 @@ struct PackedAcc {
             const uint64_t p1 = ef_next_one(e, p0);
             const uint64_t lo0 = e.l ? extract64(e.L, (uint64_t)v * e.l, e.l) : 0ull;
             const uint64_t lo1 = e.l ? extract64(e.L, (uint64_t)(v + 1) * e.l, e.l) : 0ull;
-            return make(v, ((p0 - v) << e.l) | lo0, ((p1 - v - 1) << e.l) | lo1);
+            o0 = ((p0 - v) << e.l) | lo0;
+            o1 = ((p1 - v - 1) << e.l) | lo1;
         }
+    }
+    __device__ __forceinline__ VInfo info(uint32_t v) const {
+        uint64_t o0, o1;
+        offsets(v, o0, o1);
+        return make(v, o0, o1);
     }
     // element at position `pos` (a bit position)
     __device__ __forceinline__ uint32_t get(uint64_t pos, uint32_t mask) const {
@@ -283,6 +291,46 @@ struct PlainAcc {
     __device__ __forceinline__ uint32_t get(uint64_t pos, uint32_t) const { return pv.col[pos]; }
     __device__ __forceinline__ static uint32_t step(uint32_t) { return 1; }
     __device__ __forceinline__ static uint32_t mask(uint32_t) { return 0xFFFFFFFFu; }
+};
+
+// Fixed-size gap encoding (subsection "Adding Fixed-Size Gap Encoding",
+// local approach): the list of v is its first element at w_v bits, then its
+// d_v - 1 differences at g_v bits.  The offsets are bit starts, as in the
+// local approach, so d_v follows from the list's bit length l:
+// 0 when l = 0, 1 when g_v = 0, else 1 + (l - w_v) / g_v.  Entries are read
+// in order only (a running sum); the traversal kernels, which read entries
+// at any position, do not take this accessor.
+struct GapInfo {
+    uint64_t start;
+    uint32_t deg;
+    uint32_t w;  // width of the first element
+    uint32_t g;  // width of every difference
+};
+
+template <int OFM>
+struct GapAcc {
+    PackedAcc<kIdsLocal, OFM> base;  // offsets, width table and stream
+
+    __device__ __forceinline__ uint32_t gap_width(uint32_t v) const {
+        return (uint32_t)extract64(base.pv.G, (uint64_t)v * base.pv.F, base.pv.F);
+    }
+    __device__ __forceinline__ GapInfo info(uint32_t v) const {
+        uint64_t o0, o1;
+        base.offsets(v, o0, o1);
+        GapInfo r;
+        r.start = o0;
+        r.w = base.width(v);
+        r.g = gap_width(v);
+        const uint64_t l = o1 - o0;
+        r.deg = l == 0 ? 0u : (r.g == 0 ? 1u : 1u + exact_div_width(l - r.w, r.g));
+        return r;
+    }
+    // bit position and width of entry i of a list (first element, then
+    // differences)
+    __device__ __forceinline__ static uint64_t entry_bit(const GapInfo &gi, uint64_t i) {
+        return i == 0 ? gi.start : gi.start + gi.w + (i - 1) * gi.g;
+    }
+    __device__ __forceinline__ uint32_t get(uint64_t bit, uint32_t w) const { return base.get(bit, width_mask(w)); }
 };
 
 // Upper-bit positions of ones number v0 + lane and v0 + 64 (broadcast) for a
@@ -414,6 +462,11 @@ lg_status dispatch_acc(const lg_graph *g, Fn &&fn) {
     if (g->layout == LG_LAYOUT_PLAIN) {
         if (g->poff64) return fn(PlainAcc<true>{g->plain_view()});
         return fn(PlainAcc<false>{g->plain_view()});
+    }
+    if (g->id_mode == LG_IDS_LOCAL_GAP) {
+        set_error("gap-encoded lists are read in order only: this operation is not available for them "
+                  "(lg_decode_neighbors is)");
+        return LG_ERR_UNSUPPORTED;
     }
     const PackedView pv = g->packed_view();
     if (g->id_mode == LG_IDS_GLOBAL) {

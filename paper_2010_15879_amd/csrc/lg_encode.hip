@@ -478,18 +478,32 @@ __global__ void pack_fixed_kernel(Src src, uint64_t count, uint32_t w, double in
 // atomically.
 constexpr int kPackBuf = 34;  // words one step can touch: 64 x 32 bits, misaligned, plus the carry
 
+// kGap: fixed-size gap encoding -- entry 0 of a list at w_v bits, entry i > 0
+// is its difference from entry i - 1, at g_v bits (gwid).
+template <bool kGap>
 __global__ void pack_walk_kernel(uint32_t n, const uint64_t *__restrict__ off, const uint32_t *__restrict__ col,
-                                 const uint8_t *__restrict__ wid, const uint64_t *__restrict__ P, uint64_t items,
-                                 const uint32_t *__restrict__ map, const uint64_t *__restrict__ coff,
-                                 unsigned long long *__restrict__ out) {
+                                 const uint8_t *__restrict__ wid, const uint8_t *__restrict__ gwid,
+                                 const uint64_t *__restrict__ P, uint64_t items, const uint32_t *__restrict__ map,
+                                 const uint64_t *__restrict__ coff, unsigned long long *__restrict__ out) {
     __shared__ uint64_t s_rs[4][kWave + 1];
     __shared__ uint64_t s_p[4][kWave];
     __shared__ uint32_t s_w[4][kWave];
+    __shared__ uint32_t s_g[4][kWave];
     __shared__ unsigned long long s_buf[4][kPackBuf];
     const uint32_t wv = threadIdx.x / kWave;
     const uint32_t lane = lane_id();
     const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
     const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) / kWave;
+    // bit position and width of entry i of row r of this wave's block
+    auto place = [&](uint32_t r, uint64_t i, uint64_t &bit, uint32_t &width) {
+        if (kGap) {
+            bit = s_p[wv][r] + (i == 0 ? 0ull : s_w[wv][r] + (i - 1) * s_g[wv][r]);
+            width = i == 0 ? s_w[wv][r] : s_g[wv][r];
+        } else {
+            bit = s_p[wv][r] + i * s_w[wv][r];
+            width = s_w[wv][r];
+        }
+    };
     for (uint64_t k = wave; k < items; k += nwaves) {
         const uint64_t q = map[k];
         const uint64_t v0 = q * 64;
@@ -499,6 +513,7 @@ __global__ void pack_walk_kernel(uint32_t n, const uint64_t *__restrict__ off, c
         if (lane == 0) s_rs[wv][64] = E1;
         s_p[wv][lane] = v0 + lane < n ? P[v0 + lane] : 0ull;
         s_w[wv][lane] = v0 + lane < n ? wid[v0 + lane] : 0u;
+        s_g[wv][lane] = kGap && v0 + lane < n ? gwid[v0 + lane] : 0u;
         wave_lds_sync();
         const uint64_t eb = __shfl(o, 0, kWave) + (k - coff[q]) * kWalkChunk;
         const uint64_t ee = eb + kWalkChunk < E1 ? eb + kWalkChunk : E1;
@@ -507,7 +522,10 @@ __global__ void pack_walk_kernel(uint32_t n, const uint64_t *__restrict__ off, c
 #pragma unroll
             for (uint32_t step = 32; step > 0; step >>= 1)
                 if (s_rs[wv][j + step] <= eb) j += step;
-            const uint64_t first_word = (s_p[wv][j] + (eb - s_rs[wv][j]) * s_w[wv][j]) >> 6;
+            uint64_t fb;
+            uint32_t fw;
+            place(j, eb - s_rs[wv][j], fb, fw);
+            const uint64_t first_word = fb >> 6;
             bool open = false;  // a word of the previous step is still being filled
             unsigned long long carry = 0;
             uint64_t carry_word = 0;
@@ -516,7 +534,7 @@ __global__ void pack_walk_kernel(uint32_t n, const uint64_t *__restrict__ off, c
                 uint64_t e[kSteps];
                 uint32_t row[kSteps];
                 bool valid[kSteps];
-                uint32_t x[kSteps];
+                uint32_t x[kSteps], xp[kSteps];
 #pragma unroll
                 for (int r = 0; r < kSteps; ++r) {
                     e[r] = base + (uint64_t)r * kWave + lane;
@@ -526,13 +544,23 @@ __global__ void pack_walk_kernel(uint32_t n, const uint64_t *__restrict__ off, c
                     row[r] = j;
                 }
 #pragma unroll
-                for (int r = 0; r < kSteps; ++r) x[r] = col[valid[r] ? e[r] : 0];
+                for (int r = 0; r < kSteps; ++r) {
+                    x[r] = col[valid[r] ? e[r] : 0];
+                    // the entry before (same row when it is not the row's first)
+                    xp[r] = kGap ? col[valid[r] && e[r] > 0 ? e[r] - 1 : 0] : 0u;
+                }
 #pragma unroll
                 for (int r = 0; r < kSteps; ++r) {
                     const uint64_t sb = base + (uint64_t)r * kWave;
                     if (sb >= ee) break;  // same for every lane
-                    const uint32_t ww = valid[r] ? s_w[wv][row[r]] : 0u;
-                    const uint64_t b = valid[r] ? s_p[wv][row[r]] + (e[r] - s_rs[wv][row[r]]) * ww : 0ull;
+                    uint64_t b = 0;
+                    uint32_t ww = 0;
+                    uint32_t val = 0;
+                    if (valid[r]) {
+                        const uint64_t i = e[r] - s_rs[wv][row[r]];
+                        place(row[r], i, b, ww);
+                        val = (kGap && i > 0) ? x[r] - xp[r] : x[r];
+                    }
                     const uint32_t last = (uint32_t)(ee - sb < kWave ? ee - sb : kWave) - 1;
                     const uint64_t b_first = __shfl(b, 0, kWave);
                     const uint64_t b_end = __shfl(b + ww, last, kWave);
@@ -544,8 +572,8 @@ __global__ void pack_walk_kernel(uint32_t n, const uint64_t *__restrict__ off, c
                     if (valid[r]) {
                         const uint32_t sh = (uint32_t)(b & 63);
                         const uint32_t idx = (uint32_t)((b >> 6) - kw0);
-                        atomicOr(&s_buf[wv][idx], (unsigned long long)x[r] << sh);
-                        if (sh + ww > 64) atomicOr(&s_buf[wv][idx + 1], (unsigned long long)x[r] >> (64 - sh));
+                        atomicOr(&s_buf[wv][idx], (unsigned long long)val << sh);
+                        if (sh + ww > 64) atomicOr(&s_buf[wv][idx + 1], (unsigned long long)val >> (64 - sh));
                     }
                     wave_lds_sync();
                     open = (b_end & 63) != 0;
@@ -563,6 +591,47 @@ __global__ void pack_walk_kernel(uint32_t n, const uint64_t *__restrict__ off, c
             if (open && lane == 0) atomicOr(&out[carry_word], carry);
         }
         wave_lds_sync();
+    }
+}
+
+// g_v = bl(largest difference of consecutive entries of list v): a walk over
+// the lists, per-row maxima in LDS, one global atomic per row and piece
+// (gmax starts at 0)
+__global__ void gap_max_kernel(uint32_t n, const uint64_t *__restrict__ off, const uint32_t *__restrict__ col,
+                               uint64_t items, const uint32_t *__restrict__ map, const uint64_t *__restrict__ coff,
+                               uint32_t *__restrict__ gmax) {
+    __shared__ uint64_t s_rs[4][kWave + 1];
+    __shared__ uint32_t s_max[4][kWave];
+    const uint32_t wv = threadIdx.x / kWave;
+    const uint32_t lane = lane_id();
+    const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) / kWave;
+    for (uint64_t k = wave; k < items; k += nwaves) {
+        const uint64_t v0 = (uint64_t)map[k] * 64;
+        s_max[wv][lane] = 0;
+        auto load = [&](uint64_t e, uint32_t, bool valid) {
+            return make_uint2(col[valid ? e : 0], col[valid && e > 0 ? e - 1 : 0]);
+        };
+        walk_item(n, off, map, coff, k, s_rs[wv], load, [&](uint64_t e, uint32_t j, bool valid, uint2 x) {
+            if (valid && e > s_rs[wv][j]) atomicMax(&s_max[wv][j], x.x - x.y);
+        });
+        if (v0 + lane < n && s_max[wv][lane]) atomicMax(&gmax[v0 + lane], s_max[wv][lane]);
+        wave_lds_sync();
+    }
+}
+
+// gap widths g_v = bl(gmax_v) and list bit lengths w_v + (d_v - 1) g_v (0 when
+// the list is empty)
+__global__ void gap_len_kernel(uint32_t n, const uint64_t *__restrict__ off, const uint8_t *__restrict__ w8,
+                               const uint32_t *__restrict__ gmax, uint8_t *__restrict__ g8,
+                               uint64_t *__restrict__ len) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) {
+        const uint64_t d = off[v + 1] - off[v];
+        const uint32_t gm = gmax[v];
+        const uint32_t g = gm ? 32u - (uint32_t)__clz(gm) : 0u;
+        g8[v] = (uint8_t)g;
+        len[v] = d ? (uint64_t)w8[v] + (d - 1) * (uint64_t)g : 0ull;
     }
 }
 
@@ -963,17 +1032,39 @@ static lg_status encode_impl(uint32_t n, uint64_t m, const uint64_t *row_offsets
         LG_LAUNCH(local_width_kernel, grid1(n), 256, 0, s, n, cur_off, cur_col, w8.as<uint8_t>(),
                   len.as<uint64_t>());
         LG_CHECK_LAUNCH();
+        WalkTable wp;
+        LG_TRY(walk_table(n, cur_off, wp, tmp, s));
+        const bool gap = o.id_mode == LG_IDS_LOCAL_GAP;
+        DevBuf g8, gmax;
+        if (gap) {  // gap widths, and bit lengths w_v + (d_v - 1) g_v
+            LG_TRY(g8.scratch((uint64_t)n, s));
+            LG_TRY(gmax.scratch((uint64_t)n * 4, s));
+            LG_TRY(fill_u32(gmax.as<uint32_t>(), 0, n, s));
+            if (m) {
+                LG_LAUNCH(gap_max_kernel, wp.grid, 256, 0, s, n, cur_off, cur_col, wp.items, wp.map.as<uint32_t>(),
+                          wp.coff.as<uint64_t>(), gmax.as<uint32_t>());
+                LG_CHECK_LAUNCH();
+            }
+            LG_LAUNCH(gap_len_kernel, grid1(n), 256, 0, s, n, cur_off, w8.as<uint8_t>(), gmax.as<uint32_t>(),
+                      g8.as<uint8_t>(), len.as<uint64_t>());
+            LG_CHECK_LAUNCH();
+        }
         LG_TRY(exclusive_scan_u64(len.as<uint64_t>(), P.as<uint64_t>(), n, tmp, s));
         LG_CHECK_HIP(hipMemcpyAsync(&g->U, P.as<uint64_t>() + n, 8, hipMemcpyDeviceToHost, s));
         LG_CHECK_HIP(hipStreamSynchronize(s));
         LG_TRY(pack_fixed(SrcU8{w8.as<uint8_t>()}, n, g->F, g->W, g->W_words, s));
+        if (gap) LG_TRY(pack_fixed(SrcU8{g8.as<uint8_t>()}, n, g->F, g->G, g->G_words, s));
         g->A_words = (g->U + 63) / 64 + 1;
         LG_TRY(g->A.scratch(g->A_words * 8, s));
         LG_TRY(fill_u64(g->A.as<uint64_t>(), 0, g->A_words, s));
-        WalkTable wp;
-        LG_TRY(walk_table(n, cur_off, wp, tmp, s));
-        LG_LAUNCH(pack_walk_kernel, wp.grid, 256, 0, s, n, cur_off, cur_col, w8.as<uint8_t>(), P.as<uint64_t>(),
-                  wp.items, wp.map.as<uint32_t>(), wp.coff.as<uint64_t>(), g->A.as<unsigned long long>());
+        if (gap)
+            LG_LAUNCH((pack_walk_kernel<true>), wp.grid, 256, 0, s, n, cur_off, cur_col, w8.as<uint8_t>(),
+                      g8.as<uint8_t>(), P.as<uint64_t>(), wp.items, wp.map.as<uint32_t>(), wp.coff.as<uint64_t>(),
+                      g->A.as<unsigned long long>());
+        else
+            LG_LAUNCH((pack_walk_kernel<false>), wp.grid, 256, 0, s, n, cur_off, cur_col, w8.as<uint8_t>(),
+                      (const uint8_t *)nullptr, P.as<uint64_t>(), wp.items, wp.map.as<uint32_t>(),
+                      wp.coff.as<uint64_t>(), g->A.as<unsigned long long>());
         LG_CHECK_LAUNCH();
         LG_TRY(build_offsets(g, P.as<uint64_t>(), g->U, tmp, s));
         LG_CHECK_HIP(hipStreamSynchronize(s));
@@ -995,7 +1086,7 @@ extern "C" lg_status lg_encode(uint32_t n, uint64_t m, const uint64_t *row_offse
     if (n == 0 || n >= (1u << 31)) { set_error("lg_encode: n must be in [1, 2^31)"); return LG_ERR_INVALID; }
     if (m >= (1ull << 36)) { set_error("lg_encode: m must be below 2^36"); return LG_ERR_UNSUPPORTED; }
     if (!row_offsets || (m && !col)) { set_error("lg_encode: NULL input array"); return LG_ERR_INVALID; }
-    if (o.layout > LG_LAYOUT_PLAIN || o.id_mode > LG_IDS_LOCAL || o.offset_mode > LG_OFFS_SUCCINCT ||
+    if (o.layout > LG_LAYOUT_PLAIN || o.id_mode > LG_IDS_LOCAL_GAP || o.offset_mode > LG_OFFS_SUCCINCT ||
         o.relabel > LG_RELABEL_GREEDY || o.flags || o.reserved[0] || o.reserved[1] || o.reserved[2]) {
         set_error("lg_encode: unknown option value");
         return LG_ERR_INVALID;

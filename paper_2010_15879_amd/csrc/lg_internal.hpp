@@ -143,8 +143,8 @@ struct lg_graph {
     // packed layout
     uint32_t s = 0, F = 0, wO = 0, ef_l = 0;
     uint64_t U = 0, universe = 0, hbits = 0;
-    lg::DevBuf A, O, W, L, H, rank_sb, sel;
-    uint64_t A_words = 0, O_words = 0, W_words = 0, L_words = 0, H_words = 0, n_rank = 0, n_sel = 0;
+    lg::DevBuf A, O, W, G, L, H, rank_sb, sel;  // G: gap-width table (gap mode)
+    uint64_t A_words = 0, O_words = 0, W_words = 0, G_words = 0, L_words = 0, H_words = 0, n_rank = 0, n_sel = 0;
 
     // plain layout
     lg::DevBuf poff, pcol;

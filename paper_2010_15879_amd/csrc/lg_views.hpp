@@ -26,7 +26,8 @@ struct POffView {
 
 struct PackedView {
     const uint32_t *A32;      // packed lists viewed as 32-bit words
-    const uint64_t *W;        // width table (local mode)
+    const uint64_t *W;        // width table (local modes)
+    const uint64_t *G;        // gap-width table (gap mode)
     uint32_t s;               // global width
     uint32_t F;               // width field bits
     POffView po;

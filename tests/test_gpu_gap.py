@@ -1,0 +1,115 @@
+"""Fixed-size gap encoding on the GPU (subsection "Adding Fixed-Size Gap
+Encoding", local approach): every array bit-exact against the oracle, lists
+decoded against the input, and the traversals refusing such graphs."""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as orc
+from paper_2010_15879_amd import graphgen as gg
+from test_gpu_parity import GRAPHS
+
+pytestmark = pytest.mark.gpu
+
+GAP = [
+    dict(layout="packed", ids="local-gap", offsets="packed", relabel=False),
+    dict(layout="packed", ids="local-gap", offsets="succinct", relabel=False),
+    dict(layout="packed", ids="local-gap", offsets="succinct", relabel=True),
+]
+
+
+def gid(e):
+    return f"{e['offsets']}-{'rl' if e['relabel'] else 'id'}"
+
+
+@pytest.fixture(scope="module")
+def lgmod():
+    from paper_2010_15879_amd import lg
+    lg.lib()
+    return lg
+
+
+def encode(lgmod, g, e):
+    d = g.to("cuda")
+    return lgmod.encode(d.row_offsets, d.col, g.n, **e)
+
+
+@pytest.mark.parametrize("e", GAP, ids=gid)
+@pytest.mark.parametrize("name", list(GRAPHS))
+def test_gap_encoding_bit_exact(lgmod, name, e):
+    g = GRAPHS[name]
+    print(f"[gap encode] {name} {gid(e)}", flush=True)
+    h = encode(lgmod, g, e)
+    off, col = g.numpy()
+    o = orc.Encoding(off, col, "local-gap", "ef" if e["offsets"] == "succinct" else "packed", e["relabel"])
+    info = h.info()
+    assert info["adj_bits"] == o.U
+    np.testing.assert_array_equal(h.export("adj"), o.A)
+    np.testing.assert_array_equal(h.export("widths"), o.W)
+    np.testing.assert_array_equal(h.export("gap_widths"), o.G)
+    if o.ef is None:
+        np.testing.assert_array_equal(h.export("offsets"), o.O)
+    else:
+        np.testing.assert_array_equal(h.export("ef_low"), o.ef.low)
+        np.testing.assert_array_equal(h.export("ef_high"), o.ef.high)
+        np.testing.assert_array_equal(h.export("ef_select"), o.ef.sel)
+    if e["relabel"]:
+        np.testing.assert_array_equal(h.export("perm"), o.perm)
+    h.free()
+
+
+@pytest.mark.parametrize("e", GAP, ids=gid)
+@pytest.mark.parametrize("name", ["megastar", "offhub", "kron12", "er12", "star33", "single", "isolated7",
+                                  "bigstar", "rand129"])
+def test_gap_decode(lgmod, name, e):
+    """Lists longer than 64 entries take several prefix-sum steps."""
+    g = GRAPHS[name]
+    print(f"[gap decode] {name} {gid(e)}", flush=True)
+    h = encode(lgmod, g, e)
+    off, col = g.numpy()
+    rng = np.random.default_rng(11)
+    vs = np.unique(np.concatenate([rng.integers(0, g.n, size=min(g.n, 300)), [0, 1, g.n - 1]])).astype(np.int32)
+    vs = vs[vs < g.n]
+    vt = torch.from_numpy(vs).cuda()
+    for flags in ["sorted", "original"]:
+        o_off, o_ids = lgmod.decode_neighbors(h, vt, flags)
+        o_off, o_ids = o_off.cpu().numpy(), o_ids.cpu().numpy()
+        for i, v in enumerate(vs):
+            got = o_ids[o_off[i]:o_off[i + 1]]
+            np.testing.assert_array_equal(np.sort(got) if flags == "original" else got, col[off[v]:off[v + 1]])
+    if e["relabel"]:
+        perm, inv = orc.dm_permutation(off)
+        r_off, r_ids = lgmod.decode_neighbors(h, vt, "raw")
+        r_off, r_ids = r_off.cpu().numpy(), r_ids.cpu().numpy()
+        for i, x in enumerate(vs):
+            np.testing.assert_array_equal(r_ids[r_off[i]:r_off[i + 1]], orc.relabel_row(off, col, perm, inv, int(x)))
+    h.free()
+
+
+def test_gap_traversals_unsupported(lgmod):
+    from paper_2010_15879_amd.lg import LGError, LG_ERR_UNSUPPORTED
+    g = GRAPHS["kron12"]
+    h = encode(lgmod, g, GAP[1])
+    root = gg.pick_roots(g, 1, seed=1)
+    with pytest.raises(LGError) as ei:
+        lgmod.bfs(h, root)
+    assert ei.value.status == LG_ERR_UNSUPPORTED
+    with pytest.raises(LGError) as ei:
+        lgmod.pagerank(h, 0.85, 2)
+    assert ei.value.status == LG_ERR_UNSUPPORTED
+    h.free()
+
+
+def test_gap_kronecker16_smaller(lgmod):
+    """Scale 16, degree-minimizing relabel: the gap lists are bit-exact and
+    no larger than the local-width lists."""
+    g = gg.kronecker(16, 16, seed=1)
+    h = encode(lgmod, g, GAP[2])
+    hl = encode(lgmod, g, dict(layout="packed", ids="local", offsets="succinct", relabel=True))
+    off, col = g.numpy()
+    o = orc.Encoding(off, col, "local-gap", "ef", True)
+    np.testing.assert_array_equal(h.export("adj"), o.A)
+    assert h.info()["adj_bits"] <= hl.info()["adj_bits"]
+    h.free()
+    hl.free()
