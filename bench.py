@@ -95,6 +95,9 @@ def parse():
                         "offsets (ptr32), offsets at bl(universe) bits (ptrW) and Elias-Fano offsets (bvSD): "
                         "degrees only and whole lists "
                         "(own JSON line)")
+    p.add_argument("--gap-compare", action="store_true",
+                   help="the workload's graph with local widths vs fixed-size gap encoding (with and without the "
+                        "degree-minimizing relabeling): |A|, encode time, random-vertex list decode (own JSON line)")
     p.add_argument("--pr-only", action="store_true",
                    help="counter-run mode: one 1 GiB device copy (calibration) then one PageRank call; no timing")
     return p.parse_args()
@@ -137,6 +140,8 @@ def main():
         return relabel_main(args, np, torch, lg, g, roots)
     if args.offset_fetch:
         return offset_fetch_main(args, np, torch, lg, g)
+    if args.gap_compare:
+        return gap_main(args, np, torch, lg, g)
 
     if args.pr_only:
         # A kernel of known traffic calibrates the HBM byte counters (an
@@ -486,6 +491,54 @@ def offset_fetch_main(args, np, torch, lg, g):
         log(f"[offsets] {name}: {res[name]}")
         h.free()
     print(json.dumps({"mode": "offset-fetch", "workload": args.workload, "n": n, "stored_edges": g.m,
+                      "vertices_per_call": k, "data": "synthetic", "results": res}), flush=True)
+
+
+def gap_main(args, np, torch, lg, g):
+    """Local widths (LG-l) vs fixed-size gap encoding (LG-l-gap), Elias-Fano
+    offsets, without and with the degree-minimizing relabeling: bytes of the
+    lists |A| and of the width tables, encode time, and the decode of the
+    lists of 256,000 random vertices (one call, stored labels)."""
+    import ctypes as C
+    n = g.n
+    k = 1000 * 256
+    rng = np.random.default_rng(7)
+    vt = torch.from_numpy(rng.integers(0, n, size=k).astype(np.int32)).to(g.col.device)
+    off = torch.empty(k + 1, dtype=torch.int64, device=g.col.device)
+    s = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    res = {}
+    for rl in (False, True):
+        for ids in ("local", "local-gap"):
+            name = f"{'LG-l' if ids == 'local' else 'LG-l-gap'}{'+DM' if rl else ''}"
+            hs = []
+            enc_ms = _time_ms(torch, lambda: hs.append(lg.encode(g.row_offsets, g.col, n, ids=ids,
+                                                                 offsets="succinct", relabel=rl)))
+            for h in hs[:-1]:
+                h.free()
+            h = hs[-1]
+            info = h.info()
+            lg.lib().lg_decode_neighbors(h.handle, C.c_void_p(vt.data_ptr()), k, C.c_void_p(off.data_ptr()), None,
+                                         0, 2, s)
+            total = int(off[-1].item())
+            ids_buf = torch.empty(max(total, 1), dtype=torch.int32, device=g.col.device)
+
+            def lists():
+                st = lg.lib().lg_decode_neighbors(h.handle, C.c_void_p(vt.data_ptr()), k, C.c_void_p(off.data_ptr()),
+                                                  C.c_void_p(ids_buf.data_ptr()), total, 2, s)
+                assert st == 0, lg.lib().lg_last_error()
+            dec_ms = _time_ms(torch, lists, reps=5)
+            res[name] = {"adj_bytes": info["adj_bits"] / 8.0, "widths_bytes": info["bytes_widths"],
+                         "offsets_bytes": info["bytes_offsets"], "encode_ms": round(enc_ms, 3),
+                         "decode_ms": round(dec_ms, 4), "decoded_entries": total,
+                         "decode_gentries_per_s": round(total / (dec_ms * 1e-3) / 1e9, 3)}
+            log(f"[gap] {name}: {res[name]}")
+            h.free()
+    for rl in ("", "+DM"):
+        a, b = res["LG-l" + rl], res["LG-l-gap" + rl]
+        b["adj_vs_local"] = round(b["adj_bytes"] / a["adj_bytes"], 4)
+        b["total_vs_local"] = round((b["adj_bytes"] + b["widths_bytes"] + b["offsets_bytes"])
+                                    / (a["adj_bytes"] + a["widths_bytes"] + a["offsets_bytes"]), 4)
+    print(json.dumps({"mode": "gap-compare", "workload": args.workload, "n": n, "stored_edges": g.m,
                       "vertices_per_call": k, "data": "synthetic", "results": res}), flush=True)
 
 
