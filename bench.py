@@ -498,7 +498,8 @@ def gap_main(args, np, torch, lg, g):
     """Local widths (LG-l) vs fixed-size gap encoding (LG-l-gap), Elias-Fano
     offsets, without and with the degree-minimizing relabeling: bytes of the
     lists |A| and of the width tables, encode time, and the decode of the
-    lists of 256,000 random vertices (one call, stored labels)."""
+    lists of 256,000 random vertices (one call, stored labels), and 20
+    PageRank iterations."""
     import ctypes as C
     n = g.n
     k = 1000 * 256
@@ -527,10 +528,12 @@ def gap_main(args, np, torch, lg, g):
                                                   C.c_void_p(ids_buf.data_ptr()), total, 2, s)
                 assert st == 0, lg.lib().lg_last_error()
             dec_ms = _time_ms(torch, lists, reps=5)
+            pr_ms = _time_ms(torch, lambda: lg.pagerank(h, 0.85, 20))
             res[name] = {"adj_bytes": info["adj_bits"] / 8.0, "widths_bytes": info["bytes_widths"],
                          "offsets_bytes": info["bytes_offsets"], "encode_ms": round(enc_ms, 3),
                          "decode_ms": round(dec_ms, 4), "decoded_entries": total,
-                         "decode_gentries_per_s": round(total / (dec_ms * 1e-3) / 1e9, 3)}
+                         "decode_gentries_per_s": round(total / (dec_ms * 1e-3) / 1e9, 3),
+                         "pagerank20_ms": round(pr_ms, 3)}
             log(f"[gap] {name}: {res[name]}")
             h.free()
     for rl in ("", "+DM"):

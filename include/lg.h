@@ -64,7 +64,7 @@ typedef enum lg_status {
  * of consecutive neighbors at g_v = bl(largest difference) bits (0 when
  * d_v < 2), kept in a second table of F bits/vertex; the list takes
  * w_v + (d_v - 1) g_v bits.  Such graphs are read by lg_decode_neighbors
- * (a prefix sum per list); lg_bfs, lg_pagerank, batch plans and servers
+ * and lg_pagerank (a prefix sum per list); lg_bfs, batch plans and servers
  * return LG_ERR_UNSUPPORTED for them. */
 #define LG_IDS_LOCAL_GAP 2u
 /* lg_encode_opts.offset_mode -- sections "Logarithmization of Single Offsets"

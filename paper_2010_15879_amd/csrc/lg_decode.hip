@@ -26,15 +26,6 @@ __global__ void dec_degree_kernel(Acc acc, const uint32_t *__restrict__ labels, 
         deg[i] = acc.info(labels[i]).deg;
 }
 
-template <class Acc>
-struct IsGapAcc {
-    static constexpr bool value = false;
-};
-template <int OFM>
-struct IsGapAcc<GapAcc<OFM>> {
-    static constexpr bool value = true;
-};
-
 // kSorted: emit ((i << 32) | original ID) keys for the segmented sort
 template <class Acc, bool kSorted>
 __global__ void dec_lists_kernel(Acc acc, uint32_t n, const uint32_t *__restrict__ labels, uint32_t k,
@@ -96,17 +87,6 @@ uint64_t DecodeWork::bytes() const {
     return head.bytes + scan_tmp.bytes + keys.bytes + keys2.bytes + vals.bytes + vals2.bytes + sort_tmp.bytes;
 }
 
-// dispatch_acc plus the gap accessors, which only this in-order decode takes
-template <class Fn>
-static lg_status decode_dispatch(const lg_graph *g, Fn &&fn) {
-    if (g->layout == LG_LAYOUT_PACKED && g->id_mode == LG_IDS_LOCAL_GAP) {
-        const PackedView pv = g->packed_view();
-        if (g->offset_mode == LG_OFFS_PACKED) return fn(GapAcc<kOffsPacked>{PackedAcc<kIdsLocal, kOffsPacked>{pv}});
-        return fn(GapAcc<kOffsEF>{PackedAcc<kIdsLocal, kOffsEF>{pv}});
-    }
-    return dispatch_acc(g, fn);
-}
-
 lg_status decode_run(lg_graph *g, DecodeWork &w, const uint32_t *vertices, uint32_t k, uint64_t *out_off,
                      uint32_t *out_ids, uint64_t cap, uint32_t flags, hipStream_t stream, uint64_t *total_out) {
     if (total_out) *total_out = 0;
@@ -131,7 +111,7 @@ lg_status decode_run(lg_graph *g, DecodeWork &w, const uint32_t *vertices, uint3
     LG_TRY(fill_u32(bad, 0, 1, stream));
     LG_LAUNCH(dec_map_kernel, grid_for(k, 256, 1u << 16), 256, 0, stream, g->n, vertices, k, inv, labels, bad);
     LG_CHECK_LAUNCH();
-    return decode_dispatch(g, [&](auto acc) -> lg_status {
+    return dispatch_acc_all(g, [&](auto acc) -> lg_status {
         using Acc = decltype(acc);
         LG_LAUNCH(dec_degree_kernel<Acc>, grid_for(k, 256, 1u << 16), 256, 0, stream, acc, labels, k, deg);
         LG_CHECK_LAUNCH();

@@ -465,7 +465,7 @@ lg_status dispatch_acc(const lg_graph *g, Fn &&fn) {
     }
     if (g->id_mode == LG_IDS_LOCAL_GAP) {
         set_error("gap-encoded lists are read in order only: this operation is not available for them "
-                  "(lg_decode_neighbors is)");
+                  "(lg_decode_neighbors and lg_pagerank are)");
         return LG_ERR_UNSUPPORTED;
     }
     const PackedView pv = g->packed_view();
@@ -475,6 +475,27 @@ lg_status dispatch_acc(const lg_graph *g, Fn &&fn) {
     }
     if (g->offset_mode == LG_OFFS_PACKED) return fn(PackedAcc<kIdsLocal, kOffsPacked>{pv});
     return fn(PackedAcc<kIdsLocal, kOffsEF>{pv});
+}
+
+template <class Acc>
+struct IsGapAcc {
+    static constexpr bool value = false;
+};
+template <int OFM>
+struct IsGapAcc<GapAcc<OFM>> {
+    static constexpr bool value = true;
+};
+
+// dispatch_acc plus the gap accessors, for the paths that read gap lists in
+// order (the neighbor decode and PageRank)
+template <class Fn>
+lg_status dispatch_acc_all(const lg_graph *g, Fn &&fn) {
+    if (g->layout == LG_LAYOUT_PACKED && g->id_mode == LG_IDS_LOCAL_GAP) {
+        const PackedView pv = g->packed_view();
+        if (g->offset_mode == LG_OFFS_PACKED) return fn(GapAcc<kOffsPacked>{PackedAcc<kIdsLocal, kOffsPacked>{pv}});
+        return fn(GapAcc<kOffsEF>{PackedAcc<kIdsLocal, kOffsEF>{pv}});
+    }
+    return dispatch_acc(g, fn);
 }
 
 }  // namespace lg

@@ -16,16 +16,49 @@ namespace lg {
 template <class Acc>
 __global__ void heavy_info_kernel(Acc acc, const uint32_t *__restrict__ heavy, uint32_t n_heavy,
                                   uint64_t *__restrict__ hstart, uint32_t *__restrict__ hdeg,
-                                  uint32_t *__restrict__ hw, uint32_t split, uint32_t seg_size,
-                                  uint32_t *__restrict__ segcnt) {
+                                  uint32_t *__restrict__ hw, uint32_t *__restrict__ hg, uint32_t split,
+                                  uint32_t seg_size, uint32_t *__restrict__ segcnt) {
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t h = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; h < n_heavy; h += stride) {
-        const VInfo vi = acc.info(heavy[h]);
+        const auto vi = acc.info(heavy[h]);
         hstart[h] = vi.start;
         hdeg[h] = vi.deg;
         hw[h] = vi.w;
+        if constexpr (IsGapAcc<Acc>::value) hg[h] = vi.g;
         segcnt[h] = vi.deg > split ? (vi.deg + seg_size - 1) / seg_size : 0u;
     }
+}
+
+// Gap lists: the sum of segment k's entries (the first element counts for
+// entry 0, a difference for every other), one wave per segment.
+template <class Acc>
+__global__ void gap_seg_sum_kernel(Acc acc, uint64_t n_seg, uint32_t seg_size, const uint32_t *__restrict__ seg_map,
+                                   const uint64_t *__restrict__ seg_off, const uint64_t *__restrict__ hstart,
+                                   const uint32_t *__restrict__ hdeg, const uint32_t *__restrict__ hw,
+                                   const uint32_t *__restrict__ hg, uint32_t *__restrict__ seg_sum) {
+    const uint32_t lane = lane_id();
+    const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) / kWave;
+    for (uint64_t k = wave; k < n_seg; k += nwaves) {
+        const uint32_t h = seg_map[k];
+        const uint64_t e0 = (k - seg_off[h]) * seg_size;
+        const uint64_t e1 = e0 + seg_size < hdeg[h] ? e0 + seg_size : hdeg[h];
+        const GapInfo gi{hstart[h], hdeg[h], hw[h], hg[h]};
+        uint32_t sum = 0;
+        for (uint64_t e = e0 + lane; e < e1; e += kWave)
+            sum += acc.get(Acc::entry_bit(gi, e), e == 0 ? gi.w : gi.g);
+        sum = wave_sum(sum);
+        if (lane == 0) seg_sum[k] = sum;
+    }
+}
+
+// seg_base[k] = the sums of the segments of the same list before k
+__global__ void gap_seg_base_kernel(uint64_t n_seg, const uint32_t *__restrict__ seg_map,
+                                    const uint64_t *__restrict__ seg_off, const uint64_t *__restrict__ scan,
+                                    uint32_t *__restrict__ seg_base) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n_seg; k += stride)
+        seg_base[k] = (uint32_t)(scan[k] - scan[seg_off[seg_map[k]]]);
 }
 
 __global__ void heavy_sum_kernel(uint32_t n_heavy, const uint32_t *__restrict__ hdeg, const uint32_t *__restrict__ hw,
@@ -63,9 +96,11 @@ __global__ void pr_units_kernel(Acc acc, uint32_t n, uint32_t split, uint32_t bu
     const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) / kWave;
     const uint32_t lane = lane_id();
     for (uint64_t q = wave; q < words; q += nwaves) {
-        const VInfo vi = wave_info(acc, q * 64, n);
         const uint64_t v = q * 64 + lane;
-        const uint32_t d = (v < n && vi.deg <= split) ? vi.deg : 0u;
+        uint32_t deg;
+        if constexpr (IsGapAcc<Acc>::value) deg = v < n ? acc.info((uint32_t)v).deg : 0u;
+        else deg = wave_info(acc, q * 64, n).deg;
+        const uint32_t d = (v < n && deg <= split) ? deg : 0u;
         const uint32_t excl = wave_incl_scan(d) - d;
         const uint32_t prev = __shfl_up(excl, 1, kWave);
         const bool start = v < n && (lane == 0 || excl / budget != prev / budget);
@@ -89,6 +124,8 @@ lg_status ensure_heavy_segments(lg_graph *g, hipStream_t s) {
     LG_TRY(g->hstart.scratch((uint64_t)(nh ? nh : 1) * 8, s));
     LG_TRY(g->hdeg.scratch((uint64_t)(nh ? nh : 1) * 4, s));
     LG_TRY(g->hw.scratch((uint64_t)(nh ? nh : 1) * 4, s));
+    const bool gap = g->id_mode == LG_IDS_LOCAL_GAP;
+    if (gap) LG_TRY(g->hg.scratch((uint64_t)(nh ? nh : 1) * 4, s));
     LG_TRY(g->seg_off.scratch(((uint64_t)nh + 1) * 8, s));
     g->n_seg = 0;
     DevBuf tmp;
@@ -96,11 +133,12 @@ lg_status ensure_heavy_segments(lg_graph *g, hipStream_t s) {
     if (nh) {
         DevBuf segcnt;
         LG_TRY(segcnt.scratch((uint64_t)nh * 4, s));
-        LG_TRY(dispatch_acc(g, [&](auto acc) -> lg_status {
+        LG_TRY(dispatch_acc_all(g, [&](auto acc) -> lg_status {
             using Acc = decltype(acc);
             LG_LAUNCH(heavy_info_kernel<Acc>, grid_for(nh, 256, 1u << 16), 256, 0, s, acc, g->heavy.as<uint32_t>(),
-                      nh, g->hstart.as<uint64_t>(), g->hdeg.as<uint32_t>(), g->hw.as<uint32_t>(), g->pr_split,
-                      g->seg_size, segcnt.as<uint32_t>());
+                      nh, g->hstart.as<uint64_t>(), g->hdeg.as<uint32_t>(), g->hw.as<uint32_t>(),
+                      gap ? g->hg.as<uint32_t>() : (uint32_t *)nullptr, g->pr_split, g->seg_size,
+                      segcnt.as<uint32_t>());
             LG_CHECK_LAUNCH();
             return LG_OK;
         }));
@@ -128,13 +166,39 @@ lg_status ensure_heavy_segments(lg_graph *g, hipStream_t s) {
                   g->seg_map.as<uint32_t>());
         LG_CHECK_LAUNCH();
     }
+    if (gap) {
+        LG_TRY(g->seg_base.scratch((g->n_seg ? g->n_seg : 1) * 4, s));
+        if (g->n_seg) {
+            DevBuf ssum, sscan;
+            LG_TRY(ssum.scratch(g->n_seg * 4, s));
+            LG_TRY(sscan.scratch((g->n_seg + 1) * 8, s));
+            LG_TRY(dispatch_acc_all(g, [&](auto acc) -> lg_status {
+                using Acc = decltype(acc);
+                if constexpr (IsGapAcc<Acc>::value) {
+                    LG_LAUNCH(gap_seg_sum_kernel<Acc>, grid_for(g->n_seg * kWave, 256, 1u << 16), 256, 0, s, acc,
+                              g->n_seg, g->seg_size, g->seg_map.as<uint32_t>(), g->seg_off.as<uint64_t>(),
+                              g->hstart.as<uint64_t>(), g->hdeg.as<uint32_t>(), g->hw.as<uint32_t>(),
+                              g->hg.as<uint32_t>(), ssum.as<uint32_t>());
+                    LG_CHECK_LAUNCH();
+                    return LG_OK;
+                }
+                return LG_ERR_UNSUPPORTED;
+            }));
+            LG_TRY(exclusive_scan_u32(ssum.as<uint32_t>(), sscan.as<uint64_t>(), g->n_seg, tmp, s));
+            LG_LAUNCH(gap_seg_base_kernel, grid_for(g->n_seg, 256, 1u << 16), 256, 0, s, g->n_seg,
+                      g->seg_map.as<uint32_t>(), g->seg_off.as<uint64_t>(), sscan.as<uint64_t>(),
+                      g->seg_base.as<uint32_t>());
+            LG_CHECK_LAUNCH();
+            LG_CHECK_HIP(hipStreamSynchronize(s));
+        }
+    }
     // units
     const uint64_t words = ((uint64_t)n + 63) / 64;
     DevBuf cnt, uoff;
     LG_TRY(cnt.scratch(words * 4, s));
     LG_TRY(uoff.scratch((words + 1) * 8, s));
     const uint32_t ugrid = grid_for(words * kWave, 256, 1u << 16);
-    LG_TRY(dispatch_acc(g, [&](auto acc) -> lg_status {
+    LG_TRY(dispatch_acc_all(g, [&](auto acc) -> lg_status {
         using Acc = decltype(acc);
         LG_LAUNCH((pr_units_kernel<Acc, false>), ugrid, 256, 0, s, acc, n, g->pr_split, g->pr_unit_edges,
                   cnt.as<uint32_t>(), (const uint64_t *)nullptr, (uint32_t *)nullptr);

@@ -170,7 +170,10 @@ struct lg_graph {
     // segment's sum in the current iteration).  The other vertices are taken
     // in units of consecutive vertices inside one 64-aligned block, at most
     // about pr_unit_edges edges each: unit k = [units[k], units[k+1]).
-    lg::DevBuf hstart, hdeg, hw, seg_off, seg_map, seg_part, units;
+    // With gap-encoded lists also the gap width of each heavy vertex (hg) and
+    // the value of the entry before each segment (seg_base; 0 for a list's
+    // first segment).
+    lg::DevBuf hstart, hdeg, hw, hg, seg_off, seg_map, seg_part, seg_base, units;
     uint64_t n_seg = 0, n_units = 0;
     uint32_t seg_size = 4096;       // a power of two keeping every vertex below 2^16 segments
     uint32_t pr_split = 4096;       // degree above which PageRank segments a list

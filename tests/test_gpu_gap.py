@@ -1,6 +1,7 @@
 """Fixed-size gap encoding on the GPU (subsection "Adding Fixed-Size Gap
 Encoding", local approach): every array bit-exact against the oracle, lists
-decoded against the input, and the traversals refusing such graphs."""
+decoded against the input, PageRank over them against the oracle, and BFS
+refusing such graphs."""
 
 import numpy as np
 import pytest
@@ -8,7 +9,7 @@ import torch
 
 import oracle as orc
 from paper_2010_15879_amd import graphgen as gg
-from test_gpu_parity import GRAPHS
+from test_gpu_parity import GRAPHS, PR_L1
 
 pytestmark = pytest.mark.gpu
 
@@ -87,7 +88,7 @@ def test_gap_decode(lgmod, name, e):
     h.free()
 
 
-def test_gap_traversals_unsupported(lgmod):
+def test_gap_bfs_unsupported(lgmod):
     from paper_2010_15879_amd.lg import LGError, LG_ERR_UNSUPPORTED
     g = GRAPHS["kron12"]
     h = encode(lgmod, g, GAP[1])
@@ -95,10 +96,29 @@ def test_gap_traversals_unsupported(lgmod):
     with pytest.raises(LGError) as ei:
         lgmod.bfs(h, root)
     assert ei.value.status == LG_ERR_UNSUPPORTED
-    with pytest.raises(LGError) as ei:
-        lgmod.pagerank(h, 0.85, 2)
-    assert ei.value.status == LG_ERR_UNSUPPORTED
     h.free()
+
+
+@pytest.mark.parametrize("e", GAP, ids=gid)
+@pytest.mark.parametrize("name", list(GRAPHS))
+def test_gap_pagerank(lgmod, name, e):
+    """PageRank over gap lists: within the FP32 bound of the FP64 oracle, and
+    bit-identical to PageRank over local-width lists of the same graph (the
+    decoded IDs are the same and the work split and summation order depend
+    only on the degrees)."""
+    g = GRAPHS[name]
+    off, col = g.numpy()
+    print(f"[gap pagerank] {name} {gid(e)}", flush=True)
+    h = encode(lgmod, g, e)
+    hl = encode(lgmod, g, dict(e, ids="local"))
+    for iters in [0, 1, 20]:
+        pr = lgmod.pagerank(h, 0.85, iters).cpu().numpy()
+        pr64 = orc.pagerank(off, col, 0.85, iters)
+        l1 = np.abs(pr.astype(np.float64) - pr64).sum()
+        assert l1 <= PR_L1, (iters, l1)
+        np.testing.assert_array_equal(pr, lgmod.pagerank(hl, 0.85, iters).cpu().numpy())
+    h.free()
+    hl.free()
 
 
 def test_gap_kronecker16_smaller(lgmod):
@@ -111,5 +131,7 @@ def test_gap_kronecker16_smaller(lgmod):
     o = orc.Encoding(off, col, "local-gap", "ef", True)
     np.testing.assert_array_equal(h.export("adj"), o.A)
     assert h.info()["adj_bits"] <= hl.info()["adj_bits"]
+    np.testing.assert_array_equal(lgmod.pagerank(h, 0.85, 5).cpu().numpy(),
+                                  lgmod.pagerank(hl, 0.85, 5).cpu().numpy())
     h.free()
     hl.free()

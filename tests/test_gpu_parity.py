@@ -59,7 +59,8 @@ def _tiny_graphs():
     # degrees 64 and 65 straddle the heavy-vertex threshold of the traversal kernels
     G["deg64_65"] = gg.csr_from_edges(200, [(0, i) for i in range(2, 66)] + [(1, i) for i in range(100, 165)]
                                       + [(2, 100)])
-    # a hub whose list spans several PageRank segments (1024 edges each)
+    # a hub of degree 3000: below the PageRank split, so one unit walks its
+    # whole list 64 entries at a time
     G["bigstar"] = gg.csr_from_edges(3001, [(0, i) for i in range(1, 3001)] + [(5, 6), (6, 7)])
     # a hub so large that its gap in the Elias-Fano upper bits spans more than
     # 64 words (the per-lane select fallback of the sweep kernels)
