@@ -238,6 +238,82 @@ ORC_API void orc_decode_gap_list(const uint64_t *words, uint64_t start, uint64_t
     }
 }
 
+/* ------------------------------------------------------------------ */
+/* Varint lists -- subsection "Incorporating Degree-Minimizing (DM)":   */
+/* DMf stores every label of a list, DMd the first label and then the   */
+/* differences of consecutive labels, each value as a Varint.  Reading  */
+/* (the paper names the code but not its byte layout): the common       */
+/* little-endian base-128 form, 7 value bits per byte, the lowest group */
+/* first, the top bit of a byte set when another byte of the same value */
+/* follows.  Lists follow each other in vertex order, byte-aligned; the */
+/* offsets are byte starts.                                              */
+/* ------------------------------------------------------------------ */
+
+/* The value entry i of row v stores. */
+static uint32_t varint_value(const uint64_t *off, const uint32_t *col, uint64_t v, uint64_t i, int diff) {
+    if (!diff || i == off[v]) return col[i];
+    return col[i] - col[i - 1];
+}
+
+ORC_API unsigned orc_varint_len(uint32_t x) {
+    unsigned b = 1;
+    while (x >= 128) {
+        x >>= 7;
+        b++;
+    }
+    return b;
+}
+
+/* Byte start of every list (count n + 1, the last one the stream length). */
+ORC_API void orc_varint_byte_starts(uint64_t n, const uint64_t *off, const uint32_t *col, int diff, uint64_t *P) {
+    uint64_t acc = 0;
+    for (uint64_t v = 0; v < n; v++) {
+        P[v] = acc;
+        for (uint64_t i = off[v]; i < off[v + 1]; i++) acc += orc_varint_len(varint_value(off, col, v, i, diff));
+    }
+    P[n] = acc;
+}
+
+/* The byte stream; `bytes` holds at least P[n] bytes. */
+ORC_API void orc_pack_varint(uint64_t n, const uint64_t *off, const uint32_t *col, int diff, uint8_t *bytes) {
+    uint64_t pos = 0;
+    for (uint64_t v = 0; v < n; v++) {
+        for (uint64_t i = off[v]; i < off[v + 1]; i++) {
+            uint32_t x = varint_value(off, col, v, i, diff);
+            for (;;) {
+                const uint8_t low = (uint8_t)(x & 127u);
+                x >>= 7;
+                if (x) {
+                    bytes[pos++] = (uint8_t)(low | 128u);
+                } else {
+                    bytes[pos++] = low;
+                    break;
+                }
+            }
+        }
+    }
+}
+
+/* The list held in bytes [b0, b1): returns its length, the labels in out
+ * (out must hold b1 - b0 values, the most a list of that size can have). */
+ORC_API uint64_t orc_decode_varint_list(const uint8_t *bytes, uint64_t b0, uint64_t b1, int diff, uint32_t *out) {
+    uint64_t count = 0;
+    uint64_t acc = 0;
+    unsigned shift = 0;
+    for (uint64_t p = b0; p < b1; p++) {
+        acc |= (uint64_t)(bytes[p] & 127u) << shift;
+        shift += 7;
+        if (!(bytes[p] & 128u)) {
+            uint32_t x = (uint32_t)acc;
+            if (diff && count) x += out[count - 1];
+            out[count++] = x;
+            acc = 0;
+            shift = 0;
+        }
+    }
+    return count;
+}
+
 /* Element i of a list whose first element starts at stream bit `start`. */
 ORC_API void orc_decode_list(const uint64_t *words, uint64_t start, uint64_t d, unsigned w, uint32_t *out) {
     for (uint64_t i = 0; i < d; i++)

@@ -76,6 +76,10 @@ def lib():
         "orc_gap_bit_starts": (None, [C.c_uint64, u64p, u8p, u8p, u64p]),
         "orc_pack_gap": (None, [C.c_uint64, u64p, u32p, u8p, u8p, u64p]),
         "orc_decode_gap_list": (None, [u64p, C.c_uint64, C.c_uint64, C.c_uint, C.c_uint, u32p]),
+        "orc_varint_len": (C.c_uint, [C.c_uint32]),
+        "orc_varint_byte_starts": (None, [C.c_uint64, u64p, u32p, C.c_int, u64p]),
+        "orc_pack_varint": (None, [C.c_uint64, u64p, u32p, C.c_int, u8p]),
+        "orc_decode_varint_list": (C.c_uint64, [u8p, C.c_uint64, C.c_uint64, C.c_int, u32p]),
         "orc_relabel_row": (None, [u64p, u32p, u32p, u32p, C.c_uint32, u32p]),
         "orc_bfs_labels": (C.c_int, [C.c_uint64, u64p, u32p, C.c_uint32, C.c_int32, _NullableU32,
                                      i32p, i32p]),
@@ -192,6 +196,46 @@ def decode_gap_list(words, start: int, d: int, w: int, g: int) -> np.ndarray:
     out = np.zeros(max(d, 1), dtype=np.uint32)
     lib().orc_decode_gap_list(words, start, d, w, g, out)
     return out[:d]
+
+
+def varint_len(x: int) -> int:
+    """Bytes of one Varint value (subsection "Incorporating Degree-Minimizing
+    (DM)"; base-128, lowest group first)."""
+    return int(lib().orc_varint_len(x))
+
+
+def varint_byte_starts(off, col, diff: bool) -> np.ndarray:
+    """Byte start of each Varint list (n + 1 values, the last = stream bytes);
+    diff: DMd (first label, then differences), else DMf (every label)."""
+    n, off, col = _csr(off, col)
+    P = np.zeros(n + 1, dtype=np.uint64)
+    lib().orc_varint_byte_starts(n, off, col, int(diff), P)
+    return P
+
+
+def pack_varint(off, col, diff: bool) -> np.ndarray:
+    """The Varint byte stream of every list, in vertex order."""
+    n, off, col = _csr(off, col)
+    total = int(varint_byte_starts(off, col, diff)[-1])
+    out = np.zeros(max(total, 1), dtype=np.uint8)
+    lib().orc_pack_varint(n, off, col, int(diff), out)
+    return out[:total]
+
+
+def varint_words(stream: np.ndarray) -> np.ndarray:
+    """A byte stream as little-endian 64-bit words plus one zero word (byte
+    i = bits 8(i mod 8) .. +8 of word floor(i / 8))."""
+    nw = (stream.size + 7) // 8 + 1
+    buf = np.zeros(nw * 8, dtype=np.uint8)
+    buf[: stream.size] = stream
+    return buf.view("<u8").astype(np.uint64)
+
+
+def decode_varint_list(stream, b0: int, b1: int, diff: bool) -> np.ndarray:
+    stream = np.ascontiguousarray(stream, dtype=np.uint8)
+    out = np.zeros(max(b1 - b0, 1), dtype=np.uint32)
+    cnt = lib().orc_decode_varint_list(stream if stream.size else np.zeros(1, np.uint8), b0, b1, int(diff), out)
+    return out[:cnt]
 
 
 def decode_list(words, start: int, d: int, w: int) -> np.ndarray:
@@ -318,8 +362,10 @@ class Encoding:
     """Every array of the packed representation, built by the oracle.
 
     id_mode: "global" (every ID at s bits), "local" (list v at w_v bits,
-    with a width table at F bits per vertex) or "local-gap" (first element at
-    w_v bits, the differences at g_v bits, both tables at F bits).  offset_mode: "packed"
+    with a width table at F bits per vertex), "local-gap" (first element at
+    w_v bits, the differences at g_v bits, both tables at F bits),
+    "varint-full" or "varint-diff" (a byte stream of Varint labels or of a
+    first label and differences; offsets are byte starts).  offset_mode: "packed"
     (fixed-width offsets) or "ef" (Elias-Fano with rank/select directory).
     The offset values are element offsets O[v] in global mode (bit start =
     s * O[v]) and bit starts P_v in local mode.  relabel: False, True or
@@ -341,7 +387,16 @@ class Encoding:
         self.off, self.col = off, col
         self.s = global_width(n)
         self.gwidths = None
-        if id_mode == "global":
+        self.stream = None
+        if id_mode in ("varint-full", "varint-diff"):
+            self.diff = id_mode == "varint-diff"
+            self.widths = None
+            self.stream = pack_varint(off, col, self.diff)
+            self.A = varint_words(self.stream)
+            self.U = 8 * self.stream.size
+            vals = varint_byte_starts(off, col, self.diff)
+            universe = self.stream.size
+        elif id_mode == "global":
             self.widths = None
             self.U = adjacency_bits(off, None, self.s)
             self.A = pack_adjacency(off, col, None, self.s)
@@ -366,7 +421,9 @@ class Encoding:
             self.A = pack_adjacency(off, col, self.widths, 0)
             vals = bit_starts(off, self.widths, 0)
             universe = self.U
-        if self.gwidths is None:
+        if self.stream is not None:
+            self.P = vals
+        elif self.gwidths is None:
             self.P = bit_starts(off, self.widths, self.s if self.widths is None else 0)
         else:
             self.P = vals
@@ -381,6 +438,8 @@ class Encoding:
 
     def neighbors(self, x: int) -> np.ndarray:
         """Stored list of stored label x, decoded bit by bit."""
+        if self.stream is not None:
+            return decode_varint_list(self.stream, int(self.P[x]), int(self.P[x + 1]), self.diff)
         w = self.s if self.widths is None else int(self.widths[x])
         d = int(self.off[x + 1] - self.off[x])
         if self.gwidths is not None:
