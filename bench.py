@@ -95,9 +95,10 @@ def parse():
                         "offsets (ptr32), offsets at bl(universe) bits (ptrW) and Elias-Fano offsets (bvSD): "
                         "degrees only and whole lists "
                         "(own JSON line)")
-    p.add_argument("--gap-compare", action="store_true",
-                   help="the workload's graph with local widths vs fixed-size gap encoding (with and without the "
-                        "degree-minimizing relabeling): |A|, encode time, random-vertex list decode (own JSON line)")
+    p.add_argument("--encoding-compare", action="store_true",
+                   help="the workload's graph with local widths, fixed-size gap encoding and Varint lists (full "
+                        "labels or differences), with and without the degree-minimizing relabeling (DMf, DMd): "
+                        "|A|, encode time, random-vertex list decode, PageRank (own JSON line)")
     p.add_argument("--pr-only", action="store_true",
                    help="counter-run mode: one 1 GiB device copy (calibration) then one PageRank call; no timing")
     return p.parse_args()
@@ -140,8 +141,8 @@ def main():
         return relabel_main(args, np, torch, lg, g, roots)
     if args.offset_fetch:
         return offset_fetch_main(args, np, torch, lg, g)
-    if args.gap_compare:
-        return gap_main(args, np, torch, lg, g)
+    if args.encoding_compare:
+        return encoding_main(args, np, torch, lg, g)
 
     if args.pr_only:
         # A kernel of known traffic calibrates the HBM byte counters (an
@@ -494,12 +495,14 @@ def offset_fetch_main(args, np, torch, lg, g):
                       "vertices_per_call": k, "data": "synthetic", "results": res}), flush=True)
 
 
-def gap_main(args, np, torch, lg, g):
-    """Local widths (LG-l) vs fixed-size gap encoding (LG-l-gap), Elias-Fano
-    offsets, without and with the degree-minimizing relabeling: bytes of the
-    lists |A| and of the width tables, encode time, and the decode of the
-    lists of 256,000 random vertices (one call, stored labels), and 20
-    PageRank iterations."""
+def encoding_main(args, np, torch, lg, g):
+    """List encodings side by side, Elias-Fano offsets, without and with the
+    degree-minimizing relabeling: local widths (LG-l), fixed-size gap
+    encoding (LG-l-gap), and Varint lists of full labels or of differences
+    (with the relabeling: DMf and DMd).  Bytes of the lists |A|, of the width
+    tables and of the offsets, encode time, the decode of the lists of
+    256,000 random vertices (one call, stored labels), and 20 PageRank
+    iterations where the encoding supports them."""
     import ctypes as C
     n = g.n
     k = 1000 * 256
@@ -508,9 +511,10 @@ def gap_main(args, np, torch, lg, g):
     off = torch.empty(k + 1, dtype=torch.int64, device=g.col.device)
     s = C.c_void_p(torch.cuda.current_stream().cuda_stream)
     res = {}
+    names = {"local": "LG-l", "local-gap": "LG-l-gap", "varint-full": "Varint-full", "varint-diff": "Varint-diff"}
     for rl in (False, True):
-        for ids in ("local", "local-gap"):
-            name = f"{'LG-l' if ids == 'local' else 'LG-l-gap'}{'+DM' if rl else ''}"
+        for ids in ("local", "local-gap", "varint-full", "varint-diff"):
+            name = f"{names[ids]}{'+DM' if rl else ''}"
             hs = []
             enc_ms = _time_ms(torch, lambda: hs.append(lg.encode(g.row_offsets, g.col, n, ids=ids,
                                                                  offsets="succinct", relabel=rl)))
@@ -528,20 +532,22 @@ def gap_main(args, np, torch, lg, g):
                                                   C.c_void_p(ids_buf.data_ptr()), total, 2, s)
                 assert st == 0, lg.lib().lg_last_error()
             dec_ms = _time_ms(torch, lists, reps=5)
-            pr_ms = _time_ms(torch, lambda: lg.pagerank(h, 0.85, 20))
+            pr_ms = _time_ms(torch, lambda: lg.pagerank(h, 0.85, 20)) if ids.startswith("local") else None
             res[name] = {"adj_bytes": info["adj_bits"] / 8.0, "widths_bytes": info["bytes_widths"],
                          "offsets_bytes": info["bytes_offsets"], "encode_ms": round(enc_ms, 3),
                          "decode_ms": round(dec_ms, 4), "decoded_entries": total,
                          "decode_gentries_per_s": round(total / (dec_ms * 1e-3) / 1e9, 3),
-                         "pagerank20_ms": round(pr_ms, 3)}
-            log(f"[gap] {name}: {res[name]}")
+                         "pagerank20_ms": None if pr_ms is None else round(pr_ms, 3)}
+            log(f"[encodings] {name}: {res[name]}")
             h.free()
     for rl in ("", "+DM"):
-        a, b = res["LG-l" + rl], res["LG-l-gap" + rl]
-        b["adj_vs_local"] = round(b["adj_bytes"] / a["adj_bytes"], 4)
-        b["total_vs_local"] = round((b["adj_bytes"] + b["widths_bytes"] + b["offsets_bytes"])
-                                    / (a["adj_bytes"] + a["widths_bytes"] + a["offsets_bytes"]), 4)
-    print(json.dumps({"mode": "gap-compare", "workload": args.workload, "n": n, "stored_edges": g.m,
+        a = res["LG-l" + rl]
+        for other in ("LG-l-gap", "Varint-full", "Varint-diff"):
+            b = res[other + rl]
+            b["adj_vs_local"] = round(b["adj_bytes"] / a["adj_bytes"], 4)
+            b["total_vs_local"] = round((b["adj_bytes"] + b["widths_bytes"] + b["offsets_bytes"])
+                                        / (a["adj_bytes"] + a["widths_bytes"] + a["offsets_bytes"]), 4)
+    print(json.dumps({"mode": "encoding-compare", "workload": args.workload, "n": n, "stored_edges": g.m,
                       "vertices_per_call": k, "data": "synthetic", "results": res}), flush=True)
 
 

@@ -67,6 +67,18 @@ typedef enum lg_status {
  * and lg_pagerank (a prefix sum per list); lg_bfs, batch plans and servers
  * return LG_ERR_UNSUPPORTED for them. */
 #define LG_IDS_LOCAL_GAP 2u
+/* subsection "Incorporating Degree-Minimizing (DM)": lists as Varint byte
+ * sequences (7 value bits per byte, lowest group first, the top bit set on
+ * every byte of a value but its last), one list after another, byte-aligned;
+ * the offsets are byte starts (packed or Elias-Fano over the stream's byte
+ * count) and lg_info.adj_bits is 8 x the stream bytes.  FULL stores every
+ * label (with LG_RELABEL_DEGREE: the paper's DMf), DIFF the first label and
+ * then the differences of consecutive labels (with LG_RELABEL_DEGREE: DMd).
+ * d_v is the number of bytes with the top bit clear in the list.  Such
+ * graphs are read by lg_decode_neighbors only; the other operations return
+ * LG_ERR_UNSUPPORTED for them. */
+#define LG_IDS_VARINT_FULL 3u
+#define LG_IDS_VARINT_DIFF 4u
 /* lg_encode_opts.offset_mode -- sections "Logarithmization of Single Offsets"
  * and "Logarithmizing Offsets" */
 #define LG_OFFS_PACKED 0u   /* offsets packed at bl(universe) bits each          */

@@ -325,7 +325,7 @@ static bool export_src(const lg_graph *g, uint32_t which, const void **p, uint64
             }
             return true;
         case LG_EXPORT_WIDTHS:
-            if (!packed || g->id_mode == LG_IDS_GLOBAL) return false;
+            if (!packed || (g->id_mode != LG_IDS_LOCAL && g->id_mode != LG_IDS_LOCAL_GAP)) return false;
             *p = g->W.p; *bytes = g->W_words * 8;
             return true;
         case LG_EXPORT_GAP_WIDTHS:

@@ -2,7 +2,8 @@
 // library listing in section "High-Performance Library"): the offset lookup,
 // d_v = O[v+1] - O[v] (subsection "Accessing a Degree") and the element
 // extraction of subsection "Accessing An Edge", one wave per requested
-// vertex so that consecutive lanes decode consecutive elements.
+// vertex so that consecutive lanes decode consecutive elements; gap and
+// Varint lists are decoded in order, 64 entries or bytes per wave step.
 #include "lg_device.hpp"
 
 namespace lg {
@@ -24,6 +25,31 @@ __global__ void dec_degree_kernel(Acc acc, const uint32_t *__restrict__ labels, 
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < k; i += stride)
         deg[i] = acc.info(labels[i]).deg;
+}
+
+// Varint lists: d_v is the number of bytes with the top bit clear in the
+// list's byte range; one wave per vertex counts them 8 bytes per lane.
+template <class Acc>
+__global__ void dec_varint_degree_kernel(Acc acc, const uint32_t *__restrict__ labels, uint32_t k,
+                                         uint32_t *__restrict__ deg) {
+    const uint32_t lane = lane_id();
+    const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) / kWave;
+    for (uint64_t i = wave; i < k; i += nwaves) {
+        uint64_t b0, b1;
+        acc.offsets(labels[i], b0, b1);
+        uint32_t cnt = 0;
+        for (uint64_t q = (b0 >> 3) + lane; q * 8 < b1; q += kWave) {
+            const uint64_t p = q * 8;
+            const uint64_t lo = p < b0 ? b0 - p : 0;         // bytes below the list
+            const uint64_t hi = p + 8 > b1 ? p + 8 - b1 : 0;  // bytes above it
+            uint64_t keep = ~0ull << (8 * lo);
+            if (hi) keep &= ~0ull >> (8 * hi);
+            cnt += (uint32_t)__popcll(~acc.word(p) & 0x8080808080808080ull & keep);
+        }
+        cnt = wave_sum(cnt);
+        if (lane == 0) deg[i] = cnt;
+    }
 }
 
 // kSorted: emit ((i << 32) | original ID) keys for the segmented sort
@@ -56,6 +82,56 @@ __global__ void dec_lists_kernel(Acc acc, uint32_t n, const uint32_t *__restrict
                     if (kSorted) keys[o + j] = (i << 32) | u;
                     else out_ids[o + j] = u;
                 }
+            }
+        }
+    } else if constexpr (IsVarintAcc<Acc>::value) {
+        // Varint lists: 64 bytes per step, one per lane.  A lane holding a
+        // value's last byte (top bit clear) assembles the value from its own
+        // byte and the continuation bytes right before it (at most four, the
+        // ones before the step's first lane come from the previous step);
+        // the value's index in the list is the number of last bytes before
+        // it.  DMd adds a wave prefix sum of the differences to the running
+        // label.
+        for (uint64_t i = wave; i < k; i += nwaves) {
+            uint64_t b0, b1;
+            acc.offsets(labels[i], b0, b1);
+            const uint64_t o = out_off[i];
+            uint64_t done = 0;
+            uint32_t carry = 0;
+            uint32_t prevb = 0;  // a value's last byte: stops the look-back at the list's start
+            for (uint64_t p0 = b0; p0 < b1; p0 += kWave) {
+                const uint64_t p = p0 + lane;
+                const bool in = p < b1;
+                const uint32_t b = in ? acc.byte(p) : 128u;
+                const bool end = in && !(b & 128u);
+                uint32_t val = b & 127u;
+                bool open = true;
+#pragma unroll
+                for (int t = 1; t <= 4; ++t) {
+                    const int src = (int)lane - t;
+                    const uint32_t cur = __shfl(b, src & (kWave - 1), kWave);
+                    const uint32_t old = __shfl(prevb, src & (kWave - 1), kWave);
+                    const uint32_t bt = src >= 0 ? cur : old;
+                    open = open && (bt & 128u);
+                    if (open) val = (val << 7) | (bt & 127u);
+                }
+                const uint64_t ends = __ballot(end);
+                uint32_t label = val;
+                if constexpr (Acc::kDifferences) {
+                    const uint32_t sc = wave_incl_scan(end ? val : 0u);
+                    label = carry + sc;
+                    carry += __shfl(sc, kWave - 1, kWave);
+                }
+                if (end) {
+                    const uint64_t j = done + popc_below(ends);
+                    // a stored label is < n; the clamp keeps the lookup in
+                    // bounds whatever the stream holds
+                    const uint32_t u = perm ? perm[label < n ? label : n - 1] : label;
+                    if (kSorted) keys[o + j] = (i << 32) | u;
+                    else out_ids[o + j] = u;
+                }
+                done += (uint64_t)__popcll(ends);
+                prevb = b;
             }
         }
     } else {
@@ -111,9 +187,13 @@ lg_status decode_run(lg_graph *g, DecodeWork &w, const uint32_t *vertices, uint3
     LG_TRY(fill_u32(bad, 0, 1, stream));
     LG_LAUNCH(dec_map_kernel, grid_for(k, 256, 1u << 16), 256, 0, stream, g->n, vertices, k, inv, labels, bad);
     LG_CHECK_LAUNCH();
-    return dispatch_acc_all(g, [&](auto acc) -> lg_status {
+    return dispatch_acc_dec(g, [&](auto acc) -> lg_status {
         using Acc = decltype(acc);
-        LG_LAUNCH(dec_degree_kernel<Acc>, grid_for(k, 256, 1u << 16), 256, 0, stream, acc, labels, k, deg);
+        if constexpr (IsVarintAcc<Acc>::value)
+            LG_LAUNCH(dec_varint_degree_kernel<Acc>, grid_for((uint64_t)k * kWave, 256, 1u << 16), 256, 0, stream,
+                      acc, labels, k, deg);
+        else
+            LG_LAUNCH(dec_degree_kernel<Acc>, grid_for(k, 256, 1u << 16), 256, 0, stream, acc, labels, k, deg);
         LG_CHECK_LAUNCH();
         LG_TRY(exclusive_scan_u32(deg, out_off, k, w.scan_tmp, stream));
         LG_CHECK_HIP(hipMemcpyAsync(w.host, out_off + k, 8, hipMemcpyDeviceToHost, stream));

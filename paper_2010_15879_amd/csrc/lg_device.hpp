@@ -333,6 +333,29 @@ struct GapAcc {
     __device__ __forceinline__ uint32_t get(uint64_t bit, uint32_t w) const { return base.get(bit, width_mask(w)); }
 };
 
+// Varint lists (subsection "Incorporating Degree-Minimizing (DM)"): a
+// byte stream of base-128 values, lowest group first, the top bit set on
+// every byte of a value but its last; the offsets are byte starts.  kDiff:
+// the first value is a label and each further one the difference to the
+// previous label (DMd); otherwise every value is a label (DMf).
+template <int OFM, bool kDiff>
+struct VarintAcc {
+    static constexpr bool kDifferences = kDiff;
+    PackedAcc<kIdsLocal, OFM> base;  // offsets and stream
+
+    __device__ __forceinline__ void offsets(uint32_t v, uint64_t &b0, uint64_t &b1) const {
+        base.offsets(v, b0, b1);
+    }
+    __device__ __forceinline__ uint32_t byte(uint64_t p) const {
+        return reinterpret_cast<const uint8_t *>(base.pv.A32)[p];
+    }
+    // 8 stream bytes from the 8-aligned position p (the stream ends in a zero
+    // pad word, so any word that holds a stream byte is readable)
+    __device__ __forceinline__ uint64_t word(uint64_t p) const {
+        return reinterpret_cast<const uint64_t *>(base.pv.A32)[p >> 3];
+    }
+};
+
 // Upper-bit positions of ones number v0 + lane and v0 + 64 (broadcast) for a
 // 64-aligned v0: sel[v0/64] is select1(v0) and sel[v0/64 + 1] is select1(v0 +
 // 64), so the 65 ones lie in the H words between those two positions.  When
@@ -468,6 +491,11 @@ lg_status dispatch_acc(const lg_graph *g, Fn &&fn) {
                   "(lg_decode_neighbors and lg_pagerank are)");
         return LG_ERR_UNSUPPORTED;
     }
+    if (g->id_mode == LG_IDS_VARINT_FULL || g->id_mode == LG_IDS_VARINT_DIFF) {
+        set_error("Varint lists are read in order only: this operation is not available for them "
+                  "(lg_decode_neighbors is)");
+        return LG_ERR_UNSUPPORTED;
+    }
     const PackedView pv = g->packed_view();
     if (g->id_mode == LG_IDS_GLOBAL) {
         if (g->offset_mode == LG_OFFS_PACKED) return fn(PackedAcc<kIdsGlobal, kOffsPacked>{pv});
@@ -496,6 +524,31 @@ lg_status dispatch_acc_all(const lg_graph *g, Fn &&fn) {
         return fn(GapAcc<kOffsEF>{PackedAcc<kIdsLocal, kOffsEF>{pv}});
     }
     return dispatch_acc(g, fn);
+}
+
+template <class Acc>
+struct IsVarintAcc {
+    static constexpr bool value = false;
+};
+template <int OFM, bool kDiff>
+struct IsVarintAcc<VarintAcc<OFM, kDiff>> {
+    static constexpr bool value = true;
+};
+
+// dispatch_acc_all plus the Varint accessors (the neighbor decode)
+template <class Fn>
+lg_status dispatch_acc_dec(const lg_graph *g, Fn &&fn) {
+    if (g->layout == LG_LAYOUT_PACKED && (g->id_mode == LG_IDS_VARINT_FULL || g->id_mode == LG_IDS_VARINT_DIFF)) {
+        const PackedView pv = g->packed_view();
+        const bool diff = g->id_mode == LG_IDS_VARINT_DIFF;
+        if (g->offset_mode == LG_OFFS_PACKED) {
+            const PackedAcc<kIdsLocal, kOffsPacked> b{pv};
+            return diff ? fn(VarintAcc<kOffsPacked, true>{b}) : fn(VarintAcc<kOffsPacked, false>{b});
+        }
+        const PackedAcc<kIdsLocal, kOffsEF> b{pv};
+        return diff ? fn(VarintAcc<kOffsEF, true>{b}) : fn(VarintAcc<kOffsEF, false>{b});
+    }
+    return dispatch_acc_all(g, fn);
 }
 
 }  // namespace lg

@@ -636,6 +636,64 @@ __global__ void gap_len_kernel(uint32_t n, const uint64_t *__restrict__ off, con
 }
 
 // ---------------------------------------------------------------------------
+// Varint lists (subsection "Incorporating Degree-Minimizing (DM)"): every
+// label (DMf) or the first label and then the differences (DMd), each in
+// base-128 bytes, lowest group first, the top bit set on every byte of a
+// value but its last.  One byte length per edge, an exclusive scan gives
+// every value's byte position, and each lane writes its value's bytes.
+// ---------------------------------------------------------------------------
+
+// head[e] = 1 where a non-empty row starts
+__global__ void varint_head_kernel(uint32_t n, const uint64_t *__restrict__ off, uint8_t *__restrict__ head) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride)
+        if (off[v + 1] > off[v]) head[off[v]] = 1;
+}
+
+template <bool kDiff>
+__device__ __forceinline__ uint32_t varint_value(const uint32_t *__restrict__ col,
+                                                 const uint8_t *__restrict__ head, uint64_t e) {
+    if (!kDiff || e == 0 || head[e]) return col[e];
+    return col[e] - col[e - 1];
+}
+
+__device__ __forceinline__ uint32_t varint_bytes(uint32_t x) {
+    return x < (1u << 7) ? 1u : x < (1u << 14) ? 2u : x < (1u << 21) ? 3u : x < (1u << 28) ? 4u : 5u;
+}
+
+template <bool kDiff>
+__global__ void varint_len_kernel(uint64_t m, const uint32_t *__restrict__ col, const uint8_t *__restrict__ head,
+                                  uint32_t *__restrict__ len) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += stride)
+        len[e] = varint_bytes(varint_value<kDiff>(col, head, e));
+}
+
+// byte start of every list: the position of its first value (count n + 1;
+// pos holds m + 1 entries, the last the stream length)
+__global__ void varint_starts_kernel(uint32_t n, const uint64_t *__restrict__ off, const uint64_t *__restrict__ pos,
+                                     uint64_t *__restrict__ P) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; v <= n; v += stride) P[v] = pos[off[v]];
+}
+
+template <bool kDiff>
+__global__ void varint_write_kernel(uint64_t m, const uint32_t *__restrict__ col, const uint8_t *__restrict__ head,
+                                    const uint64_t *__restrict__ pos, uint8_t *__restrict__ out) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += stride) {
+        uint32_t x = varint_value<kDiff>(col, head, e);
+        uint64_t p = pos[e];
+        for (;;) {
+            const uint32_t low = x & 127u;
+            x >>= 7;
+            out[p++] = (uint8_t)(x ? (low | 128u) : low);
+            if (!x) break;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Elias-Fano upper bits and directory
 // ---------------------------------------------------------------------------
 
@@ -1019,7 +1077,52 @@ static lg_status encode_impl(uint32_t n, uint64_t m, const uint64_t *row_offsets
 
     // -- packed representation ---------------------------------------------
     g->s = idbits ? idbits : 1;
-    if (o.id_mode == LG_IDS_GLOBAL) {
+    if (o.id_mode == LG_IDS_VARINT_FULL || o.id_mode == LG_IDS_VARINT_DIFF) {
+        const bool diff = o.id_mode == LG_IDS_VARINT_DIFF;
+        DevBuf P;
+        LG_TRY(P.scratch(((uint64_t)n + 1) * 8, s));
+        uint64_t total = 0;
+        if (m) {
+            DevBuf head, len, pos;
+            LG_TRY(head.scratch((m + 3) & ~3ull, s));
+            LG_TRY(len.scratch(m * 4, s));
+            LG_TRY(pos.scratch((m + 1) * 8, s));
+            LG_TRY(fill_u32(head.as<uint32_t>(), 0, (m + 3) / 4, s));
+            LG_LAUNCH(varint_head_kernel, grid1(n), 256, 0, s, n, cur_off, head.as<uint8_t>());
+            LG_CHECK_LAUNCH();
+            if (diff)
+                LG_LAUNCH(varint_len_kernel<true>, grid1(m), 256, 0, s, m, cur_col, head.as<uint8_t>(),
+                          len.as<uint32_t>());
+            else
+                LG_LAUNCH(varint_len_kernel<false>, grid1(m), 256, 0, s, m, cur_col, head.as<uint8_t>(),
+                          len.as<uint32_t>());
+            LG_CHECK_LAUNCH();
+            LG_TRY(exclusive_scan_u32(len.as<uint32_t>(), pos.as<uint64_t>(), m, tmp, s));
+            LG_CHECK_HIP(hipMemcpyAsync(&total, pos.as<uint64_t>() + m, 8, hipMemcpyDeviceToHost, s));
+            LG_CHECK_HIP(hipStreamSynchronize(s));
+            g->A_words = (total + 7) / 8 + 1;
+            LG_TRY(g->A.scratch(g->A_words * 8, s));
+            LG_TRY(fill_u64(g->A.as<uint64_t>(), 0, g->A_words, s));
+            if (diff)
+                LG_LAUNCH(varint_write_kernel<true>, grid1(m), 256, 0, s, m, cur_col, head.as<uint8_t>(),
+                          pos.as<uint64_t>(), g->A.as<uint8_t>());
+            else
+                LG_LAUNCH(varint_write_kernel<false>, grid1(m), 256, 0, s, m, cur_col, head.as<uint8_t>(),
+                          pos.as<uint64_t>(), g->A.as<uint8_t>());
+            LG_CHECK_LAUNCH();
+            LG_LAUNCH(varint_starts_kernel, grid1(n + 1ull), 256, 0, s, n, cur_off, pos.as<uint64_t>(),
+                      P.as<uint64_t>());
+            LG_CHECK_LAUNCH();
+            LG_CHECK_HIP(hipStreamSynchronize(s));
+        } else {
+            g->A_words = 1;
+            LG_TRY(g->A.scratch(8, s));
+            LG_TRY(fill_u64(g->A.as<uint64_t>(), 0, 1, s));
+            LG_TRY(fill_u64(P.as<uint64_t>(), 0, (uint64_t)n + 1, s));
+        }
+        g->U = total * 8;
+        LG_TRY(build_offsets(g, P.as<uint64_t>(), total, tmp, s));
+    } else if (o.id_mode == LG_IDS_GLOBAL) {
         g->U = m * g->s;
         LG_TRY(pack_fixed(SrcU32{cur_col}, m, g->s, g->A, g->A_words, s));
         LG_TRY(build_offsets(g, cur_off, m, tmp, s));
@@ -1086,7 +1189,7 @@ extern "C" lg_status lg_encode(uint32_t n, uint64_t m, const uint64_t *row_offse
     if (n == 0 || n >= (1u << 31)) { set_error("lg_encode: n must be in [1, 2^31)"); return LG_ERR_INVALID; }
     if (m >= (1ull << 36)) { set_error("lg_encode: m must be below 2^36"); return LG_ERR_UNSUPPORTED; }
     if (!row_offsets || (m && !col)) { set_error("lg_encode: NULL input array"); return LG_ERR_INVALID; }
-    if (o.layout > LG_LAYOUT_PLAIN || o.id_mode > LG_IDS_LOCAL_GAP || o.offset_mode > LG_OFFS_SUCCINCT ||
+    if (o.layout > LG_LAYOUT_PLAIN || o.id_mode > LG_IDS_VARINT_DIFF || o.offset_mode > LG_OFFS_SUCCINCT ||
         o.relabel > LG_RELABEL_GREEDY || o.flags || o.reserved[0] || o.reserved[1] || o.reserved[2]) {
         set_error("lg_encode: unknown option value");
         return LG_ERR_INVALID;

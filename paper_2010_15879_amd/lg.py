@@ -23,7 +23,7 @@ LG_OK, LG_ERR_INVALID, LG_ERR_OOM, LG_ERR_DEVICE, LG_ERR_UNSUPPORTED, LG_ERR_CAP
 STATUS_NAMES = {0: "LG_OK", 1: "LG_ERR_INVALID", 2: "LG_ERR_OOM", 3: "LG_ERR_DEVICE",
                 4: "LG_ERR_UNSUPPORTED", 5: "LG_ERR_CAPACITY"}
 LAYOUTS = {"packed": 0, "plain": 1}
-ID_MODES = {"global": 0, "local": 1, "local-gap": 2}
+ID_MODES = {"global": 0, "local": 1, "local-gap": 2, "varint-full": 3, "varint-diff": 4}
 OFFSET_MODES = {"packed": 0, "succinct": 1, "ef": 1}
 DECODE_FLAGS = {"sorted": 0, "original": 1, "raw": 2}
 BFS_FLAGS = {"do": 0, "direction-opt": 0, "top-down": 1, "td": 1, "bottom-up": 2, "bu": 2}
