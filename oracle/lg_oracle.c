@@ -314,6 +314,115 @@ ORC_API uint64_t orc_decode_varint_list(const uint8_t *bytes, uint64_t b0, uint6
     return count;
 }
 
+/* ------------------------------------------------------------------ */
+/* Weighted lists -- subsections "Logarithmization of Edge Weights" and */
+/* "Accessing an Edge Weight": each entry is the neighbor ID followed   */
+/* directly by the edge's weight.  Reading: one weight width for the    */
+/* graph, omega = max(1, bl(largest weight)); the ID keeps its global   */
+/* (s) or local (w_v) width, so an entry takes s + omega or w_v + omega */
+/* bits.                                                                 */
+/* ------------------------------------------------------------------ */
+
+ORC_API unsigned orc_weight_width(uint64_t m, const uint32_t *wt) {
+    uint32_t mx = 0;
+    for (uint64_t i = 0; i < m; i++)
+        if (wt[i] > mx) mx = wt[i];
+    const unsigned b = bitlen(mx);
+    return b ? b : 1;
+}
+
+/* w == NULL selects the global width s; `words` holds zeroed words. */
+ORC_API void orc_pack_weighted(uint64_t n, const uint64_t *off, const uint32_t *col, const uint32_t *wt,
+                               const uint8_t *w, unsigned s, unsigned omega, uint64_t *words) {
+    uint64_t pos = 0;
+    for (uint64_t v = 0; v < n; v++) {
+        const unsigned wv = w ? w[v] : s;
+        for (uint64_t i = off[v]; i < off[v + 1]; i++) {
+            put_bits(words, pos, col[i], wv);
+            pos += wv;
+            put_bits(words, pos, wt[i], omega);
+            pos += omega;
+        }
+    }
+}
+
+ORC_API void orc_decode_weighted_list(const uint64_t *words, uint64_t start, uint64_t d, unsigned w,
+                                      unsigned omega, uint32_t *ids, uint32_t *wts) {
+    for (uint64_t i = 0; i < d; i++) {
+        const uint64_t b = start + i * (uint64_t)(w + omega);
+        ids[i] = (uint32_t)get_bits(words, b, w);
+        wts[i] = (uint32_t)get_bits(words, b + w, omega);
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* SSSP (section "Considered Algorithms"): the distances themselves,    */
+/* by Dijkstra's algorithm with a binary heap (lazy deletion).  Entry i */
+/* of row u is the edge u -> col[i] of weight wt[i]; dist = -1 where    */
+/* the root does not reach.                                              */
+/* ------------------------------------------------------------------ */
+
+typedef struct {
+    int64_t d;
+    uint32_t v;
+} heap_item;
+
+static void heap_push(heap_item *h, uint64_t *size, heap_item x) {
+    uint64_t i = (*size)++;
+    h[i] = x;
+    while (i > 0) {
+        const uint64_t p = (i - 1) / 2;
+        if (h[p].d <= h[i].d) break;
+        const heap_item t = h[p];
+        h[p] = h[i];
+        h[i] = t;
+        i = p;
+    }
+}
+
+static heap_item heap_pop(heap_item *h, uint64_t *size) {
+    const heap_item top = h[0];
+    h[0] = h[--(*size)];
+    uint64_t i = 0;
+    for (;;) {
+        const uint64_t l = 2 * i + 1, r = l + 1;
+        uint64_t m = i;
+        if (l < *size && h[l].d < h[m].d) m = l;
+        if (r < *size && h[r].d < h[m].d) m = r;
+        if (m == i) break;
+        const heap_item t = h[m];
+        h[m] = h[i];
+        h[i] = t;
+        i = m;
+    }
+    return top;
+}
+
+ORC_API int orc_sssp(uint64_t n, const uint64_t *off, const uint32_t *col, const uint32_t *wt, uint32_t root,
+                     int64_t *dist) {
+    if (root >= n) return -1;
+    heap_item *h = (heap_item *)malloc(sizeof(heap_item) * (off[n] + 1));
+    if (!h) return -2;
+    for (uint64_t v = 0; v < n; v++) dist[v] = -1;
+    uint64_t size = 0;
+    dist[root] = 0;
+    heap_push(h, &size, (heap_item){0, root});
+    while (size) {
+        const heap_item it = heap_pop(h, &size);
+        if (it.d != dist[it.v]) continue;  // a stale entry
+        for (uint64_t i = off[it.v]; i < off[it.v + 1]; i++) {
+            const int64_t nd = it.d + (int64_t)wt[i];
+            const uint32_t x = col[i];
+            if (dist[x] < 0 || nd < dist[x]) {
+                dist[x] = nd;
+                heap_push(h, &size, (heap_item){nd, x});
+            }
+        }
+    }
+    free(h);
+    return 0;
+}
+
 /* Element i of a list whose first element starts at stream bit `start`. */
 ORC_API void orc_decode_list(const uint64_t *words, uint64_t start, uint64_t d, unsigned w, uint32_t *out) {
     for (uint64_t i = 0; i < d; i++)

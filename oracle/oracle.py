@@ -14,6 +14,7 @@ _lib = None
 u64p = np.ctypeslib.ndpointer(np.uint64, flags="C_CONTIGUOUS")
 u32p = np.ctypeslib.ndpointer(np.uint32, flags="C_CONTIGUOUS")
 i32p = np.ctypeslib.ndpointer(np.int32, flags="C_CONTIGUOUS")
+i64p = np.ctypeslib.ndpointer(np.int64, flags="C_CONTIGUOUS")
 u8p = np.ctypeslib.ndpointer(np.uint8, flags="C_CONTIGUOUS")
 f64p = np.ctypeslib.ndpointer(np.float64, flags="C_CONTIGUOUS")
 
@@ -80,6 +81,10 @@ def lib():
         "orc_varint_byte_starts": (None, [C.c_uint64, u64p, u32p, C.c_int, u64p]),
         "orc_pack_varint": (None, [C.c_uint64, u64p, u32p, C.c_int, u8p]),
         "orc_decode_varint_list": (C.c_uint64, [u8p, C.c_uint64, C.c_uint64, C.c_int, u32p]),
+        "orc_weight_width": (C.c_uint, [C.c_uint64, u32p]),
+        "orc_pack_weighted": (None, [C.c_uint64, u64p, u32p, u32p, _NullableU8, C.c_uint, C.c_uint, u64p]),
+        "orc_decode_weighted_list": (None, [u64p, C.c_uint64, C.c_uint64, C.c_uint, C.c_uint, u32p, u32p]),
+        "orc_sssp": (C.c_int, [C.c_uint64, u64p, u32p, u32p, C.c_uint32, i64p]),
         "orc_relabel_row": (None, [u64p, u32p, u32p, u32p, C.c_uint32, u32p]),
         "orc_bfs_labels": (C.c_int, [C.c_uint64, u64p, u32p, C.c_uint32, C.c_int32, _NullableU32,
                                      i32p, i32p]),
@@ -238,6 +243,46 @@ def decode_varint_list(stream, b0: int, b1: int, diff: bool) -> np.ndarray:
     return out[:cnt]
 
 
+def weight_width(weights) -> int:
+    """omega = max(1, bl(largest weight)): one weight width for the graph
+    (subsection "Logarithmization of Edge Weights")."""
+    wt = np.ascontiguousarray(weights, dtype=np.uint32)
+    return int(lib().orc_weight_width(wt.size, wt if wt.size else np.zeros(1, np.uint32)))
+
+
+def pack_weighted(off, col, weights, widths, s: int, omega: int) -> np.ndarray:
+    """Entries of ID then weight (subsection "Accessing an Edge Weight"); the
+    ID at w_v bits (widths) or s bits (widths None), the weight at omega."""
+    n, off, col = _csr(off, col)
+    wt = np.ascontiguousarray(weights, dtype=np.uint32)
+    per = (off[1:] - off[:-1]) * ((widths.astype(np.uint64) if widths is not None else np.uint64(s)) + omega)
+    U = int(per.sum())
+    words = np.zeros(stream_words(U), dtype=np.uint64)
+    lib().orc_pack_weighted(n, off, col, wt if wt.size else np.zeros(1, np.uint32),
+                            None if widths is None else np.ascontiguousarray(widths, np.uint8), s, omega, words)
+    return words
+
+
+def decode_weighted_list(words, start: int, d: int, w: int, omega: int):
+    words = np.ascontiguousarray(words, dtype=np.uint64)
+    ids = np.zeros(max(d, 1), dtype=np.uint32)
+    wts = np.zeros(max(d, 1), dtype=np.uint32)
+    lib().orc_decode_weighted_list(words, start, d, w, omega, ids, wts)
+    return ids[:d], wts[:d]
+
+
+def sssp(off, col, weights, root: int) -> np.ndarray:
+    """Shortest-path distances from root (int64, -1 where unreachable), by
+    Dijkstra's algorithm: SSSP of section "Considered Algorithms"."""
+    n, off, col = _csr(off, col)
+    wt = np.ascontiguousarray(weights, dtype=np.uint32)
+    dist = np.zeros(max(n, 1), dtype=np.int64)
+    rc = lib().orc_sssp(n, off, col, wt if wt.size else np.zeros(1, np.uint32), root, dist)
+    if rc != 0:
+        raise ValueError(f"orc_sssp failed ({rc})")
+    return dist[:n]
+
+
 def decode_list(words, start: int, d: int, w: int) -> np.ndarray:
     words = np.ascontiguousarray(words, dtype=np.uint64)
     out = np.zeros(max(d, 1), dtype=np.uint32)
@@ -372,10 +417,17 @@ class Encoding:
     "degree" (the degree-minimizing permutation), or "greedy" (the greedy
     heuristic), applied first."""
 
-    def __init__(self, off, col, id_mode="global", offset_mode="packed", relabel=False):
+    def __init__(self, off, col, id_mode="global", offset_mode="packed", relabel=False, weights=None):
         n, off, col = _csr(off, col)
         self.n = n
         self.m = col.size
+        self.omega = 0
+        self.weights = None
+        if weights is not None:
+            if relabel or id_mode not in ("global", "local"):
+                raise ValueError("weighted encodings: global or local IDs, no relabeling")
+            self.weights = np.ascontiguousarray(weights, dtype=np.uint32)
+            self.omega = weight_width(self.weights)
         if relabel:
             if relabel == "greedy":
                 self.perm, self.inv = greedy_permutation(off, col)
@@ -398,8 +450,11 @@ class Encoding:
             universe = self.stream.size
         elif id_mode == "global":
             self.widths = None
-            self.U = adjacency_bits(off, None, self.s)
-            self.A = pack_adjacency(off, col, None, self.s)
+            self.U = adjacency_bits(off, None, self.s + self.omega)
+            if self.weights is None:
+                self.A = pack_adjacency(off, col, None, self.s)
+            else:
+                self.A = pack_weighted(off, col, self.weights, None, self.s, self.omega)
             vals = off
             universe = self.m
         elif id_mode == "local-gap":
@@ -417,14 +472,21 @@ class Encoding:
             self.widths = local_widths(off, col)
             self.F = width_field_bits(n)
             self.W = pack_fixed(self.widths.astype(np.uint64), self.F)
-            self.U = adjacency_bits(off, self.widths, 0)
-            self.A = pack_adjacency(off, col, self.widths, 0)
-            vals = bit_starts(off, self.widths, 0)
+            if self.weights is None:
+                ew = self.widths
+                self.A = pack_adjacency(off, col, self.widths, 0)
+            else:  # an entry takes w_v + omega bits (0 for an empty list)
+                ew = np.where(off[1:] > off[:-1], self.widths.astype(np.int64) + self.omega, 0).astype(np.uint8)
+                self.A = pack_weighted(off, col, self.weights, self.widths, 0, self.omega)
+            self.U = adjacency_bits(off, ew, 0)
+            vals = bit_starts(off, ew, 0)
             universe = self.U
         if self.stream is not None:
             self.P = vals
+        elif self.gwidths is None and self.widths is None:
+            self.P = bit_starts(off, None, self.s + self.omega)
         elif self.gwidths is None:
-            self.P = bit_starts(off, self.widths, self.s if self.widths is None else 0)
+            self.P = vals
         else:
             self.P = vals
         self.offset_values = vals
@@ -436,12 +498,20 @@ class Encoding:
         else:
             self.ef = EF(vals, universe)
 
+    def weights_of(self, x: int) -> np.ndarray:
+        """Weights of the stored list of x, decoded bit by bit."""
+        w = self.s if self.widths is None else int(self.widths[x])
+        d = int(self.off[x + 1] - self.off[x])
+        return decode_weighted_list(self.A, int(self.P[x]), d, w, self.omega)[1]
+
     def neighbors(self, x: int) -> np.ndarray:
         """Stored list of stored label x, decoded bit by bit."""
         if self.stream is not None:
             return decode_varint_list(self.stream, int(self.P[x]), int(self.P[x + 1]), self.diff)
         w = self.s if self.widths is None else int(self.widths[x])
         d = int(self.off[x + 1] - self.off[x])
+        if self.weights is not None:
+            return decode_weighted_list(self.A, int(self.P[x]), d, w, self.omega)[0]
         if self.gwidths is not None:
             return decode_gap_list(self.A, int(self.P[x]), d, w, int(self.gwidths[x]))
         return decode_list(self.A, int(self.P[x]), d, w)

@@ -84,6 +84,7 @@ _STREAM_RMAT = 1
 _STREAM_SCRAMBLE = 2
 _STREAM_ER = 3
 _STREAM_ROOTS = 4
+_STREAM_WEIGHTS = 6
 
 
 def _scramble(v: torch.Tensor, scale: int, seed: int) -> torch.Tensor:
@@ -233,6 +234,21 @@ def kronecker(scale: int, edge_factor: int = 16, seed: int = 1, device="cpu") ->
 def erdos_renyi(scale: int, edge_factor: int = 16, seed: int = 1, device="cpu") -> CSR:
     n, s, d = er_edges(scale, edge_factor, seed, device=device)
     return canonical_csr(n, s, d)
+
+
+def edge_weights(g: CSR, max_weight: int = 255, seed: int = 1) -> torch.Tensor:
+    """int32 weight in [1, max_weight] for every stored entry of g, the same
+    for both directions of an edge (drawn from the stream at the index of the
+    unordered pair): uniform integer weights as the GAP suite draws them for
+    weighted Kronecker graphs."""
+    dev = g.col.device
+    deg = g.row_offsets[1:] - g.row_offsets[:-1]
+    src = torch.repeat_interleave(torch.arange(g.n, device=dev, dtype=torch.int64), deg)
+    dst = g.col.to(torch.int64)
+    pair = torch.minimum(src, dst) * g.n + torch.maximum(src, dst)
+    del src, dst
+    r = uniform53(stream_key(seed, _STREAM_WEIGHTS), pair)
+    return (1 + r % max_weight).to(torch.int32)
 
 
 def pick_roots(g: CSR, count: int = 64, seed: int = 1) -> list:
