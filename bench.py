@@ -95,6 +95,10 @@ def parse():
                         "offsets (ptr32), offsets at bl(universe) bits (ptrW) and Elias-Fano offsets (bvSD): "
                         "degrees only and whole lists "
                         "(own JSON line)")
+    p.add_argument("--sssp", action="store_true",
+                   help="the workload's graph with uniform integer weights in [1, 255]: SSSP from the roots over "
+                        "the weighted plain CSR and the weighted packed encodings, and a sweep of delta "
+                        "(own JSON line)")
     p.add_argument("--encoding-compare", action="store_true",
                    help="the workload's graph with local widths, fixed-size gap encoding and Varint lists (full "
                         "labels or differences), with and without the degree-minimizing relabeling (DMf, DMd): "
@@ -143,6 +147,8 @@ def main():
         return offset_fetch_main(args, np, torch, lg, g)
     if args.encoding_compare:
         return encoding_main(args, np, torch, lg, g)
+    if args.sssp:
+        return sssp_main(args, np, torch, gg, lg, g, roots)
 
     if args.pr_only:
         # A kernel of known traffic calibrates the HBM byte counters (an
@@ -493,6 +499,45 @@ def offset_fetch_main(args, np, torch, lg, g):
         h.free()
     print(json.dumps({"mode": "offset-fetch", "workload": args.workload, "n": n, "stored_edges": g.m,
                       "vertices_per_call": k, "data": "synthetic", "results": res}), flush=True)
+
+
+def sssp_main(args, np, torch, gg, lg, g, roots):
+    """Weighted SSSP (delta-stepping) on the workload's graph, weights uniform
+    integers in [1, 255] (the same for both directions of an edge): the
+    weighted plain CSR against the packed weighted encodings (ID then weight
+    per entry, global or local IDs, Elias-Fano offsets), bytes of the lists
+    and the time of one SSSP per root (median over the roots), then delta
+    swept on the local encoding.  Edges per second count the stored entries
+    of the vertices a root reaches, halved (as the BFS rate)."""
+    n = g.n
+    wt = gg.edge_weights(g, 255, seed=1)
+    deg = g.degrees().to(torch.float64)
+    res = {}
+    encs = [("plain", dict(layout="plain")), ("packed-global", dict(ids="global", offsets="succinct")),
+            ("packed-local", dict(ids="local", offsets="succinct"))]
+    sweep = {}
+    for name, kw in encs:
+        h = lg.encode(g.row_offsets, g.col, n, weights=wt, **kw)
+        info = h.info()
+        times, edges = [], []
+        for r in roots[:8]:
+            d = lg.sssp(h, r)
+            edges.append(float(deg[d >= 0].sum()) / 2.0)
+            times.append(_time_ms(torch, lambda: lg.sssp(h, r), reps=1))
+        med = sorted(times)[len(times) // 2]
+        res[name] = {"adj_bytes": info["adj_bits"] / 8.0 if kw.get("layout") != "plain" else 4.0 * g.m,
+                     "weight_bytes": info["bytes_weights"], "weight_bits": info["weight_bits"],
+                     "sssp_ms_median": round(med, 3),
+                     "gteps_median": round(sorted(e / t * 1e-6 for e, t in zip(edges, times))[len(times) // 2], 3)}
+        log(f"[sssp] {name}: {res[name]}")
+        if name == "packed-local":
+            for delta in (16, 64, 128, 256, 512, 1024, 4096):
+                sweep[delta] = round(_time_ms(torch, lambda: lg.sssp(h, roots[0], delta), reps=1), 3)
+            log(f"[sssp] delta sweep (root {roots[0]}): {sweep}")
+        h.free()
+    print(json.dumps({"mode": "sssp", "workload": args.workload, "n": n, "stored_edges": g.m,
+                      "roots": min(len(roots), 8), "max_weight": 255, "data": "synthetic", "results": res,
+                      "delta_sweep_ms": sweep}), flush=True)
 
 
 def encoding_main(args, np, torch, lg, g):

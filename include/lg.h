@@ -189,6 +189,47 @@ lg_status lg_bfs(const lg_graph *g, const uint32_t *roots, uint32_t r, int32_t *
                  int32_t *parent, int32_t max_depth, uint32_t flags, hipStream_t stream);
 
 /*
+ * lg_encode_weighted -- lg_encode with an integer weight per stored entry
+ * (subsections "Logarithmization of Edge Weights" and "Accessing an Edge
+ * Weight"): in the packed layout each entry is the neighbor ID followed
+ * directly by the weight, the weight at omega = max(1, bl(largest weight))
+ * bits, one width for the whole graph (lg_graph_info.weight_bits); the ID
+ * keeps its global or local width, so the offsets (element offsets or bit
+ * starts) count entries of s + omega or w_v + omega bits.  The plain layout
+ * keeps the weights as a separate uint32 array beside the CSR.
+ *
+ *   weights  dev, uint32[m]; weights[i] belongs to entry i of col (the edge
+ *            from the row's vertex to col[i]); any value, both directions
+ *            of an edge may differ
+ *   other arguments as lg_encode
+ *
+ * Supported: packed layout with LG_IDS_GLOBAL or LG_IDS_LOCAL (packed or
+ * succinct offsets), or the plain layout, without relabeling; other options
+ * return LG_ERR_UNSUPPORTED.  A packed weighted graph is read by lg_sssp
+ * only (the other operations return LG_ERR_UNSUPPORTED); a plain one by
+ * every operation.
+ */
+lg_status lg_encode_weighted(uint32_t n, uint64_t m, const uint64_t *row_offsets, const uint32_t *col,
+                             const uint32_t *weights, const lg_encode_opts *opts, hipStream_t stream,
+                             lg_graph **out);
+
+/*
+ * lg_sssp -- single-source shortest path distances over a weighted graph
+ * (SSSP of section "Considered Algorithms", a delta-stepping traversal):
+ * dist[v] = the smallest sum of weights over the paths from root to v.
+ *
+ *   root     original vertex ID, < n
+ *   delta    bucket width (distances [k delta, (k+1) delta) settle together);
+ *            0 picks a default.  The distances do not depend on it.
+ *   dist     dev, uint64[n]; UINT64_MAX for vertices the root does not reach
+ *
+ * Returns LG_ERR_UNSUPPORTED for an unweighted graph.  Synchronous: the
+ * host reads each step's frontier size back to drive the buckets.  The
+ * workspace is kept with the graph until lg_free.
+ */
+lg_status lg_sssp(const lg_graph *g, uint32_t root, uint32_t delta, uint64_t *dist, hipStream_t stream);
+
+/*
  * lg_pagerank -- pull PageRank without atomics (section "Considered
  * Algorithms"), FP32 storage:
  *   PR_0 = 1/n;  PR_{t+1}(v) = (1-a)/n + a (sum_{u in N_v} PR_t(u)/d_u + D_t/n)
@@ -356,6 +397,9 @@ typedef struct lg_graph_info {
     uint64_t heavy_edges;  /* entries of the heavy lists (0 until first use)     */
     uint64_t heavy_bits;   /* bits of the heavy lists (element bits; 32/entry on
                               the plain layout; 0 until first use)               */
+    uint32_t weight_bits;  /* omega of a weighted graph, else 0                  */
+    uint32_t reserved_w;
+    uint64_t bytes_weights;/* bytes of the separate weight array (plain layout)  */
 } lg_graph_info;
 
 lg_status lg_info(const lg_graph *g, lg_graph_info *out);
@@ -371,6 +415,7 @@ lg_status lg_info(const lg_graph *g, lg_graph_info *out);
 #define LG_EXPORT_PERM 7u      /* uint32 perm[new] = original                     */
 #define LG_EXPORT_INV 8u       /* uint32 inv[original] = new                      */
 #define LG_EXPORT_GAP_WIDTHS 9u /* gap-width-table words (uint64), gap mode       */
+#define LG_EXPORT_WEIGHTS 10u   /* weights (uint32), weighted plain layout        */
 
 /*
  * Copy one raw array of the representation to host memory (synchronous).

@@ -250,7 +250,7 @@ lg::PlainView lg_graph::plain_view() const {
 
 uint64_t lg_graph::device_bytes() const {
     uint64_t b = A.bytes + O.bytes + W.bytes + G.bytes + L.bytes + H.bytes + rank_sb.bytes + sel.bytes + poff.bytes +
-                 pcol.bytes + perm.bytes + inv.bytes + heavy.bytes + iso.bytes + hstart.bytes + hdeg.bytes + hw.bytes +
+                 pcol.bytes + pwt.bytes + perm.bytes + inv.bytes + heavy.bytes + iso.bytes + hstart.bytes + hdeg.bytes + hw.bytes +
                  hg.bytes + seg_off.bytes + seg_map.bytes + seg_part.bytes + seg_base.bytes + units.bytes + (dec ? dec->bytes() : 0);
     return b;
 }
@@ -265,6 +265,7 @@ extern "C" void lg_free(lg_graph *g) {
     (void)hipDeviceSynchronize();
     lg::bfs_free(g);
     lg::pr_free(g);
+    lg::sssp_free(g);
     delete g->dec;
     delete g;
 }
@@ -303,7 +304,9 @@ extern "C" lg_status lg_info(const lg_graph *g, lg_graph_info *out) {
         out->bytes_widths = (g->W_words + g->G_words) * 8;
     }
     out->bytes_perm = g->perm.bytes + g->inv.bytes;
-    out->device_bytes = g->device_bytes() + lg::bfs_bytes(g) + lg::pr_bytes(g);
+    out->device_bytes = g->device_bytes() + lg::bfs_bytes(g) + lg::pr_bytes(g) + lg::sssp_bytes(g);
+    out->weight_bits = g->omega;
+    out->bytes_weights = g->pwt.bytes;
     return LG_OK;
 }
 
@@ -327,6 +330,10 @@ static bool export_src(const lg_graph *g, uint32_t which, const void **p, uint64
         case LG_EXPORT_WIDTHS:
             if (!packed || (g->id_mode != LG_IDS_LOCAL && g->id_mode != LG_IDS_LOCAL_GAP)) return false;
             *p = g->W.p; *bytes = g->W_words * 8;
+            return true;
+        case LG_EXPORT_WEIGHTS:
+            if (packed || !g->weighted) return false;
+            *p = g->pwt.p; *bytes = g->m * 4;
             return true;
         case LG_EXPORT_GAP_WIDTHS:
             if (!packed || g->id_mode != LG_IDS_LOCAL_GAP) return false;

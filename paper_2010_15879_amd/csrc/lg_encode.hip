@@ -636,6 +636,65 @@ __global__ void gap_len_kernel(uint32_t n, const uint64_t *__restrict__ off, con
 }
 
 // ---------------------------------------------------------------------------
+// Weighted entries (subsections "Logarithmization of Edge Weights" and
+// "Accessing an Edge Weight"): the ID, then the weight at omega bits.
+// ---------------------------------------------------------------------------
+
+__global__ void max_u32_kernel(uint64_t count, const uint32_t *__restrict__ x, uint32_t *__restrict__ out) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    uint32_t mx = 0;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride)
+        mx = x[i] > mx ? x[i] : mx;
+#pragma unroll
+    for (int d = kWave / 2; d > 0; d >>= 1) {
+        const uint32_t o = __shfl_xor(mx, d, kWave);
+        mx = o > mx ? o : mx;
+    }
+    if (lane_id() == 0 && mx) atomicMax(out, mx);
+}
+
+// list bit lengths d_v (w_v + omega), local IDs
+__global__ void weighted_len_kernel(uint32_t n, const uint64_t *__restrict__ off, const uint8_t *__restrict__ w8,
+                                    uint32_t omega, uint64_t *__restrict__ len) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride)
+        len[v] = (off[v + 1] - off[v]) * (uint64_t)(w8[v] + omega);
+}
+
+// Entry e at bit e (s + omega) (global IDs) or P_v + (e - off_v)(w_v + omega)
+// (local IDs, the row found by a binary search of the offsets); an entry
+// spans at most two words, ORed into the zeroed stream.
+template <bool kLocal>
+__global__ void pack_weighted_kernel(uint32_t n, uint64_t m, const uint64_t *__restrict__ off,
+                                     const uint32_t *__restrict__ col, const uint32_t *__restrict__ wt,
+                                     const uint8_t *__restrict__ wid, const uint64_t *__restrict__ P, uint32_t s,
+                                     uint32_t omega, unsigned long long *__restrict__ out) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += stride) {
+        uint64_t bit;
+        uint32_t w;
+        if constexpr (kLocal) {
+            uint32_t lo = 0, hi = n;  // off[lo] <= e < off[hi]
+            while (hi - lo > 1) {
+                const uint32_t mid = lo + (hi - lo) / 2;
+                if (off[mid] <= e) lo = mid;
+                else hi = mid;
+            }
+            w = wid[lo];
+            bit = P[lo] + (e - off[lo]) * (uint64_t)(w + omega);
+        } else {
+            w = s;
+            bit = e * (uint64_t)(s + omega);
+        }
+        const uint64_t val = (uint64_t)col[e] | ((uint64_t)wt[e] << w);
+        const uint32_t sh = (uint32_t)(bit & 63);
+        const uint64_t k = bit >> 6;
+        atomicOr(&out[k], (unsigned long long)(val << sh));
+        if (sh + w + omega > 64) atomicOr(&out[k + 1], (unsigned long long)(val >> (64 - sh)));
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Varint lists (subsection "Incorporating Degree-Minimizing (DM)"): every
 // label (DMf) or the first label and then the differences (DMd), each in
 // base-128 bytes, lowest group first, the top bit set on every byte of a
@@ -910,7 +969,7 @@ static lg_status greedy_permutation(uint32_t n, const uint64_t *off, const uint3
 }
 
 static lg_status encode_impl(uint32_t n, uint64_t m, const uint64_t *row_offsets, const uint32_t *col,
-                             const lg_encode_opts &o, hipStream_t s, lg_graph *g) {
+                             const uint32_t *weights, const lg_encode_opts &o, hipStream_t s, lg_graph *g) {
     DevBuf tmp, status, deg, stats;
     LG_CHECK_HIP(hipGetDevice(&g->device));
 
@@ -968,6 +1027,18 @@ static lg_status encode_impl(uint32_t n, uint64_t m, const uint64_t *row_offsets
     LG_CHECK_HIP(hipStreamSynchronize(s));
     g->max_degree = st[0];
     g->isolated = st[1];
+    if (weights) {
+        g->weighted = true;
+        uint32_t wmax = 0;
+        if (m) {
+            LG_TRY(fill_u32(stats.as<uint32_t>(), 0, 1, s));
+            LG_LAUNCH(max_u32_kernel, grid1(m), 256, 0, s, m, weights, stats.as<uint32_t>());
+            LG_CHECK_LAUNCH();
+            LG_CHECK_HIP(hipMemcpyAsync(&wmax, stats.p, 4, hipMemcpyDeviceToHost, s));
+            LG_CHECK_HIP(hipStreamSynchronize(s));
+        }
+        g->omega = wmax ? bitlen_u64(wmax) : 1u;
+    }
 
     // -- relabeling --------------------------------------------------------
     const uint64_t *cur_off = row_offsets;
@@ -1071,6 +1142,10 @@ static lg_status encode_impl(uint32_t n, uint64_t m, const uint64_t *row_offsets
             LG_TRY(g->pcol.scratch((m ? m : 1) * 4, s));
             if (m) LG_CHECK_HIP(hipMemcpyAsync(g->pcol.p, cur_col, m * 4, hipMemcpyDeviceToDevice, s));
         }
+        if (weights) {
+            LG_TRY(g->pwt.scratch((m ? m : 1) * 4, s));
+            if (m) LG_CHECK_HIP(hipMemcpyAsync(g->pwt.p, weights, m * 4, hipMemcpyDeviceToDevice, s));
+        }
         LG_CHECK_HIP(hipStreamSynchronize(s));
         return LG_OK;
     }
@@ -1122,6 +1197,44 @@ static lg_status encode_impl(uint32_t n, uint64_t m, const uint64_t *row_offsets
         }
         g->U = total * 8;
         LG_TRY(build_offsets(g, P.as<uint64_t>(), total, tmp, s));
+    } else if (o.id_mode == LG_IDS_GLOBAL && weights) {
+        g->U = m * (uint64_t)(g->s + g->omega);
+        g->A_words = (g->U + 63) / 64 + 1;
+        LG_TRY(g->A.scratch(g->A_words * 8, s));
+        LG_TRY(fill_u64(g->A.as<uint64_t>(), 0, g->A_words, s));
+        if (m) {
+            LG_LAUNCH(pack_weighted_kernel<false>, grid1(m), 256, 0, s, n, m, cur_off, cur_col, weights,
+                      (const uint8_t *)nullptr, (const uint64_t *)nullptr, g->s, g->omega,
+                      g->A.as<unsigned long long>());
+            LG_CHECK_LAUNCH();
+        }
+        LG_TRY(build_offsets(g, cur_off, m, tmp, s));
+    } else if (o.id_mode == LG_IDS_LOCAL && weights) {
+        g->F = bitlen_u64(g->s);
+        DevBuf w8, len, P;
+        LG_TRY(w8.scratch((uint64_t)n, s));
+        LG_TRY(len.scratch((uint64_t)n * 8, s));
+        LG_TRY(P.scratch(((uint64_t)n + 1) * 8, s));
+        LG_LAUNCH(local_width_kernel, grid1(n), 256, 0, s, n, cur_off, cur_col, w8.as<uint8_t>(),
+                  len.as<uint64_t>());
+        LG_CHECK_LAUNCH();
+        LG_LAUNCH(weighted_len_kernel, grid1(n), 256, 0, s, n, cur_off, w8.as<uint8_t>(), g->omega,
+                  len.as<uint64_t>());
+        LG_CHECK_LAUNCH();
+        LG_TRY(exclusive_scan_u64(len.as<uint64_t>(), P.as<uint64_t>(), n, tmp, s));
+        LG_CHECK_HIP(hipMemcpyAsync(&g->U, P.as<uint64_t>() + n, 8, hipMemcpyDeviceToHost, s));
+        LG_CHECK_HIP(hipStreamSynchronize(s));
+        LG_TRY(pack_fixed(SrcU8{w8.as<uint8_t>()}, n, g->F, g->W, g->W_words, s));
+        g->A_words = (g->U + 63) / 64 + 1;
+        LG_TRY(g->A.scratch(g->A_words * 8, s));
+        LG_TRY(fill_u64(g->A.as<uint64_t>(), 0, g->A_words, s));
+        if (m) {
+            LG_LAUNCH(pack_weighted_kernel<true>, grid1(m), 256, 0, s, n, m, cur_off, cur_col, weights,
+                      w8.as<uint8_t>(), P.as<uint64_t>(), g->s, g->omega, g->A.as<unsigned long long>());
+            LG_CHECK_LAUNCH();
+        }
+        LG_TRY(build_offsets(g, P.as<uint64_t>(), g->U, tmp, s));
+        LG_CHECK_HIP(hipStreamSynchronize(s));
     } else if (o.id_mode == LG_IDS_GLOBAL) {
         g->U = m * g->s;
         LG_TRY(pack_fixed(SrcU32{cur_col}, m, g->s, g->A, g->A_words, s));
@@ -1176,11 +1289,46 @@ static lg_status encode_impl(uint32_t n, uint64_t m, const uint64_t *row_offsets
     return LG_OK;
 }
 
+static lg_status encode_entry(uint32_t n, uint64_t m, const uint64_t *row_offsets, const uint32_t *col,
+                              const uint32_t *weights, const lg_encode_opts *opts, hipStream_t stream,
+                              lg_graph **out);
+
 }  // namespace lg
 
 extern "C" lg_status lg_encode(uint32_t n, uint64_t m, const uint64_t *row_offsets, const uint32_t *col,
                                const lg_encode_opts *opts, hipStream_t stream, lg_graph **out) {
+    return lg::encode_entry(n, m, row_offsets, col, nullptr, opts, stream, out);
+}
+
+extern "C" lg_status lg_encode_weighted(uint32_t n, uint64_t m, const uint64_t *row_offsets, const uint32_t *col,
+                                        const uint32_t *weights, const lg_encode_opts *opts, hipStream_t stream,
+                                        lg_graph **out) {
     using namespace lg;
+    if (!weights && m) {
+        if (out) *out = nullptr;
+        set_error("lg_encode_weighted: weights is NULL");
+        return LG_ERR_INVALID;
+    }
+    lg_encode_opts o;
+    std::memset(&o, 0, sizeof(o));
+    if (opts) o = *opts;
+    if (o.relabel != LG_RELABEL_NONE ||
+        (o.layout == LG_LAYOUT_PACKED && o.id_mode != LG_IDS_GLOBAL && o.id_mode != LG_IDS_LOCAL)) {
+        if (out) *out = nullptr;
+        set_error("lg_encode_weighted: weighted graphs take global or local IDs (or the plain layout) and no "
+                  "relabeling");
+        return LG_ERR_UNSUPPORTED;
+    }
+    // a non-NULL marker when there are no entries, so the graph is weighted
+    static const uint32_t kNone = 0;
+    return encode_entry(n, m, row_offsets, col, weights ? weights : &kNone, opts, stream, out);
+}
+
+namespace lg {
+
+static lg_status encode_entry(uint32_t n, uint64_t m, const uint64_t *row_offsets, const uint32_t *col,
+                              const uint32_t *weights, const lg_encode_opts *opts, hipStream_t stream,
+                              lg_graph **out) {
     if (!out) { set_error("lg_encode: out is NULL"); return LG_ERR_INVALID; }
     *out = nullptr;
     lg_encode_opts o;
@@ -1202,7 +1350,7 @@ extern "C" lg_status lg_encode(uint32_t n, uint64_t m, const uint64_t *row_offse
     g->id_mode = o.layout == LG_LAYOUT_PACKED ? o.id_mode : 0;
     g->offset_mode = o.layout == LG_LAYOUT_PACKED ? o.offset_mode : 0;
     g->relabel = o.relabel;
-    const lg_status st = encode_impl(n, m, row_offsets, col, o, stream, g);
+    const lg_status st = encode_impl(n, m, row_offsets, col, weights, o, stream, g);
     if (st != LG_OK) {
         (void)hipStreamSynchronize(stream);
         lg_free(g);
@@ -1211,3 +1359,5 @@ extern "C" lg_status lg_encode(uint32_t n, uint64_t m, const uint64_t *row_offse
     *out = g;
     return LG_OK;
 }
+
+}  // namespace lg

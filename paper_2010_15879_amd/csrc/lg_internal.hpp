@@ -83,6 +83,7 @@ namespace lg {
 // ---------------------------------------------------------------------------
 
 struct PrWork;
+struct SsspWork;
 
 // Device workspace of one BFS at a time (grow-only buffers).
 struct BfsWork {
@@ -150,6 +151,13 @@ struct lg_graph {
     lg::DevBuf poff, pcol;
     bool poff64 = false;
 
+    // weighted graphs: omega = weight width (each packed entry is the ID,
+    // then the weight); the plain layout keeps one uint32 weight per entry
+    // in pwt
+    bool weighted = false;
+    uint32_t omega = 0;
+    lg::DevBuf pwt;
+
     // relabeling: perm[new] = old, inv[old] = new
     lg::DevBuf perm, inv;
 
@@ -186,6 +194,7 @@ struct lg_graph {
     lg::BfsWork *bfs = nullptr;
     lg::PrWork *pr = nullptr;
     lg::DecodeWork *dec = nullptr;
+    lg::SsspWork *sssp = nullptr;
 
     lg::PackedView packed_view() const;
     lg::PlainView plain_view() const;
@@ -286,5 +295,7 @@ lg_status bfs_run(lg_graph *g, BfsWork &w, const uint32_t *roots, uint32_t r, in
 lg_status decode_run(lg_graph *g, DecodeWork &w, const uint32_t *vertices, uint32_t k, uint64_t *out_off,
                      uint32_t *out_ids, uint64_t cap, uint32_t flags, hipStream_t stream, uint64_t *total);
 lg_status pr_free(lg_graph *g);
+lg_status sssp_free(lg_graph *g);
+uint64_t sssp_bytes(const lg_graph *g);
 
 }  // namespace lg

@@ -1,0 +1,241 @@
+// lg_sssp: single-source shortest paths over a weighted graph (SSSP of
+// section "Considered Algorithms", a delta-stepping traversal), reading the
+// weight stored right after each ID (subsection "Accessing an Edge Weight").
+//
+// Distances are uint64 (UINT64_MAX: not reached).  A bitmap marks vertices
+// whose distance dropped since their edges were last relaxed.  Each step of
+// bucket k (distances below hi = (k+1) delta):
+//   collect  one wave per 64-vertex word of the bitmap: marked vertices with
+//            a distance below hi leave the bitmap and, when they have edges,
+//            join the frontier queue with their list start, ID width, degree
+//            and distance; the smallest distance among the marked vertices
+//            left behind is kept for choosing the next bucket
+//   relax    the frontier's edges, flattened by an exclusive scan of the
+//            degrees, 64 consecutive edges per wave step: nd = dist(u) + w;
+//            an atomic minimum on dist(v), and v is marked when it lowered it
+// An empty frontier moves to the bucket of the smallest marked distance;
+// none marked ends the search.  Every vertex relaxed from a distance d
+// reaches the final distances of the paths through it, so the result is the
+// exact distances whatever delta and the order of the atomics.
+#include <algorithm>
+
+#include "lg_device.hpp"
+
+namespace lg {
+
+constexpr uint64_t kInfDist = ~0ull;
+constexpr uint32_t kSsspDefaultDelta = 1024;
+
+struct SsspWork {
+    DevBuf upd;                         // bitmap, one bit per vertex
+    DevBuf queue, qw, qdeg;             // frontier: vertex, ID width, degree
+    DevBuf qstart, qdist, qoff;         // list start, distance, exclusive scan of qdeg
+    DevBuf ctr;                         // [0] frontier size, [1] smallest distance left marked
+    DevBuf scan_tmp;
+    uint64_t *host = nullptr;           // pinned readback slots
+    SsspWork() = default;
+    SsspWork(const SsspWork &) = delete;
+    SsspWork &operator=(const SsspWork &) = delete;
+    ~SsspWork() {
+        if (host) (void)hipHostFree(host);
+    }
+    uint64_t bytes() const {
+        return upd.bytes + queue.bytes + qw.bytes + qdeg.bytes + qstart.bytes + qdist.bytes + qoff.bytes + ctr.bytes +
+               scan_tmp.bytes;
+    }
+};
+
+uint64_t sssp_bytes(const lg_graph *g) { return g->sssp ? g->sssp->bytes() : 0; }
+
+lg_status sssp_free(lg_graph *g) {
+    delete g->sssp;
+    g->sssp = nullptr;
+    return LG_OK;
+}
+
+__global__ void sssp_init_kernel(uint32_t n, uint64_t words, uint32_t root, uint64_t *__restrict__ dist,
+                                 uint64_t *__restrict__ upd) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    const uint64_t total = n > words ? n : words;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) {
+        if (i < n) dist[i] = i == root ? 0ull : kInfDist;
+        if (i < words) upd[i] = i == (root >> 6) ? 1ull << (root & 63) : 0ull;
+    }
+}
+
+// ctr[0] = 0 (frontier size), ctr[1] = no marked distance left
+__global__ void sssp_ctr_kernel(unsigned long long *__restrict__ ctr) {
+    if (threadIdx.x == 0) {
+        ctr[0] = 0ull;
+        ctr[1] = kInfDist;
+    }
+}
+
+template <class Acc>
+__global__ void sssp_collect_kernel(Acc acc, uint32_t n, uint64_t words, uint64_t hi,
+                                    const uint64_t *__restrict__ dist, uint64_t *__restrict__ upd,
+                                    uint32_t *__restrict__ queue, uint64_t *__restrict__ qstart,
+                                    uint32_t *__restrict__ qw, uint32_t *__restrict__ qdeg,
+                                    uint64_t *__restrict__ qdist, unsigned long long *__restrict__ ctr) {
+    const uint32_t lane = lane_id();
+    const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) / kWave;
+    for (uint64_t q = wave; q < words; q += nwaves) {
+        const uint64_t bits = upd[q];
+        if (!bits) continue;  // same for every lane
+        const uint64_t v = q * 64 + lane;
+        const bool set = ((bits >> lane) & 1ull) && v < n;
+        const uint64_t d = set ? dist[v] : kInfDist;
+        const bool take = set && d < hi;
+        const uint64_t tmask = __ballot(take);
+        // the smallest distance staying marked
+        uint64_t left = set && !take ? d : kInfDist;
+#pragma unroll
+        for (int s = kWave / 2; s > 0; s >>= 1) {
+            const uint64_t o = __shfl_xor(left, s, kWave);
+            left = o < left ? o : left;
+        }
+        if (lane == 0) {
+            if (tmask) upd[q] = bits & ~tmask;
+            if (left != kInfDist) atomicMin(&ctr[1], (unsigned long long)left);
+        }
+        if (!tmask) continue;
+        WInfo vi{0, 0, 0};
+        if (take) vi = acc.info((uint32_t)v);
+        const bool enq = take && vi.deg > 0;
+        const uint64_t emask = __ballot(enq);
+        if (!emask) continue;
+        unsigned long long base = 0;
+        if (lane == 0) base = atomicAdd(&ctr[0], (unsigned long long)__popcll(emask));
+        base = __shfl(base, 0, kWave);
+        if (enq) {
+            const uint64_t pos = base + popc_below(emask);
+            queue[pos] = (uint32_t)v;
+            qstart[pos] = vi.start;
+            qw[pos] = vi.w;
+            qdeg[pos] = vi.deg;
+            qdist[pos] = d;
+        }
+    }
+}
+
+// Edge t of the frontier belongs to slot s with qoff[s] <= t < qoff[s + 1];
+// every slot has at least one edge, so 64 consecutive edges lie in at most
+// 64 consecutive slots: one search for the step's first edge over the whole
+// scan, then each lane searches the next 64 slots.
+template <class Acc>
+__global__ void sssp_relax_kernel(Acc acc, uint32_t n, const uint64_t *__restrict__ count_p,
+                                  const uint64_t *__restrict__ qoff, const uint64_t *__restrict__ qstart,
+                                  const uint32_t *__restrict__ qw, const uint64_t *__restrict__ qdist,
+                                  unsigned long long *__restrict__ dist, unsigned long long *__restrict__ upd) {
+    const uint32_t lane = lane_id();
+    const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) / kWave;
+    const uint64_t count = *count_p;
+    const uint64_t E = qoff[count];
+    for (uint64_t t0 = wave * kWave; t0 < E; t0 += nwaves * kWave) {
+        uint64_t lo = 0, hi = count;  // qoff[lo] <= t0 < qoff[hi]
+        while (hi - lo > 1) {
+            const uint64_t mid = lo + (hi - lo) / 2;
+            if (qoff[mid] <= t0) lo = mid;
+            else hi = mid;
+        }
+        const uint64_t t = t0 + lane;
+        if (t >= E) continue;
+        uint64_t a = lo, b = lo + kWave < count ? lo + kWave : count;  // qoff[a] <= t < qoff[b]
+        while (b - a > 1) {
+            const uint64_t mid = a + (b - a) / 2;
+            if (qoff[mid] <= t) a = mid;
+            else b = mid;
+        }
+        uint32_t id, w;
+        acc.entry(qstart[a], qw[a], t - qoff[a], id, w);
+        if (id >= n) continue;  // only a corrupt stream gets here
+        const unsigned long long nd = qdist[a] + (unsigned long long)w;
+        if (nd < dist[id]) {
+            const unsigned long long old = atomicMin(&dist[id], nd);
+            if (nd < old) atomicOr(&upd[id >> 6], 1ull << (id & 63));
+        }
+    }
+}
+
+}  // namespace lg
+
+extern "C" lg_status lg_sssp(const lg_graph *gc, uint32_t root, uint32_t delta, uint64_t *dist, hipStream_t stream) {
+    using namespace lg;
+    lg_graph *g = const_cast<lg_graph *>(gc);
+    if (!g || !dist) { set_error("lg_sssp: NULL argument"); return LG_ERR_INVALID; }
+    if (root >= g->n) { set_error("lg_sssp: root %u >= n", root); return LG_ERR_INVALID; }
+    if (!g->weighted) {
+        set_error("lg_sssp: the graph has no edge weights (build it with lg_encode_weighted)");
+        return LG_ERR_UNSUPPORTED;
+    }
+    const uint64_t D = delta ? delta : kSsspDefaultDelta;
+    const uint32_t n = g->n;
+    const uint64_t words = ((uint64_t)n + 63) / 64;
+    if (!g->sssp) {
+        g->sssp = new (std::nothrow) SsspWork();
+        if (!g->sssp) { set_error("lg_sssp: host allocation failed"); return LG_ERR_OOM; }
+    }
+    SsspWork &W = *g->sssp;
+    if (!W.host) {
+        if (hipHostMalloc((void **)&W.host, 4 * sizeof(uint64_t)) != hipSuccess) {
+            W.host = nullptr;
+            set_error("lg_sssp: pinned host allocation failed");
+            return LG_ERR_OOM;
+        }
+    }
+    LG_TRY(W.upd.ensure(words * 8));
+    LG_TRY(W.queue.ensure((uint64_t)n * 4));
+    LG_TRY(W.qw.ensure((uint64_t)n * 4));
+    LG_TRY(W.qdeg.ensure((uint64_t)n * 4));
+    LG_TRY(W.qstart.ensure((uint64_t)n * 8));
+    LG_TRY(W.qdist.ensure((uint64_t)n * 8));
+    LG_TRY(W.qoff.ensure(((uint64_t)n + 1) * 8));
+    LG_TRY(W.ctr.ensure(16));
+    LG_LAUNCH(sssp_init_kernel, grid_for(std::max<uint64_t>(n, words), 256, 1u << 16), 256, 0, stream, n, words, root,
+              dist, W.upd.as<uint64_t>());
+    LG_CHECK_LAUNCH();
+    return dispatch_wacc(g, [&](auto acc) -> lg_status {
+        using Acc = decltype(acc);
+        int cus = 0;
+        LG_CHECK_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, g->device));
+        const uint32_t collect_grid = grid_for(words * kWave, 256, 1u << 16);
+        const uint32_t relax_grid = (uint32_t)std::max(1, cus) * 8;
+        uint64_t hi = D;
+        // every step either relaxes a non-empty frontier (each entry of it
+        // lowered a distance) or moves to a later bucket: bounded for
+        // non-negative weights; the cap only guards against a corrupt graph
+        const uint64_t cap = 64ull * n + 1024;
+        for (uint64_t step = 0;; ++step) {
+            if (step > cap) {
+                set_error("lg_sssp: no convergence after %llu steps", (unsigned long long)step);
+                return LG_ERR_DEVICE;
+            }
+            LG_LAUNCH(sssp_ctr_kernel, 1, 64, 0, stream, W.ctr.as<unsigned long long>());
+            LG_CHECK_LAUNCH();
+            LG_LAUNCH(sssp_collect_kernel<Acc>, collect_grid, 256, 0, stream, acc, n, words, hi,
+                      (const uint64_t *)dist, W.upd.as<uint64_t>(), W.queue.as<uint32_t>(), W.qstart.as<uint64_t>(),
+                      W.qw.as<uint32_t>(), W.qdeg.as<uint32_t>(), W.qdist.as<uint64_t>(),
+                      W.ctr.as<unsigned long long>());
+            LG_CHECK_LAUNCH();
+            LG_CHECK_HIP(hipMemcpyAsync(W.host, W.ctr.p, 16, hipMemcpyDeviceToHost, stream));
+            LG_CHECK_HIP(hipStreamSynchronize(stream));
+            const uint64_t count = W.host[0], left = W.host[1];
+            if (count == 0) {
+                if (left == kInfDist) break;
+                const uint64_t k = left / D;
+                hi = k + 1 > kInfDist / D ? kInfDist : (k + 1) * D;
+                continue;
+            }
+            LG_TRY(exclusive_scan_u32(W.qdeg.as<uint32_t>(), W.qoff.as<uint64_t>(), count, W.scan_tmp, stream));
+            LG_LAUNCH(sssp_relax_kernel<Acc>, relax_grid, 256, 0, stream, acc, n,
+                      (const uint64_t *)W.ctr.as<uint64_t>(), (const uint64_t *)W.qoff.as<uint64_t>(),
+                      (const uint64_t *)W.qstart.as<uint64_t>(), (const uint32_t *)W.qw.as<uint32_t>(),
+                      (const uint64_t *)W.qdist.as<uint64_t>(), (unsigned long long *)dist,
+                      W.upd.as<unsigned long long>());
+            LG_CHECK_LAUNCH();
+        }
+        return LG_OK;
+    });
+}

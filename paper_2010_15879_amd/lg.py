@@ -28,8 +28,9 @@ OFFSET_MODES = {"packed": 0, "succinct": 1, "ef": 1}
 DECODE_FLAGS = {"sorted": 0, "original": 1, "raw": 2}
 BFS_FLAGS = {"do": 0, "direction-opt": 0, "top-down": 1, "td": 1, "bottom-up": 2, "bu": 2}
 EXPORTS = {"adj": 0, "offsets": 1, "widths": 2, "ef_low": 3, "ef_high": 4, "ef_rank": 5,
-           "ef_select": 6, "perm": 7, "inv": 8, "gap_widths": 9}
-_EXPORT_DTYPE = {"ef_rank": np.uint32, "ef_select": np.uint32, "perm": np.uint32, "inv": np.uint32}
+           "ef_select": 6, "perm": 7, "inv": 8, "gap_widths": 9, "weights": 10}
+_EXPORT_DTYPE = {"ef_rank": np.uint32, "ef_select": np.uint32, "perm": np.uint32, "inv": np.uint32,
+                 "weights": np.uint32}
 
 
 class LGError(RuntimeError):
@@ -51,7 +52,8 @@ class GraphInfo(C.Structure):
                 ("bytes_offsets", C.c_uint64), ("bytes_widths", C.c_uint64), ("bytes_perm", C.c_uint64),
                 ("device_bytes", C.c_uint64), ("max_degree", C.c_uint32), ("isolated", C.c_uint32),
                 ("heavy_threshold", C.c_uint32), ("n_heavy", C.c_uint32), ("n_segments", C.c_uint64),
-                ("heavy_edges", C.c_uint64), ("heavy_bits", C.c_uint64)]
+                ("heavy_edges", C.c_uint64), ("heavy_bits", C.c_uint64), ("weight_bits", C.c_uint32),
+                ("reserved_w", C.c_uint32), ("bytes_weights", C.c_uint64)]
 
 
 class BfsJob(C.Structure):
@@ -100,6 +102,9 @@ FUNCTIONS = {
     "lg_bfs": (C.c_int, [C.c_void_p, C.POINTER(C.c_uint32), C.c_uint32, C.c_void_p, C.c_void_p, C.c_int32,
                          C.c_uint32, C.c_void_p]),
     "lg_pagerank": (C.c_int, [C.c_void_p, C.c_float, C.c_uint32, C.c_void_p, C.c_void_p]),
+    "lg_encode_weighted": (C.c_int, [C.c_uint32, C.c_uint64, C.c_void_p, C.c_void_p, C.c_void_p,
+                                     C.POINTER(EncodeOpts), C.c_void_p, C.POINTER(C.c_void_p)]),
+    "lg_sssp": (C.c_int, [C.c_void_p, C.c_uint32, C.c_uint32, C.c_void_p, C.c_void_p]),
     "lg_free": (None, [C.c_void_p]),
     "lg_info": (C.c_int, [C.c_void_p, C.POINTER(GraphInfo)]),
     "lg_export": (C.c_int, [C.c_void_p, C.c_uint32, C.c_void_p, C.c_uint64]),
@@ -217,10 +222,12 @@ class Graph:
 
 
 def encode(row_offsets: torch.Tensor, col: torch.Tensor, n: Optional[int] = None, *, layout="packed",
-           ids="global", offsets="packed", relabel=False, stream=None) -> Graph:
+           ids="global", offsets="packed", relabel=False, weights: Optional[torch.Tensor] = None,
+           stream=None) -> Graph:
     """lg_encode over a device CSR (row_offsets int64[n+1], col int32[M]).
     relabel: False, True or "degree" (degree-minimizing), or "greedy" (the
-    greedy heuristic)."""
+    greedy heuristic).  weights (int32[M] on the device, non-negative): an
+    edge weight per entry, through lg_encode_weighted."""
     n = row_offsets.numel() - 1 if n is None else n
     m = col.numel()
     if relabel is True or relabel == "degree":
@@ -233,10 +240,25 @@ def encode(row_offsets: torch.Tensor, col: torch.Tensor, n: Optional[int] = None
         raise ValueError(f"relabel must be False, True, 'degree' or 'greedy', not {relabel!r}")
     opts = EncodeOpts(LAYOUTS[layout], ID_MODES[ids], OFFSET_MODES[offsets], rl, 0)
     out = C.c_void_p()
+    if weights is not None:
+        if weights.numel() != m:
+            raise ValueError("weights must hold one value per entry of col")
+        _check(lib().lg_encode_weighted(n, m, _dev_ptr(row_offsets, torch.int64, "row_offsets"),
+                                        _dev_ptr(col, torch.int32, "col") if m else None,
+                                        _dev_ptr(weights, torch.int32, "weights") if m else None, C.byref(opts),
+                                        _stream(stream), C.byref(out)))
+        return Graph(out.value, n, m)
     _check(lib().lg_encode(n, m, _dev_ptr(row_offsets, torch.int64, "row_offsets"),
                            _dev_ptr(col, torch.int32, "col") if m else None, C.byref(opts), _stream(stream),
                            C.byref(out)))
     return Graph(out.value, n, m)
+
+
+def sssp(g: Graph, root: int, delta: int = 0, stream=None) -> torch.Tensor:
+    """lg_sssp: int64[n] distances from root (-1 where not reached)."""
+    dist = torch.empty(g.n, dtype=torch.int64, device=torch.device("cuda", torch.cuda.current_device()))
+    _check(lib().lg_sssp(g.handle, int(root), int(delta), C.c_void_p(dist.data_ptr()), _stream(stream)))
+    return dist
 
 
 def decode_neighbors(g: Graph, vertices: torch.Tensor, flags="sorted", cap: Optional[int] = None, stream=None):

@@ -37,7 +37,7 @@ def test_binding_matches_header():
 def test_struct_layouts():
     # lg_encode_opts: 8 uint32; lg_graph_info: fields in header order
     assert ctypes.sizeof(lg.EncodeOpts) == 32
-    assert ctypes.sizeof(lg.GraphInfo) == 2 * 8 + 8 * 4 + 8 * 8 + 4 * 4 + 3 * 8
+    assert ctypes.sizeof(lg.GraphInfo) == 2 * 8 + 8 * 4 + 8 * 8 + 4 * 4 + 3 * 8 + 2 * 4 + 8
 
 
 def test_oracle_is_not_reachable_from_the_product():
