@@ -555,80 +555,4 @@ lg_status dispatch_acc_dec(const lg_graph *g, Fn &&fn) {
     return dispatch_acc_all(g, fn);
 }
 
-// ---------------------------------------------------------------------------
-// Weighted entries (subsections "Logarithmization of Edge Weights" and
-// "Accessing an Edge Weight"): packed, each entry is the ID at its width w
-// followed by the weight at omega bits; plain, the CSR plus a weight array.
-// ---------------------------------------------------------------------------
-
-// start: first bit (packed) or first index (plain); w: ID width
-struct WInfo {
-    uint64_t start;
-    uint32_t deg;
-    uint32_t w;
-};
-
-template <int IDM, int OFM>
-struct WPackedAcc {
-    PackedAcc<IDM, OFM> base;
-    uint32_t omega;
-
-    __device__ __forceinline__ WInfo info(uint32_t v) const {
-        uint64_t o0, o1;
-        base.offsets(v, o0, o1);
-        WInfo r;
-        if constexpr (IDM == kIdsGlobal) {
-            r.w = base.pv.s;
-            r.start = o0 * (uint64_t)(r.w + omega);
-            r.deg = (uint32_t)(o1 - o0);
-        } else {
-            r.w = base.width(v);
-            r.start = o0;
-            r.deg = o1 > o0 ? (uint32_t)((o1 - o0) / (uint64_t)(r.w + omega)) : 0u;
-        }
-        return r;
-    }
-    __device__ __forceinline__ void entry(uint64_t start, uint32_t w, uint64_t i, uint32_t &id, uint32_t &wt) const {
-        const uint64_t b = start + i * (uint64_t)(w + omega);
-        id = base.get(b, width_mask(w));
-        wt = base.get(b + w, width_mask(omega));
-    }
-};
-
-template <bool OFF64>
-struct WPlainAcc {
-    PlainAcc<OFF64> base;
-    const uint32_t *wt;
-
-    __device__ __forceinline__ WInfo info(uint32_t v) const {
-        const VInfo vi = base.info(v);
-        return WInfo{vi.start, vi.deg, 32u};
-    }
-    __device__ __forceinline__ void entry(uint64_t start, uint32_t, uint64_t i, uint32_t &id, uint32_t &w) const {
-        id = base.pv.col[start + i];
-        w = wt[start + i];
-    }
-};
-
-template <class Fn>
-lg_status dispatch_wacc(const lg_graph *g, Fn &&fn) {
-    if (!g->weighted) {
-        set_error("the graph has no edge weights (build it with lg_encode_weighted)");
-        return LG_ERR_UNSUPPORTED;
-    }
-    if (g->layout == LG_LAYOUT_PLAIN) {
-        const uint32_t *wt = g->pwt.as<uint32_t>();
-        if (g->poff64) return fn(WPlainAcc<true>{PlainAcc<true>{g->plain_view()}, wt});
-        return fn(WPlainAcc<false>{PlainAcc<false>{g->plain_view()}, wt});
-    }
-    const PackedView pv = g->packed_view();
-    const uint32_t om = g->omega;
-    if (g->id_mode == LG_IDS_GLOBAL) {
-        if (g->offset_mode == LG_OFFS_PACKED) return fn(WPackedAcc<kIdsGlobal, kOffsPacked>{{pv}, om});
-        return fn(WPackedAcc<kIdsGlobal, kOffsEF>{{pv}, om});
-    }
-    if (g->offset_mode == LG_OFFS_PACKED) return fn(WPackedAcc<kIdsLocal, kOffsPacked>{{pv}, om});
-    return fn(WPackedAcc<kIdsLocal, kOffsEF>{{pv}, om});
-}
-
 }  // namespace lg
