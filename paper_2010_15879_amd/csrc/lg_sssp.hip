@@ -196,9 +196,14 @@ __global__ void sssp_collect_kernel(Acc acc, uint32_t n, uint64_t words, uint64_
 }
 
 // Edge t of the frontier belongs to slot s with qoff[s] <= t < qoff[s + 1];
-// every slot has at least one edge, so 64 consecutive edges lie in at most
-// 64 consecutive slots: one search for the step's first edge over the whole
-// scan, then each lane searches the next 64 slots.
+// every slot holds at least one edge.  Each wave takes a contiguous range
+// of edges, 64 per step, and finds its first slot by one binary search.  In
+// a step starting at edge t0 in slot s0, lane j loads the boundary
+// qoff[s0 + 1 + j]; the boundaries inside (t0, t0 + 64) form a bit mask
+// (a wave sum of distinct bits), so the slot of edge t0 + i is s0 plus the
+// number of mask bits at or below i, and the next step's slot is s0 plus
+// the number of boundaries at or below t0 + 64.  No lane runs a search per
+// edge.
 template <class Acc>
 __global__ void sssp_relax_kernel(Acc acc, uint32_t n, const uint64_t *__restrict__ count_p,
                                   const uint64_t *__restrict__ qoff, const uint64_t *__restrict__ qstart,
@@ -209,29 +214,37 @@ __global__ void sssp_relax_kernel(Acc acc, uint32_t n, const uint64_t *__restric
     const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) / kWave;
     const uint64_t count = *count_p;
     const uint64_t E = qoff[count];
-    for (uint64_t t0 = wave * kWave; t0 < E; t0 += nwaves * kWave) {
-        uint64_t lo = 0, hi = count;  // qoff[lo] <= t0 < qoff[hi]
-        while (hi - lo > 1) {
-            const uint64_t mid = lo + (hi - lo) / 2;
-            if (qoff[mid] <= t0) lo = mid;
-            else hi = mid;
-        }
+    const uint64_t per = ((E + nwaves - 1) / nwaves + kWave - 1) / kWave * kWave;
+    const uint64_t tb = wave * per;
+    if (tb >= E) return;  // same for every lane
+    const uint64_t te = tb + per < E ? tb + per : E;
+    uint64_t s0 = 0, hi = count;  // qoff[s0] <= tb < qoff[hi]
+    while (hi - s0 > 1) {
+        const uint64_t mid = s0 + (hi - s0) / 2;
+        if (qoff[mid] <= tb) s0 = mid;
+        else hi = mid;
+    }
+    const uint64_t below = lane == kWave - 1 ? ~0ull : ((2ull << lane) - 1ull);  // bits 0..lane
+    for (uint64_t t0 = tb; t0 < te; t0 += kWave) {
+        const uint64_t j = s0 + 1 + lane;
+        const uint64_t b = j <= count ? qoff[j] : ~0ull;  // > t0
+        const uint64_t o = b - t0;
+        const uint64_t M = wave_sum(o < kWave ? 1ull << o : 0ull);
+        const uint64_t adv = (uint64_t)__popcll(__ballot(o <= kWave));
         const uint64_t t = t0 + lane;
-        if (t >= E) continue;
-        uint64_t a = lo, b = lo + kWave < count ? lo + kWave : count;  // qoff[a] <= t < qoff[b]
-        while (b - a > 1) {
-            const uint64_t mid = a + (b - a) / 2;
-            if (qoff[mid] <= t) a = mid;
-            else b = mid;
+        if (t < te) {
+            const uint64_t a = s0 + (uint64_t)__popcll(M & below);
+            uint32_t id, w;
+            acc.entry(qstart[a], qw[a], t - qoff[a], id, w);
+            if (id < n) {  // only a corrupt stream fails this
+                const unsigned long long nd = qdist[a] + (unsigned long long)w;
+                if (nd < dist[id]) {
+                    const unsigned long long old = atomicMin(&dist[id], nd);
+                    if (nd < old) atomicOr(&upd[id >> 6], 1ull << (id & 63));
+                }
+            }
         }
-        uint32_t id, w;
-        acc.entry(qstart[a], qw[a], t - qoff[a], id, w);
-        if (id >= n) continue;  // only a corrupt stream gets here
-        const unsigned long long nd = qdist[a] + (unsigned long long)w;
-        if (nd < dist[id]) {
-            const unsigned long long old = atomicMin(&dist[id], nd);
-            if (nd < old) atomicOr(&upd[id >> 6], 1ull << (id & 63));
-        }
+        s0 += adv;
     }
 }
 
