@@ -146,7 +146,7 @@ def main():
     if args.offset_fetch:
         return offset_fetch_main(args, np, torch, lg, g)
     if args.encoding_compare:
-        return encoding_main(args, np, torch, lg, g)
+        return encoding_main(args, np, torch, lg, g, roots)
     if args.sssp:
         return sssp_main(args, np, torch, gg, lg, g, roots)
 
@@ -544,14 +544,15 @@ def sssp_main(args, np, torch, gg, lg, g, roots):
                       "delta_sweep_ms": sweep}), flush=True)
 
 
-def encoding_main(args, np, torch, lg, g):
+def encoding_main(args, np, torch, lg, g, roots):
     """List encodings side by side, Elias-Fano offsets, without and with the
     degree-minimizing relabeling: local widths (LG-l), fixed-size gap
     encoding (LG-l-gap), and Varint lists of full labels or of differences
     (with the relabeling: DMf and DMd).  Bytes of the lists |A|, of the width
     tables and of the offsets, encode time, the decode of the lists of
     256,000 random vertices (one call, stored labels), and 20 PageRank
-    iterations where the encoding supports them."""
+    iterations and a BFS from every root (one call) where the encoding
+    supports them."""
     import ctypes as C
     n = g.n
     k = 1000 * 256
@@ -582,11 +583,13 @@ def encoding_main(args, np, torch, lg, g):
                 assert st == 0, lg.lib().lg_last_error()
             dec_ms = _time_ms(torch, lists, reps=5)
             pr_ms = _time_ms(torch, lambda: lg.pagerank(h, 0.85, 20)) if ids.startswith("local") else None
+            bfs_ms = _time_ms(torch, lambda: lg.bfs(h, roots)) if ids.startswith("local") else None
             res[name] = {"adj_bytes": info["adj_bits"] / 8.0, "widths_bytes": info["bytes_widths"],
                          "offsets_bytes": info["bytes_offsets"], "encode_ms": round(enc_ms, 3),
                          "decode_ms": round(dec_ms, 4), "decoded_entries": total,
                          "decode_gentries_per_s": round(total / (dec_ms * 1e-3) / 1e9, 3),
-                         "pagerank20_ms": None if pr_ms is None else round(pr_ms, 3)}
+                         "pagerank20_ms": None if pr_ms is None else round(pr_ms, 3),
+                         "bfs_all_roots_ms": None if bfs_ms is None else round(bfs_ms, 3)}
             log(f"[encodings] {name}: {res[name]}")
             h.free()
     for rl in ("", "+DM"):

@@ -63,9 +63,9 @@ typedef enum lg_status {
  * element of the list of v at w_v bits (as LG_IDS_LOCAL), every difference
  * of consecutive neighbors at g_v = bl(largest difference) bits (0 when
  * d_v < 2), kept in a second table of F bits/vertex; the list takes
- * w_v + (d_v - 1) g_v bits.  Such graphs are read by lg_decode_neighbors
- * and lg_pagerank (a prefix sum per list); lg_bfs, batch plans and servers
- * return LG_ERR_UNSUPPORTED for them. */
+ * w_v + (d_v - 1) g_v bits.  Such graphs are read in order (a prefix sum
+ * per list) by lg_decode_neighbors, lg_pagerank, lg_bfs and servers; batch
+ * plans return LG_ERR_UNSUPPORTED for them. */
 #define LG_IDS_LOCAL_GAP 2u
 /* subsection "Incorporating Degree-Minimizing (DM)": lists as Varint byte
  * sequences (7 value bits per byte, lowest group first, the top bit set on

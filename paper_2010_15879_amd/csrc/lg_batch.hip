@@ -289,6 +289,11 @@ extern "C" lg_status lg_bfs_batch_plan(const lg_graph *const *graphs, uint32_t n
             set_error("lg_bfs_batch_plan: relabeled graphs are not supported in batches");
             return LG_ERR_UNSUPPORTED;
         }
+        if (g->layout == LG_LAYOUT_PACKED && (g->id_mode >= LG_IDS_LOCAL_GAP || g->weighted)) {
+            set_error("lg_bfs_batch_plan: batches take global or local IDs without weights (gap and Varint lists "
+                      "are read in order, by lg_bfs one graph at a time)");
+            return LG_ERR_UNSUPPORTED;
+        }
         qcap = std::max<uint64_t>(qcap, g->n);
     }
     std::vector<BatchJob> hj(num_jobs);

@@ -480,6 +480,194 @@ __global__ void bitmap_to_queue_kernel(uint64_t words, const uint64_t *__restric
     }
 }
 
+// ---------------------------------------------------------------------------
+// gap-encoded lists (subsection "Adding Fixed-Size Gap Encoding"): an entry
+// is the difference to the one before, so every list is read from its
+// start.  Top-down, a wave per frontier vertex takes 64 entries per step
+// and a wave prefix sum; bottom-up, a lane per unvisited vertex adds up to
+// `threshold` differences, four loads at a time, and a wave per longer
+// list without a hit goes on from there.  Depths and parents follow the
+// rules of the other encodings (the smallest label one level up).
+// ---------------------------------------------------------------------------
+
+template <class Acc>
+__global__ void gap_frontier_edges_kernel(Acc acc, const uint32_t *__restrict__ queue, uint64_t qsize,
+                                          unsigned long long *__restrict__ out) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    unsigned long long e = 0;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < qsize; i += stride)
+        e += acc.info(queue[i]).deg;
+    e = block_sum_u64(e);
+    if (threadIdx.x == 0 && e) atomicAdd(out, e);
+}
+
+template <class Acc, bool kParent>
+__global__ void td_gap_kernel(Acc acc, uint32_t n, const uint32_t *__restrict__ queue, uint64_t qsize,
+                              const uint64_t *__restrict__ visited, int32_t *__restrict__ depth,
+                              uint32_t *__restrict__ parent, int32_t next_depth, uint32_t *__restrict__ queue_out,
+                              unsigned long long *__restrict__ tail) {
+    const uint32_t lane = lane_id();
+    const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) / kWave;
+    for (uint64_t i = wave; i < qsize; i += nwaves) {
+        const uint32_t v = queue[i];
+        const GapInfo gi = acc.info(v);
+        uint32_t carry = 0;
+        for (uint64_t j0 = 0; j0 < gi.deg; j0 += kWave) {
+            const uint64_t j = j0 + lane;
+            const bool valid = j < gi.deg;
+            const uint32_t x = valid ? acc.get(Acc::entry_bit(gi, j), j ? gi.g : gi.w) : 0u;
+            const uint32_t val = wave_incl_scan(x) + carry;
+            carry = __shfl(val, kWave - 1, kWave);
+            // a stored label is < n; the clamp keeps every access in bounds
+            // whatever the stream holds
+            const uint32_t u = val < n ? val : n - 1;
+            bool won = false;
+            if (valid && !((visited[u >> 6] >> (u & 63)) & 1ull)) {
+                const int32_t old = atomicCAS(&depth[u], -1, next_depth);
+                if (kParent && (old == -1 || old == next_depth)) atomicMin(&parent[u], v);
+                won = old == -1;
+            }
+            const uint64_t m = __ballot(won);
+            if (m) {
+                unsigned long long base = 0;
+                if (lane == 0) base = atomicAdd(tail, (unsigned long long)__popcll(m));
+                base = __shfl(base, 0, kWave) + popc_below(m);
+                if (won) queue_out[base] = u;
+            }
+        }
+    }
+}
+
+template <class Acc, bool kParent>
+__global__ void bu_gap_kernel(Acc acc, uint32_t n, uint32_t threshold, const uint64_t *__restrict__ curr,
+                              uint64_t *__restrict__ visited, uint64_t *__restrict__ next,
+                              int32_t *__restrict__ depth, uint32_t *__restrict__ parent, int32_t next_depth,
+                              unsigned long long *__restrict__ counters, unsigned long long *__restrict__ next_counters,
+                              uint32_t *__restrict__ pv, uint64_t *__restrict__ pstart, uint32_t *__restrict__ pdeg,
+                              uint32_t *__restrict__ pwg, uint32_t *__restrict__ pcarry) {
+    const uint32_t lane = lane_id();
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        next_counters[1] = 0;
+        next_counters[2] = 0;
+    }
+    const uint64_t words = ((uint64_t)n + 63) / 64;
+    const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) / kWave;
+    unsigned long long woke = 0;
+    for (uint64_t q = wave; q < words; q += nwaves) {
+        const uint64_t vis = visited[q];
+        if (vis == ~0ull) {
+            if (lane == 0) next[q] = 0;
+            continue;
+        }
+        const uint64_t v = q * 64 + lane;
+        const bool open = v < n && !((vis >> lane) & 1ull);
+        const GapInfo gi = open ? acc.info((uint32_t)v) : GapInfo{0, 0, 0, 0};
+        bool found = false, pending = false;
+        uint32_t par = 0, val = 0;
+        if (open && gi.deg) {
+            const uint32_t lim = gi.deg < threshold ? gi.deg : threshold;
+            for (uint32_t i = 0; i < lim && !found; i += 4) {
+                uint32_t x[4], u[4];
+                uint64_t cw[4];
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    const uint32_t e = i + b < lim ? i + b : 0u;  // past the limit: entry 0 again, dropped
+                    x[b] = acc.get(Acc::entry_bit(gi, e), e ? gi.g : gi.w);
+                }
+                uint32_t run = val;
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    run += i + b < lim ? x[b] : 0u;
+                    u[b] = run < n ? run : n - 1;
+                }
+#pragma unroll
+                for (int b = 0; b < 4; ++b) cw[b] = curr[u[b] >> 6];
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    if (!found && i + b < lim) {
+                        val += x[b];
+                        if ((cw[b] >> (u[b] & 63)) & 1ull) { found = true; par = u[b]; }
+                    }
+                }
+            }
+            pending = !found && gi.deg > threshold;
+        }
+        const uint64_t fm = __ballot(found);
+        if (found) {
+            depth[v] = next_depth;
+            if (kParent) parent[v] = par;
+        }
+        if (lane == 0) next[q] = fm;
+        if (lane == 0 && fm) {
+            visited[q] |= fm;
+            woke += (unsigned long long)__popcll(fm);
+        }
+        const uint64_t pm = __ballot(pending);
+        if (pm) {
+            unsigned long long base = 0;
+            if (lane == 0) base = atomicAdd(&counters[2], (unsigned long long)__popcll(pm));
+            base = __shfl(base, 0, kWave) + popc_below(pm);
+            if (pending) {
+                pv[base] = (uint32_t)v;
+                pstart[base] = gi.start;
+                pdeg[base] = gi.deg;
+                pwg[base] = gi.w | (gi.g << 8);
+                pcarry[base] = val;  // the label of entry threshold - 1
+            }
+        }
+    }
+    woke = block_sum_u64(woke);
+    if (threadIdx.x == 0 && woke) atomicAdd(&counters[1], woke);
+}
+
+// the pending lists from entry `threshold` on, a wave each, 64 entries per
+// step; the first frontier neighbor is the smallest, the parent
+template <class Acc, bool kParent>
+__global__ void bu_gap_pending_kernel(Acc acc, uint32_t n, uint32_t threshold, uint64_t np,
+                                      const uint32_t *__restrict__ pv, const uint64_t *__restrict__ pstart,
+                                      const uint32_t *__restrict__ pdeg, const uint32_t *__restrict__ pwg,
+                                      const uint32_t *__restrict__ pcarry, const uint64_t *__restrict__ curr,
+                                      unsigned long long *__restrict__ visited, unsigned long long *__restrict__ next,
+                                      int32_t *__restrict__ depth, uint32_t *__restrict__ parent, int32_t next_depth,
+                                      unsigned long long *__restrict__ counters) {
+    const uint32_t lane = lane_id();
+    const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) / kWave;
+    unsigned long long woke = 0;
+    for (uint64_t p = wave; p < np; p += nwaves) {
+        const uint32_t v = pv[p];
+        const uint32_t wg = pwg[p];
+        const GapInfo gi{pstart[p], pdeg[p], wg & 255u, wg >> 8};
+        uint32_t carry = pcarry[p];
+        for (uint64_t e0 = threshold; e0 < gi.deg; e0 += kWave) {
+            const uint64_t i = e0 + lane;
+            const bool valid = i < gi.deg;
+            const uint32_t x = valid ? acc.get(Acc::entry_bit(gi, i), gi.g) : 0u;
+            const uint32_t val = wave_incl_scan(x) + carry;
+            carry = __shfl(val, kWave - 1, kWave);
+            const uint32_t u = val < n ? val : n - 1;
+            const bool hit = valid && ((curr[u >> 6] >> (u & 63)) & 1ull);
+            const uint64_t m = __ballot(hit);
+            if (m) {
+                const uint32_t first = (uint32_t)__ffsll((long long)m) - 1;
+                const uint32_t par = __shfl(u, first, kWave);
+                if (lane == 0) {
+                    depth[v] = next_depth;
+                    if (kParent) parent[v] = par;
+                    atomicOr(&next[v >> 6], 1ull << (v & 63));
+                    atomicOr(&visited[v >> 6], 1ull << (v & 63));
+                    ++woke;
+                }
+                break;
+            }
+        }
+    }
+    woke = block_sum_u64(woke);
+    if (threadIdx.x == 0 && woke) atomicAdd(&counters[1], woke);
+}
+
 // results in original IDs: depth_out[o] = depth[inv[o]], parent through perm
 // (unreached vertices, among them every edgeless one, need no parent lookup)
 __global__ void bfs_unpermute_kernel(uint32_t n, const uint32_t *__restrict__ inv, const uint32_t *__restrict__ perm,
@@ -674,26 +862,146 @@ static lg_status bfs_one(lg_graph *g, BfsWork &w, Acc acc, uint32_t root_id, con
     return LG_OK;
 }
 
+// The traversal over gap lists: the same level structure and direction
+// rule as bfs_one, with the in-order kernels above (the frontier's edge
+// count, from every frontier vertex's degree, decides the direction).
+template <class Acc>
+static lg_status bfs_one_gap(lg_graph *g, BfsWork &w, Acc acc, uint32_t root_id, const uint32_t *inv,
+                             int32_t *depth, uint32_t *parent, int32_t max_depth, uint32_t flags, double alpha,
+                             hipStream_t s) {
+    const uint32_t n = g->n;
+    const uint64_t words = ((uint64_t)n + 63) / 64;
+    const uint32_t thr = g->heavy_threshold;
+    uint32_t *qin = w.qa.as<uint32_t>(), *qout = w.qb.as<uint32_t>();
+    uint64_t *visited = w.visited.as<uint64_t>(), *curr = w.curr.as<uint64_t>(), *next = w.next.as<uint64_t>();
+    unsigned long long *ctr = w.counters.as<unsigned long long>();
+    LG_LAUNCH(bfs_init_kernel, grid_for(n, 256, 1u << 16), 256, 0, s, n, depth, parent, g->iso.as<uint64_t>(),
+              visited, root_id, inv, qin, (uint64_t *)ctr);
+    LG_CHECK_LAUNCH();
+    uint64_t qsize = 1, edges_to_check = g->m, awake = 0;
+    int32_t level = 0;
+    bool topdown = true;
+    uint32_t bu_pair = 0;
+    for (;;) {
+        if (max_depth >= 0 && level >= max_depth) break;
+        if (topdown) {
+            if (qsize == 0) break;
+            bool go_bu = flags == LG_BFS_BOTTOM_UP && level >= 1;
+            if (flags == LG_BFS_DIRECTION_OPT) {
+                LG_TRY(fill_u64(w.fscan.as<uint64_t>(), 0, 1, s));
+                LG_LAUNCH(gap_frontier_edges_kernel<Acc>, grid_for(qsize, 256, 1024), 256, 0, s, acc, qin, qsize,
+                          w.fscan.as<unsigned long long>());
+                LG_CHECK_LAUNCH();
+                LG_CHECK_HIP(hipMemcpyAsync(w.host, w.fscan.p, 8, hipMemcpyDeviceToHost, s));
+                LG_CHECK_HIP(hipStreamSynchronize(s));
+                const uint64_t fedges = w.host[0];
+                go_bu = (double)fedges > (double)edges_to_check / alpha;
+                if (!go_bu) edges_to_check = edges_to_check > fedges ? edges_to_check - fedges : 0;
+            }
+            if (go_bu) {
+                LG_TRY(fill_u64(curr, 0, words, s));
+                LG_LAUNCH(mark_queue_kernel, grid_for(qsize, 256, 1u << 16), 256, 0, s, qin, qsize,
+                          (unsigned long long *)curr, ctr);
+                LG_CHECK_LAUNCH();
+                awake = qsize;
+                topdown = false;
+                continue;
+            }
+            const uint32_t grid = grid_for(qsize * kWave, 256, kStrideBlocks);
+            if (parent)
+                LG_LAUNCH((td_gap_kernel<Acc, true>), grid, 256, 0, s, acc, n, qin, qsize, visited, depth, parent,
+                          level + 1, qout, ctr);
+            else
+                LG_LAUNCH((td_gap_kernel<Acc, false>), grid, 256, 0, s, acc, n, qin, qsize, visited, depth, parent,
+                          level + 1, qout, ctr);
+            LG_CHECK_LAUNCH();
+            LG_CHECK_HIP(hipMemcpyAsync(w.host, ctr, 8, hipMemcpyDeviceToHost, s));
+            LG_CHECK_HIP(hipStreamSynchronize(s));
+            qsize = w.host[0];
+            if (qsize) {
+                LG_LAUNCH(mark_queue_kernel, grid_for(qsize, 256, 1u << 16), 256, 0, s, qout, qsize,
+                          (unsigned long long *)visited, ctr);
+                LG_CHECK_LAUNCH();
+            }
+            std::swap(qin, qout);
+            ++level;
+        } else {
+            unsigned long long *bc = ctr + 2 * bu_pair;
+            unsigned long long *bc_next = ctr + 2 * (bu_pair ^ 1u);
+            bu_pair ^= 1u;
+            const uint32_t grid = grid_for(words * kWave, 256, kStrideBlocks);
+            if (parent)
+                LG_LAUNCH((bu_gap_kernel<Acc, true>), grid, 256, 0, s, acc, n, thr, curr, visited, next, depth, parent,
+                          level + 1, bc, bc_next, w.pv.as<uint32_t>(), w.pstart.as<uint64_t>(), w.pdeg.as<uint32_t>(),
+                          w.pw.as<uint32_t>(), w.pseg_cnt.as<uint32_t>());
+            else
+                LG_LAUNCH((bu_gap_kernel<Acc, false>), grid, 256, 0, s, acc, n, thr, curr, visited, next, depth,
+                          parent, level + 1, bc, bc_next, w.pv.as<uint32_t>(), w.pstart.as<uint64_t>(),
+                          w.pdeg.as<uint32_t>(), w.pw.as<uint32_t>(), w.pseg_cnt.as<uint32_t>());
+            LG_CHECK_LAUNCH();
+            LG_CHECK_HIP(hipMemcpyAsync(w.host, bc + 1, 16, hipMemcpyDeviceToHost, s));
+            LG_CHECK_HIP(hipStreamSynchronize(s));
+            const uint64_t np = w.host[1];
+            if (np) {
+                const uint32_t pgrid = grid_for(np * kWave, 256, kStrideBlocks);
+                if (parent)
+                    LG_LAUNCH((bu_gap_pending_kernel<Acc, true>), pgrid, 256, 0, s, acc, n, thr, np,
+                              w.pv.as<uint32_t>(), w.pstart.as<uint64_t>(), w.pdeg.as<uint32_t>(), w.pw.as<uint32_t>(),
+                              w.pseg_cnt.as<uint32_t>(), curr, (unsigned long long *)visited,
+                              (unsigned long long *)next, depth, parent, level + 1, bc);
+                else
+                    LG_LAUNCH((bu_gap_pending_kernel<Acc, false>), pgrid, 256, 0, s, acc, n, thr, np,
+                              w.pv.as<uint32_t>(), w.pstart.as<uint64_t>(), w.pdeg.as<uint32_t>(), w.pw.as<uint32_t>(),
+                              w.pseg_cnt.as<uint32_t>(), curr, (unsigned long long *)visited,
+                              (unsigned long long *)next, depth, parent, level + 1, bc);
+                LG_CHECK_LAUNCH();
+                LG_CHECK_HIP(hipMemcpyAsync(w.host, bc + 1, 8, hipMemcpyDeviceToHost, s));
+                LG_CHECK_HIP(hipStreamSynchronize(s));
+            }
+            const uint64_t now = w.host[0];
+            std::swap(curr, next);
+            ++level;
+            if (now == 0) break;
+            const bool back = flags == LG_BFS_DIRECTION_OPT && now < awake && (double)now <= (double)n / kBfsBeta;
+            awake = now;
+            if (back) {
+                LG_TRY(fill_u64((uint64_t *)ctr + 5, 0, 1, s));
+                LG_LAUNCH(bitmap_to_queue_kernel, grid_for(words, 256, 1u << 16), 256, 0, s, words, curr, qin,
+                          ctr + 5);
+                LG_CHECK_LAUNCH();
+                qsize = now;
+                topdown = true;
+            }
+        }
+    }
+    return LG_OK;
+}
+
 lg_status bfs_run(lg_graph *g, BfsWork &w, const uint32_t *roots, uint32_t r, int32_t *depth, int32_t *parent,
                   int32_t max_depth, uint32_t flags, hipStream_t stream, double alpha) {
     if (r == 0) return LG_OK;
     LG_TRY(bfs_workspace_ensure(w, g->n, g->n_heavy, g->relabel != LG_RELABEL_NONE, parent != nullptr));
     const bool rel = g->relabel != LG_RELABEL_NONE;
     const uint32_t *inv = rel ? g->inv.as<uint32_t>() : nullptr;
-    return dispatch_acc(g, [&](auto acc) -> lg_status {
+    return dispatch_acc_all(g, [&](auto acc) -> lg_status {
+        // one traversal: the in-order kernels for gap lists, else the general ones
+        auto one = [&](uint32_t root, int32_t *d, uint32_t *p) -> lg_status {
+            if constexpr (IsGapAcc<decltype(acc)>::value)
+                return bfs_one_gap(g, w, acc, root, inv, d, p, max_depth, flags, alpha, stream);
+            else
+                return bfs_one(g, w, acc, root, inv, d, p, max_depth, flags, alpha, stream);
+        };
         for (uint32_t i = 0; i < r; ++i) {
             int32_t *d_out = depth + (uint64_t)i * g->n;
             int32_t *p_out = parent ? parent + (uint64_t)i * g->n : nullptr;
             if (rel) {
-                LG_TRY(bfs_one(g, w, acc, roots[i], inv, w.depth_i.as<int32_t>(),
-                               p_out ? w.parent_i.as<uint32_t>() : nullptr, max_depth, flags, alpha, stream));
+                LG_TRY(one(roots[i], w.depth_i.as<int32_t>(), p_out ? w.parent_i.as<uint32_t>() : nullptr));
                 LG_LAUNCH(bfs_unpermute_kernel, grid_for(g->n, 256, 1u << 16), 256, 0, stream, g->n,
                           g->inv.as<uint32_t>(), g->perm.as<uint32_t>(), w.depth_i.as<int32_t>(),
                           p_out ? w.parent_i.as<uint32_t>() : nullptr, d_out, p_out);
                 LG_CHECK_LAUNCH();
             } else {
-                LG_TRY(bfs_one(g, w, acc, roots[i], inv, d_out, reinterpret_cast<uint32_t *>(p_out), max_depth, flags,
-                               alpha, stream));
+                LG_TRY(one(roots[i], d_out, reinterpret_cast<uint32_t *>(p_out)));
             }
         }
         return LG_OK;

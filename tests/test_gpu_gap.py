@@ -1,7 +1,7 @@
 """Fixed-size gap encoding on the GPU (subsection "Adding Fixed-Size Gap
 Encoding", local approach): every array bit-exact against the oracle, lists
-decoded against the input, PageRank over them against the oracle, and BFS
-refusing such graphs."""
+decoded against the input, and BFS and PageRank over them against the
+oracle."""
 
 import numpy as np
 import pytest
@@ -88,13 +88,52 @@ def test_gap_decode(lgmod, name, e):
     h.free()
 
 
-def test_gap_bfs_unsupported(lgmod):
+@pytest.mark.parametrize("mode", ["do", "td", "bu"])
+@pytest.mark.parametrize("e", GAP, ids=gid)
+@pytest.mark.parametrize("name", list(GRAPHS))
+def test_gap_bfs(lgmod, name, e, mode):
+    """BFS over gap lists (read in order): depths and parents bit-exact
+    against the oracle, every direction mode."""
+    g = GRAPHS[name]
+    off, col = g.numpy()
+    roots = gg.pick_roots(g, 3, seed=4) or [0]
+    if 0 not in roots:
+        roots = roots + [0]
+    print(f"[gap bfs] {name} {gid(e)} {mode} roots={roots}", flush=True)
+    h = encode(lgmod, g, e)
+    depth, parent = lgmod.bfs(h, roots, mode=mode)
+    depth, parent = depth.cpu().numpy(), parent.cpu().numpy()
+    for i, r in enumerate(roots):
+        d0, p0 = orc.bfs(off, col, r, relabeled=bool(e["relabel"]))
+        np.testing.assert_array_equal(depth[i], d0)
+        np.testing.assert_array_equal(parent[i], p0)
+    h.free()
+
+
+@pytest.mark.parametrize("k", [0, 1, 2])
+def test_gap_bfs_k_hop_and_no_parents(lgmod, k):
+    g = GRAPHS["kron12"]
+    off, col = g.numpy()
+    roots = gg.pick_roots(g, 3, seed=9)
+    h = encode(lgmod, g, GAP[2])
+    depth, parent = lgmod.bfs(h, roots, max_depth=k)
+    for i, r in enumerate(roots):
+        d0, p0 = orc.bfs(off, col, r, max_depth=k, relabeled=True)
+        np.testing.assert_array_equal(depth[i].cpu().numpy(), d0)
+        np.testing.assert_array_equal(parent[i].cpu().numpy(), p0)
+    depth, par = lgmod.bfs(h, roots, parent=False)
+    assert par is None
+    for i, r in enumerate(roots):
+        np.testing.assert_array_equal(depth[i].cpu().numpy(), orc.bfs(off, col, r)[0])
+    h.free()
+
+
+def test_gap_batch_unsupported(lgmod):
     from paper_2010_15879_amd.lg import LGError, LG_ERR_UNSUPPORTED
     g = GRAPHS["kron12"]
-    h = encode(lgmod, g, GAP[1])
-    root = gg.pick_roots(g, 1, seed=1)
+    h = encode(lgmod, g, GAP[0])
     with pytest.raises(LGError) as ei:
-        lgmod.bfs(h, root)
+        lgmod.BatchPlan([h], [(0, 1)])
     assert ei.value.status == LG_ERR_UNSUPPORTED
     h.free()
 
@@ -133,5 +172,10 @@ def test_gap_kronecker16_smaller(lgmod):
     assert h.info()["adj_bits"] <= hl.info()["adj_bits"]
     np.testing.assert_array_equal(lgmod.pagerank(h, 0.85, 5).cpu().numpy(),
                                   lgmod.pagerank(hl, 0.85, 5).cpu().numpy())
+    roots = gg.pick_roots(g, 4, seed=2)
+    dg, pg = lgmod.bfs(h, roots)
+    dl, pl = lgmod.bfs(hl, roots)
+    np.testing.assert_array_equal(dg.cpu().numpy(), dl.cpu().numpy())
+    np.testing.assert_array_equal(pg.cpu().numpy(), pl.cpu().numpy())
     h.free()
     hl.free()
