@@ -640,7 +640,11 @@ __global__ void gap_len_kernel(uint32_t n, const uint64_t *__restrict__ off, con
 // "Accessing an Edge Weight"): the ID, then the weight at omega bits.
 // ---------------------------------------------------------------------------
 
-__global__ void max_u32_kernel(uint64_t count, const uint32_t *__restrict__ x, uint32_t *__restrict__ out) {
+// a grid-stride maximum, one atomic per block (launched with a bounded grid:
+// atomics on one address serialize)
+__global__ __launch_bounds__(256) void max_u32_kernel(uint64_t count, const uint32_t *__restrict__ x,
+                                                      uint32_t *__restrict__ out) {
+    __shared__ uint32_t s_max[256 / kWave];
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     uint32_t mx = 0;
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride)
@@ -650,7 +654,12 @@ __global__ void max_u32_kernel(uint64_t count, const uint32_t *__restrict__ x, u
         const uint32_t o = __shfl_xor(mx, d, kWave);
         mx = o > mx ? o : mx;
     }
-    if (lane_id() == 0 && mx) atomicMax(out, mx);
+    if (lane_id() == 0) s_max[threadIdx.x / kWave] = mx;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int i = 1; i < 256 / kWave; ++i) mx = s_max[i] > mx ? s_max[i] : mx;
+        if (mx) atomicMax(out, mx);
+    }
 }
 
 // list bit lengths d_v (w_v + omega), local IDs
@@ -1032,7 +1041,7 @@ static lg_status encode_impl(uint32_t n, uint64_t m, const uint64_t *row_offsets
         uint32_t wmax = 0;
         if (m) {
             LG_TRY(fill_u32(stats.as<uint32_t>(), 0, 1, s));
-            LG_LAUNCH(max_u32_kernel, grid1(m), 256, 0, s, m, weights, stats.as<uint32_t>());
+            LG_LAUNCH(max_u32_kernel, grid_for(m, 256, 4096), 256, 0, s, m, weights, stats.as<uint32_t>());
             LG_CHECK_LAUNCH();
             LG_CHECK_HIP(hipMemcpyAsync(&wmax, stats.p, 4, hipMemcpyDeviceToHost, s));
             LG_CHECK_HIP(hipStreamSynchronize(s));

@@ -100,13 +100,14 @@ lg_status dispatch_wacc(const lg_graph *g, Fn &&fn) {
 }
 
 constexpr uint64_t kInfDist = ~0ull;
-constexpr uint32_t kSsspDefaultDelta = 1024;
+constexpr uint32_t kSsspDefaultDelta = 256;
 
 struct SsspWork {
     DevBuf upd;                         // bitmap, one bit per vertex
-    DevBuf queue, qw, qdeg;             // frontier: vertex, ID width, degree
+    DevBuf qw, qdeg;                    // frontier: ID width, degree
     DevBuf qstart, qdist, qoff;         // list start, distance, exclusive scan of qdeg
     DevBuf ctr;                         // [0] frontier size, [1] smallest distance left marked
+    DevBuf tmask, wcnt, woff;           // per bitmap word: vertices taken, their count, queue position
     DevBuf scan_tmp;
     uint64_t *host = nullptr;           // pinned readback slots
     SsspWork() = default;
@@ -116,8 +117,8 @@ struct SsspWork {
         if (host) (void)hipHostFree(host);
     }
     uint64_t bytes() const {
-        return upd.bytes + queue.bytes + qw.bytes + qdeg.bytes + qstart.bytes + qdist.bytes + qoff.bytes + ctr.bytes +
-               scan_tmp.bytes;
+        return upd.bytes + qw.bytes + qdeg.bytes + qstart.bytes + qdist.bytes + qoff.bytes + ctr.bytes +
+               tmask.bytes + wcnt.bytes + woff.bytes + scan_tmp.bytes;
     }
 };
 
@@ -147,50 +148,75 @@ __global__ void sssp_ctr_kernel(unsigned long long *__restrict__ ctr) {
     }
 }
 
-template <class Acc>
-__global__ void sssp_collect_kernel(Acc acc, uint32_t n, uint64_t words, uint64_t hi,
-                                    const uint64_t *__restrict__ dist, uint64_t *__restrict__ upd,
-                                    uint32_t *__restrict__ queue, uint64_t *__restrict__ qstart,
-                                    uint32_t *__restrict__ qw, uint32_t *__restrict__ qdeg,
-                                    uint64_t *__restrict__ qdist, unsigned long long *__restrict__ ctr) {
+// The frontier is compacted without a shared counter (one atomic add per
+// wave on a single address serializes the whole pass): a count pass takes
+// each word's marked vertices below the bound out of the bitmap and counts
+// them, an exclusive scan over the words gives every word its queue
+// position, and a write pass fills the queue.  Every marked vertex has edges
+// (it was reached over one) but the root, which may have none: it is then
+// alone in the first frontier, which holds no edges.
+constexpr int kCollectThreads = 256;
+constexpr uint32_t kCollectBlocks = 4096;
+
+__global__ __launch_bounds__(kCollectThreads) void sssp_count_kernel(
+    uint32_t n, uint64_t words, uint64_t hi, const uint64_t *__restrict__ dist, uint64_t *__restrict__ upd,
+    uint64_t *__restrict__ tmask, uint32_t *__restrict__ cnt, unsigned long long *__restrict__ ctr) {
+    __shared__ unsigned long long s_left[kCollectThreads / kWave];
     const uint32_t lane = lane_id();
     const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
     const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) / kWave;
+    uint64_t left = kInfDist;  // the smallest distance staying marked
     for (uint64_t q = wave; q < words; q += nwaves) {
         const uint64_t bits = upd[q];
-        if (!bits) continue;  // same for every lane
-        const uint64_t v = q * 64 + lane;
-        const bool set = ((bits >> lane) & 1ull) && v < n;
-        const uint64_t d = set ? dist[v] : kInfDist;
-        const bool take = set && d < hi;
-        const uint64_t tmask = __ballot(take);
-        // the smallest distance staying marked
-        uint64_t left = set && !take ? d : kInfDist;
-#pragma unroll
-        for (int s = kWave / 2; s > 0; s >>= 1) {
-            const uint64_t o = __shfl_xor(left, s, kWave);
-            left = o < left ? o : left;
+        uint64_t take_m = 0;
+        if (bits) {  // same for every lane
+            const uint64_t v = q * 64 + lane;
+            const bool set = ((bits >> lane) & 1ull) && v < n;
+            const uint64_t d = set ? dist[v] : kInfDist;
+            const bool take = set && d < hi;
+            take_m = __ballot(take);
+            if (set && !take && d < left) left = d;
+            if (lane == 0 && take_m) upd[q] = bits & ~take_m;
         }
         if (lane == 0) {
-            if (tmask) upd[q] = bits & ~tmask;
-            if (left != kInfDist) atomicMin(&ctr[1], (unsigned long long)left);
+            tmask[q] = take_m;
+            cnt[q] = (uint32_t)__popcll(take_m);
         }
-        if (!tmask) continue;
-        WInfo vi{0, 0, 0};
-        if (take) vi = acc.info((uint32_t)v);
-        const bool enq = take && vi.deg > 0;
-        const uint64_t emask = __ballot(enq);
-        if (!emask) continue;
-        unsigned long long base = 0;
-        if (lane == 0) base = atomicAdd(&ctr[0], (unsigned long long)__popcll(emask));
-        base = __shfl(base, 0, kWave);
-        if (enq) {
-            const uint64_t pos = base + popc_below(emask);
-            queue[pos] = (uint32_t)v;
+    }
+#pragma unroll
+    for (int s = kWave / 2; s > 0; s >>= 1) {
+        const uint64_t o = __shfl_xor(left, s, kWave);
+        left = o < left ? o : left;
+    }
+    if (lane == 0) s_left[threadIdx.x / kWave] = left;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long m = s_left[0];
+        for (int i = 1; i < kCollectThreads / kWave; ++i) m = s_left[i] < m ? s_left[i] : m;
+        if (m != kInfDist) atomicMin(&ctr[1], m);
+    }
+}
+
+template <class Acc>
+__global__ __launch_bounds__(kCollectThreads) void sssp_write_kernel(
+    Acc acc, uint32_t n, uint64_t words, const uint64_t *__restrict__ dist, const uint64_t *__restrict__ tmask,
+    const uint64_t *__restrict__ woff, uint64_t *__restrict__ qstart, uint32_t *__restrict__ qw,
+    uint32_t *__restrict__ qdeg, uint64_t *__restrict__ qdist, unsigned long long *__restrict__ ctr) {
+    const uint32_t lane = lane_id();
+    const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) / kWave;
+    if (blockIdx.x == 0 && threadIdx.x == 0) ctr[0] = woff[words];  // frontier size
+    for (uint64_t q = wave; q < words; q += nwaves) {
+        const uint64_t m = tmask[q];
+        if (!m) continue;  // same for every lane
+        if ((m >> lane) & 1ull) {
+            const uint64_t v = q * 64 + lane;
+            const WInfo vi = acc.info((uint32_t)v);
+            const uint64_t pos = woff[q] + popc_below(m);
             qstart[pos] = vi.start;
             qw[pos] = vi.w;
             qdeg[pos] = vi.deg;
-            qdist[pos] = d;
+            qdist[pos] = dist[v];
         }
     }
 }
@@ -275,7 +301,9 @@ extern "C" lg_status lg_sssp(const lg_graph *gc, uint32_t root, uint32_t delta, 
         }
     }
     LG_TRY(W.upd.ensure(words * 8));
-    LG_TRY(W.queue.ensure((uint64_t)n * 4));
+    LG_TRY(W.tmask.ensure(words * 8));
+    LG_TRY(W.wcnt.ensure(words * 4));
+    LG_TRY(W.woff.ensure((words + 1) * 8));
     LG_TRY(W.qw.ensure((uint64_t)n * 4));
     LG_TRY(W.qdeg.ensure((uint64_t)n * 4));
     LG_TRY(W.qstart.ensure((uint64_t)n * 8));
@@ -289,7 +317,7 @@ extern "C" lg_status lg_sssp(const lg_graph *gc, uint32_t root, uint32_t delta, 
         using Acc = decltype(acc);
         int cus = 0;
         LG_CHECK_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, g->device));
-        const uint32_t collect_grid = grid_for(words * kWave, 256, 1u << 16);
+        const uint32_t collect_grid = grid_for(words * kWave, kCollectThreads, kCollectBlocks);
         const uint32_t relax_grid = (uint32_t)std::max(1, cus) * 8;
         uint64_t hi = D;
         // every step either relaxes a non-empty frontier (each entry of it
@@ -303,10 +331,15 @@ extern "C" lg_status lg_sssp(const lg_graph *gc, uint32_t root, uint32_t delta, 
             }
             LG_LAUNCH(sssp_ctr_kernel, 1, 64, 0, stream, W.ctr.as<unsigned long long>());
             LG_CHECK_LAUNCH();
-            LG_LAUNCH(sssp_collect_kernel<Acc>, collect_grid, 256, 0, stream, acc, n, words, hi,
-                      (const uint64_t *)dist, W.upd.as<uint64_t>(), W.queue.as<uint32_t>(), W.qstart.as<uint64_t>(),
-                      W.qw.as<uint32_t>(), W.qdeg.as<uint32_t>(), W.qdist.as<uint64_t>(),
+            LG_LAUNCH(sssp_count_kernel, collect_grid, kCollectThreads, 0, stream, n, words, hi,
+                      (const uint64_t *)dist, W.upd.as<uint64_t>(), W.tmask.as<uint64_t>(), W.wcnt.as<uint32_t>(),
                       W.ctr.as<unsigned long long>());
+            LG_CHECK_LAUNCH();
+            LG_TRY(exclusive_scan_u32(W.wcnt.as<uint32_t>(), W.woff.as<uint64_t>(), words, W.scan_tmp, stream));
+            LG_LAUNCH(sssp_write_kernel<Acc>, collect_grid, kCollectThreads, 0, stream, acc, n, words,
+                      (const uint64_t *)dist, (const uint64_t *)W.tmask.as<uint64_t>(),
+                      (const uint64_t *)W.woff.as<uint64_t>(), W.qstart.as<uint64_t>(), W.qw.as<uint32_t>(),
+                      W.qdeg.as<uint32_t>(), W.qdist.as<uint64_t>(), W.ctr.as<unsigned long long>());
             LG_CHECK_LAUNCH();
             LG_CHECK_HIP(hipMemcpyAsync(W.host, W.ctr.p, 16, hipMemcpyDeviceToHost, stream));
             LG_CHECK_HIP(hipStreamSynchronize(stream));
