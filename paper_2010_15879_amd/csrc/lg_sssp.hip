@@ -5,10 +5,10 @@
 // Distances are uint64 (UINT64_MAX: not reached).  A bitmap marks vertices
 // whose distance dropped since their edges were last relaxed.  Each step of
 // bucket k (distances below hi = (k+1) delta):
-//   collect  one wave per 64-vertex word of the bitmap: marked vertices with
-//            a distance below hi leave the bitmap and, when they have edges,
-//            join the frontier queue with their list start, ID width, degree
-//            and distance; the smallest distance among the marked vertices
+//   collect  marked vertices with a distance below hi leave the bitmap and
+//            join the frontier queue with their list start, ID width,
+//            degree and distance (a count pass per 64-vertex word, a scan,
+//            a write pass); the smallest distance among the marked vertices
 //            left behind is kept for choosing the next bucket
 //   relax    the frontier's edges, flattened by an exclusive scan of the
 //            degrees, 64 consecutive edges per wave step: nd = dist(u) + w;
