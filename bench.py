@@ -550,9 +550,9 @@ def encoding_main(args, np, torch, lg, g, roots):
     encoding (LG-l-gap), and Varint lists of full labels or of differences
     (with the relabeling: DMf and DMd).  Bytes of the lists |A|, of the width
     tables and of the offsets, encode time, the decode of the lists of
-    256,000 random vertices (one call, stored labels), and 20 PageRank
-    iterations and a BFS from every root (one call) where the encoding
-    supports them."""
+    256,000 random vertices (one call, stored labels), a BFS from every root
+    (one call), and 20 PageRank iterations where the encoding supports
+    them."""
     import ctypes as C
     n = g.n
     k = 1000 * 256
@@ -583,7 +583,7 @@ def encoding_main(args, np, torch, lg, g, roots):
                 assert st == 0, lg.lib().lg_last_error()
             dec_ms = _time_ms(torch, lists, reps=5)
             pr_ms = _time_ms(torch, lambda: lg.pagerank(h, 0.85, 20)) if ids.startswith("local") else None
-            bfs_ms = _time_ms(torch, lambda: lg.bfs(h, roots)) if ids.startswith("local") else None
+            bfs_ms = _time_ms(torch, lambda: lg.bfs(h, roots))
             res[name] = {"adj_bytes": info["adj_bits"] / 8.0, "widths_bytes": info["bytes_widths"],
                          "offsets_bytes": info["bytes_offsets"], "encode_ms": round(enc_ms, 3),
                          "decode_ms": round(dec_ms, 4), "decoded_entries": total,

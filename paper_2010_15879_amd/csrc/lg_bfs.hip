@@ -668,6 +668,230 @@ __global__ void bu_gap_pending_kernel(Acc acc, uint32_t n, uint32_t threshold, u
     if (threadIdx.x == 0 && woke) atomicAdd(&counters[1], woke);
 }
 
+// ---------------------------------------------------------------------------
+// Varint lists (subsection "Incorporating Degree-Minimizing (DM)"): byte
+// streams of base-128 values, read in order like gap lists.  The direction
+// rule counts list bytes instead of entries (it changes the time, never the
+// result).  Top-down, a wave per frontier vertex takes 64 bytes per step: a
+// lane holding a value's last byte assembles the value from the (at most
+// four) continuation bytes before it, DMd adds a wave prefix sum; bottom-up,
+// a lane per unvisited vertex decodes up to `threshold` values from 8-byte
+// windows and stops at the first frontier neighbor, and a wave per longer
+// list without a hit goes on from the byte and label it reached.
+// ---------------------------------------------------------------------------
+
+template <class Acc>
+__global__ void varint_frontier_bytes_kernel(Acc acc, const uint32_t *__restrict__ queue, uint64_t qsize,
+                                             unsigned long long *__restrict__ out) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    unsigned long long e = 0;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < qsize; i += stride) {
+        uint64_t b0, b1;
+        acc.offsets(queue[i], b0, b1);
+        e += b1 - b0;
+    }
+    e = block_sum_u64(e);
+    if (threadIdx.x == 0 && e) atomicAdd(out, e);
+}
+
+// One step of 64 bytes [p0, p0 + 64) of a list ending at b1: whether this
+// lane holds a value's last byte, and the value (a label, or for DMd a
+// difference to be summed by the caller).  prevb is this lane's byte of the
+// previous step (0 before the list: a value's end).
+template <class Acc>
+__device__ __forceinline__ bool varint_step(const Acc &acc, uint64_t p0, uint64_t b1, uint32_t &prevb,
+                                            uint32_t &val) {
+    const uint32_t lane = lane_id();
+    const uint64_t p = p0 + lane;
+    const bool in = p < b1;
+    const uint32_t b = in ? acc.byte(p) : 128u;
+    const bool end = in && !(b & 128u);
+    uint32_t v = b & 127u;
+    bool open = true;
+#pragma unroll
+    for (int t = 1; t <= 4; ++t) {
+        const int src = (int)lane - t;
+        const uint32_t cur = __shfl(b, src & (kWave - 1), kWave);
+        const uint32_t old = __shfl(prevb, src & (kWave - 1), kWave);
+        const uint32_t bt = src >= 0 ? cur : old;
+        open = open && (bt & 128u);
+        if (open) v = (v << 7) | (bt & 127u);
+    }
+    prevb = b;
+    val = v;
+    return end;
+}
+
+template <class Acc, bool kParent>
+__global__ void td_varint_kernel(Acc acc, uint32_t n, const uint32_t *__restrict__ queue, uint64_t qsize,
+                                 const uint64_t *__restrict__ visited, int32_t *__restrict__ depth,
+                                 uint32_t *__restrict__ parent, int32_t next_depth, uint32_t *__restrict__ queue_out,
+                                 unsigned long long *__restrict__ tail) {
+    const uint32_t lane = lane_id();
+    const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) / kWave;
+    for (uint64_t i = wave; i < qsize; i += nwaves) {
+        const uint32_t v = queue[i];
+        uint64_t b0, b1;
+        acc.offsets(v, b0, b1);
+        uint32_t prevb = 0, carry = 0;
+        for (uint64_t p0 = b0; p0 < b1; p0 += kWave) {
+            uint32_t x;
+            const bool end = varint_step(acc, p0, b1, prevb, x);
+            uint32_t label = x;
+            if constexpr (Acc::kDifferences) {
+                const uint32_t sc = wave_incl_scan(end ? x : 0u);
+                label = carry + sc;
+                carry += __shfl(sc, kWave - 1, kWave);
+            }
+            // a stored label is < n; the clamp keeps every access in bounds
+            const uint32_t u = label < n ? label : n - 1;
+            bool won = false;
+            if (end && !((visited[u >> 6] >> (u & 63)) & 1ull)) {
+                const int32_t old = atomicCAS(&depth[u], -1, next_depth);
+                if (kParent && (old == -1 || old == next_depth)) atomicMin(&parent[u], v);
+                won = old == -1;
+            }
+            const uint64_t m = __ballot(won);
+            if (m) {
+                unsigned long long base = 0;
+                if (lane == 0) base = atomicAdd(tail, (unsigned long long)__popcll(m));
+                base = __shfl(base, 0, kWave) + popc_below(m);
+                if (won) queue_out[base] = u;
+            }
+        }
+    }
+}
+
+template <class Acc, bool kParent>
+__global__ void bu_varint_kernel(Acc acc, uint32_t n, uint32_t threshold, const uint64_t *__restrict__ curr,
+                                 uint64_t *__restrict__ visited, uint64_t *__restrict__ next,
+                                 int32_t *__restrict__ depth, uint32_t *__restrict__ parent, int32_t next_depth,
+                                 unsigned long long *__restrict__ counters,
+                                 unsigned long long *__restrict__ next_counters, uint32_t *__restrict__ pv,
+                                 uint64_t *__restrict__ ppos, uint64_t *__restrict__ pend,
+                                 uint32_t *__restrict__ plabel) {
+    const uint32_t lane = lane_id();
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        next_counters[1] = 0;
+        next_counters[2] = 0;
+    }
+    const uint64_t words = ((uint64_t)n + 63) / 64;
+    const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) / kWave;
+    unsigned long long woke = 0;
+    for (uint64_t q = wave; q < words; q += nwaves) {
+        const uint64_t vis = visited[q];
+        if (vis == ~0ull) {
+            if (lane == 0) next[q] = 0;
+            continue;
+        }
+        const uint64_t v = q * 64 + lane;
+        const bool open = v < n && !((vis >> lane) & 1ull);
+        uint64_t b0 = 0, b1 = 0;
+        if (open) acc.offsets((uint32_t)v, b0, b1);
+        bool found = false, pending = false;
+        uint32_t par = 0, label = 0, count = 0;
+        uint64_t pos = b0;
+        uint32_t acc_v = 0, shift = 0;
+        while (pos < b1 && count < threshold && !found) {
+            // the 8 stream bytes from pos (two aligned words and a funnel
+            // shift; the pad word keeps the second one in bounds)
+            const uint64_t k = pos >> 3;
+            const uint32_t sh = (uint32_t)(pos & 7) * 8;
+            const uint64_t w0 = acc.word(k * 8), w1 = acc.word(k * 8 + 8);
+            const uint64_t win = sh ? (w0 >> sh) | (w1 << (64 - sh)) : w0;
+            const uint32_t avail = b1 - pos < 8 ? (uint32_t)(b1 - pos) : 8u;
+            for (uint32_t j = 0; j < avail && count < threshold && !found; ++j) {
+                const uint32_t b = (uint32_t)(win >> (8 * j)) & 255u;
+                acc_v |= (b & 127u) << shift;
+                shift += 7;
+                ++pos;
+                if (!(b & 128u)) {
+                    label = Acc::kDifferences && count ? label + acc_v : acc_v;
+                    ++count;
+                    acc_v = 0;
+                    shift = 0;
+                    const uint32_t u = label < n ? label : n - 1;
+                    if ((curr[u >> 6] >> (u & 63)) & 1ull) { found = true; par = u; }
+                }
+            }
+        }
+        // a list cut at `threshold` values ends on a value boundary
+        pending = open && !found && pos < b1;
+        const uint64_t fm = __ballot(found);
+        if (found) {
+            depth[v] = next_depth;
+            if (kParent) parent[v] = par;
+        }
+        if (lane == 0) next[q] = fm;
+        if (lane == 0 && fm) {
+            visited[q] |= fm;
+            woke += (unsigned long long)__popcll(fm);
+        }
+        const uint64_t pm = __ballot(pending);
+        if (pm) {
+            unsigned long long base = 0;
+            if (lane == 0) base = atomicAdd(&counters[2], (unsigned long long)__popcll(pm));
+            base = __shfl(base, 0, kWave) + popc_below(pm);
+            if (pending) {
+                pv[base] = (uint32_t)v;
+                ppos[base] = pos;
+                pend[base] = b1;
+                plabel[base] = label;  // the last label read (DMd continues from it)
+            }
+        }
+    }
+    woke = block_sum_u64(woke);
+    if (threadIdx.x == 0 && woke) atomicAdd(&counters[1], woke);
+}
+
+template <class Acc, bool kParent>
+__global__ void bu_varint_pending_kernel(Acc acc, uint32_t n, uint64_t np, const uint32_t *__restrict__ pv,
+                                         const uint64_t *__restrict__ ppos, const uint64_t *__restrict__ pend,
+                                         const uint32_t *__restrict__ plabel, const uint64_t *__restrict__ curr,
+                                         unsigned long long *__restrict__ visited,
+                                         unsigned long long *__restrict__ next, int32_t *__restrict__ depth,
+                                         uint32_t *__restrict__ parent, int32_t next_depth,
+                                         unsigned long long *__restrict__ counters) {
+    const uint32_t lane = lane_id();
+    const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) / kWave;
+    unsigned long long woke = 0;
+    for (uint64_t p = wave; p < np; p += nwaves) {
+        const uint32_t v = pv[p];
+        const uint64_t b1 = pend[p];
+        uint32_t prevb = 0, carry = plabel[p];
+        for (uint64_t p0 = ppos[p]; p0 < b1; p0 += kWave) {
+            uint32_t x;
+            const bool end = varint_step(acc, p0, b1, prevb, x);
+            uint32_t label = x;
+            if constexpr (Acc::kDifferences) {
+                const uint32_t sc = wave_incl_scan(end ? x : 0u);
+                label = carry + sc;
+                carry += __shfl(sc, kWave - 1, kWave);
+            }
+            const uint32_t u = label < n ? label : n - 1;
+            const bool hit = end && ((curr[u >> 6] >> (u & 63)) & 1ull);
+            const uint64_t m = __ballot(hit);
+            if (m) {
+                const uint32_t first = (uint32_t)__ffsll((long long)m) - 1;
+                const uint32_t par = __shfl(u, first, kWave);
+                if (lane == 0) {
+                    depth[v] = next_depth;
+                    if (kParent) parent[v] = par;
+                    atomicOr(&next[v >> 6], 1ull << (v & 63));
+                    atomicOr(&visited[v >> 6], 1ull << (v & 63));
+                    ++woke;
+                }
+                break;
+            }
+        }
+    }
+    woke = block_sum_u64(woke);
+    if (threadIdx.x == 0 && woke) atomicAdd(&counters[1], woke);
+}
+
 // results in original IDs: depth_out[o] = depth[inv[o]], parent through perm
 // (unreached vertices, among them every edgeless one, need no parent lookup)
 __global__ void bfs_unpermute_kernel(uint32_t n, const uint32_t *__restrict__ inv, const uint32_t *__restrict__ perm,
@@ -862,13 +1086,15 @@ static lg_status bfs_one(lg_graph *g, BfsWork &w, Acc acc, uint32_t root_id, con
     return LG_OK;
 }
 
-// The traversal over gap lists: the same level structure and direction
-// rule as bfs_one, with the in-order kernels above (the frontier's edge
-// count, from every frontier vertex's degree, decides the direction).
+// The traversal over gap or Varint lists: the same level structure and
+// direction rule as bfs_one, with the in-order kernels above (the frontier's
+// edge count, from every frontier vertex's degree, or its list bytes for
+// Varint lists, decides the direction).
 template <class Acc>
-static lg_status bfs_one_gap(lg_graph *g, BfsWork &w, Acc acc, uint32_t root_id, const uint32_t *inv,
-                             int32_t *depth, uint32_t *parent, int32_t max_depth, uint32_t flags, double alpha,
-                             hipStream_t s) {
+static lg_status bfs_one_inorder(lg_graph *g, BfsWork &w, Acc acc, uint32_t root_id, const uint32_t *inv,
+                                 int32_t *depth, uint32_t *parent, int32_t max_depth, uint32_t flags, double alpha,
+                                 hipStream_t s) {
+    constexpr bool kGap = IsGapAcc<Acc>::value;
     const uint32_t n = g->n;
     const uint64_t words = ((uint64_t)n + 63) / 64;
     const uint32_t thr = g->heavy_threshold;
@@ -878,7 +1104,7 @@ static lg_status bfs_one_gap(lg_graph *g, BfsWork &w, Acc acc, uint32_t root_id,
     LG_LAUNCH(bfs_init_kernel, grid_for(n, 256, 1u << 16), 256, 0, s, n, depth, parent, g->iso.as<uint64_t>(),
               visited, root_id, inv, qin, (uint64_t *)ctr);
     LG_CHECK_LAUNCH();
-    uint64_t qsize = 1, edges_to_check = g->m, awake = 0;
+    uint64_t qsize = 1, edges_to_check = kGap ? g->m : g->U / 8, awake = 0;
     int32_t level = 0;
     bool topdown = true;
     uint32_t bu_pair = 0;
@@ -889,8 +1115,12 @@ static lg_status bfs_one_gap(lg_graph *g, BfsWork &w, Acc acc, uint32_t root_id,
             bool go_bu = flags == LG_BFS_BOTTOM_UP && level >= 1;
             if (flags == LG_BFS_DIRECTION_OPT) {
                 LG_TRY(fill_u64(w.fscan.as<uint64_t>(), 0, 1, s));
-                LG_LAUNCH(gap_frontier_edges_kernel<Acc>, grid_for(qsize, 256, 1024), 256, 0, s, acc, qin, qsize,
-                          w.fscan.as<unsigned long long>());
+                if constexpr (kGap)
+                    LG_LAUNCH(gap_frontier_edges_kernel<Acc>, grid_for(qsize, 256, 1024), 256, 0, s, acc, qin, qsize,
+                              w.fscan.as<unsigned long long>());
+                else
+                    LG_LAUNCH(varint_frontier_bytes_kernel<Acc>, grid_for(qsize, 256, 1024), 256, 0, s, acc, qin,
+                              qsize, w.fscan.as<unsigned long long>());
                 LG_CHECK_LAUNCH();
                 LG_CHECK_HIP(hipMemcpyAsync(w.host, w.fscan.p, 8, hipMemcpyDeviceToHost, s));
                 LG_CHECK_HIP(hipStreamSynchronize(s));
@@ -908,12 +1138,21 @@ static lg_status bfs_one_gap(lg_graph *g, BfsWork &w, Acc acc, uint32_t root_id,
                 continue;
             }
             const uint32_t grid = grid_for(qsize * kWave, 256, kStrideBlocks);
-            if (parent)
-                LG_LAUNCH((td_gap_kernel<Acc, true>), grid, 256, 0, s, acc, n, qin, qsize, visited, depth, parent,
-                          level + 1, qout, ctr);
-            else
-                LG_LAUNCH((td_gap_kernel<Acc, false>), grid, 256, 0, s, acc, n, qin, qsize, visited, depth, parent,
-                          level + 1, qout, ctr);
+            if constexpr (kGap) {
+                if (parent)
+                    LG_LAUNCH((td_gap_kernel<Acc, true>), grid, 256, 0, s, acc, n, qin, qsize, visited, depth, parent,
+                              level + 1, qout, ctr);
+                else
+                    LG_LAUNCH((td_gap_kernel<Acc, false>), grid, 256, 0, s, acc, n, qin, qsize, visited, depth,
+                              parent, level + 1, qout, ctr);
+            } else {
+                if (parent)
+                    LG_LAUNCH((td_varint_kernel<Acc, true>), grid, 256, 0, s, acc, n, qin, qsize, visited, depth,
+                              parent, level + 1, qout, ctr);
+                else
+                    LG_LAUNCH((td_varint_kernel<Acc, false>), grid, 256, 0, s, acc, n, qin, qsize, visited, depth,
+                              parent, level + 1, qout, ctr);
+            }
             LG_CHECK_LAUNCH();
             LG_CHECK_HIP(hipMemcpyAsync(w.host, ctr, 8, hipMemcpyDeviceToHost, s));
             LG_CHECK_HIP(hipStreamSynchronize(s));
@@ -930,30 +1169,57 @@ static lg_status bfs_one_gap(lg_graph *g, BfsWork &w, Acc acc, uint32_t root_id,
             unsigned long long *bc_next = ctr + 2 * (bu_pair ^ 1u);
             bu_pair ^= 1u;
             const uint32_t grid = grid_for(words * kWave, 256, kStrideBlocks);
-            if (parent)
-                LG_LAUNCH((bu_gap_kernel<Acc, true>), grid, 256, 0, s, acc, n, thr, curr, visited, next, depth, parent,
-                          level + 1, bc, bc_next, w.pv.as<uint32_t>(), w.pstart.as<uint64_t>(), w.pdeg.as<uint32_t>(),
-                          w.pw.as<uint32_t>(), w.pseg_cnt.as<uint32_t>());
-            else
-                LG_LAUNCH((bu_gap_kernel<Acc, false>), grid, 256, 0, s, acc, n, thr, curr, visited, next, depth,
-                          parent, level + 1, bc, bc_next, w.pv.as<uint32_t>(), w.pstart.as<uint64_t>(),
-                          w.pdeg.as<uint32_t>(), w.pw.as<uint32_t>(), w.pseg_cnt.as<uint32_t>());
+            // pending lists: gap -- vertex, list start, degree, widths, label
+            // of entry threshold - 1; Varint -- vertex, next byte, end byte,
+            // last label
+            if constexpr (kGap) {
+                if (parent)
+                    LG_LAUNCH((bu_gap_kernel<Acc, true>), grid, 256, 0, s, acc, n, thr, curr, visited, next, depth,
+                              parent, level + 1, bc, bc_next, w.pv.as<uint32_t>(), w.pstart.as<uint64_t>(),
+                              w.pdeg.as<uint32_t>(), w.pw.as<uint32_t>(), w.pseg_cnt.as<uint32_t>());
+                else
+                    LG_LAUNCH((bu_gap_kernel<Acc, false>), grid, 256, 0, s, acc, n, thr, curr, visited, next, depth,
+                              parent, level + 1, bc, bc_next, w.pv.as<uint32_t>(), w.pstart.as<uint64_t>(),
+                              w.pdeg.as<uint32_t>(), w.pw.as<uint32_t>(), w.pseg_cnt.as<uint32_t>());
+            } else {
+                if (parent)
+                    LG_LAUNCH((bu_varint_kernel<Acc, true>), grid, 256, 0, s, acc, n, thr, curr, visited, next, depth,
+                              parent, level + 1, bc, bc_next, w.pv.as<uint32_t>(), w.pstart.as<uint64_t>(),
+                              w.pseg_off.as<uint64_t>(), w.pseg_cnt.as<uint32_t>());
+                else
+                    LG_LAUNCH((bu_varint_kernel<Acc, false>), grid, 256, 0, s, acc, n, thr, curr, visited, next,
+                              depth, parent, level + 1, bc, bc_next, w.pv.as<uint32_t>(), w.pstart.as<uint64_t>(),
+                              w.pseg_off.as<uint64_t>(), w.pseg_cnt.as<uint32_t>());
+            }
             LG_CHECK_LAUNCH();
             LG_CHECK_HIP(hipMemcpyAsync(w.host, bc + 1, 16, hipMemcpyDeviceToHost, s));
             LG_CHECK_HIP(hipStreamSynchronize(s));
             const uint64_t np = w.host[1];
             if (np) {
                 const uint32_t pgrid = grid_for(np * kWave, 256, kStrideBlocks);
-                if (parent)
-                    LG_LAUNCH((bu_gap_pending_kernel<Acc, true>), pgrid, 256, 0, s, acc, n, thr, np,
-                              w.pv.as<uint32_t>(), w.pstart.as<uint64_t>(), w.pdeg.as<uint32_t>(), w.pw.as<uint32_t>(),
-                              w.pseg_cnt.as<uint32_t>(), curr, (unsigned long long *)visited,
-                              (unsigned long long *)next, depth, parent, level + 1, bc);
-                else
-                    LG_LAUNCH((bu_gap_pending_kernel<Acc, false>), pgrid, 256, 0, s, acc, n, thr, np,
-                              w.pv.as<uint32_t>(), w.pstart.as<uint64_t>(), w.pdeg.as<uint32_t>(), w.pw.as<uint32_t>(),
-                              w.pseg_cnt.as<uint32_t>(), curr, (unsigned long long *)visited,
-                              (unsigned long long *)next, depth, parent, level + 1, bc);
+                if constexpr (kGap) {
+                    if (parent)
+                        LG_LAUNCH((bu_gap_pending_kernel<Acc, true>), pgrid, 256, 0, s, acc, n, thr, np,
+                                  w.pv.as<uint32_t>(), w.pstart.as<uint64_t>(), w.pdeg.as<uint32_t>(),
+                                  w.pw.as<uint32_t>(), w.pseg_cnt.as<uint32_t>(), curr, (unsigned long long *)visited,
+                                  (unsigned long long *)next, depth, parent, level + 1, bc);
+                    else
+                        LG_LAUNCH((bu_gap_pending_kernel<Acc, false>), pgrid, 256, 0, s, acc, n, thr, np,
+                                  w.pv.as<uint32_t>(), w.pstart.as<uint64_t>(), w.pdeg.as<uint32_t>(),
+                                  w.pw.as<uint32_t>(), w.pseg_cnt.as<uint32_t>(), curr, (unsigned long long *)visited,
+                                  (unsigned long long *)next, depth, parent, level + 1, bc);
+                } else {
+                    if (parent)
+                        LG_LAUNCH((bu_varint_pending_kernel<Acc, true>), pgrid, 256, 0, s, acc, n, np,
+                                  w.pv.as<uint32_t>(), w.pstart.as<uint64_t>(), w.pseg_off.as<uint64_t>(),
+                                  w.pseg_cnt.as<uint32_t>(), curr, (unsigned long long *)visited,
+                                  (unsigned long long *)next, depth, parent, level + 1, bc);
+                    else
+                        LG_LAUNCH((bu_varint_pending_kernel<Acc, false>), pgrid, 256, 0, s, acc, n, np,
+                                  w.pv.as<uint32_t>(), w.pstart.as<uint64_t>(), w.pseg_off.as<uint64_t>(),
+                                  w.pseg_cnt.as<uint32_t>(), curr, (unsigned long long *)visited,
+                                  (unsigned long long *)next, depth, parent, level + 1, bc);
+                }
                 LG_CHECK_LAUNCH();
                 LG_CHECK_HIP(hipMemcpyAsync(w.host, bc + 1, 8, hipMemcpyDeviceToHost, s));
                 LG_CHECK_HIP(hipStreamSynchronize(s));
@@ -983,11 +1249,13 @@ lg_status bfs_run(lg_graph *g, BfsWork &w, const uint32_t *roots, uint32_t r, in
     LG_TRY(bfs_workspace_ensure(w, g->n, g->n_heavy, g->relabel != LG_RELABEL_NONE, parent != nullptr));
     const bool rel = g->relabel != LG_RELABEL_NONE;
     const uint32_t *inv = rel ? g->inv.as<uint32_t>() : nullptr;
-    return dispatch_acc_all(g, [&](auto acc) -> lg_status {
-        // one traversal: the in-order kernels for gap lists, else the general ones
+    return dispatch_acc_dec(g, [&](auto acc) -> lg_status {
+        // one traversal: the in-order kernels for gap and Varint lists, else
+        // the general ones
         auto one = [&](uint32_t root, int32_t *d, uint32_t *p) -> lg_status {
-            if constexpr (IsGapAcc<decltype(acc)>::value)
-                return bfs_one_gap(g, w, acc, root, inv, d, p, max_depth, flags, alpha, stream);
+            using A = decltype(acc);
+            if constexpr (IsGapAcc<A>::value || IsVarintAcc<A>::value)
+                return bfs_one_inorder(g, w, acc, root, inv, d, p, max_depth, flags, alpha, stream);
             else
                 return bfs_one(g, w, acc, root, inv, d, p, max_depth, flags, alpha, stream);
         };

@@ -1,7 +1,8 @@
 """Varint lists on the GPU (subsection "Incorporating Degree-Minimizing
 (DM)": DMf = full labels, DMd = first label and differences, each a
 base-128 Varint): every array bit-exact against the oracle, lists decoded
-against the input, and the traversals refusing such graphs."""
+against the input, BFS over them against the oracle, and PageRank and
+batch plans refusing such graphs."""
 
 import numpy as np
 import pytest
@@ -111,16 +112,58 @@ def test_varint_four_byte_values(lgmod, e):
     h.free()
 
 
-def test_varint_traversals_unsupported(lgmod):
+@pytest.mark.parametrize("mode", ["do", "td", "bu"])
+@pytest.mark.parametrize("e", VARINT, ids=vid)
+@pytest.mark.parametrize("name", list(GRAPHS))
+def test_varint_bfs(lgmod, name, e, mode):
+    """BFS over Varint lists (read in order): depths and parents bit-exact
+    against the oracle, every direction mode."""
+    g = GRAPHS[name]
+    off, col = g.numpy()
+    roots = gg.pick_roots(g, 3, seed=4) or [0]
+    if 0 not in roots:
+        roots = roots + [0]
+    print(f"[varint bfs] {name} {vid(e)} {mode} roots={roots}", flush=True)
+    h = encode(lgmod, g, e)
+    depth, parent = lgmod.bfs(h, roots, mode=mode)
+    depth, parent = depth.cpu().numpy(), parent.cpu().numpy()
+    for i, r in enumerate(roots):
+        d0, p0 = orc.bfs(off, col, r, relabeled=bool(e["relabel"]))
+        np.testing.assert_array_equal(depth[i], d0)
+        np.testing.assert_array_equal(parent[i], p0)
+    h.free()
+
+
+def test_varint_bfs_four_byte_labels(lgmod):
+    """Values of up to four bytes, hubs longer than the lane's 64-value limit."""
+    n = (1 << 21) + 300
+    rng = np.random.default_rng(5)
+    far = np.unique(rng.integers(1 << 21, n, size=200))
+    edges = [(0, int(x)) for x in np.concatenate([np.arange(1, 150), far])] + [(5, int(x)) for x in far[:40]]
+    g = gg.csr_from_edges(n, edges)
+    off, col = g.numpy()
+    for ids in ("varint-full", "varint-diff"):
+        h = encode(lgmod, g, dict(layout="packed", ids=ids, offsets="succinct", relabel=False))
+        for mode in ("do", "td", "bu"):
+            depth, parent = lgmod.bfs(h, [0, int(far[3])], mode=mode)
+            for i, r in enumerate([0, int(far[3])]):
+                d0, p0 = orc.bfs(off, col, r)
+                np.testing.assert_array_equal(depth[i].cpu().numpy(), d0)
+                np.testing.assert_array_equal(parent[i].cpu().numpy(), p0)
+        h.free()
+
+
+def test_varint_unsupported(lgmod):
     from paper_2010_15879_amd.lg import LGError, LG_ERR_UNSUPPORTED
     g = GRAPHS["kron12"]
     h = encode(lgmod, g, VARINT[-1])
-    root = gg.pick_roots(g, 1, seed=1)
-    with pytest.raises(LGError) as ei:
-        lgmod.bfs(h, root)
-    assert ei.value.status == LG_ERR_UNSUPPORTED
     with pytest.raises(LGError) as ei:
         lgmod.pagerank(h, 0.85, 2)
+    assert ei.value.status == LG_ERR_UNSUPPORTED
+    h.free()
+    h = encode(lgmod, g, VARINT[-2])
+    with pytest.raises(LGError) as ei:
+        lgmod.BatchPlan([h], [(0, 1)])
     assert ei.value.status == LG_ERR_UNSUPPORTED
     h.free()
 
@@ -137,5 +180,12 @@ def test_varint_kronecker16(lgmod):
         np.testing.assert_array_equal(h.export("adj"), o.A)
         np.testing.assert_array_equal(h.export("ef_low"), o.ef.low)
         sizes[ids] = h.info()["adj_bits"]
+        off, col = g.numpy()
+        roots = gg.pick_roots(g, 2, seed=6)
+        depth, parent = lgmod.bfs(h, roots)
+        for i, r in enumerate(roots):
+            d0, p0 = orc.bfs(off, col, r, relabeled=True)
+            np.testing.assert_array_equal(depth[i].cpu().numpy(), d0)
+            np.testing.assert_array_equal(parent[i].cpu().numpy(), p0)
         h.free()
     assert sizes["varint-diff"] <= sizes["varint-full"]
