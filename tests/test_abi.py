@@ -47,3 +47,12 @@ def test_oracle_is_not_reachable_from_the_product():
             if f.endswith((".py", ".hip", ".hpp", ".h", ".cpp")):
                 src = open(os.path.join(dirpath, f)).read()
                 assert "oracle" not in src.replace("Oracle", "").lower() or f == "graphgen.py", f
+
+
+def test_weights_length_checked_before_the_library():
+    import pytest
+    import torch
+    off = torch.tensor([0, 1, 2], dtype=torch.int64)
+    col = torch.tensor([1, 0], dtype=torch.int32)
+    with pytest.raises(ValueError):
+        lg.encode(off, col, 2, weights=torch.ones(3, dtype=torch.int32))

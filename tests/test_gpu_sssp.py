@@ -160,3 +160,16 @@ def test_weighted_plain_traversals(lgmod):
     pr = lgmod.pagerank(h, 0.85, 5).cpu().numpy().astype(np.float64)
     assert np.abs(pr - orc.pagerank(off, col, 0.85, 5)).sum() <= 1e-5
     h.free()
+
+
+def test_sssp_invalid_arguments(lgmod):
+    from paper_2010_15879_amd.lg import LGError, LG_ERR_INVALID
+    g = GRAPHS["kron12"]
+    h = encode(lgmod, g, weights_for(g), WENC[3])
+    with pytest.raises(LGError) as ei:
+        lgmod.sssp(h, g.n)
+    assert ei.value.status == LG_ERR_INVALID
+    h.free()
+    d = g.to("cuda")
+    with pytest.raises(ValueError):
+        lgmod.encode(d.row_offsets, d.col, g.n, weights=torch.ones(3, dtype=torch.int32, device="cuda"))
