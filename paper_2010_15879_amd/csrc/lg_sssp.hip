@@ -104,7 +104,7 @@ constexpr uint32_t kSsspDefaultDelta = 256;
 
 struct SsspWork {
     DevBuf upd;                         // bitmap, one bit per vertex
-    DevBuf qw, qdeg;                    // frontier: ID width, degree
+    DevBuf qv, qw, qdeg;                // frontier: vertex, ID width, degree
     DevBuf qstart, qdist, qoff;         // list start, distance, exclusive scan of qdeg
     DevBuf ctr;                         // [0] frontier size, [1] smallest distance left marked
     DevBuf tmask, wcnt, woff;           // per bitmap word: vertices taken, their count, queue position
@@ -117,7 +117,7 @@ struct SsspWork {
         if (host) (void)hipHostFree(host);
     }
     uint64_t bytes() const {
-        return upd.bytes + qw.bytes + qdeg.bytes + qstart.bytes + qdist.bytes + qoff.bytes + ctr.bytes +
+        return upd.bytes + qv.bytes + qw.bytes + qdeg.bytes + qstart.bytes + qdist.bytes + qoff.bytes + ctr.bytes +
                tmask.bytes + wcnt.bytes + woff.bytes + scan_tmp.bytes;
     }
 };
@@ -200,7 +200,7 @@ __global__ __launch_bounds__(kCollectThreads) void sssp_count_kernel(
 template <class Acc>
 __global__ __launch_bounds__(kCollectThreads) void sssp_write_kernel(
     Acc acc, uint32_t n, uint64_t words, const uint64_t *__restrict__ dist, const uint64_t *__restrict__ tmask,
-    const uint64_t *__restrict__ woff, uint64_t *__restrict__ qstart, uint32_t *__restrict__ qw,
+    const uint64_t *__restrict__ woff, uint32_t *__restrict__ qv, uint64_t *__restrict__ qstart, uint32_t *__restrict__ qw,
     uint32_t *__restrict__ qdeg, uint64_t *__restrict__ qdist, unsigned long long *__restrict__ ctr) {
     const uint32_t lane = lane_id();
     const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
@@ -213,6 +213,7 @@ __global__ __launch_bounds__(kCollectThreads) void sssp_write_kernel(
             const uint64_t v = q * 64 + lane;
             const WInfo vi = acc.info((uint32_t)v);
             const uint64_t pos = woff[q] + popc_below(m);
+            qv[pos] = (uint32_t)v;
             qstart[pos] = vi.start;
             qw[pos] = vi.w;
             qdeg[pos] = vi.deg;
@@ -232,7 +233,8 @@ __global__ __launch_bounds__(kCollectThreads) void sssp_write_kernel(
 // edge.
 template <class Acc>
 __global__ void sssp_relax_kernel(Acc acc, uint32_t n, const uint64_t *__restrict__ count_p,
-                                  const uint64_t *__restrict__ qoff, const uint64_t *__restrict__ qstart,
+                                  const uint64_t *__restrict__ qoff, const uint32_t *__restrict__ qv,
+                                  const uint64_t *__restrict__ qstart,
                                   const uint32_t *__restrict__ qw, const uint64_t *__restrict__ qdist,
                                   unsigned long long *__restrict__ dist, unsigned long long *__restrict__ upd) {
     const uint32_t lane = lane_id();
@@ -258,8 +260,11 @@ __global__ void sssp_relax_kernel(Acc acc, uint32_t n, const uint64_t *__restric
         const uint64_t M = wave_sum(o < kWave ? 1ull << o : 0ull);
         const uint64_t adv = (uint64_t)__popcll(__ballot(o <= kWave));
         const uint64_t t = t0 + lane;
-        if (t < te) {
-            const uint64_t a = s0 + (uint64_t)__popcll(M & below);
+        // a frontier vertex whose distance dropped again since it was
+        // collected is marked again and relaxes next step from the lower
+        // distance: its edges are skipped now
+        const uint64_t a = s0 + (uint64_t)__popcll(M & below);
+        if (t < te && dist[qv[a]] >= qdist[a]) {
             uint32_t id, w;
             acc.entry(qstart[a], qw[a], t - qoff[a], id, w);
             if (id < n) {  // only a corrupt stream fails this
@@ -304,6 +309,7 @@ extern "C" lg_status lg_sssp(const lg_graph *gc, uint32_t root, uint32_t delta, 
     LG_TRY(W.tmask.ensure(words * 8));
     LG_TRY(W.wcnt.ensure(words * 4));
     LG_TRY(W.woff.ensure((words + 1) * 8));
+    LG_TRY(W.qv.ensure((uint64_t)n * 4));
     LG_TRY(W.qw.ensure((uint64_t)n * 4));
     LG_TRY(W.qdeg.ensure((uint64_t)n * 4));
     LG_TRY(W.qstart.ensure((uint64_t)n * 8));
@@ -338,7 +344,7 @@ extern "C" lg_status lg_sssp(const lg_graph *gc, uint32_t root, uint32_t delta, 
             LG_TRY(exclusive_scan_u32(W.wcnt.as<uint32_t>(), W.woff.as<uint64_t>(), words, W.scan_tmp, stream));
             LG_LAUNCH(sssp_write_kernel<Acc>, collect_grid, kCollectThreads, 0, stream, acc, n, words,
                       (const uint64_t *)dist, (const uint64_t *)W.tmask.as<uint64_t>(),
-                      (const uint64_t *)W.woff.as<uint64_t>(), W.qstart.as<uint64_t>(), W.qw.as<uint32_t>(),
+                      (const uint64_t *)W.woff.as<uint64_t>(), W.qv.as<uint32_t>(), W.qstart.as<uint64_t>(), W.qw.as<uint32_t>(),
                       W.qdeg.as<uint32_t>(), W.qdist.as<uint64_t>(), W.ctr.as<unsigned long long>());
             LG_CHECK_LAUNCH();
             LG_CHECK_HIP(hipMemcpyAsync(W.host, W.ctr.p, 16, hipMemcpyDeviceToHost, stream));
@@ -353,7 +359,7 @@ extern "C" lg_status lg_sssp(const lg_graph *gc, uint32_t root, uint32_t delta, 
             LG_TRY(exclusive_scan_u32(W.qdeg.as<uint32_t>(), W.qoff.as<uint64_t>(), count, W.scan_tmp, stream));
             LG_LAUNCH(sssp_relax_kernel<Acc>, relax_grid, 256, 0, stream, acc, n,
                       (const uint64_t *)W.ctr.as<uint64_t>(), (const uint64_t *)W.qoff.as<uint64_t>(),
-                      (const uint64_t *)W.qstart.as<uint64_t>(), (const uint32_t *)W.qw.as<uint32_t>(),
+                      (const uint32_t *)W.qv.as<uint32_t>(), (const uint64_t *)W.qstart.as<uint64_t>(), (const uint32_t *)W.qw.as<uint32_t>(),
                       (const uint64_t *)W.qdist.as<uint64_t>(), (unsigned long long *)dist,
                       W.upd.as<unsigned long long>());
             LG_CHECK_LAUNCH();
