@@ -490,6 +490,55 @@ __global__ void bitmap_to_queue_kernel(uint64_t words, const uint64_t *__restric
 // rules of the other encodings (the smallest label one level up).
 // ---------------------------------------------------------------------------
 
+// The two offset values bracketing the list of v0 + lane, decoded by the
+// whole wave for a 64-aligned v0 (with Elias-Fano offsets one select per
+// wave instead of one per lane); every lane of the wave must call it.
+// Base: the local-ID packed accessor under a gap or Varint accessor.
+template <class Base>
+__device__ __forceinline__ void wave_offsets(const Base &acc, uint64_t v0, uint32_t n, uint64_t &o0, uint64_t &o1) {
+    const uint32_t lane = lane_id();
+    const uint64_t v = v0 + lane;
+    const uint64_t vv = v < n ? v : n;
+    const uint64_t ve = v0 + kWave < n ? v0 + kWave : n;
+    uint64_t end;
+    if constexpr (Base::kEF) {
+        const EFView &e = acc.pv.ef;
+        const uint64_t lo0 = e.l ? extract64(e.L, vv * e.l, e.l) : 0ull;
+        const uint64_t lo_end = (e.l && v0 + kWave <= n) ? extract64(e.L, ve * e.l, e.l) : 0ull;
+        uint64_t pos, pos_end;
+        ef_wave_select(e, v0, n + 1, ef_samples(e, v0, n + 1), pos, pos_end);
+        if (v > n) pos = 0;
+        o0 = v <= n ? (((pos - vv) << e.l) | lo0) : 0ull;
+        if (v0 + kWave <= n) end = ((pos_end - ve) << e.l) | lo_end;
+        else end = __shfl(o0, (uint32_t)(n - v0), kWave);
+    } else {
+        o0 = acc.offset_value((uint32_t)vv);
+        end = acc.offset_value((uint32_t)ve);
+    }
+    o1 = __shfl_down(o0, 1, kWave);
+    if (lane == kWave - 1) o1 = end;
+}
+
+// The sampled direction estimate of the in-order traversals: degrees (gap)
+// or list bytes (Varint) of kDirSample frontier vertices at evenly spaced
+// queue positions, a partial sum per block.
+template <class Acc>
+__global__ __launch_bounds__(kDirSampleThreads) void inorder_sample_kernel(Acc acc, const uint32_t *__restrict__ queue,
+                                                                           uint64_t qsize, uint64_t *__restrict__ part) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t v = queue[i * qsize / kDirSample];
+    unsigned long long d;
+    if constexpr (IsGapAcc<Acc>::value) {
+        d = acc.info(v).deg;
+    } else {
+        uint64_t b0, b1;
+        acc.offsets(v, b0, b1);
+        d = b1 - b0;
+    }
+    const unsigned long long t = block_sum_u64(d);
+    if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
 template <class Acc>
 __global__ void gap_frontier_edges_kernel(Acc acc, const uint32_t *__restrict__ queue, uint64_t qsize,
                                           unsigned long long *__restrict__ out) {
@@ -563,7 +612,15 @@ __global__ void bu_gap_kernel(Acc acc, uint32_t n, uint32_t threshold, const uin
         }
         const uint64_t v = q * 64 + lane;
         const bool open = v < n && !((vis >> lane) & 1ull);
-        const GapInfo gi = open ? acc.info((uint32_t)v) : GapInfo{0, 0, 0, 0};
+        uint64_t o0, o1;
+        wave_offsets(acc.base, q * 64, n, o0, o1);
+        GapInfo gi{0, 0, 0, 0};
+        if (open && o1 > o0) {
+            gi.start = o0;
+            gi.w = acc.base.width((uint32_t)v);
+            gi.g = acc.gap_width((uint32_t)v);
+            gi.deg = gi.g == 0 ? 1u : 1u + exact_div_width(o1 - o0 - gi.w, gi.g);
+        }
         bool found = false, pending = false;
         uint32_t par = 0, val = 0;
         if (open && gi.deg) {
@@ -788,8 +845,9 @@ __global__ void bu_varint_kernel(Acc acc, uint32_t n, uint32_t threshold, const 
         }
         const uint64_t v = q * 64 + lane;
         const bool open = v < n && !((vis >> lane) & 1ull);
-        uint64_t b0 = 0, b1 = 0;
-        if (open) acc.offsets((uint32_t)v, b0, b1);
+        uint64_t b0, b1;
+        wave_offsets(acc.base, q * 64, n, b0, b1);
+        if (!open) b1 = b0;
         bool found = false, pending = false;
         uint32_t par = 0, label = 0, count = 0;
         uint64_t pos = b0;
@@ -1113,7 +1171,20 @@ static lg_status bfs_one_inorder(lg_graph *g, BfsWork &w, Acc acc, uint32_t root
         if (topdown) {
             if (qsize == 0) break;
             bool go_bu = flags == LG_BFS_BOTTOM_UP && level >= 1;
-            if (flags == LG_BFS_DIRECTION_OPT) {
+            if (flags == LG_BFS_DIRECTION_OPT && qsize > 2 * (uint64_t)kDirSample) {
+                // a large frontier: a sample at twice the switch point or
+                // more turns the search bottom-up without the exact count
+                LG_LAUNCH(inorder_sample_kernel<Acc>, kDirSampleBlocks, kDirSampleThreads, 0, s, acc, qin, qsize,
+                          w.fscan.as<uint64_t>());
+                LG_CHECK_LAUNCH();
+                LG_CHECK_HIP(hipMemcpyAsync(w.host, w.fscan.p, kDirSampleBlocks * 8, hipMemcpyDeviceToHost, s));
+                LG_CHECK_HIP(hipStreamSynchronize(s));
+                uint64_t sampled = 0;
+                for (uint32_t b = 0; b < kDirSampleBlocks; ++b) sampled += w.host[b];
+                const double est = (double)sampled * ((double)qsize / (double)kDirSample);
+                go_bu = est > 2.0 * (double)edges_to_check / alpha;
+            }
+            if (flags == LG_BFS_DIRECTION_OPT && !go_bu) {
                 LG_TRY(fill_u64(w.fscan.as<uint64_t>(), 0, 1, s));
                 if constexpr (kGap)
                     LG_LAUNCH(gap_frontier_edges_kernel<Acc>, grid_for(qsize, 256, 1024), 256, 0, s, acc, qin, qsize,
