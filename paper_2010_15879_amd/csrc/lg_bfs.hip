@@ -551,7 +551,7 @@ __global__ void gap_frontier_edges_kernel(Acc acc, const uint32_t *__restrict__ 
 }
 
 template <class Acc, bool kParent>
-__global__ void td_gap_kernel(Acc acc, uint32_t n, const uint32_t *__restrict__ queue, uint64_t qsize,
+__global__ void td_gap_kernel(Acc acc, uint32_t n, uint32_t split, const uint32_t *__restrict__ queue, uint64_t qsize,
                               const uint64_t *__restrict__ visited, int32_t *__restrict__ depth,
                               uint32_t *__restrict__ parent, int32_t next_depth, uint32_t *__restrict__ queue_out,
                               unsigned long long *__restrict__ tail) {
@@ -561,6 +561,7 @@ __global__ void td_gap_kernel(Acc acc, uint32_t n, const uint32_t *__restrict__ 
     for (uint64_t i = wave; i < qsize; i += nwaves) {
         const uint32_t v = queue[i];
         const GapInfo gi = acc.info(v);
+        if (gi.deg > split) continue;  // a segmented list: td_gap_seg_kernel
         uint32_t carry = 0;
         for (uint64_t j0 = 0; j0 < gi.deg; j0 += kWave) {
             const uint64_t j = j0 + lane;
@@ -570,6 +571,55 @@ __global__ void td_gap_kernel(Acc acc, uint32_t n, const uint32_t *__restrict__ 
             carry = __shfl(val, kWave - 1, kWave);
             // a stored label is < n; the clamp keeps every access in bounds
             // whatever the stream holds
+            const uint32_t u = val < n ? val : n - 1;
+            bool won = false;
+            if (valid && !((visited[u >> 6] >> (u & 63)) & 1ull)) {
+                const int32_t old = atomicCAS(&depth[u], -1, next_depth);
+                if (kParent && (old == -1 || old == next_depth)) atomicMin(&parent[u], v);
+                won = old == -1;
+            }
+            const uint64_t m = __ballot(won);
+            if (m) {
+                unsigned long long base = 0;
+                if (lane == 0) base = atomicAdd(tail, (unsigned long long)__popcll(m));
+                base = __shfl(base, 0, kWave) + popc_below(m);
+                if (won) queue_out[base] = u;
+            }
+        }
+    }
+}
+
+// The lists longer than `split` of the frontier, one wave per segment of
+// seg_size entries (the graph's tables: segment k of heavy vertex
+// seg_map[k], whose prefix starts from seg_base[k]); a segment whose vertex
+// is not in the frontier bitmap is skipped.
+template <class Acc, bool kParent>
+__global__ void td_gap_seg_kernel(Acc acc, uint32_t n, uint64_t n_seg, uint32_t seg_size,
+                                  const uint32_t *__restrict__ seg_map, const uint64_t *__restrict__ seg_off,
+                                  const uint32_t *__restrict__ heavy, const uint64_t *__restrict__ hstart,
+                                  const uint32_t *__restrict__ hdeg, const uint32_t *__restrict__ hw,
+                                  const uint32_t *__restrict__ hg, const uint32_t *__restrict__ seg_base,
+                                  const uint64_t *__restrict__ frontier, const uint64_t *__restrict__ visited,
+                                  int32_t *__restrict__ depth, uint32_t *__restrict__ parent, int32_t next_depth,
+                                  uint32_t *__restrict__ queue_out, unsigned long long *__restrict__ tail) {
+    const uint32_t lane = lane_id();
+    const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) / kWave;
+    for (uint64_t k = wave; k < n_seg; k += nwaves) {
+        const uint32_t h = seg_map[k];
+        const uint32_t v = heavy[h];
+        if (!((frontier[v >> 6] >> (v & 63)) & 1ull)) continue;  // same for every lane
+        const uint64_t d = hdeg[h];
+        const uint64_t e0 = (k - seg_off[h]) * seg_size;
+        const uint64_t e1 = e0 + seg_size < d ? e0 + seg_size : d;
+        const GapInfo gi{hstart[h], (uint32_t)d, hw[h], hg[h]};
+        uint32_t carry = seg_base[k];
+        for (uint64_t j0 = e0; j0 < e1; j0 += kWave) {
+            const uint64_t j = j0 + lane;
+            const bool valid = j < e1;
+            const uint32_t x = valid ? acc.get(Acc::entry_bit(gi, j), j ? gi.g : gi.w) : 0u;
+            const uint32_t val = wave_incl_scan(x) + carry;
+            carry = __shfl(val, kWave - 1, kWave);
             const uint32_t u = val < n ? val : n - 1;
             bool won = false;
             if (valid && !((visited[u >> 6] >> (u & 63)) & 1ull)) {
@@ -1210,11 +1260,34 @@ static lg_status bfs_one_inorder(lg_graph *g, BfsWork &w, Acc acc, uint32_t root
             }
             const uint32_t grid = grid_for(qsize * kWave, 256, kStrideBlocks);
             if constexpr (kGap) {
+                // lists above pr_split go by segments (tables built with the
+                // encoding), the rest a wave per list
+                const uint32_t split = g->n_seg ? g->pr_split : 0xFFFFFFFFu;
+                if (g->n_seg) {
+                    LG_TRY(fill_u64(curr, 0, words, s));
+                    LG_LAUNCH(mark_queue_kernel, grid_for(qsize, 256, 1u << 16), 256, 0, s, qin, qsize,
+                              (unsigned long long *)curr, ctr);
+                    LG_CHECK_LAUNCH();
+                    const uint32_t sgrid = grid_for(g->n_seg * kWave, 256, kStrideBlocks);
+                    if (parent)
+                        LG_LAUNCH((td_gap_seg_kernel<Acc, true>), sgrid, 256, 0, s, acc, n, g->n_seg, g->seg_size,
+                                  g->seg_map.as<uint32_t>(), g->seg_off.as<uint64_t>(), g->heavy.as<uint32_t>(),
+                                  g->hstart.as<uint64_t>(), g->hdeg.as<uint32_t>(), g->hw.as<uint32_t>(),
+                                  g->hg.as<uint32_t>(), g->seg_base.as<uint32_t>(), curr, visited, depth, parent,
+                                  level + 1, qout, ctr);
+                    else
+                        LG_LAUNCH((td_gap_seg_kernel<Acc, false>), sgrid, 256, 0, s, acc, n, g->n_seg, g->seg_size,
+                                  g->seg_map.as<uint32_t>(), g->seg_off.as<uint64_t>(), g->heavy.as<uint32_t>(),
+                                  g->hstart.as<uint64_t>(), g->hdeg.as<uint32_t>(), g->hw.as<uint32_t>(),
+                                  g->hg.as<uint32_t>(), g->seg_base.as<uint32_t>(), curr, visited, depth, parent,
+                                  level + 1, qout, ctr);
+                    LG_CHECK_LAUNCH();
+                }
                 if (parent)
-                    LG_LAUNCH((td_gap_kernel<Acc, true>), grid, 256, 0, s, acc, n, qin, qsize, visited, depth, parent,
-                              level + 1, qout, ctr);
+                    LG_LAUNCH((td_gap_kernel<Acc, true>), grid, 256, 0, s, acc, n, split, qin, qsize, visited, depth,
+                              parent, level + 1, qout, ctr);
                 else
-                    LG_LAUNCH((td_gap_kernel<Acc, false>), grid, 256, 0, s, acc, n, qin, qsize, visited, depth,
+                    LG_LAUNCH((td_gap_kernel<Acc, false>), grid, 256, 0, s, acc, n, split, qin, qsize, visited, depth,
                               parent, level + 1, qout, ctr);
             } else {
                 if (parent)

@@ -1359,7 +1359,11 @@ static lg_status encode_entry(uint32_t n, uint64_t m, const uint64_t *row_offset
     g->id_mode = o.layout == LG_LAYOUT_PACKED ? o.id_mode : 0;
     g->offset_mode = o.layout == LG_LAYOUT_PACKED ? o.offset_mode : 0;
     g->relabel = o.relabel;
-    const lg_status st = encode_impl(n, m, row_offsets, col, weights, o, stream, g);
+    lg_status st = encode_impl(n, m, row_offsets, col, weights, o, stream, g);
+    // gap lists: the per-segment starting values of the long lists serve the
+    // traversals too (several BFS lanes may run at once), so build them here
+    if (st == LG_OK && g->layout == LG_LAYOUT_PACKED && g->id_mode == LG_IDS_LOCAL_GAP)
+        st = ensure_heavy_segments(g, stream);
     if (st != LG_OK) {
         (void)hipStreamSynchronize(stream);
         lg_free(g);
