@@ -830,7 +830,7 @@ __device__ __forceinline__ bool varint_step(const Acc &acc, uint64_t p0, uint64_
 }
 
 template <class Acc, bool kParent>
-__global__ void td_varint_kernel(Acc acc, uint32_t n, const uint32_t *__restrict__ queue, uint64_t qsize,
+__global__ void td_varint_kernel(Acc acc, uint32_t n, uint64_t split, const uint32_t *__restrict__ queue, uint64_t qsize,
                                  const uint64_t *__restrict__ visited, int32_t *__restrict__ depth,
                                  uint32_t *__restrict__ parent, int32_t next_depth, uint32_t *__restrict__ queue_out,
                                  unsigned long long *__restrict__ tail) {
@@ -841,6 +841,7 @@ __global__ void td_varint_kernel(Acc acc, uint32_t n, const uint32_t *__restrict
         const uint32_t v = queue[i];
         uint64_t b0, b1;
         acc.offsets(v, b0, b1);
+        if (b1 - b0 > split) continue;  // a chunked list: td_varint_seg_kernel
         uint32_t prevb = 0, carry = 0;
         for (uint64_t p0 = b0; p0 < b1; p0 += kWave) {
             uint32_t x;
@@ -852,6 +853,116 @@ __global__ void td_varint_kernel(Acc acc, uint32_t n, const uint32_t *__restrict
                 carry += __shfl(sc, kWave - 1, kWave);
             }
             // a stored label is < n; the clamp keeps every access in bounds
+            const uint32_t u = label < n ? label : n - 1;
+            bool won = false;
+            if (end && !((visited[u >> 6] >> (u & 63)) & 1ull)) {
+                const int32_t old = atomicCAS(&depth[u], -1, next_depth);
+                if (kParent && (old == -1 || old == next_depth)) atomicMin(&parent[u], v);
+                won = old == -1;
+            }
+            const uint64_t m = __ballot(won);
+            if (m) {
+                unsigned long long base = 0;
+                if (lane == 0) base = atomicAdd(tail, (unsigned long long)__popcll(m));
+                base = __shfl(base, 0, kWave) + popc_below(m);
+                if (won) queue_out[base] = u;
+            }
+        }
+    }
+}
+
+// Chunk k of a long Varint list: bytes [c0, c1) of the list [b0, b1); the
+// look-back of the first lanes reads the four bytes before c0 (0 before the
+// list: a value's end).  Returns the values ending in the chunk through fn
+// (lane, end, value-or-difference) 64 bytes at a time.
+template <class Acc>
+__device__ __forceinline__ uint32_t varint_chunk_prevb(const Acc &acc, uint64_t b0, uint64_t c0) {
+    const uint32_t lane = lane_id();
+    if (lane < kWave - 4 || c0 < b0 + (kWave - lane)) return 0u;
+    return acc.byte(c0 - (kWave - lane));
+}
+
+template <class Acc>
+__global__ void varint_seg_info_kernel(Acc acc, const uint32_t *__restrict__ heavy, uint32_t n_heavy, uint64_t split,
+                                       uint32_t chunk, uint64_t *__restrict__ hb0, uint64_t *__restrict__ hb1,
+                                       uint32_t *__restrict__ segcnt) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t h = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; h < n_heavy; h += stride) {
+        uint64_t b0, b1;
+        acc.offsets(heavy[h], b0, b1);
+        hb0[h] = b0;
+        hb1[h] = b1;
+        segcnt[h] = b1 - b0 > split ? (uint32_t)((b1 - b0 + chunk - 1) / chunk) : 0u;
+    }
+}
+
+__global__ void varint_seg_map_kernel(uint32_t n_heavy, const uint64_t *__restrict__ seg_off,
+                                      uint32_t *__restrict__ seg_map) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t h = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; h < n_heavy; h += stride)
+        for (uint64_t k = seg_off[h]; k < seg_off[h + 1]; ++k) seg_map[k] = (uint32_t)h;
+}
+
+// sum of the differences ending in each chunk (DMd), a wave per chunk
+template <class Acc>
+__global__ void varint_seg_sum_kernel(Acc acc, uint64_t n_seg, uint32_t chunk, const uint32_t *__restrict__ seg_map,
+                                      const uint64_t *__restrict__ seg_off, const uint64_t *__restrict__ hb0,
+                                      const uint64_t *__restrict__ hb1, uint32_t *__restrict__ seg_sum) {
+    const uint32_t lane = lane_id();
+    const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) / kWave;
+    for (uint64_t k = wave; k < n_seg; k += nwaves) {
+        const uint32_t h = seg_map[k];
+        const uint64_t b0 = hb0[h], b1 = hb1[h];
+        const uint64_t c0 = b0 + (k - seg_off[h]) * chunk;
+        const uint64_t c1 = c0 + chunk < b1 ? c0 + chunk : b1;
+        uint32_t prevb = varint_chunk_prevb(acc, b0, c0), sum = 0;
+        for (uint64_t p0 = c0; p0 < c1; p0 += kWave) {
+            uint32_t x;
+            const bool end = varint_step(acc, p0, c1, prevb, x);
+            sum += end ? x : 0u;
+        }
+        sum = wave_sum(sum);
+        if (lane == 0) seg_sum[k] = sum;
+    }
+}
+
+__global__ void varint_seg_base_kernel(uint64_t n_seg, const uint32_t *__restrict__ seg_map,
+                                       const uint64_t *__restrict__ seg_off, const uint64_t *__restrict__ scan,
+                                       uint32_t *__restrict__ seg_base) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n_seg; k += stride)
+        seg_base[k] = (uint32_t)(scan[k] - scan[seg_off[seg_map[k]]]);
+}
+
+template <class Acc, bool kParent>
+__global__ void td_varint_seg_kernel(Acc acc, uint32_t n, uint64_t n_seg, uint32_t chunk,
+                                     const uint32_t *__restrict__ seg_map, const uint64_t *__restrict__ seg_off,
+                                     const uint32_t *__restrict__ heavy, const uint64_t *__restrict__ hb0,
+                                     const uint64_t *__restrict__ hb1, const uint32_t *__restrict__ seg_base,
+                                     const uint64_t *__restrict__ frontier, const uint64_t *__restrict__ visited,
+                                     int32_t *__restrict__ depth, uint32_t *__restrict__ parent, int32_t next_depth,
+                                     uint32_t *__restrict__ queue_out, unsigned long long *__restrict__ tail) {
+    const uint32_t lane = lane_id();
+    const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) / kWave;
+    for (uint64_t k = wave; k < n_seg; k += nwaves) {
+        const uint32_t h = seg_map[k];
+        const uint32_t v = heavy[h];
+        if (!((frontier[v >> 6] >> (v & 63)) & 1ull)) continue;  // same for every lane
+        const uint64_t b0 = hb0[h], b1 = hb1[h];
+        const uint64_t c0 = b0 + (k - seg_off[h]) * chunk;
+        const uint64_t c1 = c0 + chunk < b1 ? c0 + chunk : b1;
+        uint32_t prevb = varint_chunk_prevb(acc, b0, c0), carry = seg_base[k];
+        for (uint64_t p0 = c0; p0 < c1; p0 += kWave) {
+            uint32_t x;
+            const bool end = varint_step(acc, p0, c1, prevb, x);
+            uint32_t label = x;
+            if constexpr (Acc::kDifferences) {
+                const uint32_t sc = wave_incl_scan(end ? x : 0u);
+                label = carry + sc;
+                carry += __shfl(sc, kWave - 1, kWave);
+            }
             const uint32_t u = label < n ? label : n - 1;
             bool won = false;
             if (end && !((visited[u >> 6] >> (u & 63)) & 1ull)) {
@@ -1290,12 +1401,33 @@ static lg_status bfs_one_inorder(lg_graph *g, BfsWork &w, Acc acc, uint32_t root
                     LG_LAUNCH((td_gap_kernel<Acc, false>), grid, 256, 0, s, acc, n, split, qin, qsize, visited, depth,
                               parent, level + 1, qout, ctr);
             } else {
+                // lists above vseg_split bytes go by chunks, the rest a wave
+                // per list
+                const uint64_t split = g->n_vseg ? g->vseg_split : ~0ull;
+                if (g->n_vseg) {
+                    LG_TRY(fill_u64(curr, 0, words, s));
+                    LG_LAUNCH(mark_queue_kernel, grid_for(qsize, 256, 1u << 16), 256, 0, s, qin, qsize,
+                              (unsigned long long *)curr, ctr);
+                    LG_CHECK_LAUNCH();
+                    const uint32_t sgrid = grid_for(g->n_vseg * kWave, 256, kStrideBlocks);
+                    if (parent)
+                        LG_LAUNCH((td_varint_seg_kernel<Acc, true>), sgrid, 256, 0, s, acc, n, g->n_vseg,
+                                  g->vseg_bytes, g->vseg_map.as<uint32_t>(), g->vseg_off.as<uint64_t>(),
+                                  g->heavy.as<uint32_t>(), g->vhb0.as<uint64_t>(), g->vhb1.as<uint64_t>(),
+                                  g->vseg_base.as<uint32_t>(), curr, visited, depth, parent, level + 1, qout, ctr);
+                    else
+                        LG_LAUNCH((td_varint_seg_kernel<Acc, false>), sgrid, 256, 0, s, acc, n, g->n_vseg,
+                                  g->vseg_bytes, g->vseg_map.as<uint32_t>(), g->vseg_off.as<uint64_t>(),
+                                  g->heavy.as<uint32_t>(), g->vhb0.as<uint64_t>(), g->vhb1.as<uint64_t>(),
+                                  g->vseg_base.as<uint32_t>(), curr, visited, depth, parent, level + 1, qout, ctr);
+                    LG_CHECK_LAUNCH();
+                }
                 if (parent)
-                    LG_LAUNCH((td_varint_kernel<Acc, true>), grid, 256, 0, s, acc, n, qin, qsize, visited, depth,
-                              parent, level + 1, qout, ctr);
+                    LG_LAUNCH((td_varint_kernel<Acc, true>), grid, 256, 0, s, acc, n, split, qin, qsize, visited,
+                              depth, parent, level + 1, qout, ctr);
                 else
-                    LG_LAUNCH((td_varint_kernel<Acc, false>), grid, 256, 0, s, acc, n, qin, qsize, visited, depth,
-                              parent, level + 1, qout, ctr);
+                    LG_LAUNCH((td_varint_kernel<Acc, false>), grid, 256, 0, s, acc, n, split, qin, qsize, visited,
+                              depth, parent, level + 1, qout, ctr);
             }
             LG_CHECK_LAUNCH();
             LG_CHECK_HIP(hipMemcpyAsync(w.host, ctr, 8, hipMemcpyDeviceToHost, s));
@@ -1385,6 +1517,59 @@ static lg_status bfs_one_inorder(lg_graph *g, BfsWork &w, Acc acc, uint32_t root
         }
     }
     return LG_OK;
+}
+
+// Chunk tables of the long Varint lists (see lg_graph), built once with the
+// encoding: per heavy vertex its byte range and chunk count, a scan, the
+// chunk map, and for differences the label before every chunk (a wave sum
+// per chunk, a scan, a per-list subtraction).
+lg_status build_varint_segments(lg_graph *g, hipStream_t s) {
+    const uint32_t nh = g->n_heavy;
+    g->n_vseg = 0;
+    LG_TRY(g->vhb0.scratch((uint64_t)(nh ? nh : 1) * 8, s));
+    LG_TRY(g->vhb1.scratch((uint64_t)(nh ? nh : 1) * 8, s));
+    LG_TRY(g->vseg_off.scratch(((uint64_t)nh + 1) * 8, s));
+    DevBuf tmp;
+    if (!nh) return fill_u64(g->vseg_off.as<uint64_t>(), 0, 1, s);
+    return dispatch_acc_dec(g, [&](auto acc) -> lg_status {
+        using Acc = decltype(acc);
+        if constexpr (IsVarintAcc<Acc>::value) {
+            DevBuf segcnt;
+            LG_TRY(segcnt.scratch((uint64_t)nh * 4, s));
+            LG_LAUNCH(varint_seg_info_kernel<Acc>, grid_for(nh, 256, 1u << 16), 256, 0, s, acc,
+                      g->heavy.as<uint32_t>(), nh, (uint64_t)g->vseg_split, g->vseg_bytes, g->vhb0.as<uint64_t>(),
+                      g->vhb1.as<uint64_t>(), segcnt.as<uint32_t>());
+            LG_CHECK_LAUNCH();
+            LG_TRY(exclusive_scan_u32(segcnt.as<uint32_t>(), g->vseg_off.as<uint64_t>(), nh, tmp, s));
+            LG_CHECK_HIP(hipMemcpyAsync(&g->n_vseg, g->vseg_off.as<uint64_t>() + nh, 8, hipMemcpyDeviceToHost, s));
+            LG_CHECK_HIP(hipStreamSynchronize(s));
+            LG_TRY(g->vseg_map.scratch((g->n_vseg ? g->n_vseg : 1) * 4, s));
+            LG_TRY(g->vseg_base.scratch((g->n_vseg ? g->n_vseg : 1) * 4, s));
+            if (!g->n_vseg) return LG_OK;
+            LG_LAUNCH(varint_seg_map_kernel, grid_for(nh, 256, 1u << 16), 256, 0, s, nh,
+                      g->vseg_off.as<uint64_t>(), g->vseg_map.as<uint32_t>());
+            LG_CHECK_LAUNCH();
+            if constexpr (Acc::kDifferences) {
+                DevBuf ssum, sscan;
+                LG_TRY(ssum.scratch(g->n_vseg * 4, s));
+                LG_TRY(sscan.scratch((g->n_vseg + 1) * 8, s));
+                LG_LAUNCH(varint_seg_sum_kernel<Acc>, grid_for(g->n_vseg * kWave, 256, 1u << 16), 256, 0, s, acc,
+                          g->n_vseg, g->vseg_bytes, g->vseg_map.as<uint32_t>(), g->vseg_off.as<uint64_t>(),
+                          g->vhb0.as<uint64_t>(), g->vhb1.as<uint64_t>(), ssum.as<uint32_t>());
+                LG_CHECK_LAUNCH();
+                LG_TRY(exclusive_scan_u32(ssum.as<uint32_t>(), sscan.as<uint64_t>(), g->n_vseg, tmp, s));
+                LG_LAUNCH(varint_seg_base_kernel, grid_for(g->n_vseg, 256, 1u << 16), 256, 0, s, g->n_vseg,
+                          g->vseg_map.as<uint32_t>(), g->vseg_off.as<uint64_t>(), sscan.as<uint64_t>(),
+                          g->vseg_base.as<uint32_t>());
+                LG_CHECK_LAUNCH();
+            } else {
+                LG_TRY(fill_u32(g->vseg_base.as<uint32_t>(), 0, g->n_vseg, s));
+            }
+            LG_CHECK_HIP(hipStreamSynchronize(s));
+            return LG_OK;
+        }
+        return LG_ERR_UNSUPPORTED;
+    });
 }
 
 lg_status bfs_run(lg_graph *g, BfsWork &w, const uint32_t *roots, uint32_t r, int32_t *depth, int32_t *parent,

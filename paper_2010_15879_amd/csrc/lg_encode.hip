@@ -1360,10 +1360,13 @@ static lg_status encode_entry(uint32_t n, uint64_t m, const uint64_t *row_offset
     g->offset_mode = o.layout == LG_LAYOUT_PACKED ? o.offset_mode : 0;
     g->relabel = o.relabel;
     lg_status st = encode_impl(n, m, row_offsets, col, weights, o, stream, g);
-    // gap lists: the per-segment starting values of the long lists serve the
+    // gap and Varint lists: the segment tables of the long lists serve the
     // traversals too (several BFS lanes may run at once), so build them here
     if (st == LG_OK && g->layout == LG_LAYOUT_PACKED && g->id_mode == LG_IDS_LOCAL_GAP)
         st = ensure_heavy_segments(g, stream);
+    if (st == LG_OK && g->layout == LG_LAYOUT_PACKED &&
+        (g->id_mode == LG_IDS_VARINT_FULL || g->id_mode == LG_IDS_VARINT_DIFF))
+        st = build_varint_segments(g, stream);
     if (st != LG_OK) {
         (void)hipStreamSynchronize(stream);
         lg_free(g);

@@ -188,6 +188,14 @@ struct lg_graph {
     uint32_t pr_unit_edges = 8192;  // edge budget of a unit (plus at most one list of <= pr_split)
     uint64_t heavy_edges = 0, heavy_bits = 0;  // entries and bits (packed) of the heavy lists
     bool segs_built = false;
+    // Varint lists longer than vseg_split bytes, in byte chunks of vseg_bytes
+    // (built with the encoding): heavy vertex h's byte range [vhb0, vhb1),
+    // its chunks vseg_off[h] .. vseg_off[h+1] (vseg_map[k] = h); a value
+    // belongs to the chunk holding its last byte, and vseg_base[k] is the
+    // label before chunk k (differences) or 0 (full labels)
+    lg::DevBuf vhb0, vhb1, vseg_off, vseg_map, vseg_base;
+    uint64_t n_vseg = 0;
+    uint32_t vseg_bytes = 4096, vseg_split = 8192;
 
     // lazily allocated workspaces of the plain calls (lg_bfs, lg_pagerank,
     // lg_decode_neighbors); the server brings its own per worker
@@ -269,6 +277,7 @@ inline uint32_t bitlen_u64(uint64_t x) { return x ? 64u - (uint32_t)__builtin_cl
 
 // Build the PageRank work tables of g (once); defined in lg_heavy.hip.
 lg_status ensure_heavy_segments(lg_graph *g, hipStream_t s);
+lg_status build_varint_segments(lg_graph *g, hipStream_t s);
 
 lg_status bfs_free(lg_graph *g);
 void bfs_pools_trim();
