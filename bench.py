@@ -582,7 +582,7 @@ def encoding_main(args, np, torch, lg, g, roots):
                                                   C.c_void_p(ids_buf.data_ptr()), total, 2, s)
                 assert st == 0, lg.lib().lg_last_error()
             dec_ms = _time_ms(torch, lists, reps=5)
-            pr_ms = _time_ms(torch, lambda: lg.pagerank(h, 0.85, 20)) if ids.startswith("local") else None
+            pr_ms = _time_ms(torch, lambda: lg.pagerank(h, 0.85, 20))
             bfs_ms = _time_ms(torch, lambda: lg.bfs(h, roots))
             res[name] = {"adj_bytes": info["adj_bits"] / 8.0, "widths_bytes": info["bytes_widths"],
                          "offsets_bytes": info["bytes_offsets"], "encode_ms": round(enc_ms, 3),

@@ -75,8 +75,8 @@ typedef enum lg_status {
  * label (with LG_RELABEL_DEGREE: the paper's DMf), DIFF the first label and
  * then the differences of consecutive labels (with LG_RELABEL_DEGREE: DMd).
  * d_v is the number of bytes with the top bit clear in the list.  Such
- * graphs are read in order by lg_decode_neighbors, lg_bfs and servers;
- * lg_pagerank and batch plans return LG_ERR_UNSUPPORTED for them. */
+ * graphs are read in order by lg_decode_neighbors, lg_bfs, lg_pagerank and
+ * servers; batch plans return LG_ERR_UNSUPPORTED for them. */
 #define LG_IDS_VARINT_FULL 3u
 #define LG_IDS_VARINT_DIFF 4u
 /* lg_encode_opts.offset_mode -- sections "Logarithmization of Single Offsets"

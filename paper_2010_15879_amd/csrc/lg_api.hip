@@ -252,7 +252,8 @@ uint64_t lg_graph::device_bytes() const {
     uint64_t b = A.bytes + O.bytes + W.bytes + G.bytes + L.bytes + H.bytes + rank_sb.bytes + sel.bytes + poff.bytes +
                  pcol.bytes + pwt.bytes + perm.bytes + inv.bytes + heavy.bytes + iso.bytes + hstart.bytes + hdeg.bytes + hw.bytes +
                  hg.bytes + seg_off.bytes + seg_map.bytes + seg_part.bytes + seg_base.bytes + units.bytes +
-                 vhb0.bytes + vhb1.bytes + vseg_off.bytes + vseg_map.bytes + vseg_base.bytes + (dec ? dec->bytes() : 0);
+                 vhb0.bytes + vhb1.bytes + vseg_off.bytes + vseg_map.bytes + vseg_base.bytes + vdeg.bytes +
+                 vca.bytes + vcb.bytes + vpart.bytes + (dec ? dec->bytes() : 0);
     return b;
 }
 

@@ -27,6 +27,7 @@
 #include <vector>
 
 #include "lg_device.hpp"
+#include "lg_varint.hpp"
 
 namespace lg {
 
@@ -801,34 +802,6 @@ __global__ void varint_frontier_bytes_kernel(Acc acc, const uint32_t *__restrict
     if (threadIdx.x == 0 && e) atomicAdd(out, e);
 }
 
-// One step of 64 bytes [p0, p0 + 64) of a list ending at b1: whether this
-// lane holds a value's last byte, and the value (a label, or for DMd a
-// difference to be summed by the caller).  prevb is this lane's byte of the
-// previous step (0 before the list: a value's end).
-template <class Acc>
-__device__ __forceinline__ bool varint_step(const Acc &acc, uint64_t p0, uint64_t b1, uint32_t &prevb,
-                                            uint32_t &val) {
-    const uint32_t lane = lane_id();
-    const uint64_t p = p0 + lane;
-    const bool in = p < b1;
-    const uint32_t b = in ? acc.byte(p) : 128u;
-    const bool end = in && !(b & 128u);
-    uint32_t v = b & 127u;
-    bool open = true;
-#pragma unroll
-    for (int t = 1; t <= 4; ++t) {
-        const int src = (int)lane - t;
-        const uint32_t cur = __shfl(b, src & (kWave - 1), kWave);
-        const uint32_t old = __shfl(prevb, src & (kWave - 1), kWave);
-        const uint32_t bt = src >= 0 ? cur : old;
-        open = open && (bt & 128u);
-        if (open) v = (v << 7) | (bt & 127u);
-    }
-    prevb = b;
-    val = v;
-    return end;
-}
-
 template <class Acc, bool kParent>
 __global__ void td_varint_kernel(Acc acc, uint32_t n, uint64_t split, const uint32_t *__restrict__ queue, uint64_t qsize,
                                  const uint64_t *__restrict__ visited, int32_t *__restrict__ depth,
@@ -869,17 +842,6 @@ __global__ void td_varint_kernel(Acc acc, uint32_t n, uint64_t split, const uint
             }
         }
     }
-}
-
-// Chunk k of a long Varint list: bytes [c0, c1) of the list [b0, b1); the
-// look-back of the first lanes reads the four bytes before c0 (0 before the
-// list: a value's end).  Returns the values ending in the chunk through fn
-// (lane, end, value-or-difference) 64 bytes at a time.
-template <class Acc>
-__device__ __forceinline__ uint32_t varint_chunk_prevb(const Acc &acc, uint64_t b0, uint64_t c0) {
-    const uint32_t lane = lane_id();
-    if (lane < kWave - 4 || c0 < b0 + (kWave - lane)) return 0u;
-    return acc.byte(c0 - (kWave - lane));
 }
 
 template <class Acc>

@@ -195,6 +195,9 @@ struct lg_graph {
     // label before chunk k (differences) or 0 (full labels)
     lg::DevBuf vhb0, vhb1, vseg_off, vseg_map, vseg_base;
     uint64_t n_vseg = 0;
+    // PageRank over Varint lists (built at its first call): d_v per vertex,
+    // the contribution ping-pong and one partial sum per chunk
+    lg::DevBuf vdeg, vca, vcb, vpart;
     uint32_t vseg_bytes = 4096, vseg_split = 8192;
 
     // lazily allocated workspaces of the plain calls (lg_bfs, lg_pagerank,
@@ -278,6 +281,7 @@ inline uint32_t bitlen_u64(uint64_t x) { return x ? 64u - (uint32_t)__builtin_cl
 // Build the PageRank work tables of g (once); defined in lg_heavy.hip.
 lg_status ensure_heavy_segments(lg_graph *g, hipStream_t s);
 lg_status build_varint_segments(lg_graph *g, hipStream_t s);
+lg_status pagerank_varint(lg_graph *g, float damping, uint32_t iters, float *scores, hipStream_t s);
 
 lg_status bfs_free(lg_graph *g);
 void bfs_pools_trim();

@@ -377,6 +377,8 @@ extern "C" lg_status lg_pagerank(const lg_graph *gc, float damping, uint32_t ite
         LG_CHECK_LAUNCH();
         return LG_OK;
     }
+    if (g->layout == LG_LAYOUT_PACKED && (g->id_mode == LG_IDS_VARINT_FULL || g->id_mode == LG_IDS_VARINT_DIFF))
+        return pagerank_varint(g, damping, iters, scores, stream);
     if (!g->pr) {
         g->pr = new (std::nothrow) PrWork();
         if (!g->pr) { set_error("lg_pagerank: host allocation failed"); return LG_ERR_OOM; }

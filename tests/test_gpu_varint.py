@@ -1,8 +1,8 @@
 """Varint lists on the GPU (subsection "Incorporating Degree-Minimizing
 (DM)": DMf = full labels, DMd = first label and differences, each a
 base-128 Varint): every array bit-exact against the oracle, lists decoded
-against the input, BFS over them against the oracle, and PageRank and
-batch plans refusing such graphs."""
+against the input, BFS and PageRank over them against the oracle, and batch
+plans refusing such graphs."""
 
 import numpy as np
 import pytest
@@ -10,7 +10,7 @@ import torch
 
 import oracle as orc
 from paper_2010_15879_amd import graphgen as gg
-from test_gpu_parity import GRAPHS
+from test_gpu_parity import GRAPHS, PR_L1
 
 pytestmark = pytest.mark.gpu
 
@@ -153,14 +153,26 @@ def test_varint_bfs_four_byte_labels(lgmod):
         h.free()
 
 
-def test_varint_unsupported(lgmod):
+@pytest.mark.parametrize("e", VARINT, ids=vid)
+@pytest.mark.parametrize("name", list(GRAPHS))
+def test_varint_pagerank(lgmod, name, e):
+    """PageRank over Varint lists: within the FP32 bound of the FP64 oracle,
+    and bit-identical from one call to the next."""
+    g = GRAPHS[name]
+    off, col = g.numpy()
+    print(f"[varint pagerank] {name} {vid(e)}", flush=True)
+    h = encode(lgmod, g, e)
+    for iters in [0, 1, 20]:
+        pr = lgmod.pagerank(h, 0.85, iters).cpu().numpy()
+        l1 = np.abs(pr.astype(np.float64) - orc.pagerank(off, col, 0.85, iters)).sum()
+        assert l1 <= PR_L1, (iters, l1)
+    np.testing.assert_array_equal(pr, lgmod.pagerank(h, 0.85, 20).cpu().numpy())
+    h.free()
+
+
+def test_varint_batch_unsupported(lgmod):
     from paper_2010_15879_amd.lg import LGError, LG_ERR_UNSUPPORTED
     g = GRAPHS["kron12"]
-    h = encode(lgmod, g, VARINT[-1])
-    with pytest.raises(LGError) as ei:
-        lgmod.pagerank(h, 0.85, 2)
-    assert ei.value.status == LG_ERR_UNSUPPORTED
-    h.free()
     h = encode(lgmod, g, VARINT[-2])
     with pytest.raises(LGError) as ei:
         lgmod.BatchPlan([h], [(0, 1)])
@@ -189,3 +201,19 @@ def test_varint_kronecker16(lgmod):
             np.testing.assert_array_equal(parent[i].cpu().numpy(), p0)
         h.free()
     assert sizes["varint-diff"] <= sizes["varint-full"]
+
+
+def test_varint_pagerank_chunked_hub(lgmod):
+    """A hub whose list spans many 4 KiB chunks with values of one to four
+    bytes: the chunk partial sums against the oracle."""
+    n = (1 << 21) + 300
+    rng = np.random.default_rng(8)
+    far = np.unique(rng.integers(1 << 21, n, size=3000))
+    edges = [(0, int(x)) for x in np.concatenate([np.arange(1, 6000), far])] + [(5, int(x)) for x in far[:40]]
+    g = gg.csr_from_edges(n, edges)
+    off, col = g.numpy()
+    for ids in ("varint-full", "varint-diff"):
+        h = encode(lgmod, g, dict(layout="packed", ids=ids, offsets="succinct", relabel=False))
+        pr = lgmod.pagerank(h, 0.85, 10).cpu().numpy().astype(np.float64)
+        assert np.abs(pr - orc.pagerank(off, col, 0.85, 10)).sum() <= PR_L1
+        h.free()
