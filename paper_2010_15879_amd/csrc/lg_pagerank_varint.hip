@@ -4,7 +4,9 @@
 //
 //   d_v: counted once per graph (the bytes with the top bit clear in each
 //        list, a wave per vertex)
-//   a list of at most vseg_split bytes: a wave per vertex, 64 bytes per step,
+//   a list of at most 64 values (not a heavy vertex): a lane per vertex,
+//        reading it from 8-byte windows
+//   a heavy list of at most vseg_split bytes: a wave each, 64 bytes per step,
 //        a lane holding a value's last byte gathers that neighbor's
 //        contribution (DMd: the label is a wave prefix sum of differences)
 //   a longer list: a wave per 4 KiB chunk of the graph's chunk tables (the
@@ -71,23 +73,74 @@ __device__ __forceinline__ float vpr_range_sum(const Acc &acc, uint32_t n, const
     return wave_sum(sum);
 }
 
+// Lists of at most lane_max values (the heavy-vertex threshold: at most five
+// bytes each), a lane per vertex over 64-vertex words (offsets decoded by the
+// whole wave): each lane reads its list from 8-byte windows (two aligned
+// words and a funnel shift; the pad word keeps the second in bounds) and
+// sums the contributions in list order.
+
 template <class Acc>
-__global__ void vpr_list_kernel(Acc acc, uint32_t n, uint64_t split, const uint32_t *__restrict__ deg,
+__global__ void vpr_lane_kernel(Acc acc, uint32_t n, uint32_t lane_max, const uint32_t *__restrict__ deg,
+                                const float *__restrict__ cin,
+                                float *__restrict__ cout, float base, float alpha, float *__restrict__ scores,
+                                const uint32_t *__restrict__ perm) {
+    const uint32_t lane = lane_id();
+    const uint64_t words = ((uint64_t)n + 63) / 64;
+    const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) / kWave;
+    for (uint64_t q = wave; q < words; q += nwaves) {
+        uint64_t b0, b1;
+        wave_offsets(acc.base, q * 64, n, b0, b1);
+        const uint64_t v = q * 64 + lane;
+        if (v >= n || deg[v] > lane_max) continue;
+        if (b1 == b0 && !scores) continue;  // no edges: contribution stays 0
+        float sum = 0.0f;
+        uint32_t label = 0, accv = 0, shift = 0, count = 0;
+        for (uint64_t pos = b0; pos < b1;) {
+            const uint64_t k = pos >> 3;
+            const uint32_t sh = (uint32_t)(pos & 7) * 8;
+            const uint64_t w0 = acc.word(k * 8), w1 = acc.word(k * 8 + 8);
+            const uint64_t win = sh ? (w0 >> sh) | (w1 << (64 - sh)) : w0;
+            const uint32_t avail = b1 - pos < 8 ? (uint32_t)(b1 - pos) : 8u;
+            for (uint32_t j = 0; j < avail; ++j) {
+                const uint32_t b = (uint32_t)(win >> (8 * j)) & 255u;
+                accv |= (b & 127u) << shift;
+                shift += 7;
+                if (!(b & 128u)) {
+                    label = Acc::kDifferences && count ? label + accv : accv;
+                    ++count;
+                    accv = 0;
+                    shift = 0;
+                    sum += cin[label < n ? label : n - 1];
+                }
+            }
+            pos += avail;
+        }
+        const float pr = base + alpha * sum;
+        const uint32_t d = deg[v];
+        cout[v] = d ? pr / (float)d : 0.0f;
+        if (scores) scores[perm ? perm[v] : v] = pr;
+    }
+}
+
+// The heavy lists that are not chunked, a wave each, from their stored
+// byte ranges
+template <class Acc>
+__global__ void vpr_list_kernel(Acc acc, uint32_t n, uint32_t n_heavy, const uint32_t *__restrict__ heavy,
+                                const uint64_t *__restrict__ hb0, const uint64_t *__restrict__ hb1,
+                                const uint64_t *__restrict__ seg_off, const uint32_t *__restrict__ deg,
                                 const float *__restrict__ cin, float *__restrict__ cout, float base, float alpha,
                                 float *__restrict__ scores, const uint32_t *__restrict__ perm) {
     const uint32_t lane = lane_id();
     const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
     const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) / kWave;
-    for (uint64_t v = wave; v < n; v += nwaves) {
-        uint64_t b0, b1;
-        acc.offsets((uint32_t)v, b0, b1);
-        if (b1 - b0 > split) continue;  // chunked: vpr_chunk_kernel
-        if (b1 == b0 && !scores) continue;  // no edges: contribution stays 0
-        const float sum = vpr_range_sum(acc, n, cin, b0, b1, 0u, 0u);
+    for (uint64_t h = wave; h < n_heavy; h += nwaves) {
+        if (seg_off[h + 1] > seg_off[h]) continue;  // chunked: vpr_chunk_kernel
+        const uint32_t v = heavy[h];
+        const float sum = vpr_range_sum(acc, n, cin, hb0[h], hb1[h], 0u, 0u);
         if (lane == 0) {
             const float pr = base + alpha * sum;
-            const uint32_t d = deg[v];
-            cout[v] = d ? pr / (float)d : 0.0f;
+            cout[v] = pr / (float)deg[v];
             if (scores) scores[perm ? perm[v] : v] = pr;
         }
     }
@@ -151,7 +204,6 @@ lg_status pagerank_varint(lg_graph *g, float damping, uint32_t iters, float *sco
             LG_LAUNCH(vpr_init_kernel, grid_for(n, 256, 1u << 16), 256, 0, s, n, g->vdeg.as<uint32_t>(), 1.0 / nd,
                       cin, cout);
             LG_CHECK_LAUNCH();
-            const uint64_t split = g->n_vseg ? g->vseg_split : ~0ull;
             double D = z / nd;
             for (uint32_t t = 0; t < iters; ++t) {
                 const double b = (1.0 - a) / nd + a * D / nd;
@@ -165,9 +217,17 @@ lg_status pagerank_varint(lg_graph *g, float damping, uint32_t iters, float *sco
                               (const float *)cin, g->vpart.as<float>());
                     LG_CHECK_LAUNCH();
                 }
-                LG_LAUNCH(vpr_list_kernel<Acc>, vgrid, 256, 0, s, acc, n, split, g->vdeg.as<uint32_t>(),
-                          (const float *)cin, cout, (float)b, (float)a, sc, pm);
+                LG_LAUNCH(vpr_lane_kernel<Acc>, grid_for(((uint64_t)n + 63) / 64 * kWave, 256, 1u << 16), 256, 0,
+                          s, acc, n, g->heavy_threshold, g->vdeg.as<uint32_t>(), (const float *)cin, cout, (float)b,
+                          (float)a, sc, pm);
                 LG_CHECK_LAUNCH();
+                if (g->n_heavy) {
+                    LG_LAUNCH(vpr_list_kernel<Acc>, grid_for((uint64_t)g->n_heavy * kWave, 256, 1u << 16), 256, 0, s,
+                              acc, n, g->n_heavy, g->heavy.as<uint32_t>(), g->vhb0.as<uint64_t>(),
+                              g->vhb1.as<uint64_t>(), g->vseg_off.as<uint64_t>(), g->vdeg.as<uint32_t>(),
+                              (const float *)cin, cout, (float)b, (float)a, sc, pm);
+                    LG_CHECK_LAUNCH();
+                }
                 if (g->n_vseg) {
                     LG_LAUNCH(vpr_heavy_kernel, grid_for(g->n_heavy, 256, 4096), 256, 0, s, g->n_heavy,
                               g->heavy.as<uint32_t>(), g->vseg_off.as<uint64_t>(), g->vdeg.as<uint32_t>(),

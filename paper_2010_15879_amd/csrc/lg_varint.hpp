@@ -45,4 +45,36 @@ __device__ __forceinline__ uint32_t varint_chunk_prevb(const Acc &acc, uint64_t 
     return acc.byte(c0 - (kWave - lane));
 }
 
+// The two offset values bracketing the list of v0 + lane, decoded by the
+// whole wave for a 64-aligned v0 (with Elias-Fano offsets one select per
+// wave instead of one per lane); every lane of the wave must call it.
+// Base: the local-ID packed accessor under a gap or Varint accessor.
+template <class Base>
+__device__ __forceinline__ void wave_offsets(const Base &acc, uint64_t v0, uint32_t n, uint64_t &o0, uint64_t &o1) {
+    const uint32_t lane = lane_id();
+    const uint64_t v = v0 + lane;
+    const uint64_t vv = v < n ? v : n;
+    const uint64_t ve = v0 + kWave < n ? v0 + kWave : n;
+    uint64_t end;
+    if constexpr (Base::kEF) {
+        const EFView &e = acc.pv.ef;
+        const uint64_t lo0 = e.l ? extract64(e.L, vv * e.l, e.l) : 0ull;
+        const uint64_t lo_end = (e.l && v0 + kWave <= n) ? extract64(e.L, ve * e.l, e.l) : 0ull;
+        uint64_t pos, pos_end;
+        ef_wave_select(e, v0, n + 1, ef_samples(e, v0, n + 1), pos, pos_end);
+        if (v > n) pos = 0;
+        o0 = v <= n ? (((pos - vv) << e.l) | lo0) : 0ull;
+        if (v0 + kWave <= n) end = ((pos_end - ve) << e.l) | lo_end;
+        else end = __shfl(o0, (uint32_t)(n - v0), kWave);
+    } else {
+        o0 = acc.offset_value((uint32_t)vv);
+        end = acc.offset_value((uint32_t)ve);
+    }
+    o1 = __shfl_down(o0, 1, kWave);
+    if (lane == kWave - 1) o1 = end;
+}
+
+// The sampled direction estimate of the in-order traversals: degrees (gap)
+// or list bytes (Varint) of kDirSample frontier vertices at evenly spaced
+// queue positions, a partial sum per block.
 }  // namespace lg
