@@ -58,7 +58,7 @@ def measured_traffic(kernel: str, workload: str):
     vals = dict(line.split(": ", 1) for line in text.splitlines()
                 if line.startswith(("traffic_bytes_per_launch: ", "source_sha256: ")))
     h = hashlib.sha256()
-    for f in ["lg_pagerank.hip", "lg_device.hpp", "lg_views.hpp", "lg_heavy.hip"]:
+    for f in ["lg_pagerank.hip", "lg_device.hpp", "lg_views.hpp", "lg_heavy.hip", "lg_varint.hpp"]:
         with open(os.path.join(ROOT, "paper_2010_15879_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     if vals.get("source_sha256", "").strip() != h.hexdigest():

@@ -30,6 +30,7 @@
 #include <algorithm>
 
 #include "lg_device.hpp"
+#include "lg_varint.hpp"
 
 namespace lg {
 
@@ -270,7 +271,19 @@ __global__ __launch_bounds__(kPrThreads) void pr_iter_gap_kernel(
         const bool mine = v >= vb && v < ve;
         const bool all_iso = iso[w0 / kWave] == ~0ull;
         if (all_iso && !scores) continue;
-        const GapInfo gi = (all_iso || v >= n) ? GapInfo{0, 0, 0, 0} : acc.info((uint32_t)v);
+        // the block's 65 offsets decoded by the whole wave (one select with
+        // Elias-Fano offsets, not one per lane)
+        GapInfo gi{0, 0, 0, 0};
+        if (!all_iso) {  // same for every lane
+            uint64_t o0, o1;
+            wave_offsets(acc.base, w0, n, o0, o1);
+            if (v < n && o1 > o0) {
+                gi.start = o0;
+                gi.w = acc.base.width((uint32_t)v);
+                gi.g = acc.gap_width((uint32_t)v);
+                gi.deg = gi.g == 0 ? 1u : 1u + exact_div_width(o1 - o0 - gi.w, gi.g);
+            }
+        }
         const bool segmented = gi.deg > split;
         const uint32_t d = (mine && !segmented) ? gi.deg : 0u;
         const uint32_t incl = wave_incl_scan(d);

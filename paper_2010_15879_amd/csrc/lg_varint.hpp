@@ -1,6 +1,7 @@
-// Wave-level reading of Varint lists (subsection "Incorporating
-// Degree-Minimizing (DM)"): base-128 values, lowest group first, the top bit
-// set on every byte of a value but its last.
+// Wave-level helpers of the in-order list readers: Varint steps (subsection
+// "Incorporating Degree-Minimizing (DM)": base-128 values, lowest group
+// first, the top bit set on every byte of a value but its last) and the
+// wave-cooperative offset decode shared with the gap-list kernels.
 #pragma once
 
 #include "lg_device.hpp"
