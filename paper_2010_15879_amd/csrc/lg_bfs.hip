@@ -18,6 +18,10 @@
 //   neighbor in the frontier bitmap, which is its smallest-label parent
 // The switch between the two follows the edge-count heuristic of
 // direction-optimizing BFS; it changes the running time only.
+// Gap and Varint lists, whose entries can only be read in order, take the
+// same level loop with in-order kernels (bfs_one_inorder): a wave per
+// frontier list or per segment of a long list top-down, a lane per list
+// with a wave pass for long lists bottom-up.
 #include <algorithm>
 #include <atomic>
 #include <map>

@@ -492,12 +492,12 @@ lg_status dispatch_acc(const lg_graph *g, Fn &&fn) {
     }
     if (g->id_mode == LG_IDS_LOCAL_GAP) {
         set_error("gap-encoded lists are read in order only: this operation is not available for them "
-                  "(lg_decode_neighbors and lg_pagerank are)");
+                  "(lg_decode_neighbors, lg_bfs and lg_pagerank are)");
         return LG_ERR_UNSUPPORTED;
     }
     if (g->id_mode == LG_IDS_VARINT_FULL || g->id_mode == LG_IDS_VARINT_DIFF) {
         set_error("Varint lists are read in order only: this operation is not available for them "
-                  "(lg_decode_neighbors is)");
+                  "(lg_decode_neighbors, lg_bfs and lg_pagerank are)");
         return LG_ERR_UNSUPPORTED;
     }
     const PackedView pv = g->packed_view();
