@@ -220,7 +220,7 @@ lg_status lg_encode_weighted(uint32_t n, uint64_t m, const uint64_t *row_offsets
  *
  *   root     original vertex ID, < n
  *   delta    bucket width (distances [k delta, (k+1) delta) settle together);
- *            0 picks a default.  The distances do not depend on it.
+ *            0 picks 2^weight_bits.  The distances do not depend on it.
  *   dist     dev, uint64[n]; UINT64_MAX for vertices the root does not reach
  *
  * Returns LG_ERR_UNSUPPORTED for an unweighted graph.  Synchronous: the

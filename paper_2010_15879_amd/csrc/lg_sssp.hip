@@ -100,7 +100,6 @@ lg_status dispatch_wacc(const lg_graph *g, Fn &&fn) {
 }
 
 constexpr uint64_t kInfDist = ~0ull;
-constexpr uint32_t kSsspDefaultDelta = 256;
 
 struct SsspWork {
     DevBuf upd;                         // bitmap, one bit per vertex
@@ -290,7 +289,10 @@ extern "C" lg_status lg_sssp(const lg_graph *gc, uint32_t root, uint32_t delta, 
         set_error("lg_sssp: the graph has no edge weights (build it with lg_encode_weighted)");
         return LG_ERR_UNSUPPORTED;
     }
-    const uint64_t D = delta ? delta : kSsspDefaultDelta;
+    // default bucket width: the weight range 2^omega (one edge of the
+    // heaviest weight spans about one bucket; 256 for 8-bit weights, the
+    // best of a sweep on weights in [1, 255])
+    const uint64_t D = delta ? delta : (1ull << g->omega);
     const uint32_t n = g->n;
     const uint64_t words = ((uint64_t)n + 63) / 64;
     if (!g->sssp) {
