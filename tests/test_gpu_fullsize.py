@@ -159,3 +159,49 @@ def test_kronecker24_greedy_relabel(lgmod):
     rows = np.concatenate([np.arange(8), rng.integers(0, n, size=64)])
     check_sampled_rows(A, P, W, F, 0, rows, lambda x: orc.relabel_row(off, col, perm, inv, int(x)))
     h.free()
+
+
+def test_kronecker24_gap_and_dmd(lgmod):
+    """Fixed-size gap lists and Varint differences (DMd), both after the
+    degree relabeling, at the benchmark's size: one whole BFS tree, the first
+    PageRank iteration, and sampled decoded lists against the oracle."""
+    print("[fullsize] kronecker s24 gap/DMd: generate", flush=True)
+    g = gg.kronecker(24, 16, seed=1, device="cuda")
+    off, col = host_csr(g)
+    root = gg.pick_roots(g, 1, seed=2)[0]
+    print("[fullsize] kronecker s24 gap/DMd: oracle BFS and PageRank", flush=True)
+    d0, p0 = orc.bfs(off, col, root, relabeled=True)
+    pr64 = orc.pagerank(off, col, 0.85, 1)
+    rng = np.random.default_rng(12)
+    vs = rng.integers(0, g.n, 300).astype(np.int32)
+    for ids in ("local-gap", "varint-diff"):
+        print(f"[fullsize] kronecker s24 {ids}: encode, BFS, PageRank, decode", flush=True)
+        h = lgmod.encode(g.row_offsets, g.col, g.n, ids=ids, offsets="succinct", relabel=True)
+        depth, parent = lgmod.bfs(h, [root])
+        np.testing.assert_array_equal(depth[0].cpu().numpy(), d0)
+        np.testing.assert_array_equal(parent[0].cpu().numpy(), p0)
+        pr = lgmod.pagerank(h, 0.85, 1).cpu().numpy().astype(np.float64)
+        assert np.abs(pr - pr64).sum() <= 1e-5
+        o_off, o_ids = lgmod.decode_neighbors(h, torch.from_numpy(vs).cuda(), "sorted")
+        o_off, o_ids = o_off.cpu().numpy(), o_ids.cpu().numpy()
+        for i, v in enumerate(vs):
+            np.testing.assert_array_equal(o_ids[o_off[i]:o_off[i + 1]], col[off[v]:off[v + 1]])
+        h.free()
+
+
+def test_kronecker22_weighted_sssp(lgmod):
+    """Weighted SSSP at Kronecker scale 22 (weights uniform in [1, 255]):
+    the whole distance array against the oracle's Dijkstra, packed local IDs
+    with Elias-Fano offsets and the plain CSR."""
+    print("[fullsize] kronecker s22 sssp: generate", flush=True)
+    g = gg.kronecker(22, 16, seed=3, device="cuda")
+    wt = gg.edge_weights(g, 255, seed=1)
+    off, col = host_csr(g)
+    root = gg.pick_roots(g, 1, seed=4)[0]
+    print("[fullsize] kronecker s22 sssp: oracle", flush=True)
+    expect = orc.sssp(off, col, wt.cpu().numpy().astype(np.uint32), root)
+    for kw in (dict(ids="local", offsets="succinct"), dict(layout="plain")):
+        print(f"[fullsize] kronecker s22 sssp: {kw}", flush=True)
+        h = lgmod.encode(g.row_offsets, g.col, g.n, weights=wt, **kw)
+        np.testing.assert_array_equal(lgmod.sssp(h, root).cpu().numpy(), expect)
+        h.free()
