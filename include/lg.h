@@ -64,8 +64,7 @@ typedef enum lg_status {
  * of consecutive neighbors at g_v = bl(largest difference) bits (0 when
  * d_v < 2), kept in a second table of F bits/vertex; the list takes
  * w_v + (d_v - 1) g_v bits.  Such graphs are read in order (a prefix sum
- * per list) by lg_decode_neighbors, lg_pagerank, lg_bfs and servers; batch
- * plans return LG_ERR_UNSUPPORTED for them. */
+ * per list) by every operation. */
 #define LG_IDS_LOCAL_GAP 2u
 /* subsection "Incorporating Degree-Minimizing (DM)": lists as Varint byte
  * sequences (7 value bits per byte, lowest group first, the top bit set on
@@ -75,8 +74,7 @@ typedef enum lg_status {
  * label (with LG_RELABEL_DEGREE: the paper's DMf), DIFF the first label and
  * then the differences of consecutive labels (with LG_RELABEL_DEGREE: DMd).
  * d_v is the number of bytes with the top bit clear in the list.  Such
- * graphs are read in order by lg_decode_neighbors, lg_bfs, lg_pagerank and
- * servers; batch plans return LG_ERR_UNSUPPORTED for them. */
+ * graphs are read in order by every operation. */
 #define LG_IDS_VARINT_FULL 3u
 #define LG_IDS_VARINT_DIFF 4u
 /* lg_encode_opts.offset_mode -- sections "Logarithmization of Single Offsets"

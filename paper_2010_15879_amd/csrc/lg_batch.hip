@@ -19,6 +19,7 @@
 #include <vector>
 
 #include "lg_device.hpp"
+#include "lg_varint.hpp"
 
 struct lg_batch_plan;
 
@@ -97,24 +98,99 @@ __global__ __launch_bounds__(kThreads) void bfs_batch_kernel(
                 __syncthreads();
                 for (uint32_t i = c0 + tid; i < c1; i += kThreads) {
                     const uint32_t v = qin[i];
-                    const VInfo vi = G.acc.info(v);
-                    if (vi.deg >= wave_threshold) {
-                        s_heavy[atomicAdd(&s_nheavy, 1u)] = v;
+                    if constexpr (IsGapAcc<Acc>::value) {
+                        // gap lists: a running sum of the differences
+                        const GapInfo gi = G.acc.info(v);
+                        if (gi.deg >= wave_threshold) {
+                            s_heavy[atomicAdd(&s_nheavy, 1u)] = v;
+                        } else {
+                            uint32_t val = 0;
+                            for (uint32_t e = 0; e < gi.deg; ++e) {
+                                val += G.acc.get(Acc::entry_bit(gi, e), e ? gi.g : gi.w);
+                                batch_visit<Acc>(val < n ? val : n - 1, v, nd, D, P, qout, &s_tail);
+                            }
+                        }
+                    } else if constexpr (IsVarintAcc<Acc>::value) {
+                        // Varint lists: bytes from 8-byte windows (the list's
+                        // byte count stands in for its degree)
+                        uint64_t b0, b1;
+                        G.acc.offsets(v, b0, b1);
+                        if (b1 - b0 >= wave_threshold) {
+                            s_heavy[atomicAdd(&s_nheavy, 1u)] = v;
+                        } else {
+                            uint32_t label = 0, accv = 0, shift = 0, count = 0;
+                            for (uint64_t pos = b0; pos < b1;) {
+                                const uint64_t k = pos >> 3;
+                                const uint32_t sh = (uint32_t)(pos & 7) * 8;
+                                const uint64_t w0 = G.acc.word(k * 8), w1 = G.acc.word(k * 8 + 8);
+                                const uint64_t win = sh ? (w0 >> sh) | (w1 << (64 - sh)) : w0;
+                                const uint32_t avail = b1 - pos < 8 ? (uint32_t)(b1 - pos) : 8u;
+                                for (uint32_t j = 0; j < avail; ++j) {
+                                    const uint32_t b = (uint32_t)(win >> (8 * j)) & 255u;
+                                    accv |= (b & 127u) << shift;
+                                    shift += 7;
+                                    if (!(b & 128u)) {
+                                        label = Acc::kDifferences && count ? label + accv : accv;
+                                        ++count;
+                                        accv = 0;
+                                        shift = 0;
+                                        batch_visit<Acc>(label < n ? label : n - 1, v, nd, D, P, qout, &s_tail);
+                                    }
+                                }
+                                pos += avail;
+                            }
+                        }
                     } else {
-                        const uint32_t st = Acc::step(vi.w), mk = Acc::mask(vi.w);
-                        uint64_t pos = vi.start;
-                        for (uint32_t e = 0; e < vi.deg; ++e, pos += st)
-                            batch_visit<Acc>(G.acc.get(pos, mk), v, nd, D, P, qout, &s_tail);
+                        const VInfo vi = G.acc.info(v);
+                        if (vi.deg >= wave_threshold) {
+                            s_heavy[atomicAdd(&s_nheavy, 1u)] = v;
+                        } else {
+                            const uint32_t st = Acc::step(vi.w), mk = Acc::mask(vi.w);
+                            uint64_t pos = vi.start;
+                            for (uint32_t e = 0; e < vi.deg; ++e, pos += st)
+                                batch_visit<Acc>(G.acc.get(pos, mk), v, nd, D, P, qout, &s_tail);
+                        }
                     }
                 }
                 __syncthreads();
                 const uint32_t nh = s_nheavy;
                 for (uint32_t h = wv; h < nh; h += kWaves) {
                     const uint32_t v = s_heavy[h];
-                    const VInfo vi = G.acc.info(v);
-                    const uint32_t st = Acc::step(vi.w), mk = Acc::mask(vi.w);
-                    for (uint32_t e = lane; e < vi.deg; e += kWave)
-                        batch_visit<Acc>(G.acc.get(vi.start + (uint64_t)e * st, mk), v, nd, D, P, qout, &s_tail);
+                    if constexpr (IsGapAcc<Acc>::value) {
+                        // 64 entries per step, a wave prefix sum
+                        const GapInfo gi = G.acc.info(v);
+                        uint32_t carry = 0;
+                        for (uint64_t e0 = 0; e0 < gi.deg; e0 += kWave) {
+                            const uint64_t e = e0 + lane;
+                            const bool valid = e < gi.deg;
+                            const uint32_t x = valid ? G.acc.get(Acc::entry_bit(gi, e), e ? gi.g : gi.w) : 0u;
+                            const uint32_t val = wave_incl_scan(x) + carry;
+                            carry = __shfl(val, kWave - 1, kWave);
+                            if (valid) batch_visit<Acc>(val < n ? val : n - 1, v, nd, D, P, qout, &s_tail);
+                        }
+                    } else if constexpr (IsVarintAcc<Acc>::value) {
+                        // 64 bytes per step (value assembly of varint_step)
+                        uint64_t b0, b1;
+                        G.acc.offsets(v, b0, b1);
+                        uint32_t prevb = 0, carry = 0;
+                        for (uint64_t p0 = b0; p0 < b1; p0 += kWave) {
+                            uint32_t x;
+                            const bool end = varint_step(G.acc, p0, b1, prevb, x);
+                            uint32_t label = x;
+                            if constexpr (Acc::kDifferences) {
+                                const uint32_t sc = wave_incl_scan(end ? x : 0u);
+                                label = carry + sc;
+                                carry += __shfl(sc, kWave - 1, kWave);
+                            }
+                            if (end) batch_visit<Acc>(label < n ? label : n - 1, v, nd, D, P, qout, &s_tail);
+                        }
+                    } else {
+                        const VInfo vi = G.acc.info(v);
+                        const uint32_t st = Acc::step(vi.w), mk = Acc::mask(vi.w);
+                        for (uint32_t e = lane; e < vi.deg; e += kWave)
+                            batch_visit<Acc>(G.acc.get(vi.start + (uint64_t)e * st, mk), v, nd, D, P, qout,
+                                             &s_tail);
+                    }
                 }
                 __syncthreads();
             }
@@ -193,7 +269,8 @@ static lg_status batch_build(lg_batch_plan *p, const lg_graph *const *gs, bool a
     std::vector<BatchGraph<Acc>> hg(p->num_graphs);
     for (uint32_t i = 0; i < p->num_graphs; ++i) {
         const lg_graph *g = gs[i];
-        if constexpr (Acc::kPacked) hg[i].acc = Acc{g->packed_view()};
+        if constexpr (IsGapAcc<Acc>::value || IsVarintAcc<Acc>::value) hg[i].acc = Acc{{g->packed_view()}};
+        else if constexpr (Acc::kPacked) hg[i].acc = Acc{g->packed_view()};
         else hg[i].acc = Acc{g->plain_view()};
         hg[i].n = g->n;
     }
@@ -289,9 +366,8 @@ extern "C" lg_status lg_bfs_batch_plan(const lg_graph *const *graphs, uint32_t n
             set_error("lg_bfs_batch_plan: relabeled graphs are not supported in batches");
             return LG_ERR_UNSUPPORTED;
         }
-        if (g->layout == LG_LAYOUT_PACKED && (g->id_mode >= LG_IDS_LOCAL_GAP || g->weighted)) {
-            set_error("lg_bfs_batch_plan: batches take global or local IDs without weights (gap and Varint lists "
-                      "are read in order, by lg_bfs one graph at a time)");
+        if (g->layout == LG_LAYOUT_PACKED && g->weighted) {
+            set_error("lg_bfs_batch_plan: packed weighted graphs are read by lg_sssp only");
             return LG_ERR_UNSUPPORTED;
         }
         qcap = std::max<uint64_t>(qcap, g->n);
@@ -329,7 +405,7 @@ extern "C" lg_status lg_bfs_batch_plan(const lg_graph *const *graphs, uint32_t n
             break;
         }
         if ((st = p->counter.alloc(8)) != LG_OK) break;
-        st = dispatch_acc(g0, [&](auto acc) -> lg_status {
+        st = dispatch_acc_dec(g0, [&](auto acc) -> lg_status {
             return batch_build<decltype(acc)>(p, graphs, (flags & LG_BATCH_AUTOTUNE) != 0, stream);
         });
     } while (0);

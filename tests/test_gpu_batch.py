@@ -1,6 +1,7 @@
 """GPU parity of the batched BFS (one persistent, graph-captured launch for
 many queries over many graphs): every query's depths and parents are
-bit-exact against the oracle, on every replay of the captured graph."""
+bit-exact against the oracle, on every replay of the captured graph, for
+fixed-width, gap and Varint lists."""
 
 import numpy as np
 import pytest
@@ -52,7 +53,11 @@ def check_plan(plan, graphs, jobs, max_depth=-1):
 
 @pytest.mark.parametrize("enc", [dict(layout="packed", ids="global", offsets="packed"),
                                  dict(layout="packed", ids="local", offsets="succinct"),
-                                 dict(layout="plain")], ids=["global-packed", "local-ef", "plain"])
+                                 dict(layout="plain"),
+                                 dict(layout="packed", ids="local-gap", offsets="succinct"),
+                                 dict(layout="packed", ids="varint-diff", offsets="packed"),
+                                 dict(layout="packed", ids="varint-full", offsets="succinct")],
+                         ids=["global-packed", "local-ef", "plain", "gap-ef", "dmd-packed", "dmf-ef"])
 def test_batch_matches_oracle_every_replay(lgmod, enc):
     graphs = small_graphs(24, 6, 12, seed0=1000)
     print(f"[batch] {enc} graphs={len(graphs)}", flush=True)

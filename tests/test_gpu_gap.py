@@ -128,16 +128,6 @@ def test_gap_bfs_k_hop_and_no_parents(lgmod, k):
     h.free()
 
 
-def test_gap_batch_unsupported(lgmod):
-    from paper_2010_15879_amd.lg import LGError, LG_ERR_UNSUPPORTED
-    g = GRAPHS["kron12"]
-    h = encode(lgmod, g, GAP[0])
-    with pytest.raises(LGError) as ei:
-        lgmod.BatchPlan([h], [(0, 1)])
-    assert ei.value.status == LG_ERR_UNSUPPORTED
-    h.free()
-
-
 @pytest.mark.parametrize("e", GAP, ids=gid)
 @pytest.mark.parametrize("name", list(GRAPHS))
 def test_gap_pagerank(lgmod, name, e):

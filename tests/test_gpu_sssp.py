@@ -131,7 +131,8 @@ def test_weighted_unsupported(lgmod):
     h = encode(lgmod, g, wt, WENC[4])
     root = gg.pick_roots(g, 1, seed=1)
     for call in (lambda: lgmod.bfs(h, root), lambda: lgmod.pagerank(h, 0.85, 2),
-                 lambda: lgmod.decode_neighbors(h, torch.tensor([0], dtype=torch.int32, device="cuda"))):
+                 lambda: lgmod.decode_neighbors(h, torch.tensor([0], dtype=torch.int32, device="cuda")),
+                 lambda: lgmod.BatchPlan([h], [(0, root[0])])):
         with pytest.raises(LGError) as ei:
             call()
         assert ei.value.status == LG_ERR_UNSUPPORTED

@@ -1,8 +1,7 @@
 """Varint lists on the GPU (subsection "Incorporating Degree-Minimizing
 (DM)": DMf = full labels, DMd = first label and differences, each a
 base-128 Varint): every array bit-exact against the oracle, lists decoded
-against the input, BFS and PageRank over them against the oracle, and batch
-plans refusing such graphs."""
+against the input, and BFS and PageRank over them against the oracle."""
 
 import numpy as np
 import pytest
@@ -167,16 +166,6 @@ def test_varint_pagerank(lgmod, name, e):
         l1 = np.abs(pr.astype(np.float64) - orc.pagerank(off, col, 0.85, iters)).sum()
         assert l1 <= PR_L1, (iters, l1)
     np.testing.assert_array_equal(pr, lgmod.pagerank(h, 0.85, 20).cpu().numpy())
-    h.free()
-
-
-def test_varint_batch_unsupported(lgmod):
-    from paper_2010_15879_amd.lg import LGError, LG_ERR_UNSUPPORTED
-    g = GRAPHS["kron12"]
-    h = encode(lgmod, g, VARINT[-2])
-    with pytest.raises(LGError) as ei:
-        lgmod.BatchPlan([h], [(0, 1)])
-    assert ei.value.status == LG_ERR_UNSUPPORTED
     h.free()
 
 
