@@ -271,6 +271,22 @@ def decode_weighted_list(words, start: int, d: int, w: int, omega: int):
     return ids[:d], wts[:d]
 
 
+def relabel_weights(off, col, weights, off_new, col_new, perm) -> np.ndarray:
+    """The weight of every relabeled entry: new entry (r, c) is the original
+    edge (perm[r], perm[c]); the original entries, row by row with ascending
+    lists, have ascending keys u * n + x, so a sorted search finds it."""
+    n = off.size - 1
+    off = np.asarray(off, np.int64)
+    rows = np.repeat(np.arange(n, dtype=np.int64), np.diff(off))
+    keys = rows * n + np.asarray(col, np.int64)
+    perm = np.asarray(perm, np.int64)
+    rows_new = np.repeat(np.arange(n, dtype=np.int64), np.diff(np.asarray(off_new, np.int64)))
+    want = perm[rows_new] * n + perm[np.asarray(col_new, np.int64)]
+    pos = np.searchsorted(keys, want)
+    assert np.array_equal(keys[pos], want)
+    return np.ascontiguousarray(np.asarray(weights, np.uint32)[pos])
+
+
 def sssp(off, col, weights, root: int) -> np.ndarray:
     """Shortest-path distances from root (int64, -1 where unreachable), by
     Dijkstra's algorithm: SSSP of section "Considered Algorithms"."""
@@ -424,8 +440,8 @@ class Encoding:
         self.omega = 0
         self.weights = None
         if weights is not None:
-            if relabel or id_mode not in ("global", "local"):
-                raise ValueError("weighted encodings: global or local IDs, no relabeling")
+            if id_mode not in ("global", "local"):
+                raise ValueError("weighted encodings: global or local IDs")
             self.weights = np.ascontiguousarray(weights, dtype=np.uint32)
             self.omega = weight_width(self.weights)
         if relabel:
@@ -433,7 +449,10 @@ class Encoding:
                 self.perm, self.inv = greedy_permutation(off, col)
             else:
                 self.perm, self.inv = dm_permutation(off)
+            off0, col0 = off, col
             off, col = globals()["relabel"](off, col, self.perm, self.inv)
+            if self.weights is not None:
+                self.weights = relabel_weights(off0, col0, self.weights, off, col, self.perm)
         else:
             self.perm = self.inv = None
         self.off, self.col = off, col

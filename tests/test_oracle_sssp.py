@@ -159,3 +159,25 @@ def test_sssp_against_heapq():
     for v, d in dist.items():
         expect[v] = d
     np.testing.assert_array_equal(orc.sssp(off, col, wt.astype(np.uint32), root), expect)
+
+
+def test_relabeled_weights_follow_their_edges():
+    """After the degree relabeling every stored entry still carries the weight
+    of the edge it stands for, and the distances from a root are the same
+    under the relabeling (mapped through it)."""
+    g = gg.kronecker(10, 8, seed=5)
+    off, col = g.numpy()
+    wt = gg.edge_weights(g, 255, seed=7).numpy().astype(np.uint32)
+    e = orc.Encoding(off, col, "local", "packed", True, weights=wt)
+    w_of = {}
+    for u in range(g.n):
+        for i in range(off[u], off[u + 1]):
+            w_of[(u, int(col[i]))] = int(wt[i])
+    for r in range(0, g.n, 17):
+        ids, ws = e.neighbors(r), e.weights_of(r)
+        for c, w in zip(ids, ws):
+            assert w_of[(int(e.perm[r]), int(e.perm[c]))] == int(w)
+    root = gg.pick_roots(g, 1, seed=3)[0]
+    d = orc.sssp(off, col, wt, root)
+    d_new = orc.sssp(e.off, e.col, e.weights, int(e.inv[root]))
+    np.testing.assert_array_equal(d_new[e.inv], d)
