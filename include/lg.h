@@ -202,8 +202,9 @@ lg_status lg_bfs(const lg_graph *g, const uint32_t *roots, uint32_t r, int32_t *
  *   other arguments as lg_encode
  *
  * Supported: packed layout with LG_IDS_GLOBAL or LG_IDS_LOCAL (packed or
- * succinct offsets), or the plain layout, without relabeling; other options
- * return LG_ERR_UNSUPPORTED.  A packed weighted graph is read by lg_sssp
+ * succinct offsets), or the plain layout, with any relabeling (each entry
+ * keeps the weight of the edge it stands for); other ID modes return
+ * LG_ERR_UNSUPPORTED.  A packed weighted graph is read by lg_sssp
  * only (the other operations return LG_ERR_UNSUPPORTED); a plain one by
  * every operation.
  */
@@ -216,7 +217,7 @@ lg_status lg_encode_weighted(uint32_t n, uint64_t m, const uint64_t *row_offsets
  * (SSSP of section "Considered Algorithms", a delta-stepping traversal):
  * dist[v] = the smallest sum of weights over the paths from root to v.
  *
- *   root     original vertex ID, < n
+ *   root     original vertex ID, < n (distances come back by original ID)
  *   delta    bucket width (distances [k delta, (k+1) delta) settle together);
  *            0 picks 2^weight_bits.  The distances do not depend on it.
  *   dist     dev, uint64[n]; UINT64_MAX for vertices the root does not reach

@@ -662,6 +662,33 @@ __global__ __launch_bounds__(256) void max_u32_kernel(uint64_t count, const uint
     }
 }
 
+// The weight of every relabeled entry: new entry e of row r stands for the
+// original edge (perm[r], perm[c]); a binary search of perm[c] in the
+// original (ascending) list of perm[r] finds its weight.
+__global__ void relabel_weights_kernel(uint32_t n, uint64_t m, const uint64_t *__restrict__ off_new,
+                                       const uint32_t *__restrict__ col_new, const uint32_t *__restrict__ perm,
+                                       const uint64_t *__restrict__ off, const uint32_t *__restrict__ col,
+                                       const uint32_t *__restrict__ wt, uint32_t *__restrict__ out) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += stride) {
+        uint32_t lo = 0, hi = n;  // off_new[lo] <= e < off_new[hi]
+        while (hi - lo > 1) {
+            const uint32_t mid = lo + (hi - lo) / 2;
+            if (off_new[mid] <= e) lo = mid;
+            else hi = mid;
+        }
+        const uint32_t u = perm[lo], x = perm[col_new[e]];
+        const uint64_t end = off[u + 1];
+        uint64_t a = off[u], b = end;
+        while (a < b) {
+            const uint64_t mid = a + (b - a) / 2;
+            if (col[mid] < x) a = mid + 1;
+            else b = mid;
+        }
+        out[e] = (a < end && col[a] == x) ? wt[a] : 0u;  // the edge exists: the input is symmetric
+    }
+}
+
 // list bit lengths d_v (w_v + omega), local IDs
 __global__ void weighted_len_kernel(uint32_t n, const uint64_t *__restrict__ off, const uint8_t *__restrict__ w8,
                                     uint32_t omega, uint64_t *__restrict__ len) {
@@ -980,6 +1007,7 @@ static lg_status greedy_permutation(uint32_t n, const uint64_t *off, const uint3
 static lg_status encode_impl(uint32_t n, uint64_t m, const uint64_t *row_offsets, const uint32_t *col,
                              const uint32_t *weights, const lg_encode_opts &o, hipStream_t s, lg_graph *g) {
     DevBuf tmp, status, deg, stats;
+    DevBuf wt_new;  // relabeled weights
     LG_CHECK_HIP(hipGetDevice(&g->device));
 
     // -- validation ------------------------------------------------------
@@ -1107,6 +1135,13 @@ static lg_status encode_impl(uint32_t n, uint64_t m, const uint64_t *row_offsets
         LG_CHECK_HIP(hipStreamSynchronize(s));
         cur_off = off_new.as<uint64_t>();
         cur_col = col_new.as<uint32_t>();
+        if (weights && m) {  // the weights follow their edges
+            LG_TRY(wt_new.scratch(m * 4, s));
+            LG_LAUNCH(relabel_weights_kernel, grid1(m), 256, 0, s, n, m, cur_off, cur_col, g->perm.as<uint32_t>(),
+                      row_offsets, col, weights, wt_new.as<uint32_t>());
+            LG_CHECK_LAUNCH();
+            weights = wt_new.as<uint32_t>();
+        }
     }
 
     // -- heavy vertex list (shared by the traversal kernels) -------------
@@ -1321,11 +1356,9 @@ extern "C" lg_status lg_encode_weighted(uint32_t n, uint64_t m, const uint64_t *
     lg_encode_opts o;
     std::memset(&o, 0, sizeof(o));
     if (opts) o = *opts;
-    if (o.relabel != LG_RELABEL_NONE ||
-        (o.layout == LG_LAYOUT_PACKED && o.id_mode != LG_IDS_GLOBAL && o.id_mode != LG_IDS_LOCAL)) {
+    if (o.layout == LG_LAYOUT_PACKED && o.id_mode != LG_IDS_GLOBAL && o.id_mode != LG_IDS_LOCAL) {
         if (out) *out = nullptr;
-        set_error("lg_encode_weighted: weighted graphs take global or local IDs (or the plain layout) and no "
-                  "relabeling");
+        set_error("lg_encode_weighted: weighted graphs take global or local IDs (or the plain layout)");
         return LG_ERR_UNSUPPORTED;
     }
     // a non-NULL marker when there are no entries, so the graph is weighted

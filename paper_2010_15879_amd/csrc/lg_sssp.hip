@@ -107,6 +107,7 @@ struct SsspWork {
     DevBuf qstart, qdist, qoff;         // list start, distance, exclusive scan of qdeg
     DevBuf ctr;                         // [0] frontier size, [1] smallest distance left marked
     DevBuf tmask, wcnt, woff;           // per bitmap word: vertices taken, their count, queue position
+    DevBuf dl;                          // label-space distances (relabeled graphs)
     DevBuf scan_tmp;
     uint64_t *host = nullptr;           // pinned readback slots
     SsspWork() = default;
@@ -117,7 +118,7 @@ struct SsspWork {
     }
     uint64_t bytes() const {
         return upd.bytes + qv.bytes + qw.bytes + qdeg.bytes + qstart.bytes + qdist.bytes + qoff.bytes + ctr.bytes +
-               tmask.bytes + wcnt.bytes + woff.bytes + scan_tmp.bytes;
+               tmask.bytes + wcnt.bytes + woff.bytes + dl.bytes + scan_tmp.bytes;
     }
 };
 
@@ -129,10 +130,13 @@ lg_status sssp_free(lg_graph *g) {
     return LG_OK;
 }
 
-__global__ void sssp_init_kernel(uint32_t n, uint64_t words, uint32_t root, uint64_t *__restrict__ dist,
-                                 uint64_t *__restrict__ upd) {
+// The root arrives as its original ID and is mapped to its label (inv,
+// when relabeled) here.
+__global__ void sssp_init_kernel(uint32_t n, uint64_t words, uint32_t root_id, const uint32_t *__restrict__ inv,
+                                 uint64_t *__restrict__ dist, uint64_t *__restrict__ upd) {
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     const uint64_t total = n > words ? n : words;
+    const uint32_t root = inv ? inv[root_id] : root_id;
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) {
         if (i < n) dist[i] = i == root ? 0ull : kInfDist;
         if (i < words) upd[i] = i == (root >> 6) ? 1ull << (root & 63) : 0ull;
@@ -278,6 +282,13 @@ __global__ void sssp_relax_kernel(Acc acc, uint32_t n, const uint64_t *__restric
     }
 }
 
+// distances in original IDs: dist[o] = dist of label inv[o]
+__global__ void sssp_unpermute_kernel(uint32_t n, const uint32_t *__restrict__ inv, const uint64_t *__restrict__ dl,
+                                      uint64_t *__restrict__ dist) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t o = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; o < n; o += stride) dist[o] = dl[inv[o]];
+}
+
 }  // namespace lg
 
 extern "C" lg_status lg_sssp(const lg_graph *gc, uint32_t root, uint32_t delta, uint64_t *dist, hipStream_t stream) {
@@ -318,8 +329,15 @@ extern "C" lg_status lg_sssp(const lg_graph *gc, uint32_t root, uint32_t delta, 
     LG_TRY(W.qdist.ensure((uint64_t)n * 8));
     LG_TRY(W.qoff.ensure(((uint64_t)n + 1) * 8));
     LG_TRY(W.ctr.ensure(16));
+    // a relabeled graph runs in label space, then maps back
+    const bool rel = g->relabel != LG_RELABEL_NONE;
+    uint64_t *const dist_out = dist;
+    if (rel) {
+        LG_TRY(W.dl.ensure((uint64_t)n * 8));
+        dist = W.dl.as<uint64_t>();
+    }
     LG_LAUNCH(sssp_init_kernel, grid_for(std::max<uint64_t>(n, words), 256, 1u << 16), 256, 0, stream, n, words, root,
-              dist, W.upd.as<uint64_t>());
+              rel ? (const uint32_t *)g->inv.as<uint32_t>() : (const uint32_t *)nullptr, dist, W.upd.as<uint64_t>());
     LG_CHECK_LAUNCH();
     return dispatch_wacc(g, [&](auto acc) -> lg_status {
         using Acc = decltype(acc);
@@ -364,6 +382,11 @@ extern "C" lg_status lg_sssp(const lg_graph *gc, uint32_t root, uint32_t delta, 
                       (const uint32_t *)W.qv.as<uint32_t>(), (const uint64_t *)W.qstart.as<uint64_t>(), (const uint32_t *)W.qw.as<uint32_t>(),
                       (const uint64_t *)W.qdist.as<uint64_t>(), (unsigned long long *)dist,
                       W.upd.as<unsigned long long>());
+            LG_CHECK_LAUNCH();
+        }
+        if (rel) {
+            LG_LAUNCH(sssp_unpermute_kernel, grid_for(n, 256, 1u << 16), 256, 0, stream, n, g->inv.as<uint32_t>(),
+                      (const uint64_t *)dist, dist_out);
             LG_CHECK_LAUNCH();
         }
         return LG_OK;

@@ -143,8 +143,8 @@ def test_weighted_unsupported(lgmod):
         lgmod.sssp(hu, root[0])
     assert ei.value.status == LG_ERR_UNSUPPORTED
     hu.free()
-    for bad in (dict(layout="packed", ids="local", offsets="packed", relabel=True),
-                dict(layout="packed", ids="local-gap", offsets="packed")):
+    for bad in (dict(layout="packed", ids="local-gap", offsets="packed"),
+                dict(layout="packed", ids="varint-diff", offsets="packed")):
         with pytest.raises(LGError) as ei:
             encode(lgmod, g, wt, bad)
         assert ei.value.status == LG_ERR_UNSUPPORTED
@@ -174,3 +174,33 @@ def test_sssp_invalid_arguments(lgmod):
     d = g.to("cuda")
     with pytest.raises(ValueError):
         lgmod.encode(d.row_offsets, d.col, g.n, weights=torch.ones(3, dtype=torch.int32, device="cuda"))
+
+
+WREL = [
+    dict(layout="packed", ids="local", offsets="succinct", relabel=True),
+    dict(layout="packed", ids="global", offsets="packed", relabel="greedy"),
+    dict(layout="plain", relabel=True),
+]
+
+
+@pytest.mark.parametrize("e", WREL, ids=["local-ef-dm", "global-packed-greedy", "plain-dm"])
+@pytest.mark.parametrize("name", ["kron12", "er12", "megastar", "hubtail", "rand129", "isolated7", "bigstar"])
+def test_weighted_relabeled(lgmod, name, e):
+    """Weights under a relabeling: every entry keeps its edge's weight
+    (streams bit-exact against the oracle), and the distances come back by
+    original ID, equal to the oracle's Dijkstra on the original graph."""
+    g = GRAPHS[name]
+    off, col = g.numpy()
+    wt = weights_for(g, 255, seed=9)
+    print(f"[weighted relabel] {name} {e}", flush=True)
+    h = encode(lgmod, g, wt, e)
+    o = orc.Encoding(off, col, e.get("ids", "global"), "ef" if e.get("offsets") == "succinct" else "packed",
+                     e["relabel"], weights=wt)
+    if e["layout"] == "plain":
+        np.testing.assert_array_equal(h.export("adj"), o.col)
+        np.testing.assert_array_equal(h.export("weights"), o.weights)
+    else:
+        np.testing.assert_array_equal(h.export("adj"), o.A)
+    for root in roots_of(g):
+        np.testing.assert_array_equal(lgmod.sssp(h, root).cpu().numpy(), orc.sssp(off, col, wt, root))
+    h.free()
