@@ -509,16 +509,18 @@ def sssp_main(args, np, torch, gg, lg, g, roots):
     """Weighted SSSP (delta-stepping) on the workload's graph, weights uniform
     integers in [1, 255] (the same for both directions of an edge): the
     weighted plain CSR against the packed weighted encodings (ID then weight
-    per entry, global or local IDs, Elias-Fano offsets), bytes of the lists
-    and the time of one SSSP per root (median over the roots), then delta
-    swept on the local encoding.  Edges per second count the stored entries
+    per entry, global or local IDs, Elias-Fano offsets; local IDs also after
+    the degree-minimizing relabeling), bytes of the lists and the time of one
+    SSSP per root (median over the roots), then delta swept on the local
+    encoding.  Edges per second count the stored entries
     of the vertices a root reaches, halved (as the BFS rate)."""
     n = g.n
     wt = gg.edge_weights(g, 255, seed=1)
     deg = g.degrees().to(torch.float64)
     res = {}
     encs = [("plain", dict(layout="plain")), ("packed-global", dict(ids="global", offsets="succinct")),
-            ("packed-local", dict(ids="local", offsets="succinct"))]
+            ("packed-local", dict(ids="local", offsets="succinct")),
+            ("packed-local-dm", dict(ids="local", offsets="succinct", relabel=True))]
     sweep = {}
     for name, kw in encs:
         h = lg.encode(g.row_offsets, g.col, n, weights=wt, **kw)
