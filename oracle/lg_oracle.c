@@ -24,6 +24,7 @@
  * (closed forms, brute force, textbook library routines, hand-computed
  * fixtures); none is "parity unpinned".
  */
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -726,3 +727,121 @@ ORC_API int orc_pagerank(uint64_t n, const uint64_t *off, const uint32_t *col,
     free(next);
     return 0;
 }
+
+/* ------------------------------------------------------------------ */
+/* The same two results on every host core (OpenMP), for graphs where  */
+/* the one-thread loops above take minutes.  They compute the same     */
+/* definitions; the tests hold them to the one-thread versions and to  */
+/* the same independent pins.                                           */
+/* ------------------------------------------------------------------ */
+
+/* PageRank as orc_pagerank, bit for bit: the dangling mass is summed in the
+ * same vertex order on one thread, each PR_t(u)/d_u is the same division
+ * (taken once per vertex instead of once per edge), and each vertex's sum
+ * runs over its list in the same order; only different vertices go to
+ * different threads.  threads <= 0 takes OpenMP's default. */
+ORC_API int orc_pagerank_par(uint64_t n, const uint64_t *off, const uint32_t *col, double alpha, uint32_t iters,
+                             double *pr, int threads) {
+    if (n == 0) return 0;
+    double *next = (double *)malloc(sizeof(double) * n);
+    double *contrib = (double *)malloc(sizeof(double) * n);
+    if (!next || !contrib) { free(next); free(contrib); return -2; }
+    if (threads > 0) omp_set_num_threads(threads);
+    const int64_t nn = (int64_t)n;
+    for (uint64_t v = 0; v < n; v++) pr[v] = 1.0 / (double)n;
+    for (uint32_t t = 0; t < iters; t++) {
+        double dangling = 0.0;
+        for (uint64_t u = 0; u < n; u++)
+            if (off[u + 1] == off[u]) dangling += pr[u];
+#pragma omp parallel for schedule(static)
+        for (int64_t u = 0; u < nn; u++) {
+            const uint64_t d = off[u + 1] - off[u];
+            contrib[u] = d ? pr[u] / (double)d : 0.0;
+        }
+#pragma omp parallel for schedule(dynamic, 1024)
+        for (int64_t v = 0; v < nn; v++) {
+            double sum = 0.0;
+            for (uint64_t i = off[v]; i < off[v + 1]; i++) sum += contrib[col[i]];
+            next[v] = (1.0 - alpha) / (double)n + alpha * (sum + dangling / (double)n);
+        }
+        memcpy(pr, next, sizeof(double) * n);
+    }
+    free(next);
+    free(contrib);
+    return 0;
+}
+
+/* Level-synchronous breadth-first search: level d + 1 is every unreached
+ * neighbor of a level-d vertex (frontier vertices on several threads; a
+ * vertex is claimed by one compare-and-swap of its depth).  Depths equal the
+ * FIFO search's; parents follow the same rule as orc_bfs_labels (smallest
+ * stored label one level up), taken after the depths are final.  `label`
+ * NULL: the vertex's own ID.  With max_depth >= 0 the search stops after
+ * that level. */
+ORC_API int orc_bfs_levels(uint64_t n, const uint64_t *off, const uint32_t *col, uint32_t root, int32_t max_depth,
+                           const uint32_t *label, int32_t *depth, int32_t *parent, int threads) {
+    if (root >= n) return -1;
+    if (threads > 0) omp_set_num_threads(threads);
+    const int64_t nn = (int64_t)n;
+    uint32_t *front = (uint32_t *)malloc(sizeof(uint32_t) * n);
+    uint32_t *nextf = (uint32_t *)malloc(sizeof(uint32_t) * n);
+    if (!front || !nextf) { free(front); free(nextf); return -2; }
+#pragma omp parallel for schedule(static)
+    for (int64_t v = 0; v < nn; v++) depth[v] = -1;
+    depth[root] = 0;
+    front[0] = root;
+    uint64_t fsize = 1, nsize = 0;
+    for (int32_t d = 0; fsize > 0 && (max_depth < 0 || d < max_depth); d++) {
+        nsize = 0;
+#pragma omp parallel
+        {
+            /* claimed vertices gather in a small local buffer, then move to
+             * the next frontier in one reservation */
+            uint32_t buf[1024];
+            uint64_t nb = 0;
+#pragma omp for schedule(dynamic, 64)
+            for (int64_t k = 0; k < (int64_t)fsize; k++) {
+                const uint32_t v = front[k];
+                for (uint64_t i = off[v]; i < off[v + 1]; i++) {
+                    const uint32_t u = col[i];
+                    int32_t expect = -1;
+                    if (__atomic_load_n(&depth[u], __ATOMIC_RELAXED) == -1 &&
+                        __atomic_compare_exchange_n(&depth[u], &expect, d + 1, 0, __ATOMIC_RELAXED,
+                                                    __ATOMIC_RELAXED)) {
+                        buf[nb++] = u;
+                        if (nb == 1024) {
+                            const uint64_t at = __atomic_fetch_add(&nsize, nb, __ATOMIC_RELAXED);
+                            memcpy(nextf + at, buf, nb * sizeof(uint32_t));
+                            nb = 0;
+                        }
+                    }
+                }
+            }
+            if (nb) {
+                const uint64_t at = __atomic_fetch_add(&nsize, nb, __ATOMIC_RELAXED);
+                memcpy(nextf + at, buf, nb * sizeof(uint32_t));
+            }
+        }
+        uint32_t *t = front; front = nextf; nextf = t;
+        fsize = nsize;
+    }
+    free(front);
+    free(nextf);
+#pragma omp parallel for schedule(dynamic, 4096)
+    for (int64_t v = 0; v < nn; v++) {
+        parent[v] = -1;
+        if (depth[v] < 0) continue;
+        if ((uint64_t)v == root) { parent[v] = (int32_t)root; continue; }
+        uint32_t best = UINT32_MAX, best_label = UINT32_MAX;
+        for (uint64_t i = off[v]; i < off[v + 1]; i++) {
+            const uint32_t u = col[i];
+            const uint32_t lu = label ? label[u] : u;
+            if (depth[u] == depth[v] - 1 && lu < best_label) { best_label = lu; best = u; }
+        }
+        parent[v] = (int32_t)best;
+    }
+    return 0;
+}
+
+/* Threads OpenMP would use by default (the host's cores unless limited). */
+ORC_API int orc_max_threads(void) { return omp_get_max_threads(); }

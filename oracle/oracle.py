@@ -91,6 +91,10 @@ def lib():
         "orc_bfs": (C.c_int, [C.c_uint64, u64p, u32p, C.c_uint32, C.c_int32, i32p, i32p]),
         "orc_bfs_relabeled": (C.c_int, [C.c_uint64, u64p, u32p, C.c_uint32, C.c_int32, i32p, i32p]),
         "orc_pagerank": (C.c_int, [C.c_uint64, u64p, u32p, C.c_double, C.c_uint32, f64p]),
+        "orc_pagerank_par": (C.c_int, [C.c_uint64, u64p, u32p, C.c_double, C.c_uint32, f64p, C.c_int]),
+        "orc_bfs_levels": (C.c_int, [C.c_uint64, u64p, u32p, C.c_uint32, C.c_int32, _NullableU32, i32p, i32p,
+                                     C.c_int]),
+        "orc_max_threads": (C.c_int, []),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -415,6 +419,36 @@ def pagerank(off, col, alpha: float = 0.85, iters: int = 20) -> np.ndarray:
     if rc != 0:
         raise ValueError("oracle pagerank failed")
     return pr[:n]
+
+
+def pagerank_par(off, col, alpha: float = 0.85, iters: int = 20, threads: int = 0) -> np.ndarray:
+    """pagerank() on every host core (threads <= 0: OpenMP's default);
+    bit-identical to the one-thread result."""
+    n, off, col = _csr(off, col)
+    pr = np.zeros(max(n, 1), dtype=np.float64)
+    rc = lib().orc_pagerank_par(n, off, col, alpha, iters, pr, int(threads))
+    if rc != 0:
+        raise ValueError("oracle pagerank_par failed")
+    return pr[:n]
+
+
+def bfs_levels(off, col, root: int, max_depth: int = -1, labels=None, threads: int = 0):
+    """Level-synchronous BFS on every host core: the same depths and parents
+    as bfs() (labels: the stored label of every vertex for the parent rule,
+    e.g. the inverse degree permutation; None: the IDs themselves)."""
+    n, off, col = _csr(off, col)
+    depth = np.zeros(max(n, 1), dtype=np.int32)
+    parent = np.zeros(max(n, 1), dtype=np.int32)
+    lab = None if labels is None else np.ascontiguousarray(labels, np.uint32)
+    rc = lib().orc_bfs_levels(n, off, col, root, max_depth, lab, depth, parent, int(threads))
+    if rc != 0:
+        raise ValueError(f"oracle bfs_levels failed ({rc})")
+    return depth[:n], parent[:n]
+
+
+def max_threads() -> int:
+    """Threads the all-core oracle functions use by default."""
+    return int(lib().orc_max_threads())
 
 
 # -- the whole encoding as the oracle defines it --------------------
