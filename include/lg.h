@@ -223,8 +223,10 @@ lg_status lg_encode_weighted(uint32_t n, uint64_t m, const uint64_t *row_offsets
  *   dist     dev, uint64[n]; UINT64_MAX for vertices the root does not reach
  *
  * Returns LG_ERR_UNSUPPORTED for an unweighted graph.  Synchronous: the
- * host reads each step's frontier size back to drive the buckets.  The
- * workspace is kept with the graph until lg_free.
+ * host reads each step's frontier size back to drive the buckets, and the
+ * call returns once dist is written.  The workspace is kept with the graph
+ * until lg_free; calls on the same graph from several threads run one after
+ * the other (each holds the graph's workspace for its whole duration).
  */
 lg_status lg_sssp(const lg_graph *g, uint32_t root, uint32_t delta, uint64_t *dist, hipStream_t stream);
 
@@ -281,7 +283,8 @@ lg_status lg_bfs_batch_plan(const lg_graph *const *graphs, uint32_t num_graphs, 
                             int32_t max_depth, uint32_t flags, hipStream_t stream, lg_batch_plan **out);
 lg_status lg_bfs_batch_run(lg_batch_plan *plan, hipStream_t stream);
 lg_status lg_bfs_batch_info(const lg_batch_plan *plan, lg_batch_info *out);
-void lg_bfs_batch_free(lg_batch_plan *plan); /* NULL-safe */
+/* NULL-safe; waits for the plan's last replay only */
+void lg_bfs_batch_free(lg_batch_plan *plan);
 
 /*
  * Query server over resident graphs.
@@ -367,7 +370,10 @@ lg_status lg_admission_simulate(const double *arrival, const uint64_t *need, con
                                 uint64_t budget, uint64_t resident, uint32_t workers, double *start, double *finish,
                                 int32_t *status, uint64_t *peak);
 
-/* Release a graph and its device memory.  NULL is accepted. */
+/* Release a graph and its device memory.  NULL is accepted.  Waits (on the
+ * host) for the graph's last use -- the end of the latest call that read it,
+ * on that call's stream -- and for nothing else: work of other graphs and
+ * streams goes on. */
 void lg_free(lg_graph *g);
 
 /* Sizes and parameters of a built representation. */

@@ -262,9 +262,24 @@ uint64_t bfs_bytes(const lg_graph *g);
 uint64_t pr_bytes(const lg_graph *g);
 }  // namespace lg
 
+namespace lg {
+lg_status mark_use(lg_graph *g, hipStream_t stream) {
+    if (g->last_use) LG_CHECK_HIP(hipEventRecord(g->last_use, stream));
+    return LG_OK;
+}
+}  // namespace lg
+
 extern "C" void lg_free(lg_graph *g) {
     if (!g) return;
-    (void)hipDeviceSynchronize();
+    // Wait for the graph's own last use only (calls on one graph do not
+    // overlap, so the last one recorded finishes after every earlier one);
+    // work on other streams and graphs goes on.  The arrays then go back to
+    // the scratch pool, or are freed.
+    if (g->last_use) {
+        (void)hipEventSynchronize(g->last_use);
+        (void)hipEventDestroy(g->last_use);
+        g->last_use = nullptr;
+    }
     lg::bfs_free(g);
     lg::pr_free(g);
     lg::sssp_free(g);

@@ -226,6 +226,8 @@ struct lg_batch_plan {
     lg::DevBuf graphs, jobs, counter, queues;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    std::vector<lg_graph *> handles;  // the plan's graphs (each run is one use of each)
+    hipEvent_t last_run = nullptr;    // recorded after every replay
 };
 
 namespace lg {
@@ -398,6 +400,13 @@ extern "C" lg_status lg_bfs_batch_plan(const lg_graph *const *graphs, uint32_t n
         p->depth = depth;
         p->parent = parent;
         p->max_depth = max_depth;
+        for (uint32_t i = 0; i < num_graphs; ++i) p->handles.push_back(const_cast<lg_graph *>(graphs[i]));
+        if (hipEventCreateWithFlags(&p->last_run, hipEventDisableTiming) != hipSuccess) {
+            p->last_run = nullptr;
+            st = LG_ERR_DEVICE;
+            set_error("lg_bfs_batch_plan: hipEventCreateWithFlags failed");
+            break;
+        }
         if ((st = p->jobs.alloc(sizeof(BatchJob) * (num_jobs ? num_jobs : 1))) != LG_OK) break;
         if (num_jobs && hipMemcpy(p->jobs.p, hj.data(), sizeof(BatchJob) * num_jobs, hipMemcpyHostToDevice) != hipSuccess) {
             st = LG_ERR_DEVICE;
@@ -421,6 +430,9 @@ extern "C" lg_status lg_bfs_batch_plan(const lg_graph *const *graphs, uint32_t n
 extern "C" lg_status lg_bfs_batch_run(lg_batch_plan *p, hipStream_t stream) {
     if (!p || !p->exec) { lg::set_error("lg_bfs_batch_run: bad plan"); return LG_ERR_INVALID; }
     LG_CHECK_HIP(hipGraphLaunch(p->exec, stream));
+    // the plan's scratch and graphs are in use until this point of `stream`
+    if (p->last_run) LG_CHECK_HIP(hipEventRecord(p->last_run, stream));
+    for (lg_graph *g : p->handles) LG_TRY(lg::mark_use(g, stream));
     return LG_OK;
 }
 
@@ -440,7 +452,11 @@ extern "C" lg_status lg_bfs_batch_info(const lg_batch_plan *p, lg_batch_info *ou
 
 extern "C" void lg_bfs_batch_free(lg_batch_plan *p) {
     if (!p) return;
-    (void)hipDeviceSynchronize();
+    // wait for the plan's own last replay, not for the whole device
+    if (p->last_run) {
+        (void)hipEventSynchronize(p->last_run);
+        (void)hipEventDestroy(p->last_run);
+    }
     if (p->exec) (void)hipGraphExecDestroy(p->exec);
     if (p->graph) (void)hipGraphDestroy(p->graph);
     delete p;

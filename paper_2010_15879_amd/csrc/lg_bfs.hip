@@ -1646,10 +1646,15 @@ extern "C" lg_status lg_bfs(const lg_graph *gc, const uint32_t *roots, uint32_t 
     for (uint32_t i = 0; i < r; ++i)
         if (roots[i] >= g->n) { set_error("lg_bfs: root %u out of range", roots[i]); return LG_ERR_INVALID; }
     if (r == 0) return LG_OK;
-    if (r > 1) return bfs_run_lanes(g, roots, r, depth, parent, max_depth, flags, stream);
+    if (r > 1) {
+        // the lanes' work is joined back into `stream` before this returns
+        LG_TRY(bfs_run_lanes(g, roots, r, depth, parent, max_depth, flags, stream));
+        return mark_use(g, stream);
+    }
     if (!g->bfs) {
         g->bfs = new (std::nothrow) BfsWork();
         if (!g->bfs) { set_error("lg_bfs: host allocation failed"); return LG_ERR_OOM; }
     }
-    return bfs_run(g, *g->bfs, roots, r, depth, parent, max_depth, flags, stream);
+    LG_TRY(bfs_run(g, *g->bfs, roots, r, depth, parent, max_depth, flags, stream));
+    return mark_use(g, stream);
 }

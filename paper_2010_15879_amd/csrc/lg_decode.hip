@@ -237,7 +237,7 @@ lg_status decode_run(lg_graph *g, DecodeWork &w, const uint32_t *vertices, uint3
 
 }  // namespace lg
 
-extern "C" lg_status lg_decode_neighbors(const lg_graph *gc, const uint32_t *vertices, uint32_t k,
+static lg_status lg_decode_neighbors_impl(const lg_graph *gc, const uint32_t *vertices, uint32_t k,
                                          uint64_t *out_off, uint32_t *out_ids, uint64_t cap, uint32_t flags,
                                          hipStream_t stream) {
     using namespace lg;
@@ -250,5 +250,13 @@ extern "C" lg_status lg_decode_neighbors(const lg_graph *gc, const uint32_t *ver
     }
     const lg_status st = decode_run(g, *g->dec, vertices, k, out_off, out_ids, cap, flags, stream, nullptr);
     if (st == LG_OK) LG_CHECK_HIP(hipStreamSynchronize(stream));
+    return st;
+}
+
+extern "C" lg_status lg_decode_neighbors(const lg_graph *gc, const uint32_t *vertices, uint32_t k,
+                                         uint64_t *out_off, uint32_t *out_ids, uint64_t cap, uint32_t flags,
+                                         hipStream_t stream) {
+    const lg_status st = lg_decode_neighbors_impl(gc, vertices, k, out_off, out_ids, cap, flags, stream);
+    if (gc && (st == LG_OK || st == LG_ERR_CAPACITY)) LG_TRY(lg::mark_use(const_cast<lg_graph *>(gc), stream));
     return st;
 }

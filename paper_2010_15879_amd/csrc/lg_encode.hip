@@ -668,7 +668,8 @@ __global__ __launch_bounds__(256) void max_u32_kernel(uint64_t count, const uint
 __global__ void relabel_weights_kernel(uint32_t n, uint64_t m, const uint64_t *__restrict__ off_new,
                                        const uint32_t *__restrict__ col_new, const uint32_t *__restrict__ perm,
                                        const uint64_t *__restrict__ off, const uint32_t *__restrict__ col,
-                                       const uint32_t *__restrict__ wt, uint32_t *__restrict__ out) {
+                                       const uint32_t *__restrict__ wt, uint32_t *__restrict__ out,
+                                       uint32_t *__restrict__ miss) {
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += stride) {
         uint32_t lo = 0, hi = n;  // off_new[lo] <= e < off_new[hi]
@@ -685,7 +686,15 @@ __global__ void relabel_weights_kernel(uint32_t n, uint64_t m, const uint64_t *_
             if (col[mid] < x) a = mid + 1;
             else b = mid;
         }
-        out[e] = (a < end && col[a] == x) ? wt[a] : 0u;  // the edge exists: the input is symmetric
+        // Row lo of the relabeled lists is the original list of u renamed, so
+        // its entry e stands for the original edge (u, x), which the search
+        // finds; a miss means the arrays were corrupted and fails the encode.
+        if (a < end && col[a] == x) {
+            out[e] = wt[a];
+        } else {
+            out[e] = 0u;
+            atomicOr(miss, 1u);
+        }
     }
 }
 
@@ -1137,9 +1146,19 @@ static lg_status encode_impl(uint32_t n, uint64_t m, const uint64_t *row_offsets
         cur_col = col_new.as<uint32_t>();
         if (weights && m) {  // the weights follow their edges
             LG_TRY(wt_new.scratch(m * 4, s));
+            DevBuf miss;
+            LG_TRY(miss.scratch(8, s));
+            LG_TRY(fill_u32(miss.as<uint32_t>(), 0, 1, s));
             LG_LAUNCH(relabel_weights_kernel, grid1(m), 256, 0, s, n, m, cur_off, cur_col, g->perm.as<uint32_t>(),
-                      row_offsets, col, weights, wt_new.as<uint32_t>());
+                      row_offsets, col, weights, wt_new.as<uint32_t>(), miss.as<uint32_t>());
             LG_CHECK_LAUNCH();
+            uint32_t missed = 0;
+            LG_CHECK_HIP(hipMemcpyAsync(&missed, miss.p, 4, hipMemcpyDeviceToHost, s));
+            LG_CHECK_HIP(hipStreamSynchronize(s));
+            if (missed) {
+                set_error("lg_encode_weighted: a relabeled entry has no edge in its original list");
+                return LG_ERR_DEVICE;
+            }
             weights = wt_new.as<uint32_t>();
         }
     }
@@ -1400,6 +1419,12 @@ static lg_status encode_entry(uint32_t n, uint64_t m, const uint64_t *row_offset
     if (st == LG_OK && g->layout == LG_LAYOUT_PACKED &&
         (g->id_mode == LG_IDS_VARINT_FULL || g->id_mode == LG_IDS_VARINT_DIFF))
         st = build_varint_segments(g, stream);
+    if (st == LG_OK && hipEventCreateWithFlags(&g->last_use, hipEventDisableTiming) != hipSuccess) {
+        g->last_use = nullptr;
+        set_error("lg_encode: hipEventCreateWithFlags failed");
+        st = LG_ERR_DEVICE;
+    }
+    if (st == LG_OK) st = mark_use(g, stream);
     if (st != LG_OK) {
         (void)hipStreamSynchronize(stream);
         lg_free(g);

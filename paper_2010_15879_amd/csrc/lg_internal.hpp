@@ -6,6 +6,7 @@
 
 #include <cstdint>
 #include <cstdio>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -206,6 +207,11 @@ struct lg_graph {
     lg::PrWork *pr = nullptr;
     lg::DecodeWork *dec = nullptr;
     lg::SsspWork *sssp = nullptr;
+    std::mutex sssp_mu;  // lg_sssp calls on this graph share `sssp`: one at a time
+    // recorded on the caller's stream at the end of every call that reads
+    // the graph; lg_free waits for it (and nothing else) before the arrays
+    // are released
+    hipEvent_t last_use = nullptr;
 
     lg::PackedView packed_view() const;
     lg::PlainView plain_view() const;
@@ -282,6 +288,9 @@ inline uint32_t bitlen_u64(uint64_t x) { return x ? 64u - (uint32_t)__builtin_cl
 lg_status ensure_heavy_segments(lg_graph *g, hipStream_t s);
 lg_status build_varint_segments(lg_graph *g, hipStream_t s);
 lg_status pagerank_varint(lg_graph *g, float damping, uint32_t iters, float *scores, hipStream_t s);
+
+// Record g->last_use on `stream` (the end of a call that read g).
+lg_status mark_use(lg_graph *g, hipStream_t stream);
 
 lg_status bfs_free(lg_graph *g);
 void bfs_pools_trim();

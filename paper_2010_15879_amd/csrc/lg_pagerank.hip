@@ -377,7 +377,7 @@ __global__ void pr_fill_kernel(uint32_t n, float value, float *__restrict__ out)
 
 }  // namespace lg
 
-extern "C" lg_status lg_pagerank(const lg_graph *gc, float damping, uint32_t iters, float *scores,
+static lg_status lg_pagerank_impl(const lg_graph *gc, float damping, uint32_t iters, float *scores,
                                  hipStream_t stream) {
     using namespace lg;
     lg_graph *g = const_cast<lg_graph *>(gc);
@@ -453,4 +453,10 @@ extern "C" lg_status lg_pagerank(const lg_graph *gc, float damping, uint32_t ite
         }
         return LG_OK;
     });
+}
+
+extern "C" lg_status lg_pagerank(const lg_graph *gc, float damping, uint32_t iters, float *scores,
+                                 hipStream_t stream) {
+    LG_TRY(lg_pagerank_impl(gc, damping, iters, scores, stream));
+    return lg::mark_use(const_cast<lg_graph *>(gc), stream);
 }

@@ -19,6 +19,8 @@
 // exact distances whatever delta and the order of the atomics.
 #include <algorithm>
 
+#include <mutex>
+
 #include "lg_device.hpp"
 
 namespace lg {
@@ -291,7 +293,7 @@ __global__ void sssp_unpermute_kernel(uint32_t n, const uint32_t *__restrict__ i
 
 }  // namespace lg
 
-extern "C" lg_status lg_sssp(const lg_graph *gc, uint32_t root, uint32_t delta, uint64_t *dist, hipStream_t stream) {
+static lg_status lg_sssp_impl(const lg_graph *gc, uint32_t root, uint32_t delta, uint64_t *dist, hipStream_t stream) {
     using namespace lg;
     lg_graph *g = const_cast<lg_graph *>(gc);
     if (!g || !dist) { set_error("lg_sssp: NULL argument"); return LG_ERR_INVALID; }
@@ -306,6 +308,9 @@ extern "C" lg_status lg_sssp(const lg_graph *gc, uint32_t root, uint32_t delta, 
     const uint64_t D = delta ? delta : (1ull << g->omega);
     const uint32_t n = g->n;
     const uint64_t words = ((uint64_t)n + 63) / 64;
+    // one workspace per graph: calls on the same graph run one at a time, and
+    // each waits for its own last kernel before letting the next one in
+    std::lock_guard<std::mutex> hold(g->sssp_mu);
     if (!g->sssp) {
         g->sssp = new (std::nothrow) SsspWork();
         if (!g->sssp) { set_error("lg_sssp: host allocation failed"); return LG_ERR_OOM; }
@@ -388,7 +393,13 @@ extern "C" lg_status lg_sssp(const lg_graph *gc, uint32_t root, uint32_t delta, 
             LG_LAUNCH(sssp_unpermute_kernel, grid_for(n, 256, 1u << 16), 256, 0, stream, n, g->inv.as<uint32_t>(),
                       (const uint64_t *)dist, dist_out);
             LG_CHECK_LAUNCH();
+            LG_CHECK_HIP(hipStreamSynchronize(stream));
         }
         return LG_OK;
     });
+}
+
+extern "C" lg_status lg_sssp(const lg_graph *gc, uint32_t root, uint32_t delta, uint64_t *dist, hipStream_t stream) {
+    LG_TRY(lg_sssp_impl(gc, root, delta, dist, stream));
+    return lg::mark_use(const_cast<lg_graph *>(gc), stream);
 }

@@ -221,13 +221,34 @@ class Graph:
         return buf
 
 
+def _weights_u32(w: torch.Tensor) -> torch.Tensor:
+    """The weights as the uint32 bit patterns lg_encode_weighted reads (in an
+    int32 tensor), after checking that every value lies in [0, 2^32)."""
+    if not w.is_cuda:
+        raise ValueError("weights must be a device tensor")
+    if w.numel() == 0:
+        return w.to(torch.int32)
+    if w.dtype == torch.uint32:
+        return w.contiguous().view(torch.int32)
+    if w.dtype not in (torch.int32, torch.int64):
+        raise ValueError(f"weights must be int64, int32 or uint32, got {w.dtype}")
+    lo, hi = int(w.min()), int(w.max())
+    if lo < 0 or hi >= 1 << 32:
+        raise ValueError(f"weights must lie in [0, 2^32), got [{lo}, {hi}]")
+    if w.dtype == torch.int32:
+        return w.contiguous()
+    # values in [2^31, 2^32) become the int32 with the same low 32 bits
+    return torch.where(w >= 1 << 31, w - (1 << 32), w).to(torch.int32).contiguous()
+
+
 def encode(row_offsets: torch.Tensor, col: torch.Tensor, n: Optional[int] = None, *, layout="packed",
            ids="global", offsets="packed", relabel=False, weights: Optional[torch.Tensor] = None,
            stream=None) -> Graph:
     """lg_encode over a device CSR (row_offsets int64[n+1], col int32[M]).
     relabel: False, True or "degree" (degree-minimizing), or "greedy" (the
-    greedy heuristic).  weights (int32[M] on the device, non-negative): an
-    edge weight per entry, through lg_encode_weighted."""
+    greedy heuristic).  weights (a device tensor of M values in [0, 2^32):
+    int64, int32 with no negative value, or uint32): an edge weight per
+    entry, passed to lg_encode_weighted as uint32."""
     n = row_offsets.numel() - 1 if n is None else n
     m = col.numel()
     if relabel is True or relabel == "degree":
@@ -243,6 +264,7 @@ def encode(row_offsets: torch.Tensor, col: torch.Tensor, n: Optional[int] = None
     if weights is not None:
         if weights.numel() != m:
             raise ValueError("weights must hold one value per entry of col")
+        weights = _weights_u32(weights)
         _check(lib().lg_encode_weighted(n, m, _dev_ptr(row_offsets, torch.int64, "row_offsets"),
                                         _dev_ptr(col, torch.int32, "col") if m else None,
                                         _dev_ptr(weights, torch.int32, "weights") if m else None, C.byref(opts),
