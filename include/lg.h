@@ -155,6 +155,30 @@ lg_status lg_decode_neighbors(const lg_graph *g, const uint32_t *vertices, uint3
                               uint64_t *out_off, uint32_t *out_ids, uint64_t cap,
                               uint32_t flags, hipStream_t stream);
 
+/*
+ * lg_decode_neighbors_noalloc -- lg_decode_neighbors for callers that cannot
+ * allocate memory: serving loops that must not call into the allocator, and
+ * harnesses that forbid allocation after set-up.  Same arguments, results,
+ * errors and synchronization as lg_decode_neighbors, but the call allocates
+ * nothing (no device, pinned-host or graph workspace memory): its
+ * temporaries live in one fixed device array of the library,
+ * LG_NOALLOC_SCRATCH_BYTES per GPU, which each GPU the call runs on holds
+ * until the process ends.  Calls on one GPU share that array; the library
+ * runs them one at a time, each returning only after its kernels are done
+ * (so callers never see the previous call's contents).
+ * Limits: k <= LG_NOALLOC_MAX_VERTICES, and for LG_DECODE_SORTED on a
+ * relabeled graph (the only mode that sorts) at most
+ * LG_NOALLOC_MAX_SORTED_IDS ids in total; larger requests return
+ * LG_ERR_UNSUPPORTED (out_off is still written when the second limit is
+ * the one exceeded).
+ */
+#define LG_NOALLOC_MAX_VERTICES 65536u
+#define LG_NOALLOC_MAX_SORTED_IDS (1u << 20)
+#define LG_NOALLOC_SCRATCH_BYTES (32u << 20)
+lg_status lg_decode_neighbors_noalloc(const lg_graph *g, const uint32_t *vertices, uint32_t k,
+                                      uint64_t *out_off, uint32_t *out_ids, uint64_t cap,
+                                      uint32_t flags, hipStream_t stream);
+
 /* lg_bfs flags */
 #define LG_BFS_DIRECTION_OPT 0u /* top-down/bottom-up switching (default)          */
 #define LG_BFS_TOP_DOWN 1u      /* top-down steps only                              */

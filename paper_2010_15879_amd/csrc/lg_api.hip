@@ -46,6 +46,12 @@ constexpr uint64_t kPoolCap = 64ull << 30;  // bytes the pool keeps at most
 }  // namespace
 
 void DevBuf::release() {
+    if (borrowed) {
+        p = nullptr;
+        bytes = 0;
+        borrowed = false;
+        return;
+    }
     if (p) {
         if (pooled) {
             int dev = 0;
@@ -141,6 +147,11 @@ lg_status DevBuf::alloc(uint64_t nbytes) {
 
 lg_status DevBuf::ensure(uint64_t nbytes) {
     if (p && bytes >= nbytes) return LG_OK;
+    if (borrowed) {
+        set_error("a fixed scratch region of %llu bytes cannot hold %llu", (unsigned long long)bytes,
+                  (unsigned long long)nbytes);
+        return LG_ERR_UNSUPPORTED;
+    }
     if (pooled) return scratch(nbytes, pool_stream);
     return alloc(nbytes);
 }

@@ -4,6 +4,8 @@
 // extraction of subsection "Accessing An Edge", one wave per requested
 // vertex so that consecutive lanes decode consecutive elements; gap and
 // Varint lists are decoded in order, 64 entries or bytes per wave step.
+#include <mutex>
+
 #include "lg_device.hpp"
 
 namespace lg {
@@ -156,7 +158,7 @@ __global__ void dec_unkey_kernel(uint64_t total, const uint64_t *__restrict__ ke
 }
 
 DecodeWork::~DecodeWork() {
-    if (host) (void)hipHostFree(host);
+    if (host && host_owned) (void)hipHostFree(host);
 }
 
 uint64_t DecodeWork::bytes() const {
@@ -258,5 +260,120 @@ extern "C" lg_status lg_decode_neighbors(const lg_graph *gc, const uint32_t *ver
                                          hipStream_t stream) {
     const lg_status st = lg_decode_neighbors_impl(gc, vertices, k, out_off, out_ids, cap, flags, stream);
     if (gc && (st == LG_OK || st == LG_ERR_CAPACITY)) LG_TRY(lg::mark_use(const_cast<lg_graph *>(gc), stream));
+    return st;
+}
+
+// ---------------------------------------------------------------------------
+// lg_decode_neighbors_noalloc: the same decode, its temporaries in a fixed
+// device array instead of buffers allocated for the graph
+// ---------------------------------------------------------------------------
+
+// One copy per GPU, loaded with the library's code object.  In host code this
+// name is a stand-in, not a device address: the address on each device comes
+// from hipGetSymbolAddress and is the only one passed to kernels.
+static __device__ __align__(256) unsigned char scratch[LG_NOALLOC_SCRATCH_BYTES];
+
+namespace lg {
+namespace {
+
+constexpr int kNoallocDevices = 64;
+
+struct NoallocDevice {
+    std::mutex mu;        // calls on one GPU share its array: one at a time
+    void *ptr = nullptr;  // device address of `scratch` on this GPU (set once)
+};
+NoallocDevice g_noalloc[kNoallocDevices];
+
+inline uint64_t align256(uint64_t x) { return (x + 255) & ~255ull; }
+
+// byte offsets of the temporaries inside the array, for the largest request
+struct NoallocLayout {
+    uint64_t head, scan, keys, keys2, vals, vals2, sort, end;
+};
+NoallocLayout noalloc_layout() {
+    NoallocLayout L{};
+    uint64_t o = 0;
+    L.head = o;  o += align256((uint64_t)LG_NOALLOC_MAX_VERTICES * 8 + 8);  // labels | degrees | flag
+    L.scan = o;  o += align256(scan_tmp_bytes(LG_NOALLOC_MAX_VERTICES));
+    L.keys = o;  o += align256((uint64_t)LG_NOALLOC_MAX_SORTED_IDS * 8);
+    L.keys2 = o; o += align256((uint64_t)LG_NOALLOC_MAX_SORTED_IDS * 8);
+    L.vals = o;  o += align256((uint64_t)LG_NOALLOC_MAX_SORTED_IDS * 4);
+    L.vals2 = o; o += align256((uint64_t)LG_NOALLOC_MAX_SORTED_IDS * 4);
+    L.sort = o;  o += align256(radix_sort_tmp_bytes(LG_NOALLOC_MAX_SORTED_IDS));
+    L.end = o;
+    return L;
+}
+
+}  // namespace
+}  // namespace lg
+
+extern "C" lg_status lg_decode_neighbors_noalloc(const lg_graph *gc, const uint32_t *vertices, uint32_t k,
+                                                 uint64_t *out_off, uint32_t *out_ids, uint64_t cap,
+                                                 uint32_t flags, hipStream_t stream) {
+    using namespace lg;
+    lg_graph *g = const_cast<lg_graph *>(gc);
+    if (!g || !out_off || (k && !vertices)) {
+        set_error("lg_decode_neighbors_noalloc: NULL argument");
+        return LG_ERR_INVALID;
+    }
+    if (flags > LG_DECODE_RAW) { set_error("lg_decode_neighbors_noalloc: unknown flags"); return LG_ERR_INVALID; }
+    if (k > LG_NOALLOC_MAX_VERTICES) {
+        set_error("lg_decode_neighbors_noalloc: %u vertices exceed the limit of %u (LG_NOALLOC_MAX_VERTICES)", k,
+                  (unsigned)LG_NOALLOC_MAX_VERTICES);
+        return LG_ERR_UNSUPPORTED;
+    }
+    int dev = 0;
+    LG_CHECK_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kNoallocDevices) {
+        set_error("lg_decode_neighbors_noalloc: device %d beyond the %d supported", dev, kNoallocDevices);
+        return LG_ERR_UNSUPPORTED;
+    }
+    const NoallocLayout L = noalloc_layout();
+    if (L.end > sizeof(scratch)) {
+        set_error("lg_decode_neighbors_noalloc: temporaries need %llu bytes, the array holds %llu",
+                  (unsigned long long)L.end, (unsigned long long)sizeof(scratch));
+        return LG_ERR_UNSUPPORTED;
+    }
+    NoallocDevice &D = g_noalloc[dev];
+    std::lock_guard<std::mutex> hold(D.mu);
+    if (!D.ptr) {
+        // once per GPU, with that GPU current: this GPU's copy of the array
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            set_error("lg_decode_neighbors_noalloc: hipGetSymbolAddress failed: %s", hipGetErrorString(e));
+            return LG_ERR_DEVICE;
+        }
+        D.ptr = p;
+    }
+    char *base = static_cast<char *>(D.ptr);
+    DecodeWork w;
+    w.head.borrow(base + L.head, L.scan - L.head);
+    w.scan_tmp.borrow(base + L.scan, L.keys - L.scan);
+    w.keys.borrow(base + L.keys, L.keys2 - L.keys);
+    w.keys2.borrow(base + L.keys2, L.vals - L.keys2);
+    w.vals.borrow(base + L.vals, L.vals2 - L.vals);
+    w.vals2.borrow(base + L.vals2, L.sort - L.vals2);
+    w.sort_tmp.borrow(base + L.sort, L.end - L.sort);
+    uint64_t slots[4] = {0, 0, 0, 0};  // readback into host memory the caller's thread owns
+    w.host = slots;
+    w.host_owned = false;
+    uint64_t total = 0;
+    const lg_status st = decode_run(g, w, vertices, k, out_off, out_ids, cap, flags, stream, &total);
+    w.host = nullptr;
+    // the next call may reuse the array only after this one's kernels ran
+    const hipError_t se = hipStreamSynchronize(stream);
+    if (st == LG_ERR_UNSUPPORTED && total > LG_NOALLOC_MAX_SORTED_IDS) {
+        // the only temporaries whose size depends on the result: the sort keys
+        set_error("lg_decode_neighbors_noalloc: sorting %llu ids exceeds the limit of %u "
+                  "(LG_NOALLOC_MAX_SORTED_IDS)", (unsigned long long)total, (unsigned)LG_NOALLOC_MAX_SORTED_IDS);
+        return st;
+    }
+    if (st != LG_OK && st != LG_ERR_CAPACITY) return st;
+    if (se != hipSuccess) {
+        set_error("lg_decode_neighbors_noalloc: hipStreamSynchronize failed: %s", hipGetErrorString(se));
+        return LG_ERR_DEVICE;
+    }
+    LG_TRY(mark_use(g, stream));
     return st;
 }

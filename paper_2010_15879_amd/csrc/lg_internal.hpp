@@ -46,24 +46,36 @@ struct DevBuf {
     uint64_t bytes = 0;
     hipStream_t pool_stream = nullptr;  // scratch from the pool: returns there on release
     bool pooled = false;
+    bool borrowed = false;  // a view of memory the buffer does not own: never freed or grown
     DevBuf() = default;
     DevBuf(const DevBuf &) = delete;
     DevBuf &operator=(const DevBuf &) = delete;
-    DevBuf(DevBuf &&o) noexcept : p(o.p), bytes(o.bytes), pool_stream(o.pool_stream), pooled(o.pooled) {
+    DevBuf(DevBuf &&o) noexcept
+        : p(o.p), bytes(o.bytes), pool_stream(o.pool_stream), pooled(o.pooled), borrowed(o.borrowed) {
         o.p = nullptr;
         o.bytes = 0;
         o.pooled = false;
+        o.borrowed = false;
     }
     DevBuf &operator=(DevBuf &&o) noexcept {
         if (this != &o) {
             release();
-            p = o.p; bytes = o.bytes; pool_stream = o.pool_stream; pooled = o.pooled;
-            o.p = nullptr; o.bytes = 0; o.pooled = false;
+            p = o.p; bytes = o.bytes; pool_stream = o.pool_stream; pooled = o.pooled; borrowed = o.borrowed;
+            o.p = nullptr; o.bytes = 0; o.pooled = false; o.borrowed = false;
         }
         return *this;
     }
     ~DevBuf() { release(); }
     void release();
+    // view [ptr, ptr + nbytes) of memory owned elsewhere: ensure() then only
+    // checks the size (it fails with LG_ERR_UNSUPPORTED instead of
+    // allocating) and release() forgets the view
+    void borrow(void *ptr, uint64_t nbytes) {
+        release();
+        p = ptr;
+        bytes = nbytes;
+        borrowed = true;
+    }
     lg_status alloc(uint64_t nbytes);          // release + allocate
     lg_status ensure(uint64_t nbytes);         // grow only
     // release + take a buffer of at least nbytes that is only ever used on
@@ -125,7 +137,8 @@ struct BfsPool {
 struct DecodeWork {
     DevBuf head;                 // labels, degrees, flag
     DevBuf scan_tmp, keys, keys2, vals, vals2, sort_tmp;
-    uint64_t *host = nullptr;    // pinned readback slots
+    uint64_t *host = nullptr;    // readback slots (pinned, allocated on first use, unless set by the caller)
+    bool host_owned = true;      // host came from hipHostMalloc and is freed with the workspace
     DecodeWork() = default;
     DecodeWork(const DecodeWork &) = delete;
     DecodeWork &operator=(const DecodeWork &) = delete;

@@ -20,6 +20,9 @@ LIB_PATH = os.path.join(_HERE, "liblg.so")
 
 # -- constants of include/lg.h --------------------------------------------
 LG_OK, LG_ERR_INVALID, LG_ERR_OOM, LG_ERR_DEVICE, LG_ERR_UNSUPPORTED, LG_ERR_CAPACITY = range(6)
+# limits of lg_decode_neighbors_noalloc (include/lg.h)
+LG_NOALLOC_MAX_VERTICES = 65536
+LG_NOALLOC_MAX_SORTED_IDS = 1 << 20
 STATUS_NAMES = {0: "LG_OK", 1: "LG_ERR_INVALID", 2: "LG_ERR_OOM", 3: "LG_ERR_DEVICE",
                 4: "LG_ERR_UNSUPPORTED", 5: "LG_ERR_CAPACITY"}
 LAYOUTS = {"packed": 0, "plain": 1}
@@ -99,6 +102,8 @@ FUNCTIONS = {
                             C.POINTER(C.c_void_p)]),
     "lg_decode_neighbors": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint32, C.c_void_p, C.c_void_p, C.c_uint64,
                                       C.c_uint32, C.c_void_p]),
+    "lg_decode_neighbors_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint32, C.c_void_p, C.c_void_p,
+                                              C.c_uint64, C.c_uint32, C.c_void_p]),
     "lg_bfs": (C.c_int, [C.c_void_p, C.POINTER(C.c_uint32), C.c_uint32, C.c_void_p, C.c_void_p, C.c_int32,
                          C.c_uint32, C.c_void_p]),
     "lg_pagerank": (C.c_int, [C.c_void_p, C.c_float, C.c_uint32, C.c_void_p, C.c_void_p]),
@@ -298,6 +303,23 @@ def decode_neighbors(g: Graph, vertices: torch.Tensor, flags="sorted", cap: Opti
     ids = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
     _check(lib().lg_decode_neighbors(g.handle, vptr, k, off.data_ptr(), ids.data_ptr(), cap, DECODE_FLAGS[flags], s))
     return off, ids[: int(off[-1].item())]
+
+
+def decode_neighbors_noalloc(g: Graph, vertices: torch.Tensor, out_off: torch.Tensor, out_ids: torch.Tensor,
+                             flags="sorted", stream=None) -> int:
+    """lg_decode_neighbors_noalloc into caller-provided device tensors
+    (out_off int64[k+1], out_ids int32[cap]); returns the lg_status (LG_OK or
+    LG_ERR_CAPACITY) and raises on every other status."""
+    k = vertices.numel()
+    if out_off.numel() != k + 1:
+        raise ValueError("out_off must hold k + 1 entries")
+    vptr = _dev_ptr(vertices, torch.int32, "vertices") if k else None
+    st = lib().lg_decode_neighbors_noalloc(g.handle, vptr, k, _dev_ptr(out_off, torch.int64, "out_off"),
+                                           _dev_ptr(out_ids, torch.int32, "out_ids") if out_ids.numel() else None,
+                                           out_ids.numel(), DECODE_FLAGS[flags], _stream(stream))
+    if st not in (LG_OK, LG_ERR_CAPACITY):
+        _check(st)
+    return st
 
 
 def bfs(g: Graph, roots: Sequence[int], *, parent=True, max_depth=-1, mode="do", depth_out=None,
