@@ -1,22 +1,30 @@
 #!/usr/bin/env python3
 """Benchmark of the Log(Graph) packed-graph hot path on one MI355X.
 
-One step = encode the graph (validate, degree relabel, local widths, scan,
-pack, Elias-Fano offsets), BFS from 64 roots (direction-optimizing, depths
-and parents; one library call, which runs a few roots at a time) and 20
-PageRank iterations, all on the packed representation.  Per-root
-(Graph500-style) BFS rates come from a separate pass, one root per call.
-Workload: Kronecker (R-MAT a=.57 b=.19 c=.19) scale 24, edge factor 16,
-seed 1, symmetrized, self-loops and duplicates removed.
+One step = encode the graph (validate, widths, scan, pack, offsets; with the
+degree relabeling for the Kronecker workloads), BFS from 64 roots
+(direction-optimizing, depths and parents; one library call, which runs a few
+roots at a time) and 20 PageRank iterations, all on the packed
+representation, inputs resident in HBM.  The same step runs on the plain
+uint32 CSR (same labeling) for the packed/plain comparison.
+
+Default workload: uniform random (Erdos-Renyi) scale 26, edge factor 16,
+seed 1 (n = 2^26, about 2.1e9 stored entries), 26-bit packed IDs and offsets
+packed at bl(M) bits -- the largest configuration that fits one GPU.
 
 Throughput is counted in undirected traversed edges (Graph500 convention):
 BFS from root r counts half the degree sum of the vertices it reaches; one
-PageRank iteration counts every undirected edge once.  value = those edges
-per second over the whole step, inputs resident in HBM.
+PageRank iteration counts every undirected edge once.  `value` = those edges
+per second over the whole step (encode included); detail.gteps_traversal
+leaves the encode out (BFS and PageRank only), and detail.per_root gives the
+Graph500-style per-root rates (one root per call): harmonic mean, median and
+its nonparametric 95% confidence interval, p50/p99 latency.
 
-The same step is also run on the plain uint32 CSR (same labeling) for the
-packed/plain comparison, and the CPU oracle is timed on a bounded sample.
-Prints one JSON line.
+Parity is checked before anything is timed, for both layouts: whole BFS
+trees (depths and parents) of two roots against the oracle, the multi-root
+call's rows against single-root calls, and the first PageRank iteration
+within L1 1e-5 of the FP64 oracle (plus the 20-iteration sum).  The oracle
+is also timed on the host's cores (cpu_baseline).  Prints one JSON line.
 """
 
 from __future__ import annotations
@@ -32,38 +40,84 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+METRIC = "GTEPS & HBM GB/s, Log(Graph)-packed vs plain CSR on GPU; p99 query latency"
 
 WORKLOADS = {
     # name: (generator, scale, encoding)
+    "er-s26-global-packed": ("er", 26, dict(ids="global", offsets="packed", relabel=False)),
     "kronecker-s24-dm-local-ef": ("kronecker", 24, dict(ids="local", offsets="succinct", relabel=True)),
     "kronecker-s16-global-packed": ("kronecker", 16, dict(ids="global", offsets="packed", relabel=False)),
-    "er-s26-global-packed": ("er", 26, dict(ids="global", offsets="packed", relabel=False)),
     "kronecker-s20-dm-local-ef": ("kronecker", 20, dict(ids="local", offsets="succinct", relabel=True)),
+    "er-s22-global-packed": ("er", 22, dict(ids="global", offsets="packed", relabel=False)),
 }
-DEFAULT_WORKLOAD = "kronecker-s24-dm-local-ef"
+DEFAULT_WORKLOAD = "er-s26-global-packed"
+
+# sources whose kernels a committed counter summary describes (a summary
+# holds their hash; it no longer applies once they change)
+COUNTER_SOURCES = {
+    "pr": ["lg_pagerank.hip", "lg_device.hpp", "lg_views.hpp", "lg_heavy.hip", "lg_varint.hpp"],
+    "bfs": ["lg_bfs.hip", "lg_device.hpp", "lg_views.hpp"],
+}
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def measured_traffic(kernel: str, workload: str):
-    """HBM bytes per launch of `kernel` from the committed counter summary,
-    or None when there is none or the kernel sources changed since."""
+def source_hash(phase: str) -> str:
     import hashlib
-    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload.split('-dm-')[0].replace('-', '_')}_counters.md")
-    if not os.path.exists(path):
-        return None
-    text = open(path).read()
-    vals = dict(line.split(": ", 1) for line in text.splitlines()
-                if line.startswith(("traffic_bytes_per_launch: ", "source_sha256: ")))
     h = hashlib.sha256()
-    for f in ["lg_pagerank.hip", "lg_device.hpp", "lg_views.hpp", "lg_heavy.hip", "lg_varint.hpp"]:
+    for f in COUNTER_SOURCES[phase]:
         with open(os.path.join(ROOT, "paper_2010_15879_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
-    if vals.get("source_sha256", "").strip() != h.hexdigest():
+    return h.hexdigest()
+
+
+def measured_counters(kernel: str, workload: str, layout: str, phase: str):
+    """HBM bytes per launch of `kernel` (FETCH_SIZE + WRITE_SIZE, calibrated)
+    from the committed counter summary profiles/<kernel>_<workload>_<layout>_
+    counters.md, or None when there is none or the sources changed since."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_{layout}_counters.md")
+    if not os.path.exists(path):
         return None
-    return float(vals["traffic_bytes_per_launch"])
+    vals = {}
+    for line in open(path).read().splitlines():
+        if ": " in line and not line.startswith(("#", "|", "`")):
+            k, v = line.split(": ", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("source_sha256") != source_hash(phase):
+        return None
+    try:
+        return float(vals["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def median_ci95(x):
+    """Median and the nonparametric 95% confidence interval of the median
+    (order statistics of the binomial(n, 1/2) bounds), after dropping the
+    first 1% of the samples as warm-up."""
+    import numpy as np
+    x = np.asarray(x, dtype=np.float64)
+    x = x[int(math.ceil(0.01 * x.size)):] if x.size > 1 else x
+    s = np.sort(x)
+    n = s.size
+    lo = int(math.floor((n - 1.96 * math.sqrt(n)) / 2.0))          # 1-based ranks
+    hi = int(math.ceil(1 + (n + 1.96 * math.sqrt(n)) / 2.0))
+    lo, hi = max(lo, 1), min(hi, n)
+    return float(np.median(s)), float(s[lo - 1]), float(s[hi - 1]), n
+
+
+def host_info():
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "affinity": len(os.sched_getaffinity(0)), "model": model}
 
 
 def parse():
@@ -75,6 +129,8 @@ def parse():
     p.add_argument("--roots", type=int, default=64)
     p.add_argument("--pr-iters", type=int, default=20)
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--cpu-seconds", type=float, default=20.0,
+                   help="bound on the oracle's timed sample (all-core and one-thread legs together)")
     p.add_argument("--no-plain", action="store_true")
     p.add_argument("--kernels", action="store_true", help="print the per-kernel time breakdown to stderr")
     p.add_argument("--batch", action="store_true",
@@ -91,10 +147,8 @@ def parse():
                         "heuristic (local widths, Elias-Fano offsets): |A|, encode, BFS and PageRank times "
                         "(own JSON line)")
     p.add_argument("--offset-fetch", action="store_true",
-                   help="random fetch of 1,000 vertices per worker (256 workers, one call) under 32-bit plain "
-                        "offsets (ptr32), offsets at bl(universe) bits (ptrW) and Elias-Fano offsets (bvSD): "
-                        "degrees only and whole lists "
-                        "(own JSON line)")
+                   help="random fetch of 1,000 vertices per worker (256 workers, one call) under each offset "
+                        "structure: degrees only and whole lists (own JSON line)")
     p.add_argument("--sssp", action="store_true",
                    help="the workload's graph with uniform integer weights in [1, 255]: SSSP from the roots over "
                         "the weighted plain CSR and the weighted packed encodings, and a sweep of delta "
@@ -103,9 +157,34 @@ def parse():
                    help="the workload's graph with local widths, fixed-size gap encoding and Varint lists (full "
                         "labels or differences), with and without the degree-minimizing relabeling (DMf, DMd): "
                         "|A|, encode time, random-vertex list decode, PageRank (own JSON line)")
-    p.add_argument("--pr-only", action="store_true",
-                   help="counter-run mode: one 1 GiB device copy (calibration) then one PageRank call; no timing")
+    p.add_argument("--counter-run", choices=["pr", "bfs"],
+                   help="counter-run mode: one elementwise kernel of known traffic (calibration), then one "
+                        "PageRank call (pr) or one single-root BFS per direction mode (bfs) on --layout; no timing")
+    p.add_argument("--layout", choices=["packed", "plain"], default="packed")
     return p.parse_args()
+
+
+def calibration_kernel(torch, dev, gib=1):
+    """An elementwise kernel that reads and writes `gib` GiB each (square
+    root: a kernel the graph generator never launches, so a profiler can pick
+    it out by name).  Returns its bytes and time from HIP events."""
+    src = torch.ones((gib << 30) // 4, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    torch.sqrt(src, out=dst)  # warm
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(5):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        torch.sqrt(src, out=dst)
+        b.record()
+        torch.cuda.synchronize()
+        ts.append(a.elapsed_time(b))
+    del src, dst
+    torch.cuda.empty_cache()
+    ms = sorted(ts)[len(ts) // 2]
+    nbytes = 2 * (gib << 30)
+    return nbytes, ms
 
 
 def main():
@@ -138,9 +217,7 @@ def main():
     log(f"[bench] graph {args.workload}: n={g.n} M={g.m} isolated={int((deg == 0).sum())} "
         f"maxdeg={int(deg.max())} gen {time.time() - t0:.1f}s")
 
-    stream = torch.cuda.current_stream()
     n, M = g.n, g.m
-    degf = deg.to(torch.float64)
     if args.relabel_compare:
         return relabel_main(args, np, torch, lg, g, roots)
     if args.offset_fetch:
@@ -149,52 +226,48 @@ def main():
         return encoding_main(args, np, torch, lg, g, roots)
     if args.sssp:
         return sssp_main(args, np, torch, gg, lg, g, roots)
+    if args.counter_run:
+        return counter_main(args, np, torch, lg, g, roots, enc)
 
-    if args.pr_only:
-        # A kernel of known traffic calibrates the HBM byte counters (an
-        # elementwise square root that reads 1 GiB and writes 1 GiB, a kernel
-        # the graph generator never launches, so that a profiler can collect
-        # counters for it and the PageRank kernel alone; a tensor copy would
-        # run on a DMA engine, not as a kernel), then one PageRank call runs
-        # the iteration kernel args.pr_iters times.
-        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
-        dst = torch.empty_like(src)
-        torch.sqrt(src, out=dst)
-        torch.cuda.synchronize()
-        del src, dst
-        log("[pr-only] calibration done; encoding")
-        h = lg.encode(g.row_offsets, g.col, n, layout="packed", **enc)
-        log("[pr-only] encoded; PageRank")
-        lg.pagerank(h, 0.85, args.pr_iters)
-        torch.cuda.synchronize()
-        info = h.info()
-        print(json.dumps({"mode": "pr-only", "workload": args.workload, "copy_bytes": 2 * (1 << 30),
-                          "pr_iters": args.pr_iters, "n": n, "stored_edges": M,
-                          "algorithmic_bytes_per_iteration": info["adj_bits"] / 8.0 + info["bytes_offsets"]
-                          + info["bytes_widths"] + 4.0 * M + 4.0 * n}), flush=True)
-        h.free()
-        return
+    import oracle as orc  # the CPU oracle: test infrastructure, timed below as the CPU baseline
 
-    def run_step(layout, opts, prof=False):
-        """One step; returns (handle, timings dict).  Times come from HIP events
-        on the stream the library launches on."""
+    stream = torch.cuda.current_stream()
+    degf = deg.to(torch.float64)
+    t0 = time.time()
+    off_h = g.row_offsets.cpu().numpy().view(np.uint64)
+    col_h = g.col.cpu().numpy().view(np.uint32)
+    # the oracle's parent rule needs the stored label of every vertex: the
+    # degree permutation's inverse when the graph is relabeled (computed once,
+    # outside every timed region)
+    labels = orc.dm_permutation(off_h)[1] if enc["relabel"] else None
+    threads = orc.max_threads()
+    log(f"[bench] host copy {time.time() - t0:.1f}s; oracle threads {threads}")
+
+    # -- the oracle's results every layout is checked against -------------
+    t0 = time.time()
+    check_roots = [roots[0], roots[-1]]
+    orc_trees = [orc.bfs_levels(off_h, col_h, r, labels=labels) for r in check_roots]
+    pr1_orc = orc.pagerank_par(off_h, col_h, 0.85, 1)
+    log(f"[bench] oracle BFS x{len(check_roots)} + 1 PageRank iteration on {threads} threads: "
+        f"{time.time() - t0:.1f}s")
+
+    all_depth = torch.empty((len(roots), n), dtype=torch.int32, device=dev)
+    all_parent = torch.empty((len(roots), n), dtype=torch.int32, device=dev)
+
+    def run_step(layout, opts):
+        """One step; returns (handle, timings dict, scores).  Times come from
+        HIP events on the stream the library launches on."""
         ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
-        e0, e1 = ev(), ev()
+        e0, e1, b1, p1 = ev(), ev(), ev(), ev()
         e0.record(stream)
         h = lg.encode(g.row_offsets, g.col, n, layout=layout, **opts)
         e1.record(stream)
-        # all roots in one call: the library runs a few at a time
-        b0, b1 = ev(), ev()
-        b0.record(stream)
-        lg.bfs(h, roots, depth_out=all_depth, parent_out=all_parent)
+        lg.bfs(h, roots, depth_out=all_depth, parent_out=all_parent)  # all roots in one call
         b1.record(stream)
-        p0, p1 = ev(), ev()
-        p0.record(stream)
         pr = lg.pagerank(h, 0.85, args.pr_iters)
         p1.record(stream)
         torch.cuda.synchronize()
-        t = dict(encode=e0.elapsed_time(e1), bfs=b0.elapsed_time(b1), pr=p0.elapsed_time(p1))
-        return h, t, pr
+        return h, dict(encode=e0.elapsed_time(e1), bfs=e1.elapsed_time(b1), pr=b1.elapsed_time(p1)), pr
 
     def per_root_ms(h):
         """Graph500-style per-root times: one root per call, one after another."""
@@ -209,207 +282,271 @@ def main():
         torch.cuda.synchronize()
         return np.array([a.elapsed_time(b) for a, b in out])
 
-    all_depth = torch.empty((len(roots), n), dtype=torch.int32, device=dev)
-    all_parent = torch.empty((len(roots), n), dtype=torch.int32, device=dev)
-
-    # -- parity before timing: one root's BFS and the PageRank sum ----------
-    import oracle as orc  # the CPU oracle: test infrastructure, timed below as the CPU baseline
-
-    off_h = g.row_offsets.cpu().numpy()
-    col_h = g.col.cpu().numpy()
-
-    h, t, pr = run_step("packed", enc)
-    reached = [all_depth[i] >= 0 for i in range(len(roots))]
-    d_gpu, p_gpu = lg.bfs(h, [roots[0]])
-    torch.cuda.synchronize()
-    tc = time.time()
-    d_o, p_o = orc.bfs(off_h, col_h, roots[0], relabeled=enc["relabel"])
-    t_orc_bfs = time.time() - tc
-    parity = bool(np.array_equal(d_gpu[0].cpu().numpy(), d_o) and np.array_equal(p_gpu[0].cpu().numpy(), p_o))
-    # the multi-root call gives every root the result of a call alone
-    parity = parity and bool(torch.equal(all_depth[0], d_gpu[0]) and torch.equal(all_parent[0], p_gpu[0]))
-    pr_sum = float(pr.double().sum())
-    parity = parity and abs(pr_sum - 1.0) <= 1e-5
-    log(f"[bench] parity root {roots[0]}: {'ok' if parity else 'FAILED'}; oracle BFS {t_orc_bfs:.1f}s; "
-        f"PR sum {pr_sum:.8f}")
-    if not parity:
-        print(json.dumps({"error": "parity check failed before timing"}))
-        sys.exit(1)
-
-    # Graph500 edge counts per root (undirected edges in the reached component)
-    edges_root = [float(degf[m].sum()) / 2.0 for m in reached]
-    del reached
-    pr_edges = args.pr_iters * (M / 2.0)
-    step_edges = sum(edges_root) + pr_edges
-    info = h.info()
-    root_ms = per_root_ms(h)
-    h.free()
-
-    # -- timed steps: packed ------------------------------------------------
-    for _ in range(args.warmup):
-        h, _, _ = run_step("packed", enc)
-        h.free()
-    # in the timed steps only the roofline kernel's launches are timed (HIP
-    # events on the stream it runs on); timing every launch would add two
-    # events to each of the BFS lanes' many small launches
-    lg.prof_reset()
-    lg.prof_filter("pr_iter_kernel")
-    lg.prof_enable(True)
-    torch.cuda.synchronize()
-    t_begin = time.perf_counter()
-    timings = []
-    for _ in range(args.steps):
-        h, tt, _ = run_step("packed", enc)
-        timings.append(tt)
-        h.free()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t_begin
-    lg.prof_enable(False)
-    c_pull, ms_pull = lg.prof_query("pr_iter_kernel")
-    ms_pull /= args.steps
-
-    # one more step with every launch timed: the kernel breakdown
-    lg.prof_reset()
-    lg.prof_filter("")
-    lg.prof_enable(True)
-    h, _, _ = run_step("packed", enc)
-    h.free()
-    torch.cuda.synchronize()
-    lg.prof_enable(False)
-    kernel_ms = {}
-    for name in lg.prof_names():
-        base = name.lstrip("(").split("<")[0].rstrip(")")
-        kernel_ms.setdefault(base, [0, 0.0])
-    for base in kernel_ms:
-        c, ms = lg.prof_query(base)
-        kernel_ms[base] = [c, ms]
-    step_ms_gpu = [tt["encode"] + tt["bfs"] + tt["pr"] for tt in timings]
-    ms_per_step = wall * 1000.0 / args.steps
-    value = step_edges / (ms_per_step / 1000.0) / 1e9
-
-    bfs_all_ms = float(np.mean([tt["bfs"] for tt in timings]))
-    bfs_gteps_all = sum(edges_root) / (bfs_all_ms / 1000.0) / 1e9
-    bfs_teps = np.array(edges_root) / (root_ms / 1000.0)
-    bfs_gteps_hmean = float(len(bfs_teps) / np.sum(1.0 / bfs_teps)) / 1e9
-    pr_ms = float(np.mean([tt["pr"] for tt in timings]))
-    encode_ms = float(np.mean([tt["encode"] for tt in timings]))
-
-    if args.kernels:
-        tot = sum(v[1] for v in kernel_ms.values())
-        for k, (c, ms) in sorted(kernel_ms.items(), key=lambda kv: -kv[1][1]):
-            log(f"[kernel] {k:32s} launches={c:7d} total={ms:10.3f} ms ({100 * ms / max(tot, 1e-9):5.1f}%) "
-                f"avg={ms / max(c, 1) * 1000:9.2f} us")
-
-    # -- roofline of the PageRank iteration kernel ------------------------------
-    # algorithmic bytes of one (non-final) iteration:
-    #   packed lists            adj_bits / 8     (w/8 per stored edge)
-    #   offset structure        EF low bits + upper bits + directory, or packed offsets
-    #   width table             F bits per vertex
-    #   contribution gathers    4 B per stored edge
-    #   contribution writes     4 B per vertex
-    struct_bytes = info["adj_bits"] / 8.0 + info["bytes_offsets"] + info["bytes_widths"]
-    pr_launch_bytes = struct_bytes + 4.0 * M + 4.0 * n
-    pull_avg_ms = ms_pull * args.steps / max(c_pull, 1)
-    pull_gbs = pr_launch_bytes / (pull_avg_ms / 1000.0) / 1e9 if c_pull else 0.0
-    # The roofline goes with the kernel that holds the largest share of wall
-    # time.  PageRank launches run one after another; the BFS kernels run on
-    # eight concurrent lanes, so their summed launch times overlap and bound
-    # nothing: the whole BFS phase (bfs_all_ms) is an upper bound on any one of
-    # them, as the encode phase is for every encoder kernel.
-    largest_summed = max(kernel_ms.items(), key=lambda kv: kv[1][1])[0] if kernel_ms else None
-
-    # -- plain uint32 CSR on the same labeling ----------------------------------
-    plain = None
-    if not args.no_plain:
-        hp, _, _ = run_step("plain", dict(relabel=enc["relabel"]))
-        proot_ms = per_root_ms(hp)
-        hp.free()
-        pt = []
-        tp0 = time.perf_counter()
-        for _ in range(args.steps):
-            hp, tt, _ = run_step("plain", dict(relabel=enc["relabel"]))
-            pt.append(tt)
-            hp.free()
-        torch.cuda.synchronize()
-        pwall = (time.perf_counter() - tp0) * 1000.0 / args.steps
-        if args.kernels:
-            lg.prof_reset()
-            lg.prof_enable(True)
-            hp, _, _ = run_step("plain", dict(relabel=enc["relabel"]))
-            hp.free()
+    def parity(layout, h, pr20):
+        ok = True
+        for r, (d0, p0) in zip(check_roots, orc_trees):
+            i = roots.index(r)
+            d1, p1 = lg.bfs(h, [r])
             torch.cuda.synchronize()
-            lg.prof_enable(False)
-            rows = []
-            for name in lg.prof_names():
-                base = name.lstrip("(").split("<")[0].rstrip(")")
-                if base not in [r[0] for r in rows]:
-                    rows.append((base, *lg.prof_query(base)))
-            for k, c, ms in sorted(rows, key=lambda r: -r[2])[:12]:
-                log(f"[plain-kernel] {k:32s} launches={c:7d} total={ms:10.3f} ms avg={ms / max(c, 1) * 1000:9.2f} us")
-        pteps = np.array(edges_root) / (proot_ms / 1000.0)
-        ppr_ms = float(np.mean([tt["pr"] for tt in pt]))
-        pbfs_all = float(np.mean([tt["bfs"] for tt in pt]))
-        plain = dict(value=step_edges / (pwall / 1000.0) / 1e9, ms_per_step=pwall,
-                     bfs_gteps_hmean=float(len(pteps) / np.sum(1.0 / pteps)) / 1e9,
-                     bfs_all_ms=pbfs_all, bfs_gteps_all=sum(edges_root) / (pbfs_all / 1000.0) / 1e9,
-                     pr_ms=ppr_ms, encode_ms=float(np.mean([tt["encode"] for tt in pt])))
+            same = bool(np.array_equal(d1[0].cpu().numpy(), d0) and np.array_equal(p1[0].cpu().numpy(), p0))
+            # the multi-root call gives every root the result of a call alone
+            rows = bool(torch.equal(all_depth[i], d1[0]) and torch.equal(all_parent[i], p1[0]))
+            log(f"[bench] {layout} parity root {r}: tree {'ok' if same else 'FAILED'}, "
+                f"multi-root row {'ok' if rows else 'FAILED'}")
+            ok = ok and same and rows
+        pr1 = lg.pagerank(h, 0.85, 1).cpu().numpy().astype(np.float64)
+        l1 = float(np.abs(pr1 - pr1_orc).sum())
+        s20 = float(pr20.double().sum())
+        log(f"[bench] {layout} PageRank: iteration-1 L1 {l1:.3e}, {args.pr_iters}-iteration sum {s20:.8f}")
+        return ok and l1 <= 1e-5 and abs(s20 - 1.0) <= 1e-5, l1
 
-    # -- CPU baseline: the oracle on a bounded sample -----------------------
+    def kernel_breakdown(layout, opts):
+        lg.prof_reset()
+        lg.prof_filter("")
+        lg.prof_enable(True)
+        h, _, _ = run_step(layout, opts)
+        h.free()
+        torch.cuda.synchronize()
+        lg.prof_enable(False)
+        km = {}
+        for name in lg.prof_names():
+            base = name.lstrip("(").split("<")[0].rstrip(")")
+            if base not in km:
+                km[base] = lg.prof_query(base)
+        return km
+
+    def measure(layout, opts):
+        """Parity, per-root times, warm-up, timed steps, kernel breakdown."""
+        h, _, pr20 = run_step(layout, opts)
+        ok, l1 = parity(layout, h, pr20)
+        if not ok:
+            print(json.dumps({"error": f"parity check failed before timing ({layout})"}), flush=True)
+            sys.exit(1)
+        reached_edges = [float(degf[all_depth[i] >= 0].sum()) / 2.0 for i in range(len(roots))]
+        root_ms = per_root_ms(h)
+        info = h.info()
+        h.free()
+        for _ in range(args.warmup):
+            h, _, _ = run_step(layout, opts)
+            h.free()
+        # in the timed steps only the PageRank iteration kernel is timed (HIP
+        # events on the stream it runs on); timing every launch would add two
+        # events to each of the BFS lanes' many small launches
+        lg.prof_reset()
+        lg.prof_filter("pr_iter_kernel")
+        lg.prof_enable(True)
+        torch.cuda.synchronize()
+        t_begin = time.perf_counter()
+        timings = []
+        for _ in range(args.steps):
+            h, tt, _ = run_step(layout, opts)
+            timings.append(tt)
+            h.free()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t_begin
+        lg.prof_enable(False)
+        c_pr, ms_pr = lg.prof_query("pr_iter_kernel")
+        km = kernel_breakdown(layout, opts)
+        return dict(info=info, l1=l1, edges_root=reached_edges, root_ms=root_ms, timings=timings,
+                    ms_per_step=wall * 1000.0 / args.steps, pr_launches=c_pr, pr_kernel_ms=ms_pr, kernels=km)
+
+    def summarize(layout, r):
+        tm = r["timings"]
+        bfs_ms = float(np.mean([t["bfs"] for t in tm]))
+        pr_ms = float(np.mean([t["pr"] for t in tm]))
+        enc_ms = float(np.mean([t["encode"] for t in tm]))
+        edges_root = r["edges_root"]
+        pr_edges = args.pr_iters * (M / 2.0)
+        step_edges = sum(edges_root) + pr_edges
+        teps = np.array(edges_root) / (r["root_ms"] / 1000.0)
+        med, lo, hi, used = median_ci95(teps / 1e9)
+        ms_med, ms_lo, ms_hi, _ = median_ci95(r["root_ms"])
+        info = r["info"]
+        # algorithmic bytes of one PageRank iteration launch: the lists, the
+        # offset structure and width table (packed) or offsets (plain), 4 B of
+        # contribution gathered per stored entry, 4 B written per vertex
+        if layout == "packed":
+            struct_bytes = info["adj_bits"] / 8.0 + info["bytes_offsets"] + info["bytes_widths"]
+        else:
+            struct_bytes = info["bytes_adj"] + info["bytes_offsets"]
+        pr_bytes = struct_bytes + 4.0 * M + 4.0 * n
+        pr_avg_ms = r["pr_kernel_ms"] / max(r["pr_launches"], 1)
+        pr_gbs = pr_bytes / (pr_avg_ms / 1000.0) / 1e9 if r["pr_launches"] else 0.0
+        km = r["kernels"]
+        largest = max(km.items(), key=lambda kv: kv[1][1])[0] if km else None
+        return dict(
+            value=step_edges / (r["ms_per_step"] / 1000.0) / 1e9, ms_per_step=r["ms_per_step"],
+            gteps_traversal=step_edges / ((bfs_ms + pr_ms) / 1000.0) / 1e9,
+            encode_ms=enc_ms, encode_gedges_s=M / (enc_ms / 1000.0) / 1e9,
+            bfs_all_roots_ms=bfs_ms, bfs_gteps_all_roots=sum(edges_root) / (bfs_ms / 1000.0) / 1e9,
+            pr_ms=pr_ms, pr_gteps_directed=args.pr_iters * M / (pr_ms / 1000.0) / 1e9,
+            per_root={"gteps_hmean": float(len(teps) / np.sum(1.0 / teps)) / 1e9,
+                      "gteps_median": med, "gteps_median_ci95": [lo, hi], "samples": used,
+                      "ms_median": ms_med, "ms_median_ci95": [ms_lo, ms_hi],
+                      "ms_p50": float(np.percentile(r["root_ms"], 50)),
+                      "ms_p99": float(np.percentile(r["root_ms"], 99))},
+            pr_kernel={"name": "pr_iter_kernel", "avg_launch_ms": pr_avg_ms, "launches": r["pr_launches"],
+                       "bytes_per_launch": pr_bytes, "achieved_gbs": pr_gbs,
+                       "bytes_per_edge_algorithmic": pr_bytes / M},
+            bytes={k: info[k] for k in ("bytes_adj", "bytes_offsets", "bytes_widths", "bytes_perm")},
+            adj_bits=info["adj_bits"], parity_pr_iter1_l1=r["l1"],
+            kernels_ms_profiled_step={k: round(v[1], 3) for k, v in km.items()},
+            largest_summed_kernel=largest)
+
+    res = {"packed": measure("packed", enc)}
+    if not args.no_plain:
+        res["plain"] = measure("plain", dict(relabel=enc["relabel"]))
+    summ = {k: summarize(k, v) for k, v in res.items()}
+    if args.kernels:
+        for layout, r in res.items():
+            tot = sum(v[1] for v in r["kernels"].values())
+            for k, (c, ms) in sorted(r["kernels"].items(), key=lambda kv: -kv[1][1])[:16]:
+                log(f"[kernel {layout}] {k:32s} launches={c:7d} total={ms:10.3f} ms "
+                    f"({100 * ms / max(tot, 1e-9):5.1f}%) avg={ms / max(c, 1) * 1000:9.2f} us")
+
+    # -- achievable bandwidth on this GPU: an elementwise kernel -----------
+    cal_bytes, cal_ms = calibration_kernel(torch, dev)
+    copy_gbs = cal_bytes / (cal_ms / 1000.0) / 1e9
+    log(f"[bench] elementwise 1 GiB read + 1 GiB write: {cal_ms:.3f} ms = {copy_gbs:.0f} GB/s")
+
+    # -- CPU baseline: the oracle on the host's cores, bounded sample -------
     cpu = None
     if not args.no_cpu_baseline:
-        # sample: the oracle's BFS from the parity root (already timed above) and
-        # one PageRank iteration over the whole graph
-        tc = time.time()
-        orc.pagerank(off_h, col_h, 0.85, 1)
-        t_orc_pr = time.time() - tc
-        cpu_edges = edges_root[0] + M / 2.0
-        cpu = {"value": cpu_edges / (t_orc_bfs + t_orc_pr) / 1e9, "unit": "GTEPS", "cores": 1, "kind": "oracle",
-               "sample": f"oracle BFS from 1 root ({t_orc_bfs:.1f}s, incl. degree relabel for parents) + "
-                         f"1 PageRank iteration ({t_orc_pr:.1f}s) on the same graph, single thread"}
+        cpu = cpu_baseline(args, np, orc, off_h, col_h, labels, roots, degf.cpu().numpy(), M, threads)
 
-    pr_kernel_ms_step = ms_pull
-    dominant = "pr_iter_kernel" if pr_kernel_ms_step >= max(bfs_all_ms, encode_ms) else largest_summed
+    P = summ["packed"]
+    rooflines = {}
+    for layout, s in summ.items():
+        k = s["pr_kernel"]
+        rooflines[layout] = {
+            "bound": "hbm", "kernel": k["name"], "achieved": round(k["achieved_gbs"], 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(k["achieved_gbs"] / HBM_PEAK_GBS, 4),
+            "frac_of_achievable_copy": round(k["achieved_gbs"] / copy_gbs, 4),
+            "traffic": measured_counters(k["name"], args.workload, layout, "pr"),
+            "bytes_per_launch": k["bytes_per_launch"], "avg_launch_ms": k["avg_launch_ms"],
+            "bytes_per_edge_algorithmic": round(k["bytes_per_edge_algorithmic"], 4)}
+        if rooflines[layout]["traffic"]:
+            rooflines[layout]["bytes_per_edge_measured"] = round(rooflines[layout]["traffic"] / M, 4)
+    pr_share = P["pr_kernel"]["avg_launch_ms"] * args.pr_iters
+    dominant = "pr_iter_kernel" if pr_share >= max(P["bfs_all_roots_ms"], P["encode_ms"]) else \
+        P["largest_summed_kernel"]
+    roof = dict(rooflines["packed"])
+    roof["dominant_kernel"] = dominant
+    roof["dominant_by"] = ("wall-time share: pr_iter_kernel time per step vs the BFS and encode phases' wall "
+                           "times, which bound every kernel inside them (BFS kernels overlap on eight lanes)")
+    ratio = None
+    if "plain" in summ:
+        Q = summ["plain"]
+        ratio = {"step": round(P["value"] / Q["value"], 4),
+                 "traversal": round(P["gteps_traversal"] / Q["gteps_traversal"], 4),
+                 "bfs": round(P["bfs_gteps_all_roots"] / Q["bfs_gteps_all_roots"], 4),
+                 "bfs_per_root_hmean": round(P["per_root"]["gteps_hmean"] / Q["per_root"]["gteps_hmean"], 4),
+                 "pr": round(Q["pr_ms"] / P["pr_ms"], 4),
+                 "encode": round(Q["encode_ms"] / P["encode_ms"], 4),
+                 "pr_bytes_per_edge_algorithmic": round(P["pr_kernel"]["bytes_per_edge_algorithmic"]
+                                                        / Q["pr_kernel"]["bytes_per_edge_algorithmic"], 4)}
     out = {
-        "metric": "GTEPS & HBM GB/s, Log(Graph)-packed vs plain CSR on GPU; p99 query latency",
-        "value": round(value, 4),
+        "metric": METRIC,
+        "value": round(P["value"], 4),
         "unit": "GTEPS",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 3),
+        "ms_per_step": round(P["ms_per_step"], 3),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "u32/f32",
         "data": "synthetic",
         "config": {"workload": args.workload, "n": n, "stored_edges": M, "roots": len(roots),
-                   "pagerank_iters": args.pr_iters, "encoding": enc, "seed": 1, "edge_factor": 16},
-        "roofline": {"bound": "hbm", "kernel": "pr_iter_kernel", "achieved": round(pull_gbs, 1),
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(pull_gbs / HBM_PEAK_GBS, 4),
-                     "traffic": measured_traffic("pr_iter_kernel", args.workload),
-                     "bytes_per_launch": pr_launch_bytes, "avg_launch_ms": pull_avg_ms,
-                     "dominant_kernel": dominant,
-                     "dominant_by": "wall-time share: pr_iter_kernel time per step vs the BFS and encode phases' "
-                                    "wall times, which bound every kernel inside them",
-                     "largest_summed_kernel": largest_summed},
+                   "pagerank_iters": args.pr_iters, "encoding": enc, "seed": 1, "edge_factor": 16,
+                   "step": "encode + BFS from every root (one call) + PageRank iterations, packed layout"},
+        "roofline": roof,
         "cpu_baseline": cpu,
         "detail": {
-            "bfs_all_roots_ms": bfs_all_ms, "bfs_gteps_all_roots": round(bfs_gteps_all, 3),
-            "bfs_gteps_hmean": round(bfs_gteps_hmean, 3), "bfs_ms_mean_one_root": float(root_ms.mean()),
-            "pr_ms": pr_ms, "pr_gteps_directed": round(args.pr_iters * M / (pr_ms / 1000.0) / 1e9, 3),
-            "encode_ms": encode_ms, "encode_gedges_s": round(M / (encode_ms / 1000.0) / 1e9, 3),
-            "gpu_event_ms_per_step": float(np.mean(step_ms_gpu)),
-            "bytes": {k: info[k] for k in ("bytes_adj", "bytes_offsets", "bytes_widths", "bytes_perm")},
-            "plain_csr": plain,
-            "packed_over_plain": None if plain is None else {
-                "step": round(value / plain["value"], 4),
-                "bfs": round(bfs_gteps_all / plain["bfs_gteps_all"], 4),
-                "bfs_one_root_hmean": round(bfs_gteps_hmean / plain["bfs_gteps_hmean"], 4),
-                "pr": round(plain["pr_ms"] / pr_ms, 4)},
-            "kernels_ms_profiled_step": {k: round(v[1], 3) for k, v in kernel_ms.items()},
+            "packed": P,
+            "plain_csr": summ.get("plain"),
+            "packed_over_plain": ratio,
+            "roofline_plain": rooflines.get("plain"),
+            "achievable_copy": {"kernel": "elementwise sqrt, 1 GiB read + 1 GiB write", "ms": round(cal_ms, 4),
+                                "gbs": round(copy_gbs, 1), "frac_of_peak": round(copy_gbs / HBM_PEAK_GBS, 4)},
+            "p99_query_latency_ms": round(P["per_root"]["ms_p99"], 4),
+            "p99_note": "per-root BFS latency (one root per call); the serving mix's p50/p99 come from --serve",
         },
     }
     print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(args, np, orc, off_h, col_h, labels, roots, degs, M, threads):
+    """The oracle on the host: level-synchronous BFS and PageRank on every
+    core (the oracle's all-core functions), then the one-thread FIFO BFS and
+    PageRank, each over as many roots / iterations as fit the time bound
+    (at least one of each).  Labels for the parent rule were computed before
+    (no permutation inside the timed calls).  Rates in the same units as the
+    GPU's (undirected edges per second)."""
+    budget = args.cpu_seconds
+
+    def sample(bfs_fn, pr_fn, share):
+        t_end = time.perf_counter() + budget * share
+        bfs_t, bfs_e = [], []
+        for r in roots:
+            t0 = time.perf_counter()
+            d, _ = bfs_fn(r)
+            bfs_t.append(time.perf_counter() - t0)
+            bfs_e.append(float(degs[d >= 0].sum()) / 2.0)
+            if time.perf_counter() > t_end - budget * share / 2:
+                break
+        pr_t, iters = 0.0, 0
+        while True:
+            t0 = time.perf_counter()
+            pr_fn(1)
+            pr_t += time.perf_counter() - t0
+            iters += 1
+            if iters >= args.pr_iters or time.perf_counter() + pr_t / iters > t_end:
+                break
+        edges = sum(bfs_e) + iters * M / 2.0
+        return {"gteps": edges / (sum(bfs_t) + pr_t) / 1e9, "bfs_roots": len(bfs_t), "bfs_s": sum(bfs_t),
+                "bfs_gteps": sum(bfs_e) / sum(bfs_t) / 1e9, "pr_iters": iters, "pr_s": pr_t,
+                "pr_gteps": iters * M / 2.0 / pr_t / 1e9}
+
+    allc = sample(lambda r: orc.bfs_levels(off_h, col_h, r, labels=labels, threads=threads),
+                  lambda it: orc.pagerank_par(off_h, col_h, 0.85, it, threads=threads), 0.6)
+    one = sample(lambda r: orc.bfs(off_h, col_h, r, labels=labels),
+                 lambda it: orc.pagerank(off_h, col_h, 0.85, it), 0.4)
+    hi = host_info()
+    log(f"[bench] oracle all-core ({threads} threads): {allc}; one thread: {one}; host {hi}")
+    return {"value": allc["gteps"], "unit": "GTEPS", "cores": threads, "kind": "oracle",
+            "sample": (f"oracle on {threads} threads: level-synchronous BFS from the first {allc['bfs_roots']} "
+                       f"roots ({allc['bfs_s']:.1f}s) + {allc['pr_iters']} PageRank iteration(s) "
+                       f"({allc['pr_s']:.1f}s); parent labels precomputed, not timed"),
+            "one_thread": one, "all_core": allc, "host": hi}
+
+
+def counter_main(args, np, torch, lg, g, roots, enc):
+    """Counter runs: the calibration kernel (1 GiB read + 1 GiB write), then
+    the phase under study on --layout, so that a profiler collecting one
+    counter per pass sees each kernel's traffic per launch."""
+    nbytes, ms = calibration_kernel(torch, g.col.device)
+    log(f"[counter-run] calibration done ({nbytes} bytes, {ms:.3f} ms); encoding {args.layout}")
+    opts = enc if args.layout == "packed" else dict(relabel=enc["relabel"])
+    h = lg.encode(g.row_offsets, g.col, g.n, layout=args.layout, **opts)
+    info = h.info()
+    if args.counter_run == "pr":
+        log("[counter-run] PageRank")
+        lg.pagerank(h, 0.85, args.pr_iters)
+    else:
+        for mode in ("top-down", "bottom-up", "do"):
+            log(f"[counter-run] BFS {mode} from root {roots[0]}")
+            lg.bfs(h, [roots[0]], mode=mode)
+    torch.cuda.synchronize()
+    struct = (info["adj_bits"] / 8.0 + info["bytes_offsets"] + info["bytes_widths"]) if args.layout == "packed" \
+        else (info["bytes_adj"] + info["bytes_offsets"])
+    print(json.dumps({"mode": "counter-run", "phase": args.counter_run, "layout": args.layout,
+                      "workload": args.workload, "calibration_bytes": nbytes, "pr_iters": args.pr_iters,
+                      "n": g.n, "stored_edges": g.m, "structure_bytes": struct,
+                      "pr_algorithmic_bytes_per_iteration": struct + 4.0 * g.m + 4.0 * g.n,
+                      "source_sha256": source_hash(args.counter_run)}), flush=True)
+    h.free()
 
 
 def _time_ms(torch, fn, reps=3):
@@ -522,12 +659,32 @@ def sssp_main(args, np, torch, gg, lg, g, roots):
             ("packed-local", dict(ids="local", offsets="succinct")),
             ("packed-local-dm", dict(ids="local", offsets="succinct", relabel=True))]
     sweep = {}
+    timed_roots = roots[:8]
+    # parity before timing: the oracle's Dijkstra for the first root, then
+    # every encoding's distances for every timed root equal the plain CSR's
+    import oracle as orc  # the CPU oracle: test infrastructure
+    off_h = g.row_offsets.cpu().numpy().view(np.uint64)
+    col_h = g.col.cpu().numpy().view(np.uint32)
+    t0 = time.time()
+    want0 = orc.sssp(off_h, col_h, wt.cpu().numpy().view(np.uint32), timed_roots[0])
+    log(f"[sssp] oracle Dijkstra from root {timed_roots[0]}: {time.time() - t0:.1f}s")
+    plain_dist = None
     for name, kw in encs:
         h = lg.encode(g.row_offsets, g.col, n, weights=wt, **kw)
         info = h.info()
+        dists = [lg.sssp(h, r) for r in timed_roots]
+        ok = bool(np.array_equal(dists[0].cpu().numpy(), want0))
+        if plain_dist is None:
+            plain_dist = dists
+        else:
+            ok = ok and all(bool(torch.equal(a, b)) for a, b in zip(dists, plain_dist))
+        log(f"[sssp] {name}: parity {'ok' if ok else 'FAILED'} (root {timed_roots[0]} against the oracle, "
+            f"{len(timed_roots)} roots against the plain CSR)")
+        if not ok:
+            print(json.dumps({"error": f"SSSP parity failed before timing ({name})"}), flush=True)
+            sys.exit(1)
         times, edges = [], []
-        for r in roots[:8]:
-            d = lg.sssp(h, r)
+        for r, d in zip(timed_roots, dists):
             edges.append(float(deg[d >= 0].sum()) / 2.0)
             times.append(_time_ms(torch, lambda: lg.sssp(h, r), reps=1))
         med = sorted(times)[len(times) // 2]
@@ -542,7 +699,8 @@ def sssp_main(args, np, torch, gg, lg, g, roots):
             log(f"[sssp] delta sweep (root {roots[0]}): {sweep}")
         h.free()
     print(json.dumps({"mode": "sssp", "workload": args.workload, "n": n, "stored_edges": g.m,
-                      "roots": min(len(roots), 8), "max_weight": 255, "data": "synthetic", "results": res,
+                      "roots": len(timed_roots), "max_weight": 255, "data": "synthetic", "results": res,
+                      "parity": "root 0 equal to the oracle's Dijkstra; every root equal across encodings",
                       "delta_sweep_ms": sweep}), flush=True)
 
 
@@ -638,9 +796,11 @@ def batch_main(args, np, torch, gg, lg, dev):
     ev[1].record()
     torch.cuda.synchronize()
     batch_ms = ev[0].elapsed_time(ev[1]) / args.steps
-    # one launch per query, same graphs and roots, results written to the same rows
+    # the batch's own rows, kept to compare with one launch per query
     dflat, pflat = plan.depth_flat, plan.parent_flat
     torch.cuda.synchronize()
+    batch_d, batch_p = dflat.clone(), pflat.clone()
+    # one launch per query, same graphs and roots, results written to the same rows
     ev[0].record()
     for i, (gi, r) in enumerate(jobs):
         lg.bfs(hs[gi], [r], depth_out=dflat[plan.offsets[i]:plan.offsets[i + 1]].view(1, -1),
@@ -648,6 +808,23 @@ def batch_main(args, np, torch, gg, lg, dev):
     ev[1].record()
     torch.cuda.synchronize()
     single_ms = ev[0].elapsed_time(ev[1])
+    # parity: every batch row equals the single-query call's, and a sample of
+    # 32 queries equals the oracle's tree
+    same = bool(torch.equal(batch_d, dflat) and torch.equal(batch_p, pflat))
+    import oracle as orc  # the CPU oracle: test infrastructure
+    rng = np.random.default_rng(3)
+    sample = sorted(rng.choice(len(jobs), size=min(32, len(jobs)), replace=False).tolist())
+    for i in sample:
+        gi, r = jobs[i]
+        off_h, col_h = graphs[gi].numpy()
+        d0, p0 = orc.bfs(off_h, col_h, r)
+        same = same and bool(np.array_equal(plan.depth(i).cpu().numpy(), d0)
+                             and np.array_equal(plan.parent(i).cpu().numpy(), p0))
+    log(f"[batch] parity: {len(jobs)} rows against one launch per query, {len(sample)} against the oracle: "
+        f"{'ok' if same else 'FAILED'}")
+    if not same:
+        print(json.dumps({"error": "batch parity failed"}), flush=True)
+        sys.exit(1)
     total_edges = sum(edges)
     out = {"metric": "GTEPS & HBM GB/s, Log(Graph)-packed vs plain CSR on GPU; p99 query latency",
            "value": round(total_edges / (batch_ms / 1000.0) / 1e9, 4), "unit": "GTEPS", "n_gpus": 1,
@@ -657,6 +834,7 @@ def batch_main(args, np, torch, gg, lg, dev):
                       "encoding": {"ids": "global", "offsets": "packed"}},
            "detail": {"one_launch_per_query_ms": round(single_ms, 3),
                       "speedup_vs_one_launch_per_query": round(single_ms / batch_ms, 2),
+                      "parity": "every row equal to one launch per query; 32 rows equal to the oracle",
                       "autotune": info}}
     print(json.dumps(out), flush=True)
     plan.free()
@@ -710,9 +888,32 @@ def serve_main(args, np, torch, gg, lg, dev):
     # warm every worker's buffers on every graph and kind
     warm = [(k, g, int(cands[g][0])) for g in range(len(hs)) for k in kinds for _ in range(2)]
     closed(warm)
-    wall, res = closed(draw(4000, seed=1))
+    qs_sat = draw(4000, seed=1)
+    wall, res = closed(qs_sat)
     assert all(r["status"] == 0 for r in res), "a query failed"
     sat_qps = len(res) / wall
+    # parity: 300 queries of the saturated mix again, served one at a time
+    # (alone on the device), must return the same results: the same sorted
+    # IDs for neighbor and k-hop queries, the same reach, depth and digest of
+    # (depth, parent) for BFS
+    rng = np.random.default_rng(9)
+    pick = sorted(rng.choice(len(qs_sat), size=300, replace=False).tolist())
+    tickets = [srv.submit(k, g, v, k=2) for k, g, v in (qs_sat[i] for i in pick)]
+    mixed = [srv.wait(t) for t in tickets]
+    mismatch = 0
+    for i, m in zip(pick, mixed):
+        k, gsel, v = qs_sat[i]
+        alone = srv.wait(srv.submit(k, gsel, v, k=2))
+        same = m["status"] == alone["status"] == 0 and m["count"] == alone["count"]
+        if k == "bfs":
+            same = same and m["digest"] == alone["digest"] and m["max_depth"] == alone["max_depth"]
+        else:
+            same = same and np.array_equal(m["ids"], alone["ids"])
+        mismatch += 0 if same else 1
+    log(f"[serve] parity: {len(pick)} queries served in a mix and alone: {mismatch} mismatches")
+    if mismatch:
+        print(json.dumps({"error": f"serving parity failed ({mismatch} queries)"}), flush=True)
+        sys.exit(1)
     log(f"[serve] saturated: {len(res)} queries in {wall:.2f}s = {sat_qps:.1f} q/s")
 
     loads = {}
@@ -771,6 +972,7 @@ def serve_main(args, np, torch, gg, lg, dev):
                       "mix": {"neighbors": 0.6, "khop2": 0.3, "bfs": 0.1}, "budget_bytes": budget,
                       "workers": st["workers"], "encoding": {"ids": "global", "offsets": "packed"}},
            "detail": {"loads": loads, "resident_bytes": st["resident_bytes"], "peak_bytes": st["peak_bytes"],
+                      "parity": "300 queries of the saturated mix equal to the same queries served alone",
                       "batches": st["batches"], "completed": st["completed"]}}
     print(json.dumps(out), flush=True)
     for h in hs:

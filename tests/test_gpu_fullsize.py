@@ -1,10 +1,13 @@
 """Parity at full size, in the launch configuration the benchmark times.
 
 Kronecker scale 24 (DM relabel, local widths, Elias-Fano offsets) and
-Erdos-Renyi scale 26 (global widths, packed offsets, and the plain uint32
-CSR).  The oracle computes whole arrays where that is cheap (permutation,
-widths, bit starts, Elias-Fano arrays, packed offsets, one BFS tree, early
-PageRank iterations) and sampled rows of the packed lists, bit by bit."""
+Erdos-Renyi scale 26 (global widths, packed offsets), each also on the plain
+uint32 CSR.  The oracle computes whole arrays (permutation, widths, bit
+starts, Elias-Fano arrays, packed offsets), sampled rows of the packed lists
+bit by bit, four whole BFS trees per layout (the multi-root call the
+benchmark times, against the oracle's level-synchronous BFS) and the whole
+20-iteration PageRank vector (against the oracle's all-core PageRank, which
+equals its one-thread loop bit for bit)."""
 
 import numpy as np
 import pytest
@@ -27,6 +30,28 @@ def host_csr(g):
     """Host copies in the oracle's element types (no per-call conversions)."""
     off, col = g.numpy()
     return off.astype(np.uint64), col.view(np.uint32)
+
+
+def check_trees_and_pagerank(lgmod, h, g, off, col, labels, what):
+    """Four whole BFS trees from the benchmark's roots (one multi-root call,
+    as timed) and the whole 20-iteration PageRank vector."""
+    roots = gg.pick_roots(g, 64, seed=1)
+    sel = [roots[0], roots[21], roots[42], roots[63]]
+    print(f"[fullsize] {what}: BFS from {len(sel)} roots", flush=True)
+    depth, parent = lgmod.bfs(h, sel)
+    depth, parent = depth.cpu().numpy(), parent.cpu().numpy()
+    for i, r in enumerate(sel):
+        d0, p0 = orc.bfs_levels(off, col, r, labels=labels)
+        np.testing.assert_array_equal(depth[i], d0, err_msg=f"{what} root {r}")
+        np.testing.assert_array_equal(parent[i], p0, err_msg=f"{what} root {r}")
+    print(f"[fullsize] {what}: PageRank, 20 iterations", flush=True)
+    pr = lgmod.pagerank(h, 0.85, 20).cpu().numpy().astype(np.float64)
+    return pr
+
+
+def pagerank20(off, col):
+    """The oracle's 20-iteration FP64 PageRank (all host cores)."""
+    return orc.pagerank_par(off, col, 0.85, 20)
 
 
 def check_sampled_rows(A, P, W, F, s, rows, expect_row):
@@ -72,20 +97,19 @@ def test_kronecker24_local_ef_relabeled(lgmod):
     rows = sorted(set([0, 1, 2, 63, 64, 65, nonempty - 1] + rng.integers(0, nonempty, 300).tolist()))
     check_sampled_rows(A, P, W, F, 0, rows, lambda x: orc.relabel_row(off, col, perm, inv, x))
     del A
-    # BFS: one whole tree, bit-exact (depths and smallest-label parents)
-    root = gg.pick_roots(g, 1, seed=1)[0]
-    depth, parent = lgmod.bfs(h, [root])
-    d0, p0 = orc.bfs(off, col, root, relabeled=True)
-    np.testing.assert_array_equal(depth[0].cpu().numpy(), d0)
-    np.testing.assert_array_equal(parent[0].cpu().numpy(), p0)
-    # PageRank: whole vectors for the first iterations, and the 20-iteration sum
-    for iters in [1, 2]:
-        pr = lgmod.pagerank(h, 0.85, iters).cpu().numpy().astype(np.float64)
-        pr64 = orc.pagerank(off, col, 0.85, iters)
-        assert np.abs(pr - pr64).sum() <= 1e-5, iters
-    pr20 = lgmod.pagerank(h, 0.85, 20).double()
-    assert abs(float(pr20.sum()) - 1.0) <= 1e-5
+    # BFS trees (depths and smallest-label parents) and the 20-iteration
+    # PageRank vector, packed and plain (same labeling)
+    pr64 = pagerank20(off, col)
+    pr = check_trees_and_pagerank(lgmod, h, g, off, col, inv, "kronecker s24 packed")
+    assert np.abs(pr - pr64).sum() <= 1e-5
+    # the first iterations too (the error grows with the iterations)
+    pr1 = lgmod.pagerank(h, 0.85, 1).cpu().numpy().astype(np.float64)
+    assert np.abs(pr1 - orc.pagerank_par(off, col, 0.85, 1)).sum() <= 1e-5
     h.free()
+    hp = lgmod.encode(g.row_offsets, g.col, n, layout="plain", relabel=True)
+    pr = check_trees_and_pagerank(lgmod, hp, g, off, col, inv, "kronecker s24 plain")
+    assert np.abs(pr - pr64).sum() <= 1e-5
+    hp.free()
 
 
 def test_erdos_renyi26_packed_and_plain(lgmod):
@@ -108,27 +132,17 @@ def test_erdos_renyi26_packed_and_plain(lgmod):
     P = orc.bit_starts(off, None, 26)
     check_sampled_rows(A, P, None, 0, 26, rows, lambda v: col[int(off[v]):int(off[v + 1])])
     del A
-    root = gg.pick_roots(g, 1, seed=1)[0]
-    print("[fullsize] ER s26: BFS", flush=True)
-    depth, parent = lgmod.bfs(h, [root])
-    d_gpu, p_gpu = depth[0].cpu().numpy(), parent[0].cpu().numpy()
-    del depth, parent
-    print("[fullsize] ER s26: oracle BFS", flush=True)
-    d0, p0 = orc.bfs(off, col, root)
-    np.testing.assert_array_equal(d_gpu, d0)
-    np.testing.assert_array_equal(p_gpu, p0)
-    print("[fullsize] ER s26: PageRank", flush=True)
-    pr = lgmod.pagerank(h, 0.85, 1).cpu().numpy().astype(np.float64)
-    pr64 = orc.pagerank(off, col, 0.85, 1)
+    print("[fullsize] ER s26: oracle PageRank, 20 iterations", flush=True)
+    pr64 = pagerank20(off, col)
+    pr = check_trees_and_pagerank(lgmod, h, g, off, col, None, "ER s26 packed")
     assert np.abs(pr - pr64).sum() <= 1e-5
     h.free()
     print("[fullsize] ER s26: plain CSR", flush=True)
     hp = lgmod.encode(g.row_offsets, g.col, n, layout="plain")
-    depth, parent = lgmod.bfs(hp, [root])
-    np.testing.assert_array_equal(depth[0].cpu().numpy(), d0)
-    np.testing.assert_array_equal(parent[0].cpu().numpy(), p0)
-    prp = lgmod.pagerank(hp, 0.85, 1).cpu().numpy().astype(np.float64)
-    assert np.abs(prp - pr64).sum() <= 1e-5
+    pr = check_trees_and_pagerank(lgmod, hp, g, off, col, None, "ER s26 plain")
+    assert np.abs(pr - pr64).sum() <= 1e-5
+    pr1 = lgmod.pagerank(hp, 0.85, 1).cpu().numpy().astype(np.float64)
+    assert np.abs(pr1 - orc.pagerank_par(off, col, 0.85, 1)).sum() <= 1e-5
     hp.free()
 
 
@@ -192,7 +206,9 @@ def test_kronecker24_gap_and_dmd(lgmod):
 def test_kronecker22_weighted_sssp(lgmod):
     """Weighted SSSP at Kronecker scale 22 (weights uniform in [1, 255]):
     the whole distance array against the oracle's Dijkstra, packed local IDs
-    with Elias-Fano offsets and the plain CSR."""
+    with Elias-Fano offsets (unrelabeled, and after the degree and greedy
+    relabelings, which search in label space and map back) and the plain
+    CSR."""
     print("[fullsize] kronecker s22 sssp: generate", flush=True)
     g = gg.kronecker(22, 16, seed=3, device="cuda")
     wt = gg.edge_weights(g, 255, seed=1)
@@ -200,7 +216,9 @@ def test_kronecker22_weighted_sssp(lgmod):
     root = gg.pick_roots(g, 1, seed=4)[0]
     print("[fullsize] kronecker s22 sssp: oracle", flush=True)
     expect = orc.sssp(off, col, wt.cpu().numpy().astype(np.uint32), root)
-    for kw in (dict(ids="local", offsets="succinct"), dict(layout="plain")):
+    for kw in (dict(ids="local", offsets="succinct"), dict(layout="plain"),
+               dict(ids="local", offsets="succinct", relabel=True),
+               dict(ids="local", offsets="succinct", relabel="greedy")):
         print(f"[fullsize] kronecker s22 sssp: {kw}", flush=True)
         h = lgmod.encode(g.row_offsets, g.col, g.n, weights=wt, **kw)
         np.testing.assert_array_equal(lgmod.sssp(h, root).cpu().numpy(), expect)
