@@ -845,3 +845,85 @@ ORC_API int orc_bfs_levels(uint64_t n, const uint64_t *off, const uint32_t *col,
 
 /* Threads OpenMP would use by default (the host's cores unless limited). */
 ORC_API int orc_max_threads(void) { return omp_get_max_threads(); }
+
+/* ------------------------------------------------------------------ */
+/* Plain and interleaved bit vectors for O -- subsection "Arrays of    */
+/* Offsets vs. Bit Vectors for O" and its table of offset structures   */
+/* (bvPL, bvIL)                                                         */
+/* ------------------------------------------------------------------ */
+
+/* Both hold the offsets x_0 <= x_1 <= ... <= x_n (universe u = x_n) as one
+ * plain bit vector in which the one of list v marks where that list starts.
+ * Reading (the paper sets the bit of the block where a list starts, which
+ * cannot mark two lists starting at the same place, i.e. empty lists): as
+ * for the Elias-Fano upper bits, the one of list v goes to position
+ * x_v + v, so the vector has u + n + 1 bits, exactly n + 1 ones, and
+ * select1(v) - v = x_v.  The blocks are the units of the offsets themselves:
+ * elements with global IDs, bits with local IDs. */
+ORC_API uint64_t orc_bv_bits(uint64_t count, uint64_t universe) { return universe + count; }
+
+/* bvPL: the plain bit vector plus a directory for select, kept in the same
+ * form as the Elias-Fano one so that every entry is a plain rank or select
+ * value: rank_sb[b] = rank1(512 b) for b = 0 .. ceil(bits / 512) (the extra
+ * last entry holds all n + 1 ones) and sel[j] = select1(64 j) for
+ * j < ceil((n + 1) / 64).  `bits` holds orc_stream_words(orc_bv_bits(..))
+ * zeroed words; positions must stay below 2^32 (sel is 32-bit). */
+ORC_API void orc_bv_plain_build(const uint64_t *x, uint64_t count, uint64_t universe, uint64_t *bits,
+                                uint32_t *rank_sb, uint32_t *sel) {
+    const uint64_t nbits = orc_bv_bits(count, universe);
+    for (uint64_t v = 0; v < count; v++) put_bit(bits, x[v] + v);
+    const uint64_t nr = orc_ef_rank_entries(nbits), ns = orc_ef_select_entries(count);
+    uint64_t ones = 0;
+    for (uint64_t p = 0; p <= nbits; p++) {
+        if (p % 512 == 0 && p / 512 < nr) rank_sb[p / 512] = (uint32_t)ones;
+        if (p == nbits) break;
+        if (get_bit(bits, p)) {
+            if (ones % 64 == 0 && ones / 64 < ns) sel[ones / 64] = (uint32_t)p;
+            ones++;
+        }
+    }
+    rank_sb[nr - 1] = (uint32_t)ones;
+}
+
+/* x_v from the plain bit vector: select1(v) - v (linear scan) */
+ORC_API uint64_t orc_bv_plain_get(const uint64_t *bits, uint64_t nbits, uint64_t v) {
+    return orc_select1(bits, nbits, v) - v;
+}
+
+/* bvIL: the same bit vector cut into blocks of 512 bits, each block preceded
+ * by one 64-bit word holding the number of ones before it (the cumulative
+ * sums the paper interleaves with the data every L bits; L = 512 here).
+ * Block j takes words [9 j, 9 j + 9): word 9 j = rank1(512 j), words
+ * 9 j + 1 .. 9 j + 8 = bits [512 j, 512 j + 512) of the vector.  One word
+ * after the last block holds the total, n + 1.  `words` holds
+ * orc_bvil_words(..) zeroed words. */
+ORC_API uint64_t orc_bvil_words(uint64_t nbits) { return ((nbits + 511) / 512) * 9 + 1; }
+
+ORC_API void orc_bvil_build(const uint64_t *x, uint64_t count, uint64_t universe, uint64_t *words) {
+    const uint64_t nbits = orc_bv_bits(count, universe);
+    const uint64_t blocks = (nbits + 511) / 512;
+    for (uint64_t v = 0; v < count; v++) {
+        const uint64_t p = x[v] + v;                      /* bit p of the vector */
+        const uint64_t j = p / 512, in = p % 512;         /* block j, bit `in` of its data */
+        put_bit(words, (9 * j + 1) * 64 + in);
+    }
+    uint64_t ones = 0;
+    for (uint64_t j = 0; j < blocks; j++) {
+        words[9 * j] = ones;
+        for (uint64_t in = 0; in < 512; in++) ones += (uint64_t)get_bit(words, (9 * j + 1) * 64 + in);
+    }
+    words[9 * blocks] = ones;
+}
+
+/* x_v from the interleaved layout: the v-th one, found by walking the data
+ * bits of the blocks in order (the count words are not used), minus v */
+ORC_API uint64_t orc_bvil_get(const uint64_t *words, uint64_t nbits, uint64_t v) {
+    uint64_t seen = 0;
+    for (uint64_t p = 0; p < nbits; p++) {
+        if (get_bit(words, (9 * (p / 512) + 1) * 64 + p % 512)) {
+            if (seen == v) return p - v;
+            seen++;
+        }
+    }
+    return UINT64_MAX;
+}

@@ -95,6 +95,12 @@ def lib():
         "orc_bfs_levels": (C.c_int, [C.c_uint64, u64p, u32p, C.c_uint32, C.c_int32, _NullableU32, i32p, i32p,
                                      C.c_int]),
         "orc_max_threads": (C.c_int, []),
+        "orc_bv_bits": (C.c_uint64, [C.c_uint64, C.c_uint64]),
+        "orc_bv_plain_build": (None, [u64p, C.c_uint64, C.c_uint64, u64p, u32p, u32p]),
+        "orc_bv_plain_get": (C.c_uint64, [u64p, C.c_uint64, C.c_uint64]),
+        "orc_bvil_words": (C.c_uint64, [C.c_uint64]),
+        "orc_bvil_build": (None, [u64p, C.c_uint64, C.c_uint64, u64p]),
+        "orc_bvil_get": (C.c_uint64, [u64p, C.c_uint64, C.c_uint64]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -353,6 +359,43 @@ class EF:
         return int(lib().orc_ef_get(self.low, self.high, self.hbits, self.l, v))
 
 
+class PlainBV:
+    """bvPL offsets as the oracle builds them: the plain bit vector with the
+    one of list v at x_v + v, and its rank/select directory."""
+
+    def __init__(self, x, universe: int):
+        x = np.ascontiguousarray(x, dtype=np.uint64)
+        L = lib()
+        self.count = x.size
+        self.universe = int(universe)
+        self.nbits = int(L.orc_bv_bits(self.count, self.universe))
+        self.bits = np.zeros(stream_words(self.nbits), dtype=np.uint64)
+        self.rank_sb = np.zeros(int(L.orc_ef_rank_entries(self.nbits)), dtype=np.uint32)
+        self.sel = np.zeros(max(int(L.orc_ef_select_entries(self.count)), 1), dtype=np.uint32)
+        L.orc_bv_plain_build(x, self.count, self.universe, self.bits, self.rank_sb, self.sel)
+        self.sel = self.sel[: int(L.orc_ef_select_entries(self.count))]
+
+    def get(self, v: int) -> int:
+        return int(lib().orc_bv_plain_get(self.bits, self.nbits, v))
+
+
+class InterleavedBV:
+    """bvIL offsets as the oracle builds them: 512-bit blocks of the plain
+    bit vector, each preceded by the 64-bit count of ones before it."""
+
+    def __init__(self, x, universe: int):
+        x = np.ascontiguousarray(x, dtype=np.uint64)
+        L = lib()
+        self.count = x.size
+        self.universe = int(universe)
+        self.nbits = int(L.orc_bv_bits(self.count, self.universe))
+        self.words = np.zeros(int(L.orc_bvil_words(self.nbits)), dtype=np.uint64)
+        L.orc_bvil_build(x, self.count, self.universe, self.words)
+
+    def get(self, v: int) -> int:
+        return int(lib().orc_bvil_get(self.words, self.nbits, v))
+
+
 # -- relabeling -------------------------------------------------------
 
 def dm_permutation(off):
@@ -461,7 +504,9 @@ class Encoding:
     w_v bits, the differences at g_v bits, both tables at F bits),
     "varint-full" or "varint-diff" (a byte stream of Varint labels or of a
     first label and differences; offsets are byte starts).  offset_mode: "packed"
-    (fixed-width offsets) or "ef" (Elias-Fano with rank/select directory).
+    (fixed-width offsets), "ef" (Elias-Fano with rank/select directory),
+    "plain-bv" (bvPL: plain bit vector with a rank/select directory) or
+    "interleaved-bv" (bvIL: the bit vector with interleaved 64-bit counts).
     The offset values are element offsets O[v] in global mode (bit start =
     s * O[v]) and bit starts P_v in local mode.  relabel: False, True or
     "degree" (the degree-minimizing permutation), or "greedy" (the greedy
@@ -544,10 +589,14 @@ class Encoding:
             self.P = vals
         self.offset_values = vals
         self.universe = universe
+        self.ef = self.bv = self.bvil = None
         if offset_mode == "packed":
             self.wO = bitlen(universe)
             self.O = pack_fixed(vals, self.wO)
-            self.ef = None
+        elif offset_mode == "plain-bv":
+            self.bv = PlainBV(vals, universe)
+        elif offset_mode == "interleaved-bv":
+            self.bvil = InterleavedBV(vals, universe)
         else:
             self.ef = EF(vals, universe)
 
