@@ -602,8 +602,9 @@ def offset_fetch_main(args, np, torch, lg, g):
     """Random fetch under each offset structure (the random-offset-fetch test
     of the offset-structure comparison: 1,000 random vertices per worker;
     here 256 workers, one per compute unit, in one call), no relabeling,
-    local widths: degrees only (one offset pair per vertex: the structure's
-    random access) and whole lists."""
+    global widths, so that every structure indexes elements of the lists as
+    in the paper's comparison: degrees only (one offset pair per vertex: the
+    structure's random access) and whole lists."""
     import ctypes as C
     n = g.n
     k = 1000 * 256
@@ -612,10 +613,14 @@ def offset_fetch_main(args, np, torch, lg, g):
     off = torch.empty(k + 1, dtype=torch.int64, device=g.col.device)
     s = C.c_void_p(torch.cuda.current_stream().cuda_stream)
     res = {}
-    # ptr32: plain 32-bit element offsets; ptrW: offsets at bl(universe) bits
-    # (logarithmized single offsets); bvSD: the Elias-Fano sparse bit vector
-    for name, kw in [("ptr32", dict(layout="plain")), ("ptrW", dict(ids="local", offsets="packed")),
-                     ("bvSD", dict(ids="local", offsets="succinct"))]:
+    # ptr32: plain 32-bit element offsets; ptrW: offsets at bl(M) bits
+    # (logarithmized single offsets); bvPL: the plain bit vector with a
+    # rank/select directory; bvIL: the bit vector with interleaved 64-bit
+    # counts; bvSD: the Elias-Fano sparse bit vector
+    for name, kw in [("ptr32", dict(layout="plain")), ("ptrW", dict(ids="global", offsets="packed")),
+                     ("bvPL", dict(ids="global", offsets="plain-bv")),
+                     ("bvIL", dict(ids="global", offsets="interleaved-bv")),
+                     ("bvSD", dict(ids="global", offsets="succinct"))]:
         h = lg.encode(g.row_offsets, g.col, n, **kw)
         info = h.info()
 
@@ -626,6 +631,12 @@ def offset_fetch_main(args, np, torch, lg, g):
                                          2, s)
         deg_ms = _time_ms(torch, degrees_only, reps=5)
         total = int(off[-1].item())
+        # parity before the numbers count: every structure gives the input's
+        # degrees for the fetched vertices
+        want = (g.row_offsets[vt.long() + 1] - g.row_offsets[vt.long()]).cumsum(0)
+        if not (int(off[0].item()) == 0 and torch.equal(off[1:], want)):
+            print(json.dumps({"error": f"offset fetch parity failed ({name})"}), flush=True)
+            sys.exit(1)
         ids = torch.empty(max(total, 1), dtype=torch.int32, device=g.col.device)
 
         def lists():
@@ -633,6 +644,11 @@ def offset_fetch_main(args, np, torch, lg, g):
                                               C.c_void_p(ids.data_ptr()), total, 2, s)
             assert st == 0, lg.lib().lg_last_error()
         lists_ms = _time_ms(torch, lists, reps=5)
+        if name == "ptr32":
+            ref_ids = ids.clone()
+        elif not torch.equal(ids, ref_ids):
+            print(json.dumps({"error": f"offset fetch list parity failed ({name})"}), flush=True)
+            sys.exit(1)
         res[name] = {"offsets_bytes": info["bytes_offsets"], "degrees_only_ms": round(deg_ms, 4),
                      "ns_per_offset_fetch": round(deg_ms * 1e6 / k, 3), "lists_ms": round(lists_ms, 4),
                      "entries": total, "gentries_per_s": round(total / (lists_ms * 1e-3) / 1e9, 3)}

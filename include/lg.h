@@ -82,6 +82,22 @@ typedef enum lg_status {
 #define LG_OFFS_PACKED 0u   /* offsets packed at bl(universe) bits each          */
 #define LG_OFFS_SUCCINCT 1u /* Elias-Fano sequence (sparse bit vector bvSD) with
                                a rank/select directory                           */
+/* subsection "Arrays of Offsets vs. Bit Vectors for O" and its table of
+ * offset structures: the offsets x_0 <= .. <= x_n (universe u) as one plain
+ * bit vector of u + n + 1 bits whose one for list v sits at x_v + v (so an
+ * empty list keeps its own one); x_v = select1(v) - v.  Units of x: elements
+ * (global IDs) or bits (local IDs). */
+#define LG_OFFS_PLAIN_BV 2u       /* bvPL: the vector plus a directory for select
+                                     (rank1 every 512 bits, select1 every 64th one);
+                                     u + n + 1 must stay below 2^32; every
+                                     operation reads it                          */
+#define LG_OFFS_INTERLEAVED_BV 3u /* bvIL: the vector in 512-bit blocks, each led
+                                     by a 64-bit count of the ones before it
+                                     (select by binary search over the counts);
+                                     global or local IDs, unweighted; read by
+                                     lg_decode_neighbors (and its allocation-free
+                                     variant) only, the other operations return
+                                     LG_ERR_UNSUPPORTED                          */
 /* lg_encode_opts.relabel -- section "Incorporating Degree-Minimizing (DM)" */
 #define LG_RELABEL_NONE 0u
 #define LG_RELABEL_DEGREE 1u /* new label = rank by (degree desc, ID asc)         */
@@ -411,7 +427,8 @@ typedef struct lg_graph_info {
     uint32_t ef_l;         /* Elias-Fano low bits (succinct offsets), else 0     */
     uint64_t universe;     /* largest offset value: M (global) or U (local)      */
     uint64_t adj_bits;     /* U: bits of the packed lists                        */
-    uint64_t ef_high_bits; /* |H| in bits (succinct offsets)                     */
+    uint64_t ef_high_bits; /* |H| in bits (succinct offsets); the bit vector's
+                              length u + n + 1 (bvPL, bvIL)                      */
     uint64_t bytes_adj;    /* bytes of the neighbor data (packed words / uint32) */
     uint64_t bytes_offsets;/* bytes of the offset structure incl. directory      */
     uint64_t bytes_widths; /* bytes of the width table(s) (both in gap mode)     */
@@ -445,6 +462,11 @@ lg_status lg_info(const lg_graph *g, lg_graph_info *out);
 #define LG_EXPORT_INV 8u       /* uint32 inv[original] = new                      */
 #define LG_EXPORT_GAP_WIDTHS 9u /* gap-width-table words (uint64), gap mode       */
 #define LG_EXPORT_WEIGHTS 10u   /* weights (uint32), weighted plain layout        */
+/* with LG_OFFS_PLAIN_BV the bit vector and its directory come out as
+ * LG_EXPORT_EF_HIGH, LG_EXPORT_EF_RANK and LG_EXPORT_EF_SELECT */
+#define LG_EXPORT_BV_INTERLEAVED 11u /* bvIL words (uint64): block j at words
+                                        [9j, 9j+9) = count of ones before it, then
+                                        512 bits; one last word = n + 1        */
 
 /*
  * Copy one raw array of the representation to host memory (synchronous).

@@ -249,6 +249,8 @@ lg::PackedView lg_graph::packed_view() const {
     v.ef.n_sel = (uint32_t)n_sel;
     v.ef.n_sb = n_rank ? (uint32_t)(n_rank - 1) : 0;
     v.ef.n_hw = (uint32_t)H_words;
+    v.il.W = IL.as<uint64_t>();
+    v.il.blocks = il_blocks;
     return v;
 }
 
@@ -260,7 +262,8 @@ lg::PlainView lg_graph::plain_view() const {
 }
 
 uint64_t lg_graph::device_bytes() const {
-    uint64_t b = A.bytes + O.bytes + W.bytes + G.bytes + L.bytes + H.bytes + rank_sb.bytes + sel.bytes + poff.bytes +
+    uint64_t b = A.bytes + O.bytes + W.bytes + G.bytes + L.bytes + H.bytes + rank_sb.bytes + sel.bytes + IL.bytes +
+                 poff.bytes +
                  pcol.bytes + pwt.bytes + perm.bytes + inv.bytes + heavy.bytes + iso.bytes + hstart.bytes + hdeg.bytes + hw.bytes +
                  hg.bytes + seg_off.bytes + seg_map.bytes + seg_part.bytes + seg_base.bytes + units.bytes +
                  vhb0.bytes + vhb1.bytes + vseg_off.bytes + vseg_map.bytes + vseg_base.bytes + vdeg.bytes +
@@ -326,8 +329,8 @@ extern "C" lg_status lg_info(const lg_graph *g, lg_graph_info *out) {
         out->adj_bits = g->U;
         out->ef_high_bits = g->hbits;
         out->bytes_adj = g->A_words * 8;
-        out->bytes_offsets = g->offset_mode == LG_OFFS_PACKED
-                                 ? g->O_words * 8
+        out->bytes_offsets = g->offset_mode == LG_OFFS_PACKED           ? g->O_words * 8
+                             : g->offset_mode == LG_OFFS_INTERLEAVED_BV ? g->IL_words * 8
                                  : g->L_words * 8 + g->H_words * 8 + g->n_rank * 4 + g->n_sel * 4;
         out->bytes_widths = (g->W_words + g->G_words) * 8;
     }
@@ -371,11 +374,16 @@ static bool export_src(const lg_graph *g, uint32_t which, const void **p, uint64
         case LG_EXPORT_EF_HIGH:
         case LG_EXPORT_EF_RANK:
         case LG_EXPORT_EF_SELECT:
-            if (!packed || g->offset_mode != LG_OFFS_SUCCINCT) return false;
+            if (!packed || (g->offset_mode != LG_OFFS_SUCCINCT && g->offset_mode != LG_OFFS_PLAIN_BV)) return false;
+            if (which == LG_EXPORT_EF_LOW && g->offset_mode != LG_OFFS_SUCCINCT) return false;
             if (which == LG_EXPORT_EF_LOW) { *p = g->L.p; *bytes = g->L_words * 8; }
             if (which == LG_EXPORT_EF_HIGH) { *p = g->H.p; *bytes = g->H_words * 8; }
             if (which == LG_EXPORT_EF_RANK) { *p = g->rank_sb.p; *bytes = g->n_rank * 4; }
             if (which == LG_EXPORT_EF_SELECT) { *p = g->sel.p; *bytes = g->n_sel * 4; }
+            return true;
+        case LG_EXPORT_BV_INTERLEAVED:
+            if (!packed || g->offset_mode != LG_OFFS_INTERLEAVED_BV) return false;
+            *p = g->IL.p; *bytes = g->IL_words * 8;
             return true;
         case LG_EXPORT_PERM:
         case LG_EXPORT_INV:

@@ -37,7 +37,7 @@ namespace lg {
 
 uint64_t BfsWork::bytes() const {
     return qa.bytes + qb.bytes + fstart.bytes + fdeg.bytes + fw.bytes + fscan.bytes + visited.bytes + curr.bytes +
-           next.bytes + counters.bytes + depth_i.bytes + parent_i.bytes + scan_tmp.bytes + pv.bytes + pstart.bytes +
+           next.bytes + counters.bytes + sample.bytes + depth_i.bytes + parent_i.bytes + scan_tmp.bytes + pv.bytes + pstart.bytes +
            pdeg.bytes + pw.bytes + pseg_cnt.bytes + pseg_off.bytes;
 }
 
@@ -90,6 +90,7 @@ lg_status bfs_workspace_ensure(BfsWork &w, uint64_t n, uint64_t n_heavy, bool re
     LG_TRY(w.curr.ensure(words * 8));
     LG_TRY(w.next.ensure(words * 8));
     LG_TRY(w.counters.ensure(8 * 8));
+    LG_TRY(w.sample.ensure(8 * 8));
     const uint64_t nh = n_heavy ? n_heavy : 1;
     LG_TRY(w.pv.ensure(nh * 4));
     LG_TRY(w.pstart.ensure(nh * 8));
@@ -145,6 +146,36 @@ __global__ __launch_bounds__(kDirSampleThreads) void td_sample_kernel(Acc acc, c
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const unsigned long long d = acc.info(queue[i * qsize / kDirSample]).deg;
     const unsigned long long t = block_sum_u64(d);
+    if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+// Bottom-up cost of the next level on a sample: kDirSample vertices at evenly
+// spaced labels; one not yet visited reads its list in order until its first
+// neighbour in the frontier bitmap (at most kBuSampleWalk entries), as the
+// bottom-up sweep would; its cost is one (its offsets) plus the entries read.
+// Partial sums per block.
+constexpr uint32_t kBuSampleWalk = 1024;
+
+template <class Acc>
+__global__ __launch_bounds__(kDirSampleThreads) void bu_cost_sample_kernel(Acc acc, uint32_t n,
+                                                                           const uint64_t *__restrict__ visited,
+                                                                           const uint64_t *__restrict__ curr,
+                                                                           uint64_t *__restrict__ part) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t v = (uint32_t)(((2 * i + 1) * (uint64_t)n) / (2ull * kDirSample));
+    unsigned long long cost = 0;
+    if (v < n && !((visited[v >> 6] >> (v & 63)) & 1ull)) {
+        const VInfo vi = acc.info(v);
+        const uint32_t st = Acc::step(vi.w), mk = Acc::mask(vi.w);
+        const uint32_t lim = vi.deg < kBuSampleWalk ? vi.deg : kBuSampleWalk;
+        cost = 1;
+        for (uint32_t j = 0; j < lim; ++j) {
+            const uint32_t u = acc.get(vi.start + (uint64_t)j * st, mk);
+            ++cost;
+            if (u < n && ((curr[u >> 6] >> (u & 63)) & 1ull)) break;
+        }
+    }
+    const unsigned long long t = block_sum_u64(cost);
     if (threadIdx.x == 0) part[blockIdx.x] = t;
 }
 
@@ -300,6 +331,32 @@ __global__ void mark_queue_kernel(const uint32_t *__restrict__ queue, uint64_t q
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < q; i += stride) {
         const uint32_t u = queue[i];
         atomicOr(&bits[u >> 6], 1ull << (u & 63));
+    }
+}
+
+// The bitmaps of a level whose queue holds a large share of the vertices,
+// streamed from the depth array (a wave per 64-vertex word, one coalesced
+// read): `frontier` = the vertices at depth d, `visited` = every reached
+// vertex and every vertex without edges.  One atomic per queued vertex costs
+// far more once the queue holds millions of vertices (30 M at one level of a
+// uniform random graph of 67 M vertices: 2.5 ms against 0.1 ms).  Either
+// bitmap may be NULL.  Clears the queue counter as mark_queue_kernel does.
+__global__ void level_bitmaps_kernel(uint32_t n, const int32_t *__restrict__ depth, int32_t d,
+                                     const uint64_t *__restrict__ iso, uint64_t *__restrict__ frontier,
+                                     uint64_t *__restrict__ visited, unsigned long long *__restrict__ counter) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) *counter = 0;
+    const uint32_t lane = lane_id();
+    const uint64_t words = ((uint64_t)n + 63) / 64;
+    const uint64_t wstride = ((uint64_t)gridDim.x * blockDim.x) / kWave;
+    for (uint64_t w = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave; w < words; w += wstride) {
+        const uint64_t v = w * 64 + lane;
+        const int32_t dv = v < n ? depth[v] : -1;
+        const uint64_t at = __ballot(dv == d);
+        const uint64_t reached = __ballot(dv >= 0);
+        if (lane == 0) {
+            if (frontier) frontier[w] = at;
+            if (visited) visited[w] = reached | iso[w];
+        }
     }
 }
 
@@ -1087,6 +1144,44 @@ static lg_status bfs_one(lg_graph *g, BfsWork &w, Acc acc, uint32_t root_id, con
     bool topdown = true;
     bool bu_done = false;  // a bottom-up phase is over: the frontier only shrinks from here
     uint32_t bu_pair = 0;  // counter pair of the next bottom-up level
+    // queues above this size mark their bitmaps by a streaming pass over the
+    // depths instead of one atomic per vertex
+    const uint64_t stream_marks = std::max<uint64_t>(4096, n / 64);
+    const uint32_t wgrid = grid_for(words * kWave, 256, kStrideBlocks);
+    int32_t curr_level = -1;  // the level whose frontier curr holds (-1: none)
+    // the frontier bitmap of the queue qin (what a bottom-up level reads)
+    auto mark_frontier = [&]() -> lg_status {
+        if (curr_level == level) return LG_OK;
+        if (qsize > stream_marks) {
+            LG_LAUNCH(level_bitmaps_kernel, wgrid, 256, 0, s, n, (const int32_t *)depth, level,
+                      g->iso.as<uint64_t>(), curr, (uint64_t *)nullptr, ctr);
+        } else {
+            LG_TRY(fill_u64(curr, 0, words, s));
+            LG_LAUNCH(mark_queue_kernel, grid_for(qsize, 256, 1u << 16), 256, 0, s, qin, qsize,
+                      (unsigned long long *)curr, ctr);
+        }
+        LG_CHECK_LAUNCH();
+        curr_level = level;
+        return LG_OK;
+    };
+    // Between the switch points, is a bottom-up level cheaper than expanding
+    // `td_cost` frontier edges?  Builds the frontier bitmap as a side effect.
+    auto bottom_up_cheaper = [&](double td_cost, bool &cheaper) -> lg_status {
+        LG_TRY(mark_frontier());
+        LG_LAUNCH(bu_cost_sample_kernel<Acc>, kDirSampleBlocks, kDirSampleThreads, 0, s, acc, n, visited, curr,
+                  w.sample.as<uint64_t>());
+        LG_CHECK_LAUNCH();
+        LG_CHECK_HIP(hipMemcpyAsync(w.host, w.sample.p, kDirSampleBlocks * 8, hipMemcpyDeviceToHost, s));
+        LG_CHECK_HIP(hipStreamSynchronize(s));
+        uint64_t sampled = 0;
+        for (uint32_t b = 0; b < kDirSampleBlocks; ++b) sampled += w.host[b];
+        const double bu_cost = (double)sampled * ((double)n / (double)kDirSample);
+        cheaper = td_cost > kBfsProbeCost * bu_cost;
+        return LG_OK;
+    };
+    // with a late switch point beyond the early one, the band between them is sampled
+    const bool banded = flags == LG_BFS_DIRECTION_OPT && alpha > kBfsAlphaLate;
+    int32_t sampled_level = -1;  // the level whose sample chose top-down
     for (;;) {
         if (max_depth >= 0 && level >= max_depth) break;
         // ctr[0], the queue counter, is zero at every level's start: bfs_init
@@ -1130,13 +1225,18 @@ static lg_status bfs_one(lg_graph *g, BfsWork &w, Acc acc, uint32_t root_id, con
                 for (uint32_t b = 0; b < kDirSampleBlocks; ++b) sampled += w.host[b];
                 const double est = (double)sampled * ((double)qsize / (double)kDirSample);
                 if (est > 2.0 * (double)edges_to_check / alpha) {
-                    LG_TRY(fill_u64(curr, 0, words, s));
-                    LG_LAUNCH(mark_queue_kernel, grid_for(qsize, 256, 1u << 16), 256, 0, s, qin, qsize,
-                              (unsigned long long *)curr, ctr);
-                    LG_CHECK_LAUNCH();
-                    awake = qsize;
-                    topdown = false;
-                    continue;
+                    bool cheaper = true;
+                    if (banded && est <= 2.0 * (double)edges_to_check / kBfsAlphaLate) {
+                        LG_TRY(bottom_up_cheaper(est, cheaper));
+                        sampled_level = level;
+                    } else {
+                        LG_TRY(mark_frontier());
+                    }
+                    if (cheaper) {
+                        awake = qsize;
+                        topdown = false;
+                        continue;
+                    }
                 }
             }
             LG_LAUNCH(td_prepare_kernel<Acc>, grid_for(qsize, 256, 1u << 16), 256, 0, s, acc, qin, (uint32_t)qsize,
@@ -1146,13 +1246,21 @@ static lg_status bfs_one(lg_graph *g, BfsWork &w, Acc acc, uint32_t root_id, con
             LG_CHECK_HIP(hipMemcpyAsync(w.host, w.fscan.as<uint64_t>() + qsize, 8, hipMemcpyDeviceToHost, s));
             LG_CHECK_HIP(hipStreamSynchronize(s));
             const uint64_t fedges = w.host[0];
-            const bool go_bu = (flags == LG_BFS_BOTTOM_UP && level >= 1) ||
-                               (flags == LG_BFS_DIRECTION_OPT && (double)fedges > (double)edges_to_check / alpha);
+            bool go_bu = (flags == LG_BFS_BOTTOM_UP && level >= 1) ||
+                         (flags == LG_BFS_DIRECTION_OPT && (double)fedges > (double)edges_to_check / alpha);
+            bool marked = false;
+            if (go_bu && banded && (double)fedges <= (double)edges_to_check / kBfsAlphaLate) {
+                // in the band: measured unless this level's sample already
+                // chose top-down
+                if (sampled_level == level) {
+                    go_bu = false;
+                } else {
+                    LG_TRY(bottom_up_cheaper((double)fedges, go_bu));
+                    marked = true;
+                }
+            }
             if (go_bu) {
-                LG_TRY(fill_u64(curr, 0, words, s));
-                LG_LAUNCH(mark_queue_kernel, grid_for(qsize, 256, 1u << 16), 256, 0, s, qin, qsize,
-                          (unsigned long long *)curr, ctr);
-                LG_CHECK_LAUNCH();
+                if (!marked) LG_TRY(mark_frontier());
                 awake = qsize;
                 topdown = false;
                 continue;
@@ -1173,7 +1281,13 @@ static lg_status bfs_one(lg_graph *g, BfsWork &w, Acc acc, uint32_t root_id, con
             LG_CHECK_HIP(hipMemcpyAsync(w.host, ctr, 8, hipMemcpyDeviceToHost, s));
             LG_CHECK_HIP(hipStreamSynchronize(s));
             qsize = w.host[0];
-            if (qsize) {
+            if (qsize > stream_marks) {
+                // the next frontier's bitmap comes with the visited one
+                LG_LAUNCH(level_bitmaps_kernel, wgrid, 256, 0, s, n, (const int32_t *)depth, level + 1,
+                          g->iso.as<uint64_t>(), curr, visited, ctr);
+                LG_CHECK_LAUNCH();
+                curr_level = level + 1;
+            } else if (qsize) {
                 LG_LAUNCH(mark_queue_kernel, grid_for(qsize, 256, 1u << 16), 256, 0, s, qout, qsize,
                           (unsigned long long *)visited, ctr);
                 LG_CHECK_LAUNCH();
@@ -1222,6 +1336,7 @@ static lg_status bfs_one(lg_graph *g, BfsWork &w, Acc acc, uint32_t root_id, con
             const uint64_t now = w.host[0];
             std::swap(curr, next);
             ++level;
+            curr_level = level;  // the sweep wrote this level's frontier
             if (now == 0) break;
             const bool back = flags == LG_BFS_DIRECTION_OPT && now < awake && (double)now <= (double)n / kBfsBeta;
             awake = now;

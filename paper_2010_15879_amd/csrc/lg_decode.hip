@@ -189,7 +189,7 @@ lg_status decode_run(lg_graph *g, DecodeWork &w, const uint32_t *vertices, uint3
     LG_TRY(fill_u32(bad, 0, 1, stream));
     LG_LAUNCH(dec_map_kernel, grid_for(k, 256, 1u << 16), 256, 0, stream, g->n, vertices, k, inv, labels, bad);
     LG_CHECK_LAUNCH();
-    return dispatch_acc_dec(g, [&](auto acc) -> lg_status {
+    return dispatch_acc_decode(g, [&](auto acc) -> lg_status {
         using Acc = decltype(acc);
         if constexpr (IsVarintAcc<Acc>::value)
             LG_LAUNCH(dec_varint_degree_kernel<Acc>, grid_for((uint64_t)k * kWave, 256, 1u << 16), 256, 0, stream,

@@ -170,6 +170,48 @@ __device__ __forceinline__ uint64_t ef_get(const EFView &e, uint32_t v) {
     return ((pos - v) << e.l) | low;
 }
 
+// ---------------------------------------------------------------------------
+// select over the interleaved bit vector (bvIL)
+// ---------------------------------------------------------------------------
+
+// select1(k): a binary search over the blocks' leading counts for the block
+// holding the k-th one (the last block whose count of earlier ones is at most
+// k; the k-th one sits at position >= k, so no block before k / 512), then a
+// popcount scan of at most eight data words.  k must be below the number of
+// ones.
+__device__ __forceinline__ uint64_t il_select1(const ILView &e, uint64_t k) {
+    uint64_t lo = k >> 9, hi = e.blocks - 1;
+    if (lo > hi) lo = hi;
+    while (lo < hi) {
+        const uint64_t mid = (lo + hi + 1) >> 1;
+        if (e.W[9 * mid] <= k) lo = mid; else hi = mid - 1;
+    }
+    uint64_t r = k - e.W[9 * lo];
+    const uint64_t *d = e.W + 9 * lo + 1;
+    uint32_t t = 0;
+    for (; t < 7; ++t) {
+        const uint64_t c = (uint64_t)__popcll(d[t]);
+        if (r < c) break;
+        r -= c;
+    }
+    return lo * 512 + (uint64_t)t * 64 + select_in_word(d[t], (uint32_t)r);
+}
+
+// position of the first one after position p, skipping the count words
+// between blocks (one must exist)
+__device__ __forceinline__ uint64_t il_next_one(const ILView &e, uint64_t p) {
+    const uint64_t q = p + 1;
+    uint64_t j = q >> 9;
+    uint32_t t = (uint32_t)(q >> 6) & 7u;
+    const uint32_t sh = (uint32_t)q & 63u;
+    uint64_t x = e.W[9 * j + 1 + t] & (~0ull << sh);
+    while (!x) {
+        if (++t == 8) { t = 0; ++j; }
+        x = e.W[9 * j + 1 + t];
+    }
+    return j * 512 + (uint64_t)t * 64 + (uint64_t)(__ffsll((long long)x) - 1);
+}
+
 // exact quotient of a multiple of w (1 <= w <= 32) by w, below 2^51
 static __device__ __constant__ double c_inv_width[33] = {
     0.0, 1.0, 1.0 / 2, 1.0 / 3, 1.0 / 4, 1.0 / 5, 1.0 / 6, 1.0 / 7, 1.0 / 8, 1.0 / 9, 1.0 / 10,
@@ -194,7 +236,7 @@ struct VInfo {
 };
 
 enum : int { kIdsGlobal = 0, kIdsLocal = 1 };
-enum : int { kOffsPacked = 0, kOffsEF = 1 };
+enum : int { kOffsPacked = 0, kOffsEF = 1, kOffsIL = 2 };
 
 template <int IDM, int OFM>
 struct PackedAcc {
@@ -204,6 +246,7 @@ struct PackedAcc {
 
     __device__ __forceinline__ uint64_t offset_value(uint32_t v) const {
         if constexpr (OFM == kOffsPacked) return extract64(pv.po.O, (uint64_t)v * pv.po.w, pv.po.w);
+        else if constexpr (OFM == kOffsIL) return il_select1(pv.il, v) - v;
         else return ef_get(pv.ef, v);
     }
     __device__ __forceinline__ uint32_t width(uint32_t v) const {
@@ -244,6 +287,11 @@ struct PackedAcc {
         if constexpr (OFM == kOffsPacked) {
             o0 = offset_value(v);
             o1 = offset_value(v + 1);
+        } else if constexpr (OFM == kOffsIL) {
+            // x_{v+1}'s one is the next one after x_v's
+            const uint64_t p0 = il_select1(pv.il, v);
+            o0 = p0 - v;
+            o1 = il_next_one(pv.il, p0) - v - 1;
         } else {
             // x_{v+1}'s upper bit is the next one of H after x_v's
             const EFView &e = pv.ef;
@@ -500,6 +548,11 @@ lg_status dispatch_acc(const lg_graph *g, Fn &&fn) {
                   "(lg_decode_neighbors, lg_bfs and lg_pagerank are)");
         return LG_ERR_UNSUPPORTED;
     }
+    if (g->offset_mode == LG_OFFS_INTERLEAVED_BV) {
+        set_error("interleaved bit-vector offsets (bvIL) are read by lg_decode_neighbors only");
+        return LG_ERR_UNSUPPORTED;
+    }
+    // the plain bit vector (LG_OFFS_PLAIN_BV) is read as Elias-Fano without low bits
     const PackedView pv = g->packed_view();
     if (g->id_mode == LG_IDS_GLOBAL) {
         if (g->offset_mode == LG_OFFS_PACKED) return fn(PackedAcc<kIdsGlobal, kOffsPacked>{pv});
@@ -553,6 +606,18 @@ lg_status dispatch_acc_dec(const lg_graph *g, Fn &&fn) {
         return diff ? fn(VarintAcc<kOffsEF, true>{b}) : fn(VarintAcc<kOffsEF, false>{b});
     }
     return dispatch_acc_all(g, fn);
+}
+
+// dispatch_acc_dec plus the interleaved bit-vector offsets (bvIL), which
+// only the neighbor decode reads
+template <class Fn>
+lg_status dispatch_acc_decode(const lg_graph *g, Fn &&fn) {
+    if (g->layout == LG_LAYOUT_PACKED && g->offset_mode == LG_OFFS_INTERLEAVED_BV) {
+        const PackedView pv = g->packed_view();
+        if (g->id_mode == LG_IDS_GLOBAL) return fn(PackedAcc<kIdsGlobal, kOffsIL>{pv});
+        return fn(PackedAcc<kIdsLocal, kOffsIL>{pv});
+    }
+    return dispatch_acc_dec(g, fn);
 }
 
 }  // namespace lg

@@ -904,6 +904,54 @@ static lg_status pack_fixed(Src src, uint64_t count, uint32_t w, DevBuf &dst, ui
 }
 
 // offsets structure over the values x[0..n] (element offsets or bit starts)
+// bvIL words: block j at [9j, 9j + 9) = ones before it (the exclusive scan of
+// the per-block counts), then the block's eight words of the plain vector;
+// the last word is the total
+__global__ void il_interleave_kernel(uint64_t blocks, const uint64_t *__restrict__ H, uint64_t hwords,
+                                     const uint64_t *__restrict__ before, uint64_t *__restrict__ out) {
+    const uint64_t total = 9 * blocks + 1;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) {
+        const uint64_t j = i / 9, r = i - 9 * j;
+        if (r == 0) {
+            out[i] = before[j];  // j == blocks: the total
+        } else {
+            const uint64_t k = 8 * j + r - 1;
+            out[i] = k < hwords ? H[k] : 0ull;
+        }
+    }
+}
+
+// Interleaved bit vector (bvIL): the plain vector (one at x_v + v) is built
+// in a temporary, counted per 512-bit block, scanned, and laid out with the
+// counts in front of the blocks.
+static lg_status build_interleaved_bv(lg_graph *g, const uint64_t *x, uint64_t universe, DevBuf &tmp, hipStream_t s) {
+    const uint64_t count = (uint64_t)g->n + 1;
+    g->hbits = universe + count;
+    const uint64_t hwords = (g->hbits + 63) / 64;
+    DevBuf H, cnt, before;
+    LG_TRY(H.scratch((hwords + 1) * 8, s));
+    LG_TRY(fill_u64(H.as<uint64_t>(), 0, hwords + 1, s));
+    LG_LAUNCH(ef_high_kernel, grid1(count), 256, 0, s, count, x, 0u, H.as<unsigned long long>());
+    LG_CHECK_LAUNCH();
+    const uint64_t blocks = (g->hbits + 511) / 512;
+    LG_TRY(cnt.scratch(blocks * 4, s));
+    LG_TRY(before.scratch((blocks + 1) * 8, s));
+    LG_LAUNCH(ef_superblock_count_kernel, grid1(blocks), 256, 0, s, blocks, hwords, H.as<uint64_t>(),
+              cnt.as<uint32_t>());
+    LG_CHECK_LAUNCH();
+    LG_TRY(exclusive_scan_u32(cnt.as<uint32_t>(), before.as<uint64_t>(), blocks, tmp, s));
+    g->il_blocks = blocks;
+    g->IL_words = 9 * blocks + 1;
+    LG_TRY(g->IL.scratch(g->IL_words * 8, s));
+    LG_LAUNCH(il_interleave_kernel, grid1(g->IL_words), 256, 0, s, blocks, H.as<uint64_t>(), hwords,
+              before.as<uint64_t>(), g->IL.as<uint64_t>());
+    LG_CHECK_LAUNCH();
+    // the temporaries are read before this function returns and frees them
+    LG_CHECK_HIP(hipStreamSynchronize(s));
+    return LG_OK;
+}
+
 static lg_status build_offsets(lg_graph *g, const uint64_t *x, uint64_t universe, DevBuf &tmp, hipStream_t s) {
     const uint64_t count = (uint64_t)g->n + 1;
     g->universe = universe;
@@ -911,16 +959,22 @@ static lg_status build_offsets(lg_graph *g, const uint64_t *x, uint64_t universe
         g->wO = bitlen_u64(universe);  // 0 when every offset is 0 (no edges)
         return pack_fixed(SrcU64Mask{x, ~0ull}, count, g->wO, g->O, g->O_words, s);
     }
-    // Elias-Fano: l = floor(log2(universe / count)) when universe >= count
-    const uint32_t l = universe >= count ? bitlen_u64(universe / count) - 1 : 0;
+    if (g->offset_mode == LG_OFFS_INTERLEAVED_BV) return build_interleaved_bv(g, x, universe, tmp, s);
+    // Elias-Fano: l = floor(log2(universe / count)) when universe >= count.
+    // The plain bit vector (bvPL) is the same vector and directory without
+    // low bits: its one for list v sits at x_v + v.
+    const uint32_t l =
+        (g->offset_mode == LG_OFFS_SUCCINCT && universe >= count) ? bitlen_u64(universe / count) - 1 : 0;
     g->ef_l = l;
     g->hbits = (universe >> l) + count;
     if (g->hbits >= (1ull << 32)) {
-        set_error("succinct offsets: upper bit vector of %llu bits exceeds 2^32", (unsigned long long)g->hbits);
+        set_error("%s offsets: bit vector of %llu bits exceeds 2^32",
+                  g->offset_mode == LG_OFFS_SUCCINCT ? "succinct" : "plain bit-vector", (unsigned long long)g->hbits);
         return LG_ERR_UNSUPPORTED;
     }
     const uint64_t lowmask = l ? ((1ull << l) - 1) : 0ull;
-    LG_TRY(pack_fixed(SrcU64Mask{x, lowmask}, count, l, g->L, g->L_words, s));
+    if (g->offset_mode == LG_OFFS_SUCCINCT)  // bvPL keeps no low bits
+        LG_TRY(pack_fixed(SrcU64Mask{x, lowmask}, count, l, g->L, g->L_words, s));
     g->H_words = (g->hbits + 63) / 64 + 1;
     LG_TRY(g->H.scratch(g->H_words * 8, s));
     LG_TRY(fill_u64(g->H.as<uint64_t>(), 0, g->H_words, s));
@@ -1398,10 +1452,15 @@ static lg_status encode_entry(uint32_t n, uint64_t m, const uint64_t *row_offset
     if (n == 0 || n >= (1u << 31)) { set_error("lg_encode: n must be in [1, 2^31)"); return LG_ERR_INVALID; }
     if (m >= (1ull << 36)) { set_error("lg_encode: m must be below 2^36"); return LG_ERR_UNSUPPORTED; }
     if (!row_offsets || (m && !col)) { set_error("lg_encode: NULL input array"); return LG_ERR_INVALID; }
-    if (o.layout > LG_LAYOUT_PLAIN || o.id_mode > LG_IDS_VARINT_DIFF || o.offset_mode > LG_OFFS_SUCCINCT ||
+    if (o.layout > LG_LAYOUT_PLAIN || o.id_mode > LG_IDS_VARINT_DIFF || o.offset_mode > LG_OFFS_INTERLEAVED_BV ||
         o.relabel > LG_RELABEL_GREEDY || o.flags || o.reserved[0] || o.reserved[1] || o.reserved[2]) {
         set_error("lg_encode: unknown option value");
         return LG_ERR_INVALID;
+    }
+    if (o.layout == LG_LAYOUT_PACKED && o.offset_mode == LG_OFFS_INTERLEAVED_BV &&
+        (weights || (o.id_mode != LG_IDS_GLOBAL && o.id_mode != LG_IDS_LOCAL))) {
+        set_error("lg_encode: interleaved bit-vector offsets take global or local IDs without weights");
+        return LG_ERR_UNSUPPORTED;
     }
     lg_graph *g = new (std::nothrow) lg_graph();
     if (!g) { set_error("lg_encode: host allocation failed"); return LG_ERR_OOM; }

@@ -105,6 +105,7 @@ struct BfsWork {
     DevBuf fscan;                // exclusive scan of fdeg
     DevBuf visited, curr, next;  // bitmaps, one bit per vertex
     DevBuf counters;             // [0] queue tail, [1] awakened count, [2] pending count
+    DevBuf sample;               // partial sums of the sampled bottom-up cost (8 words)
     DevBuf pv, pstart, pdeg, pw; // bottom-up: heavy vertices left for the segment pass
     DevBuf pseg_cnt, pseg_off;
     DevBuf depth_i, parent_i;    // label-space results when relabeled
@@ -160,6 +161,9 @@ struct lg_graph {
     uint64_t U = 0, universe = 0, hbits = 0;
     lg::DevBuf A, O, W, G, L, H, rank_sb, sel;  // G: gap-width table (gap mode)
     uint64_t A_words = 0, O_words = 0, W_words = 0, G_words = 0, L_words = 0, H_words = 0, n_rank = 0, n_sel = 0;
+    // interleaved bit-vector offsets (bvIL): 9 words per 512-bit block + 1
+    lg::DevBuf IL;
+    uint64_t IL_words = 0, il_blocks = 0;
 
     // plain layout
     lg::DevBuf poff, pcol;
@@ -322,6 +326,19 @@ lg_status bfs_workspace_ensure(BfsWork &w, uint64_t n, uint64_t n_heavy, bool re
 //                     queries per second than 60 at a third of the p99.
 constexpr double kBfsAlphaLatency = 60.0;
 constexpr double kBfsAlphaShared = 15.0;
+// Between the two switch points (frontier edges in (m_u/60, m_u/15]) the
+// right direction depends on how soon an unvisited vertex meets the
+// frontier: on a Kronecker graph whose lists start with the hubs, within a
+// probe or two (bottom-up wins at 60), on a uniform random graph with a
+// frontier of 1.5 % of the vertices, only after most of its list (top-down
+// wins: bottom-up at that level cost 4x the search on Erdos-Renyi scale 26).
+// There lg_bfs measures it: the bottom-up cost of a sample of vertices
+// (entries read until the first frontier neighbour), scaled to the graph,
+// against the top-down cost (the frontier's edges).  kBfsProbeCost is the
+// cost of a bottom-up entry relative to a top-down edge (a sequential read
+// and a bitmap probe against a random claim): about 1/6 on both graphs.
+constexpr double kBfsAlphaLate = 15.0;
+constexpr double kBfsProbeCost = 1.0 / 6.0;
 
 // BFS from host roots on an explicit workspace (lg_bfs without argument checks)
 lg_status bfs_run(lg_graph *g, BfsWork &w, const uint32_t *roots, uint32_t r, int32_t *depth, int32_t *parent,

@@ -250,6 +250,7 @@ void lg_server::plan(Worker &W, const lg_query &q, uint32_t batch, std::vector<R
     out.push_back({&b.curr, words * 8});
     out.push_back({&b.next, words * 8});
     out.push_back({&b.counters, 8 * 8});
+    out.push_back({&b.sample, 8 * 8});
     out.push_back({&b.pv, nh * 4});
     out.push_back({&b.pstart, nh * 8});
     out.push_back({&b.pdeg, nh * 4});

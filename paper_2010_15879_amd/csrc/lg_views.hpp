@@ -18,6 +18,14 @@ struct EFView {
     uint32_t n_hw;            // words of H
 };
 
+// Interleaved bit vector (bvIL): block j at words [9j, 9j + 9): the number of
+// ones before it, then 512 bits of the vector whose one for list v sits at
+// x_v + v.
+struct ILView {
+    const uint64_t *W;
+    uint64_t blocks;
+};
+
 // Packed offsets: value v at bits [v*w, v*w + w).
 struct POffView {
     const uint64_t *O;
@@ -32,6 +40,7 @@ struct PackedView {
     uint32_t F;               // width field bits
     POffView po;
     EFView ef;
+    ILView il;
 };
 
 struct PlainView {

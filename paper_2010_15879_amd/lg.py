@@ -27,11 +27,11 @@ STATUS_NAMES = {0: "LG_OK", 1: "LG_ERR_INVALID", 2: "LG_ERR_OOM", 3: "LG_ERR_DEV
                 4: "LG_ERR_UNSUPPORTED", 5: "LG_ERR_CAPACITY"}
 LAYOUTS = {"packed": 0, "plain": 1}
 ID_MODES = {"global": 0, "local": 1, "local-gap": 2, "varint-full": 3, "varint-diff": 4}
-OFFSET_MODES = {"packed": 0, "succinct": 1, "ef": 1}
+OFFSET_MODES = {"packed": 0, "succinct": 1, "ef": 1, "plain-bv": 2, "interleaved-bv": 3}
 DECODE_FLAGS = {"sorted": 0, "original": 1, "raw": 2}
 BFS_FLAGS = {"do": 0, "direction-opt": 0, "top-down": 1, "td": 1, "bottom-up": 2, "bu": 2}
 EXPORTS = {"adj": 0, "offsets": 1, "widths": 2, "ef_low": 3, "ef_high": 4, "ef_rank": 5,
-           "ef_select": 6, "perm": 7, "inv": 8, "gap_widths": 9, "weights": 10}
+           "ef_select": 6, "perm": 7, "inv": 8, "gap_widths": 9, "weights": 10, "bv_interleaved": 11}
 _EXPORT_DTYPE = {"ef_rank": np.uint32, "ef_select": np.uint32, "perm": np.uint32, "inv": np.uint32,
                  "weights": np.uint32}
 
