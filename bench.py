@@ -55,9 +55,16 @@ DEFAULT_WORKLOAD = "er-s26-global-packed"
 # sources whose kernels a committed counter summary describes (a summary
 # holds their hash; it no longer applies once they change)
 COUNTER_SOURCES = {
-    "pr": ["lg_pagerank.hip", "lg_device.hpp", "lg_views.hpp", "lg_heavy.hip", "lg_varint.hpp"],
+    "pr": ["lg_pagerank.hip", "lg_pagerank_pb.hip", "lg_device.hpp", "lg_views.hpp", "lg_heavy.hip",
+           "lg_varint.hpp"],
     "bfs": ["lg_bfs.hip", "lg_device.hpp", "lg_views.hpp"],
 }
+
+
+# the kernels of one PageRank iteration: the pull (iteration kernel plus the
+# sum of cut lists) or propagation blocking (two binning levels and the
+# accumulation)
+PR_KERNELS = ["pr_iter_kernel", "pr_segmented_kernel", "pb_bin1_kernel", "pb_bin2_kernel", "pb_accum_kernel"]
 
 
 def log(*a):
@@ -329,11 +336,11 @@ def main():
         for _ in range(args.warmup):
             h, _, _ = run_step(layout, opts)
             h.free()
-        # in the timed steps only the PageRank iteration kernel is timed (HIP
-        # events on the stream it runs on); timing every launch would add two
-        # events to each of the BFS lanes' many small launches
+        # in the timed steps only the PageRank iteration's kernels are timed
+        # (HIP events on the stream they run on); timing every launch would
+        # add two events to each of the BFS lanes' many small launches
         lg.prof_reset()
-        lg.prof_filter("pr_iter_kernel")
+        lg.prof_filter("|".join(PR_KERNELS))
         lg.prof_enable(True)
         torch.cuda.synchronize()
         t_begin = time.perf_counter()
@@ -345,10 +352,11 @@ def main():
         torch.cuda.synchronize()
         wall = time.perf_counter() - t_begin
         lg.prof_enable(False)
-        c_pr, ms_pr = lg.prof_query("pr_iter_kernel")
+        pr_k = {k: lg.prof_query(k) for k in PR_KERNELS}
+        pr_k = {k: v for k, v in pr_k.items() if v[0]}
         km = kernel_breakdown(layout, opts)
         return dict(info=info, l1=l1, edges_root=reached_edges, root_ms=root_ms, timings=timings,
-                    ms_per_step=wall * 1000.0 / args.steps, pr_launches=c_pr, pr_kernel_ms=ms_pr, kernels=km)
+                    ms_per_step=wall * 1000.0 / args.steps, pr_kernels=pr_k, kernels=km)
 
     def summarize(layout, r):
         tm = r["timings"]
@@ -370,8 +378,9 @@ def main():
         else:
             struct_bytes = info["bytes_adj"] + info["bytes_offsets"]
         pr_bytes = struct_bytes + 4.0 * M + 4.0 * n
-        pr_avg_ms = r["pr_kernel_ms"] / max(r["pr_launches"], 1)
-        pr_gbs = pr_bytes / (pr_avg_ms / 1000.0) / 1e9 if r["pr_launches"] else 0.0
+        iters_timed = args.steps * args.pr_iters
+        pr_avg_ms = sum(v[1] for v in r["pr_kernels"].values()) / max(iters_timed, 1)  # per iteration
+        pr_gbs = pr_bytes / (pr_avg_ms / 1000.0) / 1e9 if pr_avg_ms > 0 else 0.0
         km = r["kernels"]
         largest = max(km.items(), key=lambda kv: kv[1][1])[0] if km else None
         return dict(
@@ -385,7 +394,10 @@ def main():
                       "ms_median": ms_med, "ms_median_ci95": [ms_lo, ms_hi],
                       "ms_p50": float(np.percentile(r["root_ms"], 50)),
                       "ms_p99": float(np.percentile(r["root_ms"], 99))},
-            pr_kernel={"name": "pr_iter_kernel", "avg_launch_ms": pr_avg_ms, "launches": r["pr_launches"],
+            pr_kernel={"name": "+".join(r["pr_kernels"]), "kernels": list(r["pr_kernels"]),
+                       "avg_launch_ms": pr_avg_ms,
+                       "per_kernel_avg_ms": {k: v[1] / max(v[0], 1) for k, v in r["pr_kernels"].items()},
+                       "launches": {k: v[0] for k, v in r["pr_kernels"].items()},
                        "bytes_per_launch": pr_bytes, "achieved_gbs": pr_gbs,
                        "bytes_per_edge_algorithmic": pr_bytes / M},
             bytes={k: info[k] for k in ("bytes_adj", "bytes_offsets", "bytes_widths", "bytes_perm")},
@@ -418,22 +430,29 @@ def main():
     rooflines = {}
     for layout, s in summ.items():
         k = s["pr_kernel"]
+        # counter bytes of the iteration: the sum over its kernels, when every
+        # one has a current summary
+        parts = [measured_counters(name, args.workload, layout, "pr") for name in k["kernels"]]
+        traffic = sum(parts) if parts and all(p is not None for p in parts) else None
         rooflines[layout] = {
             "bound": "hbm", "kernel": k["name"], "achieved": round(k["achieved_gbs"], 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(k["achieved_gbs"] / HBM_PEAK_GBS, 4),
             "frac_of_achievable_copy": round(k["achieved_gbs"] / copy_gbs, 4),
-            "traffic": measured_counters(k["name"], args.workload, layout, "pr"),
+            "traffic": traffic,
             "bytes_per_launch": k["bytes_per_launch"], "avg_launch_ms": k["avg_launch_ms"],
+            "launch_unit": "one PageRank iteration (every kernel it launches)",
+            "per_kernel_avg_ms": k["per_kernel_avg_ms"],
             "bytes_per_edge_algorithmic": round(k["bytes_per_edge_algorithmic"], 4)}
         if rooflines[layout]["traffic"]:
             rooflines[layout]["bytes_per_edge_measured"] = round(rooflines[layout]["traffic"] / M, 4)
     pr_share = P["pr_kernel"]["avg_launch_ms"] * args.pr_iters
-    dominant = "pr_iter_kernel" if pr_share >= max(P["bfs_all_roots_ms"], P["encode_ms"]) else \
+    dominant = P["pr_kernel"]["name"] if pr_share >= max(P["bfs_all_roots_ms"], P["encode_ms"]) else \
         P["largest_summed_kernel"]
     roof = dict(rooflines["packed"])
     roof["dominant_kernel"] = dominant
-    roof["dominant_by"] = ("wall-time share: pr_iter_kernel time per step vs the BFS and encode phases' wall "
-                           "times, which bound every kernel inside them (BFS kernels overlap on eight lanes)")
+    roof["dominant_by"] = ("wall-time share: the PageRank iteration kernels' time per step vs the BFS and encode "
+                           "phases' wall times, which bound every kernel inside them (BFS kernels overlap on eight "
+                           "lanes)")
     ratio = None
     if "plain" in summ:
         Q = summ["plain"]

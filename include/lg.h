@@ -497,8 +497,9 @@ void lg_trim(void);
  * names, newline separated, into buf.
  */
 lg_status lg_prof_enable(int on);
-/* Time only launches whose kernel name contains substr (NULL or "": all);
- * set it while no library call is running. */
+/* Time only launches whose kernel name contains substr, or one of its
+ * '|'-separated parts (NULL or "": all); set it while no library call is
+ * running. */
 lg_status lg_prof_filter(const char *substr);
 lg_status lg_prof_reset(void);
 lg_status lg_prof_query(const char *kernel, uint64_t *launches, double *total_ms);

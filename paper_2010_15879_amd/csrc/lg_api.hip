@@ -204,9 +204,25 @@ void drain(ProfState &st, bool wait) {
 
 bool prof_on() { return prof().on; }
 
+// does the kernel name contain one of the '|'-separated filter parts?
+static bool prof_match(const char *filter, const char *name) {
+    char part[sizeof(ProfState::filter)];
+    const char *p = filter;
+    while (*p) {
+        size_t k = 0;
+        while (p[k] && p[k] != '|') ++k;
+        std::memcpy(part, p, k);
+        part[k] = 0;
+        if (k && std::strstr(name, part)) return true;
+        p += k;
+        if (*p == '|') ++p;
+    }
+    return false;
+}
+
 ProfMark prof_begin(const char *name, hipStream_t stream) {
     ProfState &st = prof();
-    if (st.filter[0] && !std::strstr(name, st.filter)) return ProfMark{};
+    if (st.filter[0] && !prof_match(st.filter, name)) return ProfMark{};
     std::lock_guard<std::mutex> g(st.mu);
     ProfMark m;
     if (st.pending.size() > 4096) drain(st, false);
@@ -296,6 +312,7 @@ extern "C" void lg_free(lg_graph *g) {
     }
     lg::bfs_free(g);
     lg::pr_free(g);
+    lg::pb_free(g);
     lg::sssp_free(g);
     delete g->dec;
     delete g;
@@ -335,7 +352,7 @@ extern "C" lg_status lg_info(const lg_graph *g, lg_graph_info *out) {
         out->bytes_widths = (g->W_words + g->G_words) * 8;
     }
     out->bytes_perm = g->perm.bytes + g->inv.bytes;
-    out->device_bytes = g->device_bytes() + lg::bfs_bytes(g) + lg::pr_bytes(g) + lg::sssp_bytes(g);
+    out->device_bytes = g->device_bytes() + lg::bfs_bytes(g) + lg::pr_bytes(g) + lg::pb_bytes(g) + lg::sssp_bytes(g);
     out->weight_bits = g->omega;
     out->bytes_weights = g->pwt.bytes;
     return LG_OK;

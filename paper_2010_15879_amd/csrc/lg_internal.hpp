@@ -96,6 +96,7 @@ namespace lg {
 // ---------------------------------------------------------------------------
 
 struct PrWork;
+struct PbWork;
 struct SsspWork;
 
 // Device workspace of one BFS at a time (grow-only buffers).
@@ -222,6 +223,7 @@ struct lg_graph {
     // lg_decode_neighbors); the server brings its own per worker
     lg::BfsWork *bfs = nullptr;
     lg::PrWork *pr = nullptr;
+    lg::PbWork *pb = nullptr;  // PageRank by propagation blocking (lg_pagerank_pb.hip)
     lg::DecodeWork *dec = nullptr;
     lg::SsspWork *sssp = nullptr;
     std::mutex sssp_mu;  // lg_sssp calls on this graph share `sssp`: one at a time
@@ -347,6 +349,12 @@ lg_status bfs_run(lg_graph *g, BfsWork &w, const uint32_t *roots, uint32_t r, in
 lg_status decode_run(lg_graph *g, DecodeWork &w, const uint32_t *vertices, uint32_t k, uint64_t *out_off,
                      uint32_t *out_ids, uint64_t cap, uint32_t flags, hipStream_t stream, uint64_t *total);
 lg_status pr_free(lg_graph *g);
+// PageRank by propagation blocking: the graphs it serves, its driver, its
+// workspace (lg_pagerank_pb.hip)
+bool pb_applies(const lg_graph *g);
+lg_status pagerank_pb(lg_graph *g, float damping, uint32_t iters, float *scores, hipStream_t s);
+uint64_t pb_bytes(const lg_graph *g);
+void pb_free(lg_graph *g);
 lg_status sssp_free(lg_graph *g);
 uint64_t sssp_bytes(const lg_graph *g);
 

@@ -392,6 +392,9 @@ static lg_status lg_pagerank_impl(const lg_graph *gc, float damping, uint32_t it
     }
     if (g->layout == LG_LAYOUT_PACKED && (g->id_mode == LG_IDS_VARINT_FULL || g->id_mode == LG_IDS_VARINT_DIFF))
         return pagerank_varint(g, damping, iters, scores, stream);
+    // contributions without locality (large unrelabeled graphs): streamed
+    // through destination bins instead of gathered
+    if (pb_applies(g)) return pagerank_pb(g, damping, iters, scores, stream);
     if (!g->pr) {
         g->pr = new (std::nothrow) PrWork();
         if (!g->pr) { set_error("lg_pagerank: host allocation failed"); return LG_ERR_OOM; }

@@ -1,0 +1,598 @@
+// PageRank by propagation blocking (the PR of section "Considered
+// Algorithms", same iteration as lg_pagerank.hip), for graphs whose labels
+// give the contribution gathers of the pull no locality: unrelabeled graphs
+// of at least 2^22 vertices.
+//
+// The pull reads contrib[u] for every stored entry at a random place of a
+// 4n-byte array; once that array outgrows the caches, every gather costs a
+// line transfer and the iteration runs at the random-access rate of the
+// memory side cache, not at the stream rate (Erdos-Renyi scale 26: 2.1e9
+// gathers, 40 ms per iteration).  Propagation blocking turns the gathers
+// into streams.  A symmetric graph's list of u is also the set of vertices
+// whose lists hold u, so reading the lists in order and sending contrib[u]
+// to every neighbour v computes the same sums:
+//
+//   level 1  the lists are read in storage order, a workgroup per equal range
+//            of entries; every entry (v, contrib[u]) goes to coarse bin
+//            v >> 20.  A workgroup takes 4,096 entries per round (their rows'
+//            offsets all loaded at once, the list loads issued together),
+//            counting-sorts them by bin in LDS and writes each bin's run
+//            whole, so the writes are long runs, not scattered words.
+//   level 2  each coarse bin is split into 64 fine bins of 2^14 vertices
+//            the same way.
+//   level 3  a workgroup per fine bin adds its entries in LDS and finalizes
+//            its vertices.
+//
+// Every (workgroup, bin) writes into its own region, whose place is fixed
+// once per graph by a counting pass (the graph does not change): no global
+// atomics.  The sums are taken in 64-bit fixed point (units of 2^-60) with
+// LDS integer atomics: exact whatever the order of the entries, so the
+// scores repeat bit for bit and carry no summation error beyond the FP32
+// rounding of each contribution.
+#include <algorithm>
+#include <vector>
+
+#include "lg_device.hpp"
+
+namespace lg {
+
+constexpr uint32_t kPbThreads = 1024;
+constexpr uint32_t kPbWaves = kPbThreads / kWave;     // 16
+constexpr uint32_t kPbSteps = 8;                       // level 2: entries per thread per round
+constexpr uint32_t kPbRound = kPbThreads * kPbSteps;   // level 2: entries per round, 8,192
+// level 1: 64-entry steps per wave per round, 4,096 entries per round, so
+// that its LDS (about 60 KB) lets two workgroups share a compute unit
+constexpr uint32_t kPb1Steps = 4;
+constexpr uint32_t kPb1Round = kPbThreads * kPb1Steps;
+constexpr uint32_t kPb1PerCU = 2;
+constexpr uint32_t kFineShift = 14;                    // fine bin: 16,384 vertices
+constexpr uint32_t kFine = 1u << kFineShift;
+constexpr uint32_t kSubBins = 64;                      // fine bins per coarse bin
+constexpr uint32_t kCoarseShift = kFineShift + 6;      // coarse bin: 2^20 vertices
+constexpr uint32_t kPbMaxCoarse = 255;                 // coarse bins fit a byte below the 0xFF sentinel
+constexpr double kFixScale = 1152921504606846976.0;    // 2^60
+constexpr double kFixUnit = 1.0 / 1152921504606846976.0;
+
+// Workgroup barrier that orders LDS only.  Threads of these kernels share
+// data through LDS alone (the bins they write to global memory are read by
+// the next kernel), so a barrier need not wait for their global stores, as
+// __syncthreads() does: the stores of one round stay in flight while the
+// next round runs.
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// below this many vertices the pull's gathers stay in cache
+constexpr uint32_t kPbMinVertices = 1u << 22;
+
+struct PbWork {
+    uint32_t nwg = 0;      // level-1 workgroups
+    uint32_t nc = 0;       // coarse bins
+    uint32_t nf = 0;       // fine bins
+    DevBuf row_lo, k_lo;   // u32[nwg]: row holding each level-1 workgroup's first entry, entries before it
+    DevBuf base1;          // u64[nwg * nc]: level-1 region start of (workgroup, coarse bin)
+    DevBuf len1;           // u32[nwg * nc]: entries of that region
+    DevBuf base2;          // u64[nwg * nc * 64]: level-2 region start of ((w, c), fine bin)
+    DevBuf fstart;         // u64[nf + 1]: fine bin starts in buf2
+    DevBuf buf1, buf2;     // uint2[m]: (local vertex, contribution bits)
+    DevBuf ca, cb;         // contribution ping-pong
+    bool built = false;
+};
+
+uint64_t pb_bytes(const lg_graph *g) {
+    if (!g->pb) return 0;
+    const PbWork &w = *g->pb;
+    return w.row_lo.bytes + w.k_lo.bytes + w.base1.bytes + w.len1.bytes + w.base2.bytes + w.fstart.bytes + w.buf1.bytes +
+           w.buf2.bytes + w.ca.bytes + w.cb.bytes;
+}
+
+void pb_free(lg_graph *g) {
+    delete g->pb;
+    g->pb = nullptr;
+}
+
+// Is propagation blocking the PageRank of this graph?  A rule of the graph
+// alone (never of timing), so that results do not depend on the run.
+bool pb_applies(const lg_graph *g) {
+    if (g->relabel != LG_RELABEL_NONE || g->weighted || g->n < kPbMinVertices) return false;
+    if (((uint64_t)g->n + (1u << kCoarseShift) - 1) >> kCoarseShift > kPbMaxCoarse) return false;
+    if (g->layout == LG_LAYOUT_PLAIN) return true;
+    return (g->id_mode == LG_IDS_GLOBAL || g->id_mode == LG_IDS_LOCAL) && g->offset_mode != LG_OFFS_INTERLEAVED_BV;
+}
+
+// ---------------------------------------------------------------------------
+// level 1: workgroup w streams entries [w m / nwg, (w + 1) m / nwg) of the
+// lists in storage order
+// ---------------------------------------------------------------------------
+
+// d_v of every vertex (a wave per 64 vertices)
+template <class Acc>
+__global__ void pb_degree_kernel(Acc acc, uint32_t n, uint32_t *__restrict__ deg) {
+    const uint64_t words = ((uint64_t)n + 63) / 64;
+    const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) / kWave;
+    for (uint64_t q = wave; q < words; q += nwaves) {
+        const VInfo vi = wave_info(acc, q * 64, n);
+        const uint64_t v = q * 64 + lane_id();
+        if (v < n) deg[v] = vi.deg;
+    }
+}
+
+// the row holding entry w m / nwg (the last row whose first entry is at or
+// before it) and the entries of that row before it
+__global__ void pb_row_lo_kernel(uint32_t n, uint64_t m, uint32_t nwg, const uint64_t *__restrict__ eoff,
+                                 uint32_t *__restrict__ row_lo, uint32_t *__restrict__ k_lo) {
+    const uint32_t w = blockIdx.x * blockDim.x + threadIdx.x;
+    if (w >= nwg) return;
+    const uint64_t e = m * w / nwg;
+    uint32_t lo = 0, hi = n - 1;  // eoff[0] = 0 <= e
+    while (lo < hi) {
+        const uint32_t mid = lo + (hi - lo + 1) / 2;
+        if (eoff[mid] <= e) lo = mid; else hi = mid - 1;
+    }
+    row_lo[w] = lo;
+    k_lo[w] = (uint32_t)(e - eoff[lo]);
+}
+
+// A window is 1,024 rows from the 64-aligned block of the first row with
+// entries left: their offsets and contributions come in once, a workgroup
+// scan gives each row's first entry within the window, and the rows with
+// entries mark those first entries in a bitmap of the window's first
+// kWinCap entries, with the marks before each 32-bit word alongside.  The
+// window then serves rounds of up to 4,096 entries until its bitmap is used
+// up: each thread takes kPb1Steps entries of the round, finds their rows by
+// the rank of the bitmap (one popcount; a binary search per entry made the
+// kernel bound by its instruction count) and issues their list loads
+// together.  Write mode: entries (v & (2^20 - 1), contrib[u]) counting-sorted
+// by coarse bin v >> 20 and written as runs at the workgroup's region
+// cursors; the counts alternate between two arrays so that folding one
+// round's counts into the cursors needs no barrier of its own.  Count mode:
+// entries per fine bin.
+constexpr uint32_t kWin = kPbThreads;           // rows per window
+constexpr uint32_t kWinCap = 32 * kPbThreads;   // window entries with a bitmap bit (one word per thread)
+constexpr uint32_t kPb1WavesPerEU = kPb1PerCU * kPbWaves / 4;  // waves per SIMD for two workgroups per CU
+
+template <class Acc, bool kCount>
+__global__ __launch_bounds__(kPbThreads, kPb1WavesPerEU) void pb_bin1_kernel(
+    Acc acc, uint32_t n, uint64_t m, uint32_t nwg, const float *__restrict__ cin,
+    const uint32_t *__restrict__ row_lo, const uint32_t *__restrict__ k_lo, uint32_t nc,
+    const uint64_t *__restrict__ base1, uint2 *__restrict__ buf1, uint32_t nf, uint32_t *__restrict__ hist_out) {
+    extern __shared__ uint32_t s_fhist[];  // count mode: entries per fine bin
+    __shared__ uint2 s_buf[kCount ? 1 : kPb1Round];   // (vertex, contribution bits) sorted by coarse bin
+    __shared__ uint32_t s_hist[2][kCount ? 1 : kPbMaxCoarse + 1];
+    __shared__ uint32_t s_start[kCount ? 1 : kPbMaxCoarse + 1];
+    __shared__ uint64_t s_cur[kCount ? 1 : kPbMaxCoarse + 1];
+    // window row t: stream position of its next entry (low word; high bits
+    // with the element width in the top byte), first entry within the
+    // window, contribution bits
+    __shared__ uint4 s_row[kWin];
+    __shared__ uint2 s_mk[kWinCap / 32];   // bitmap word, marks in the words before
+    __shared__ uint16_t s_rowk[kWin];      // window row of the k-th row with entries
+    __shared__ uint32_t s_wsum[kPbWaves], s_wnz[kPbWaves], s_wmk[kPbWaves];  // per-wave totals
+    const uint32_t lane = lane_id();
+    const uint32_t wv = threadIdx.x / kWave;
+    const uint32_t w = blockIdx.x;
+    const uint64_t e_end = m * (w + 1) / nwg;
+    if constexpr (kCount) {
+        for (uint32_t b = threadIdx.x; b < nf; b += kPbThreads) s_fhist[b] = 0;
+    } else {
+        for (uint32_t c = threadIdx.x; c < nc; c += kPbThreads) {
+            s_hist[0][c] = s_hist[1][c] = 0;
+            s_cur[c] = base1[(uint64_t)w * nc + c];
+        }
+    }
+    // the next entry: row r0, entry k0 of its list, position e in the stream
+    // (the same in every thread)
+    uint32_t r0 = row_lo[w], k0 = k_lo[w];
+    uint64_t e = m * w / nwg;
+    uint32_t par = 0;
+    // the number of bitmap marks at or before window entry j: the window row
+    // of entry j is the one with that many marks
+    auto row_of = [&](uint32_t j) -> uint32_t {
+        const uint2 mk = s_mk[j >> 5];
+        return s_rowk[mk.y + __popc(mk.x & (0xFFFFFFFFu >> (31u - (j & 31u)))) - 1];
+    };
+    while (e < e_end) {
+        // -- the window
+        if constexpr (kCount) lds_barrier();  // the last round's lookups are done
+        const uint64_t a0 = r0 & ~(uint64_t)(kWave - 1);
+        const uint64_t v = a0 + threadIdx.x;
+        const VInfo vi = wave_info(acc, a0 + (uint64_t)wv * kWave, n);
+        uint32_t d = (v >= r0 && v < n) ? vi.deg : 0u;
+        uint64_t st = vi.start;
+        if (v == r0) {
+            d -= k0;
+            st += (uint64_t)k0 * Acc::step(vi.w);
+        }
+        const float cv = d ? cin[v] : 0.f;
+        // a row past the bitmap counts as kWinCap: the sum of 1,024 rows stays
+        // in 32 bits, and every row the bitmap reaches keeps its exact start
+        const uint32_t dc = d < kWinCap ? d : kWinCap;
+        const uint32_t incl = wave_incl_scan(dc);
+        const uint32_t nzi = wave_incl_scan(d ? 1u : 0u);
+        if (lane == kWave - 1) {
+            s_wsum[wv] = incl;
+            s_wnz[wv] = nzi;
+        }
+        s_mk[threadIdx.x].x = 0;
+        lds_barrier();
+        // every wave scans the 16 wave totals itself (no barrier for a scan by one wave)
+        uint32_t total, E, k_nz;
+        {
+            const uint32_t x = lane < kPbWaves ? s_wsum[lane] : 0u;
+            const uint32_t y = lane < kPbWaves ? s_wnz[lane] : 0u;
+            const uint32_t xi = wave_incl_scan(x), yi = wave_incl_scan(y);
+            total = __shfl(xi, kPbWaves - 1, kWave);
+            E = __shfl(xi - x, wv, kWave) + incl - dc;
+            k_nz = __shfl(yi - y, wv, kWave) + nzi - 1;
+        }
+        const uint32_t jn = total < kWinCap ? total : kWinCap;
+        if (d) {
+            if (E < kWinCap) atomicOr(&s_mk[E >> 5].x, 1u << (E & 31));
+            s_rowk[k_nz] = (uint16_t)threadIdx.x;
+        }
+        s_row[threadIdx.x] = make_uint4((uint32_t)st, (uint32_t)(st >> 32) | (vi.w << 24), E, __float_as_uint(cv));
+        lds_barrier();
+        const uint32_t pc = __popc(s_mk[threadIdx.x].x);
+        const uint32_t pci = wave_incl_scan(pc);
+        if (lane == kWave - 1) s_wmk[wv] = pci;
+        lds_barrier();
+        {
+            const uint32_t x = lane < kPbWaves ? s_wmk[lane] : 0u;
+            const uint32_t xi = wave_incl_scan(x);
+            s_mk[threadIdx.x].y = __shfl(xi - x, wv, kWave) + pci - pc;
+        }
+        lds_barrier();
+        // where the next window starts
+        uint32_t nr0, nk0;
+        if (total < kWinCap) {  // the window's rows have no entries past its bitmap (a capped row makes total >= kWinCap)
+            nr0 = (uint32_t)(a0 + kWin < n ? a0 + kWin : n);
+            nk0 = 0;
+        } else {  // the bitmap ends inside row t
+            const uint32_t t = row_of(kWinCap - 1);
+            nk0 = (a0 + t == r0 ? k0 : 0u) + (kWinCap - s_row[t].z);
+            nr0 = (uint32_t)(a0 + t);
+        }
+        // -- rounds over the window's entries [j0, jn)
+        uint32_t j0 = 0;
+        while (j0 < jn && e < e_end) {
+            const uint64_t left = e_end - e;
+            uint32_t R = jn - j0;
+            if (R > kPb1Round) R = kPb1Round;
+            if (R > left) R = (uint32_t)left;
+            uint64_t e_pos[kPb1Steps];
+            uint32_t e_mask[kPb1Steps], e_val[kPb1Steps];
+            uint32_t ok = 0;
+#pragma unroll
+            for (uint32_t q = 0; q < kPb1Steps; ++q) {
+                const uint32_t i = threadIdx.x + q * kPbThreads;
+                e_pos[q] = 0;
+                e_mask[q] = e_val[q] = 0;
+                if (i < R) {
+                    const uint32_t j = j0 + i;
+                    const uint4 ri = s_row[row_of(j)];
+                    const uint32_t ww = ri.y >> 24;
+                    const uint64_t rs = ((uint64_t)(ri.y & 0xFFFFFFu) << 32) | ri.x;
+                    e_pos[q] = rs + (uint64_t)(j - ri.z) * Acc::step(ww);
+                    e_mask[q] = Acc::mask(ww);
+                    e_val[q] = ri.w;
+                    ok |= 1u << q;
+                }
+            }
+            uint32_t e_v[kPb1Steps];
+#pragma unroll
+            for (uint32_t q = 0; q < kPb1Steps; ++q) e_v[q] = ((ok >> q) & 1u) ? acc.get(e_pos[q], e_mask[q]) : 0u;
+            uint32_t e_rank[kPb1Steps];
+#pragma unroll
+            for (uint32_t q = 0; q < kPb1Steps; ++q) {
+                e_rank[q] = 0;
+                if (!((ok >> q) & 1u)) continue;
+                e_v[q] = e_v[q] < n ? e_v[q] : n - 1;  // a stored ID is < n; keeps a corrupt stream in bounds
+                if constexpr (kCount) atomicAdd(&s_fhist[e_v[q] >> kFineShift], 1u);
+                else e_rank[q] = atomicAdd(&s_hist[par][e_v[q] >> kCoarseShift], 1u);
+            }
+            if constexpr (!kCount) {
+                lds_barrier();  // ranks taken; the last round's copy-out is done
+                if (wv == 0) {
+                    // the last round's counts move the cursors; this round's give the run starts
+                    uint32_t carry = 0;
+                    for (uint32_t c0 = 0; c0 < nc; c0 += kWave) {
+                        const uint32_t c = c0 + lane;
+                        uint32_t h = 0;
+                        if (c < nc) {
+                            s_cur[c] += s_hist[par ^ 1][c];
+                            s_hist[par ^ 1][c] = 0;
+                            h = s_hist[par][c];
+                        }
+                        const uint32_t hi = wave_incl_scan(h);
+                        if (c < nc) s_start[c] = carry + hi - h;
+                        carry += __shfl(hi, kWave - 1, kWave);
+                    }
+                }
+                lds_barrier();
+#pragma unroll
+                for (uint32_t q = 0; q < kPb1Steps; ++q)
+                    if ((ok >> q) & 1u)
+                        s_buf[s_start[e_v[q] >> kCoarseShift] + e_rank[q]] = make_uint2(e_v[q], e_val[q]);
+                lds_barrier();
+                for (uint32_t i = threadIdx.x; i < R; i += kPbThreads) {
+                    const uint2 x = s_buf[i];
+                    const uint32_t c = x.x >> kCoarseShift;
+                    buf1[s_cur[c] + (i - s_start[c])] = make_uint2(x.x & ((1u << kCoarseShift) - 1u), x.y);
+                }
+                par ^= 1u;
+            }
+            j0 += R;
+            e += R;
+        }
+        r0 = nr0;
+        k0 = nk0;
+    }
+    if constexpr (kCount) {
+        lds_barrier();
+        for (uint32_t b = threadIdx.x; b < nf; b += kPbThreads) hist_out[(uint64_t)w * nf + b] = s_fhist[b];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// level 2: one workgroup per level-1 region (w, c), 64 fine bins
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(kPbThreads) void pb_bin2_kernel(const uint2 *__restrict__ buf1,
+                                                             const uint64_t *__restrict__ base1,
+                                                             const uint32_t *__restrict__ len1,
+                                                             const uint64_t *__restrict__ base2,
+                                                             uint2 *__restrict__ buf2) {
+    __shared__ uint2 s_buf[kPbRound];
+    __shared__ uint8_t s_bin[kPbRound];
+    __shared__ uint32_t s_hist[kSubBins];
+    __shared__ uint32_t s_start[kSubBins + 1];
+    __shared__ uint64_t s_cur[kSubBins];
+    const uint32_t lane = lane_id();
+    const uint32_t wv = threadIdx.x / kWave;
+    const uint64_t r = blockIdx.x;
+    const uint64_t b0 = base1[r];
+    const uint32_t len = len1[r];
+    if (threadIdx.x < kSubBins) {
+        s_hist[threadIdx.x] = 0;
+        s_cur[threadIdx.x] = base2[r * kSubBins + threadIdx.x];
+    }
+    lds_barrier();
+    for (uint32_t at = 0; at < len; at += kPbRound) {
+        uint2 e[kPbSteps];
+        uint32_t rank[kPbSteps];
+#pragma unroll
+        for (uint32_t st = 0; st < kPbSteps; ++st) {
+            const uint32_t i = at + st * kPbThreads + threadIdx.x;
+            e[st] = i < len ? buf1[b0 + i] : make_uint2(0xFFFFFFFFu, 0u);
+        }
+#pragma unroll
+        for (uint32_t st = 0; st < kPbSteps; ++st)
+            rank[st] = e[st].x != 0xFFFFFFFFu ? atomicAdd(&s_hist[e[st].x >> kFineShift], 1u) : 0u;
+        lds_barrier();
+        if (wv == 0) {
+            const uint32_t h = s_hist[lane];
+            const uint32_t incl = wave_incl_scan(h);
+            s_start[lane] = incl - h;
+            if (lane == kWave - 1) s_start[kSubBins] = incl;
+        }
+        lds_barrier();
+#pragma unroll
+        for (uint32_t st = 0; st < kPbSteps; ++st) {
+            if (e[st].x != 0xFFFFFFFFu) {
+                const uint32_t f = e[st].x >> kFineShift;
+                const uint32_t p = s_start[f] + rank[st];
+                s_buf[p] = make_uint2(e[st].x & (kFine - 1u), e[st].y);
+                s_bin[p] = (uint8_t)f;
+            }
+        }
+        lds_barrier();
+        const uint32_t total = s_start[kSubBins];
+        for (uint32_t i = threadIdx.x; i < total; i += kPbThreads) {
+            const uint32_t f = s_bin[i];
+            buf2[s_cur[f] + (i - s_start[f])] = s_buf[i];
+        }
+        lds_barrier();
+        if (threadIdx.x < kSubBins) {
+            s_cur[threadIdx.x] += s_hist[threadIdx.x];
+            s_hist[threadIdx.x] = 0;
+        }
+        lds_barrier();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// level 3: one workgroup per fine bin, exact sums, finalize
+// ---------------------------------------------------------------------------
+
+template <class Acc>
+__global__ __launch_bounds__(kPbThreads) void pb_accum_kernel(Acc acc, uint32_t n, const uint64_t *__restrict__ fstart,
+                                                              const uint2 *__restrict__ buf2, float base, float alpha,
+                                                              const uint64_t *__restrict__ iso, float *__restrict__ cout,
+                                                              float *__restrict__ scores,
+                                                              const uint32_t *__restrict__ perm) {
+    __shared__ unsigned long long s_acc[kFine];
+    const uint32_t b = blockIdx.x;
+    for (uint32_t i = threadIdx.x; i < kFine; i += kPbThreads) s_acc[i] = 0ull;
+    lds_barrier();
+    const uint64_t a = fstart[b], z = fstart[b + 1];
+    constexpr uint32_t kIn = 4;  // independent loads in flight per thread
+    for (uint64_t i = a + threadIdx.x; i < z; i += (uint64_t)kPbThreads * kIn) {
+        uint2 t[kIn];
+#pragma unroll
+        for (uint32_t q = 0; q < kIn; ++q) {
+            const uint64_t k = i + (uint64_t)q * kPbThreads;
+            t[q] = k < z ? buf2[k] : make_uint2(0u, 0u);
+        }
+#pragma unroll
+        for (uint32_t q = 0; q < kIn; ++q) {
+            // a contribution is in [0, 1]: its fixed-point value fits
+            const double x = (double)__uint_as_float(t[q].y) * kFixScale;
+            if (t[q].y) atomicAdd(&s_acc[t[q].x & (kFine - 1u)], (unsigned long long)__double2ll_rn(x));
+        }
+    }
+    lds_barrier();
+    const uint32_t lane = lane_id();
+    const uint32_t wv = threadIdx.x / kWave;
+    const uint64_t v_lo = (uint64_t)b * kFine;
+    for (uint32_t q = wv; q < kFine / kWave; q += kPbWaves) {
+        const uint64_t w0 = v_lo + (uint64_t)q * kWave;
+        if (w0 >= n) break;
+        const bool all_iso = iso[w0 / kWave] == ~0ull;
+        if (all_iso && !scores) continue;
+        const uint64_t v = w0 + lane;
+        const VInfo vi = all_iso ? VInfo{0, 0, 0} : wave_info(acc, w0, n);
+        if (v < n) {
+            const double sum = (double)(long long)s_acc[q * kWave + lane] * kFixUnit;
+            const float pr = (float)((double)base + (double)alpha * sum);
+            if (!all_iso) cout[v] = vi.deg ? pr / (float)vi.deg : 0.0f;
+            if (scores) scores[perm ? perm[v] : v] = pr;
+        }
+    }
+}
+
+// contrib_0 = PR_0 / d (0 for vertices without edges)
+template <class Acc>
+__global__ void pb_init_kernel(Acc acc, uint32_t n, double inv_n, float *__restrict__ ca, float *__restrict__ cb) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t v0 = (uint64_t)blockIdx.x * blockDim.x; v0 < n; v0 += stride) {
+        const uint64_t w0 = v0 + (threadIdx.x & ~(uint64_t)(kWave - 1));
+        const uint64_t v = w0 + lane_id();
+        const uint32_t deg = wave_info(acc, w0, n).deg;
+        if (v < n) {
+            const float c = deg ? (float)(inv_n / (double)deg) : 0.0f;
+            ca[v] = c;
+            cb[v] = c;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// host driver
+// ---------------------------------------------------------------------------
+
+template <class Acc>
+static lg_status pb_build(lg_graph *g, Acc acc, hipStream_t s) {
+    PbWork &W = *g->pb;
+    const uint32_t n = g->n;
+    int cus = 0;
+    LG_CHECK_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, g->device));
+    W.nwg = (uint32_t)std::max(1, cus) * kPb1PerCU;
+    W.nf = (uint32_t)(((uint64_t)n + kFine - 1) >> kFineShift);
+    W.nc = (W.nf + kSubBins - 1) / kSubBins;
+    // first row of every level-1 workgroup's entry range, from the element
+    // offsets (degrees, then a scan)
+    {
+        DevBuf deg, eoff, tmp;
+        LG_TRY(deg.scratch((uint64_t)n * 4, s));
+        LG_TRY(eoff.scratch(((uint64_t)n + 1) * 8, s));
+        LG_LAUNCH(pb_degree_kernel<Acc>, grid_for(((uint64_t)n + 63) / 64 * kWave, 256, 1u << 16), 256, 0, s, acc,
+                  n, deg.as<uint32_t>());
+        LG_CHECK_LAUNCH();
+        LG_TRY(exclusive_scan_u32(deg.as<uint32_t>(), eoff.as<uint64_t>(), n, tmp, s));
+        LG_TRY(W.row_lo.alloc((uint64_t)W.nwg * 4));
+        LG_TRY(W.k_lo.alloc((uint64_t)W.nwg * 4));
+        LG_LAUNCH(pb_row_lo_kernel, grid_for(W.nwg, 256, 1u << 16), 256, 0, s, n, g->m, W.nwg,
+                  (const uint64_t *)eoff.as<uint64_t>(), W.row_lo.as<uint32_t>(), W.k_lo.as<uint32_t>());
+        LG_CHECK_LAUNCH();
+        LG_CHECK_HIP(hipStreamSynchronize(s));  // the temporaries are freed here
+    }
+    // counting pass: entries of each workgroup per fine bin
+    DevBuf hist;
+    LG_TRY(hist.scratch((uint64_t)W.nwg * W.nf * 4, s));
+    LG_LAUNCH((pb_bin1_kernel<Acc, true>), W.nwg, kPbThreads, W.nf * 4, s, acc, n, g->m, W.nwg,
+              (const float *)W.ca.p, W.row_lo.as<uint32_t>(), W.k_lo.as<uint32_t>(), W.nc,
+              (const uint64_t *)nullptr, (uint2 *)nullptr, W.nf, hist.as<uint32_t>());
+    LG_CHECK_LAUNCH();
+    std::vector<uint32_t> h((uint64_t)W.nwg * W.nf);
+    LG_CHECK_HIP(hipMemcpyAsync(h.data(), hist.p, h.size() * 4, hipMemcpyDeviceToHost, s));
+    LG_CHECK_HIP(hipStreamSynchronize(s));
+    // regions: coarse bin c's level-1 data is the concatenation over w of
+    // region (w, c); fine bin b's level-2 data the concatenation over the
+    // regions (w, c) of their part for b
+    const uint32_t nwg = W.nwg, nc = W.nc, nf = W.nf;
+    std::vector<uint64_t> base1((uint64_t)nwg * nc), base2((uint64_t)nwg * nc * kSubBins, 0ull),
+        fstart((uint64_t)nf + 1, 0ull);
+    std::vector<uint32_t> len1((uint64_t)nwg * nc, 0u);
+    for (uint32_t w = 0; w < nwg; ++w)
+        for (uint32_t b = 0; b < nf; ++b) len1[(uint64_t)w * nc + b / kSubBins] += h[(uint64_t)w * nf + b];
+    uint64_t at = 0;
+    for (uint32_t c = 0; c < nc; ++c)
+        for (uint32_t w = 0; w < nwg; ++w) {
+            base1[(uint64_t)w * nc + c] = at;
+            at += len1[(uint64_t)w * nc + c];
+        }
+    if (at != g->m) {
+        set_error("lg_pagerank: propagation-blocking count %llu differs from %llu entries", (unsigned long long)at,
+                  (unsigned long long)g->m);
+        return LG_ERR_DEVICE;
+    }
+    at = 0;
+    for (uint32_t b = 0; b < nf; ++b) {
+        fstart[b] = at;
+        const uint32_t c = b / kSubBins, f = b % kSubBins;
+        for (uint32_t w = 0; w < nwg; ++w) {
+            base2[((uint64_t)w * nc + c) * kSubBins + f] = at;
+            at += h[(uint64_t)w * nf + b];
+        }
+    }
+    fstart[nf] = at;
+    LG_TRY(W.base1.alloc(base1.size() * 8));
+    LG_TRY(W.len1.alloc(len1.size() * 4));
+    LG_TRY(W.base2.alloc(base2.size() * 8));
+    LG_TRY(W.fstart.alloc(fstart.size() * 8));
+    LG_CHECK_HIP(hipMemcpyAsync(W.base1.p, base1.data(), base1.size() * 8, hipMemcpyHostToDevice, s));
+    LG_CHECK_HIP(hipMemcpyAsync(W.len1.p, len1.data(), len1.size() * 4, hipMemcpyHostToDevice, s));
+    LG_CHECK_HIP(hipMemcpyAsync(W.base2.p, base2.data(), base2.size() * 8, hipMemcpyHostToDevice, s));
+    LG_CHECK_HIP(hipMemcpyAsync(W.fstart.p, fstart.data(), fstart.size() * 8, hipMemcpyHostToDevice, s));
+    LG_TRY(W.buf1.alloc((g->m ? g->m : 1) * 8));
+    LG_TRY(W.buf2.alloc((g->m ? g->m : 1) * 8));
+    LG_CHECK_HIP(hipStreamSynchronize(s));  // the host vectors go out of scope
+    W.built = true;
+    return LG_OK;
+}
+
+lg_status pagerank_pb(lg_graph *g, float damping, uint32_t iters, float *scores, hipStream_t s) {
+    if (!g->pb) {
+        g->pb = new (std::nothrow) PbWork();
+        if (!g->pb) { set_error("lg_pagerank: host allocation failed"); return LG_ERR_OOM; }
+    }
+    PbWork &W = *g->pb;
+    const uint32_t n = g->n;
+    if (W.ca.bytes < (uint64_t)n * 4) LG_TRY(W.ca.alloc((uint64_t)n * 4));
+    if (W.cb.bytes < (uint64_t)n * 4) LG_TRY(W.cb.alloc((uint64_t)n * 4));
+    const uint32_t *perm = g->relabel != LG_RELABEL_NONE ? g->perm.as<uint32_t>() : nullptr;
+    const double nd = (double)n, a = damping, z = g->isolated;
+    return dispatch_acc(g, [&](auto acc) -> lg_status {
+        using Acc = decltype(acc);
+        if (!W.built) LG_TRY(pb_build<Acc>(g, acc, s));
+        float *cin = W.ca.as<float>(), *cout = W.cb.as<float>();
+        LG_LAUNCH(pb_init_kernel<Acc>, grid_for(n, 256, 1u << 16), 256, 0, s, acc, n, 1.0 / nd, cin, cout);
+        LG_CHECK_LAUNCH();
+        double D = z / nd;
+        for (uint32_t t = 0; t < iters; ++t) {
+            const double b = (1.0 - a) / nd + a * D / nd;
+            const bool last = t + 1 == iters;
+            if (g->m) {
+                LG_LAUNCH((pb_bin1_kernel<Acc, false>), W.nwg, kPbThreads, 0, s, acc, n, g->m, W.nwg,
+                          (const float *)cin, W.row_lo.as<uint32_t>(), W.k_lo.as<uint32_t>(), W.nc,
+                          W.base1.as<uint64_t>(), W.buf1.as<uint2>(), W.nf, (uint32_t *)nullptr);
+                LG_CHECK_LAUNCH();
+                LG_LAUNCH(pb_bin2_kernel, W.nwg * W.nc, kPbThreads, 0, s, (const uint2 *)W.buf1.p,
+                          W.base1.as<uint64_t>(), W.len1.as<uint32_t>(), W.base2.as<uint64_t>(), W.buf2.as<uint2>());
+                LG_CHECK_LAUNCH();
+            }
+            LG_LAUNCH(pb_accum_kernel<Acc>, W.nf, kPbThreads, 0, s, acc, n, W.fstart.as<uint64_t>(),
+                      (const uint2 *)W.buf2.p, (float)b, (float)a, g->iso.as<uint64_t>(), cout,
+                      last ? scores : (float *)nullptr, last ? perm : (const uint32_t *)nullptr);
+            LG_CHECK_LAUNCH();
+            D = z * b;
+            std::swap(cin, cout);
+        }
+        return LG_OK;
+    });
+}
+
+}  // namespace lg
