@@ -241,26 +241,49 @@ __global__ __launch_bounds__(kTdThreads) void td_expand_kernel(
         __syncthreads();
         // every thread decodes its (up to) kTdEdgesPerThread edges, keeps the
         // vertices it claimed, and the block reserves queue space once
+        // in phases, so that a thread's list loads and then its bitmap loads
+        // are in flight together: a load under a per-edge branch waits for its
+        // data before the branch ends.  An idle slot reads stream position 0
+        // with mask 0 (the level has edges, so the stream holds one) and then
+        // bitmap word 0.
+        uint64_t epos[kTdEdgesPerThread];
+        uint32_t msk[kTdEdgesPerThread], src[kTdEdgesPerThread];
+        uint32_t live = 0;
+#pragma unroll
+        for (int r = 0; r < kTdEdgesPerThread; ++r) {
+            const uint64_t e = e0 + (uint64_t)r * kTdThreads + threadIdx.x;
+            epos[r] = 0;
+            msk[r] = src[r] = 0;
+            if (e < e1) {
+                uint64_t base_e, start;
+                uint32_t w, v;
+                if (staged) {
+                    const uint32_t j = last_le(s_scan, 0, span - 1, e);
+                    base_e = s_scan[j]; start = s_start[j]; w = s_w[j]; v = s_v[j];
+                } else {
+                    const uint32_t j = last_le(fscan, i0, s_range[1], e);
+                    base_e = fscan[j]; start = fstart[j]; w = fw[j]; v = queue[j];
+                }
+                epos[r] = start + (e - base_e) * Acc::step(w);
+                msk[r] = Acc::mask(w);
+                src[r] = v;
+                live |= 1u << r;
+            }
+        }
+        uint32_t u[kTdEdgesPerThread];
+        uint64_t vw[kTdEdgesPerThread];
+#pragma unroll
+        for (int r = 0; r < kTdEdgesPerThread; ++r) u[r] = acc.get(epos[r], msk[r]);
+#pragma unroll
+        for (int r = 0; r < kTdEdgesPerThread; ++r) vw[r] = visited[u[r] >> 6];
         uint32_t won[kTdEdgesPerThread];
         uint32_t nwon = 0;
 #pragma unroll
         for (int r = 0; r < kTdEdgesPerThread; ++r) {
-            const uint64_t e = e0 + (uint64_t)r * kTdThreads + threadIdx.x;
-            if (e >= e1) continue;
-            uint64_t base_e, start;
-            uint32_t w, v;
-            if (staged) {
-                const uint32_t j = last_le(s_scan, 0, span - 1, e);
-                base_e = s_scan[j]; start = s_start[j]; w = s_w[j]; v = s_v[j];
-            } else {
-                const uint32_t j = last_le(fscan, i0, s_range[1], e);
-                base_e = fscan[j]; start = fstart[j]; w = fw[j]; v = queue[j];
-            }
-            const uint32_t u = acc.get(start + (e - base_e) * Acc::step(w), Acc::mask(w));
-            if (!((visited[u >> 6] >> (u & 63)) & 1ull)) {
-                const int32_t old = atomicCAS(&depth[u], -1, next_depth);
-                if (kParent && (old == -1 || old == next_depth)) atomicMin(&parent[u], v);
-                if (old == -1) won[nwon++] = u;
+            if (((live >> r) & 1u) && !((vw[r] >> (u[r] & 63)) & 1ull)) {
+                const int32_t old = atomicCAS(&depth[u[r]], -1, next_depth);
+                if (kParent && (old == -1 || old == next_depth)) atomicMin(&parent[u[r]], src[r]);
+                if (old == -1) won[nwon++] = u[r];
             }
         }
         // block exclusive scan of the claim counts, one atomic per tile

@@ -206,7 +206,8 @@ __global__ __launch_bounds__(kPbThreads, kPb1WavesPerEU) void pb_bin1_kernel(
             d -= k0;
             st += (uint64_t)k0 * Acc::step(vi.w);
         }
-        const float cv = d ? cin[v] : 0.f;
+        const float cl = cin[v < n ? v : n - 1];  // unconditional (see the entry loads below)
+        const float cv = d ? cl : 0.f;
         // a row past the bitmap counts as kWinCap: the sum of 1,024 rows stays
         // in 32 bits, and every row the bitmap reaches keeps its exact start
         const uint32_t dc = d < kWinCap ? d : kWinCap;
@@ -224,7 +225,7 @@ __global__ __launch_bounds__(kPbThreads, kPb1WavesPerEU) void pb_bin1_kernel(
             const uint32_t x = lane < kPbWaves ? s_wsum[lane] : 0u;
             const uint32_t y = lane < kPbWaves ? s_wnz[lane] : 0u;
             const uint32_t xi = wave_incl_scan(x), yi = wave_incl_scan(y);
-            total = __shfl(xi, kPbWaves - 1, kWave);
+            total = __builtin_amdgcn_readfirstlane(__shfl(xi, kPbWaves - 1, kWave));  // uniform: a scalar register
             E = __shfl(xi - x, wv, kWave) + incl - dc;
             k_nz = __shfl(yi - y, wv, kWave) + nzi - 1;
         }
@@ -251,8 +252,8 @@ __global__ __launch_bounds__(kPbThreads, kPb1WavesPerEU) void pb_bin1_kernel(
             nr0 = (uint32_t)(a0 + kWin < n ? a0 + kWin : n);
             nk0 = 0;
         } else {  // the bitmap ends inside row t
-            const uint32_t t = row_of(kWinCap - 1);
-            nk0 = (a0 + t == r0 ? k0 : 0u) + (kWinCap - s_row[t].z);
+            const uint32_t t = __builtin_amdgcn_readfirstlane(row_of(kWinCap - 1));
+            nk0 = (a0 + t == r0 ? k0 : 0u) + (kWinCap - __builtin_amdgcn_readfirstlane(s_row[t].z));
             nr0 = (uint32_t)(a0 + t);
         }
         // -- rounds over the window's entries [j0, jn)
@@ -281,9 +282,13 @@ __global__ __launch_bounds__(kPbThreads, kPb1WavesPerEU) void pb_bin1_kernel(
                     ok |= 1u << q;
                 }
             }
+            // every slot loads (an idle one reads position 0 with mask 0: the
+            // stream holds an entry, and its pad word keeps the read in
+            // bounds); a load under a branch waits for its data before the
+            // branch ends, which would leave one load per wave in flight
             uint32_t e_v[kPb1Steps];
 #pragma unroll
-            for (uint32_t q = 0; q < kPb1Steps; ++q) e_v[q] = ((ok >> q) & 1u) ? acc.get(e_pos[q], e_mask[q]) : 0u;
+            for (uint32_t q = 0; q < kPb1Steps; ++q) e_v[q] = acc.get(e_pos[q], e_mask[q]);
             uint32_t e_rank[kPb1Steps];
 #pragma unroll
             for (uint32_t q = 0; q < kPb1Steps; ++q) {
@@ -340,15 +345,16 @@ __global__ __launch_bounds__(kPbThreads, kPb1WavesPerEU) void pb_bin1_kernel(
 // level 2: one workgroup per level-1 region (w, c), 64 fine bins
 // ---------------------------------------------------------------------------
 
-__global__ __launch_bounds__(kPbThreads) void pb_bin2_kernel(const uint2 *__restrict__ buf1,
-                                                             const uint64_t *__restrict__ base1,
-                                                             const uint32_t *__restrict__ len1,
-                                                             const uint64_t *__restrict__ base2,
-                                                             uint2 *__restrict__ buf2) {
-    __shared__ uint2 s_buf[kPbRound];
-    __shared__ uint8_t s_bin[kPbRound];
-    __shared__ uint32_t s_hist[kSubBins];
-    __shared__ uint32_t s_start[kSubBins + 1];
+static_assert(kSubBins == kWave, "level 2 scans its fine bins with one wave");
+
+__global__ __launch_bounds__(kPbThreads, kPb1WavesPerEU) void pb_bin2_kernel(const uint2 *__restrict__ buf1,
+                                                                             const uint64_t *__restrict__ base1,
+                                                                             const uint32_t *__restrict__ len1,
+                                                                             const uint64_t *__restrict__ base2,
+                                                                             uint2 *__restrict__ buf2) {
+    __shared__ uint2 s_buf[kPbRound];  // entries sorted by fine bin (bits 14..19 of the local vertex)
+    __shared__ uint32_t s_hist[2][kSubBins];
+    __shared__ uint32_t s_start[kSubBins];
     __shared__ uint64_t s_cur[kSubBins];
     const uint32_t lane = lane_id();
     const uint32_t wv = threadIdx.x / kWave;
@@ -356,50 +362,49 @@ __global__ __launch_bounds__(kPbThreads) void pb_bin2_kernel(const uint2 *__rest
     const uint64_t b0 = base1[r];
     const uint32_t len = len1[r];
     if (threadIdx.x < kSubBins) {
-        s_hist[threadIdx.x] = 0;
+        s_hist[0][threadIdx.x] = s_hist[1][threadIdx.x] = 0;
         s_cur[threadIdx.x] = base2[r * kSubBins + threadIdx.x];
     }
+    // round k + 1's entries are loaded while round k is sorted and written
+    uint2 nx[kPbSteps];
+    auto load = [&](uint32_t at) {
+#pragma unroll
+        for (uint32_t st = 0; st < kPbSteps; ++st) {
+            const uint32_t i = at + st * kPbThreads + threadIdx.x;
+            nx[st] = i < len ? buf1[b0 + i] : make_uint2(0xFFFFFFFFu, 0u);
+        }
+    };
+    load(0);
     lds_barrier();
+    uint32_t par = 0;
     for (uint32_t at = 0; at < len; at += kPbRound) {
         uint2 e[kPbSteps];
         uint32_t rank[kPbSteps];
 #pragma unroll
         for (uint32_t st = 0; st < kPbSteps; ++st) {
-            const uint32_t i = at + st * kPbThreads + threadIdx.x;
-            e[st] = i < len ? buf1[b0 + i] : make_uint2(0xFFFFFFFFu, 0u);
+            e[st] = nx[st];
+            rank[st] = e[st].x != 0xFFFFFFFFu ? atomicAdd(&s_hist[par][e[st].x >> kFineShift], 1u) : 0u;
         }
+        if (at + kPbRound < len) load(at + kPbRound);
+        lds_barrier();  // ranks taken; the last round's copy-out is done
+        if (wv == 0) {  // the last round's counts move the cursors; this round's give the run starts
+            s_cur[lane] += s_hist[par ^ 1][lane];
+            s_hist[par ^ 1][lane] = 0;
+            const uint32_t h = s_hist[par][lane];
+            s_start[lane] = wave_incl_scan(h) - h;
+        }
+        lds_barrier();
 #pragma unroll
         for (uint32_t st = 0; st < kPbSteps; ++st)
-            rank[st] = e[st].x != 0xFFFFFFFFu ? atomicAdd(&s_hist[e[st].x >> kFineShift], 1u) : 0u;
+            if (e[st].x != 0xFFFFFFFFu) s_buf[s_start[e[st].x >> kFineShift] + rank[st]] = e[st];
         lds_barrier();
-        if (wv == 0) {
-            const uint32_t h = s_hist[lane];
-            const uint32_t incl = wave_incl_scan(h);
-            s_start[lane] = incl - h;
-            if (lane == kWave - 1) s_start[kSubBins] = incl;
-        }
-        lds_barrier();
-#pragma unroll
-        for (uint32_t st = 0; st < kPbSteps; ++st) {
-            if (e[st].x != 0xFFFFFFFFu) {
-                const uint32_t f = e[st].x >> kFineShift;
-                const uint32_t p = s_start[f] + rank[st];
-                s_buf[p] = make_uint2(e[st].x & (kFine - 1u), e[st].y);
-                s_bin[p] = (uint8_t)f;
-            }
-        }
-        lds_barrier();
-        const uint32_t total = s_start[kSubBins];
+        const uint32_t total = len - at < kPbRound ? len - at : kPbRound;
         for (uint32_t i = threadIdx.x; i < total; i += kPbThreads) {
-            const uint32_t f = s_bin[i];
-            buf2[s_cur[f] + (i - s_start[f])] = s_buf[i];
+            const uint2 x = s_buf[i];
+            const uint32_t f = x.x >> kFineShift;
+            buf2[s_cur[f] + (i - s_start[f])] = make_uint2(x.x & (kFine - 1u), x.y);
         }
-        lds_barrier();
-        if (threadIdx.x < kSubBins) {
-            s_cur[threadIdx.x] += s_hist[threadIdx.x];
-            s_hist[threadIdx.x] = 0;
-        }
-        lds_barrier();
+        par ^= 1u;
     }
 }
 
@@ -418,19 +423,22 @@ __global__ __launch_bounds__(kPbThreads) void pb_accum_kernel(Acc acc, uint32_t 
     for (uint32_t i = threadIdx.x; i < kFine; i += kPbThreads) s_acc[i] = 0ull;
     lds_barrier();
     const uint64_t a = fstart[b], z = fstart[b + 1];
-    constexpr uint32_t kIn = 4;  // independent loads in flight per thread
+    constexpr uint32_t kIn = 8;  // independent loads in flight per thread (one workgroup per CU)
     for (uint64_t i = a + threadIdx.x; i < z; i += (uint64_t)kPbThreads * kIn) {
+        // unconditional loads at clamped indexes: a load under a branch waits
+        // for its data before the branch ends, one load per wave in flight
         uint2 t[kIn];
 #pragma unroll
         for (uint32_t q = 0; q < kIn; ++q) {
             const uint64_t k = i + (uint64_t)q * kPbThreads;
-            t[q] = k < z ? buf2[k] : make_uint2(0u, 0u);
+            t[q] = buf2[k < z ? k : z - 1];
         }
 #pragma unroll
         for (uint32_t q = 0; q < kIn; ++q) {
             // a contribution is in [0, 1]: its fixed-point value fits
             const double x = (double)__uint_as_float(t[q].y) * kFixScale;
-            if (t[q].y) atomicAdd(&s_acc[t[q].x & (kFine - 1u)], (unsigned long long)__double2ll_rn(x));
+            if (t[q].y && i + (uint64_t)q * kPbThreads < z)
+                atomicAdd(&s_acc[t[q].x & (kFine - 1u)], (unsigned long long)__double2ll_rn(x));
         }
     }
     lds_barrier();
