@@ -351,6 +351,8 @@ def main():
             h.free()
         torch.cuda.synchronize()
         wall = time.perf_counter() - t_begin
+        log(f"[bench] {layout} timed steps (encode / BFS / PageRank ms): " +
+            "; ".join(f"{t['encode']:.0f}/{t['bfs']:.0f}/{t['pr']:.0f}" for t in timings))
         lg.prof_enable(False)
         pr_k = {k: lg.prof_query(k) for k in PR_KERNELS}
         pr_k = {k: v for k, v in pr_k.items() if v[0]}
@@ -362,6 +364,7 @@ def main():
         tm = r["timings"]
         bfs_ms = float(np.mean([t["bfs"] for t in tm]))
         pr_ms = float(np.mean([t["pr"] for t in tm]))
+        step_ms = np.array([t["encode"] + t["bfs"] + t["pr"] for t in tm])
         enc_ms = float(np.mean([t["encode"] for t in tm]))
         edges_root = r["edges_root"]
         pr_edges = args.pr_iters * (M / 2.0)
@@ -385,6 +388,8 @@ def main():
         largest = max(km.items(), key=lambda kv: kv[1][1])[0] if km else None
         return dict(
             value=step_edges / (r["ms_per_step"] / 1000.0) / 1e9, ms_per_step=r["ms_per_step"],
+            step_ms_events={"p50": float(np.percentile(step_ms, 50)), "p90": float(np.percentile(step_ms, 90)),
+                            "min": float(step_ms.min()), "max": float(step_ms.max())},
             gteps_traversal=step_edges / ((bfs_ms + pr_ms) / 1000.0) / 1e9,
             encode_ms=enc_ms, encode_gedges_s=M / (enc_ms / 1000.0) / 1e9,
             bfs_all_roots_ms=bfs_ms, bfs_gteps_all_roots=sum(edges_root) / (bfs_ms / 1000.0) / 1e9,

@@ -484,9 +484,12 @@ const char *lg_last_error(void);
  * PageRank tables, when lg_free releases them) go to a per-process cache for
  * the next request on the same device and stream, instead of being freed, so
  * that repeated encodes neither allocate nor synchronize the device to free.
- * The cache holds at most 64 GiB.  lg_trim frees it, and the per-device
- * workspaces of multi-root lg_bfs calls.  Call it when no library call is
- * running. */
+ * The cache holds at most 64 GiB.  The two bin buffers of a PageRank by
+ * propagation blocking (8 bytes per stored entry each) are kept apart from
+ * it: lg_free parks the pair of one graph per device for the next graph of
+ * about the same size.  lg_trim frees the cache, that pair, and the
+ * per-device workspaces of multi-root lg_bfs calls.  Call it when no library
+ * call is running. */
 void lg_trim(void);
 
 /*

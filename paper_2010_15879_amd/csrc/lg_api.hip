@@ -440,6 +440,7 @@ extern "C" const char *lg_last_error(void) { return lg::t_err; }
 
 extern "C" void lg_trim(void) {
     lg::bfs_pools_trim();
+    lg::pb_trim();
     lg::Pool &pl = lg::pool();
     std::lock_guard<std::mutex> g(pl.mu);
     for (const lg::Cached &c : pl.list) (void)hipFree(c.p);

@@ -355,6 +355,7 @@ bool pb_applies(const lg_graph *g);
 lg_status pagerank_pb(lg_graph *g, float damping, uint32_t iters, float *scores, hipStream_t s);
 uint64_t pb_bytes(const lg_graph *g);
 void pb_free(lg_graph *g);
+void pb_trim();  // frees the bin buffers parked for the next graph
 lg_status sssp_free(lg_graph *g);
 uint64_t sssp_bytes(const lg_graph *g);
 

@@ -88,9 +88,63 @@ uint64_t pb_bytes(const lg_graph *g) {
            w.buf2.bytes + w.ca.bytes + w.cb.bytes;
 }
 
+// The two bin buffers (8 B per stored entry each) outlive their graph in one
+// slot per device: the next graph of about the same size takes them without
+// an allocation, which at this size can stall for hundreds of milliseconds.
+// lg_free parks them only after the graph's last use, so whoever takes them
+// finds them idle; lg_trim frees them.
+namespace {
+constexpr int kPbSlots = 64;  // devices
+struct PbSlot {
+    DevBuf buf1, buf2;
+};
+std::mutex g_pb_slot_mu;
+PbSlot *pb_slots() {
+    static PbSlot *p = new PbSlot[kPbSlots];  // never destroyed: no frees during static teardown
+    return p;
+}
+}  // namespace
+
 void pb_free(lg_graph *g) {
+    if (g->pb && g->pb->built && g->device >= 0 && g->device < kPbSlots) {
+        std::lock_guard<std::mutex> lk(g_pb_slot_mu);
+        PbSlot &sl = pb_slots()[g->device];
+        if (!sl.buf1.p || sl.buf1.bytes < g->pb->buf1.bytes) {  // keep the larger pair
+            sl.buf1 = std::move(g->pb->buf1);
+            sl.buf2 = std::move(g->pb->buf2);
+        }
+    }
     delete g->pb;
     g->pb = nullptr;
+}
+
+void pb_trim() {
+    std::lock_guard<std::mutex> lk(g_pb_slot_mu);
+    for (int d = 0; d < kPbSlots; ++d) {
+        pb_slots()[d].buf1.release();
+        pb_slots()[d].buf2.release();
+    }
+}
+
+// bin buffers of `bytes` each: the parked pair when it fits (at most a
+// quarter larger), else new ones (a parked pair that does not fit is freed
+// first, so that its memory is available)
+static lg_status pb_take_bins(lg_graph *g, uint64_t bytes) {
+    PbWork &W = *g->pb;
+    if (g->device >= 0 && g->device < kPbSlots) {
+        std::lock_guard<std::mutex> lk(g_pb_slot_mu);
+        PbSlot &sl = pb_slots()[g->device];
+        if (sl.buf1.p && sl.buf1.bytes >= bytes && sl.buf1.bytes <= bytes + bytes / 4) {
+            W.buf1 = std::move(sl.buf1);
+            W.buf2 = std::move(sl.buf2);
+            return LG_OK;
+        }
+        sl.buf1.release();
+        sl.buf2.release();
+    }
+    LG_TRY(W.buf1.alloc(bytes));
+    LG_TRY(W.buf2.alloc(bytes));
+    return LG_OK;
 }
 
 // Is propagation blocking the PageRank of this graph?  A rule of the graph
@@ -555,8 +609,7 @@ static lg_status pb_build(lg_graph *g, Acc acc, hipStream_t s) {
     LG_CHECK_HIP(hipMemcpyAsync(W.len1.p, len1.data(), len1.size() * 4, hipMemcpyHostToDevice, s));
     LG_CHECK_HIP(hipMemcpyAsync(W.base2.p, base2.data(), base2.size() * 8, hipMemcpyHostToDevice, s));
     LG_CHECK_HIP(hipMemcpyAsync(W.fstart.p, fstart.data(), fstart.size() * 8, hipMemcpyHostToDevice, s));
-    LG_TRY(W.buf1.alloc((g->m ? g->m : 1) * 8));
-    LG_TRY(W.buf2.alloc((g->m ? g->m : 1) * 8));
+    LG_TRY(pb_take_bins(g, (g->m ? g->m : 1) * 8));
     LG_CHECK_HIP(hipStreamSynchronize(s));  // the host vectors go out of scope
     W.built = true;
     return LG_OK;
