@@ -67,6 +67,22 @@ COUNTER_SOURCES = {
 PR_KERNELS = ["pr_iter_kernel", "pr_segmented_kernel", "pb_bin1_kernel", "pb_bin2_kernel", "pb_accum_kernel"]
 
 
+# counter passes of a counter summary: each runs the same counter-run
+# command under rocprofv3 --pmc with these counters (at most 4 TCC counters
+# per pass)
+COUNTER_PASSES = {
+    "fetch": ["FETCH_SIZE"],
+    "write": ["WRITE_SIZE"],
+    "rdreq": ["TCC_EA0_RDREQ_32B_sum", "TCC_EA0_RDREQ_64B_sum", "TCC_EA0_RDREQ_128B_sum", "TCC_EA0_RDREQ_sum"],
+    "wrreq": ["TCC_EA0_WRREQ_sum", "TCC_EA0_WRREQ_64B_sum", "TCC_EA0_RDREQ_DRAM_sum", "TCC_EA0_WRREQ_DRAM_sum"],
+}
+COUNTER_KERNEL_REGEX = "sqrt|cos|lg::"
+
+
+def counters_path(workload: str, layout: str, phase: str) -> str:
+    return os.path.join(ROOT, "profiles", f"counters_{workload}_{layout}_{phase}.md")
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -80,24 +96,162 @@ def source_hash(phase: str) -> str:
     return h.hexdigest()
 
 
-def measured_counters(kernel: str, workload: str, layout: str, phase: str):
-    """HBM bytes per launch of `kernel` (FETCH_SIZE + WRITE_SIZE, calibrated)
-    from the committed counter summary profiles/<kernel>_<workload>_<layout>_
-    counters.md, or None when there is none or the sources changed since."""
-    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_{layout}_counters.md")
+def measured_counters(key: str, workload: str, layout: str, phase: str):
+    """A figure of the committed counter summary profiles/counters_<workload>_
+    <layout>_<phase>.md (`traffic_bytes_per_launch.<kernel>`: HBM bytes per
+    launch, FETCH_SIZE + WRITE_SIZE calibrated; `traffic_bytes_per_phase`),
+    or None when there is none or the sources changed since."""
+    path = counters_path(workload, layout, phase)
     if not os.path.exists(path):
         return None
     vals = {}
     for line in open(path).read().splitlines():
-        if ": " in line and not line.startswith(("#", "|", "`")):
+        if ": " in line and not line.startswith(("#", "|", "`", "-")):
             k, v = line.split(": ", 1)
             vals[k.strip()] = v.strip()
     if vals.get("source_sha256") != source_hash(phase):
         return None
     try:
-        return float(vals["traffic_bytes_per_launch"])
+        return float(vals[key])
     except (KeyError, ValueError):
         return None
+
+
+def _kernel_key(name: str) -> str:
+    """Base name of a kernel in a trace ("void lg::pb_bin1_kernel<lg::PlainAcc<
+    false>, true>(...)" -> "pb_bin1_kernel[count]" for the counting instance)."""
+    base = name.split("(")[0]
+    tmpl = base[base.find("<"):] if "<" in base else ""
+    base = base.split("<")[0].replace("void ", "").strip()
+    base = base.split("::")[-1]
+    if base == "pb_bin1_kernel" and tmpl.rstrip(">").rstrip().endswith("true"):
+        base += "[count]"
+    return base
+
+
+def counter_summary_main(args):
+    """Summary of one counter-run under the passes of COUNTER_PASSES: the
+    calibration factors (what each counter reads for the elementwise kernel
+    of known bytes), each phase kernel's bytes per launch, and the phase's
+    total; written as text with the commands that made it."""
+    import csv
+    import statistics
+    d = args.counter_summary
+    run = json.loads(open(os.path.join(d, "run.json")).read().strip().splitlines()[-1])
+    per = {}   # counter -> list of (dispatch, kernel name, value)
+    for pas, ctrs in COUNTER_PASSES.items():
+        files = [os.path.join(dp, f) for dp, _, fs in os.walk(os.path.join(d, pas)) for f in fs
+                 if f.endswith("counter_collection.csv")]
+        if not files:
+            raise SystemExit(f"counter summary: no counter_collection.csv under {d}/{pas}")
+        rows = list(csv.DictReader(open(files[0])))
+        for c in ctrs:
+            got = sorted((int(r["Dispatch_Id"]), r["Kernel_Name"], float(r["Counter_Value"]))
+                         for r in rows if r["Counter_Name"] == c)
+            per[c] = got
+    def split(c):
+        rows = per[c]
+        cal = [v for _, k, v in rows if "sqrt" in k]
+        marks = [i for i, (_, k, _) in enumerate(rows) if "cos" in k and "lg::" not in k]
+        phase = rows[marks[-1] + 1:] if marks else []
+        return cal, phase
+    cal_bytes = run["calibration_bytes"] // 2   # read = written = half
+    factor, cal_raw = {}, {}
+    for c in per:
+        cal, _ = split(c)
+        cal_raw[c] = statistics.median(cal) if cal else float("nan")
+    # bytes each counter set gives for the calibration kernel
+    rd_req = lambda x: 32 * x["TCC_EA0_RDREQ_32B_sum"] + 64 * x["TCC_EA0_RDREQ_64B_sum"] + \
+        128 * x["TCC_EA0_RDREQ_128B_sum"]  # noqa: E731
+    wr_req = lambda x: 64 * x["TCC_EA0_WRREQ_64B_sum"] + 32 * (x["TCC_EA0_WRREQ_sum"] - x["TCC_EA0_WRREQ_64B_sum"])  # noqa: E731
+    factor["FETCH_SIZE"] = cal_bytes / (cal_raw["FETCH_SIZE"] * 1024.0)
+    factor["WRITE_SIZE"] = cal_bytes / (cal_raw["WRITE_SIZE"] * 1024.0)
+    factor["rdreq"] = cal_bytes / rd_req(cal_raw)
+    factor["wrreq"] = cal_bytes / wr_req(cal_raw)
+    # phase dispatches, kernel by kernel (the passes run the same launches in
+    # the same order)
+    phase = {c: split(c)[1] for c in per}
+    nd = {c: len(v) for c, v in phase.items()}
+    if len(set(nd.values())) != 1:
+        raise SystemExit(f"counter summary: passes saw different phase dispatch counts {nd}")
+    kernels = {}
+    for i in range(next(iter(nd.values()))):
+        name = phase["FETCH_SIZE"][i][1]
+        x = {c: phase[c][i][2] for c in per}
+        rec = kernels.setdefault(_kernel_key(name), [])
+        rec.append(dict(fetch=x["FETCH_SIZE"] * 1024.0 * factor["FETCH_SIZE"],
+                        write=x["WRITE_SIZE"] * 1024.0 * factor["WRITE_SIZE"],
+                        rdreq=rd_req(x), wrreq=wr_req(x),
+                        r32=x["TCC_EA0_RDREQ_32B_sum"], r64=x["TCC_EA0_RDREQ_64B_sum"],
+                        r128=x["TCC_EA0_RDREQ_128B_sum"], rdram=x["TCC_EA0_RDREQ_DRAM_sum"],
+                        rtot=x["TCC_EA0_RDREQ_sum"]))
+    m = run["stored_edges"]
+    phase_name = {"pr": f"one PageRank call of {run['pr_iters']} iterations (with its first-call setup)",
+                  "bfs": f"single-root BFS, modes {run.get('bfs_modes')}"}[run["phase"]]
+    cmd_of = lambda pas: (f"timeout -s KILL 300 rocprofv3 --pmc {' '.join(COUNTER_PASSES[pas])} "  # noqa: E731
+                          f"--kernel-include-regex \"{COUNTER_KERNEL_REGEX}\" --output-format csv "
+                          f"-d gpurun_out/cnt/{args.workload}_{args.layout}_{run['phase']}/{pas} -o {pas} -- "
+                          f"python3 bench.py --workload {args.workload} --counter-run {run['phase']} "
+                          f"--layout {args.layout} --pr-iters {run['pr_iters']} --bfs-modes {run.get('bfs_modes')}")
+    out = []
+    out.append(f"# HBM traffic by kernel: {args.workload}, {args.layout} layout, {phase_name}")
+    out.append("")
+    out.append("Commands (from the repository root, one MI355X, one pass per counter set; then this summary):")
+    out.append("")
+    out.append("```")
+    out.append("cd /tmp && export TMPDIR=/tmp   # then back in the repository root for the runs")
+    for pas in COUNTER_PASSES:
+        out.append(cmd_of(pas))
+    out.append(f"python3 bench.py --workload {args.workload} --counter-run {run['phase']} --layout {args.layout} "
+               f"--pr-iters {run['pr_iters']} --bfs-modes {run.get('bfs_modes')} > gpurun_out/cnt/"
+               f"{args.workload}_{args.layout}_{run['phase']}/run.json")
+    out.append(f"python3 bench.py --workload {args.workload} --layout {args.layout} --counter-summary "
+               f"gpurun_out/cnt/{args.workload}_{args.layout}_{run['phase']} --summary-out "
+               f"profiles/counters_{args.workload}_{args.layout}_{run['phase']}.md")
+    out.append("```")
+    out.append("")
+    out.append(f"n = {run['n']}, stored entries m = {m}; structure bytes {run['structure_bytes']:.0f}.  "
+               "The calibration kernel is torch.sqrt over 2^28 floats (reads 1 GiB, writes 1 GiB); "
+               "a one-element cos kernel marks where the phase begins.")
+    out.append("")
+    out.append("| counter set | calibration reads | factor to true bytes |")
+    out.append("|---|---:|---:|")
+    out.append(f"| FETCH_SIZE (KiB) | {cal_raw['FETCH_SIZE']:.1f} | {factor['FETCH_SIZE']:.4f} |")
+    out.append(f"| WRITE_SIZE (KiB) | {cal_raw['WRITE_SIZE']:.1f} | {factor['WRITE_SIZE']:.4f} |")
+    out.append(f"| 32/64/128 B read requests (bytes) | {rd_req(cal_raw):.0f} | {factor['rdreq']:.4f} |")
+    out.append(f"| 32/64 B write requests (bytes) | {wr_req(cal_raw):.0f} | {factor['wrreq']:.4f} |")
+    out.append("")
+    out.append("Per kernel (medians over its launches; bytes calibrated; read requests by size as counted):")
+    out.append("")
+    out.append("| kernel | launches | read B/launch | written B/launch | read B from request sizes | "
+               "128 B / 64 B / 32 B read requests (% ) | DRAM share of reads | total B (all launches) |")
+    out.append("|---|---:|---:|---:|---:|---|---:|---:|")
+    total = 0.0
+    med = lambda recs, k: statistics.median(r[k] for r in recs)  # noqa: E731
+    for k, recs in sorted(kernels.items(), key=lambda kv: -sum(r["fetch"] + r["write"] for r in kv[1])):
+        tot = sum(r["fetch"] + r["write"] for r in recs)
+        total += tot
+        rq = sum(r["rtot"] for r in recs) or 1.0
+        mix = "/".join(f"{100.0 * sum(r[x] for r in recs) / rq:.0f}" for x in ("r128", "r64", "r32"))
+        dram = sum(r["rdram"] for r in recs) / rq
+        out.append(f"| {k} | {len(recs)} | {med(recs, 'fetch'):.4g} | {med(recs, 'write'):.4g} | "
+                   f"{med(recs, 'rdreq'):.4g} | {mix} | {dram:.2f} | {tot:.4g} |")
+    out.append("")
+    out.append("Machine-readable (bench.py reads these while source_sha256 matches the sources):")
+    out.append("")
+    for k, recs in sorted(kernels.items()):
+        out.append(f"traffic_bytes_per_launch.{k}: {med(recs, 'fetch') + med(recs, 'write'):.0f}")
+    out.append(f"traffic_bytes_per_phase: {total:.0f}")
+    out.append(f"traffic_bytes_per_stored_entry_per_phase: {total / m:.4f}")
+    out.append(f"source_sha256: {run['source_sha256']}")
+    out.append("")
+    out.append(f"(source_sha256 covers {', '.join(COUNTER_SOURCES[run['phase']])}.)")
+    text = "\n".join(out) + "\n"
+    if args.summary_out:
+        with open(args.summary_out, "w") as fh:
+            fh.write(text)
+    else:
+        sys.stdout.write(text)
 
 
 def median_ci95(x):
@@ -166,8 +320,16 @@ def parse():
                         "|A|, encode time, random-vertex list decode, PageRank (own JSON line)")
     p.add_argument("--counter-run", choices=["pr", "bfs"],
                    help="counter-run mode: one elementwise kernel of known traffic (calibration), then one "
-                        "PageRank call (pr) or one single-root BFS per direction mode (bfs) on --layout; no timing")
+                        "PageRank call (pr) or one single-root BFS per direction mode in --bfs-modes (bfs) on "
+                        "--layout, after a one-element cos kernel that marks where the phase begins; no timing")
+    p.add_argument("--bfs-modes", default="top-down,bottom-up,do",
+                   help="counter-run bfs: the direction modes searched, comma separated")
     p.add_argument("--layout", choices=["packed", "plain"], default="packed")
+    p.add_argument("--counter-summary", metavar="DIR",
+                   help="write the counter summary of --workload, --layout and --counter-run from the rocprofv3 "
+                        "CSV output of the passes in DIR/<pass> (passes: " + ", ".join(COUNTER_PASSES) + ") "
+                        "and the counter-run's JSON line in DIR/run.json, to --summary-out")
+    p.add_argument("--summary-out", default=None, help="counter-summary output file (default: stdout)")
     return p.parse_args()
 
 
@@ -196,6 +358,8 @@ def calibration_kernel(torch, dev, gib=1):
 
 def main():
     args = parse()
+    if args.counter_summary:
+        return counter_summary_main(args)
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: --gpus {args.gpus} is not supported "
               f"(the path runs on a single MI355X and has no multi-GPU sharding)", file=sys.stderr)
@@ -406,6 +570,7 @@ def main():
                        "bytes_per_launch": pr_bytes, "achieved_gbs": pr_gbs,
                        "bytes_per_edge_algorithmic": pr_bytes / M},
             bytes={k: info[k] for k in ("bytes_adj", "bytes_offsets", "bytes_widths", "bytes_perm")},
+            structure_bytes=struct_bytes,
             adj_bits=info["adj_bits"], parity_pr_iter1_l1=r["l1"],
             kernels_ms_profiled_step={k: round(v[1], 3) for k, v in km.items()},
             largest_summed_kernel=largest)
@@ -437,7 +602,8 @@ def main():
         k = s["pr_kernel"]
         # counter bytes of the iteration: the sum over its kernels, when every
         # one has a current summary
-        parts = [measured_counters(name, args.workload, layout, "pr") for name in k["kernels"]]
+        parts = [measured_counters(f"traffic_bytes_per_launch.{name}", args.workload, layout, "pr")
+                 for name in k["kernels"]]
         traffic = sum(parts) if parts and all(p is not None for p in parts) else None
         rooflines[layout] = {
             "bound": "hbm", "kernel": k["name"], "achieved": round(k["achieved_gbs"], 1), "peak": HBM_PEAK_GBS,
@@ -450,6 +616,20 @@ def main():
             "bytes_per_edge_algorithmic": round(k["bytes_per_edge_algorithmic"], 4)}
         if rooflines[layout]["traffic"]:
             rooflines[layout]["bytes_per_edge_measured"] = round(rooflines[layout]["traffic"] / M, 4)
+        if "pb_bin1_kernel" in k["kernels"]:
+            # propagation blocking streams more than the algorithmic bytes by
+            # design: level 1 reads the structure and the contributions and
+            # writes 8 B per entry, level 2 reads and writes 8 B per entry, the
+            # accumulation reads 8 B per entry and writes 4 B per vertex
+            design = s["structure_bytes"] + 4.0 * n + 32.0 * M + 4.0 * n
+            rooflines[layout]["design_bytes_per_launch"] = design
+            rooflines[layout]["design_frac"] = round(design / (k["avg_launch_ms"] / 1000.0) / 1e9 / HBM_PEAK_GBS, 4)
+        tb = measured_counters("traffic_bytes_per_phase", args.workload, layout, "bfs")
+        if tb:
+            rooflines[layout]["bfs_traffic_bytes_per_search"] = tb
+            rooflines[layout]["bfs_bytes_per_stored_entry_measured"] = round(tb / M, 4)
+            rooflines[layout]["bfs_achieved_gbs_median_root"] = round(
+                tb / (s["per_root"]["ms_median"] / 1000.0) / 1e9, 1)
     pr_share = P["pr_kernel"]["avg_launch_ms"] * args.pr_iters
     dominant = P["pr_kernel"]["name"] if pr_share >= max(P["bfs_all_roots_ms"], P["encode_ms"]) else \
         P["largest_summed_kernel"]
@@ -555,11 +735,14 @@ def counter_main(args, np, torch, lg, g, roots, enc):
     opts = enc if args.layout == "packed" else dict(relabel=enc["relabel"])
     h = lg.encode(g.row_offsets, g.col, g.n, layout=args.layout, **opts)
     info = h.info()
+    torch.cuda.synchronize()
+    torch.cos(torch.zeros(1, device=g.col.device))  # marks where the phase begins
+    torch.cuda.synchronize()
     if args.counter_run == "pr":
         log("[counter-run] PageRank")
         lg.pagerank(h, 0.85, args.pr_iters)
     else:
-        for mode in ("top-down", "bottom-up", "do"):
+        for mode in args.bfs_modes.split(","):
             log(f"[counter-run] BFS {mode} from root {roots[0]}")
             lg.bfs(h, [roots[0]], mode=mode)
     torch.cuda.synchronize()
@@ -567,6 +750,7 @@ def counter_main(args, np, torch, lg, g, roots, enc):
         else (info["bytes_adj"] + info["bytes_offsets"])
     print(json.dumps({"mode": "counter-run", "phase": args.counter_run, "layout": args.layout,
                       "workload": args.workload, "calibration_bytes": nbytes, "pr_iters": args.pr_iters,
+                      "bfs_modes": args.bfs_modes,
                       "n": g.n, "stored_edges": g.m, "structure_bytes": struct,
                       "pr_algorithmic_bytes_per_iteration": struct + 4.0 * g.m + 4.0 * g.n,
                       "source_sha256": source_hash(args.counter_run)}), flush=True)
