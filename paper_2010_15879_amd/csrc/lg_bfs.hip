@@ -207,7 +207,14 @@ __device__ __forceinline__ uint32_t last_le(const T *a, uint32_t lo, uint32_t hi
     return lo;
 }
 
-template <class Acc, bool kParent>
+// kMin: a level large enough that a pass over every vertex is cheap beside
+// it.  Each edge to an unvisited vertex does one atomicMin of the parent
+// (whose result nobody waits for; without parents, a plain store of the
+// depth, the same value from every writer) instead of a CAS on the depth,
+// the atomicMin and a queue append: td_finish_kernel then finds the new
+// vertices.  The smallest label among the level's claimants is the parent
+// either way.
+template <class Acc, bool kParent, bool kMin = false>
 __global__ __launch_bounds__(kTdThreads) void td_expand_kernel(
     Acc acc, const uint32_t *__restrict__ queue, uint32_t qsize, const uint64_t *__restrict__ fstart,
     const uint32_t *__restrict__ fw, const uint64_t *__restrict__ fscan, uint64_t edges,
@@ -276,6 +283,17 @@ __global__ __launch_bounds__(kTdThreads) void td_expand_kernel(
         for (int r = 0; r < kTdEdgesPerThread; ++r) u[r] = acc.get(epos[r], msk[r]);
 #pragma unroll
         for (int r = 0; r < kTdEdgesPerThread; ++r) vw[r] = visited[u[r] >> 6];
+        if constexpr (kMin) {
+#pragma unroll
+            for (int r = 0; r < kTdEdgesPerThread; ++r) {
+                if (((live >> r) & 1u) && !((vw[r] >> (u[r] & 63)) & 1ull)) {
+                    if constexpr (kParent) atomicMin(&parent[u[r]], src[r]);
+                    else depth[u[r]] = next_depth;
+                }
+            }
+            __syncthreads();  // the next tile rewrites the staged ranges
+            continue;
+        }
         uint32_t won[kTdEdgesPerThread];
         uint32_t nwon = 0;
 #pragma unroll
@@ -299,6 +317,36 @@ __global__ __launch_bounds__(kTdThreads) void td_expand_kernel(
         unsigned long long pos = s_base + s_wsum[threadIdx.x / kWave] + (incl - nwon);
         for (uint32_t i = 0; i < nwon; ++i) queue_out[pos + i] = won[i];
         __syncthreads();
+    }
+}
+
+// After a claim-only level (td_expand_kernel<..., kMin = true>): a wave per
+// 64-vertex word finds the vertices not visited before whose parent (or,
+// without parents, depth) the level set, writes their depth, and writes the
+// word of the next frontier's bitmap and the visited one.  Past n the
+// visited bits are set (the isolated-vertex bitmap pads them).
+template <bool kParent>
+__global__ void td_finish_kernel(uint32_t n, uint64_t *__restrict__ visited, const uint32_t *__restrict__ parent,
+                                 int32_t *__restrict__ depth, int32_t next_depth, uint64_t *__restrict__ frontier) {
+    const uint32_t lane = lane_id();
+    const uint64_t words = ((uint64_t)n + 63) / 64;
+    const uint64_t wstride = ((uint64_t)gridDim.x * blockDim.x) / kWave;
+    for (uint64_t w = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave; w < words; w += wstride) {
+        const uint64_t v = w * 64 + lane;
+        const uint64_t vc = v < n ? v : n - 1;
+        // both loads at once (a load under a branch waits before the branch ends)
+        const uint64_t vis = visited[w];
+        uint32_t pv = 0;
+        int32_t dv = 0;
+        if constexpr (kParent) pv = parent[vc];
+        else dv = depth[vc];
+        const bool fresh = !((vis >> lane) & 1ull) && (kParent ? pv != 0xFFFFFFFFu : dv == next_depth);
+        if (kParent && fresh) depth[v] = next_depth;
+        const uint64_t m = __ballot(fresh);
+        if (lane == 0) {
+            frontier[w] = m;
+            if (m) visited[w] = vis | m;
+        }
     }
 }
 
@@ -1289,17 +1337,51 @@ static lg_status bfs_one(lg_graph *g, BfsWork &w, Acc acc, uint32_t root_id, con
                 continue;
             }
             edges_to_check = edges_to_check > fedges ? edges_to_check - fedges : 0;
+            // a level of more than n/16 edges claims without CAS or queue
+            // appends; a pass over the vertices then finds the new ones
+            const bool claim_min = fedges > (uint64_t)n / 16;
             if (fedges) {
                 const uint32_t tiles = grid_for(fedges, kTdTile, 1u << 20);
-                if (parent)
+                if (claim_min) {
+                    if (parent)
+                        LG_LAUNCH((td_expand_kernel<Acc, true, true>), tiles, kTdThreads, 0, s, acc, qin,
+                                  (uint32_t)qsize, w.fstart.as<uint64_t>(), w.fw.as<uint32_t>(),
+                                  w.fscan.as<uint64_t>(), fedges, visited, depth, parent, level + 1, qout, ctr);
+                    else
+                        LG_LAUNCH((td_expand_kernel<Acc, false, true>), tiles, kTdThreads, 0, s, acc, qin,
+                                  (uint32_t)qsize, w.fstart.as<uint64_t>(), w.fw.as<uint32_t>(),
+                                  w.fscan.as<uint64_t>(), fedges, visited, depth, parent, level + 1, qout, ctr);
+                } else if (parent) {
                     LG_LAUNCH((td_expand_kernel<Acc, true>), tiles, kTdThreads, 0, s, acc, qin, (uint32_t)qsize,
                               w.fstart.as<uint64_t>(), w.fw.as<uint32_t>(), w.fscan.as<uint64_t>(), fedges, visited,
                               depth, parent, level + 1, qout, ctr);
-                else
+                } else {
                     LG_LAUNCH((td_expand_kernel<Acc, false>), tiles, kTdThreads, 0, s, acc, qin, (uint32_t)qsize,
                               w.fstart.as<uint64_t>(), w.fw.as<uint32_t>(), w.fscan.as<uint64_t>(), fedges, visited,
                               depth, parent, level + 1, qout, ctr);
+                }
                 LG_CHECK_LAUNCH();
+            }
+            if (claim_min) {
+                // the next frontier's bitmap and the visited one from the pass,
+                // its queue from the bitmap (the queue counter is zero here)
+                if (parent)
+                    LG_LAUNCH(td_finish_kernel<true>, wgrid, 256, 0, s, n, visited, (const uint32_t *)parent, depth,
+                              level + 1, curr);
+                else
+                    LG_LAUNCH(td_finish_kernel<false>, wgrid, 256, 0, s, n, visited, (const uint32_t *)parent, depth,
+                              level + 1, curr);
+                LG_CHECK_LAUNCH();
+                LG_LAUNCH(bitmap_to_queue_kernel, grid_for(words, 256, 1u << 16), 256, 0, s, words, curr, qout, ctr);
+                LG_CHECK_LAUNCH();
+                LG_CHECK_HIP(hipMemcpyAsync(w.host, ctr, 8, hipMemcpyDeviceToHost, s));
+                LG_CHECK_HIP(hipStreamSynchronize(s));
+                qsize = w.host[0];
+                LG_TRY(fill_u64((uint64_t *)ctr, 0, 1, s));  // the next level's queue counter
+                curr_level = level + 1;
+                std::swap(qin, qout);
+                ++level;
+                continue;
             }
             LG_CHECK_HIP(hipMemcpyAsync(w.host, ctr, 8, hipMemcpyDeviceToHost, s));
             LG_CHECK_HIP(hipStreamSynchronize(s));

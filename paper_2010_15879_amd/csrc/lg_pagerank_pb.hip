@@ -64,6 +64,24 @@ __device__ __forceinline__ void lds_barrier() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
+// Inclusive prefix sum over the 64 lanes of a wave with DPP moves (the
+// cross-lane scan of the GCN ISA: shifts by 1, 2, 4 and 8 lanes inside each
+// row of 16, then the last lane of a row broadcast into the rows after it).
+// Unlike a shuffle scan it needs no lane-address registers, which the
+// compiler keeps live across the whole kernel: in the binning kernels,
+// which run at the 64-VGPR limit, those registers forced a spill whose
+// reload waited for every load in flight.
+__device__ __forceinline__ uint32_t wave_scan_dpp(uint32_t x) {
+    // dpp_ctrl: row_shr:n = 0x110 + n, row_bcast:15 = 0x142, row_bcast:31 = 0x143
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xF, 0xF, true);
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xF, 0xF, true);
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xF, 0xF, true);
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xF, 0xF, true);
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xA, 0xF, false);  // rows 1, 3 += end of rows 0, 2
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xC, 0xF, false);  // rows 2, 3 += end of row 1
+    return x;
+}
+
 // below this many vertices the pull's gathers stay in cache
 constexpr uint32_t kPbMinVertices = 1u << 22;
 
@@ -75,8 +93,10 @@ struct PbWork {
     DevBuf base1;          // u64[nwg * nc]: level-1 region start of (workgroup, coarse bin)
     DevBuf len1;           // u32[nwg * nc]: entries of that region
     DevBuf base2;          // u64[nwg * nc * 64]: level-2 region start of ((w, c), fine bin)
-    DevBuf fstart;         // u64[nf + 1]: fine bin starts in buf2
-    DevBuf buf1, buf2;     // uint2[m]: (local vertex, contribution bits)
+    DevBuf fstart;         // u64[nf + 1]: fine bin starts in the level-2 arrays
+    DevBuf buf1;           // uint2[m]: (vertex within the coarse bin, contribution bits)
+    DevBuf buf2;           // u16[m] vertex within the fine bin, then (at val_off) f32[m] contribution
+    uint64_t val_off = 0;  // byte offset of the contributions in buf2
     DevBuf ca, cb;         // contribution ping-pong
     bool built = false;
 };
@@ -126,15 +146,16 @@ void pb_trim() {
     }
 }
 
-// bin buffers of `bytes` each: the parked pair when it fits (at most a
-// quarter larger), else new ones (a parked pair that does not fit is freed
-// first, so that its memory is available)
-static lg_status pb_take_bins(lg_graph *g, uint64_t bytes) {
+// bin buffers of `bytes1` and `bytes2`: the parked pair when it fits (at
+// most a quarter larger), else new ones (a parked pair that does not fit is
+// freed first, so that its memory is available)
+static lg_status pb_take_bins(lg_graph *g, uint64_t bytes1, uint64_t bytes2) {
     PbWork &W = *g->pb;
+    auto fits = [](const DevBuf &b, uint64_t need) { return b.p && b.bytes >= need && b.bytes <= need + need / 4; };
     if (g->device >= 0 && g->device < kPbSlots) {
         std::lock_guard<std::mutex> lk(g_pb_slot_mu);
         PbSlot &sl = pb_slots()[g->device];
-        if (sl.buf1.p && sl.buf1.bytes >= bytes && sl.buf1.bytes <= bytes + bytes / 4) {
+        if (fits(sl.buf1, bytes1) && fits(sl.buf2, bytes2)) {
             W.buf1 = std::move(sl.buf1);
             W.buf2 = std::move(sl.buf2);
             return LG_OK;
@@ -142,8 +163,8 @@ static lg_status pb_take_bins(lg_graph *g, uint64_t bytes) {
         sl.buf1.release();
         sl.buf2.release();
     }
-    LG_TRY(W.buf1.alloc(bytes));
-    LG_TRY(W.buf2.alloc(bytes));
+    LG_TRY(W.buf1.alloc(bytes1));
+    LG_TRY(W.buf2.alloc(bytes2));
     return LG_OK;
 }
 
@@ -265,8 +286,8 @@ __global__ __launch_bounds__(kPbThreads, kPb1WavesPerEU) void pb_bin1_kernel(
         // a row past the bitmap counts as kWinCap: the sum of 1,024 rows stays
         // in 32 bits, and every row the bitmap reaches keeps its exact start
         const uint32_t dc = d < kWinCap ? d : kWinCap;
-        const uint32_t incl = wave_incl_scan(dc);
-        const uint32_t nzi = wave_incl_scan(d ? 1u : 0u);
+        const uint32_t incl = wave_scan_dpp(dc);
+        const uint32_t nzi = wave_scan_dpp(d ? 1u : 0u);
         if (lane == kWave - 1) {
             s_wsum[wv] = incl;
             s_wnz[wv] = nzi;
@@ -278,7 +299,7 @@ __global__ __launch_bounds__(kPbThreads, kPb1WavesPerEU) void pb_bin1_kernel(
         {
             const uint32_t x = lane < kPbWaves ? s_wsum[lane] : 0u;
             const uint32_t y = lane < kPbWaves ? s_wnz[lane] : 0u;
-            const uint32_t xi = wave_incl_scan(x), yi = wave_incl_scan(y);
+            const uint32_t xi = wave_scan_dpp(x), yi = wave_scan_dpp(y);
             total = __builtin_amdgcn_readfirstlane(__shfl(xi, kPbWaves - 1, kWave));  // uniform: a scalar register
             E = __shfl(xi - x, wv, kWave) + incl - dc;
             k_nz = __shfl(yi - y, wv, kWave) + nzi - 1;
@@ -291,12 +312,12 @@ __global__ __launch_bounds__(kPbThreads, kPb1WavesPerEU) void pb_bin1_kernel(
         s_row[threadIdx.x] = make_uint4((uint32_t)st, (uint32_t)(st >> 32) | (vi.w << 24), E, __float_as_uint(cv));
         lds_barrier();
         const uint32_t pc = __popc(s_mk[threadIdx.x].x);
-        const uint32_t pci = wave_incl_scan(pc);
+        const uint32_t pci = wave_scan_dpp(pc);
         if (lane == kWave - 1) s_wmk[wv] = pci;
         lds_barrier();
         {
             const uint32_t x = lane < kPbWaves ? s_wmk[lane] : 0u;
-            const uint32_t xi = wave_incl_scan(x);
+            const uint32_t xi = wave_scan_dpp(x);
             s_mk[threadIdx.x].y = __shfl(xi - x, wv, kWave) + pci - pc;
         }
         lds_barrier();
@@ -365,7 +386,7 @@ __global__ __launch_bounds__(kPbThreads, kPb1WavesPerEU) void pb_bin1_kernel(
                             s_hist[par ^ 1][c] = 0;
                             h = s_hist[par][c];
                         }
-                        const uint32_t hi = wave_incl_scan(h);
+                        const uint32_t hi = wave_scan_dpp(h);
                         if (c < nc) s_start[c] = carry + hi - h;
                         carry += __shfl(hi, kWave - 1, kWave);
                     }
@@ -405,7 +426,8 @@ __global__ __launch_bounds__(kPbThreads, kPb1WavesPerEU) void pb_bin2_kernel(con
                                                                              const uint64_t *__restrict__ base1,
                                                                              const uint32_t *__restrict__ len1,
                                                                              const uint64_t *__restrict__ base2,
-                                                                             uint2 *__restrict__ buf2) {
+                                                                             uint16_t *__restrict__ loc2,
+                                                                             float *__restrict__ val2) {
     __shared__ uint2 s_buf[kPbRound];  // entries sorted by fine bin (bits 14..19 of the local vertex)
     __shared__ uint32_t s_hist[2][kSubBins];
     __shared__ uint32_t s_start[kSubBins];
@@ -445,7 +467,7 @@ __global__ __launch_bounds__(kPbThreads, kPb1WavesPerEU) void pb_bin2_kernel(con
             s_cur[lane] += s_hist[par ^ 1][lane];
             s_hist[par ^ 1][lane] = 0;
             const uint32_t h = s_hist[par][lane];
-            s_start[lane] = wave_incl_scan(h) - h;
+            s_start[lane] = wave_scan_dpp(h) - h;
         }
         lds_barrier();
 #pragma unroll
@@ -456,7 +478,9 @@ __global__ __launch_bounds__(kPbThreads, kPb1WavesPerEU) void pb_bin2_kernel(con
         for (uint32_t i = threadIdx.x; i < total; i += kPbThreads) {
             const uint2 x = s_buf[i];
             const uint32_t f = x.x >> kFineShift;
-            buf2[s_cur[f] + (i - s_start[f])] = make_uint2(x.x & (kFine - 1u), x.y);
+            const uint64_t at2 = s_cur[f] + (i - s_start[f]);
+            loc2[at2] = (uint16_t)(x.x & (kFine - 1u));
+            val2[at2] = __uint_as_float(x.y);
         }
         par ^= 1u;
     }
@@ -468,7 +492,8 @@ __global__ __launch_bounds__(kPbThreads, kPb1WavesPerEU) void pb_bin2_kernel(con
 
 template <class Acc>
 __global__ __launch_bounds__(kPbThreads) void pb_accum_kernel(Acc acc, uint32_t n, const uint64_t *__restrict__ fstart,
-                                                              const uint2 *__restrict__ buf2, float base, float alpha,
+                                                              const uint16_t *__restrict__ loc2,
+                                                              const float *__restrict__ val2, float base, float alpha,
                                                               const uint64_t *__restrict__ iso, float *__restrict__ cout,
                                                               float *__restrict__ scores,
                                                               const uint32_t *__restrict__ perm) {
@@ -481,18 +506,21 @@ __global__ __launch_bounds__(kPbThreads) void pb_accum_kernel(Acc acc, uint32_t 
     for (uint64_t i = a + threadIdx.x; i < z; i += (uint64_t)kPbThreads * kIn) {
         // unconditional loads at clamped indexes: a load under a branch waits
         // for its data before the branch ends, one load per wave in flight
-        uint2 t[kIn];
+        uint32_t lv[kIn];
+        float xv[kIn];
 #pragma unroll
         for (uint32_t q = 0; q < kIn; ++q) {
             const uint64_t k = i + (uint64_t)q * kPbThreads;
-            t[q] = buf2[k < z ? k : z - 1];
+            const uint64_t kk = k < z ? k : z - 1;
+            lv[q] = loc2[kk];
+            xv[q] = val2[kk];
         }
 #pragma unroll
         for (uint32_t q = 0; q < kIn; ++q) {
             // a contribution is in [0, 1]: its fixed-point value fits
-            const double x = (double)__uint_as_float(t[q].y) * kFixScale;
-            if (t[q].y && i + (uint64_t)q * kPbThreads < z)
-                atomicAdd(&s_acc[t[q].x & (kFine - 1u)], (unsigned long long)__double2ll_rn(x));
+            const double x = (double)xv[q] * kFixScale;
+            if (xv[q] != 0.0f && i + (uint64_t)q * kPbThreads < z)
+                atomicAdd(&s_acc[lv[q] & (kFine - 1u)], (unsigned long long)__double2ll_rn(x));
         }
     }
     lds_barrier();
@@ -609,7 +637,12 @@ static lg_status pb_build(lg_graph *g, Acc acc, hipStream_t s) {
     LG_CHECK_HIP(hipMemcpyAsync(W.len1.p, len1.data(), len1.size() * 4, hipMemcpyHostToDevice, s));
     LG_CHECK_HIP(hipMemcpyAsync(W.base2.p, base2.data(), base2.size() * 8, hipMemcpyHostToDevice, s));
     LG_CHECK_HIP(hipMemcpyAsync(W.fstart.p, fstart.data(), fstart.size() * 8, hipMemcpyHostToDevice, s));
-    LG_TRY(pb_take_bins(g, (g->m ? g->m : 1) * 8));
+    // level 2 keeps a fine-bin vertex in 16 bits and its contribution in a
+    // second array: 6 B per entry instead of 8 for level 2's writes and the
+    // accumulation's reads
+    const uint64_t me = g->m ? g->m : 1;
+    W.val_off = (me * 2 + 255) & ~255ull;
+    LG_TRY(pb_take_bins(g, me * 8, W.val_off + me * 4));
     LG_CHECK_HIP(hipStreamSynchronize(s));  // the host vectors go out of scope
     W.built = true;
     return LG_OK;
@@ -642,11 +675,13 @@ lg_status pagerank_pb(lg_graph *g, float damping, uint32_t iters, float *scores,
                           W.base1.as<uint64_t>(), W.buf1.as<uint2>(), W.nf, (uint32_t *)nullptr);
                 LG_CHECK_LAUNCH();
                 LG_LAUNCH(pb_bin2_kernel, W.nwg * W.nc, kPbThreads, 0, s, (const uint2 *)W.buf1.p,
-                          W.base1.as<uint64_t>(), W.len1.as<uint32_t>(), W.base2.as<uint64_t>(), W.buf2.as<uint2>());
+                          W.base1.as<uint64_t>(), W.len1.as<uint32_t>(), W.base2.as<uint64_t>(),
+                          W.buf2.as<uint16_t>(), (float *)((char *)W.buf2.p + W.val_off));
                 LG_CHECK_LAUNCH();
             }
             LG_LAUNCH(pb_accum_kernel<Acc>, W.nf, kPbThreads, 0, s, acc, n, W.fstart.as<uint64_t>(),
-                      (const uint2 *)W.buf2.p, (float)b, (float)a, g->iso.as<uint64_t>(), cout,
+                      (const uint16_t *)W.buf2.p, (const float *)((char *)W.buf2.p + W.val_off), (float)b, (float)a,
+                      g->iso.as<uint64_t>(), cout,
                       last ? scores : (float *)nullptr, last ? perm : (const uint32_t *)nullptr);
             LG_CHECK_LAUNCH();
             D = z * b;
