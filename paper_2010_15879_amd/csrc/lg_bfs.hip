@@ -591,24 +591,39 @@ __global__ void bu_pending_kernel(Acc acc, uint32_t threshold, uint64_t np, cons
     if (threadIdx.x == 0 && woke) atomicAdd(&counters[1], woke);
 }
 
-// frontier bitmap -> queue
+// frontier bitmap -> queue.  A wave takes 64 consecutive words (one per
+// lane), reserves their entries with one atomic and writes them in order,
+// 64 consecutive queue slots per step: slot j's word is the one whose
+// prefix count range holds j (a binary search of the wave's inclusive
+// counts), its bit the (j - count before)-th one of that word.  One lane
+// writing its word's ones one after another scattered every store.
 __global__ void bitmap_to_queue_kernel(uint64_t words, const uint64_t *__restrict__ bits,
                                        uint32_t *__restrict__ queue, unsigned long long *__restrict__ tail) {
     const uint32_t lane = lane_id();
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t base = (uint64_t)blockIdx.x * blockDim.x; base < words; base += stride) {
-        const uint64_t q = base + threadIdx.x;
-        uint64_t b = q < words ? bits[q] : 0ull;
+    const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) / kWave;
+    for (uint64_t w0 = wave * kWave; w0 < words; w0 += nwaves * kWave) {
+        const uint64_t q = w0 + lane;
+        const uint64_t b = q < words ? bits[q] : 0ull;
         const uint32_t c = (uint32_t)__popcll(b);
         const uint32_t incl = wave_incl_scan(c);
         const uint32_t total = __shfl(incl, kWave - 1, kWave);
+        if (total == 0) continue;  // wave-uniform
         unsigned long long off = 0;
-        if (lane == 0 && total) off = atomicAdd(tail, (unsigned long long)total);
-        off = __shfl(off, 0, kWave) + (incl - c);
-        while (b) {
-            const uint32_t bit = (uint32_t)__ffsll((long long)b) - 1;
-            queue[off++] = (uint32_t)(q * 64 + bit);
-            b &= b - 1;
+        if (lane == 0) off = atomicAdd(tail, (unsigned long long)total);
+        off = __shfl(off, 0, kWave);
+        for (uint32_t j0 = 0; j0 < total; j0 += kWave) {
+            const uint32_t j = j0 + lane;
+            // the number of words whose inclusive count is <= j (at most 63:
+            // the last word's count is total > j); power-of-two steps keep
+            // every shuffle index in the wave
+            uint32_t k = 0;
+#pragma unroll
+            for (uint32_t step = kWave / 2; step > 0; step >>= 1)
+                if (__shfl(incl, k + step - 1, kWave) <= j) k += step;
+            const uint64_t x = __shfl(b, k, kWave);
+            const uint32_t before = __shfl(incl, k, kWave) - __shfl(c, k, kWave);
+            if (j < total) queue[off + j] = (uint32_t)((w0 + k) * 64 + select_in_word(x, j - before));
         }
     }
 }
