@@ -30,7 +30,6 @@
 // scores repeat bit for bit and carry no summation error beyond the FP32
 // rounding of each contribution.
 #include <algorithm>
-#include <vector>
 
 #include "lg_device.hpp"
 
@@ -560,6 +559,53 @@ __global__ void pb_init_kernel(Acc acc, uint32_t n, double inv_n, float *__restr
 }
 
 // ---------------------------------------------------------------------------
+// region tables from the counting pass (hist[w][b]: workgroup w's entries in
+// fine bin b = 64 c + f)
+// ---------------------------------------------------------------------------
+
+// level-1 region lengths len1[w][c], and the same counts in coarse-major
+// order (c, w) for the scan that places the level-1 regions; the counts in
+// fine-major order (b, w) for the scan that places the level-2 regions
+__global__ void pb_tables_count_kernel(const uint32_t *__restrict__ hist, uint32_t nwg, uint32_t nc, uint32_t nf,
+                                       uint32_t *__restrict__ len1, uint32_t *__restrict__ len1_cw,
+                                       uint32_t *__restrict__ hist_bw) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    const uint64_t cells = (uint64_t)nwg * nf;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cells; i += stride) {
+        const uint32_t w = (uint32_t)(i / nf), b = (uint32_t)(i % nf);
+        hist_bw[(uint64_t)b * nwg + w] = hist[i];
+    }
+    const uint64_t regions = (uint64_t)nwg * nc;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < regions; i += stride) {
+        const uint32_t w = (uint32_t)(i / nc), c = (uint32_t)(i % nc);
+        uint32_t sum = 0;
+        for (uint32_t b = c * kSubBins; b < (c + 1) * kSubBins && b < nf; ++b) sum += hist[(uint64_t)w * nf + b];
+        len1[i] = sum;
+        len1_cw[(uint64_t)c * nwg + w] = sum;
+    }
+}
+
+// region starts from the two exclusive scans: base1[w][c] (level 1,
+// coarse-major), base2[w][c][f] and fstart[b] (level 2, fine-major)
+__global__ void pb_tables_place_kernel(const uint64_t *__restrict__ scan_cw, const uint64_t *__restrict__ scan_bw,
+                                       uint32_t nwg, uint32_t nc, uint32_t nf, uint64_t *__restrict__ base1,
+                                       uint64_t *__restrict__ base2, uint64_t *__restrict__ fstart) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    const uint64_t cells = (uint64_t)nwg * nc * kSubBins;  // base2 slots, fine bins past nf included
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cells; i += stride) {
+        const uint32_t w = (uint32_t)(i / ((uint64_t)nc * kSubBins)), b = (uint32_t)(i % ((uint64_t)nc * kSubBins));
+        base2[i] = b < nf ? scan_bw[(uint64_t)b * nwg + w] : scan_bw[(uint64_t)nf * nwg];
+        if (w == 0 && b < nf) fstart[b] = scan_bw[(uint64_t)b * nwg];
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) fstart[nf] = scan_bw[(uint64_t)nf * nwg];
+    const uint64_t regions = (uint64_t)nwg * nc;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < regions; i += stride) {
+        const uint32_t w = (uint32_t)(i / nc), c = (uint32_t)(i % nc);
+        base1[i] = scan_cw[(uint64_t)c * nwg + w];
+    }
+}
+
+// ---------------------------------------------------------------------------
 // host driver
 // ---------------------------------------------------------------------------
 
@@ -582,8 +628,8 @@ static lg_status pb_build(lg_graph *g, Acc acc, hipStream_t s) {
                   n, deg.as<uint32_t>());
         LG_CHECK_LAUNCH();
         LG_TRY(exclusive_scan_u32(deg.as<uint32_t>(), eoff.as<uint64_t>(), n, tmp, s));
-        LG_TRY(W.row_lo.alloc((uint64_t)W.nwg * 4));
-        LG_TRY(W.k_lo.alloc((uint64_t)W.nwg * 4));
+        LG_TRY(W.row_lo.scratch((uint64_t)W.nwg * 4, s));
+        LG_TRY(W.k_lo.scratch((uint64_t)W.nwg * 4, s));
         LG_LAUNCH(pb_row_lo_kernel, grid_for(W.nwg, 256, 1u << 16), 256, 0, s, n, g->m, W.nwg,
                   (const uint64_t *)eoff.as<uint64_t>(), W.row_lo.as<uint32_t>(), W.k_lo.as<uint32_t>());
         LG_CHECK_LAUNCH();
@@ -596,54 +642,47 @@ static lg_status pb_build(lg_graph *g, Acc acc, hipStream_t s) {
               (const float *)W.ca.p, W.row_lo.as<uint32_t>(), W.k_lo.as<uint32_t>(), W.nc,
               (const uint64_t *)nullptr, (uint2 *)nullptr, W.nf, hist.as<uint32_t>());
     LG_CHECK_LAUNCH();
-    std::vector<uint32_t> h((uint64_t)W.nwg * W.nf);
-    LG_CHECK_HIP(hipMemcpyAsync(h.data(), hist.p, h.size() * 4, hipMemcpyDeviceToHost, s));
-    LG_CHECK_HIP(hipStreamSynchronize(s));
     // regions: coarse bin c's level-1 data is the concatenation over w of
     // region (w, c); fine bin b's level-2 data the concatenation over the
-    // regions (w, c) of their part for b
+    // regions (w, c) of their part for b (both laid out by exclusive scans on
+    // the device; the host reads back the two totals only)
     const uint32_t nwg = W.nwg, nc = W.nc, nf = W.nf;
-    std::vector<uint64_t> base1((uint64_t)nwg * nc), base2((uint64_t)nwg * nc * kSubBins, 0ull),
-        fstart((uint64_t)nf + 1, 0ull);
-    std::vector<uint32_t> len1((uint64_t)nwg * nc, 0u);
-    for (uint32_t w = 0; w < nwg; ++w)
-        for (uint32_t b = 0; b < nf; ++b) len1[(uint64_t)w * nc + b / kSubBins] += h[(uint64_t)w * nf + b];
-    uint64_t at = 0;
-    for (uint32_t c = 0; c < nc; ++c)
-        for (uint32_t w = 0; w < nwg; ++w) {
-            base1[(uint64_t)w * nc + c] = at;
-            at += len1[(uint64_t)w * nc + c];
+    {
+        DevBuf len1_cw, hist_bw, scan_cw, scan_bw, tmp;
+        LG_TRY(W.len1.scratch((uint64_t)nwg * nc * 4, s));
+        LG_TRY(W.base1.scratch((uint64_t)nwg * nc * 8, s));
+        LG_TRY(W.base2.scratch((uint64_t)nwg * nc * kSubBins * 8, s));
+        LG_TRY(W.fstart.scratch(((uint64_t)nf + 1) * 8, s));
+        LG_TRY(len1_cw.scratch((uint64_t)nwg * nc * 4, s));
+        LG_TRY(hist_bw.scratch((uint64_t)nwg * nf * 4, s));
+        LG_TRY(scan_cw.scratch(((uint64_t)nwg * nc + 1) * 8, s));
+        LG_TRY(scan_bw.scratch(((uint64_t)nwg * nf + 1) * 8, s));
+        const uint32_t grid = grid_for((uint64_t)nwg * nc * kSubBins, 256, 1u << 14);
+        LG_LAUNCH(pb_tables_count_kernel, grid, 256, 0, s, (const uint32_t *)hist.as<uint32_t>(), nwg, nc, nf,
+                  W.len1.as<uint32_t>(), len1_cw.as<uint32_t>(), hist_bw.as<uint32_t>());
+        LG_CHECK_LAUNCH();
+        LG_TRY(exclusive_scan_u32(len1_cw.as<uint32_t>(), scan_cw.as<uint64_t>(), (uint64_t)nwg * nc, tmp, s));
+        LG_TRY(exclusive_scan_u32(hist_bw.as<uint32_t>(), scan_bw.as<uint64_t>(), (uint64_t)nwg * nf, tmp, s));
+        LG_LAUNCH(pb_tables_place_kernel, grid, 256, 0, s, (const uint64_t *)scan_cw.as<uint64_t>(),
+                  (const uint64_t *)scan_bw.as<uint64_t>(), nwg, nc, nf, W.base1.as<uint64_t>(),
+                  W.base2.as<uint64_t>(), W.fstart.as<uint64_t>());
+        LG_CHECK_LAUNCH();
+        uint64_t tot[2] = {0, 0};
+        LG_CHECK_HIP(hipMemcpyAsync(&tot[0], scan_cw.as<uint64_t>() + (uint64_t)nwg * nc, 8, hipMemcpyDeviceToHost, s));
+        LG_CHECK_HIP(hipMemcpyAsync(&tot[1], scan_bw.as<uint64_t>() + (uint64_t)nwg * nf, 8, hipMemcpyDeviceToHost, s));
+        LG_CHECK_HIP(hipStreamSynchronize(s));  // the temporaries are released here
+        if (tot[0] != g->m || tot[1] != g->m) {
+            set_error("lg_pagerank: propagation-blocking counts %llu, %llu differ from %llu entries",
+                      (unsigned long long)tot[0], (unsigned long long)tot[1], (unsigned long long)g->m);
+            return LG_ERR_DEVICE;
         }
-    if (at != g->m) {
-        set_error("lg_pagerank: propagation-blocking count %llu differs from %llu entries", (unsigned long long)at,
-                  (unsigned long long)g->m);
-        return LG_ERR_DEVICE;
     }
-    at = 0;
-    for (uint32_t b = 0; b < nf; ++b) {
-        fstart[b] = at;
-        const uint32_t c = b / kSubBins, f = b % kSubBins;
-        for (uint32_t w = 0; w < nwg; ++w) {
-            base2[((uint64_t)w * nc + c) * kSubBins + f] = at;
-            at += h[(uint64_t)w * nf + b];
-        }
-    }
-    fstart[nf] = at;
-    LG_TRY(W.base1.alloc(base1.size() * 8));
-    LG_TRY(W.len1.alloc(len1.size() * 4));
-    LG_TRY(W.base2.alloc(base2.size() * 8));
-    LG_TRY(W.fstart.alloc(fstart.size() * 8));
-    LG_CHECK_HIP(hipMemcpyAsync(W.base1.p, base1.data(), base1.size() * 8, hipMemcpyHostToDevice, s));
-    LG_CHECK_HIP(hipMemcpyAsync(W.len1.p, len1.data(), len1.size() * 4, hipMemcpyHostToDevice, s));
-    LG_CHECK_HIP(hipMemcpyAsync(W.base2.p, base2.data(), base2.size() * 8, hipMemcpyHostToDevice, s));
-    LG_CHECK_HIP(hipMemcpyAsync(W.fstart.p, fstart.data(), fstart.size() * 8, hipMemcpyHostToDevice, s));
     // level 2 keeps a fine-bin vertex in 16 bits and its contribution in a
     // second array: 6 B per entry instead of 8 for level 2's writes and the
     // accumulation's reads
     const uint64_t me = g->m ? g->m : 1;
     W.val_off = (me * 2 + 255) & ~255ull;
     LG_TRY(pb_take_bins(g, me * 8, W.val_off + me * 4));
-    LG_CHECK_HIP(hipStreamSynchronize(s));  // the host vectors go out of scope
     W.built = true;
     return LG_OK;
 }
