@@ -226,7 +226,7 @@ __global__ void pb_row_lo_kernel(uint32_t n, uint64_t m, uint32_t nwg, const uin
 // entries per fine bin.
 constexpr uint32_t kWin = kPbThreads;           // rows per window
 constexpr uint32_t kWinCap = 32 * kPbThreads;   // window entries with a bitmap bit (one word per thread)
-constexpr uint32_t kPb1WavesPerEU = kPb1PerCU * kPbWaves / 4;  // waves per SIMD for two workgroups per CU
+constexpr uint32_t kPb1WavesPerEU = kPb1PerCU * kPbWaves / 4;  // waves per SIMD for kPb1PerCU workgroups per CU
 
 template <class Acc, bool kCount>
 __global__ __launch_bounds__(kPbThreads, kPb1WavesPerEU) void pb_bin1_kernel(
@@ -330,47 +330,85 @@ __global__ __launch_bounds__(kPbThreads, kPb1WavesPerEU) void pb_bin1_kernel(
             nk0 = (a0 + t == r0 ? k0 : 0u) + (kWinCap - __builtin_amdgcn_readfirstlane(s_row[t].z));
             nr0 = (uint32_t)(a0 + t);
         }
-        // -- rounds over the window's entries [j0, jn)
-        uint32_t j0 = 0;
-        while (j0 < jn && e < e_end) {
-            const uint64_t left = e_end - e;
-            uint32_t R = jn - j0;
+        // -- rounds over the window's entries [j0, jn).  The next round's
+        // list loads go out while this round sorts and writes; every thread
+        // issues the same loads and stores in every round (idle slots read
+        // stream position 0 with mask 0 and store to the sink entry m), so
+        // that the wait for the next round's entries, on the counter that
+        // loads and stores share in order, need not wait for this round's
+        // stores
+        auto round_len = [&](uint32_t jb, uint64_t eb) -> uint32_t {
+            uint32_t R = jn - jb;
             if (R > kPb1Round) R = kPb1Round;
+            const uint64_t left = e_end - eb;
             if (R > left) R = (uint32_t)left;
-            uint64_t e_pos[kPb1Steps];
-            uint32_t e_mask[kPb1Steps], e_val[kPb1Steps];
-            uint32_t ok = 0;
+            return R;
+        };
+        // slot q of a round: the list words holding its entry, and its window
+        // row | bit offset << 10 | width << 16 | valid << 31
+        uint32_t nlo[kPb1Steps], nhi[kPb1Steps], nmeta[kPb1Steps];
+        auto issue = [&](uint32_t jb, uint32_t Rb) {
+            uint64_t pos[kPb1Steps];
 #pragma unroll
             for (uint32_t q = 0; q < kPb1Steps; ++q) {
                 const uint32_t i = threadIdx.x + q * kPbThreads;
-                e_pos[q] = 0;
-                e_mask[q] = e_val[q] = 0;
-                if (i < R) {
-                    const uint32_t j = j0 + i;
-                    const uint4 ri = s_row[row_of(j)];
+                pos[q] = 0;
+                nmeta[q] = 0;
+                if (i < Rb) {
+                    const uint32_t j = jb + i;
+                    const uint32_t t = row_of(j);
+                    const uint4 ri = s_row[t];
                     const uint32_t ww = ri.y >> 24;
                     const uint64_t rs = ((uint64_t)(ri.y & 0xFFFFFFu) << 32) | ri.x;
-                    e_pos[q] = rs + (uint64_t)(j - ri.z) * Acc::step(ww);
-                    e_mask[q] = Acc::mask(ww);
-                    e_val[q] = ri.w;
-                    ok |= 1u << q;
+                    pos[q] = rs + (uint64_t)(j - ri.z) * Acc::step(ww);
+                    nmeta[q] = t | (((uint32_t)pos[q] & 31u) << 10) | (ww << 16) | (1u << 31);
                 }
             }
-            // every slot loads (an idle one reads position 0 with mask 0: the
-            // stream holds an entry, and its pad word keeps the read in
-            // bounds); a load under a branch waits for its data before the
-            // branch ends, which would leave one load per wave in flight
-            uint32_t e_v[kPb1Steps];
 #pragma unroll
-            for (uint32_t q = 0; q < kPb1Steps; ++q) e_v[q] = acc.get(e_pos[q], e_mask[q]);
-            uint32_t e_rank[kPb1Steps];
+            for (uint32_t q = 0; q < kPb1Steps; ++q) {
+                if constexpr (Acc::kPacked) {
+                    const uint64_t k = pos[q] >> 5;  // the pad word keeps k + 1 in bounds
+                    nlo[q] = acc.pv.A32[k];
+                    nhi[q] = acc.pv.A32[k + 1];
+                } else {
+                    nlo[q] = acc.pv.col[pos[q]];
+                    nhi[q] = 0;
+                }
+            }
+        };
+        // the round's entries from the loaded words (the loop is rotated:
+        // each round's entries are taken at the end of the round before, where
+        // only that round's stores follow their loads)
+        uint32_t e_v[kPb1Steps], e_meta[kPb1Steps], e_rank[kPb1Steps];
+        auto take = [&]() {
+#pragma unroll
+            for (uint32_t q = 0; q < kPb1Steps; ++q) {
+                e_meta[q] = nmeta[q];
+                if constexpr (Acc::kPacked) {
+                    const uint32_t ww = (e_meta[q] >> 16) & 63u;
+                    e_v[q] = __builtin_amdgcn_alignbit(nhi[q], nlo[q], (e_meta[q] >> 10) & 31u) & width_mask(ww);
+                } else {
+                    e_v[q] = nlo[q];
+                }
+            }
+        };
+        uint32_t j0 = 0;
+        issue(0, e < e_end ? round_len(0, e) : 0u);
+        take();
+        while (j0 < jn && e < e_end) {
+            const uint32_t R = round_len(j0, e);
 #pragma unroll
             for (uint32_t q = 0; q < kPb1Steps; ++q) {
                 e_rank[q] = 0;
-                if (!((ok >> q) & 1u)) continue;
+                if (!(e_meta[q] >> 31)) continue;
                 e_v[q] = e_v[q] < n ? e_v[q] : n - 1;  // a stored ID is < n; keeps a corrupt stream in bounds
                 if constexpr (kCount) atomicAdd(&s_fhist[e_v[q] >> kFineShift], 1u);
                 else e_rank[q] = atomicAdd(&s_hist[par][e_v[q] >> kCoarseShift], 1u);
+            }
+            {  // the next round of this window (none: every slot idle)
+                const uint32_t jb = j0 + R;
+                const uint64_t eb = e + R;
+                issue(jb, (jb < jn && eb < e_end) ? round_len(jb, eb) : 0u);
             }
             if constexpr (!kCount) {
                 lds_barrier();  // ranks taken; the last round's copy-out is done
@@ -393,18 +431,23 @@ __global__ __launch_bounds__(kPbThreads, kPb1WavesPerEU) void pb_bin1_kernel(
                 lds_barrier();
 #pragma unroll
                 for (uint32_t q = 0; q < kPb1Steps; ++q)
-                    if ((ok >> q) & 1u)
-                        s_buf[s_start[e_v[q] >> kCoarseShift] + e_rank[q]] = make_uint2(e_v[q], e_val[q]);
+                    if (e_meta[q] >> 31)
+                        s_buf[s_start[e_v[q] >> kCoarseShift] + e_rank[q]] =
+                            make_uint2(e_v[q], s_row[e_meta[q] & 0x3FFu].w);
                 lds_barrier();
-                for (uint32_t i = threadIdx.x; i < R; i += kPbThreads) {
-                    const uint2 x = s_buf[i];
+#pragma unroll
+                for (uint32_t q = 0; q < kPb1Steps; ++q) {
+                    const uint32_t i = threadIdx.x + q * kPbThreads;
+                    const uint2 x = s_buf[i < R ? i : 0u];
                     const uint32_t c = x.x >> kCoarseShift;
-                    buf1[s_cur[c] + (i - s_start[c])] = make_uint2(x.x & ((1u << kCoarseShift) - 1u), x.y);
+                    const uint64_t dst = i < R ? s_cur[c] + (i - s_start[c]) : m;
+                    buf1[dst] = make_uint2(x.x & ((1u << kCoarseShift) - 1u), x.y);
                 }
                 par ^= 1u;
             }
             j0 += R;
             e += R;
+            take();
         }
         r0 = nr0;
         k0 = nk0;
@@ -420,14 +463,21 @@ __global__ __launch_bounds__(kPbThreads, kPb1WavesPerEU) void pb_bin1_kernel(
 // ---------------------------------------------------------------------------
 
 static_assert(kSubBins == kWave, "level 2 scans its fine bins with one wave");
+// level 2: one 1,024-thread workgroup per CU, 16 entries per thread, rounds
+// of 16,384 entries (runs of 256 entries per fine bin)
+constexpr uint32_t kPb2Threads = 1024;
+constexpr uint32_t kPb2Steps = 16;
+constexpr uint32_t kPb2Round = kPb2Threads * kPb2Steps;
+constexpr uint32_t kPb2WavesPerEU = (kPb2Threads / kWave) / 4;
 
-__global__ __launch_bounds__(kPbThreads, kPb1WavesPerEU) void pb_bin2_kernel(const uint2 *__restrict__ buf1,
+__global__ __launch_bounds__(kPb2Threads, kPb2WavesPerEU) void pb_bin2_kernel(const uint2 *__restrict__ buf1,
                                                                              const uint64_t *__restrict__ base1,
                                                                              const uint32_t *__restrict__ len1,
                                                                              const uint64_t *__restrict__ base2,
                                                                              uint16_t *__restrict__ loc2,
-                                                                             float *__restrict__ val2) {
-    __shared__ uint2 s_buf[kPbRound];  // entries sorted by fine bin (bits 14..19 of the local vertex)
+                                                                             float *__restrict__ val2,
+                                                                             uint64_t sink) {
+    __shared__ uint2 s_buf[kPb2Round];  // entries sorted by fine bin (bits 14..19 of the local vertex)
     __shared__ uint32_t s_hist[2][kSubBins];
     __shared__ uint32_t s_start[kSubBins];
     __shared__ uint64_t s_cur[kSubBins];
@@ -440,27 +490,33 @@ __global__ __launch_bounds__(kPbThreads, kPb1WavesPerEU) void pb_bin2_kernel(con
         s_hist[0][threadIdx.x] = s_hist[1][threadIdx.x] = 0;
         s_cur[threadIdx.x] = base2[r * kSubBins + threadIdx.x];
     }
-    // round k + 1's entries are loaded while round k is sorted and written
-    uint2 nx[kPbSteps];
+    // round k + 1's entries are loaded while round k is sorted and written.
+    // Loads and stores share one in-order counter: so that the wait for the
+    // next round's entries need not wait for this round's stores, every
+    // thread issues the same loads and stores in every round (a slot past
+    // the region reads its first entry, and stores to the sink entry m of
+    // the level-2 arrays).
+    uint2 nx[kPb2Steps];
     auto load = [&](uint32_t at) {
 #pragma unroll
-        for (uint32_t st = 0; st < kPbSteps; ++st) {
-            const uint32_t i = at + st * kPbThreads + threadIdx.x;
-            nx[st] = i < len ? buf1[b0 + i] : make_uint2(0xFFFFFFFFu, 0u);
+        for (uint32_t st = 0; st < kPb2Steps; ++st) {
+            const uint32_t i = at + st * kPb2Threads + threadIdx.x;
+            nx[st] = buf1[b0 + (i < len ? i : 0u)];
+            if (i >= len) nx[st].x = 0xFFFFFFFFu;
         }
     };
     load(0);
     lds_barrier();
     uint32_t par = 0;
-    for (uint32_t at = 0; at < len; at += kPbRound) {
-        uint2 e[kPbSteps];
-        uint32_t rank[kPbSteps];
+    for (uint32_t at = 0; at < len; at += kPb2Round) {
+        uint2 e[kPb2Steps];
+        uint32_t rank[kPb2Steps];
 #pragma unroll
-        for (uint32_t st = 0; st < kPbSteps; ++st) {
+        for (uint32_t st = 0; st < kPb2Steps; ++st) {
             e[st] = nx[st];
             rank[st] = e[st].x != 0xFFFFFFFFu ? atomicAdd(&s_hist[par][e[st].x >> kFineShift], 1u) : 0u;
         }
-        if (at + kPbRound < len) load(at + kPbRound);
+        load(at + kPb2Round);  // past the region: slots marked empty
         lds_barrier();  // ranks taken; the last round's copy-out is done
         if (wv == 0) {  // the last round's counts move the cursors; this round's give the run starts
             s_cur[lane] += s_hist[par ^ 1][lane];
@@ -470,14 +526,16 @@ __global__ __launch_bounds__(kPbThreads, kPb1WavesPerEU) void pb_bin2_kernel(con
         }
         lds_barrier();
 #pragma unroll
-        for (uint32_t st = 0; st < kPbSteps; ++st)
+        for (uint32_t st = 0; st < kPb2Steps; ++st)
             if (e[st].x != 0xFFFFFFFFu) s_buf[s_start[e[st].x >> kFineShift] + rank[st]] = e[st];
         lds_barrier();
-        const uint32_t total = len - at < kPbRound ? len - at : kPbRound;
-        for (uint32_t i = threadIdx.x; i < total; i += kPbThreads) {
-            const uint2 x = s_buf[i];
+        const uint32_t total = len - at < kPb2Round ? len - at : kPb2Round;
+#pragma unroll
+        for (uint32_t st = 0; st < kPb2Steps; ++st) {
+            const uint32_t i = st * kPb2Threads + threadIdx.x;
+            const uint2 x = s_buf[i < total ? i : 0u];
             const uint32_t f = x.x >> kFineShift;
-            const uint64_t at2 = s_cur[f] + (i - s_start[f]);
+            const uint64_t at2 = i < total ? s_cur[f] + (i - s_start[f]) : sink;
             loc2[at2] = (uint16_t)(x.x & (kFine - 1u));
             val2[at2] = __uint_as_float(x.y);
         }
@@ -680,7 +738,8 @@ static lg_status pb_build(lg_graph *g, Acc acc, hipStream_t s) {
     // level 2 keeps a fine-bin vertex in 16 bits and its contribution in a
     // second array: 6 B per entry instead of 8 for level 2's writes and the
     // accumulation's reads
-    const uint64_t me = g->m ? g->m : 1;
+    // (one more entry in each: the sink that idle slots of a round store to)
+    const uint64_t me = g->m + 1;
     W.val_off = (me * 2 + 255) & ~255ull;
     LG_TRY(pb_take_bins(g, me * 8, W.val_off + me * 4));
     W.built = true;
@@ -713,9 +772,9 @@ lg_status pagerank_pb(lg_graph *g, float damping, uint32_t iters, float *scores,
                           (const float *)cin, W.row_lo.as<uint32_t>(), W.k_lo.as<uint32_t>(), W.nc,
                           W.base1.as<uint64_t>(), W.buf1.as<uint2>(), W.nf, (uint32_t *)nullptr);
                 LG_CHECK_LAUNCH();
-                LG_LAUNCH(pb_bin2_kernel, W.nwg * W.nc, kPbThreads, 0, s, (const uint2 *)W.buf1.p,
+                LG_LAUNCH(pb_bin2_kernel, W.nwg * W.nc, kPb2Threads, 0, s, (const uint2 *)W.buf1.p,
                           W.base1.as<uint64_t>(), W.len1.as<uint32_t>(), W.base2.as<uint64_t>(),
-                          W.buf2.as<uint16_t>(), (float *)((char *)W.buf2.p + W.val_off));
+                          W.buf2.as<uint16_t>(), (float *)((char *)W.buf2.p + W.val_off), g->m);
                 LG_CHECK_LAUNCH();
             }
             LG_LAUNCH(pb_accum_kernel<Acc>, W.nf, kPbThreads, 0, s, acc, n, W.fstart.as<uint64_t>(),
