@@ -619,9 +619,9 @@ def main():
         if "pb_bin1_kernel" in k["kernels"]:
             # propagation blocking streams more than the algorithmic bytes by
             # design: level 1 reads the structure and the contributions and
-            # writes 8 B per entry, level 2 reads and writes 8 B per entry, the
-            # accumulation reads 8 B per entry and writes 4 B per vertex
-            design = s["structure_bytes"] + 4.0 * n + 32.0 * M + 4.0 * n
+            # writes 8 B per entry, level 2 reads 8 B and writes 6 B per entry,
+            # the accumulation reads 6 B per entry and writes 4 B per vertex
+            design = s["structure_bytes"] + 4.0 * n + 28.0 * M + 4.0 * n
             rooflines[layout]["design_bytes_per_launch"] = design
             rooflines[layout]["design_frac"] = round(design / (k["avg_launch_ms"] / 1000.0) / 1e9 / HBM_PEAK_GBS, 4)
         tb = measured_counters("traffic_bytes_per_phase", args.workload, layout, "bfs")
