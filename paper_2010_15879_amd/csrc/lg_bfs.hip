@@ -58,7 +58,7 @@ BfsPool::~BfsPool() {
 }
 
 uint64_t BfsPool::bytes() const {
-    uint64_t b = 0;
+    uint64_t b = ms.bytes();
     for (const BfsLane *l : lanes) b += l->work.bytes();
     return b;
 }
@@ -1774,6 +1774,390 @@ lg_status bfs_run(lg_graph *g, BfsWork &w, const uint32_t *roots, uint32_t r, in
     });
 }
 
+// ---------------------------------------------------------------------------
+// Multi-source BFS: the roots of one call (up to 64 at a time) in one
+// traversal.  Every vertex holds 64-bit masks, bit i for root i: vis (the
+// searches that reached it), fr (those with it in this level's frontier),
+// nx (the next level's).  A level either marks candidates top-down (every
+// frontier edge (u, v) ORs fr[u] & ~vis[v] into nx[v]) and then finds their
+// parents, or finds the next frontier bottom-up over every vertex with open
+// bits.  Either way a vertex reads its list in order and takes, for each
+// bit, the first neighbor whose frontier mask holds it: the neighbor one
+// level up with the smallest label, so every row equals the search from its
+// root alone.  Each list is read once per level for all roots.
+// ---------------------------------------------------------------------------
+
+constexpr uint32_t kMsRoots = 64;
+constexpr uint32_t kMsLaneLimit = 256;  // entries a lane reads before a wave finishes its list
+constexpr int kMsThreads = 256;
+
+__device__ __forceinline__ unsigned long long wave_or64(unsigned long long x) {
+    const uint32_t lo = wave_or((uint32_t)x), hi = wave_or((uint32_t)(x >> 32));
+    return ((unsigned long long)hi << 32) | lo;
+}
+
+// the roots: reached at depth 0, their own parents, in the first frontier
+__global__ void ms_roots_kernel(uint32_t r, const uint32_t *__restrict__ roots, uint64_t n,
+                                unsigned long long *__restrict__ vis, unsigned long long *__restrict__ fr,
+                                int32_t *__restrict__ depth, int32_t *__restrict__ parent) {
+    const uint32_t i = threadIdx.x;
+    if (i >= r) return;
+    const uint32_t x = roots[i];
+    atomicOr(&vis[x], 1ull << i);
+    atomicOr(&fr[x], 1ull << i);
+    depth[(uint64_t)i * n + x] = 0;
+    if (parent) parent[(uint64_t)i * n + x] = (int32_t)x;
+}
+
+// bitmap of the vertices with a non-empty mask
+__global__ void ms_bits_kernel(uint32_t n, const unsigned long long *__restrict__ fr, uint64_t *__restrict__ bits) {
+    const uint32_t lane = lane_id();
+    const uint64_t words = ((uint64_t)n + 63) / 64;
+    const uint64_t wstride = ((uint64_t)gridDim.x * blockDim.x) / kWave;
+    for (uint64_t q = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave; q < words; q += wstride) {
+        const uint64_t v = q * 64 + lane;
+        const uint64_t m = __ballot(v < n && fr[v < n ? v : n - 1] != 0ull);
+        if (lane == 0) bits[q] = m;
+    }
+}
+
+// Top-down marking over the frontier's edges, tiled as td_expand_kernel
+// tiles them: nx[v] |= fr[u] & ~vis[v] for every frontier edge (u, v).
+template <class Acc>
+__global__ __launch_bounds__(kTdThreads) void ms_mark_kernel(
+    Acc acc, const uint32_t *__restrict__ queue, uint32_t qsize, const uint64_t *__restrict__ fstart,
+    const uint32_t *__restrict__ fw, const uint64_t *__restrict__ fscan, uint64_t edges,
+    const unsigned long long *__restrict__ fr, const unsigned long long *__restrict__ vis,
+    unsigned long long *__restrict__ nx) {
+    __shared__ uint64_t s_scan[kTdTile + 1];
+    __shared__ uint64_t s_start[kTdTile];
+    __shared__ uint32_t s_w[kTdTile];
+    __shared__ unsigned long long s_fr[kTdTile];
+    __shared__ uint32_t s_range[2];
+    for (uint64_t t = blockIdx.x; t * kTdTile < edges; t += gridDim.x) {
+        const uint64_t e0 = t * kTdTile;
+        const uint64_t e1 = e0 + kTdTile < edges ? e0 + kTdTile : edges;
+        if (threadIdx.x == 0) s_range[0] = last_le(fscan, 0, qsize - 1, e0);
+        if (threadIdx.x == 1) s_range[1] = last_le(fscan, 0, qsize - 1, e1 - 1);
+        __syncthreads();
+        const uint32_t i0 = s_range[0];
+        const uint32_t span = s_range[1] - i0 + 1;
+        const bool staged = span <= kTdTile;
+        if (staged) {
+            for (uint32_t j = threadIdx.x; j < span; j += kTdThreads) {
+                s_scan[j] = fscan[i0 + j];
+                s_start[j] = fstart[i0 + j];
+                s_w[j] = fw[i0 + j];
+                s_fr[j] = fr[queue[i0 + j]];
+            }
+        }
+        __syncthreads();
+        // in phases, so that the list loads and then the mask loads of a
+        // thread's edges are in flight together (idle slots: position 0 with
+        // mask 0, an empty frontier mask)
+        uint64_t epos[kTdEdgesPerThread];
+        uint32_t msk[kTdEdgesPerThread];
+        unsigned long long fm[kTdEdgesPerThread];
+#pragma unroll
+        for (int r = 0; r < kTdEdgesPerThread; ++r) {
+            const uint64_t e = e0 + (uint64_t)r * kTdThreads + threadIdx.x;
+            epos[r] = 0;
+            msk[r] = 0;
+            fm[r] = 0ull;
+            if (e < e1) {
+                uint64_t base_e, start;
+                uint32_t w;
+                unsigned long long f;
+                if (staged) {
+                    const uint32_t j = last_le(s_scan, 0, span - 1, e);
+                    base_e = s_scan[j]; start = s_start[j]; w = s_w[j]; f = s_fr[j];
+                } else {
+                    const uint32_t j = last_le(fscan, i0, s_range[1], e);
+                    base_e = fscan[j]; start = fstart[j]; w = fw[j]; f = fr[queue[j]];
+                }
+                epos[r] = start + (e - base_e) * Acc::step(w);
+                msk[r] = Acc::mask(w);
+                fm[r] = f;
+            }
+        }
+        uint32_t u[kTdEdgesPerThread];
+        unsigned long long vw[kTdEdgesPerThread];
+#pragma unroll
+        for (int r = 0; r < kTdEdgesPerThread; ++r) u[r] = acc.get(epos[r], msk[r]);
+#pragma unroll
+        for (int r = 0; r < kTdEdgesPerThread; ++r) vw[r] = vis[u[r]];
+#pragma unroll
+        for (int r = 0; r < kTdEdgesPerThread; ++r) {
+            const unsigned long long add = fm[r] & ~vw[r];
+            if (add) atomicOr(&nx[u[r]], add);
+        }
+        __syncthreads();  // the next tile rewrites the staged ranges
+    }
+}
+
+// One level's parents and depths, a lane per vertex over 64-vertex words.
+// Open bits P: the candidates nx[v] (top-down) or every unreached bit of a
+// search still running (bottom-up).  The lane reads its list in order, four
+// entries per step, until every open bit is found (top-down: each has a
+// frontier neighbor) or kMsLaneLimit entries; a longer list goes to
+// ms_pending_kernel with the bits still open.  A lane's parents wait in LDS
+// until its vertex is done; rows are then written one root at a time, so
+// that the lanes of a wave write one row's consecutive entries together.
+template <class Acc, bool kParent, bool kTD>
+__global__ __launch_bounds__(kMsThreads) void ms_resolve_kernel(
+    Acc acc, uint32_t n, int32_t next_depth, unsigned long long active, const unsigned long long *__restrict__ fr,
+    unsigned long long *__restrict__ vis, unsigned long long *__restrict__ nx, int32_t *__restrict__ depth,
+    int32_t *__restrict__ parent, uint64_t *__restrict__ bits, uint32_t *__restrict__ pend_v,
+    unsigned long long *__restrict__ pend_m, unsigned long long *__restrict__ ctr) {
+    __shared__ uint32_t s_par[kParent ? kMsThreads * (kMsRoots + 1) : 1];  // 65 per lane: conflict-free by root
+    __shared__ unsigned long long s_act[kMsThreads / kWave];
+    uint32_t *par = &s_par[kParent ? threadIdx.x * (kMsRoots + 1) : 0];
+    const uint32_t lane = lane_id();
+    const uint64_t words = ((uint64_t)n + 63) / 64;
+    const uint64_t wstride = ((uint64_t)gridDim.x * blockDim.x) / kWave;
+    unsigned long long act = 0ull;  // searches with a vertex in the next frontier
+    for (uint64_t q = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave; q < words; q += wstride) {
+        const uint64_t v = q * 64 + lane;
+        const bool valid = v < n;
+        const uint64_t vc = valid ? v : n - 1;
+        unsigned long long P;
+        if constexpr (kTD) P = valid ? nx[vc] : 0ull;
+        else P = valid ? (~vis[vc] & active) : 0ull;
+        if (__ballot(P != 0ull) == 0) {  // wave-uniform: nothing open in this word
+            if constexpr (!kTD) {
+                if (valid) nx[v] = 0ull;
+            }
+            if (lane == 0) bits[q] = 0ull;
+            continue;
+        }
+        const VInfo vi = wave_info(acc, q * 64, n);
+        unsigned long long found = 0ull;
+        bool pending = false;
+        if (P && vi.deg) {
+            const uint32_t st = Acc::step(vi.w), mk = Acc::mask(vi.w);
+            const uint32_t lim = vi.deg < kMsLaneLimit ? vi.deg : kMsLaneLimit;
+            for (uint32_t i = 0; i < lim && found != P; i += 4) {
+                // four list loads, then four mask loads (entries past the
+                // limit re-read the first one, which exists)
+                uint32_t u[4];
+                unsigned long long m[4];
+#pragma unroll
+                for (int b = 0; b < 4; ++b) u[b] = acc.get(vi.start + (uint64_t)(i + b < lim ? i + b : 0u) * st, mk);
+#pragma unroll
+                for (int b = 0; b < 4; ++b) m[b] = fr[u[b]];
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    unsigned long long h = (i + b < lim) ? (m[b] & P & ~found) : 0ull;
+                    found |= h;
+                    if constexpr (kParent) {
+                        while (h) {
+                            par[__ffsll((long long)h) - 1] = u[b];
+                            h &= h - 1;
+                        }
+                    }
+                }
+            }
+            pending = found != P && vi.deg > lim;
+        }
+        // the rows of the roots found here, one root at a time
+        for (unsigned long long bb = wave_or64(found); bb; bb &= bb - 1) {
+            const uint32_t r = (uint32_t)__ffsll((long long)bb) - 1;
+            if ((found >> r) & 1ull) {
+                depth[(uint64_t)r * n + v] = next_depth;
+                if constexpr (kParent) parent[(uint64_t)r * n + v] = (int32_t)par[r];
+            }
+        }
+        if (valid) {
+            if constexpr (kTD) {
+                vis[v] |= P;  // every candidate is reached at this level
+            } else {
+                vis[v] |= found;
+                nx[v] = found;
+            }
+        }
+        act |= kTD ? P : found;
+        const uint64_t pm = __ballot(pending);
+        if (pm) {
+            unsigned long long base = 0;
+            if (lane == 0) base = atomicAdd(&ctr[3], (unsigned long long)__popcll(pm));
+            base = __shfl(base, 0, kWave) + popc_below(pm);
+            if (pending) {
+                pend_v[base] = (uint32_t)v;
+                pend_m[base] = P & ~found;
+            }
+        }
+        // the next frontier's words: a pending bottom-up vertex may still
+        // find bits (counting it costs nothing if it does not)
+        const uint64_t fw_bits = __ballot(valid && (kTD ? P != 0ull : (found != 0ull || pending)));
+        if (lane == 0) bits[q] = fw_bits;
+    }
+    act = wave_or64(act);
+    if (lane == 0) s_act[threadIdx.x / kWave] = act;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long a = 0ull;
+        for (int i = 0; i < kMsThreads / kWave; ++i) a |= s_act[i];
+        if (a) atomicOr(&ctr[2], a);
+    }
+}
+
+// The long lists left by ms_resolve_kernel: a wave per vertex reads the rest
+// of the list 64 entries per step; for each open bit the first lane holding
+// it gives the parent.
+template <class Acc, bool kParent, bool kTD>
+__global__ void ms_pending_kernel(Acc acc, uint32_t n, int32_t next_depth, const unsigned long long *__restrict__ fr,
+                                  unsigned long long *__restrict__ vis, unsigned long long *__restrict__ nx,
+                                  int32_t *__restrict__ depth, int32_t *__restrict__ parent,
+                                  const uint32_t *__restrict__ pend_v, const unsigned long long *__restrict__ pend_m,
+                                  unsigned long long *__restrict__ ctr) {
+    const uint32_t lane = lane_id();
+    const uint64_t np = ctr[3];
+    const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) / kWave;
+    unsigned long long act = 0ull;
+    for (uint64_t k = wave; k < np; k += nwaves) {
+        const uint32_t v = pend_v[k];
+        unsigned long long P = pend_m[k];
+        const VInfo vi = acc.info(v);
+        const uint32_t st = Acc::step(vi.w), mk = Acc::mask(vi.w);
+        unsigned long long got = 0ull;
+        for (uint64_t e0 = kMsLaneLimit; e0 < vi.deg && P; e0 += kWave) {
+            const uint64_t idx = e0 + lane;
+            const bool in = idx < vi.deg;
+            const uint32_t u = acc.get(vi.start + (in ? idx : 0ull) * st, mk);
+            const unsigned long long m = in ? (fr[u] & P) : 0ull;
+            const unsigned long long uni = wave_or64(m);
+            for (unsigned long long bb = uni; bb; bb &= bb - 1) {
+                const uint32_t r = (uint32_t)__ffsll((long long)bb) - 1;
+                const uint64_t holders = __ballot((m >> r) & 1ull);
+                const uint32_t first = (uint32_t)__ffsll((long long)holders) - 1;
+                const uint32_t pu = __shfl(u, first, kWave);
+                if (lane == 0) {
+                    depth[(uint64_t)r * n + v] = next_depth;
+                    if constexpr (kParent) parent[(uint64_t)r * n + v] = (int32_t)pu;
+                }
+            }
+            P &= ~uni;
+            got |= uni;
+        }
+        if (lane == 0 && got) {
+            if constexpr (!kTD) {
+                atomicOr(&nx[v], got);
+                atomicOr(&vis[v], got);
+            }
+        }
+        act |= got;
+    }
+    if (lane == 0 && act) atomicOr(&ctr[2], act);
+}
+
+// After the last level: -1 in the rows of the searches that never reached v.
+__global__ void ms_finish_kernel(uint32_t n, uint32_t r, const unsigned long long *__restrict__ vis,
+                                 int32_t *__restrict__ depth, int32_t *__restrict__ parent) {
+    const uint32_t lane = lane_id();
+    const uint64_t words = ((uint64_t)n + 63) / 64;
+    const uint64_t wstride = ((uint64_t)gridDim.x * blockDim.x) / kWave;
+    const unsigned long long all = r >= 64 ? ~0ull : ((1ull << r) - 1ull);
+    for (uint64_t q = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave; q < words; q += wstride) {
+        const uint64_t v = q * 64 + lane;
+        const unsigned long long open = v < n ? (~vis[v] & all) : 0ull;
+        for (unsigned long long bb = wave_or64(open); bb; bb &= bb - 1) {
+            const uint32_t i = (uint32_t)__ffsll((long long)bb) - 1;
+            if ((open >> i) & 1ull) {
+                depth[(uint64_t)i * n + v] = -1;
+                if (parent) parent[(uint64_t)i * n + v] = -1;
+            }
+        }
+    }
+}
+
+// One batch of at most 64 roots (stored labels = original IDs: the graph is
+// not relabeled).  The host reads two counters per level: the next
+// frontier's size and the searches still running.
+template <class Acc>
+static lg_status bfs_ms_batch(lg_graph *g, BfsWork &w, MsWork &ms, Acc acc, const uint32_t *roots, uint32_t r,
+                              int32_t *depth, int32_t *parent, int32_t max_depth, hipStream_t s) {
+    const uint32_t n = g->n;
+    const uint64_t words = ((uint64_t)n + 63) / 64;
+    unsigned long long *vis = ms.vis.as<unsigned long long>();
+    unsigned long long *fr = ms.fr.as<unsigned long long>();
+    unsigned long long *nx = ms.nx.as<unsigned long long>();
+    uint64_t *bits = ms.bits.as<uint64_t>();
+    unsigned long long *ctr = w.counters.as<unsigned long long>();
+    uint32_t *queue = w.qa.as<uint32_t>();
+    const uint32_t wgrid = grid_for(words * kWave, 256, kStrideBlocks);
+    LG_TRY(fill_u64((uint64_t *)vis, 0, n, s));
+    LG_TRY(fill_u64((uint64_t *)fr, 0, n, s));
+    LG_TRY(fill_u64((uint64_t *)ctr, 0, 8, s));
+    LG_CHECK_HIP(hipMemcpyAsync(ms.roots.p, roots, (uint64_t)r * 4, hipMemcpyHostToDevice, s));
+    LG_LAUNCH(ms_roots_kernel, 1, kMsRoots, 0, s, r, ms.roots.as<uint32_t>(), (uint64_t)n, vis, fr, depth, parent);
+    LG_CHECK_LAUNCH();
+    LG_LAUNCH(ms_bits_kernel, wgrid, 256, 0, s, n, (const unsigned long long *)fr, bits);
+    LG_CHECK_LAUNCH();
+    LG_LAUNCH(bitmap_to_queue_kernel, grid_for(words, 256, 1u << 16), 256, 0, s, words, bits, queue, ctr);
+    LG_CHECK_LAUNCH();
+    LG_CHECK_HIP(hipMemcpyAsync(w.host, ctr, 8, hipMemcpyDeviceToHost, s));
+    LG_CHECK_HIP(hipStreamSynchronize(s));
+    uint64_t fsize = w.host[0];
+    unsigned long long active = r >= 64 ? ~0ull : ((1ull << r) - 1ull);
+    const uint32_t rgrid = grid_for(words * kWave, kMsThreads, kStrideBlocks);
+    for (int32_t level = 0; fsize && active && (max_depth < 0 || level < max_depth); ++level) {
+        // top-down while the frontier's edges are under an eighth of the
+        // graph's (a bottom-up level reads every open vertex's list)
+        bool td = fsize <= (uint64_t)n / 32;
+        uint64_t fedges = 0;
+        if (td) {
+            LG_LAUNCH(td_prepare_kernel<Acc>, grid_for(fsize, 256, 1u << 16), 256, 0, s, acc, queue, (uint32_t)fsize,
+                      w.fstart.as<uint64_t>(), w.fdeg.as<uint32_t>(), w.fw.as<uint32_t>());
+            LG_CHECK_LAUNCH();
+            LG_TRY(exclusive_scan_u32(w.fdeg.as<uint32_t>(), w.fscan.as<uint64_t>(), fsize, w.scan_tmp, s));
+            LG_CHECK_HIP(hipMemcpyAsync(w.host, w.fscan.as<uint64_t>() + fsize, 8, hipMemcpyDeviceToHost, s));
+            LG_CHECK_HIP(hipStreamSynchronize(s));
+            fedges = w.host[0];
+            td = fedges * 8 < g->m;
+        }
+        LG_TRY(fill_u64((uint64_t *)ctr, 0, 8, s));  // [0] queue, [2] running searches, [3] pending
+        if (td) {
+            LG_TRY(fill_u64((uint64_t *)nx, 0, n, s));
+            if (fedges) {
+                LG_LAUNCH(ms_mark_kernel<Acc>, grid_for(fedges, kTdTile, 1u << 20), kTdThreads, 0, s, acc, queue,
+                          (uint32_t)fsize, w.fstart.as<uint64_t>(), w.fw.as<uint32_t>(), w.fscan.as<uint64_t>(),
+                          fedges, (const unsigned long long *)fr, (const unsigned long long *)vis, nx);
+                LG_CHECK_LAUNCH();
+            }
+        }
+        auto resolve = [&](auto kpar, auto ktd) -> lg_status {
+            constexpr bool P = decltype(kpar)::value, T = decltype(ktd)::value;
+            LG_LAUNCH((ms_resolve_kernel<Acc, P, T>), rgrid, kMsThreads, 0, s, acc, n, level + 1, active,
+                      (const unsigned long long *)fr, vis, nx, depth, parent, bits, ms.pend_v.as<uint32_t>(),
+                      ms.pend_m.as<unsigned long long>(), ctr);
+            LG_CHECK_LAUNCH();
+            LG_LAUNCH((ms_pending_kernel<Acc, P, T>), kStrideBlocks, 256, 0, s, acc, n, level + 1,
+                      (const unsigned long long *)fr, vis, nx, depth, parent, (const uint32_t *)ms.pend_v.p,
+                      (const unsigned long long *)ms.pend_m.p, ctr);
+            LG_CHECK_LAUNCH();
+            return LG_OK;
+        };
+        if (parent) {
+            if (td) LG_TRY(resolve(std::true_type{}, std::true_type{}));
+            else LG_TRY(resolve(std::true_type{}, std::false_type{}));
+        } else {
+            if (td) LG_TRY(resolve(std::false_type{}, std::true_type{}));
+            else LG_TRY(resolve(std::false_type{}, std::false_type{}));
+        }
+        LG_LAUNCH(bitmap_to_queue_kernel, grid_for(words, 256, 1u << 16), 256, 0, s, words, bits, queue, ctr);
+        LG_CHECK_LAUNCH();
+        LG_CHECK_HIP(hipMemcpyAsync(w.host, ctr, 24, hipMemcpyDeviceToHost, s));
+        LG_CHECK_HIP(hipStreamSynchronize(s));
+        fsize = w.host[0];
+        active = w.host[2];
+        std::swap(fr, nx);
+    }
+    LG_LAUNCH(ms_finish_kernel, wgrid, 256, 0, s, n, r, (const unsigned long long *)vis, depth, parent);
+    LG_CHECK_LAUNCH();
+    return LG_OK;
+}
+
 constexpr uint32_t kBfsLanes = 8;
 
 // One set of lanes per device, shared by all graphs (workspaces grow to the
@@ -1870,6 +2254,53 @@ static lg_status bfs_run_lanes(lg_graph *g, const uint32_t *roots, uint32_t r, i
     return LG_OK;
 }
 
+// Several roots of a direction-optimizing search on a graph that is not
+// relabeled and not read in order only: the multi-source traversal, 64
+// roots per batch.  It runs on `stream` and holds the device's BFS pool
+// (its lane 0 workspace, the multi-source masks) for its duration.
+static bool bfs_ms_applies(const lg_graph *g, uint32_t r, uint32_t flags) {
+    if (r < 2 || flags != LG_BFS_DIRECTION_OPT || g->relabel != LG_RELABEL_NONE) return false;
+    if (g->layout == LG_LAYOUT_PLAIN) return true;
+    return !g->weighted && (g->id_mode == LG_IDS_GLOBAL || g->id_mode == LG_IDS_LOCAL) &&
+           g->offset_mode != LG_OFFS_INTERLEAVED_BV;
+}
+
+static lg_status bfs_run_ms(lg_graph *g, const uint32_t *roots, uint32_t r, int32_t *depth, int32_t *parent,
+                            int32_t max_depth, hipStream_t stream) {
+    DevicePools &dp = device_pools();
+    std::mutex *dev_lock;
+    BfsPool **slot;
+    {
+        std::lock_guard<std::mutex> gl(dp.mu);
+        if (!dp.locks.count(g->device)) dp.locks[g->device] = new std::mutex();
+        dev_lock = dp.locks[g->device];
+        slot = &dp.pools[g->device];
+    }
+    std::lock_guard<std::mutex> hold(*dev_lock);
+    LG_TRY(pool_ensure(*slot, 1));
+    BfsPool &p = **slot;
+    BfsWork &w = p.lanes[0]->work;
+    MsWork &ms = p.ms;
+    const uint64_t n = g->n, words = (n + 63) / 64;
+    LG_TRY(bfs_workspace_ensure(w, n, g->n_heavy, false, parent != nullptr));
+    LG_TRY(ms.vis.ensure(n * 8));
+    LG_TRY(ms.fr.ensure(n * 8));
+    LG_TRY(ms.nx.ensure(n * 8));
+    LG_TRY(ms.bits.ensure(words * 8));
+    LG_TRY(ms.pend_v.ensure(n * 4));
+    LG_TRY(ms.pend_m.ensure(n * 8));
+    LG_TRY(ms.roots.ensure(kMsRoots * 4));
+    // lane 0's stream is not used: everything runs on the caller's stream
+    return dispatch_acc(g, [&](auto acc) -> lg_status {
+        for (uint32_t b0 = 0; b0 < r; b0 += kMsRoots) {
+            const uint32_t rb = std::min<uint32_t>(kMsRoots, r - b0);
+            LG_TRY(bfs_ms_batch(g, w, ms, acc, roots + b0, rb, depth + (uint64_t)b0 * n,
+                                parent ? parent + (uint64_t)b0 * n : nullptr, max_depth, stream));
+        }
+        return LG_OK;  // batches follow each other on the caller's stream (shared masks and roots buffer)
+    });
+}
+
 }  // namespace lg
 
 extern "C" lg_status lg_bfs(const lg_graph *gc, const uint32_t *roots, uint32_t r, int32_t *depth, int32_t *parent,
@@ -1881,6 +2312,10 @@ extern "C" lg_status lg_bfs(const lg_graph *gc, const uint32_t *roots, uint32_t 
     for (uint32_t i = 0; i < r; ++i)
         if (roots[i] >= g->n) { set_error("lg_bfs: root %u out of range", roots[i]); return LG_ERR_INVALID; }
     if (r == 0) return LG_OK;
+    if (bfs_ms_applies(g, r, flags)) {
+        LG_TRY(bfs_run_ms(g, roots, r, depth, parent, max_depth, stream));
+        return mark_use(g, stream);
+    }
     if (r > 1) {
         // the lanes' work is joined back into `stream` before this returns
         LG_TRY(bfs_run_lanes(g, roots, r, depth, parent, max_depth, flags, stream));

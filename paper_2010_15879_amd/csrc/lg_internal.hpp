@@ -128,9 +128,22 @@ struct BfsLane {
     hipEvent_t done = nullptr;
     BfsWork work;
 };
+// Multi-source BFS of up to 64 roots at once (lg_bfs.hip): per vertex a
+// 64-bit mask per state (bit i: root i), a frontier bitmap, and the vertices
+// whose long lists a whole wave finishes.
+struct MsWork {
+    DevBuf vis, fr, nx;          // u64[n]: reached, in this level's frontier, in the next one
+    DevBuf bits;                 // u64[words]: vertices of the next frontier
+    DevBuf pend_v, pend_m;       // u32[n], u64[n]: vertices left for the wave pass, their open bits
+    DevBuf roots;                // u32[64]: the batch's roots
+    uint64_t bytes() const {
+        return vis.bytes + fr.bytes + nx.bytes + bits.bytes + pend_v.bytes + pend_m.bytes + roots.bytes;
+    }
+};
 struct BfsPool {
     std::vector<BfsLane *> lanes;
     hipEvent_t start = nullptr;
+    MsWork ms;
     ~BfsPool();
     uint64_t bytes() const;
 };
