@@ -1796,13 +1796,14 @@ __device__ __forceinline__ unsigned long long wave_or64(unsigned long long x) {
     return ((unsigned long long)hi << 32) | lo;
 }
 
-// the roots: reached at depth 0, their own parents, in the first frontier
-__global__ void ms_roots_kernel(uint32_t r, const uint32_t *__restrict__ roots, uint64_t n,
-                                unsigned long long *__restrict__ vis, unsigned long long *__restrict__ fr,
+// the roots (original IDs, mapped to labels through inv when relabeled):
+// reached at depth 0, their own parents, in the first frontier
+__global__ void ms_roots_kernel(uint32_t r, const uint32_t *__restrict__ roots, const uint32_t *__restrict__ inv,
+                                uint64_t n, unsigned long long *__restrict__ vis, unsigned long long *__restrict__ fr,
                                 int32_t *__restrict__ depth, int32_t *__restrict__ parent) {
     const uint32_t i = threadIdx.x;
     if (i >= r) return;
-    const uint32_t x = roots[i];
+    const uint32_t x = inv ? inv[roots[i]] : roots[i];
     atomicOr(&vis[x], 1ull << i);
     atomicOr(&fr[x], 1ull << i);
     depth[(uint64_t)i * n + x] = 0;
@@ -1900,18 +1901,29 @@ __global__ __launch_bounds__(kTdThreads) void ms_mark_kernel(
 // search still running (bottom-up).  The lane reads its list in order, four
 // entries per step, until every open bit is found (top-down: each has a
 // frontier neighbor) or kMsLaneLimit entries; a longer list goes to
-// ms_pending_kernel with the bits still open.  A lane's parents wait in LDS
-// until its vertex is done; rows are then written one root at a time, so
-// that the lanes of a wave write one row's consecutive entries together.
+// ms_pending_kernel with the bits still open.  A lane keeps, per root, the
+// list position of the parent (one byte: positions stay under kMsLaneLimit)
+// in LDS until its vertex is done; rows are then written four roots at a
+// time, so that the lanes of a wave write one row's consecutive entries
+// together and the parents' list reads are in flight together.  The byte
+// stage and the register bound let eight waves share a SIMD: the list and
+// mask reads are dependent random loads, so the kernel lives on occupancy.
+constexpr uint32_t kMsParStride = kMsRoots + 4;  // bytes per lane: 17 words, so lanes fall on distinct banks
+static_assert(kMsLaneLimit <= 256, "a parent's list position is kept in one byte");
+
+// (the Elias-Fano offset lookup of wave_info needs more registers: five waves)
+template <class A> struct MsWavesPerEU { static constexpr int value = 8; };
+template <int I, int O> struct MsWavesPerEU<PackedAcc<I, O>> { static constexpr int value = O == kOffsEF ? 5 : 8; };
+
 template <class Acc, bool kParent, bool kTD>
-__global__ __launch_bounds__(kMsThreads) void ms_resolve_kernel(
+__global__ __launch_bounds__(kMsThreads, MsWavesPerEU<Acc>::value) void ms_resolve_kernel(
     Acc acc, uint32_t n, int32_t next_depth, unsigned long long active, const unsigned long long *__restrict__ fr,
     unsigned long long *__restrict__ vis, unsigned long long *__restrict__ nx, int32_t *__restrict__ depth,
     int32_t *__restrict__ parent, uint64_t *__restrict__ bits, uint32_t *__restrict__ pend_v,
     unsigned long long *__restrict__ pend_m, unsigned long long *__restrict__ ctr) {
-    __shared__ uint32_t s_par[kParent ? kMsThreads * (kMsRoots + 1) : 1];  // 65 per lane: conflict-free by root
+    __shared__ uint8_t s_par[kParent ? kMsThreads * kMsParStride : 4];
     __shared__ unsigned long long s_act[kMsThreads / kWave];
-    uint32_t *par = &s_par[kParent ? threadIdx.x * (kMsRoots + 1) : 0];
+    uint8_t *par = &s_par[kParent ? threadIdx.x * kMsParStride : 0];
     const uint32_t lane = lane_id();
     const uint64_t words = ((uint64_t)n + 63) / 64;
     const uint64_t wstride = ((uint64_t)gridDim.x * blockDim.x) / kWave;
@@ -1933,8 +1945,8 @@ __global__ __launch_bounds__(kMsThreads) void ms_resolve_kernel(
         const VInfo vi = wave_info(acc, q * 64, n);
         unsigned long long found = 0ull;
         bool pending = false;
+        const uint32_t st = Acc::step(vi.w), mk = Acc::mask(vi.w);
         if (P && vi.deg) {
-            const uint32_t st = Acc::step(vi.w), mk = Acc::mask(vi.w);
             const uint32_t lim = vi.deg < kMsLaneLimit ? vi.deg : kMsLaneLimit;
             for (uint32_t i = 0; i < lim && found != P; i += 4) {
                 // four list loads, then four mask loads (entries past the
@@ -1951,7 +1963,7 @@ __global__ __launch_bounds__(kMsThreads) void ms_resolve_kernel(
                     found |= h;
                     if constexpr (kParent) {
                         while (h) {
-                            par[__ffsll((long long)h) - 1] = u[b];
+                            par[__ffsll((long long)h) - 1] = (uint8_t)(i + b);
                             h &= h - 1;
                         }
                     }
@@ -1959,12 +1971,34 @@ __global__ __launch_bounds__(kMsThreads) void ms_resolve_kernel(
             }
             pending = found != P && vi.deg > lim;
         }
-        // the rows of the roots found here, one root at a time
-        for (unsigned long long bb = wave_or64(found); bb; bb &= bb - 1) {
-            const uint32_t r = (uint32_t)__ffsll((long long)bb) - 1;
-            if ((found >> r) & 1ull) {
-                depth[(uint64_t)r * n + v] = next_depth;
-                if constexpr (kParent) parent[(uint64_t)r * n + v] = (int32_t)par[r];
+        // the rows of the roots found here, four roots at a time (a found
+        // bit implies a non-empty list, so its position names an entry; the
+        // other lanes read the array's first entry, which exists whenever
+        // any bit is found, and drop it)
+        for (unsigned long long bb = wave_or64(found); bb;) {
+            uint32_t rr[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                rr[k] = bb ? (uint32_t)__ffsll((long long)bb) - 1 : kMsRoots;
+                bb &= bb - 1;
+            }
+            bool has[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) has[k] = rr[k] < kMsRoots && ((found >> rr[k]) & 1ull);
+            uint32_t pu[4];
+            if constexpr (kParent) {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const uint64_t pos = has[k] ? vi.start + (uint64_t)par[rr[k]] * st : 0ull;
+                    pu[k] = acc.get(pos, mk);
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                if (has[k]) {
+                    depth[(uint64_t)rr[k] * n + v] = next_depth;
+                    if constexpr (kParent) parent[(uint64_t)rr[k] * n + v] = (int32_t)pu[k];
+                }
             }
         }
         if (valid) {
@@ -2071,13 +2105,16 @@ __global__ void ms_finish_kernel(uint32_t n, uint32_t r, const unsigned long lon
     }
 }
 
-// One batch of at most 64 roots (stored labels = original IDs: the graph is
-// not relabeled).  The host reads two counters per level: the next
-// frontier's size and the searches still running.
+// One batch of at most 64 roots.  The rows are computed in label space; on
+// a relabeled graph each row then goes through one workspace row and back
+// in original IDs (bfs_unpermute_kernel, as for a single root).  The host
+// reads two counters per level: the next frontier's size and the searches
+// still running.
 template <class Acc>
 static lg_status bfs_ms_batch(lg_graph *g, BfsWork &w, MsWork &ms, Acc acc, const uint32_t *roots, uint32_t r,
                               int32_t *depth, int32_t *parent, int32_t max_depth, hipStream_t s) {
     const uint32_t n = g->n;
+    const bool rel = g->relabel != LG_RELABEL_NONE;
     const uint64_t words = ((uint64_t)n + 63) / 64;
     unsigned long long *vis = ms.vis.as<unsigned long long>();
     unsigned long long *fr = ms.fr.as<unsigned long long>();
@@ -2090,7 +2127,8 @@ static lg_status bfs_ms_batch(lg_graph *g, BfsWork &w, MsWork &ms, Acc acc, cons
     LG_TRY(fill_u64((uint64_t *)fr, 0, n, s));
     LG_TRY(fill_u64((uint64_t *)ctr, 0, 8, s));
     LG_CHECK_HIP(hipMemcpyAsync(ms.roots.p, roots, (uint64_t)r * 4, hipMemcpyHostToDevice, s));
-    LG_LAUNCH(ms_roots_kernel, 1, kMsRoots, 0, s, r, ms.roots.as<uint32_t>(), (uint64_t)n, vis, fr, depth, parent);
+    LG_LAUNCH(ms_roots_kernel, 1, kMsRoots, 0, s, r, ms.roots.as<uint32_t>(), rel ? g->inv.as<uint32_t>() : nullptr,
+              (uint64_t)n, vis, fr, depth, parent);
     LG_CHECK_LAUNCH();
     LG_LAUNCH(ms_bits_kernel, wgrid, 256, 0, s, n, (const unsigned long long *)fr, bits);
     LG_CHECK_LAUNCH();
@@ -2100,7 +2138,14 @@ static lg_status bfs_ms_batch(lg_graph *g, BfsWork &w, MsWork &ms, Acc acc, cons
     LG_CHECK_HIP(hipStreamSynchronize(s));
     uint64_t fsize = w.host[0];
     unsigned long long active = r >= 64 ? ~0ull : ((1ull << r) - 1ull);
-    const uint32_t rgrid = grid_for(words * kWave, kMsThreads, kStrideBlocks);
+    // the resolve grid: on graphs with even degrees two workgroups per CU
+    // (more waves only evict the lanes' list lines under the random mask
+    // reads: measured slower); on skewed ones, where lanes of a wave wait
+    // on each other's long lists, the full grid hides the latency
+    int cus = 0;
+    LG_CHECK_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, g->device));
+    const bool skewed = (uint64_t)g->n_heavy * 256 > n;
+    const uint32_t rgrid = grid_for(words * kWave, kMsThreads, skewed ? kStrideBlocks : (uint32_t)std::max(1, 2 * cus));
     for (int32_t level = 0; fsize && active && (max_depth < 0 || level < max_depth); ++level) {
         // top-down while the frontier's edges are under an eighth of the
         // graph's (a bottom-up level reads every open vertex's list)
@@ -2155,6 +2200,19 @@ static lg_status bfs_ms_batch(lg_graph *g, BfsWork &w, MsWork &ms, Acc acc, cons
     }
     LG_LAUNCH(ms_finish_kernel, wgrid, 256, 0, s, n, r, (const unsigned long long *)vis, depth, parent);
     LG_CHECK_LAUNCH();
+    if (rel) {
+        int32_t *tmp_d = w.depth_i.as<int32_t>();
+        uint32_t *tmp_p = parent ? w.parent_i.as<uint32_t>() : nullptr;
+        for (uint32_t i = 0; i < r; ++i) {
+            int32_t *d_row = depth + (uint64_t)i * n;
+            int32_t *p_row = parent ? parent + (uint64_t)i * n : nullptr;
+            LG_CHECK_HIP(hipMemcpyAsync(tmp_d, d_row, (uint64_t)n * 4, hipMemcpyDeviceToDevice, s));
+            if (p_row) LG_CHECK_HIP(hipMemcpyAsync(tmp_p, p_row, (uint64_t)n * 4, hipMemcpyDeviceToDevice, s));
+            LG_LAUNCH(bfs_unpermute_kernel, grid_for(n, 256, 1u << 16), 256, 0, s, n, g->inv.as<uint32_t>(),
+                      g->perm.as<uint32_t>(), (const int32_t *)tmp_d, (const uint32_t *)tmp_p, d_row, p_row);
+            LG_CHECK_LAUNCH();
+        }
+    }
     return LG_OK;
 }
 
@@ -2254,15 +2312,27 @@ static lg_status bfs_run_lanes(lg_graph *g, const uint32_t *roots, uint32_t r, i
     return LG_OK;
 }
 
-// Several roots of a direction-optimizing search on a graph that is not
-// relabeled and not read in order only: the multi-source traversal, 64
-// roots per batch.  It runs on `stream` and holds the device's BFS pool
-// (its lane 0 workspace, the multi-source masks) for its duration.
-static bool bfs_ms_applies(const lg_graph *g, uint32_t r, uint32_t flags) {
-    if (r < 2 || flags != LG_BFS_DIRECTION_OPT || g->relabel != LG_RELABEL_NONE) return false;
+// Several roots of a direction-optimizing search on a graph whose lists are
+// not read in order only: the multi-source traversal, in batches of up to
+// 64 roots while at least kMsMinRoots are left (fewer go to the lanes: a
+// multi-source level reads whole lists for every search still open, which
+// the one-root searches beat below about 32 roots on the graphs measured).
+// It runs on `stream` and holds the device's BFS pool (its lane 0
+// workspace, the multi-source masks) for its duration.
+constexpr uint32_t kMsMinRoots = 32;
+
+static bool bfs_ms_graph(const lg_graph *g, uint32_t flags) {
+    if (flags != LG_BFS_DIRECTION_OPT) return false;
     if (g->layout == LG_LAYOUT_PLAIN) return true;
     return !g->weighted && (g->id_mode == LG_IDS_GLOBAL || g->id_mode == LG_IDS_LOCAL) &&
            g->offset_mode != LG_OFFS_INTERLEAVED_BV;
+}
+
+// how many of r roots the multi-source batches take (the first ones)
+static uint32_t bfs_ms_roots(uint32_t r) {
+    uint32_t k = 0;
+    while (r - k >= kMsMinRoots) k += std::min<uint32_t>(kMsRoots, r - k);
+    return k;
 }
 
 static lg_status bfs_run_ms(lg_graph *g, const uint32_t *roots, uint32_t r, int32_t *depth, int32_t *parent,
@@ -2282,7 +2352,7 @@ static lg_status bfs_run_ms(lg_graph *g, const uint32_t *roots, uint32_t r, int3
     BfsWork &w = p.lanes[0]->work;
     MsWork &ms = p.ms;
     const uint64_t n = g->n, words = (n + 63) / 64;
-    LG_TRY(bfs_workspace_ensure(w, n, g->n_heavy, false, parent != nullptr));
+    LG_TRY(bfs_workspace_ensure(w, n, g->n_heavy, g->relabel != LG_RELABEL_NONE, parent != nullptr));
     LG_TRY(ms.vis.ensure(n * 8));
     LG_TRY(ms.fr.ensure(n * 8));
     LG_TRY(ms.nx.ensure(n * 8));
@@ -2312,8 +2382,14 @@ extern "C" lg_status lg_bfs(const lg_graph *gc, const uint32_t *roots, uint32_t 
     for (uint32_t i = 0; i < r; ++i)
         if (roots[i] >= g->n) { set_error("lg_bfs: root %u out of range", roots[i]); return LG_ERR_INVALID; }
     if (r == 0) return LG_OK;
-    if (bfs_ms_applies(g, r, flags)) {
-        LG_TRY(bfs_run_ms(g, roots, r, depth, parent, max_depth, stream));
+    const uint32_t r_ms = bfs_ms_graph(g, flags) ? bfs_ms_roots(r) : 0;
+    if (r_ms) {
+        LG_TRY(bfs_run_ms(g, roots, r_ms, depth, parent, max_depth, stream));
+        if (r_ms < r) {
+            const uint64_t off = (uint64_t)r_ms * g->n;
+            LG_TRY(bfs_run_lanes(g, roots + r_ms, r - r_ms, depth + off, parent ? parent + off : nullptr, max_depth,
+                                 flags, stream));
+        }
         return mark_use(g, stream);
     }
     if (r > 1) {

@@ -1,6 +1,8 @@
-"""lg_bfs with many roots runs them a few at a time on internal streams:
-every row must equal the result of a call with that root alone, and work on
-the caller's stream must be ordered around the call."""
+"""lg_bfs with many roots runs batches of at least 32 of them as one
+multi-source traversal and the rest a few at a time on internal streams:
+every row must equal the result of a call with that root alone, whichever
+path took it, and work on the caller's stream must be ordered around the
+call."""
 
 import numpy as np
 import pytest
@@ -19,19 +21,31 @@ def lgmod():
     return lg
 
 
+def small_graph(name):
+    """A skewed graph (many vertices over the heavy-degree threshold) and an
+    even-degree one: the multi-source resolve picks its grid by that."""
+    if name == "kron13":
+        return gg.kronecker(13, 16, seed=5, device="cuda")
+    return gg.erdos_renyi(13, 8, seed=3, device="cuda")
+
+
+@pytest.mark.parametrize("graph", ["kron13", "er13"])
+@pytest.mark.parametrize("count", [9, 37, 70])
 @pytest.mark.parametrize("kw", [dict(), dict(ids="local", offsets="succinct", relabel=True),
                                 dict(layout="plain", relabel=True)])
 @pytest.mark.parametrize("max_depth", [-1, 2])
-def test_many_roots_equal_one_at_a_time(lgmod, kw, max_depth):
-    g = gg.kronecker(13, 16, seed=5, device="cuda")
+def test_many_roots_equal_one_at_a_time(lgmod, graph, count, kw, max_depth):
+    """9 roots: lanes only; 37: one multi-source batch; 70: a batch of 64 and
+    six roots on the lanes."""
+    g = small_graph(graph)
     h = lgmod.encode(g.row_offsets, g.col, g.n, **kw)
-    roots = gg.pick_roots(g, 37, seed=2)
+    roots = gg.pick_roots(g, count, seed=2)
     d_all, p_all = lgmod.bfs(h, roots, max_depth=max_depth)
     for i, r in enumerate(roots):
         d1, p1 = lgmod.bfs(h, [r], max_depth=max_depth)
         assert torch.equal(d_all[i], d1[0]) and torch.equal(p_all[i], p1[0]), (i, r)
     off, col = g.numpy()
-    for i in [0, 17, len(roots) - 1]:
+    for i in sorted({0, len(roots) // 2, len(roots) - 1}):
         d0, p0 = orc.bfs(off.astype(np.uint64), col.view(np.uint32), roots[i], max_depth=max_depth,
                          relabeled=bool(kw.get("relabel")))
         np.testing.assert_array_equal(d_all[i].cpu().numpy(), d0)
@@ -39,12 +53,13 @@ def test_many_roots_equal_one_at_a_time(lgmod, kw, max_depth):
     h.free()
 
 
-def test_stream_order_around_the_call(lgmod):
+@pytest.mark.parametrize("count", [9, 40])
+def test_stream_order_around_the_call(lgmod, count):
     """Outputs written on the caller's stream before the call are overwritten by
     it, and a kernel queued after the call sees the final rows."""
     g = gg.kronecker(12, 16, seed=9, device="cuda")
     h = lgmod.encode(g.row_offsets, g.col, g.n)
-    roots = gg.pick_roots(g, 9, seed=3)
+    roots = gg.pick_roots(g, count, seed=3)
     ref, _ = lgmod.bfs(h, roots)
     torch.cuda.synchronize()
     for _ in range(3):
