@@ -167,46 +167,92 @@ __global__ void validate_edges_kernel(uint32_t n, const uint64_t *__restrict__ o
     }
 }
 
-// Symmetry, exactly: the entries (v, u) emitted in row order and sorted
-// stably by u list the transpose in adjacency-array order; the graph is
-// symmetric iff that is the input itself, entry for entry.
+// Symmetry, exactly, from the entries below the diagonal.  Row v's entries
+// smaller than v come first in its sorted list: low[v] of them.  Taken in
+// row order and transposed, (v, u) -> (u, v), then sorted stably by u, they
+// list for every u the rows v > u that hold u, ascending.  The graph is
+// symmetric iff that sequence is, entry for entry, the entries above the
+// diagonal in row order: row u's entries larger than u.  Both halves hold
+// lowoff[n] entries (checked first), and the upper entry at stream position
+// e of row u has index e - lowoff[u + 1] among the upper entries.
+
+// low[v]: the entries of row v smaller than v (binary search of its list)
+__global__ void sym_low_kernel(uint32_t n, const uint64_t *__restrict__ off, const uint32_t *__restrict__ col,
+                               uint32_t *__restrict__ low) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) {
+        uint64_t lo = off[v], hi = off[v + 1];
+        const uint64_t b = lo;
+        while (lo < hi) {
+            const uint64_t mid = lo + (hi - lo) / 2;
+            if (col[mid] < (uint32_t)v) lo = mid + 1;
+            else hi = mid;
+        }
+        low[v] = (uint32_t)(lo - b);
+    }
+}
+
+// the rows' lowoff values for block q (65 of them, clamped at n) into s_lo
+__device__ __forceinline__ void sym_block_lowoff(uint32_t n, const uint32_t *__restrict__ map, uint64_t k,
+                                                 const uint64_t *__restrict__ lowoff, uint64_t *s_lo) {
+    const uint32_t lane = lane_id();
+    const uint64_t v0 = (uint64_t)map[k] * 64;
+    s_lo[lane] = lowoff[v0 + lane <= n ? v0 + lane : n];
+    if (lane == 0) s_lo[64] = lowoff[v0 + 64 <= n ? v0 + 64 : n];
+    // walk_item's opening wave sync orders these writes before its uses
+}
+
 __global__ void sym_emit_kernel(uint32_t n, const uint64_t *__restrict__ off, const uint32_t *__restrict__ col,
                                 uint64_t items, const uint32_t *__restrict__ map, const uint64_t *__restrict__ coff,
-                                uint32_t *__restrict__ key, uint32_t *__restrict__ val) {
+                                const uint64_t *__restrict__ lowoff, uint32_t *__restrict__ key,
+                                uint32_t *__restrict__ val) {
     __shared__ uint64_t s_rs[4][kWave + 1];
+    __shared__ uint64_t s_lo[4][kWave + 1];
     const uint32_t wv = threadIdx.x / kWave;
     const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
     const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) / kWave;
     for (uint64_t k = wave; k < items; k += nwaves) {
         const uint32_t v0 = map[k] * 64u;
+        sym_block_lowoff(n, map, k, lowoff, s_lo[wv]);
         walk_item(
             n, off, map, coff, k, s_rs[wv], [&](uint64_t e, uint32_t, bool valid) { return col[valid ? e : 0]; },
             [&](uint64_t e, uint32_t j, bool valid, uint32_t u) {
-                if (!valid) return;
-                key[e] = u;
-                val[e] = v0 + j;
+                if (!valid || u >= v0 + j) return;  // the row's entries below the diagonal only
+                const uint64_t pos = s_lo[wv][j] + (e - s_rs[wv][j]);
+                key[pos] = u;
+                val[pos] = v0 + j;
             });
     }
 }
 
 __global__ void sym_check_kernel(uint32_t n, const uint64_t *__restrict__ off, const uint32_t *__restrict__ col,
                                  uint64_t items, const uint32_t *__restrict__ map, const uint64_t *__restrict__ coff,
+                                 const uint64_t *__restrict__ lowoff, uint64_t half,
                                  const uint32_t *__restrict__ key, const uint32_t *__restrict__ val,
                                  uint32_t *__restrict__ status) {
     __shared__ uint64_t s_rs[4][kWave + 1];
+    __shared__ uint64_t s_lo[4][kWave + 1];
     const uint32_t wv = threadIdx.x / kWave;
     const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
     const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) / kWave;
     bool bad = false;
     for (uint64_t k = wave; k < items; k += nwaves) {
         const uint32_t v0 = map[k] * 64u;
-        auto load = [&](uint64_t e, uint32_t, bool valid) {
-            const uint64_t i = valid ? e : 0;
-            return make_uint3(key[i], val[i], col[i]);
+        sym_block_lowoff(n, map, k, lowoff, s_lo[wv]);
+        // every entry's would-be index among the upper entries (meaningful for
+        // upper entries only; others read index 0)
+        auto upper_index = [&](uint64_t e, uint32_t j) -> uint64_t {
+            const uint64_t lo1 = s_lo[wv][j + 1];
+            return e >= lo1 && e - lo1 < half ? e - lo1 : 0;
         };
-        walk_item(n, off, map, coff, k, s_rs[wv], load, [&](uint64_t, uint32_t j, bool valid, uint3 x) {
-            if (!valid) return;
-            bad |= x.x != v0 + j || x.y != x.z;
+        auto load = [&](uint64_t e, uint32_t j, bool valid) {
+            const uint64_t i = valid ? upper_index(e, j) : 0;
+            return make_uint3(key[i], val[i], col[valid ? e : 0]);
+        };
+        walk_item(n, off, map, coff, k, s_rs[wv], load, [&](uint64_t e, uint32_t j, bool valid, uint3 x) {
+            if (!valid || x.z <= v0 + j) return;  // the row's entries above the diagonal only
+            const uint64_t lo1 = s_lo[wv][j + 1];
+            bad |= e < lo1 || e - lo1 >= half || x.x != v0 + j || x.y != x.z;
         });
     }
     if (__ballot(bad) && lane_id() == 0) atomicOr(status, kAsymmetric);
@@ -1095,23 +1141,38 @@ static lg_status encode_impl(uint32_t n, uint64_t m, const uint64_t *row_offsets
         LG_CHECK_HIP(hipStreamSynchronize(s));
     }
     if (!bad && m) {
-        DevBuf key, val, key2, val2;
-        LG_TRY(key.scratch(m * 4, s));
-        LG_TRY(val.scratch(m * 4, s));
-        LG_TRY(key2.scratch(m * 4, s));
-        LG_TRY(val2.scratch(m * 4, s));
-        LG_LAUNCH(sym_emit_kernel, walk.grid, 256, 0, s, n, row_offsets, col, walk.items, walk.map.as<uint32_t>(),
-                  walk.coff.as<uint64_t>(), key.as<uint32_t>(), val.as<uint32_t>());
+        // the entries below the diagonal: per row, then their offsets
+        DevBuf low, lowoff;
+        LG_TRY(low.scratch((uint64_t)n * 4, s));
+        LG_TRY(lowoff.scratch(((uint64_t)n + 1) * 8, s));
+        LG_LAUNCH(sym_low_kernel, grid1(n), 256, 0, s, n, row_offsets, col, low.as<uint32_t>());
         LG_CHECK_LAUNCH();
-        int alt = 0;
-        LG_TRY(radix_sort_pairs(key.as<uint32_t>(), val.as<uint32_t>(), key2.as<uint32_t>(), val2.as<uint32_t>(), m,
-                                bitlen_u64(n - 1), tmp, s, &alt));
-        LG_LAUNCH(sym_check_kernel, walk.grid, 256, 0, s, n, row_offsets, col, walk.items, walk.map.as<uint32_t>(),
-                  walk.coff.as<uint64_t>(), (alt ? key2 : key).as<uint32_t>(), (alt ? val2 : val).as<uint32_t>(),
-                  status.as<uint32_t>());
-        LG_CHECK_LAUNCH();
-        LG_CHECK_HIP(hipMemcpyAsync(&bad, status.p, 4, hipMemcpyDeviceToHost, s));
+        LG_TRY(exclusive_scan_u32(low.as<uint32_t>(), lowoff.as<uint64_t>(), n, tmp, s));
+        uint64_t half = 0;
+        LG_CHECK_HIP(hipMemcpyAsync(&half, lowoff.as<uint64_t>() + n, 8, hipMemcpyDeviceToHost, s));
         LG_CHECK_HIP(hipStreamSynchronize(s));
+        if (2 * half != m) {
+            bad = kAsymmetric;  // the two halves differ in size
+        } else {
+            DevBuf key, val, key2, val2;
+            LG_TRY(key.scratch(half * 4, s));
+            LG_TRY(val.scratch(half * 4, s));
+            LG_TRY(key2.scratch(half * 4, s));
+            LG_TRY(val2.scratch(half * 4, s));
+            LG_LAUNCH(sym_emit_kernel, walk.grid, 256, 0, s, n, row_offsets, col, walk.items,
+                      walk.map.as<uint32_t>(), walk.coff.as<uint64_t>(), (const uint64_t *)lowoff.p,
+                      key.as<uint32_t>(), val.as<uint32_t>());
+            LG_CHECK_LAUNCH();
+            int alt = 0;
+            LG_TRY(radix_sort_pairs(key.as<uint32_t>(), val.as<uint32_t>(), key2.as<uint32_t>(),
+                                    val2.as<uint32_t>(), half, bitlen_u64(n - 1), tmp, s, &alt));
+            LG_LAUNCH(sym_check_kernel, walk.grid, 256, 0, s, n, row_offsets, col, walk.items,
+                      walk.map.as<uint32_t>(), walk.coff.as<uint64_t>(), (const uint64_t *)lowoff.p, half,
+                      (alt ? key2 : key).as<uint32_t>(), (alt ? val2 : val).as<uint32_t>(), status.as<uint32_t>());
+            LG_CHECK_LAUNCH();
+            LG_CHECK_HIP(hipMemcpyAsync(&bad, status.p, 4, hipMemcpyDeviceToHost, s));
+            LG_CHECK_HIP(hipStreamSynchronize(s));
+        }
     }
     if (bad) {
         set_error("invalid input graph:%s%s%s%s%s", (bad & kBadOffsets) ? " bad-offsets" : "",
