@@ -58,6 +58,7 @@ COUNTER_SOURCES = {
     "pr": ["lg_pagerank.hip", "lg_pagerank_pb.hip", "lg_device.hpp", "lg_views.hpp", "lg_heavy.hip",
            "lg_varint.hpp"],
     "bfs": ["lg_bfs.hip", "lg_device.hpp", "lg_views.hpp"],
+    "bfsall": ["lg_bfs.hip", "lg_device.hpp", "lg_views.hpp"],
 }
 
 
@@ -187,7 +188,9 @@ def counter_summary_main(args):
                         rtot=x["TCC_EA0_RDREQ_sum"]))
     m = run["stored_edges"]
     phase_name = {"pr": f"one PageRank call of {run['pr_iters']} iterations (with its first-call setup)",
-                  "bfs": f"single-root BFS, modes {run.get('bfs_modes')}"}[run["phase"]]
+                  "bfs": f"single-root BFS, modes {run.get('bfs_modes')}",
+                  "bfsall": f"BFS from all {run.get('roots')} roots in one call (the call the benchmark times)"}[
+                      run["phase"]]
     cmd_of = lambda pas: (f"timeout -s KILL 300 rocprofv3 --pmc {' '.join(COUNTER_PASSES[pas])} "  # noqa: E731
                           f"--kernel-include-regex \"{COUNTER_KERNEL_REGEX}\" --output-format csv "
                           f"-d gpurun_out/cnt/{args.workload}_{args.layout}_{run['phase']}/{pas} -o {pas} -- "
@@ -318,10 +321,11 @@ def parse():
                    help="the workload's graph with local widths, fixed-size gap encoding and Varint lists (full "
                         "labels or differences), with and without the degree-minimizing relabeling (DMf, DMd): "
                         "|A|, encode time, random-vertex list decode, PageRank (own JSON line)")
-    p.add_argument("--counter-run", choices=["pr", "bfs"],
+    p.add_argument("--counter-run", choices=["pr", "bfs", "bfsall"],
                    help="counter-run mode: one elementwise kernel of known traffic (calibration), then one "
-                        "PageRank call (pr) or one single-root BFS per direction mode in --bfs-modes (bfs) on "
-                        "--layout, after a one-element cos kernel that marks where the phase begins; no timing")
+                        "PageRank call (pr), one single-root BFS per direction mode in --bfs-modes (bfs) or the "
+                        "BFS call from all --roots (bfsall) on --layout, after a one-element cos kernel that marks "
+                        "where the phase begins; no timing")
     p.add_argument("--bfs-modes", default="top-down,bottom-up,do",
                    help="counter-run bfs: the direction modes searched, comma separated")
     p.add_argument("--layout", choices=["packed", "plain"], default="packed")
@@ -630,6 +634,11 @@ def main():
             rooflines[layout]["bfs_bytes_per_stored_entry_measured"] = round(tb / M, 4)
             rooflines[layout]["bfs_achieved_gbs_median_root"] = round(
                 tb / (s["per_root"]["ms_median"] / 1000.0) / 1e9, 1)
+        ta = measured_counters("traffic_bytes_per_phase", args.workload, layout, "bfsall")
+        if ta:
+            # the BFS phase as timed: all roots in one call
+            rooflines[layout]["bfs_all_roots_traffic_bytes"] = ta
+            rooflines[layout]["bfs_all_roots_achieved_gbs"] = round(ta / (s["bfs_all_roots_ms"] / 1000.0) / 1e9, 1)
     pr_share = P["pr_kernel"]["avg_launch_ms"] * args.pr_iters
     dominant = P["pr_kernel"]["name"] if pr_share >= max(P["bfs_all_roots_ms"], P["encode_ms"]) else \
         P["largest_summed_kernel"]
@@ -741,16 +750,19 @@ def counter_main(args, np, torch, lg, g, roots, enc):
     if args.counter_run == "pr":
         log("[counter-run] PageRank")
         lg.pagerank(h, 0.85, args.pr_iters)
-    else:
+    elif args.counter_run == "bfs":
         for mode in args.bfs_modes.split(","):
             log(f"[counter-run] BFS {mode} from root {roots[0]}")
             lg.bfs(h, [roots[0]], mode=mode)
+    else:
+        log(f"[counter-run] BFS from all {len(roots)} roots in one call")
+        lg.bfs(h, roots)
     torch.cuda.synchronize()
     struct = (info["adj_bits"] / 8.0 + info["bytes_offsets"] + info["bytes_widths"]) if args.layout == "packed" \
         else (info["bytes_adj"] + info["bytes_offsets"])
     print(json.dumps({"mode": "counter-run", "phase": args.counter_run, "layout": args.layout,
                       "workload": args.workload, "calibration_bytes": nbytes, "pr_iters": args.pr_iters,
-                      "bfs_modes": args.bfs_modes,
+                      "bfs_modes": args.bfs_modes, "roots": len(roots),
                       "n": g.n, "stored_edges": g.m, "structure_bytes": struct,
                       "pr_algorithmic_bytes_per_iteration": struct + 4.0 * g.m + 4.0 * g.n,
                       "source_sha256": source_hash(args.counter_run)}), flush=True)
