@@ -1823,17 +1823,22 @@ __global__ void ms_bits_kernel(uint32_t n, const unsigned long long *__restrict_
 }
 
 // Top-down marking over the frontier's edges, tiled as td_expand_kernel
-// tiles them: nx[v] |= fr[u] & ~vis[v] for every frontier edge (u, v).
-template <class Acc>
+// tiles them: nx[v] |= fr[u] & ~vis[v] for every frontier edge (u, v), and
+// for each bit b so set parent[b][v] = min(parent[b][v], u).  The rows hold
+// -1 (the largest value unsigned) where no parent is set yet, so the row
+// ends with the smallest frontier neighbour: the first in v's sorted list,
+// the parent a search from root b alone takes.
+template <class Acc, bool kParent>
 __global__ __launch_bounds__(kTdThreads) void ms_mark_kernel(
     Acc acc, const uint32_t *__restrict__ queue, uint32_t qsize, const uint64_t *__restrict__ fstart,
     const uint32_t *__restrict__ fw, const uint64_t *__restrict__ fscan, uint64_t edges,
     const unsigned long long *__restrict__ fr, const unsigned long long *__restrict__ vis,
-    unsigned long long *__restrict__ nx) {
+    unsigned long long *__restrict__ nx, uint64_t n, uint32_t *__restrict__ parent) {
     __shared__ uint64_t s_scan[kTdTile + 1];
     __shared__ uint64_t s_start[kTdTile];
     __shared__ uint32_t s_w[kTdTile];
     __shared__ unsigned long long s_fr[kTdTile];
+    __shared__ uint32_t s_q[kParent ? kTdTile : 1];
     __shared__ uint32_t s_range[2];
     for (uint64_t t = blockIdx.x; t * kTdTile < edges; t += gridDim.x) {
         const uint64_t e0 = t * kTdTile;
@@ -1849,7 +1854,9 @@ __global__ __launch_bounds__(kTdThreads) void ms_mark_kernel(
                 s_scan[j] = fscan[i0 + j];
                 s_start[j] = fstart[i0 + j];
                 s_w[j] = fw[i0 + j];
-                s_fr[j] = fr[queue[i0 + j]];
+                const uint32_t q = queue[i0 + j];
+                s_fr[j] = fr[q];
+                if constexpr (kParent) s_q[j] = q;
             }
         }
         __syncthreads();
@@ -1857,7 +1864,7 @@ __global__ __launch_bounds__(kTdThreads) void ms_mark_kernel(
         // thread's edges are in flight together (idle slots: position 0 with
         // mask 0, an empty frontier mask)
         uint64_t epos[kTdEdgesPerThread];
-        uint32_t msk[kTdEdgesPerThread];
+        uint32_t msk[kTdEdgesPerThread], src[kTdEdgesPerThread];
         unsigned long long fm[kTdEdgesPerThread];
 #pragma unroll
         for (int r = 0; r < kTdEdgesPerThread; ++r) {
@@ -1865,20 +1872,24 @@ __global__ __launch_bounds__(kTdThreads) void ms_mark_kernel(
             epos[r] = 0;
             msk[r] = 0;
             fm[r] = 0ull;
+            src[r] = 0;
             if (e < e1) {
                 uint64_t base_e, start;
-                uint32_t w;
+                uint32_t w, q = 0;
                 unsigned long long f;
                 if (staged) {
                     const uint32_t j = last_le(s_scan, 0, span - 1, e);
                     base_e = s_scan[j]; start = s_start[j]; w = s_w[j]; f = s_fr[j];
+                    if constexpr (kParent) q = s_q[j];
                 } else {
                     const uint32_t j = last_le(fscan, i0, s_range[1], e);
-                    base_e = fscan[j]; start = fstart[j]; w = fw[j]; f = fr[queue[j]];
+                    q = queue[j];
+                    base_e = fscan[j]; start = fstart[j]; w = fw[j]; f = fr[q];
                 }
                 epos[r] = start + (e - base_e) * Acc::step(w);
                 msk[r] = Acc::mask(w);
                 fm[r] = f;
+                src[r] = q;
             }
         }
         uint32_t u[kTdEdgesPerThread];
@@ -1890,18 +1901,25 @@ __global__ __launch_bounds__(kTdThreads) void ms_mark_kernel(
 #pragma unroll
         for (int r = 0; r < kTdEdgesPerThread; ++r) {
             const unsigned long long add = fm[r] & ~vw[r];
-            if (add) atomicOr(&nx[u[r]], add);
+            if (add) {
+                atomicOr(&nx[u[r]], add);
+                if constexpr (kParent) {
+                    for (unsigned long long h = add; h; h &= h - 1)
+                        atomicMin(&parent[(uint64_t)(__ffsll((long long)h) - 1) * n + u[r]], src[r]);
+                }
+            }
         }
         __syncthreads();  // the next tile rewrites the staged ranges
     }
 }
 
-// One level's parents and depths, a lane per vertex over 64-vertex words.
-// Open bits P: the candidates nx[v] (top-down) or every unreached bit of a
-// search still running (bottom-up).  The lane reads its list in order, four
-// entries per step, until every open bit is found (top-down: each has a
-// frontier neighbor) or kMsLaneLimit entries; a longer list goes to
-// ms_pending_kernel with the bits still open.  A lane keeps, per root, the
+// One level's depths (and, bottom-up, parents), a lane per vertex over
+// 64-vertex words.  Top-down, the candidates nx[v] are the level's new bits
+// (their parents came with the marking).  Bottom-up, the open bits P are
+// every unreached bit of a search still running: the lane reads its list in
+// order, four entries per step, until every open bit is found or
+// kMsLaneLimit entries; a longer list goes to ms_pending_kernel with the
+// bits still open.  A lane keeps, per root, the
 // list position of the parent (one byte: positions stay under kMsLaneLimit)
 // in LDS until its vertex is done; rows are then written four roots at a
 // time, so that the lanes of a wave write one row's consecutive entries
@@ -1942,11 +1960,11 @@ __global__ __launch_bounds__(kMsThreads, MsWavesPerEU<Acc>::value) void ms_resol
             if (lane == 0) bits[q] = 0ull;
             continue;
         }
-        const VInfo vi = wave_info(acc, q * 64, n);
-        unsigned long long found = 0ull;
+        unsigned long long found = kTD ? P : 0ull;
         bool pending = false;
+        const VInfo vi = kTD ? VInfo{0, 0, 0} : wave_info(acc, q * 64, n);
         const uint32_t st = Acc::step(vi.w), mk = Acc::mask(vi.w);
-        if (P && vi.deg) {
+        if (!kTD && P && vi.deg) {
             const uint32_t lim = vi.deg < kMsLaneLimit ? vi.deg : kMsLaneLimit;
             for (uint32_t i = 0; i < lim && found != P; i += 4) {
                 // four list loads, then four mask loads (entries past the
@@ -1986,7 +2004,7 @@ __global__ __launch_bounds__(kMsThreads, MsWavesPerEU<Acc>::value) void ms_resol
 #pragma unroll
             for (int k = 0; k < 4; ++k) has[k] = rr[k] < kMsRoots && ((found >> rr[k]) & 1ull);
             uint32_t pu[4];
-            if constexpr (kParent) {
+            if constexpr (kParent && !kTD) {
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {
                     const uint64_t pos = has[k] ? vi.start + (uint64_t)par[rr[k]] * st : 0ull;
@@ -1997,7 +2015,7 @@ __global__ __launch_bounds__(kMsThreads, MsWavesPerEU<Acc>::value) void ms_resol
             for (int k = 0; k < 4; ++k) {
                 if (has[k]) {
                     depth[(uint64_t)rr[k] * n + v] = next_depth;
-                    if constexpr (kParent) parent[(uint64_t)rr[k] * n + v] = (int32_t)pu[k];
+                    if constexpr (kParent && !kTD) parent[(uint64_t)rr[k] * n + v] = (int32_t)pu[k];
                 }
             }
         }
@@ -2038,7 +2056,7 @@ __global__ __launch_bounds__(kMsThreads, MsWavesPerEU<Acc>::value) void ms_resol
 // The long lists left by ms_resolve_kernel: a wave per vertex reads the rest
 // of the list 64 entries per step; for each open bit the first lane holding
 // it gives the parent.
-template <class Acc, bool kParent, bool kTD>
+template <class Acc, bool kParent>
 __global__ void ms_pending_kernel(Acc acc, uint32_t n, int32_t next_depth, const unsigned long long *__restrict__ fr,
                                   unsigned long long *__restrict__ vis, unsigned long long *__restrict__ nx,
                                   int32_t *__restrict__ depth, int32_t *__restrict__ parent,
@@ -2075,10 +2093,8 @@ __global__ void ms_pending_kernel(Acc acc, uint32_t n, int32_t next_depth, const
             got |= uni;
         }
         if (lane == 0 && got) {
-            if constexpr (!kTD) {
-                atomicOr(&nx[v], got);
-                atomicOr(&vis[v], got);
-            }
+            atomicOr(&nx[v], got);
+            atomicOr(&vis[v], got);
         }
         act |= got;
     }
@@ -2126,6 +2142,8 @@ static lg_status bfs_ms_batch(lg_graph *g, BfsWork &w, MsWork &ms, Acc acc, cons
     LG_TRY(fill_u64((uint64_t *)vis, 0, n, s));
     LG_TRY(fill_u64((uint64_t *)fr, 0, n, s));
     LG_TRY(fill_u64((uint64_t *)ctr, 0, 8, s));
+    // top-down levels take parents by atomic minimum over rows that start at -1
+    if (parent) LG_TRY(fill_u32(reinterpret_cast<uint32_t *>(parent), 0xFFFFFFFFu, (uint64_t)r * n, s));
     LG_CHECK_HIP(hipMemcpyAsync(ms.roots.p, roots, (uint64_t)r * 4, hipMemcpyHostToDevice, s));
     LG_LAUNCH(ms_roots_kernel, 1, kMsRoots, 0, s, r, ms.roots.as<uint32_t>(), rel ? g->inv.as<uint32_t>() : nullptr,
               (uint64_t)n, vis, fr, depth, parent);
@@ -2147,9 +2165,13 @@ static lg_status bfs_ms_batch(lg_graph *g, BfsWork &w, MsWork &ms, Acc acc, cons
     const bool skewed = (uint64_t)g->n_heavy * 256 > n;
     const uint32_t rgrid = grid_for(words * kWave, kMsThreads, skewed ? kStrideBlocks : (uint32_t)std::max(1, 2 * cus));
     for (int32_t level = 0; fsize && active && (max_depth < 0 || level < max_depth); ++level) {
-        // top-down while the frontier's edges are under an eighth of the
-        // graph's (a bottom-up level reads every open vertex's list)
-        bool td = fsize <= (uint64_t)n / 32;
+        // top-down while the frontier's edges are under a third of the
+        // graph's: a top-down edge costs a mask read and one or two atomics,
+        // a bottom-up level reads every open vertex's list until its open
+        // bits are found, in the early levels the whole list (measured at
+        // Erdos-Renyi scale 26: the level with 3% of the edges on the
+        // frontier 45 ms bottom-up, a few ms top-down)
+        bool td = fsize <= (uint64_t)n / 4;
         uint64_t fedges = 0;
         if (td) {
             LG_LAUNCH(td_prepare_kernel<Acc>, grid_for(fsize, 256, 1u << 16), 256, 0, s, acc, queue, (uint32_t)fsize,
@@ -2159,16 +2181,22 @@ static lg_status bfs_ms_batch(lg_graph *g, BfsWork &w, MsWork &ms, Acc acc, cons
             LG_CHECK_HIP(hipMemcpyAsync(w.host, w.fscan.as<uint64_t>() + fsize, 8, hipMemcpyDeviceToHost, s));
             LG_CHECK_HIP(hipStreamSynchronize(s));
             fedges = w.host[0];
-            td = fedges * 8 < g->m;
+            td = fedges * 3 < g->m;
         }
         LG_TRY(fill_u64((uint64_t *)ctr, 0, 8, s));  // [0] queue, [2] running searches, [3] pending
         if (td) {
             LG_TRY(fill_u64((uint64_t *)nx, 0, n, s));
             if (fedges) {
-                LG_LAUNCH(ms_mark_kernel<Acc>, grid_for(fedges, kTdTile, 1u << 20), kTdThreads, 0, s, acc, queue,
-                          (uint32_t)fsize, w.fstart.as<uint64_t>(), w.fw.as<uint32_t>(), w.fscan.as<uint64_t>(),
-                          fedges, (const unsigned long long *)fr, (const unsigned long long *)vis, nx);
-                LG_CHECK_LAUNCH();
+                auto mark = [&](auto kpar) -> lg_status {
+                    LG_LAUNCH((ms_mark_kernel<Acc, decltype(kpar)::value>), grid_for(fedges, kTdTile, 1u << 20),
+                              kTdThreads, 0, s, acc, queue, (uint32_t)fsize, w.fstart.as<uint64_t>(),
+                              w.fw.as<uint32_t>(), w.fscan.as<uint64_t>(), fedges, (const unsigned long long *)fr,
+                              (const unsigned long long *)vis, nx, (uint64_t)n, reinterpret_cast<uint32_t *>(parent));
+                    LG_CHECK_LAUNCH();
+                    return LG_OK;
+                };
+                if (parent) LG_TRY(mark(std::true_type{}));
+                else LG_TRY(mark(std::false_type{}));
             }
         }
         auto resolve = [&](auto kpar, auto ktd) -> lg_status {
@@ -2177,10 +2205,12 @@ static lg_status bfs_ms_batch(lg_graph *g, BfsWork &w, MsWork &ms, Acc acc, cons
                       (const unsigned long long *)fr, vis, nx, depth, parent, bits, ms.pend_v.as<uint32_t>(),
                       ms.pend_m.as<unsigned long long>(), ctr);
             LG_CHECK_LAUNCH();
-            LG_LAUNCH((ms_pending_kernel<Acc, P, T>), kStrideBlocks, 256, 0, s, acc, n, level + 1,
-                      (const unsigned long long *)fr, vis, nx, depth, parent, (const uint32_t *)ms.pend_v.p,
-                      (const unsigned long long *)ms.pend_m.p, ctr);
-            LG_CHECK_LAUNCH();
+            if constexpr (!T) {  // only bottom-up levels leave long lists
+                LG_LAUNCH((ms_pending_kernel<Acc, P>), kStrideBlocks, 256, 0, s, acc, n, level + 1,
+                          (const unsigned long long *)fr, vis, nx, depth, parent, (const uint32_t *)ms.pend_v.p,
+                          (const unsigned long long *)ms.pend_m.p, ctr);
+                LG_CHECK_LAUNCH();
+            }
             return LG_OK;
         };
         if (parent) {
