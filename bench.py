@@ -645,8 +645,7 @@ def main():
     roof = dict(rooflines["packed"])
     roof["dominant_kernel"] = dominant
     roof["dominant_by"] = ("wall-time share: the PageRank iteration kernels' time per step vs the BFS and encode "
-                           "phases' wall times, which bound every kernel inside them (BFS kernels overlap on eight "
-                           "lanes)")
+                           "phases' wall times, which bound every kernel inside them")
     ratio = None
     if "plain" in summ:
         Q = summ["plain"]
