@@ -215,13 +215,21 @@ lg_status lg_decode_neighbors_noalloc(const lg_graph *g, const uint32_t *vertice
  *              unreached vertices
  *   max_depth  -1 for a full traversal; k >= 0 stops after depth k (k-hop)
  * Results are independent of the flags and of the direction switching.
- * With r > 1 the roots run a few at a time, each on its own internal stream
- * with its own workspace; work queued on `stream` before the call completes
- * first, and work queued on `stream` after it waits for every root.  The
- * call returns once every root has been enqueued; each row equals the result
- * of a call with that root alone.  Those streams and workspaces belong to the
- * device, not to the graph: they grow to the largest graph searched and stay
- * until lg_trim; multi-root calls on one device run one after the other.
+ * With r > 1 every row equals the result of a call with that root alone;
+ * work queued on `stream` before the call completes first, and work queued
+ * on `stream` after it waits for every root.  Two ways of running them:
+ *   - with LG_BFS_DIRECTION_OPT on a graph whose lists are not gap or Varint
+ *     coded, not weighted and without bvIL offsets, the first roots go in
+ *     batches of up to 64 while at least 16 are left, each batch one
+ *     multi-source traversal on `stream` (64-bit visit and frontier masks
+ *     per vertex, 36 bytes per vertex of device workspace); the host reads
+ *     a few counters per level, so the call returns when these batches are
+ *     done;
+ *   - the other roots run a few at a time, each on its own internal stream
+ *     with its own workspace; the call returns once each is enqueued.
+ * These streams and workspaces belong to the device, not to the graph: they
+ * grow to the largest graph searched and stay until lg_trim; multi-root
+ * calls on one device run one after the other.
  */
 lg_status lg_bfs(const lg_graph *g, const uint32_t *roots, uint32_t r, int32_t *depth,
                  int32_t *parent, int32_t max_depth, uint32_t flags, hipStream_t stream);

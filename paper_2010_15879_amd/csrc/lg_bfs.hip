@@ -2345,11 +2345,12 @@ static lg_status bfs_run_lanes(lg_graph *g, const uint32_t *roots, uint32_t r, i
 // Several roots of a direction-optimizing search on a graph whose lists are
 // not read in order only: the multi-source traversal, in batches of up to
 // 64 roots while at least kMsMinRoots are left (fewer go to the lanes: a
-// multi-source level reads whole lists for every search still open, which
-// the one-root searches beat below about 32 roots on the graphs measured).
+// bottom-up multi-source level reads whole lists for every search still
+// open, which the one-root searches beat below about 16 roots on the graphs
+// measured).
 // It runs on `stream` and holds the device's BFS pool (its lane 0
 // workspace, the multi-source masks) for its duration.
-constexpr uint32_t kMsMinRoots = 32;
+constexpr uint32_t kMsMinRoots = 16;
 
 static bool bfs_ms_graph(const lg_graph *g, uint32_t flags) {
     if (flags != LG_BFS_DIRECTION_OPT) return false;

@@ -1,4 +1,4 @@
-"""lg_bfs with many roots runs batches of at least 32 of them as one
+"""lg_bfs with many roots runs batches of at least 16 of them as one
 multi-source traversal and the rest a few at a time on internal streams:
 every row must equal the result of a call with that root alone, whichever
 path took it, and work on the caller's stream must be ordered around the
@@ -70,4 +70,34 @@ def test_stream_order_around_the_call(lgmod, count):
         total = depth.sum()       # queued after: must see the finished rows
         assert torch.equal(depth, ref)
         assert int(total) == int(ref.sum())
+    h.free()
+
+
+@pytest.mark.parametrize("graph", ["kron12", "er12"])
+@pytest.mark.parametrize("kw", [dict(), dict(ids="local", offsets="succinct", relabel=True),
+                                dict(layout="plain")])
+def test_repeated_and_edgeless_roots_over_two_batches(lgmod, graph, kw):
+    """About 100 roots (two multi-source batches back to back, sharing the
+    masks), with a root given three times and edgeless roots among them:
+    every row equals the call with that root alone, and an edgeless root's
+    row holds only itself."""
+    g = gg.kronecker(12, 8, seed=7, device="cuda") if graph == "kron12" else \
+        gg.erdos_renyi(12, 2, seed=7, device="cuda")
+    iso = torch.nonzero(g.degrees() == 0).flatten()[:3].tolist()
+    assert len(iso) == 3
+    base = gg.pick_roots(g, 95, seed=4)
+    roots = base[:30] + [base[3], base[3]] + iso + base[30:]
+    assert len(roots) > 64 + 32
+    h = lgmod.encode(g.row_offsets, g.col, g.n, **kw)
+    d_all, p_all = lgmod.bfs(h, roots)
+    for i, r in enumerate(roots):
+        d1, p1 = lgmod.bfs(h, [r])
+        assert torch.equal(d_all[i], d1[0]) and torch.equal(p_all[i], p1[0]), (i, r)
+    for r in iso:
+        i = roots.index(r)
+        want_d = torch.full((g.n,), -1, dtype=torch.int32, device="cuda")
+        want_d[r] = 0
+        want_p = want_d.clone()
+        want_p[r] = r
+        assert torch.equal(d_all[i], want_d) and torch.equal(p_all[i], want_p), r
     h.free()
