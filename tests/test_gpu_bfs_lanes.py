@@ -101,3 +101,28 @@ def test_repeated_and_edgeless_roots_over_two_batches(lgmod, graph, kw):
         want_p[r] = r
         assert torch.equal(d_all[i], want_d) and torch.equal(p_all[i], want_p), r
     h.free()
+
+
+@pytest.mark.parametrize("n,p", [(1000, 0.012), (777, 0.004), (65, 0.2)])
+@pytest.mark.parametrize("kw", [dict(), dict(ids="local", offsets="succinct", relabel=True),
+                                dict(layout="plain", relabel=True)])
+def test_ragged_vertex_counts(lgmod, n, p, kw):
+    """Vertex counts that end inside a 64-vertex word (the multi-source sweeps'
+    last word is partial), sparse enough to leave some vertices unreached:
+    16 and 40 roots against one-root calls, and oracle rows."""
+    g = gg.random_graph(n, p, seed=n, device="cuda")
+    h = lgmod.encode(g.row_offsets, g.col, g.n, **kw)
+    off, col = g.numpy()
+    for count in (16, 40):
+        roots = gg.pick_roots(g, count, seed=3)
+        roots = (roots * ((count + len(roots) - 1) // len(roots)))[:count]  # repeats when few vertices have edges
+        d_all, p_all = lgmod.bfs(h, roots)
+        for i, r in enumerate(roots):
+            d1, p1 = lgmod.bfs(h, [r])
+            assert torch.equal(d_all[i], d1[0]) and torch.equal(p_all[i], p1[0]), (count, i, r)
+        for i in (0, count - 1):
+            d0, p0 = orc.bfs(off.astype(np.uint64), col.view(np.uint32), roots[i],
+                             relabeled=bool(kw.get("relabel")))
+            np.testing.assert_array_equal(d_all[i].cpu().numpy(), d0)
+            np.testing.assert_array_equal(p_all[i].cpu().numpy(), p0)
+    h.free()
