@@ -37,13 +37,20 @@ namespace lg {
 
 constexpr uint32_t kPbThreads = 1024;
 constexpr uint32_t kPbWaves = kPbThreads / kWave;     // 16
-constexpr uint32_t kPbSteps = 8;                       // level 2: entries per thread per round
-constexpr uint32_t kPbRound = kPbThreads * kPbSteps;   // level 2: entries per round, 8,192
 // level 1: 64-entry steps per wave per round, 4,096 entries per round, so
 // that its LDS (about 60 KB) lets two workgroups share a compute unit
 constexpr uint32_t kPb1Steps = 4;
 constexpr uint32_t kPb1Round = kPbThreads * kPb1Steps;
 constexpr uint32_t kPb1PerCU = 2;
+// level 1's grid: 16 workgroups per CU, two resident at a time.  Smaller
+// entry ranges even out the workgroups' ends (windows cost more where rows
+// are short); level 2 then takes kPb2Merge neighbouring level-1 regions per
+// workgroup, so that its regions stay about two rounds long.  Measured at
+// Erdos-Renyi scale 26 against one range per resident workgroup and one
+// region per level-2 workgroup: 16.5 -> 15.4 ms per iteration (mean of
+// three alternating runs, both layouts; the results are bit-identical)
+constexpr uint32_t kPb1Grid = 16;
+constexpr uint32_t kPb2Merge = 4;
 constexpr uint32_t kFineShift = 14;                    // fine bin: 16,384 vertices
 constexpr uint32_t kFine = 1u << kFineShift;
 constexpr uint32_t kSubBins = 64;                      // fine bins per coarse bin
@@ -459,7 +466,11 @@ __global__ __launch_bounds__(kPbThreads, kPb1WavesPerEU) void pb_bin1_kernel(
 }
 
 // ---------------------------------------------------------------------------
-// level 2: one workgroup per level-1 region (w, c), 64 fine bins
+// level 2: one workgroup per kPb2Merge neighbouring level-1 regions
+// (w .. w + kPb2Merge - 1, c), 64 fine bins.  Those regions are one range of
+// the level-1 buffer (regions are placed coarse-major) and their chunks of
+// every fine bin one range of the level-2 arrays (placed fine-major), so
+// the workgroup streams them as one region.
 // ---------------------------------------------------------------------------
 
 static_assert(kSubBins == kWave, "level 2 scans its fine bins with one wave");
@@ -476,16 +487,19 @@ __global__ __launch_bounds__(kPb2Threads, kPb2WavesPerEU) void pb_bin2_kernel(co
                                                                              const uint64_t *__restrict__ base2,
                                                                              uint16_t *__restrict__ loc2,
                                                                              float *__restrict__ val2,
-                                                                             uint64_t sink) {
+                                                                             uint64_t sink, uint32_t nwg,
+                                                                             uint32_t nc) {
     __shared__ uint2 s_buf[kPb2Round];  // entries sorted by fine bin (bits 14..19 of the local vertex)
     __shared__ uint32_t s_hist[2][kSubBins];
     __shared__ uint32_t s_start[kSubBins];
     __shared__ uint64_t s_cur[kSubBins];
     const uint32_t lane = lane_id();
     const uint32_t wv = threadIdx.x / kWave;
-    const uint64_t r = blockIdx.x;
+    const uint32_t w0 = blockIdx.x / nc * kPb2Merge, c = blockIdx.x % nc;
+    const uint64_t r = (uint64_t)w0 * nc + c;  // the first of the merged regions
     const uint64_t b0 = base1[r];
-    const uint32_t len = len1[r];
+    uint32_t len = 0;
+    for (uint32_t k = 0; k < kPb2Merge && w0 + k < nwg; ++k) len += len1[r + (uint64_t)k * nc];
     if (threadIdx.x < kSubBins) {
         s_hist[0][threadIdx.x] = s_hist[1][threadIdx.x] = 0;
         s_cur[threadIdx.x] = base2[r * kSubBins + threadIdx.x];
@@ -673,7 +687,7 @@ static lg_status pb_build(lg_graph *g, Acc acc, hipStream_t s) {
     const uint32_t n = g->n;
     int cus = 0;
     LG_CHECK_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, g->device));
-    W.nwg = (uint32_t)std::max(1, cus) * kPb1PerCU;
+    W.nwg = (uint32_t)std::max(1, cus) * kPb1Grid;
     W.nf = (uint32_t)(((uint64_t)n + kFine - 1) >> kFineShift);
     W.nc = (W.nf + kSubBins - 1) / kSubBins;
     // first row of every level-1 workgroup's entry range, from the element
@@ -772,9 +786,10 @@ lg_status pagerank_pb(lg_graph *g, float damping, uint32_t iters, float *scores,
                           (const float *)cin, W.row_lo.as<uint32_t>(), W.k_lo.as<uint32_t>(), W.nc,
                           W.base1.as<uint64_t>(), W.buf1.as<uint2>(), W.nf, (uint32_t *)nullptr);
                 LG_CHECK_LAUNCH();
-                LG_LAUNCH(pb_bin2_kernel, W.nwg * W.nc, kPb2Threads, 0, s, (const uint2 *)W.buf1.p,
-                          W.base1.as<uint64_t>(), W.len1.as<uint32_t>(), W.base2.as<uint64_t>(),
-                          W.buf2.as<uint16_t>(), (float *)((char *)W.buf2.p + W.val_off), g->m);
+                LG_LAUNCH(pb_bin2_kernel, (W.nwg + kPb2Merge - 1) / kPb2Merge * W.nc, kPb2Threads, 0, s,
+                          (const uint2 *)W.buf1.p, W.base1.as<uint64_t>(), W.len1.as<uint32_t>(),
+                          W.base2.as<uint64_t>(), W.buf2.as<uint16_t>(), (float *)((char *)W.buf2.p + W.val_off),
+                          g->m, W.nwg, W.nc);
                 LG_CHECK_LAUNCH();
             }
             LG_LAUNCH(pb_accum_kernel<Acc>, W.nf, kPbThreads, 0, s, acc, n, W.fstart.as<uint64_t>(),
