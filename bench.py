@@ -191,9 +191,11 @@ def counter_summary_main(args):
                   "bfs": f"single-root BFS, modes {run.get('bfs_modes')}",
                   "bfsall": f"BFS from all {run.get('roots')} roots in one call (the call the benchmark times)"}[
                       run["phase"]]
+    # the passes' directory as given, relative to the repository root
+    cdir = os.path.relpath(os.path.abspath(args.counter_summary), ROOT)
     cmd_of = lambda pas: (f"timeout -s KILL 300 rocprofv3 --pmc {' '.join(COUNTER_PASSES[pas])} "  # noqa: E731
                           f"--kernel-include-regex \"{COUNTER_KERNEL_REGEX}\" --output-format csv "
-                          f"-d gpurun_out/cnt/{args.workload}_{args.layout}_{run['phase']}/{pas} -o {pas} -- "
+                          f"-d {cdir}/{pas} -o {pas} -- "
                           f"python3 bench.py --workload {args.workload} --counter-run {run['phase']} "
                           f"--layout {args.layout} --pr-iters {run['pr_iters']} --bfs-modes {run.get('bfs_modes')}")
     out = []
@@ -206,10 +208,9 @@ def counter_summary_main(args):
     for pas in COUNTER_PASSES:
         out.append(cmd_of(pas))
     out.append(f"python3 bench.py --workload {args.workload} --counter-run {run['phase']} --layout {args.layout} "
-               f"--pr-iters {run['pr_iters']} --bfs-modes {run.get('bfs_modes')} > gpurun_out/cnt/"
-               f"{args.workload}_{args.layout}_{run['phase']}/run.json")
+               f"--pr-iters {run['pr_iters']} --bfs-modes {run.get('bfs_modes')} > {cdir}/run.json")
     out.append(f"python3 bench.py --workload {args.workload} --layout {args.layout} --counter-summary "
-               f"gpurun_out/cnt/{args.workload}_{args.layout}_{run['phase']} --summary-out "
+               f"{cdir} --summary-out "
                f"profiles/counters_{args.workload}_{args.layout}_{run['phase']}.md")
     out.append("```")
     out.append("")
