@@ -53,3 +53,32 @@ def test_pagerank_pb_parity(lgmod, graph, kw):
     z = lgmod.pagerank(h, 0.85, 0).cpu().numpy()
     np.testing.assert_allclose(z, 1.0 / g.n, rtol=0, atol=0)
     h.free()
+
+
+@pytest.mark.parametrize("edges", ["none", "sparse"])
+def test_pagerank_pb_nearly_empty(lgmod, edges):
+    """2^22 vertices with no edges, or a few thousand edges and one hub: most
+    level-1 workgroups get no entries (or none at all), and the scores still
+    match the oracle."""
+    n = 1 << 22
+    if edges == "none":
+        g = gg.csr_from_edges(n, [], device="cuda")
+    else:
+        rng = np.random.default_rng(5)
+        src = rng.integers(0, n, 3000)
+        dst = rng.integers(0, n, 3000)
+        hub = np.full(2000, 12345)
+        leaves = rng.integers(0, n, 2000)
+        s = torch.from_numpy(np.concatenate([src, hub])).cuda()
+        d = torch.from_numpy(np.concatenate([dst, leaves])).cuda()
+        g = gg.canonical_csr(n, s, d)
+    off, col = g.numpy()
+    off, col = off.astype(np.uint64), col.view(np.uint32)
+    for kw in (dict(ids="global", offsets="packed"), dict(layout="plain")):
+        print(f"[pb] nearly empty ({edges}, m={g.m}) {kw}", flush=True)
+        h = lgmod.encode(g.row_offsets, g.col, g.n, **kw)
+        for t in (1, 20):
+            pr = lgmod.pagerank(h, 0.85, t).cpu().numpy().astype(np.float64)
+            l1 = float(np.abs(pr - orc.pagerank_par(off, col, 0.85, t)).sum())
+            assert l1 <= 1e-5, (edges, kw, t, l1)
+        h.free()
