@@ -1779,12 +1779,13 @@ lg_status bfs_run(lg_graph *g, BfsWork &w, const uint32_t *roots, uint32_t r, in
 // traversal.  Every vertex holds 64-bit masks, bit i for root i: vis (the
 // searches that reached it), fr (those with it in this level's frontier),
 // nx (the next level's).  A level either marks candidates top-down (every
-// frontier edge (u, v) ORs fr[u] & ~vis[v] into nx[v]) and then finds their
-// parents, or finds the next frontier bottom-up over every vertex with open
-// bits.  Either way a vertex reads its list in order and takes, for each
-// bit, the first neighbor whose frontier mask holds it: the neighbor one
-// level up with the smallest label, so every row equals the search from its
-// root alone.  Each list is read once per level for all roots.
+// frontier edge (u, v) ORs fr[u] & ~vis[v] into nx[v] and offers u as the
+// parent of each bit so set, the smallest offer winning), or finds the next
+// frontier bottom-up over every vertex with open bits, reading its list in
+// order and taking for each bit the first neighbor whose frontier mask
+// holds it.  Either way the parent is the neighbor one level up with the
+// smallest label, so every row equals the search from its root alone.  A
+// bottom-up level reads each open vertex's list once for all roots.
 // ---------------------------------------------------------------------------
 
 constexpr uint32_t kMsRoots = 64;
@@ -1924,8 +1925,9 @@ __global__ __launch_bounds__(kTdThreads) void ms_mark_kernel(
 // in LDS until its vertex is done; rows are then written four roots at a
 // time, so that the lanes of a wave write one row's consecutive entries
 // together and the parents' list reads are in flight together.  The byte
-// stage and the register bound let eight waves share a SIMD: the list and
-// mask reads are dependent random loads, so the kernel lives on occupancy.
+// stage and the register bound let eight waves share a SIMD, which skewed
+// graphs need to hide lanes waiting on long lists (the host caps the grid
+// on even-degree graphs, where more waves only evict the lanes' list lines).
 constexpr uint32_t kMsParStride = kMsRoots + 4;  // bytes per lane: 17 words, so lanes fall on distinct banks
 static_assert(kMsLaneLimit <= 256, "a parent's list position is kept in one byte");
 
@@ -2169,8 +2171,8 @@ static lg_status bfs_ms_batch(lg_graph *g, BfsWork &w, MsWork &ms, Acc acc, cons
         // graph's: a top-down edge costs a mask read and one or two atomics,
         // a bottom-up level reads every open vertex's list until its open
         // bits are found, in the early levels the whole list (measured at
-        // Erdos-Renyi scale 26: the level with 3% of the edges on the
-        // frontier 45 ms bottom-up, a few ms top-down)
+        // Erdos-Renyi scale 26, 64 roots: the level with 3% of the edges on
+        // the frontier took 45 ms bottom-up, 10 ms top-down)
         bool td = fsize <= (uint64_t)n / 4;
         uint64_t fedges = 0;
         if (td) {
