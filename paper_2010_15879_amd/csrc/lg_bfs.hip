@@ -2394,14 +2394,18 @@ static lg_status bfs_run_ms(lg_graph *g, const uint32_t *roots, uint32_t r, int3
     LG_TRY(ms.pend_m.ensure(n * 8));
     LG_TRY(ms.roots.ensure(kMsRoots * 4));
     // lane 0's stream is not used: everything runs on the caller's stream
-    return dispatch_acc(g, [&](auto acc) -> lg_status {
+    LG_TRY(dispatch_acc(g, [&](auto acc) -> lg_status {
         for (uint32_t b0 = 0; b0 < r; b0 += kMsRoots) {
             const uint32_t rb = std::min<uint32_t>(kMsRoots, r - b0);
             LG_TRY(bfs_ms_batch(g, w, ms, acc, roots + b0, rb, depth + (uint64_t)b0 * n,
                                 parent ? parent + (uint64_t)b0 * n : nullptr, max_depth, stream));
         }
         return LG_OK;  // batches follow each other on the caller's stream (shared masks and roots buffer)
-    });
+    }));
+    // the last batch's finishing kernels still read the masks: another call
+    // may take them (on another stream) once the device lock is released
+    LG_CHECK_HIP(hipStreamSynchronize(stream));
+    return LG_OK;
 }
 
 }  // namespace lg

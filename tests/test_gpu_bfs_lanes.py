@@ -126,3 +126,40 @@ def test_ragged_vertex_counts(lgmod, n, p, kw):
             np.testing.assert_array_equal(d_all[i].cpu().numpy(), d0)
             np.testing.assert_array_equal(p_all[i].cpu().numpy(), p0)
     h.free()
+
+
+def test_multi_root_calls_from_two_threads(lgmod):
+    """Two threads, each with its own stream, run 40-root calls (multi-source
+    batches sharing the device's masks) on two graphs at once: every result
+    equals the same call made alone."""
+    import threading
+    graphs = [gg.kronecker(13, 16, seed=11, device="cuda"), gg.erdos_renyi(13, 8, seed=12, device="cuda")]
+    hs = [lgmod.encode(g.row_offsets, g.col, g.n) for g in graphs]
+    roots = [gg.pick_roots(g, 40, seed=5) for g in graphs]
+    ref = [lgmod.bfs(h, r) for h, r in zip(hs, roots)]
+    torch.cuda.synchronize()
+    out = [[None] * 6, [None] * 6]
+    errors = []
+
+    def work(i):
+        try:
+            s = torch.cuda.Stream()
+            for k in range(6):
+                with torch.cuda.stream(s):
+                    d, p = lgmod.bfs(hs[i], roots[i], stream=s)
+                s.synchronize()
+                out[i][k] = (d, p)
+        except Exception as e:  # surfaced below
+            errors.append(e)
+
+    th = [threading.Thread(target=work, args=(i,)) for i in range(2)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    assert not errors, errors
+    for i in range(2):
+        for d, p in out[i]:
+            assert torch.equal(d, ref[i][0]) and torch.equal(p, ref[i][1]), i
+    for h in hs:
+        h.free()
