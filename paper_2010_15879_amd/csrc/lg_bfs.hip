@@ -2384,6 +2384,9 @@ static lg_status bfs_run_ms(lg_graph *g, const uint32_t *roots, uint32_t r, int3
     BfsPool &p = **slot;
     BfsWork &w = p.lanes[0]->work;
     MsWork &ms = p.ms;
+    // lane 0's workspace may still be in use by an earlier lanes call's
+    // kernels on lane 0's stream (its event marks their end)
+    LG_CHECK_HIP(hipStreamWaitEvent(stream, p.lanes[0]->done, 0));
     const uint64_t n = g->n, words = (n + 63) / 64;
     LG_TRY(bfs_workspace_ensure(w, n, g->n_heavy, g->relabel != LG_RELABEL_NONE, parent != nullptr));
     LG_TRY(ms.vis.ensure(n * 8));

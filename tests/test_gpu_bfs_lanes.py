@@ -128,14 +128,16 @@ def test_ragged_vertex_counts(lgmod, n, p, kw):
     h.free()
 
 
-def test_multi_root_calls_from_two_threads(lgmod):
-    """Two threads, each with its own stream, run 40-root calls (multi-source
-    batches sharing the device's masks) on two graphs at once: every result
-    equals the same call made alone."""
+@pytest.mark.parametrize("counts", [(40, 40), (9, 40)])
+def test_multi_root_calls_from_two_threads(lgmod, counts):
+    """Two threads, each with its own stream, run multi-root calls on two
+    graphs at once: 40 roots (multi-source batches sharing the device's masks
+    and lane 0's workspace) or 9 (the lanes): every result equals the same
+    call made alone."""
     import threading
     graphs = [gg.kronecker(13, 16, seed=11, device="cuda"), gg.erdos_renyi(13, 8, seed=12, device="cuda")]
     hs = [lgmod.encode(g.row_offsets, g.col, g.n) for g in graphs]
-    roots = [gg.pick_roots(g, 40, seed=5) for g in graphs]
+    roots = [gg.pick_roots(g, c, seed=5) for g, c in zip(graphs, counts)]
     ref = [lgmod.bfs(h, r) for h, r in zip(hs, roots)]
     torch.cuda.synchronize()
     out = [[None] * 6, [None] * 6]
