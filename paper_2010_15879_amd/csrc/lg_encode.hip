@@ -492,7 +492,34 @@ struct SrcU64Mask {
 };
 
 // Value j of a sequence of `count` values occupies bits [j*w, j*w + w).
-// Word k gathers the values overlapping bits [64k, 64k + 64).
+// Word k gathers the values overlapping bits [64k, 64k + 64): the value j0
+// holding bit 64k and those after it, at most ceil(63 / w) + 1 of them.
+// With kMax >= that bound the loads go out together (indices clamped into
+// the sequence, values past the word or the sequence dropped); kMax = 0 is
+// the loop for narrow widths.
+template <int kMax, class Src>
+__device__ __forceinline__ uint64_t pack_word(Src src, uint64_t count, uint32_t w, uint64_t b0, uint64_t j0) {
+    uint64_t word = 0;
+    if constexpr (kMax > 0) {
+        uint64_t x[kMax];
+#pragma unroll
+        for (int t = 0; t < kMax; ++t) x[t] = src(j0 + t < count ? j0 + t : count - 1);
+#pragma unroll
+        for (int t = 0; t < kMax; ++t) {
+            const uint64_t j = j0 + t, b = j * w;
+            if (j < count && b < b0 + 64) word |= (b >= b0) ? (x[t] << (b - b0)) : (x[t] >> (b0 - b));
+        }
+    } else {
+        for (uint64_t j = j0; j < count; ++j) {
+            const uint64_t b = j * w;
+            if (b >= b0 + 64) break;
+            const uint64_t x = src(j);
+            word |= (b >= b0) ? (x << (b - b0)) : (x >> (b0 - b));
+        }
+    }
+    return word;
+}
+
 template <class Src>
 __global__ void pack_fixed_kernel(Src src, uint64_t count, uint32_t w, double inv_w, uint64_t words,
                                   uint64_t *__restrict__ out) {
@@ -502,12 +529,12 @@ __global__ void pack_fixed_kernel(Src src, uint64_t count, uint32_t w, double in
         const uint64_t b0 = k * 64;
         uint64_t word = 0;
         if (w && b0 < total_bits) {
-            for (uint64_t j = div_small(b0, w, inv_w); j < count; ++j) {
-                const uint64_t b = j * w;
-                if (b >= b0 + 64) break;
-                const uint64_t x = src(j);
-                word |= (b >= b0) ? (x << (b - b0)) : (x >> (b0 - b));
-            }
+            const uint64_t j0 = div_small(b0, w, inv_w);
+            if (w >= 22) word = pack_word<4>(src, count, w, b0, j0);        // ceil(63/22) + 1 = 4
+            else if (w >= 16) word = pack_word<5>(src, count, w, b0, j0);   // ceil(63/16) + 1 = 5
+            else if (w >= 11) word = pack_word<7>(src, count, w, b0, j0);   // ceil(63/11) + 1 = 7
+            else if (w >= 8) word = pack_word<9>(src, count, w, b0, j0);    // ceil(63/8) + 1 = 9
+            else word = pack_word<0>(src, count, w, b0, j0);
         }
         out[k] = word;
     }
