@@ -134,9 +134,14 @@ __device__ __forceinline__ void walk_item(uint32_t n, const uint64_t *__restrict
 }
 
 // IDs < n, no self-loop, strictly increasing lists.
+// Also low[v], the entries of row v below v (the symmetry check's split of
+// each row): in a sorted row without v the first entry above v sits at
+// position low[v], and a row whose last entry is below v has low[v] = its
+// degree; one store per row (empty rows keep the zero low starts with).
 __global__ void validate_edges_kernel(uint32_t n, const uint64_t *__restrict__ off, const uint32_t *__restrict__ col,
                                       uint64_t items, const uint32_t *__restrict__ map,
-                                      const uint64_t *__restrict__ coff, uint32_t *__restrict__ status) {
+                                      const uint64_t *__restrict__ coff, uint32_t *__restrict__ status,
+                                      uint32_t *__restrict__ low) {
     __shared__ uint64_t s_rs[4][kWave + 1];
     const uint32_t wv = threadIdx.x / kWave;
     const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
@@ -156,9 +161,13 @@ __global__ void validate_edges_kernel(uint32_t n, const uint64_t *__restrict__ o
             uint32_t prev = __shfl_up(u, 1, kWave);
             if (!valid) return;
             if (lane_id() == 0) prev = x.y;
+            const uint32_t v = (uint32_t)(v0 + j);
+            const uint64_t rs = s_rs[wv][j], re = s_rs[wv][j + 1];
             if (u >= n) flags |= kBadId;
-            if (u == v0 + j) flags |= kSelfLoop;
-            if (e > s_rs[wv][j] && prev >= u) flags |= kUnsorted;
+            if (u == v) flags |= kSelfLoop;
+            if (e > rs && prev >= u) flags |= kUnsorted;
+            if (u > v && (e == rs || prev < v)) low[v] = (uint32_t)(e - rs);  // the row's first entry above v
+            else if (u < v && e + 1 == re) low[v] = (uint32_t)(re - rs);     // all of the row is below v
         });
     }
     if (__ballot(flags != 0)) {
@@ -175,22 +184,6 @@ __global__ void validate_edges_kernel(uint32_t n, const uint64_t *__restrict__ o
 // diagonal in row order: row u's entries larger than u.  Both halves hold
 // lowoff[n] entries (checked first), and the upper entry at stream position
 // e of row u has index e - lowoff[u + 1] among the upper entries.
-
-// low[v]: the entries of row v smaller than v (binary search of its list)
-__global__ void sym_low_kernel(uint32_t n, const uint64_t *__restrict__ off, const uint32_t *__restrict__ col,
-                               uint32_t *__restrict__ low) {
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) {
-        uint64_t lo = off[v], hi = off[v + 1];
-        const uint64_t b = lo;
-        while (lo < hi) {
-            const uint64_t mid = lo + (hi - lo) / 2;
-            if (col[mid] < (uint32_t)v) lo = mid + 1;
-            else hi = mid;
-        }
-        low[v] = (uint32_t)(lo - b);
-    }
-}
 
 // the rows' lowoff values for block q (65 of them, clamped at n) into s_lo
 __device__ __forceinline__ void sym_block_lowoff(uint32_t n, const uint32_t *__restrict__ map, uint64_t k,
@@ -1159,21 +1152,21 @@ static lg_status encode_impl(uint32_t n, uint64_t m, const uint64_t *row_offsets
     LG_CHECK_HIP(hipMemcpyAsync(&bad, status.p, 4, hipMemcpyDeviceToHost, s));
     LG_CHECK_HIP(hipStreamSynchronize(s));
     WalkTable walk;
+    DevBuf low;  // entries below the diagonal per row (the symmetry check's split)
     if (!bad) {  // the offsets are sound: walk the lists
         LG_TRY(walk_table(n, row_offsets, walk, tmp, s));
+        LG_TRY(low.scratch((uint64_t)n * 4, s));
+        LG_TRY(fill_u32(low.as<uint32_t>(), 0, n, s));
         LG_LAUNCH(validate_edges_kernel, walk.grid, 256, 0, s, n, row_offsets, col, walk.items,
-                  walk.map.as<uint32_t>(), walk.coff.as<uint64_t>(), status.as<uint32_t>());
+                  walk.map.as<uint32_t>(), walk.coff.as<uint64_t>(), status.as<uint32_t>(), low.as<uint32_t>());
         LG_CHECK_LAUNCH();
         LG_CHECK_HIP(hipMemcpyAsync(&bad, status.p, 4, hipMemcpyDeviceToHost, s));
         LG_CHECK_HIP(hipStreamSynchronize(s));
     }
     if (!bad && m) {
-        // the entries below the diagonal: per row, then their offsets
-        DevBuf low, lowoff;
-        LG_TRY(low.scratch((uint64_t)n * 4, s));
+        // the offsets of the entries below the diagonal (counted by the validation walk)
+        DevBuf lowoff;
         LG_TRY(lowoff.scratch(((uint64_t)n + 1) * 8, s));
-        LG_LAUNCH(sym_low_kernel, grid1(n), 256, 0, s, n, row_offsets, col, low.as<uint32_t>());
-        LG_CHECK_LAUNCH();
         LG_TRY(exclusive_scan_u32(low.as<uint32_t>(), lowoff.as<uint64_t>(), n, tmp, s));
         uint64_t half = 0;
         LG_CHECK_HIP(hipMemcpyAsync(&half, lowoff.as<uint64_t>() + n, 8, hipMemcpyDeviceToHost, s));
