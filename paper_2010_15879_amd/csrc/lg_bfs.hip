@@ -2123,16 +2123,20 @@ __global__ void ms_finish_kernel(uint32_t n, uint32_t r, const unsigned long lon
     }
 }
 
-// One batch of at most 64 roots.  The rows are computed in label space; on
-// a relabeled graph each row then goes through one workspace row and back
-// in original IDs (bfs_unpermute_kernel, as for a single root).  The host
-// reads two counters per level: the next frontier's size and the searches
-// still running.
+// One batch of at most 64 roots.  The rows are computed in label space.  On
+// a relabeled graph they are then unpermuted into original IDs
+// (bfs_unpermute_kernel, as for a single root): from the workspace rows
+// `ws` (depth rows, then parent rows) when the caller has them, else each
+// row is first copied to a one-row workspace.  The host reads two counters
+// per level: the next frontier's size and the searches still running.
 template <class Acc>
 static lg_status bfs_ms_batch(lg_graph *g, BfsWork &w, MsWork &ms, Acc acc, const uint32_t *roots, uint32_t r,
-                              int32_t *depth, int32_t *parent, int32_t max_depth, hipStream_t s) {
+                              int32_t *depth_out, int32_t *parent_out, int32_t max_depth, int32_t *ws,
+                              hipStream_t s) {
     const uint32_t n = g->n;
     const bool rel = g->relabel != LG_RELABEL_NONE;
+    int32_t *depth = rel && ws ? ws : depth_out;
+    int32_t *parent = parent_out ? (rel && ws ? ws + (uint64_t)r * n : parent_out) : nullptr;
     const uint64_t words = ((uint64_t)n + 63) / 64;
     unsigned long long *vis = ms.vis.as<unsigned long long>();
     unsigned long long *fr = ms.fr.as<unsigned long long>();
@@ -2233,15 +2237,21 @@ static lg_status bfs_ms_batch(lg_graph *g, BfsWork &w, MsWork &ms, Acc acc, cons
     LG_LAUNCH(ms_finish_kernel, wgrid, 256, 0, s, n, r, (const unsigned long long *)vis, depth, parent);
     LG_CHECK_LAUNCH();
     if (rel) {
-        int32_t *tmp_d = w.depth_i.as<int32_t>();
-        uint32_t *tmp_p = parent ? w.parent_i.as<uint32_t>() : nullptr;
         for (uint32_t i = 0; i < r; ++i) {
-            int32_t *d_row = depth + (uint64_t)i * n;
-            int32_t *p_row = parent ? parent + (uint64_t)i * n : nullptr;
-            LG_CHECK_HIP(hipMemcpyAsync(tmp_d, d_row, (uint64_t)n * 4, hipMemcpyDeviceToDevice, s));
-            if (p_row) LG_CHECK_HIP(hipMemcpyAsync(tmp_p, p_row, (uint64_t)n * 4, hipMemcpyDeviceToDevice, s));
+            int32_t *d_row = depth_out + (uint64_t)i * n;
+            int32_t *p_row = parent_out ? parent_out + (uint64_t)i * n : nullptr;
+            const int32_t *d_in = depth + (uint64_t)i * n;
+            const uint32_t *p_in = parent ? reinterpret_cast<const uint32_t *>(parent + (uint64_t)i * n) : nullptr;
+            if (!ws) {  // the row is its own output: copy it aside first
+                int32_t *tmp_d = w.depth_i.as<int32_t>();
+                uint32_t *tmp_p = parent ? w.parent_i.as<uint32_t>() : nullptr;
+                LG_CHECK_HIP(hipMemcpyAsync(tmp_d, d_row, (uint64_t)n * 4, hipMemcpyDeviceToDevice, s));
+                if (p_row) LG_CHECK_HIP(hipMemcpyAsync(tmp_p, p_row, (uint64_t)n * 4, hipMemcpyDeviceToDevice, s));
+                d_in = tmp_d;
+                p_in = tmp_p;
+            }
             LG_LAUNCH(bfs_unpermute_kernel, grid_for(n, 256, 1u << 16), 256, 0, s, n, g->inv.as<uint32_t>(),
-                      g->perm.as<uint32_t>(), (const int32_t *)tmp_d, (const uint32_t *)tmp_p, d_row, p_row);
+                      g->perm.as<uint32_t>(), d_in, p_in, d_row, p_row);
             LG_CHECK_LAUNCH();
         }
     }
@@ -2353,6 +2363,7 @@ static lg_status bfs_run_lanes(lg_graph *g, const uint32_t *roots, uint32_t r, i
 // It runs on `stream` and holds the device's BFS pool (its lane 0
 // workspace, the multi-source masks) for its duration.
 constexpr uint32_t kMsMinRoots = 16;
+constexpr uint64_t kMsRowsCap = 16ull << 30;  // bytes of label-space rows a relabeled batch may keep aside
 
 static bool bfs_ms_graph(const lg_graph *g, uint32_t flags) {
     if (flags != LG_BFS_DIRECTION_OPT) return false;
@@ -2396,12 +2407,23 @@ static lg_status bfs_run_ms(lg_graph *g, const uint32_t *roots, uint32_t r, int3
     LG_TRY(ms.pend_v.ensure(n * 4));
     LG_TRY(ms.pend_m.ensure(n * 8));
     LG_TRY(ms.roots.ensure(kMsRoots * 4));
+    // relabeled graphs: a batch's label-space rows in a workspace, so that
+    // they unpermute straight into the caller's rows, when it stays within
+    // kMsRowsCap (else every row is copied aside before its unpermute)
+    int32_t *ws = nullptr;
+    if (g->relabel != LG_RELABEL_NONE) {
+        const uint64_t need = (uint64_t)std::min<uint32_t>(r, kMsRoots) * n * (parent ? 8 : 4);
+        if (need <= kMsRowsCap) {
+            LG_TRY(ms.rows.ensure(need));
+            ws = ms.rows.as<int32_t>();
+        }
+    }
     // lane 0's stream is not used: everything runs on the caller's stream
     LG_TRY(dispatch_acc(g, [&](auto acc) -> lg_status {
         for (uint32_t b0 = 0; b0 < r; b0 += kMsRoots) {
             const uint32_t rb = std::min<uint32_t>(kMsRoots, r - b0);
             LG_TRY(bfs_ms_batch(g, w, ms, acc, roots + b0, rb, depth + (uint64_t)b0 * n,
-                                parent ? parent + (uint64_t)b0 * n : nullptr, max_depth, stream));
+                                parent ? parent + (uint64_t)b0 * n : nullptr, max_depth, ws, stream));
         }
         return LG_OK;  // batches follow each other on the caller's stream (shared masks and roots buffer)
     }));

@@ -136,8 +136,9 @@ struct MsWork {
     DevBuf bits;                 // u64[words]: vertices of the next frontier
     DevBuf pend_v, pend_m;       // u32[n], u64[n]: vertices left for the wave pass, their open bits
     DevBuf roots;                // u32[64]: the batch's roots
+    DevBuf rows;                 // relabeled graphs: the batch's depth and parent rows in label space
     uint64_t bytes() const {
-        return vis.bytes + fr.bytes + nx.bytes + bits.bytes + pend_v.bytes + pend_m.bytes + roots.bytes;
+        return vis.bytes + fr.bytes + nx.bytes + bits.bytes + pend_v.bytes + pend_m.bytes + roots.bytes + rows.bytes;
     }
 };
 struct BfsPool {
