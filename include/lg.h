@@ -222,9 +222,10 @@ lg_status lg_decode_neighbors_noalloc(const lg_graph *g, const uint32_t *vertice
  *     coded, not weighted and without bvIL offsets, the first roots go in
  *     batches of up to 64 while at least 16 are left, each batch one
  *     multi-source traversal on `stream` (64-bit visit and frontier masks
- *     per vertex, 36 bytes per vertex of device workspace); the host reads
- *     a few counters per level, so the call returns when these batches are
- *     done;
+ *     per vertex, 36 bytes per vertex of device workspace; on a relabeled
+ *     graph also the batch's rows in label space, 8 bytes per root and
+ *     vertex, when that stays within 16 GiB); the host reads a few
+ *     counters per level, so the call returns when these batches are done;
  *   - the other roots run a few at a time, each on its own internal stream
  *     with its own workspace; the call returns once each is enqueued.
  * These streams and workspaces belong to the device, not to the graph: they
