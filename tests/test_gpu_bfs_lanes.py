@@ -165,3 +165,25 @@ def test_multi_root_calls_from_two_threads(lgmod, counts):
             assert torch.equal(d, ref[i][0]) and torch.equal(p, ref[i][1]), i
     for h in hs:
         h.free()
+
+
+@pytest.mark.parametrize("kw", [dict(), dict(ids="local", offsets="succinct", relabel=True),
+                                dict(layout="plain", relabel=True)])
+@pytest.mark.parametrize("max_depth", [-1, 3])
+def test_many_roots_depths_only(lgmod, kw, max_depth):
+    """40 roots without parent rows (the multi-source kernels' depth-only
+    forms): depths equal the one-root calls' and the oracle's."""
+    g = small_graph("kron13")
+    h = lgmod.encode(g.row_offsets, g.col, g.n, **kw)
+    roots = gg.pick_roots(g, 40, seed=8)
+    d_all, p_all = lgmod.bfs(h, roots, parent=False, max_depth=max_depth)
+    assert p_all is None
+    for i, r in enumerate(roots):
+        d1, _ = lgmod.bfs(h, [r], max_depth=max_depth)
+        assert torch.equal(d_all[i], d1[0]), (i, r)
+    off, col = g.numpy()
+    for i in (0, 39):
+        d0, _ = orc.bfs(off.astype(np.uint64), col.view(np.uint32), roots[i], max_depth=max_depth,
+                        relabeled=bool(kw.get("relabel")))
+        np.testing.assert_array_equal(d_all[i].cpu().numpy(), d0)
+    h.free()
