@@ -187,3 +187,35 @@ def test_many_roots_depths_only(lgmod, kw, max_depth):
                         relabeled=bool(kw.get("relabel")))
         np.testing.assert_array_equal(d_all[i].cpu().numpy(), d0)
     h.free()
+
+
+@pytest.mark.parametrize("kw", [dict(ids="global", offsets="plain-bv"), dict(ids="local", offsets="packed"),
+                                dict(ids="local", offsets="plain-bv", relabel=True),
+                                dict(ids="local-gap", offsets="packed"),
+                                dict(ids="varint-diff", offsets="succinct", relabel=True)],
+                         ids=lambda k: "-".join(str(v) for v in k.values()))
+def test_many_roots_every_encoding(lgmod, kw):
+    """20 roots over the other encodings: bvPL and local packed offsets run
+    the multi-source batch, gap and Varint lists (read in order only) run on
+    the lanes; every row equals the one-root call."""
+    g = small_graph("kron13")
+    h = lgmod.encode(g.row_offsets, g.col, g.n, **kw)
+    roots = gg.pick_roots(g, 20, seed=9)
+    d_all, p_all = lgmod.bfs(h, roots)
+    for i, r in enumerate(roots):
+        d1, p1 = lgmod.bfs(h, [r])
+        assert torch.equal(d_all[i], d1[0]) and torch.equal(p_all[i], p1[0]), (i, r)
+    h.free()
+
+
+def test_many_roots_rejected_on_interleaved_offsets(lgmod):
+    """bvIL offsets serve the neighbor decode only: a multi-root BFS call is
+    rejected as a one-root call is."""
+    from paper_2010_15879_amd.lg import LGError, LG_ERR_UNSUPPORTED
+    g = small_graph("kron13")
+    h = lgmod.encode(g.row_offsets, g.col, g.n, ids="global", offsets="interleaved-bv")
+    for count in (1, 20):
+        with pytest.raises(LGError) as ei:
+            lgmod.bfs(h, gg.pick_roots(g, count, seed=9))
+        assert ei.value.status == LG_ERR_UNSUPPORTED, count
+    h.free()
